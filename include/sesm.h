@@ -1,0 +1,178 @@
+/*
+ * sesm.h - C ABI of the MI355X library for 2-D periodic sound-soft (Dirichlet,
+ * TE/PEC) scattering with the shifted (multipolar, Wood-anomaly capable)
+ * quasi-periodic Green function and shifted-equivalent-source FFT acceleration.
+ *
+ * Method: O. P. Bruno and M. Maas, "Shifted equivalent sources and FFT
+ * acceleration for periodic scattering problems, including Wood anomalies".
+ * Section and equation names below refer to that paper.
+ *
+ * Conventions shared by every entry point
+ *  - Units are those of the caller (lengths and wavenumbers consistent).
+ *  - Complex numbers are interleaved FP64 pairs (sesm_c64), the memory layout
+ *    of torch.complex128 / std::complex<double>.
+ *  - Pointers documented as "device" must point to device memory of the
+ *    context's GPU, of at least the stated length; "host" pointers are plain
+ *    CPU memory.  The library never frees caller memory.
+ *  - All device work is enqueued on the stream given to sesm_create; calls
+ *    that return results in host memory (sesm_solve's info, sesm_efficiencies,
+ *    sesm_get_info) synchronise that stream before returning.
+ *  - Return value 0 means success; negative values are SESM_E* codes and
+ *    sesm_last_error() returns a human-readable message.  No C++ exception
+ *    crosses this interface.  One context must not be used from two threads
+ *    at once.
+ *  - Quadrature nodes: x_l = l d / N, l = 0..N-1 (the paper numbers them
+ *    1..N with x_N = d; by the quasi-periodicity mu_{l+N} = mu_l e^{i alpha d},
+ *    eq. (quasiper_disc), this relabels one unknown).  Densities mu_l are the
+ *    Nystrom values of eq. (discrete_eq).
+ */
+#ifndef SESM_H
+#define SESM_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define SESM_API __attribute__((visibility("default")))
+#else
+#define SESM_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SESM_OK 0
+#define SESM_EINVAL (-1)     /* invalid argument or parameter combination      */
+#define SESM_ENOSURF (-2)    /* sesm_set_surface has not succeeded yet          */
+#define SESM_ENOMEM (-3)     /* device allocation failed                        */
+#define SESM_EHIP (-4)       /* HIP runtime error (text in sesm_last_error)     */
+#define SESM_ERESONANT (-5)  /* accelerator cell side L is a Dirichlet resonance */
+#define SESM_ENOCONV (-6)    /* GMRES did not reach tol; outputs still written   */
+
+#define SESM_MODE_DENSE 0    /* precomputed dense direct operator, Sec. 4.3     */
+#define SESM_MODE_ACCEL 1    /* shifted-equivalent-source FFT acceleration, Sec. 5 */
+
+typedef struct sesm_ctx sesm_ctx;
+
+typedef struct {
+  double re, im;
+} sesm_c64;
+
+/* Profile f(x) = a[0] + sum_{m=1}^{n_modes} a[m] cos(2 pi m x/d) + b[m] sin(2 pi m x/d).
+ * a, b: host arrays of length n_modes + 1 (b[0] is ignored). */
+typedef struct {
+  int32_t n_modes;
+  const double* a;
+  const double* b;
+} sesm_profile;
+
+/* Discretisation parameters.  A zero field selects the documented default. */
+typedef struct {
+  int32_t N;          /* number of quadrature nodes per period (required, >= 8)          */
+  double h;           /* shift of G_j, eq. (shifted_green_function); default pi / k       */
+  double c_window;    /* plateau fraction c of the window S_{cA,A}, eq. (na_A); default 0.5 */
+  int32_t n_a;        /* singular window radius a = n_a d/N, eq. (dsing_def);
+                         default floor(0.8 min(L_cell, d) N / d), at least 8 */
+  double gamma_frac;  /* gamma = gamma_frac * a, eq. (S_def); default 0.5                 */
+  double eta;         /* completion threshold of U^eta, eq. (M_eta); default 1e-3          */
+  int32_t mode;       /* SESM_MODE_DENSE (default) or SESM_MODE_ACCEL                     */
+  double L_cell;      /* accelerator cell side L, eq. (L_constr); default 0.5 * 2 pi / k  */
+  int32_t n_side;     /* accelerator: equivalent-source grid intervals per cell side      */
+  int32_t n_ext;      /* accelerator: extra equivalent-source points beyond each corner    */
+  int32_t n_coll;     /* accelerator: collocation points per side of the 3L square, eq. (eq_source_point) */
+  int32_t n_plw;      /* accelerator: plane waves per cell, eq. (planewave)               */
+  int32_t reserved[8];
+} sesm_params;
+
+typedef struct {
+  int32_t iters;          /* Krylov iterations performed            */
+  double rel_residual;    /* final ||b - A mu|| / ||b|| estimate     */
+  int32_t converged;      /* 1 if rel_residual <= tol               */
+} sesm_solve_info;
+
+/* Read-only description of the discretisation chosen by sesm_set_surface. */
+typedef struct {
+  int32_t N;
+  int32_t n_a;
+  double dx, a, gamma, h, A_len;
+  int32_t mode;
+  int32_t n_eta;              /* |U^eta|                                    */
+  int32_t U_eta[16];          /* its first 16 members                       */
+  int32_t n_first, n_count;   /* propagating orders n_first..n_first+n_count-1 */
+  /* accelerator geometry (zeros in dense mode) */
+  int32_t n_x, n_y, n_cells_occupied, stencil_rows;
+  double L, y0, delta;
+  int64_t device_bytes;       /* device memory held by the context          */
+} sesm_surface_info;
+
+/* Create a context on HIP device `device`; `hip_stream` is a hipStream_t (NULL
+ * selects the default stream).  *out receives the context. */
+SESM_API int sesm_create(sesm_ctx** out, int device, void* hip_stream);
+
+/* Release a context and every device buffer it owns.  NULL is accepted. */
+SESM_API int sesm_destroy(sesm_ctx* ctx);
+
+/* Algorithm 2 (Initialization): set up the surface and precompute every
+ * operator table.  d: period; k: wavenumber; alpha: Bloch wavenumber
+ * (alpha = k sin theta, Sec. 2); j: shift order of G_j; A_periods: window
+ * half-width A of S_{cA,A} in periods (eq. na_A).  params may be NULL only if
+ * N is given through a non-NULL struct, so in practice it is required.
+ * Rejects |alpha| > k, a >= d, (accelerated mode) a >= L or a resonant cell
+ * side (Remark non-resonant), and non-finite profile values. */
+SESM_API int sesm_set_surface(sesm_ctx* ctx, const sesm_profile* profile, double d, double k,
+                     double alpha, int32_t j, double A_periods, const sesm_params* params);
+
+/* Algorithm 3 (forward map): y = (1/2 I + D^dx) mu, eq. (discrete_eq).
+ * mu, y: device arrays of N sesm_c64; they must not overlap. */
+SESM_API int sesm_matvec(sesm_ctx* ctx, const sesm_c64* mu, sesm_c64* y);
+
+/* Right-hand side of eq. (discrete_eq): b_l = -u^inc(x_l, f(x_l)) with
+ * u^inc = exp(i (alpha x - beta y)), beta = sqrt(k^2 - alpha^2) (Sec. 2).
+ * b: device array of N sesm_c64. */
+SESM_API int sesm_rhs(sesm_ctx* ctx, sesm_c64* b);
+
+/* Algorithm 1: GMRES solve of (1/2 I + D^dx) mu = b.  b: device array of N
+ * (NULL selects the incident-field right-hand side of sesm_rhs).  mu: device
+ * array of N, output only (the iteration starts from zero).  tol: relative residual;
+ * max_iter: iteration cap; restart: Krylov dimension (0 = max_iter, i.e.
+ * unrestarted).  info: host struct, may be NULL.  Returns SESM_ENOCONV if tol
+ * was not reached (mu and info still hold the last iterate). */
+SESM_API int sesm_solve(sesm_ctx* ctx, const sesm_c64* b, sesm_c64* mu, double tol, int32_t max_iter,
+               int32_t restart, sesm_solve_info* info);
+
+/* Efficiencies e_n = (beta_n / beta) |B_n|^2 of the propagating orders
+ * (Sec. 2) and the energy-balance error eps = 1 - sum e_n, eq. (energy_error).
+ * B_n are the Rayleigh coefficients of the representation
+ * eq. (eq:int_eq_dirichlet) above the surface (spectral series
+ * eq. (shifted_periodic_green_function_spectral) plus M^eta), by the
+ * trapezoidal rule.  mu: device array of N.  On return *n_first, *n_count
+ * describe the orders n_first..n_first+n_count-1; e_host (host, capacity
+ * e_capacity) receives min(n_count, e_capacity) values; energy_error (host)
+ * may be NULL.  Synchronises the stream. */
+SESM_API int sesm_efficiencies(sesm_ctx* ctx, const sesm_c64* mu, int32_t* n_first, int32_t* n_count,
+                      double* e_host, int32_t e_capacity, double* energy_error);
+
+/* Rayleigh coefficients B_n for the n_orders integer orders in orders_host
+ * (host array); B_host (host, n_orders entries) receives them.  Same
+ * formula as sesm_efficiencies.  Synchronises the stream. */
+SESM_API int sesm_rayleigh(sesm_ctx* ctx, const sesm_c64* mu, const int32_t* orders_host, int32_t n_orders,
+                  sesm_c64* B_host);
+
+/* Describe the current discretisation (host struct).  Returns SESM_ENOSURF
+ * before a successful sesm_set_surface. */
+SESM_API int sesm_get_info(const sesm_ctx* ctx, sesm_surface_info* info);
+
+/* Message of the last failing call on ctx ("" if none).  Never NULL. */
+SESM_API const char* sesm_last_error(const sesm_ctx* ctx);
+
+/* Diagnostic: evaluate the library's FP64 Hankel functions H0^(1)(x),
+ * H1^(1)(x) (used by every Green-function kernel, eq. free_space) at n
+ * points.  x: device array of n doubles (x > 0); h0, h1: device arrays of n
+ * sesm_c64.  Enqueued on the context's stream. */
+SESM_API int sesm_diag_hankel(sesm_ctx* ctx, const double* x, int32_t n, sesm_c64* h0, sesm_c64* h1);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SESM_H */

@@ -1,0 +1,201 @@
+"""Python binding of libsesm (C ABI in include/sesm.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+PyTorch provides device memory (complex128 CUDA tensors) and the stream.
+Importing this module does not load the library; the first Solver() does, and
+raises if libsesm.so has not been built (python -m paper_1707_04950_amd.build).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsesm.so")
+
+SESM_OK = 0
+SESM_EINVAL = -1
+SESM_ENOSURF = -2
+SESM_ENOMEM = -3
+SESM_EHIP = -4
+SESM_ERESONANT = -5
+SESM_ENOCONV = -6
+MODE_DENSE = 0
+MODE_ACCEL = 1
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("n_modes", ctypes.c_int32), ("a", ctypes.POINTER(ctypes.c_double)),
+                ("b", ctypes.POINTER(ctypes.c_double))]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("h", ctypes.c_double), ("c_window", ctypes.c_double),
+                ("n_a", ctypes.c_int32), ("gamma_frac", ctypes.c_double), ("eta", ctypes.c_double),
+                ("mode", ctypes.c_int32), ("L_cell", ctypes.c_double), ("n_side", ctypes.c_int32),
+                ("n_ext", ctypes.c_int32), ("n_coll", ctypes.c_int32), ("n_plw", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 8)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("rel_residual", ctypes.c_double), ("converged", ctypes.c_int32)]
+
+
+class SurfaceInfo(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("n_a", ctypes.c_int32), ("dx", ctypes.c_double),
+                ("a", ctypes.c_double), ("gamma", ctypes.c_double), ("h", ctypes.c_double),
+                ("A_len", ctypes.c_double), ("mode", ctypes.c_int32), ("n_eta", ctypes.c_int32),
+                ("U_eta", ctypes.c_int32 * 16), ("n_first", ctypes.c_int32), ("n_count", ctypes.c_int32),
+                ("n_x", ctypes.c_int32), ("n_y", ctypes.c_int32), ("n_cells_occupied", ctypes.c_int32),
+                ("stencil_rows", ctypes.c_int32), ("L", ctypes.c_double), ("y0", ctypes.c_double),
+                ("delta", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I = ctypes.c_int32
+_D = ctypes.c_double
+
+
+def load_library(path=LIB_PATH):
+    """Load libsesm.so and declare the C signatures (no GPU work)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libsesm.so is not built (%s); run `python -m paper_1707_04950_amd.build`" % path)
+    lib = ctypes.CDLL(path)
+    sig = {
+        "sesm_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, _P]),
+        "sesm_destroy": (ctypes.c_int, [_P]),
+        "sesm_set_surface": (ctypes.c_int, [_P, ctypes.POINTER(Profile), _D, _D, _D, _I, _D,
+                                            ctypes.POINTER(Params)]),
+        "sesm_matvec": (ctypes.c_int, [_P, _P, _P]),
+        "sesm_rhs": (ctypes.c_int, [_P, _P]),
+        "sesm_solve": (ctypes.c_int, [_P, _P, _P, _D, _I, _I, ctypes.POINTER(SolveInfo)]),
+        "sesm_efficiencies": (ctypes.c_int, [_P, _P, ctypes.POINTER(_I), ctypes.POINTER(_I),
+                                             ctypes.POINTER(_D), _I, ctypes.POINTER(_D)]),
+        "sesm_rayleigh": (ctypes.c_int, [_P, _P, ctypes.POINTER(_I), _I, _P]),
+        "sesm_get_info": (ctypes.c_int, [_P, ctypes.POINTER(SurfaceInfo)]),
+        "sesm_last_error": (ctypes.c_char_p, [_P]),
+        "sesm_diag_hankel": (ctypes.c_int, [_P, _P, _I, _P, _P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class SesmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("sesm error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _ptr(t):
+    import torch
+    if not (t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()):
+        raise ValueError("expected a contiguous complex128 CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One library context on a GPU (one stream)."""
+
+    def __init__(self, device=0, stream=None):
+        import torch
+        self._torch = torch
+        self.lib = load_library()
+        self.device = torch.device("cuda", device)
+        st = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.stream = st
+        h = _P()
+        rc = self.lib.sesm_create(ctypes.byref(h), device, ctypes.c_void_p(st.cuda_stream))
+        if rc != 0:
+            raise SesmError(rc, "sesm_create failed")
+        self.h = h
+        self.N = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.sesm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow=()):
+        if rc != 0 and rc not in allow:
+            raise SesmError(rc, self.lib.sesm_last_error(self.h).decode())
+        return rc
+
+    def set_surface(self, a_coef, b_coef, d, k, alpha, j, A, N, h=0.0, c=0.0, n_a=0, gamma_frac=0.0,
+                    eta=0.0, mode=MODE_DENSE, L=0.0, n_side=0, n_ext=0, n_coll=0, n_plw=0):
+        a = np.ascontiguousarray(a_coef, dtype=np.float64)
+        b = np.zeros_like(a)
+        bb = np.asarray(b_coef, dtype=np.float64)
+        b[: min(len(a), len(bb))] = bb[: len(a)]
+        self._a, self._b = a, b  # keep alive during the call
+        prof = Profile(len(a) - 1, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                       b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        prm = Params(N=N, h=h, c_window=c, n_a=n_a, gamma_frac=gamma_frac, eta=eta, mode=mode, L_cell=L,
+                     n_side=n_side, n_ext=n_ext, n_coll=n_coll, n_plw=n_plw)
+        self._check(self.lib.sesm_set_surface(self.h, ctypes.byref(prof), d, k, alpha, j, A, ctypes.byref(prm)))
+        self.N = N
+
+    def info(self):
+        inf = SurfaceInfo()
+        self._check(self.lib.sesm_get_info(self.h, ctypes.byref(inf)))
+        out = {f: getattr(inf, f) for f, _ in SurfaceInfo._fields_}
+        out["U_eta"] = list(inf.U_eta)[: inf.n_eta]
+        return out
+
+    def empty(self):
+        return self._torch.empty(self.N, dtype=self._torch.complex128, device=self.device)
+
+    def matvec(self, mu, out=None):
+        out = self.empty() if out is None else out
+        self._check(self.lib.sesm_matvec(self.h, _ptr(mu), _ptr(out)))
+        return out
+
+    def rhs(self, out=None):
+        out = self.empty() if out is None else out
+        self._check(self.lib.sesm_rhs(self.h, _ptr(out)))
+        return out
+
+    def solve(self, b=None, tol=1e-10, max_iter=1000, restart=0, out=None, allow_noconv=False):
+        out = self.empty() if out is None else out
+        inf = SolveInfo()
+        bp = _ptr(b) if b is not None else None
+        rc = self.lib.sesm_solve(self.h, bp, _ptr(out), tol, max_iter, restart, ctypes.byref(inf))
+        self._check(rc, allow=(SESM_ENOCONV,) if allow_noconv else ())
+        return out, {"iters": inf.iters, "rel_residual": inf.rel_residual, "converged": bool(inf.converged)}
+
+    def efficiencies(self, mu):
+        cap = 4096
+        e = np.zeros(cap)
+        n0, nc = _I(), _I()
+        eps = _D()
+        self._check(self.lib.sesm_efficiencies(self.h, _ptr(mu), ctypes.byref(n0), ctypes.byref(nc),
+                                               e.ctypes.data_as(ctypes.POINTER(_D)), cap, ctypes.byref(eps)))
+        return np.arange(n0.value, n0.value + nc.value), e[: nc.value].copy(), eps.value
+
+    def rayleigh(self, mu, orders):
+        o = np.ascontiguousarray(orders, dtype=np.int32)
+        B = np.zeros(len(o), dtype=np.complex128)
+        self._check(self.lib.sesm_rayleigh(self.h, _ptr(mu), o.ctypes.data_as(ctypes.POINTER(_I)), len(o),
+                                           ctypes.c_void_p(B.ctypes.data)))
+        return B
+
+    def diag_hankel(self, x):
+        torch = self._torch
+        x = x.to(device=self.device, dtype=torch.float64).contiguous()
+        h0 = torch.empty(x.numel(), dtype=torch.complex128, device=self.device)
+        h1 = torch.empty_like(h0)
+        self._check(self.lib.sesm_diag_hankel(self.h, ctypes.c_void_p(x.data_ptr()), x.numel(), _ptr(h0), _ptr(h1)))
+        return h0, h1

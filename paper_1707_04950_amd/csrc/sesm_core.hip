@@ -1,0 +1,462 @@
+// Context, surface set-up (Algorithm 2), right-hand side, Rayleigh
+// coefficients and efficiencies, and the operator dispatch.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+
+#include "sesm_impl.h"
+
+namespace {
+
+constexpr double PI = 3.14159265358979323846;
+
+// x_l = l d/N and f, f', f'' of the trigonometric profile at x_l.
+__global__ void k_surface(int N, double d, int nm, const double* __restrict__ a, const double* __restrict__ b,
+                          double* x, double* f, double* fp, double* fpp, double* J) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= N) return;
+  const double xl = (double)l * (d / (double)N);
+  double v = a[0], v1 = 0.0, v2 = 0.0;
+  for (int m = 1; m <= nm; ++m) {
+    const double w = 2.0 * PI * (double)m / d;
+    double s, c;
+    sincos(w * xl, &s, &c);
+    v += a[m] * c + b[m] * s;
+    v1 += w * (-a[m] * s + b[m] * c);
+    v2 += -w * w * (a[m] * c + b[m] * s);
+  }
+  x[l] = xl;
+  f[l] = v;
+  fp[l] = v1;
+  fpp[l] = v2;
+  J[l] = sqrt(1.0 + v1 * v1);
+}
+
+// b_l = -exp(i (alpha x_l - beta f_l)), the Dirichlet data -u^inc of eq. (fist_eq).
+__global__ void k_rhs(int N, double alpha, double beta, const double* __restrict__ x, const double* __restrict__ f,
+                      cplx* b) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= N) return;
+  const cplx e = cexp_i(alpha * x[l] - beta * f[l]);
+  b[l] = cplx{-e.re, -e.im};
+}
+
+struct OrderCoef {
+  double an, br, bi;  // alpha_n, beta_n = br + i bi
+  double qr, qi;      // (1 - e^{i beta_n h})^j / beta_n
+  int inU;            // n in U^eta
+  int pad;
+};
+
+// B_n = dx sum_l [ -(alpha_n f'_l - beta_n) Q_n / (2d) + 1[n in U^eta] J_l ]
+//                * exp(-i alpha_n x_l - i beta_n f_l) mu_l      (one block per order)
+__global__ void k_rayleigh(int N, double d, double dx, const OrderCoef* __restrict__ oc,
+                           const double* __restrict__ x, const double* __restrict__ f,
+                           const double* __restrict__ fp, const double* __restrict__ J,
+                           const cplx* __restrict__ mu, cplx* B) {
+  __shared__ cplx sh[4];
+  const OrderCoef o = oc[blockIdx.x];
+  const cplx Q = cplx{o.qr, o.qi};
+  const cplx bn = cplx{o.br, o.bi};
+  cplx acc = cplx{0.0, 0.0};
+  for (int l = threadIdx.x; l < N; l += blockDim.x) {
+    // -(alpha_n f' - beta_n) Q / (2d)
+    const cplx g = cplx{-o.an * fp[l] + bn.re, bn.im};
+    cplx kern = (1.0 / (2.0 * d)) * (g * Q);
+    if (o.inU) kern.re += J[l];
+    // exp(-i alpha_n x - i beta_n f) = exp(bi f) exp(-i (alpha_n x + br f))
+    const double mag = exp(o.bi * f[l]);
+    const cplx e = cexp_i(-(o.an * x[l] + o.br * f[l]));
+    acc += (mag * (kern * e)) * mu[l];
+  }
+  const cplx s = block_sum<256>(acc, sh);
+  if (threadIdx.x == 0) B[blockIdx.x] = dx * s;
+}
+
+__global__ void k_diag_hankel(int n, const double* __restrict__ x, cplx* h0, cplx* h1) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  cplx a, b;
+  sesm_hankel01(x[i], &a, &b);
+  h0[i] = a;
+  h1[i] = b;
+}
+
+double binom(int n, int m) {
+  double r = 1.0;
+  for (int t = 1; t <= m; ++t) r = r * (double)(n - m + t) / (double)t;
+  return r;
+}
+
+std::complex<double> beta_of(double k, double an) {
+  const double disc = k * k - an * an;
+  return disc >= 0 ? std::complex<double>(std::sqrt(std::fabs(disc)), 0.0)
+                   : std::complex<double>(0.0, std::sqrt(std::fabs(disc)));
+}
+
+// (1 - e^{i beta h})^j / beta with 1 - e^{iz} = -2i sin(z/2) e^{iz/2}
+std::complex<double> shift_quotient(std::complex<double> b, double h, int j) {
+  if (b == 0.0) {
+    if (j >= 2) return 0.0;
+    if (j == 1) return std::complex<double>(0.0, -h);
+    return std::complex<double>(INFINITY, 0.0);
+  }
+  const std::complex<double> z = b * h;
+  const std::complex<double> I(0.0, 1.0);
+  return std::pow(-2.0 * I, j) * std::pow(std::sin(z / 2.0), j) * std::exp(0.5 * (double)j * I * z) / b;
+}
+
+}  // namespace
+
+int sesm_alloc(sesm_ctx* ctx, void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return ctx->fail(SESM_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+  }
+  ctx->owned.push_back(*p);
+  ctx->bytes += (int64_t)bytes;
+  return SESM_OK;
+}
+
+void sesm_release_surface(sesm_ctx* ctx) {
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  sesm_accel_free(ctx);
+  for (void* p : ctx->owned) (void)hipFree(p);
+  ctx->owned.clear();
+  ctx->bytes = 0;
+  ctx->x = ctx->f = ctx->fp = ctx->fpp = ctx->J = ctx->logw = nullptr;
+  ctx->Mdense = nullptr;
+  ctx->V = nullptr;
+  ctx->V_cols = 0;
+  ctx->hcol = ctx->hpart = ctx->ybuf = ctx->wtmp = nullptr;
+  if (ctx->hhost) (void)hipHostFree(ctx->hhost);
+  ctx->hhost = nullptr;
+  ctx->ready = false;
+}
+
+KParams sesm_ctx::kparams() const {
+  KParams K{};
+  K.N = P.N;
+  K.j = P.j;
+  K.n_a = P.n_a;
+  K.pmin = P.pmin;
+  K.pmax = P.pmax;
+  K.nU = P.nU;
+  K.d = P.d;
+  K.k = P.k;
+  K.alpha = P.alpha;
+  K.dx = P.dx;
+  K.h = P.h;
+  K.A_len = P.A_len;
+  K.cA = P.cA;
+  K.a = P.a;
+  K.gamma = P.gamma;
+  for (int m = 0; m <= SESM_MAX_J; ++m) K.wshift[m] = P.wshift[m];
+  for (int t = 0; t < SESM_MAX_UETA; ++t) {
+    K.Ua[t] = P.Ua[t];
+    K.Ubr[t] = P.Ubr[t];
+    K.Ubi[t] = P.Ubi[t];
+  }
+  return K;
+}
+
+int sesm_apply(sesm_ctx* ctx, const cplx* mu, cplx* y) {
+  if (ctx->P.mode == SESM_MODE_ACCEL) return sesm_accel_matvec(ctx, mu, y);
+  return sesm_dense_matvec(ctx, mu, y);
+}
+
+extern "C" {
+
+int sesm_create(sesm_ctx** out, int device, void* hip_stream) {
+  if (!out) return SESM_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    (void)hipGetLastError();
+    return SESM_EHIP;
+  }
+  if (hipSetDevice(device) != hipSuccess) return SESM_EHIP;
+  sesm_ctx* ctx = new (std::nothrow) sesm_ctx();
+  if (!ctx) return SESM_ENOMEM;
+  ctx->device = device;
+  ctx->stream = (hipStream_t)hip_stream;
+  *out = ctx;
+  return SESM_OK;
+}
+
+int sesm_destroy(sesm_ctx* ctx) {
+  if (!ctx) return SESM_OK;
+  (void)hipSetDevice(ctx->device);
+  sesm_release_surface(ctx);
+  delete ctx;
+  return SESM_OK;
+}
+
+const char* sesm_last_error(const sesm_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int sesm_set_surface(sesm_ctx* ctx, const sesm_profile* prof, double d, double k, double alpha, int32_t j,
+                     double A_periods, const sesm_params* params) {
+  if (!ctx) return SESM_EINVAL;
+  ctx->err.clear();
+  if (!prof || !params) return ctx->fail(SESM_EINVAL, "profile and params are required");
+  if (prof->n_modes < 0 || prof->n_modes > 1 << 20 || !prof->a || (prof->n_modes > 0 && !prof->b))
+    return ctx->fail(SESM_EINVAL, "invalid profile");
+  for (int m = 0; m <= prof->n_modes; ++m)
+    if (!std::isfinite(prof->a[m]) || (m > 0 && !std::isfinite(prof->b[m])))
+      return ctx->fail(SESM_EINVAL, "non-finite profile coefficient");
+  if (!(d > 0) || !std::isfinite(d) || !(k > 0) || !std::isfinite(k) || !std::isfinite(alpha))
+    return ctx->fail(SESM_EINVAL, "d and k must be positive and finite");
+  if (!(std::fabs(alpha) < k)) return ctx->fail(SESM_EINVAL, "need |alpha| < k (non-grazing incidence)");
+  if (j < 0 || j > SESM_MAX_J) return ctx->fail(SESM_EINVAL, "shift order j must be in [0, 16]");
+  if (!(A_periods > 0) || !std::isfinite(A_periods) || A_periods > 1e5)
+    return ctx->fail(SESM_EINVAL, "window half-width A (periods) must be positive");
+  sesm_params prm = *params;
+  if (prm.N < 8 || prm.N > (1 << 26)) return ctx->fail(SESM_EINVAL, "N must be in [8, 2^26]");
+  const double lambda = 2.0 * PI / k;
+  if (prm.h == 0) prm.h = 0.5 * lambda;
+  if (prm.c_window == 0) prm.c_window = 0.5;
+  if (prm.gamma_frac == 0) prm.gamma_frac = 0.5;
+  if (prm.eta == 0) prm.eta = 1e-3;
+  if (prm.L_cell == 0) prm.L_cell = 0.5 * lambda;
+  const double dx = d / prm.N;
+  if (prm.n_a == 0) prm.n_a = std::max(8, (int)std::floor(0.8 * std::min(prm.L_cell, d) / dx));
+  if (!(prm.h > 0) || !(prm.c_window > 0 && prm.c_window < 1) || !(prm.gamma_frac > 0 && prm.gamma_frac < 1) ||
+      !(prm.eta > 0) || !(prm.L_cell > 0) || prm.n_a < 2)
+    return ctx->fail(SESM_EINVAL, "invalid discretisation parameter");
+  if (prm.mode != SESM_MODE_DENSE && prm.mode != SESM_MODE_ACCEL) return ctx->fail(SESM_EINVAL, "unknown mode");
+  const double a = prm.n_a * dx;
+  if (!(a < d)) return ctx->fail(SESM_EINVAL, "singular window a = n_a dx must be < d (Remark selec_a)");
+  if (!(prm.c_window * A_periods * d > a)) return ctx->fail(SESM_EINVAL, "window plateau c A must exceed a");
+  if (hipSetDevice(ctx->device) != hipSuccess) return ctx->fail(SESM_EHIP, "hipSetDevice failed");
+
+  sesm_release_surface(ctx);
+  ctx->prm = prm;
+  Problem& P = ctx->P;
+  P = Problem();
+  P.N = prm.N;
+  P.j = j;
+  P.n_a = prm.n_a;
+  P.mode = prm.mode;
+  P.d = d;
+  P.k = k;
+  P.alpha = alpha;
+  P.beta = std::sqrt(k * k - alpha * alpha);
+  P.h = prm.h;
+  P.A_len = A_periods * d;
+  P.cA = prm.c_window * P.A_len;
+  P.dx = dx;
+  P.a = a;
+  P.gamma = prm.gamma_frac * a;
+  P.eta = prm.eta;
+  for (int m = 0; m <= SESM_MAX_J; ++m) P.wshift[m] = (m <= j) ? ((m & 1) ? -1.0 : 1.0) * binom(j, m) : 0.0;
+  P.pmax = (int)std::ceil(A_periods) + 1;
+  P.pmin = -P.pmax;
+  // U^eta = {n : |1 - e^{i beta_n h}|^j < eta}  (eq. M_eta, see oracle.rayleigh for the reading)
+  P.nU = 0;
+  if (j > 0) {
+    const double t = std::pow(prm.eta, 1.0 / j);
+    const double kmax = -std::log(1.0 - std::min(t, 0.999999)) / prm.h + 1.0;
+    const double K = std::sqrt(k * k + kmax * kmax);
+    const int nlo = (int)std::floor((-K - alpha) * d / (2 * PI)) - 1;
+    const int nhi = (int)std::ceil((K - alpha) * d / (2 * PI)) + 1;
+    for (int n = nlo; n <= nhi; ++n) {
+      const double an = alpha + 2.0 * PI * n / d;
+      const std::complex<double> b = beta_of(k, an);
+      const double fac = std::pow(std::abs(1.0 - std::exp(std::complex<double>(0.0, 1.0) * b * prm.h)), j);
+      if (fac < prm.eta) {
+        if (P.nU >= SESM_MAX_UETA) return ctx->fail(SESM_EINVAL, "more than 16 completion modes; lower eta");
+        P.U[P.nU] = n;
+        P.Ua[P.nU] = an;
+        P.Ubr[P.nU] = b.real();
+        P.Ubi[P.nU] = b.imag();
+        ++P.nU;
+      }
+    }
+  }
+  {
+    const int nlo = (int)std::floor((-k - alpha) * d / (2 * PI)) - 1;
+    const int nhi = (int)std::ceil((k - alpha) * d / (2 * PI)) + 1;
+    int first = 0, count = 0;
+    for (int n = nlo; n <= nhi; ++n) {
+      const double an = alpha + 2.0 * PI * n / d;
+      if (k * k - an * an > 0) {
+        if (count == 0) first = n;
+        ++count;
+      }
+    }
+    P.n_first = first;
+    P.n_count = count;
+  }
+
+  // surface samples
+  int rc;
+  const size_t Nb = sizeof(double) * (size_t)P.N;
+  if ((rc = sesm_alloc(ctx, (void**)&ctx->x, Nb)) || (rc = sesm_alloc(ctx, (void**)&ctx->f, Nb)) ||
+      (rc = sesm_alloc(ctx, (void**)&ctx->fp, Nb)) || (rc = sesm_alloc(ctx, (void**)&ctx->fpp, Nb)) ||
+      (rc = sesm_alloc(ctx, (void**)&ctx->J, Nb)))
+    return rc;
+  const int nm = prof->n_modes;
+  std::vector<double> ab(2 * (size_t)(nm + 1), 0.0);
+  for (int m = 0; m <= nm; ++m) {
+    ab[m] = prof->a[m];
+    ab[nm + 1 + m] = m > 0 ? prof->b[m] : 0.0;
+  }
+  double* dab = nullptr;
+  if ((rc = sesm_alloc(ctx, (void**)&dab, sizeof(double) * ab.size()))) return rc;
+  SESM_HIP(hipMemcpyAsync(dab, ab.data(), sizeof(double) * ab.size(), hipMemcpyHostToDevice, ctx->stream));
+  hipLaunchKernelGGL(k_surface, dim3((P.N + 255) / 256), dim3(256), 0, ctx->stream, P.N, d, nm, dab, dab + nm + 1,
+                     ctx->x, ctx->f, ctx->fp, ctx->fpp, ctx->J);
+  SESM_LAUNCH_CHECK();
+  // log-quadrature weights R_m, m = 0..n_a-1 (eq. local_mat; derivation in oracle.greens.log_weights)
+  {
+    std::vector<double> R(P.n_a);
+    for (int m = 0; m < P.n_a; ++m) {
+      double s = 0.0;
+      for (int q = 1; q <= P.n_a / 2; ++q) {
+        const double w = (2 * q == P.n_a) ? 0.5 : 1.0;
+        s += w * std::cos(2.0 * PI * q * m / P.n_a) / q;
+      }
+      R[m] = -2.0 * dx * s;
+    }
+    if ((rc = sesm_alloc(ctx, (void**)&ctx->logw, sizeof(double) * P.n_a))) return rc;
+    SESM_HIP(hipMemcpyAsync(ctx->logw, R.data(), sizeof(double) * P.n_a, hipMemcpyHostToDevice, ctx->stream));
+  }
+  if (P.mode == SESM_MODE_DENSE) {
+    if ((rc = sesm_dense_setup(ctx))) return rc;
+  } else {
+    if ((rc = sesm_accel_setup(ctx))) return rc;
+  }
+  SESM_HIP(hipStreamSynchronize(ctx->stream));
+  ctx->ready = true;
+  return SESM_OK;
+}
+
+int sesm_get_info(const sesm_ctx* ctx, sesm_surface_info* info) {
+  if (!ctx || !info) return SESM_EINVAL;
+  if (!ctx->ready) return SESM_ENOSURF;
+  std::memset(info, 0, sizeof(*info));
+  const Problem& P = ctx->P;
+  info->N = P.N;
+  info->n_a = P.n_a;
+  info->dx = P.dx;
+  info->a = P.a;
+  info->gamma = P.gamma;
+  info->h = P.h;
+  info->A_len = P.A_len;
+  info->mode = P.mode;
+  info->n_eta = P.nU;
+  for (int t = 0; t < P.nU && t < 16; ++t) info->U_eta[t] = P.U[t];
+  info->n_first = P.n_first;
+  info->n_count = P.n_count;
+  info->device_bytes = ctx->bytes;
+  if (P.mode == SESM_MODE_ACCEL) sesm_accel_info(ctx, info);
+  return SESM_OK;
+}
+
+int sesm_matvec(sesm_ctx* ctx, const sesm_c64* mu, sesm_c64* y) {
+  if (!ctx) return SESM_EINVAL;
+  if (!ctx->ready) return ctx->fail(SESM_ENOSURF, "no surface");
+  if (!mu || !y || (const void*)mu == (const void*)y) return ctx->fail(SESM_EINVAL, "invalid vectors");
+  SESM_HIP(hipSetDevice(ctx->device));
+  return sesm_apply(ctx, (const cplx*)mu, (cplx*)y);
+}
+
+int sesm_rhs(sesm_ctx* ctx, sesm_c64* b) {
+  if (!ctx) return SESM_EINVAL;
+  if (!ctx->ready) return ctx->fail(SESM_ENOSURF, "no surface");
+  if (!b) return ctx->fail(SESM_EINVAL, "null vector");
+  SESM_HIP(hipSetDevice(ctx->device));
+  const Problem& P = ctx->P;
+  hipLaunchKernelGGL(k_rhs, dim3((P.N + 255) / 256), dim3(256), 0, ctx->stream, P.N, P.alpha, P.beta, ctx->x,
+                     ctx->f, (cplx*)b);
+  SESM_LAUNCH_CHECK();
+  return SESM_OK;
+}
+
+int sesm_rayleigh(sesm_ctx* ctx, const sesm_c64* mu, const int32_t* orders, int32_t n_orders, sesm_c64* B_host) {
+  if (!ctx) return SESM_EINVAL;
+  if (!ctx->ready) return ctx->fail(SESM_ENOSURF, "no surface");
+  if (!mu || !orders || !B_host || n_orders < 0 || n_orders > 1 << 20) return ctx->fail(SESM_EINVAL, "bad args");
+  if (n_orders == 0) return SESM_OK;
+  SESM_HIP(hipSetDevice(ctx->device));
+  const Problem& P = ctx->P;
+  std::vector<OrderCoef> oc(n_orders);
+  for (int t = 0; t < n_orders; ++t) {
+    const int n = orders[t];
+    const double an = P.alpha + 2.0 * PI * n / P.d;
+    const std::complex<double> b = beta_of(P.k, an);
+    const std::complex<double> q = shift_quotient(b, P.h, P.j);
+    oc[t].an = an;
+    oc[t].br = b.real();
+    oc[t].bi = b.imag();
+    oc[t].qr = q.real();
+    oc[t].qi = q.imag();
+    oc[t].inU = 0;
+    for (int u = 0; u < P.nU; ++u)
+      if (P.U[u] == n) oc[t].inU = 1;
+    if (!std::isfinite(q.real()) || !std::isfinite(q.imag()))
+      return ctx->fail(SESM_EINVAL, "Rayleigh coefficient undefined (Wood order with j = 0)");
+  }
+  OrderCoef* doc = nullptr;
+  cplx* dB = nullptr;
+  SESM_HIP(hipStreamSynchronize(ctx->stream));
+  SESM_HIP(hipMalloc((void**)&doc, sizeof(OrderCoef) * n_orders));
+  if (hipMalloc((void**)&dB, sizeof(cplx) * n_orders) != hipSuccess) {
+    (void)hipFree(doc);
+    return ctx->fail(SESM_ENOMEM, "hipMalloc failed");
+  }
+  SESM_HIP(hipMemcpyAsync(doc, oc.data(), sizeof(OrderCoef) * n_orders, hipMemcpyHostToDevice, ctx->stream));
+  hipLaunchKernelGGL(k_rayleigh, dim3(n_orders), dim3(256), 0, ctx->stream, P.N, P.d, P.dx, doc, ctx->x, ctx->f,
+                     ctx->fp, ctx->J, (const cplx*)mu, dB);
+  SESM_LAUNCH_CHECK();
+  hipError_t e1 = hipMemcpyAsync(B_host, dB, sizeof(cplx) * n_orders, hipMemcpyDeviceToHost, ctx->stream);
+  hipError_t e2 = hipStreamSynchronize(ctx->stream);
+  (void)hipFree(doc);
+  (void)hipFree(dB);
+  if (e1 != hipSuccess || e2 != hipSuccess)
+    return ctx->fail(SESM_EHIP, std::string("rayleigh: ") + hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+  return SESM_OK;
+}
+
+int sesm_efficiencies(sesm_ctx* ctx, const sesm_c64* mu, int32_t* n_first, int32_t* n_count, double* e_host,
+                      int32_t e_capacity, double* energy_error) {
+  if (!ctx) return SESM_EINVAL;
+  if (!ctx->ready) return ctx->fail(SESM_ENOSURF, "no surface");
+  if (!mu || !n_first || !n_count || (e_capacity > 0 && !e_host) || e_capacity < 0)
+    return ctx->fail(SESM_EINVAL, "bad args");
+  const Problem& P = ctx->P;
+  std::vector<int32_t> ord(P.n_count);
+  for (int t = 0; t < P.n_count; ++t) ord[t] = P.n_first + t;
+  std::vector<sesm_c64> B(P.n_count);
+  int rc = sesm_rayleigh(ctx, mu, ord.data(), P.n_count, B.data());
+  if (rc) return rc;
+  double s = 0.0;
+  for (int t = 0; t < P.n_count; ++t) {
+    const double an = P.alpha + 2.0 * PI * ord[t] / P.d;
+    const double bn = std::sqrt(std::fabs(P.k * P.k - an * an));
+    const double e = bn / P.beta * (B[t].re * B[t].re + B[t].im * B[t].im);
+    s += e;
+    if (t < e_capacity) e_host[t] = e;
+  }
+  *n_first = P.n_first;
+  *n_count = P.n_count;
+  if (energy_error) *energy_error = 1.0 - s;
+  return SESM_OK;
+}
+
+int sesm_diag_hankel(sesm_ctx* ctx, const double* x, int32_t n, sesm_c64* h0, sesm_c64* h1) {
+  if (!ctx) return SESM_EINVAL;
+  if (!x || !h0 || !h1 || n < 0) return ctx->fail(SESM_EINVAL, "bad args");
+  if (n == 0) return SESM_OK;
+  SESM_HIP(hipSetDevice(ctx->device));
+  hipLaunchKernelGGL(k_diag_hankel, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, n, x, (cplx*)h0, (cplx*)h1);
+  SESM_LAUNCH_CHECK();
+  return SESM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,277 @@
+// GMRES (Algorithm 1: "Run GMRES iterations, using the forward map").
+//
+// Device-resident Krylov basis V[(m+1) x N]; classical Gram-Schmidt applied
+// twice (CGS2) with tall-skinny dot-product kernels (each kernel reads every
+// basis vector once, coalesced); Givens rotations of the small Hessenberg
+// matrix on the host, which reads one column per iteration.
+#include <cmath>
+#include <complex>
+#include <vector>
+
+#include "sesm_impl.h"
+
+namespace {
+
+constexpr int VT = 8;         // basis vectors per dot-product block
+constexpr int NCHUNK = 240;   // N-chunks per dot product (about one per CU)
+
+// part[v * NCHUNK + c] = sum_{i in chunk c} conj(V_v[i]) w[i], v in [0, nv)
+__global__ __launch_bounds__(256) void k_dots(int N, int nv, const cplx* __restrict__ V, int64_t ldv,
+                                              const cplx* __restrict__ w, cplx* __restrict__ part) {
+  __shared__ cplx sh[VT][4];
+  const int c = blockIdx.x, v0 = blockIdx.y * VT;
+  const int per = (N + NCHUNK - 1) / NCHUNK;
+  const int lo = c * per, hi = min(N, lo + per);
+  cplx acc[VT];
+#pragma unroll
+  for (int t = 0; t < VT; ++t) acc[t] = cplx{0.0, 0.0};
+  for (int i = lo + threadIdx.x; i < hi; i += 256) {
+    const cplx wi = w[i];
+#pragma unroll
+    for (int t = 0; t < VT; ++t)
+      if (v0 + t < nv) acc[t] += cmul_conj(V[(int64_t)(v0 + t) * ldv + i], wi);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int t = 0; t < VT; ++t) {
+    const cplx s = wave_sum(acc[t]);
+    if (lane == 0) sh[t][wv] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < VT && v0 + (int)threadIdx.x < nv) {
+    const int t = threadIdx.x;
+    part[(int64_t)(v0 + t) * NCHUNK + c] = sh[t][0] + sh[t][1] + sh[t][2] + sh[t][3];
+  }
+}
+
+// h[v] (=|+=) sum_c part[v * NCHUNK + c]; one wave per v
+__global__ void k_dots_final(int nv, const cplx* __restrict__ part, cplx* __restrict__ h, int accumulate) {
+  const int v = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (v >= nv) return;
+  cplx s = cplx{0.0, 0.0};
+  for (int c = lane; c < NCHUNK; c += 64) s += part[(int64_t)v * NCHUNK + c];
+  s = wave_sum(s);
+  if (lane == 0) h[v] = accumulate ? h[v] + s : s;
+}
+
+// w[i] -= sum_{v < nv} V_v[i] h[v]
+__global__ __launch_bounds__(256) void k_update(int N, int nv, const cplx* __restrict__ V, int64_t ldv,
+                                                const cplx* __restrict__ h, cplx* __restrict__ w) {
+  extern __shared__ cplx hs[];
+  for (int v = threadIdx.x; v < nv; v += 256) hs[v] = h[v];
+  __syncthreads();
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
+  cplx s = w[i];
+  for (int v = 0; v < nv; ++v) s -= V[(int64_t)v * ldv + i] * hs[v];
+  w[i] = s;
+}
+
+// x[i] += sum_{v < nv} V_v[i] y[v]
+__global__ __launch_bounds__(256) void k_combine(int N, int nv, const cplx* __restrict__ V, int64_t ldv,
+                                                 const cplx* __restrict__ y, cplx* __restrict__ x, int add) {
+  extern __shared__ cplx ys[];
+  for (int v = threadIdx.x; v < nv; v += 256) ys[v] = y[v];
+  __syncthreads();
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
+  cplx s = add ? x[i] : cplx{0.0, 0.0};
+  for (int v = 0; v < nv; ++v) s += V[(int64_t)v * ldv + i] * ys[v];
+  x[i] = s;
+}
+
+__global__ __launch_bounds__(256) void k_norm2_part(int N, const cplx* __restrict__ w, double* __restrict__ part) {
+  __shared__ cplx sh[4];
+  const int per = (N + NCHUNK - 1) / NCHUNK;
+  const int lo = blockIdx.x * per, hi = min(N, lo + per);
+  double s = 0.0;
+  for (int i = lo + threadIdx.x; i < hi; i += 256) s += abs2(w[i]);
+  const cplx r = block_sum<256>(cplx{s, 0.0}, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = r.re;
+}
+
+// out = cplx(sqrt(sum part), 0)
+__global__ void k_norm_final(const double* __restrict__ part, cplx* __restrict__ out) {
+  const int lane = threadIdx.x;
+  double s = 0.0;
+  for (int c = lane; c < NCHUNK; c += 64) s += part[c];
+  s = wave_sum(cplx{s, 0.0}).re;
+  if (lane == 0) *out = cplx{sqrt(s), 0.0};
+}
+
+// dst = src / norm (norm read from device; zero norm leaves zeros)
+__global__ void k_scale(int N, const cplx* src, const cplx* __restrict__ nrm, cplx* dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double n = nrm->re;
+  const double s = n > 0 ? 1.0 / n : 0.0;
+  dst[i] = s * src[i];
+}
+
+// r = b - r
+__global__ void k_sub_from(int N, const cplx* __restrict__ b, cplx* __restrict__ r) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  r[i] = b[i] - r[i];
+}
+
+int ensure_workspace(sesm_ctx* ctx, int m) {
+  const int N = ctx->P.N;
+  if (ctx->V && ctx->V_cols >= m + 1) return SESM_OK;
+  auto drop = [&](void* p) {
+    if (!p) return;
+    for (size_t t = 0; t < ctx->owned.size(); ++t)
+      if (ctx->owned[t] == p) {
+        ctx->owned.erase(ctx->owned.begin() + t);
+        break;
+      }
+    (void)hipFree(p);
+  };
+  (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->V) ctx->bytes -= (int64_t)ctx->V_cols * N * (int64_t)sizeof(cplx);
+  drop(ctx->V);
+  ctx->V = nullptr;
+  ctx->V_cols = 0;
+  int rc = sesm_alloc(ctx, (void**)&ctx->V, sizeof(cplx) * (size_t)(m + 1) * N);
+  if (rc) return rc;
+  ctx->V_cols = m + 1;
+  if (!ctx->hcol) {
+    if ((rc = sesm_alloc(ctx, (void**)&ctx->hcol, sizeof(cplx) * 4200))) return rc;
+    if ((rc = sesm_alloc(ctx, (void**)&ctx->hpart, sizeof(cplx) * (size_t)4200 * NCHUNK))) return rc;
+    if ((rc = sesm_alloc(ctx, (void**)&ctx->ybuf, sizeof(cplx) * 4200))) return rc;
+    if ((rc = sesm_alloc(ctx, (void**)&ctx->wtmp, sizeof(cplx) * (size_t)N))) return rc;
+    if (hipHostMalloc((void**)&ctx->hhost, sizeof(cplx) * 4200, 0) != hipSuccess)
+      return ctx->fail(SESM_ENOMEM, "hipHostMalloc failed");
+  }
+  return SESM_OK;
+}
+
+}  // namespace
+
+extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out, double tol, int32_t max_iter,
+                          int32_t restart, sesm_solve_info* info) {
+  if (!ctx) return SESM_EINVAL;
+  if (!ctx->ready) return ctx->fail(SESM_ENOSURF, "no surface");
+  if (!mu_out || !(tol > 0) || max_iter < 1 || max_iter > 100000 || restart < 0)
+    return ctx->fail(SESM_EINVAL, "bad solve arguments");
+  SESM_HIP(hipSetDevice(ctx->device));
+  const int N = ctx->P.N;
+  int m = (restart == 0 || restart > max_iter) ? max_iter : restart;
+  if (m > 4000) return ctx->fail(SESM_EINVAL, "Krylov dimension above 4000; use restart");
+  int rc = ensure_workspace(ctx, m);
+  if (rc) return rc;
+  hipStream_t st = ctx->stream;
+  const int nb = (N + 255) / 256;
+  cplx* x = (cplx*)mu_out;
+  cplx* V = ctx->V;
+  const int64_t ldv = N;
+  double* npart = (double*)ctx->hpart;  // reuse for norm partials
+
+  // right-hand side (incident field written into the workspace vector when NULL)
+  const cplx* b = (const cplx*)b_in;
+  if (!b) {
+    if ((rc = sesm_rhs(ctx, (sesm_c64*)ctx->wtmp))) return rc;
+    b = ctx->wtmp;
+  }
+  auto norm_to_host = [&](const cplx* v, double* out) -> int {
+    hipLaunchKernelGGL(k_norm2_part, dim3(NCHUNK), dim3(256), 0, st, N, v, npart);
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(64), 0, st, npart, ctx->hcol);
+    SESM_LAUNCH_CHECK();
+    SESM_HIP(hipMemcpyAsync(ctx->hhost, ctx->hcol, sizeof(cplx), hipMemcpyDeviceToHost, st));
+    SESM_HIP(hipStreamSynchronize(st));
+    *out = ctx->hhost[0].re;
+    return SESM_OK;
+  };
+  double bnorm = 0.0;
+  if ((rc = norm_to_host(b, &bnorm))) return rc;
+  SESM_HIP(hipMemsetAsync(x, 0, sizeof(cplx) * (size_t)N, st));
+  sesm_solve_info inf{0, 0.0, 0};
+  if (bnorm == 0.0) {
+    inf.converged = 1;
+    if (info) *info = inf;
+    return SESM_OK;
+  }
+  std::vector<std::complex<double>> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1);
+  int total = 0;
+  double res = 1.0;
+  bool first = true;
+  while (total < max_iter) {
+    // r = b - A x  (x = 0 on the first cycle)
+    double beta0;
+    if (first) {
+      SESM_HIP(hipMemcpyAsync(V, b, sizeof(cplx) * (size_t)N, hipMemcpyDeviceToDevice, st));
+      first = false;
+    } else {
+      if ((rc = sesm_apply(ctx, x, V))) return rc;
+      hipLaunchKernelGGL(k_sub_from, dim3(nb), dim3(256), 0, st, N, b, V);
+      SESM_LAUNCH_CHECK();
+    }
+    if ((rc = norm_to_host(V, &beta0))) return rc;
+    res = beta0 / bnorm;
+    if (res <= tol) break;
+    hipLaunchKernelGGL(k_scale, dim3(nb), dim3(256), 0, st, N, V, ctx->hcol, V);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta0;
+    int it = 0;
+    for (; it < m && total < max_iter; ++it, ++total) {
+      cplx* w = V + (int64_t)(it + 1) * ldv;
+      if ((rc = sesm_apply(ctx, V + (int64_t)it * ldv, w))) return rc;
+      const int nv = it + 1;
+      const dim3 gd(NCHUNK, (nv + VT - 1) / VT);
+      for (int pass = 0; pass < 2; ++pass) {
+        hipLaunchKernelGGL(k_dots, gd, dim3(256), 0, st, N, nv, V, ldv, w, ctx->hpart);
+        hipLaunchKernelGGL(k_dots_final, dim3((nv + 3) / 4), dim3(256), 0, st, nv, ctx->hpart, ctx->hcol, pass);
+        hipLaunchKernelGGL(k_dots_final, dim3((nv + 3) / 4), dim3(256), 0, st, nv, ctx->hpart, ctx->ybuf, 0);
+        hipLaunchKernelGGL(k_update, dim3(nb), dim3(256), sizeof(cplx) * nv, st, N, nv, V, ldv, ctx->ybuf, w);
+      }
+      hipLaunchKernelGGL(k_norm2_part, dim3(NCHUNK), dim3(256), 0, st, N, w, npart);
+      hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(64), 0, st, npart, ctx->hcol + nv);
+      hipLaunchKernelGGL(k_scale, dim3(nb), dim3(256), 0, st, N, w, ctx->hcol + nv, w);
+      SESM_LAUNCH_CHECK();
+      SESM_HIP(hipMemcpyAsync(ctx->hhost, ctx->hcol, sizeof(cplx) * (nv + 1), hipMemcpyDeviceToHost, st));
+      SESM_HIP(hipStreamSynchronize(st));
+      std::complex<double>* col = &H[(size_t)it * (m + 1)];
+      for (int t = 0; t <= nv; ++t) col[t] = std::complex<double>(ctx->hhost[t].re, ctx->hhost[t].im);
+      for (int t = 0; t < it; ++t) {  // previous rotations [[conj c, conj s], [-s, c]]
+        const std::complex<double> u = col[t], v = col[t + 1];
+        col[t] = std::conj(cs[t]) * u + std::conj(sn[t]) * v;
+        col[t + 1] = -sn[t] * u + cs[t] * v;
+      }
+      const std::complex<double> a = col[it], bb = col[it + 1];
+      const double r = std::sqrt(std::norm(a) + std::norm(bb));
+      cs[it] = r != 0 ? a / r : 1.0;
+      sn[it] = r != 0 ? bb / r : 0.0;
+      col[it] = r;
+      col[it + 1] = 0.0;
+      g[it + 1] = -sn[it] * g[it];
+      g[it] = std::conj(cs[it]) * g[it];
+      res = std::abs(g[it + 1]) / bnorm;
+      if (res <= tol || r == 0.0) {
+        ++it;
+        ++total;
+        break;
+      }
+    }
+    // y = R^{-1} g, x += V y
+    const int nv = it;
+    std::vector<std::complex<double>> y(nv);
+    for (int t = nv - 1; t >= 0; --t) {
+      std::complex<double> s = g[t];
+      for (int u = t + 1; u < nv; ++u) s -= H[(size_t)u * (m + 1) + t] * y[u];
+      y[t] = s / H[(size_t)t * (m + 1) + t];
+    }
+    for (int t = 0; t < nv; ++t) ctx->hhost[t] = cplx{y[t].real(), y[t].imag()};
+    SESM_HIP(hipMemcpyAsync(ctx->ybuf, ctx->hhost, sizeof(cplx) * nv, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), sizeof(cplx) * nv, st, N, nv, V, ldv, ctx->ybuf, x, 1);
+    SESM_LAUNCH_CHECK();
+    SESM_HIP(hipStreamSynchronize(st));
+    if (res <= tol) break;
+  }
+  inf.iters = total;
+  inf.rel_residual = res;
+  inf.converged = res <= tol ? 1 : 0;
+  if (info) *info = inf;
+  if (!inf.converged) return ctx->fail(SESM_ENOCONV, "GMRES did not reach the tolerance");
+  return SESM_OK;
+}
