@@ -1,0 +1,167 @@
+"""Benchmark: GMRES solves/s and matvec Munknowns/s on the near-grazing Wood
+workload (Gaussian random surface, d = 100 wavelengths, rms 1 wavelength,
+89 degree incidence, k on a Wood anomaly, N = 32768, j = 8, A = 40 periods).
+
+One step = one pass of the whole path: set_surface (Algorithm 2), GMRES solve
+with the forward map (Algorithms 1 and 3) and the efficiencies.  Inputs are
+synthetic (seeded surface coefficients).  Prints one JSON line.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode accel|dense]
+                       [--N 32768] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GMRES solves/s and matvec Munknowns/s at N=32768, efficiency err ≤1e-6"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--mode", choices=["accel", "dense"], default=os.environ.get("SESM_BENCH_MODE", "dense"))
+    ap.add_argument("--N", type=int, default=32768)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--max-iter", type=int, default=3000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(wl, N, target_s=15.0):
+    """Time the oracle (as is) on a bounded sample: dense operator rows of the
+    same workload, assembled and applied on the host."""
+    import numpy as np
+    from oracle import dense
+    import workloads as W
+    disc = dense.Discretization(wl, N=N)
+    mu = W.random_density(N, 1)
+    rows_done, t0 = 0, time.perf_counter()
+    r = 0
+    while time.perf_counter() - t0 < target_s and rows_done < N:
+        dense.matvec_rows(disc, mu, [r])
+        rows_done += 1
+        r = (r + 997) % N
+    dt = time.perf_counter() - t0
+    per_row = dt / rows_done
+    return {
+        "value": 1.0 / (per_row * N),
+        "unit": "solves/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": "%d dense operator rows of the N=%d workload in %.1f s; a solve needs all N rows "
+                  "(assembly dominates), GMRES time not added" % (rows_done, N, dt),
+        "matvec_munknowns_per_s": rows_done / dt / 1e6,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1707_04950_amd as lib
+    import workloads as W
+
+    wl = W.config_grazing_wood(args.N)
+    mode = lib.MODE_ACCEL if args.mode == "accel" else lib.MODE_DENSE
+    s = lib.Solver(0)
+    n_a = max(8, int(math.floor(0.8 * min(wl.L, wl.d) / wl.dx)))
+
+    def setup():
+        s.set_surface(np.asarray(wl.a_coef), np.asarray(wl.b_coef), wl.d, wl.k, wl.alpha, wl.j, wl.A, args.N,
+                      h=wl.h, c=wl.c, n_a=n_a, gamma_frac=wl.gamma_frac, eta=wl.eta, mode=mode, L=wl.L)
+
+    def step():
+        t0 = time.perf_counter()
+        setup()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        mu, info = s.solve(tol=args.tol, max_iter=args.max_iter, allow_noconv=True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        n, e, eps = s.efficiencies(mu)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        return dict(setup=t1 - t0, solve=t2 - t1, eff=t3 - t2, iters=info["iters"], res=info["rel_residual"],
+                    eps=eps, n_orders=len(n))
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    ms_per_step = 1e3 * total / args.steps
+
+    # steady-state matvec: events on the library's stream (torch's current stream)
+    mu = torch.from_numpy(W.random_density(args.N, 1)).cuda()
+    y = torch.empty_like(mu)
+    for _ in range(5):
+        s.matvec(mu, y)
+    reps = 30
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        s.matvec(mu, y)
+    ev1.record()
+    torch.cuda.synchronize()
+    mv_s = ev0.elapsed_time(ev1) / 1e3 / reps
+
+    inf = s.info()
+    if mode == lib.MODE_DENSE:
+        # one kernel per matvec: the row-parallel complex GEMV over the stored operator
+        bytes_alg = 16.0 * args.N * args.N + 2 * 16.0 * args.N
+        roof = {"kernel": "k_gemv_rows (dense operator GEMV)", "bound": "hbm",
+                "achieved": bytes_alg / mv_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    else:
+        bytes_alg = float(inf.get("device_bytes", 0))
+        roof = {"kernel": "accelerated matvec (all stages)", "bound": "hbm",
+                "achieved": bytes_alg / mv_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+
+    out = {
+        "metric": METRIC,
+        "value": args.steps / total,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "N": args.N, "d_over_lambda": wl.d * wl.k / (2 * math.pi),
+                   "theta_deg": wl.theta_deg, "j": wl.j, "h": wl.h, "A_periods": wl.A, "mode": args.mode,
+                   "gmres_tol": args.tol},
+        "matvec_munknowns_per_s": args.N / mv_s / 1e6,
+        "matvec_ms": mv_s * 1e3,
+        "gmres_iters": recs[-1]["iters"],
+        "gmres_rel_residual": recs[-1]["res"],
+        "energy_balance_error": recs[-1]["eps"],
+        "phase_s": {k: float(np.mean([r[k] for r in recs])) for k in ("setup", "solve", "eff")},
+        "roofline": roof,
+    }
+    s.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.N)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -36,10 +36,10 @@ __global__ __launch_bounds__(256) void k_dense_assemble(KParams K, const double*
                                                         const double* __restrict__ J,
                                                         const double* __restrict__ logw, cplx* __restrict__ M) {
   const int lane = threadIdx.x & 63;
-  const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int64_t NN = (int64_t)K.N * K.N;
-  if (e >= NN) return;  // wave-uniform
-  const int i = (int)(e / K.N), l = (int)(e % K.N);
+  const int i = blockIdx.y;                             // row (target node)
+  const int l = blockIdx.x * 4 + (threadIdx.x >> 6);    // column (source node), one per wave
+  if (l >= K.N) return;  // wave-uniform
+  const int64_t e = (int64_t)i * K.N + l;
   const double X0 = x[i] - x[l], Y = f[i] - f[l], fps = fp[l];
   cplx acc = cplx{0.0, 0.0};
   for (int p = K.pmin + lane; p <= K.pmax; p += 64) {
@@ -97,9 +97,8 @@ int sesm_dense_setup(sesm_ctx* ctx) {
   int rc = sesm_alloc(ctx, (void**)&ctx->Mdense, sizeof(cplx) * (size_t)NN);
   if (rc) return rc;
   const KParams K = ctx->kparams();
-  const int64_t nblk = (NN + 3) / 4;
-  if (nblk > 0x7fffffffLL) return ctx->fail(SESM_EINVAL, "dense operator too large");
-  hipLaunchKernelGGL(k_dense_assemble, dim3((unsigned)nblk), dim3(256), 0, ctx->stream, K, ctx->x, ctx->f, ctx->fp,
+  if (P.N > 65535) return ctx->fail(SESM_EINVAL, "dense mode supports N <= 65535");
+  hipLaunchKernelGGL(k_dense_assemble, dim3((P.N + 3) / 4, P.N), dim3(256), 0, ctx->stream, K, ctx->x, ctx->f, ctx->fp,
                      ctx->fpp, ctx->J, ctx->logw, ctx->Mdense);
   SESM_LAUNCH_CHECK();
   return SESM_OK;
