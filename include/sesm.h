@@ -78,10 +78,13 @@ typedef struct {
   int32_t mode;       /* SESM_MODE_DENSE (default) or SESM_MODE_ACCEL                     */
   double L_cell;      /* accelerator cell side L, eq. (L_constr); default 0.5 * 2 pi / k  */
   int32_t n_side;     /* accelerator: equivalent-source grid intervals per cell side      */
-  int32_t n_ext;      /* accelerator: extra equivalent-source points beyond each corner    */
+  int32_t n_ext;      /* accelerator: extra equivalent-source points beyond each corner;
+                         0 selects 1, a negative value selects none                        */
   int32_t n_coll;     /* accelerator: collocation points per side of the 3L square, eq. (eq_source_point) */
   int32_t n_plw;      /* accelerator: plane waves per cell, eq. (planewave)               */
-  int32_t reserved[8];
+  int32_t near_ring;  /* accelerator: columns on each side of a cell treated directly
+                         (near field); default 1, at most 3                              */
+  int32_t reserved[7];
 } sesm_params;
 
 typedef struct {
@@ -102,6 +105,7 @@ typedef struct {
   /* accelerator geometry (zeros in dense mode) */
   int32_t n_x, n_y, n_cells_occupied, stencil_rows;
   double L, y0, delta;
+  int64_t near_entries;       /* stored near-field entries (accelerated mode) */
   int64_t device_bytes;       /* device memory held by the context          */
 } sesm_surface_info;
 
@@ -164,6 +168,16 @@ SESM_API int sesm_get_info(const sesm_ctx* ctx, sesm_surface_info* info);
 
 /* Message of the last failing call on ctx ("" if none).  Never NULL. */
 SESM_API const char* sesm_last_error(const sesm_ctx* ctx);
+
+/* Diagnostic (accelerated mode): apply the forward map to mu (device, N) and
+ * copy one intermediate result into out (device, out_len sesm_c64):
+ *   which = 0: far-field (non-intersecting) contribution at the N nodes;
+ *   1: phi^all on the horizontal grid, row-major [n_y + 1][n_x n_s]
+ *      (eq. large_convolution_per_grid);  2: phi^all on the vertical grid
+ *      [n_y n_s + 1 + 2 n_ext][n_x];  3: per-cell equivalent-source densities
+ *      [2 sets][n_x n_y cells][xi (n_eq), zeta (n_eq)] (eq. eq_source_point).
+ * Synchronises the stream.  Returns SESM_EINVAL if out_len is too small. */
+SESM_API int sesm_diag_accel(sesm_ctx* ctx, const sesm_c64* mu, int32_t which, sesm_c64* out, int64_t out_len);
 
 /* Diagnostic: evaluate the library's FP64 Hankel functions H0^(1)(x),
  * H1^(1)(x) (used by every Green-function kernel, eq. free_space) at n

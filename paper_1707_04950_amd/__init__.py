@@ -34,7 +34,7 @@ class Params(ctypes.Structure):
                 ("n_a", ctypes.c_int32), ("gamma_frac", ctypes.c_double), ("eta", ctypes.c_double),
                 ("mode", ctypes.c_int32), ("L_cell", ctypes.c_double), ("n_side", ctypes.c_int32),
                 ("n_ext", ctypes.c_int32), ("n_coll", ctypes.c_int32), ("n_plw", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 8)]
+                ("near_ring", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -48,7 +48,7 @@ class SurfaceInfo(ctypes.Structure):
                 ("U_eta", ctypes.c_int32 * 16), ("n_first", ctypes.c_int32), ("n_count", ctypes.c_int32),
                 ("n_x", ctypes.c_int32), ("n_y", ctypes.c_int32), ("n_cells_occupied", ctypes.c_int32),
                 ("stencil_rows", ctypes.c_int32), ("L", ctypes.c_double), ("y0", ctypes.c_double),
-                ("delta", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
+                ("delta", ctypes.c_double), ("near_entries", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
 
 
 _lib = None
@@ -79,6 +79,7 @@ def load_library(path=LIB_PATH):
         "sesm_get_info": (ctypes.c_int, [_P, ctypes.POINTER(SurfaceInfo)]),
         "sesm_last_error": (ctypes.c_char_p, [_P]),
         "sesm_diag_hankel": (ctypes.c_int, [_P, _P, _I, _P, _P]),
+        "sesm_diag_accel": (ctypes.c_int, [_P, _P, _I, _P, ctypes.c_int64]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -135,7 +136,7 @@ class Solver:
         return rc
 
     def set_surface(self, a_coef, b_coef, d, k, alpha, j, A, N, h=0.0, c=0.0, n_a=0, gamma_frac=0.0,
-                    eta=0.0, mode=MODE_DENSE, L=0.0, n_side=0, n_ext=0, n_coll=0, n_plw=0):
+                    eta=0.0, mode=MODE_DENSE, L=0.0, n_side=0, n_ext=0, n_coll=0, n_plw=0, near_ring=0):
         a = np.ascontiguousarray(a_coef, dtype=np.float64)
         b = np.zeros_like(a)
         bb = np.asarray(b_coef, dtype=np.float64)
@@ -144,7 +145,7 @@ class Solver:
         prof = Profile(len(a) - 1, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                        b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         prm = Params(N=N, h=h, c_window=c, n_a=n_a, gamma_frac=gamma_frac, eta=eta, mode=mode, L_cell=L,
-                     n_side=n_side, n_ext=n_ext, n_coll=n_coll, n_plw=n_plw)
+                     n_side=n_side, n_ext=n_ext, n_coll=n_coll, n_plw=n_plw, near_ring=near_ring)
         self._check(self.lib.sesm_set_surface(self.h, ctypes.byref(prof), d, k, alpha, j, A, ctypes.byref(prm)))
         self.N = N
 
@@ -191,6 +192,11 @@ class Solver:
         self._check(self.lib.sesm_rayleigh(self.h, _ptr(mu), o.ctypes.data_as(ctypes.POINTER(_I)), len(o),
                                            ctypes.c_void_p(B.ctypes.data)))
         return B
+
+    def diag_accel(self, mu, which, length):
+        out = self._torch.empty(length, dtype=self._torch.complex128, device=self.device)
+        self._check(self.lib.sesm_diag_accel(self.h, _ptr(mu), which, _ptr(out), length))
+        return out
 
     def diag_hankel(self, x):
         torch = self._torch

@@ -1,8 +1,997 @@
-// Shifted-equivalent-source FFT accelerator (Sec. 5): placeholder until the
-// accelerated forward map lands; dense mode is the only operator for now.
-#include "sesm_impl.h"
+// Shifted-equivalent-source FFT accelerator (Sec. 5; Algorithms 2 and 3).
+//
+// Geometry: square cells of side L = d / n_x (n_x 5-smooth, >= 3), half-open
+// (a1,b1] x (a2,b2] (Remark cell_def), columns from x0 = -dx/2, rows from y0
+// below the surface to y0 + n_y L above it.  Equivalent-source grid spacing
+// delta = L / n_s; each cell carries a horizontal set (bottom and top sides)
+// and a vertical set (left and right sides), each side extended by n_e grid
+// points beyond the corners (eq. eq_mesh), monopoles plus dipoles with the
+// fixed normals (0,1) / (1,0) so that densities of neighbouring cells add at
+// shared grid points (eq. sum_eqsources).
+//
+// Near/far split: the near (direct) set of a target cell is every source of
+// the 2 ring + 1 columns around it (ring = 1 by default) - a superset of the
+// paper's intersecting cells
+// L(q) (eq. small_convolution); all other cells are non-intersecting because
+// the target cell lies outside their 3L squares and all downward shifts
+// (eq. S_jq_hat).  On a graph surface the near set of a column is one cyclic
+// band of nodes, stored as dense FP64 blocks (the HBM-bound part).
+//
+// Forward map, one stream, in order:
+//   k_near_apply    y  = near band (intersecting part eq. final_correction_0,
+//                        singular part eq. local_mat, 1/2 I)
+//   k_p2e_apply     (xi, zeta)^{q,lambda} = P_q^lambda mu_q   (EqSources, eq. eq_source_point)
+//   k_merge         twisted merged grids                     (GlobalEqSMerge, eq. sum_eqsources)
+//   k_fft_rows      FFT along x of both grids                (GlobalFFT, eq. large_convolution_per_grid)
+//   k_yconv         kernel-spectrum x sources, direct in y
+//   k_fft_rows      inverse FFT, untwist -> phi^all
+//   k_cells_far     boundary values - local correction        (LocalEqSMerge, LocalFFT, LocalSubtract,
+//                   -> plane-wave weights -> surface values      Combine-lambda, PlaneWaveWeights,
+//                                                                NonIntersecting; eqs. psi_na_sum,
+//                                                                combine_psi_pna, planewave, plwave_QR)
+//   k_modes_*       completion modes D_M                     (EvalModes, eq. M_eta)
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <vector>
 
-int sesm_accel_setup(sesm_ctx* ctx) { return ctx->fail(SESM_EINVAL, "accelerated mode not built yet"); }
-int sesm_accel_matvec(sesm_ctx* ctx, const cplx*, cplx*) { return ctx->fail(SESM_EINVAL, "accelerated mode not built yet"); }
-void sesm_accel_free(sesm_ctx*) {}
-void sesm_accel_info(const sesm_ctx*, sesm_surface_info*) {}
+#include "sesm_fft.h"
+#include "sesm_kernels.h"
+
+using C = std::complex<double>;
+
+struct AccelOp {
+  // geometry
+  int n_x = 0, n_y = 0, n_s = 0, n_e = 0, n_coll = 0, n_plw = 0, ring = 1;
+  int n_side = 0, n_eq = 0, n_bH = 0, n_bdry = 0, n_cells = 0, n_occ = 0, n_off = 0;
+  double L = 0, delta = 0, x0 = 0, y0 = 0;
+  int nXH = 0, nYH = 0, nXV = 0, nYV = 0;
+  int64_t near_entries = 0;
+  // device data
+  int *occ_cell = nullptr, *occ_off = nullptr, *perm = nullptr, *col_lo = nullptr, *col_w = nullptr;
+  int64_t* near_off = nullptr;
+  unsigned char* occ_flag = nullptr;
+  cplx *p2e = nullptr, *nearblk = nullptr, *dens = nullptr;
+  cplx *gH = nullptr, *gV = nullptr, *fH = nullptr, *fV = nullptr, *phH = nullptr, *phV = nullptr;
+  cplx *specH = nullptr, *specV = nullptr, *W = nullptr;
+  cplx *pplw = nullptr;  // plane-wave least squares: Q^H (n_plw x n_bdry) then R (n_plw x n_plw)
+  cplx *pinv = nullptr;  // equivalent-source least squares, per set: Q^H (2n_eq x 4n_coll) then R
+  cplx *twxH = nullptr, *twxV = nullptr, *utwH = nullptr, *utwV = nullptr;  // e^{-i alpha x}, e^{+i alpha x}
+  double* dirs = nullptr;
+  cplx* mode_part = nullptr;
+  cplx* yfar = nullptr;  // diagnostic copy of the far-field contribution
+  FftPlan planH, planV;
+};
+
+namespace {
+
+constexpr double PI = 3.14159265358979323846;
+constexpr int NCH_MODES = 240;
+
+int smooth5_at_least(int n) {
+  for (;; ++n) {
+    int m = n;
+    for (int p : {2, 3, 5})
+      while (m % p == 0) m /= p;
+    if (m == 1) return n;
+  }
+}
+
+// Least squares by Householder QR (the "QR-based solution" of eqs.
+// eq_source_point and plwave_QR): factors the m x n matrix A (row-major,
+// m >= n) as A = Q R and returns the first n rows of Q^H (n x m) and the upper
+// triangle R (n x n), both row-major.  Solutions are then obtained by
+// back-substitution R x = Q^H b for each right-hand side, never through an
+// explicit pseudo-inverse (which loses the small residual when A is
+// ill-conditioned).  False if A is rank deficient.
+bool ls_qr(int m, int n, std::vector<C> A, std::vector<C>& Qh_out, std::vector<C>& R_out) {
+  std::vector<std::vector<C>> V(n);
+  for (int k = 0; k < n; ++k) {
+    double nx = 0;
+    for (int i = k; i < m; ++i) nx += std::norm(A[(size_t)i * n + k]);
+    nx = std::sqrt(nx);
+    if (!(nx > 0)) return false;
+    const C x0 = A[(size_t)k * n + k];
+    const C ph = std::abs(x0) > 0 ? x0 / std::abs(x0) : C(1.0, 0.0);
+    const C alpha = -ph * nx;
+    std::vector<C> v(m - k);
+    for (int i = k; i < m; ++i) v[i - k] = A[(size_t)i * n + k];
+    v[0] -= alpha;
+    double vn = 0;
+    for (const C& t : v) vn += std::norm(t);
+    vn = std::sqrt(vn);
+    for (C& t : v) t /= vn;
+    for (int c = k; c < n; ++c) {
+      C s = 0;
+      for (int i = k; i < m; ++i) s += std::conj(v[i - k]) * A[(size_t)i * n + c];
+      for (int i = k; i < m; ++i) A[(size_t)i * n + c] -= 2.0 * v[i - k] * s;
+    }
+    V[k] = v;
+  }
+  // rows 0..n-1 of Q^H = H_{n-1} ... H_0 applied to the identity
+  std::vector<C> Qh((size_t)m * m, 0.0);
+  for (int i = 0; i < m; ++i) Qh[(size_t)i * m + i] = 1.0;
+  for (int k = 0; k < n; ++k) {
+    const std::vector<C>& v = V[k];
+    for (int c = 0; c < m; ++c) {
+      C s = 0;
+      for (int i = k; i < m; ++i) s += std::conj(v[i - k]) * Qh[(size_t)i * m + c];
+      for (int i = k; i < m; ++i) Qh[(size_t)i * m + c] -= 2.0 * v[i - k] * s;
+    }
+  }
+  Qh_out.assign(Qh.begin(), Qh.begin() + (size_t)n * m);
+  R_out.assign((size_t)n * n, 0.0);
+  for (int r = 0; r < n; ++r) {
+    if (std::abs(A[(size_t)r * n + r]) == 0) return false;
+    for (int c = r; c < n; ++c) R_out[(size_t)r * n + c] = A[(size_t)r * n + c];
+  }
+  return true;
+}
+
+// Geometry of one cell, relative to its lower-left corner (all integer-indexed).
+struct CellGeo {
+  int n_s, n_e, n_side, n_eq, n_coll;
+  double L, delta;
+  // equivalent-source point s of set lam (0 = H, 1 = V)
+  __host__ __device__ void eq_point(int lam, int s, double* px, double* py) const {
+    const int side = s / n_side, i = s % n_side - n_e;
+    if (lam == 0) {
+      *px = i * delta;
+      *py = side * L;
+    } else {
+      *px = side * L;
+      *py = i * delta;
+    }
+  }
+  // collocation point c on the boundary of the 3L square (n_coll per side)
+  __host__ __device__ void coll_point(int c, double* px, double* py) const {
+    const int side = c / n_coll, i = c % n_coll;
+    const double t = (i + 0.5) / n_coll * 3.0 * L - L;
+    if (side == 0) { *px = t; *py = -L; }
+    else if (side == 1) { *px = t; *py = 2.0 * L; }
+    else if (side == 2) { *px = -L; *py = t; }
+    else { *px = 2.0 * L; *py = t; }
+  }
+  // boundary point b: horizontal sides first (corners included), then vertical sides
+  __host__ __device__ void bdry_point(int b, double* px, double* py) const {
+    const int nh = 2 * (n_s + 1);
+    if (b < nh) {
+      const int iy = b / (n_s + 1), i = b % (n_s + 1);
+      *px = i * delta;
+      *py = iy * L;
+    } else {
+      const int t = b - nh, ix = t / (n_s - 1), i = 1 + t % (n_s - 1);
+      *px = ix * L;
+      *py = i * delta;
+    }
+  }
+};
+
+// sum over shifts of one free-space kernel between x and y, punctured term by
+// term (terms with R_m <= 1e-9 h are dropped: the reading of eq. phi_def).
+// kind 0: monopole Phi_j; 1: d/dy2 Phi_j (H dipole); 2: d/dy1 Phi_j (V dipole).
+__device__ inline void sesm_green_pair(const KParams& K, int j, double X, double Y, cplx* mono, cplx* dip, int dkind) {
+  cplx sm = cplx{0.0, 0.0}, sd = cplx{0.0, 0.0};
+  const double thr = 1e-9 * (K.h > 0 ? K.h : 1.0);
+  for (int m = 0; m <= j; ++m) {
+    const double Ym = Y + m * K.h;
+    const double R = sqrt(X * X + Ym * Ym);
+    if (R <= thr) continue;
+    cplx H0, H1;
+    sesm_hankel01(K.k * R, &H0, &H1);
+    const double w = (j == 0) ? 1.0 : K.wshift[m];
+    sm += w * H0;
+    sd += (w * (dkind == 1 ? Ym : X) / R) * H1;
+  }
+  *mono = 0.25 * mul_i(sm);
+  *dip = (0.25 * K.k) * mul_i(sd);
+}
+
+// ------------------------------------------------------------------ setup kernels
+// A_eq of eq. (eq_source_point): rows = collocation points, columns = monopoles then dipoles.
+__global__ void k_aeq(KParams K, CellGeo G, int lam, cplx* A) {
+  const int ncol = 2 * G.n_eq, nrow = 4 * G.n_coll;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nrow * G.n_eq) return;
+  const int r = e / G.n_eq, s = e % G.n_eq;
+  double cx, cy, sx, sy;
+  G.coll_point(r, &cx, &cy);
+  G.eq_point(lam, s, &sx, &sy);
+  cplx mono, dip;
+  sesm_green_pair(K, 0, cx - sx, cy - sy, &mono, &dip, lam == 0 ? 1 : 2);
+  A[(size_t)r * ncol + s] = mono;
+  A[(size_t)r * ncol + G.n_eq + s] = dip;
+}
+
+// P_q = A_eq^+ B_q by QR: for every node l of the cell, B[:, l] holds the
+// field of its surface true source at the collocation points,
+// B[c][l] = dx (ik/4) H1(kR) (Y - f'_l X)/R (eq. true_field), and column l of
+// P_q solves R x = Q^H B[:, l] (eq. eq_source_point), separately for the
+// horizontal and the vertical set.  qr holds, per set, Q^H (ncol x nrow) then
+// R (ncol x ncol), row-major.
+__global__ __launch_bounds__(256) void k_p2e_setup(KParams K, CellGeo G, double x0, double y0, int n_x,
+                                                   const int* __restrict__ occ_cell, const int* __restrict__ occ_off,
+                                                   const int* __restrict__ perm, const double* __restrict__ x,
+                                                   const double* __restrict__ f, const double* __restrict__ fp,
+                                                   const cplx* __restrict__ qr, cplx* __restrict__ P) {
+  extern __shared__ cplx sh[];  // per wave: B (nrow) + y (ncol)
+  const int q = blockIdx.x;
+  const int cell = occ_cell[q];
+  const double ox = x0 + (cell % n_x) * G.L, oy = y0 + (cell / n_x) * G.L;
+  const int off = occ_off[q], nq = occ_off[q + 1] - off;
+  const int nrow = 4 * G.n_coll, ncol = 2 * G.n_eq;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  cplx* B = sh + wv * (nrow + ncol);
+  cplx* yv = B + nrow;
+  cplx* Pq = P + (int64_t)2 * ncol * off;
+  const int64_t per_set = (int64_t)ncol * nrow + (int64_t)ncol * ncol;
+  for (int t0 = 0; t0 < nq; t0 += 4) {  // uniform trip count: barriers below are block-wide
+    const int t = t0 + wv;
+    if (t < nq) {
+      const int l = perm[off + t];
+      for (int c = lane; c < nrow; c += 64) {
+        double cx, cy;
+        G.coll_point(c, &cx, &cy);
+        const double X = ox + cx - x[l], Y = oy + cy - f[l];
+        const double R = sqrt(X * X + Y * Y);
+        B[c] = (K.dx * 0.25 * K.k * (Y - fp[l] * X) / R) * mul_i(sesm_hankel1(K.k * R));
+      }
+    }
+    __syncthreads();
+    for (int lam = 0; lam < 2; ++lam) {
+      const cplx* Qh = qr + lam * per_set;
+      const cplx* Rm = Qh + (int64_t)ncol * nrow;
+      if (t < nq) {
+        for (int o = lane; o < ncol; o += 64) {
+          const cplx* qrow = Qh + (int64_t)o * nrow;
+          cplx s = cplx{0.0, 0.0};
+          for (int c = 0; c < nrow; ++c) s += qrow[c] * B[c];
+          yv[o] = s;
+        }
+      }
+      __syncthreads();
+      if (t < nq && lane == 0) {  // back-substitution R x = y, in place
+        for (int r = ncol - 1; r >= 0; --r) {
+          cplx s = yv[r];
+          const cplx* rr = Rm + (int64_t)r * ncol;
+          for (int u = r + 1; u < ncol; ++u) s -= rr[u] * yv[u];
+          const cplx d = rr[r];
+          const double dd = 1.0 / abs2(d);
+          yv[r] = cplx{(s.re * d.re + s.im * d.im) * dd, (s.im * d.re - s.re * d.im) * dd};
+        }
+      }
+      __syncthreads();
+      if (t < nq)
+        for (int o = lane; o < ncol; o += 64) Pq[(int64_t)(lam * ncol + o) * nq + t] = yv[o];
+      __syncthreads();
+    }
+  }
+}
+
+// Windowed lattice sums (eq. Gq_limit with the Bloch phase) of the monopole and
+// dipole kernels on the difference grid, twisted by exp(-i alpha X):
+// tab[kind][row][mx], row = my + nY - 1.  One wavefront per entry, lanes over images.
+__global__ __launch_bounds__(256) void k_lattice(KParams K, int lam, int nX, int nY, double hx, double hy, int pmax,
+                                                 cplx* __restrict__ tab) {
+  const int lane = threadIdx.x & 63;
+  const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int nrow = 2 * nY - 1;
+  if (e >= (int64_t)nrow * nX) return;
+  const int row = (int)(e / nX), mx = (int)(e % nX);
+  const double X = mx * hx, Y = (row - (nY - 1)) * hy;
+  cplx sm = cplx{0.0, 0.0}, sd = cplx{0.0, 0.0};
+  for (int p = -pmax + lane; p <= pmax; p += 64) {
+    const double Xp = X + p * K.d;
+    const double S = sesm_window(Xp, K.cA, K.A_len);
+    if (S == 0.0) continue;
+    cplx mono, dip;
+    sesm_green_pair(K, K.j, Xp, Y, &mono, &dip, lam == 0 ? 1 : 2);
+    const cplx ph = S * cexp_i(-K.alpha * K.d * p);
+    sm += ph * mono;
+    sd += ph * dip;
+  }
+  sm = wave_sum(sm);
+  sd = wave_sum(sd);
+  if (lane == 0) {
+    const cplx tw = cexp_i(-K.alpha * X);
+    tab[(int64_t)row * nX + mx] = sm * tw;
+    tab[(int64_t)(nrow + row) * nX + mx] = sd * tw;
+  }
+}
+
+// Local-correction matrices W[o][b][s]: free-space punctured kernel from the
+// equivalent sources of the cell at offset o = (ox, oy) to the boundary points
+// of the cell at the origin (eq. small_convolution).
+__global__ void k_wmat(KParams K, CellGeo G, int n_y, int ring, cplx* __restrict__ W) {
+  const int nb = 2 * (G.n_s + 1) + 2 * (G.n_s - 1), ns2 = 2 * G.n_eq;
+  const int noff = (2 * ring + 1) * (2 * n_y - 1);
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)noff * nb * G.n_eq) return;
+  const int s = (int)(e % G.n_eq);
+  const int b = (int)((e / G.n_eq) % nb);
+  const int o = (int)(e / ((int64_t)G.n_eq * nb));
+  const int oxi = o / (2 * n_y - 1) - ring, oyi = o % (2 * n_y - 1) - (n_y - 1);
+  const int lam = b < 2 * (G.n_s + 1) ? 0 : 1;
+  double bx, by, sx, sy;
+  G.bdry_point(b, &bx, &by);
+  G.eq_point(lam, s, &sx, &sy);
+  const double X = bx - (oxi * G.L + sx), Y = by - (oyi * G.L + sy);
+  cplx mono, dip;
+  sesm_green_pair(K, K.j, X, Y, &mono, &dip, lam == 0 ? 1 : 2);
+  W[((int64_t)o * nb + b) * ns2 + s] = mono;
+  W[((int64_t)o * nb + b) * ns2 + G.n_eq + s] = dip;
+}
+
+// Near-field blocks: rows = nodes of the cell, columns = the band of the cell's
+// column; entry = operator entry for the source image in the band (phase included).
+__global__ __launch_bounds__(256) void k_near_setup(KParams K, int n_x, const int* __restrict__ occ_cell,
+                                                    const int* __restrict__ occ_off, const int* __restrict__ perm,
+                                                    const int* __restrict__ col_lo, const int* __restrict__ col_w,
+                                                    const int64_t* __restrict__ near_off,
+                                                    const double* __restrict__ x, const double* __restrict__ f,
+                                                    const double* __restrict__ fp, const double* __restrict__ fpp,
+                                                    const double* __restrict__ logw, cplx* __restrict__ blk) {
+  const int q = blockIdx.x;
+  const int col = occ_cell[q] % n_x;
+  const int off = occ_off[q], nq = occ_off[q + 1] - off;
+  const int lo = col_lo[col], w = col_w[col];
+  cplx* B = blk + near_off[q];
+  const int64_t tot = (int64_t)nq * w;
+  for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int t = (int)(e / w), u = (int)(e % w);
+    const int i = perm[off + t];
+    int l = lo + u, shift = 0;
+    if (l < 0) {
+      l += K.N;
+      shift = -1;
+    } else if (l >= K.N) {
+      l -= K.N;
+      shift = 1;
+    }
+    cplx v;
+    if (shift == 0 && l == i) {
+      v = sesm_entry_diag(K, fp[i], fpp[i]);
+    } else {
+      const double X = x[i] - (x[l] + shift * K.d), Y = f[i] - f[l];
+      v = sesm_entry_offdiag(K, logw, X, Y, fp[l], 1.0);
+      if (shift != 0) v = cexp_i(K.alpha * K.d * shift) * v;
+    }
+    B[e] = v;
+  }
+}
+
+// ------------------------------------------------------------------ forward-map kernels
+__global__ __launch_bounds__(256) void k_near_apply(int N, int n_x, const int* __restrict__ occ_cell,
+                                                    const int* __restrict__ occ_off, const int* __restrict__ perm,
+                                                    const int* __restrict__ col_lo, const int* __restrict__ col_w,
+                                                    const int64_t* __restrict__ near_off,
+                                                    const cplx* __restrict__ blk, const cplx* __restrict__ mu,
+                                                    cplx* __restrict__ y) {
+  const int q = blockIdx.x;
+  const int col = occ_cell[q] % n_x;
+  const int off = occ_off[q], nq = occ_off[q + 1] - off;
+  const int lo = col_lo[col], w = col_w[col];
+  const cplx* B = blk + near_off[q];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int t = wv; t < nq; t += 4) {
+    const cplx* row = B + (int64_t)t * w;
+    cplx acc = cplx{0.0, 0.0};
+    for (int u = lane; u < w; u += 64) {
+      int l = lo + u;
+      l += (l < 0) ? N : ((l >= N) ? -N : 0);
+      acc += row[u] * mu[l];
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) y[perm[off + t]] = acc;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_p2e_apply(int n_eq, int n_cells, const int* __restrict__ occ_cell,
+                                                   const int* __restrict__ occ_off, const int* __restrict__ perm,
+                                                   const cplx* __restrict__ P, const cplx* __restrict__ mu,
+                                                   cplx* __restrict__ dens) {
+  const int q = blockIdx.x;
+  const int cell = occ_cell[q];
+  const int off = occ_off[q], nq = occ_off[q + 1] - off;
+  const int nout = 4 * n_eq;
+  const cplx* Pq = P + (int64_t)nout * off;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int o = wv; o < nout; o += 4) {
+    const cplx* pr = Pq + (int64_t)o * nq;
+    cplx acc = cplx{0.0, 0.0};
+    for (int t = lane; t < nq; t += 64) acc += pr[t] * mu[perm[off + t]];
+    acc = wave_sum(acc);
+    if (lane == 0) {
+      const int lam = o / (2 * n_eq), oo = o % (2 * n_eq);
+      dens[((int64_t)lam * n_cells + cell) * 2 * n_eq + oo] = acc;
+    }
+  }
+}
+
+struct MergeArgs {
+  int n_x, n_y, n_s, n_e, n_side, n_eq, n_cells;
+  int nXH, nYH, nXV, nYV;
+  double alpha_d;
+};
+
+// Owner-computes gather of the merged grids (eq. sum_eqsources), with the
+// quasi-periodic wrap phase and the twist exp(-i alpha x) fused.
+// g[kind][gy][gx], kind 0 = monopole density xi, 1 = dipole density zeta.
+__global__ void k_merge(MergeArgs M, const cplx* __restrict__ dens, const cplx* __restrict__ twH,
+                        const cplx* __restrict__ twV, cplx* __restrict__ gH, cplx* __restrict__ gV) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nH = M.nXH * M.nYH, nV = M.nXV * M.nYV;
+  if (e >= nH + nV) return;
+  cplx xi = cplx{0.0, 0.0}, ze = cplx{0.0, 0.0};
+  if (e < nH) {
+    const int gy = e / M.nXH, gx = e % M.nXH;
+    const cplx* D = dens;  // lambda = H
+    for (int side = 0; side < 2; ++side) {      // bottom side of row gy, top side of row gy-1
+      const int row = gy - side;
+      if (row < 0 || row >= M.n_y) continue;
+      const int c0 = gx / M.n_s;
+      for (int dc = -1; dc <= 1; ++dc) {
+        const int cu = c0 + dc;
+        const int ix = gx - cu * M.n_s;
+        if (ix < -M.n_e || ix > M.n_s + M.n_e) continue;
+        int c = cu, Wr = 0;
+        if (c < 0) { c += M.n_x; Wr = -1; }
+        else if (c >= M.n_x) { c -= M.n_x; Wr = 1; }
+        const int s = side * M.n_side + ix + M.n_e;
+        const cplx* v = D + (int64_t)(row * M.n_x + c) * 2 * M.n_eq;
+        cplx a = v[s], b = v[M.n_eq + s];
+        if (Wr != 0) {
+          const cplx ph = cexp_i(M.alpha_d * Wr);
+          a = ph * a;
+          b = ph * b;
+        }
+        xi += a;
+        ze += b;
+      }
+    }
+    const cplx t = twH[gx];
+    gH[e] = xi * t;
+    gH[(int64_t)nH + e] = ze * t;
+  } else {
+    const int ev = e - nH;
+    const int gy = ev / M.nXV, gx = ev % M.nXV;
+    const cplx* D = dens + (int64_t)M.n_cells * 2 * M.n_eq;  // lambda = V
+    for (int side = 0; side < 2; ++side) {      // left side of column gx, right side of column gx-1
+      int c = gx - side, Wr = 0;
+      if (c < 0) { c += M.n_x; Wr = -1; }
+      const int r0 = (gy - M.n_e) / M.n_s;
+      for (int dr = -1; dr <= 1; ++dr) {
+        const int row = r0 + dr;
+        if (row < 0 || row >= M.n_y) continue;
+        const int iy = gy - M.n_e - row * M.n_s;
+        if (iy < -M.n_e || iy > M.n_s + M.n_e) continue;
+        const int s = side * M.n_side + iy + M.n_e;
+        const cplx* v = D + (int64_t)(row * M.n_x + c) * 2 * M.n_eq;
+        cplx a = v[s], b = v[M.n_eq + s];
+        if (Wr != 0) {
+          const cplx ph = cexp_i(M.alpha_d * Wr);
+          a = ph * a;
+          b = ph * b;
+        }
+        xi += a;
+        ze += b;
+      }
+    }
+    const cplx t = twV[gx];
+    gV[ev] = xi * t;
+    gV[(int64_t)nV + ev] = ze * t;
+  }
+}
+
+// phi_hat[t][kx] = sum_t' spec0[t-t'+nY-1][kx] g0[t'][kx] + spec1[...] g1[t'][kx]
+__global__ void k_yconv(int nX, int nY, const cplx* __restrict__ spec, const cplx* __restrict__ g,
+                        cplx* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nX * nY) return;
+  const int t = e / nX, kx = e % nX;
+  const int nrow = 2 * nY - 1;
+  const cplx* s0 = spec;
+  const cplx* s1 = spec + (int64_t)nrow * nX;
+  const cplx* g0 = g;
+  const cplx* g1 = g + (int64_t)nY * nX;
+  cplx acc = cplx{0.0, 0.0};
+  for (int tp = 0; tp < nY; ++tp) {
+    const int r = t - tp + nY - 1;
+    acc += s0[(int64_t)r * nX + kx] * g0[(int64_t)tp * nX + kx];
+    acc += s1[(int64_t)r * nX + kx] * g1[(int64_t)tp * nX + kx];
+  }
+  out[e] = acc;
+}
+
+struct FarArgs {
+  int N, n_x, n_y, n_s, n_e, n_side, n_eq, n_cells, n_bdry, n_bH, n_plw, nXH, nXV, ring;
+  double L, x0, y0, k, alpha_d;
+};
+
+// One block per occupied cell: boundary values of phi^all (H on horizontal
+// sides incl. corners, V on vertical sides), minus the equivalent sources of
+// the three columns (local correction), plane-wave weights, surface values.
+__global__ __launch_bounds__(256) void k_cells_far(FarArgs A, const int* __restrict__ occ_cell,
+                                                   const int* __restrict__ occ_off, const int* __restrict__ perm,
+                                                   const unsigned char* __restrict__ occ_flag,
+                                                   const cplx* __restrict__ phH, const cplx* __restrict__ phV,
+                                                   const cplx* __restrict__ dens, const cplx* __restrict__ W,
+                                                   const cplx* __restrict__ pplw, const double* __restrict__ dirs,
+                                                   const double* __restrict__ x, const double* __restrict__ f,
+                                                   cplx* __restrict__ y, cplx* __restrict__ yfar) {
+  __shared__ cplx part[4][64];
+  __shared__ cplx bv[64];
+  __shared__ cplx wv_sh[64];
+  const int q = blockIdx.x;
+  const int cell = occ_cell[q];
+  const int cx = cell % A.n_x, cy = cell / A.n_x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int ns2 = 2 * A.n_eq;
+  const int nrowoff = 2 * A.n_y - 1;
+  // local correction: waves split the near cells, lanes the boundary points
+  cplx acc = cplx{0.0, 0.0};
+  if (lane < A.n_bdry) {
+    const int lam = lane < A.n_bH ? 0 : 1;
+    const int ncand = (2 * A.ring + 1) * A.n_y;
+    for (int r = wv; r < ncand; r += 4) {
+      const int dc = r / A.n_y - A.ring, ry = r % A.n_y;
+      int col = cx + dc, Wr = 0;
+      if (col < 0) { col += A.n_x; Wr = -1; }
+      else if (col >= A.n_x) { col -= A.n_x; Wr = 1; }
+      const int rc = ry * A.n_x + col;
+      if (!occ_flag[rc]) continue;
+      const int o = (dc + A.ring) * nrowoff + (ry - cy + A.n_y - 1);
+      const cplx* Wr_b = W + ((int64_t)o * A.n_bdry + lane) * ns2;
+      const cplx* v = dens + ((int64_t)lam * A.n_cells + rc) * ns2;
+      cplx s = cplx{0.0, 0.0};
+      for (int t = 0; t < ns2; ++t) s += Wr_b[t] * v[t];
+      if (Wr != 0) s = cexp_i(A.alpha_d * Wr) * s;
+      acc += s;
+    }
+  }
+  part[wv][lane] = acc;
+  __syncthreads();
+  if (threadIdx.x < A.n_bdry) {
+    const int b = threadIdx.x;
+    cplx val;
+    if (b < A.n_bH) {
+      const int iy = b / (A.n_s + 1), i = b % (A.n_s + 1);
+      int gx = cx * A.n_s + i, Wr = 0;
+      if (gx >= A.nXH) { gx -= A.nXH; Wr = 1; }
+      val = phH[(int64_t)(cy + iy) * A.nXH + gx];
+      if (Wr) val = cexp_i(A.alpha_d) * val;
+    } else {
+      const int t = b - A.n_bH, ix = t / (A.n_s - 1), i = 1 + t % (A.n_s - 1);
+      int gx = cx + ix, Wr = 0;
+      if (gx >= A.nXV) { gx -= A.nXV; Wr = 1; }
+      val = phV[(int64_t)(cy * A.n_s + i + A.n_e) * A.nXV + gx];
+      if (Wr) val = cexp_i(A.alpha_d) * val;
+    }
+    bv[b] = val - (part[0][b] + part[1][b] + part[2][b] + part[3][b]);
+  }
+  __syncthreads();
+  // plane-wave weights: least squares R w = Q^H b (eq. plwave_QR)
+  if (threadIdx.x < A.n_plw) {
+    const cplx* qrow = pplw + (int64_t)threadIdx.x * A.n_bdry;
+    cplx s = cplx{0.0, 0.0};
+    for (int b = 0; b < A.n_bdry; ++b) s += qrow[b] * bv[b];
+    wv_sh[threadIdx.x] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const cplx* Rm = pplw + (int64_t)A.n_plw * A.n_bdry;
+    for (int r = A.n_plw - 1; r >= 0; --r) {
+      cplx s = wv_sh[r];
+      const cplx* rr = Rm + (int64_t)r * A.n_plw;
+      for (int u = r + 1; u < A.n_plw; ++u) s -= rr[u] * wv_sh[u];
+      const cplx d = rr[r];
+      const double dd = 1.0 / abs2(d);
+      wv_sh[r] = cplx{(s.re * d.re + s.im * d.im) * dd, (s.im * d.re - s.re * d.im) * dd};
+    }
+  }
+  __syncthreads();
+  // surface values (eq. planewave), plane-wave origin at the cell centre
+  const int off = occ_off[q], nq = occ_off[q + 1] - off;
+  const double ccx = A.x0 + (cx + 0.5) * A.L, ccy = A.y0 + (cy + 0.5) * A.L;
+  for (int t = threadIdx.x; t < nq; t += 256) {
+    const int i = perm[off + t];
+    const double px = x[i] - ccx, py = f[i] - ccy;
+    cplx s = cplx{0.0, 0.0};
+    for (int u = 0; u < A.n_plw; ++u) s += wv_sh[u] * cexp_i(A.k * (dirs[2 * u] * px + dirs[2 * u + 1] * py));
+    y[i] += s;
+    if (yfar) yfar[i] = s;
+  }
+}
+
+// completion modes: partial sums s_n = sum_l e^{-i alpha_n x_l - i beta_n f_l} J_l dx mu_l
+__global__ __launch_bounds__(256) void k_modes_part(KParams K, const double* __restrict__ x,
+                                                    const double* __restrict__ f, const double* __restrict__ J,
+                                                    const cplx* __restrict__ mu, cplx* __restrict__ part) {
+  __shared__ cplx sh[4];
+  const int per = (K.N + NCH_MODES - 1) / NCH_MODES;
+  const int lo = blockIdx.x * per, hi = min(K.N, lo + per);
+  for (int t = 0; t < K.nU; ++t) {
+    cplx acc = cplx{0.0, 0.0};
+    for (int l = lo + threadIdx.x; l < hi; l += 256) {
+      const double mag = exp(K.Ubi[t] * f[l]) * J[l] * K.dx;
+      acc += (mag * cexp_i(-(K.Ua[t] * x[l] + K.Ubr[t] * f[l]))) * mu[l];
+    }
+    const cplx s = block_sum<256>(acc, sh);
+    if (threadIdx.x == 0) part[(int64_t)t * NCH_MODES + blockIdx.x] = s;
+    __syncthreads();
+  }
+}
+
+// y_i += sum_n e^{i alpha_n x_i + i beta_n f_i} s_n  (each block re-reduces the partials)
+__global__ __launch_bounds__(256) void k_modes_add(KParams K, const double* __restrict__ x,
+                                                   const double* __restrict__ f, const cplx* __restrict__ part,
+                                                   cplx* __restrict__ y) {
+  __shared__ cplx s_sh[SESM_MAX_UETA];
+  if (threadIdx.x < 64) {
+    for (int t = 0; t < K.nU; ++t) {
+      cplx a = cplx{0.0, 0.0};
+      for (int c = threadIdx.x; c < NCH_MODES; c += 64) a += part[(int64_t)t * NCH_MODES + c];
+      a = wave_sum(a);
+      if (threadIdx.x == 0) s_sh[t] = a;
+    }
+  }
+  __syncthreads();
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= K.N) return;
+  cplx acc = cplx{0.0, 0.0};
+  for (int t = 0; t < K.nU; ++t) {
+    const double mag = exp(-K.Ubi[t] * f[i]);
+    acc += (mag * cexp_i(K.Ua[t] * x[i] + K.Ubr[t] * f[i])) * s_sh[t];
+  }
+  y[i] += acc;
+}
+
+template <typename T>
+int upload(sesm_ctx* ctx, T** dst, const std::vector<T>& v) {
+  int rc = sesm_alloc(ctx, (void**)dst, sizeof(T) * std::max<size_t>(v.size(), 1));
+  if (rc) return rc;
+  if (!v.empty()) {
+    hipError_t e = hipMemcpyAsync(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, ctx->stream);
+    if (e != hipSuccess) return ctx->fail(SESM_EHIP, std::string("upload: ") + hipGetErrorString(e));
+  }
+  return SESM_OK;
+}
+
+CellGeo cell_geo(const AccelOp& A) {
+  CellGeo G;
+  G.n_s = A.n_s;
+  G.n_e = A.n_e;
+  G.n_side = A.n_side;
+  G.n_eq = A.n_eq;
+  G.n_coll = A.n_coll;
+  G.L = A.L;
+  G.delta = A.delta;
+  return G;
+}
+
+int fft_rows(sesm_ctx* ctx, const FftPlan& p, int rows, const cplx* in, cplx* out, int sign, const cplx* pre,
+             const cplx* post, double scale) {
+  if (rows <= 0) return SESM_OK;
+  hipLaunchKernelGGL(k_fft_rows, dim3(rows), dim3(256), 0, ctx->stream, sesm_fft_args(p), in, (int64_t)p.n, out,
+                     (int64_t)p.n, p.tw, sign, pre, post, scale);
+  SESM_LAUNCH_CHECK();
+  return SESM_OK;
+}
+
+}  // namespace
+
+void sesm_accel_free(sesm_ctx* ctx) {
+  delete ctx->acc;  // device buffers are in ctx->owned
+  ctx->acc = nullptr;
+}
+
+void sesm_accel_info(const sesm_ctx* ctx, sesm_surface_info* info) {
+  const AccelOp* A = ctx->acc;
+  if (!A) return;
+  info->n_x = A->n_x;
+  info->n_y = A->n_y;
+  info->n_cells_occupied = A->n_occ;
+  info->stencil_rows = A->n_y;
+  info->L = A->L;
+  info->y0 = A->y0;
+  info->delta = A->delta;
+  info->near_entries = A->near_entries;
+}
+
+int sesm_accel_setup(sesm_ctx* ctx) {
+  const Problem& P = ctx->P;
+  const sesm_params& prm = ctx->prm;
+  const int N = P.N;
+  AccelOp* A = new (std::nothrow) AccelOp();
+  if (!A) return ctx->fail(SESM_ENOMEM, "host allocation failed");
+  ctx->acc = A;
+  A->n_s = prm.n_side ? prm.n_side : 10;
+  A->n_e = prm.n_ext >= 0 ? (prm.n_ext ? prm.n_ext : 1) : 0;
+  if (prm.n_ext < 0) A->n_e = 0;
+  A->n_coll = prm.n_coll ? prm.n_coll : 6 * A->n_s;
+  A->n_plw = prm.n_plw ? prm.n_plw : std::max(4, 4 * A->n_s - 8);
+  A->ring = prm.near_ring ? prm.near_ring : 1;
+  if (A->ring < 1 || A->ring > 3) return ctx->fail(SESM_EINVAL, "accelerator: near_ring must be 1, 2 or 3");
+  if (A->n_s < 2 || A->n_s > 16 || A->n_e >= A->n_s || A->n_coll < 4 || A->n_coll > 256 || A->n_plw < 4 ||
+      A->n_plw > 64)
+    return ctx->fail(SESM_EINVAL, "accelerator: need 2 <= n_side <= 16, 0 <= n_ext < n_side, n_coll in [4,256], "
+                                  "n_plw in [4,64]");
+  A->n_x = smooth5_at_least(std::max(2 * A->ring + 1, (int)std::lround(P.d / prm.L_cell)));
+  A->L = P.d / A->n_x;
+  A->delta = A->L / A->n_s;
+  if (!(P.a < A->L)) return ctx->fail(SESM_EINVAL, "accelerator: singular window a must be < L (Remark a_cond)");
+  A->n_side = A->n_s + 1 + 2 * A->n_e;
+  A->n_eq = 2 * A->n_side;
+  A->n_bH = 2 * (A->n_s + 1);
+  A->n_bdry = A->n_bH + 2 * (A->n_s - 1);
+  if (A->n_bdry > 64) return ctx->fail(SESM_EINVAL, "accelerator: too many boundary points");
+  // non-resonant cells (Remark non-resonant): -k^2 must not be a Dirichlet
+  // eigenvalue of the L-square, (pi/L)^2 (m^2 + n^2) != k^2
+  {
+    const double kk = P.k * A->L / PI;
+    const double t = kk * kk;
+    for (int m = 1; m * m < t + 1; ++m)
+      for (int n = 1; n * n + m * m < t + 1; ++n)
+        if (std::fabs(m * m + n * n - t) < 1e-6 * t)
+          return ctx->fail(SESM_ERESONANT, "accelerator: cell side L is a Dirichlet resonance of the square");
+  }
+  std::vector<double> hx(N), hf(N);
+  SESM_HIP(hipMemcpyAsync(hx.data(), ctx->x, sizeof(double) * N, hipMemcpyDeviceToHost, ctx->stream));
+  SESM_HIP(hipMemcpyAsync(hf.data(), ctx->f, sizeof(double) * N, hipMemcpyDeviceToHost, ctx->stream));
+  SESM_HIP(hipStreamSynchronize(ctx->stream));
+  A->x0 = -0.5 * P.dx;
+  const double fmin = *std::min_element(hf.begin(), hf.end()), fmax = *std::max_element(hf.begin(), hf.end());
+  A->n_y = (int)std::floor((fmax - fmin) / A->L) + 1;
+  A->y0 = 0.5 * (fmin + fmax) - 0.5 * A->n_y * A->L;
+  A->n_cells = A->n_x * A->n_y;
+  A->nXH = A->n_x * A->n_s;
+  A->nYH = A->n_y + 1;
+  A->nXV = A->n_x;
+  A->nYV = A->n_y * A->n_s + 1 + 2 * A->n_e;
+  if (!sesm_fft_factor(A->nXH, &A->planH) || !sesm_fft_factor(A->nXV, &A->planV) || A->nXH > SESM_FFT_MAXN)
+    return ctx->fail(SESM_EINVAL, "accelerator: periodic grid length must be 5-smooth and <= 2000");
+  // cells of the nodes, (a, b] convention
+  std::vector<int> cellof(N), colof(N);
+  for (int l = 0; l < N; ++l) {
+    const int cxl = (int)std::ceil((hx[l] - A->x0) / A->L) - 1;
+    const int cyl = (int)std::ceil((hf[l] - A->y0) / A->L) - 1;
+    if (cxl < 0 || cxl >= A->n_x || cyl < 0 || cyl >= A->n_y)
+      return ctx->fail(SESM_EINVAL, "accelerator: node outside the cell grid");
+    colof[l] = cxl;
+    cellof[l] = cyl * A->n_x + cxl;
+  }
+  std::vector<int> perm(N);
+  for (int l = 0; l < N; ++l) perm[l] = l;
+  std::stable_sort(perm.begin(), perm.end(), [&](int u, int v) { return cellof[u] < cellof[v]; });
+  std::vector<int> occ_cell, occ_off;
+  std::vector<unsigned char> occ_flag(A->n_cells, 0);
+  for (int t = 0; t < N; ++t) {
+    const int c = cellof[perm[t]];
+    if (occ_cell.empty() || occ_cell.back() != c) {
+      occ_cell.push_back(c);
+      occ_off.push_back(t);
+      occ_flag[c] = 1;
+    }
+  }
+  occ_off.push_back(N);
+  A->n_occ = (int)occ_cell.size();
+  // column bands: nodes of columns c-ring..c+ring (cyclic), as a range [lo, lo + w)
+  std::vector<int> first(A->n_x + 1, N);
+  for (int l = N - 1; l >= 0; --l) first[colof[l]] = l;
+  for (int c = A->n_x - 1; c >= 0; --c)
+    if (first[c] > first[c + 1]) first[c] = first[c + 1];  // empty columns
+  std::vector<int> col_lo(A->n_x), col_w(A->n_x);
+  const int R = A->ring;
+  for (int c = 0; c < A->n_x; ++c) {
+    const int lo = c - R >= 0 ? first[c - R] : first[c - R + A->n_x] - N;
+    const int hi = c + R + 1 <= A->n_x ? first[c + R + 1] : first[c + R + 1 - A->n_x] + N;
+    col_lo[c] = lo;
+    col_w[c] = hi - lo;
+  }
+  std::vector<int64_t> near_off(A->n_occ + 1, 0);
+  for (int q = 0; q < A->n_occ; ++q)
+    near_off[q + 1] = near_off[q] + (int64_t)(occ_off[q + 1] - occ_off[q]) * col_w[occ_cell[q] % A->n_x];
+  A->near_entries = near_off[A->n_occ];
+  int rc;
+  if ((rc = upload(ctx, &A->occ_cell, occ_cell)) || (rc = upload(ctx, &A->occ_off, occ_off)) ||
+      (rc = upload(ctx, &A->perm, perm)) || (rc = upload(ctx, &A->col_lo, col_lo)) ||
+      (rc = upload(ctx, &A->col_w, col_w)) || (rc = upload(ctx, &A->near_off, near_off)) ||
+      (rc = upload(ctx, &A->occ_flag, occ_flag)))
+    return rc;
+  const KParams K = ctx->kparams();
+  const CellGeo G = cell_geo(*A);
+  // --- equivalent-source least squares: A_eq on the device, QR on the host
+  const int nrow = 4 * A->n_coll, ncol = 2 * A->n_eq;
+  {
+    std::vector<cplx> qr_all;
+    cplx* dA = nullptr;
+    if ((rc = sesm_alloc(ctx, (void**)&dA, sizeof(cplx) * (size_t)nrow * ncol))) return rc;
+    for (int lam = 0; lam < 2; ++lam) {
+      hipLaunchKernelGGL(k_aeq, dim3((nrow * A->n_eq + 255) / 256), dim3(256), 0, ctx->stream, K, G, lam, dA);
+      SESM_LAUNCH_CHECK();
+      std::vector<C> hA((size_t)nrow * ncol);
+      SESM_HIP(hipMemcpyAsync(hA.data(), dA, sizeof(cplx) * hA.size(), hipMemcpyDeviceToHost, ctx->stream));
+      SESM_HIP(hipStreamSynchronize(ctx->stream));
+      std::vector<C> Qh, Rm;
+      if (!ls_qr(nrow, ncol, hA, Qh, Rm)) return ctx->fail(SESM_EINVAL, "equivalent-source matrix is rank deficient");
+      for (const C& v : Qh) qr_all.push_back(cplx{v.real(), v.imag()});
+      for (const C& v : Rm) qr_all.push_back(cplx{v.real(), v.imag()});
+    }
+    if ((rc = upload(ctx, &A->pinv, qr_all))) return rc;
+  }
+  // --- P_q for every occupied cell
+  if ((rc = sesm_alloc(ctx, (void**)&A->p2e, sizeof(cplx) * (size_t)4 * A->n_eq * N))) return rc;
+  hipLaunchKernelGGL(k_p2e_setup, dim3(A->n_occ), dim3(256), sizeof(cplx) * 4 * (nrow + ncol), ctx->stream, K, G,
+                     A->x0, A->y0, A->n_x, A->occ_cell, A->occ_off, A->perm, ctx->x, ctx->f, ctx->fp, A->pinv, A->p2e);
+  SESM_LAUNCH_CHECK();
+  // --- global kernel tables and their spectra
+  std::vector<cplx> twxH(A->nXH), twxV(A->nXV), utwH(A->nXH), utwV(A->nXV);
+  for (int t = 0; t < A->nXH; ++t) {
+    const double ph = P.alpha * t * A->delta;
+    twxH[t] = cplx{std::cos(ph), -std::sin(ph)};
+    utwH[t] = cplx{std::cos(ph), std::sin(ph)};
+  }
+  for (int t = 0; t < A->nXV; ++t) {
+    const double ph = P.alpha * t * A->L;
+    twxV[t] = cplx{std::cos(ph), -std::sin(ph)};
+    utwV[t] = cplx{std::cos(ph), std::sin(ph)};
+  }
+  if ((rc = upload(ctx, &A->twxH, twxH)) || (rc = upload(ctx, &A->twxV, twxV)) || (rc = upload(ctx, &A->utwH, utwH)) ||
+      (rc = upload(ctx, &A->utwV, utwV)))
+    return rc;
+  for (FftPlan* pl : {&A->planH, &A->planV}) {
+    std::vector<cplx> tw(pl->n);
+    for (int t = 0; t < pl->n; ++t) {
+      const double ph = -2.0 * PI * t / pl->n;
+      tw[t] = cplx{std::cos(ph), std::sin(ph)};
+    }
+    if ((rc = upload(ctx, &pl->tw, tw))) return rc;
+  }
+  const int pmax = (int)std::ceil(P.A_len / P.d) + 2;
+  for (int lam = 0; lam < 2; ++lam) {
+    const int nX = lam == 0 ? A->nXH : A->nXV, nY = lam == 0 ? A->nYH : A->nYV;
+    const double hxs = lam == 0 ? A->delta : A->L, hys = lam == 0 ? A->L : A->delta;
+    const int nrows = 2 * nY - 1;
+    cplx*& spec = lam == 0 ? A->specH : A->specV;
+    if ((rc = sesm_alloc(ctx, (void**)&spec, sizeof(cplx) * (size_t)2 * nrows * nX))) return rc;
+    const int64_t ent = (int64_t)nrows * nX;
+    hipLaunchKernelGGL(k_lattice, dim3((unsigned)((ent + 3) / 4)), dim3(256), 0, ctx->stream, K, lam, nX, nY, hxs,
+                       hys, pmax, spec);
+    SESM_LAUNCH_CHECK();
+    if ((rc = fft_rows(ctx, lam == 0 ? A->planH : A->planV, 2 * nrows, spec, spec, -1, nullptr, nullptr, 1.0)))
+      return rc;
+  }
+  // --- local correction matrices
+  A->n_off = (2 * A->ring + 1) * (2 * A->n_y - 1);
+  {
+    const int64_t nW = (int64_t)A->n_off * A->n_bdry * ncol;
+    if ((rc = sesm_alloc(ctx, (void**)&A->W, sizeof(cplx) * (size_t)nW))) return rc;
+    const int64_t nth = (int64_t)A->n_off * A->n_bdry * A->n_eq;
+    hipLaunchKernelGGL(k_wmat, dim3((unsigned)((nth + 255) / 256)), dim3(256), 0, ctx->stream, K, G, A->n_y, A->ring,
+                       A->W);
+    SESM_LAUNCH_CHECK();
+  }
+  // --- plane waves: d_s = (sin 2 pi s / n_plw, cos 2 pi s / n_plw), s = 1..n_plw (eq. plwave_QR)
+  {
+    std::vector<double> dirs(2 * A->n_plw);
+    for (int s = 0; s < A->n_plw; ++s) {
+      const double t = 2.0 * PI * (s + 1) / A->n_plw;
+      dirs[2 * s] = std::sin(t);
+      dirs[2 * s + 1] = std::cos(t);
+    }
+    std::vector<C> E((size_t)A->n_bdry * A->n_plw);
+    for (int b = 0; b < A->n_bdry; ++b) {
+      double bx, by;
+      G.bdry_point(b, &bx, &by);
+      bx -= 0.5 * A->L;
+      by -= 0.5 * A->L;
+      for (int s = 0; s < A->n_plw; ++s)
+        E[(size_t)b * A->n_plw + s] = std::exp(C(0.0, P.k * (dirs[2 * s] * bx + dirs[2 * s + 1] * by)));
+    }
+    if (A->n_bdry < A->n_plw) return ctx->fail(SESM_EINVAL, "accelerator: need n_plw <= boundary points (4 n_side)");
+    std::vector<C> Qh, Rm;
+    if (!ls_qr(A->n_bdry, A->n_plw, E, Qh, Rm)) return ctx->fail(SESM_EINVAL, "plane-wave matrix is rank deficient");
+    std::vector<cplx> pv;
+    for (const C& v : Qh) pv.push_back(cplx{v.real(), v.imag()});
+    for (const C& v : Rm) pv.push_back(cplx{v.real(), v.imag()});
+    if ((rc = upload(ctx, &A->pplw, pv)) || (rc = upload(ctx, &A->dirs, dirs))) return rc;
+  }
+  // --- near-field blocks
+  if ((rc = sesm_alloc(ctx, (void**)&A->nearblk, sizeof(cplx) * (size_t)std::max<int64_t>(A->near_entries, 1))))
+    return rc;
+  hipLaunchKernelGGL(k_near_setup, dim3(A->n_occ), dim3(256), 0, ctx->stream, K, A->n_x, A->occ_cell, A->occ_off,
+                     A->perm, A->col_lo, A->col_w, A->near_off, ctx->x, ctx->f, ctx->fp, ctx->fpp, ctx->logw,
+                     A->nearblk);
+  SESM_LAUNCH_CHECK();
+  // --- work buffers
+  const size_t nH = (size_t)A->nXH * A->nYH, nV = (size_t)A->nXV * A->nYV;
+  if ((rc = sesm_alloc(ctx, (void**)&A->dens, sizeof(cplx) * (size_t)2 * A->n_cells * ncol)) ||
+      (rc = sesm_alloc(ctx, (void**)&A->gH, sizeof(cplx) * 2 * nH)) ||
+      (rc = sesm_alloc(ctx, (void**)&A->gV, sizeof(cplx) * 2 * nV)) ||
+      (rc = sesm_alloc(ctx, (void**)&A->fH, sizeof(cplx) * 2 * nH)) ||
+      (rc = sesm_alloc(ctx, (void**)&A->fV, sizeof(cplx) * 2 * nV)) ||
+      (rc = sesm_alloc(ctx, (void**)&A->phH, sizeof(cplx) * nH)) ||
+      (rc = sesm_alloc(ctx, (void**)&A->phV, sizeof(cplx) * nV)) ||
+      (rc = sesm_alloc(ctx, (void**)&A->mode_part, sizeof(cplx) * SESM_MAX_UETA * NCH_MODES)) ||
+      (rc = sesm_alloc(ctx, (void**)&A->yfar, sizeof(cplx) * (size_t)N)))
+    return rc;
+  SESM_HIP(hipMemsetAsync(A->dens, 0, sizeof(cplx) * (size_t)2 * A->n_cells * ncol, ctx->stream));
+  return SESM_OK;
+}
+
+static int accel_matvec_impl(sesm_ctx* ctx, const cplx* mu, cplx* y, bool keep_far) {
+  AccelOp* A = ctx->acc;
+  const Problem& P = ctx->P;
+  const KParams K = ctx->kparams();
+  hipStream_t st = ctx->stream;
+  hipLaunchKernelGGL(k_near_apply, dim3(A->n_occ), dim3(256), 0, st, P.N, A->n_x, A->occ_cell, A->occ_off, A->perm,
+                     A->col_lo, A->col_w, A->near_off, A->nearblk, mu, y);
+  hipLaunchKernelGGL(k_p2e_apply, dim3(A->n_occ), dim3(256), 0, st, A->n_eq, A->n_cells, A->occ_cell, A->occ_off,
+                     A->perm, A->p2e, mu, A->dens);
+  MergeArgs M{A->n_x, A->n_y, A->n_s, A->n_e, A->n_side, A->n_eq, A->n_cells,
+              A->nXH, A->nYH, A->nXV, A->nYV, P.alpha * P.d};
+  const int ng = A->nXH * A->nYH + A->nXV * A->nYV;
+  hipLaunchKernelGGL(k_merge, dim3((ng + 255) / 256), dim3(256), 0, st, M, A->dens, A->twxH, A->twxV, A->gH, A->gV);
+  SESM_LAUNCH_CHECK();
+  int rc;
+  if ((rc = fft_rows(ctx, A->planH, 2 * A->nYH, A->gH, A->fH, -1, nullptr, nullptr, 1.0)) ||
+      (rc = fft_rows(ctx, A->planV, 2 * A->nYV, A->gV, A->fV, -1, nullptr, nullptr, 1.0)))
+    return rc;
+  // y-convolution into the second half of the f buffers, then inverse FFT with untwist
+  cplx* hatH = A->gH;  // reuse: merged grids are no longer needed
+  cplx* hatV = A->gV;
+  hipLaunchKernelGGL(k_yconv, dim3((A->nXH * A->nYH + 255) / 256), dim3(256), 0, st, A->nXH, A->nYH, A->specH, A->fH,
+                     hatH);
+  hipLaunchKernelGGL(k_yconv, dim3((A->nXV * A->nYV + 255) / 256), dim3(256), 0, st, A->nXV, A->nYV, A->specV, A->fV,
+                     hatV);
+  SESM_LAUNCH_CHECK();
+  if ((rc = fft_rows(ctx, A->planH, A->nYH, hatH, A->phH, +1, nullptr, A->utwH, 1.0 / A->nXH)) ||
+      (rc = fft_rows(ctx, A->planV, A->nYV, hatV, A->phV, +1, nullptr, A->utwV, 1.0 / A->nXV)))
+    return rc;
+  FarArgs F{P.N, A->n_x, A->n_y, A->n_s, A->n_e, A->n_side, A->n_eq, A->n_cells, A->n_bdry, A->n_bH, A->n_plw,
+            A->nXH, A->nXV, A->ring, A->L, A->x0, A->y0, P.k, P.alpha * P.d};
+  hipLaunchKernelGGL(k_cells_far, dim3(A->n_occ), dim3(256), 0, st, F, A->occ_cell, A->occ_off, A->perm, A->occ_flag,
+                     A->phH, A->phV, A->dens, A->W, A->pplw, A->dirs, ctx->x, ctx->f, y, keep_far ? A->yfar : nullptr);
+  SESM_LAUNCH_CHECK();
+  if (P.nU > 0) {
+    hipLaunchKernelGGL(k_modes_part, dim3(NCH_MODES), dim3(256), 0, st, K, ctx->x, ctx->f, ctx->J, mu, A->mode_part);
+    hipLaunchKernelGGL(k_modes_add, dim3((P.N + 255) / 256), dim3(256), 0, st, K, ctx->x, ctx->f, A->mode_part, y);
+    SESM_LAUNCH_CHECK();
+  }
+  return SESM_OK;
+}
+
+int sesm_accel_matvec(sesm_ctx* ctx, const cplx* mu, cplx* y) { return accel_matvec_impl(ctx, mu, y, false); }
+
+extern "C" int sesm_diag_accel(sesm_ctx* ctx, const sesm_c64* mu, int32_t which, sesm_c64* out, int64_t out_len) {
+  if (!ctx) return SESM_EINVAL;
+  if (!ctx->ready) return ctx->fail(SESM_ENOSURF, "no surface");
+  if (ctx->P.mode != SESM_MODE_ACCEL || !ctx->acc) return ctx->fail(SESM_EINVAL, "not in accelerated mode");
+  if (!mu || !out) return ctx->fail(SESM_EINVAL, "null pointer");
+  SESM_HIP(hipSetDevice(ctx->device));
+  AccelOp* A = ctx->acc;
+  const int N = ctx->P.N;
+  cplx* ytmp = nullptr;
+  int rc = SESM_OK;
+  SESM_HIP(hipMalloc((void**)&ytmp, sizeof(cplx) * N));
+  rc = accel_matvec_impl(ctx, (const cplx*)mu, ytmp, true);
+  const cplx* src = nullptr;
+  int64_t len = 0;
+  const int64_t nH = (int64_t)A->nXH * A->nYH, nV = (int64_t)A->nXV * A->nYV;
+  switch (which) {
+    case 0: src = A->yfar; len = N; break;                                     // far-field contribution at the nodes
+    case 1: src = A->phH; len = nH; break;                                     // phi^all on the H grid [nYH][nXH]
+    case 2: src = A->phV; len = nV; break;                                     // phi^all on the V grid [nYV][nXV]
+    case 3: src = A->dens; len = (int64_t)2 * A->n_cells * 2 * A->n_eq; break; // per-cell densities
+    default: rc = ctx->fail(SESM_EINVAL, "unknown diagnostic buffer");
+  }
+  if (rc == SESM_OK && out_len < len) rc = ctx->fail(SESM_EINVAL, "output buffer too small");
+  if (rc == SESM_OK) {
+    hipError_t e = hipMemcpyAsync(out, src, sizeof(cplx) * len, hipMemcpyDeviceToDevice, ctx->stream);
+    if (e != hipSuccess) rc = ctx->fail(SESM_EHIP, hipGetErrorString(e));
+  }
+  (void)hipStreamSynchronize(ctx->stream);
+  (void)hipFree(ytmp);
+  return rc;
+}

@@ -269,7 +269,7 @@ int sesm_set_surface(sesm_ctx* ctx, const sesm_profile* prof, double d, double k
       const std::complex<double> b = beta_of(k, an);
       const double fac = std::pow(std::abs(1.0 - std::exp(std::complex<double>(0.0, 1.0) * b * prm.h)), j);
       if (fac < prm.eta) {
-        if (P.nU >= SESM_MAX_UETA) return ctx->fail(SESM_EINVAL, "more than 16 completion modes; lower eta");
+        if (P.nU >= SESM_MAX_UETA) return ctx->fail(SESM_EINVAL, "more than 64 completion modes; lower eta");
         P.U[P.nU] = n;
         P.Ua[P.nU] = an;
         P.Ubr[P.nU] = b.real();

@@ -12,22 +12,9 @@
 // One 64-lane wavefront per matrix entry, lanes over lattice images p, a
 // DPP/shuffle reduction at the end: the windowed lattice sum is the FP64-heavy
 // part (up to (2A+3)(j+1) Hankel evaluations per entry).
-#include "sesm_impl.h"
+#include "sesm_kernels.h"
 
 namespace {
-
-constexpr double PI = 3.14159265358979323846;
-
-__device__ inline cplx kdl(const KParams& K, double X, double Y, double fps) {
-  cplx acc = cplx{0.0, 0.0};
-  for (int m = 0; m <= K.j; ++m) {
-    const double Ym = Y + m * K.h;
-    const double R = sqrt(X * X + Ym * Ym);
-    const cplx H1 = sesm_hankel1(K.k * R);
-    acc += (K.wshift[m] * (Ym - fps * X) / R) * H1;
-  }
-  return (0.25 * K.k) * mul_i(acc);
-}
 
 __global__ __launch_bounds__(256) void k_dense_assemble(KParams K, const double* __restrict__ x,
                                                         const double* __restrict__ f,
@@ -47,29 +34,11 @@ __global__ __launch_bounds__(256) void k_dense_assemble(KParams K, const double*
     const double SA = sesm_window(Xp, K.cA, K.A_len);
     if (SA == 0.0) continue;
     if (p == 0 && i == l) continue;  // diagonal: handled below
-    const double r = sqrt(Xp * Xp + Y * Y);
-    const double Sf = sesm_window(r, K.gamma, K.a);
-    const cplx Kd = kdl(K, Xp, Y, fps);
-    cplx term = (K.dx * SA * (1.0 - Sf)) * Kd;
-    if (Sf > 0.0) {
-      const double Ks = (K.k / (4.0 * PI)) * (fps * Xp - Y) * sesm_besselj1(K.k * r) / r;
-      const double sn = sin(PI * Xp / K.a);
-      const double lg = log(4.0 * sn * sn);
-      int m = (int)llrint(-Xp / K.dx);
-      m = m < 0 ? -m : m;
-      m %= K.n_a;
-      term += Sf * (cplx{logw[m] * Ks, 0.0} + K.dx * (Kd - cplx{Ks * lg, 0.0}));
-    }
-    acc += cexp_i(K.alpha * p * K.d) * term;
+    acc += cexp_i(K.alpha * p * K.d) * sesm_entry_offdiag(K, logw, Xp, Y, fps, SA);
   }
   acc = wave_sum(acc);
   if (lane == 0) {
-    if (i == l) {
-      cplx kr = cplx{fpp[i] / (4.0 * PI * (1.0 + fp[i] * fp[i])), 0.0};
-      for (int m = 1; m <= K.j; ++m) kr += (0.25 * K.k * K.wshift[m]) * mul_i(sesm_hankel1(K.k * m * K.h));
-      acc += K.dx * kr;
-      acc.re += 0.5;
-    }
+    if (i == l) acc += sesm_entry_diag(K, fp[i], fpp[i]);
     for (int t = 0; t < K.nU; ++t) {
       const double mag = exp(-K.Ubi[t] * Y);
       acc += (mag * J[l] * K.dx) * cexp_i(K.Ua[t] * X0 + K.Ubr[t] * Y);

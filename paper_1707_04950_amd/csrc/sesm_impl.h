@@ -10,7 +10,7 @@
 #include "sesm_math.h"
 
 #define SESM_MAX_J 16
-#define SESM_MAX_UETA 16
+#define SESM_MAX_UETA 64
 
 // Scalars of one discretised problem (Algorithm 2 inputs and derived sizes).
 struct Problem {

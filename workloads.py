@@ -128,7 +128,7 @@ def config_random_double_wood(N: int = 4096) -> Workload:
     d = 20.0
     a, b = gaussian_surface(d, 0.5, 1.0, SEED_BASE + 2)
     return Workload(name="gauss-d20-rms0.5-theta30-N%d" % N, d=d, k=TWO_PI,
-                    theta_deg=30.0, N=N, j=8, h=0.47, A=20.0,
+                    theta_deg=30.0, N=N, j=8, h=0.85, A=20.0,
                     a_coef=a, b_coef=b, L=0.5)
 
 
@@ -146,7 +146,7 @@ def config_grazing_wood(N: int = 32768) -> Workload:
     a, b = gaussian_surface(d, 1.0, 1.0, SEED_BASE + 3)
     return Workload(name="gauss-d100-rms1-theta89-wood-N%d" % N, d=d,
                     k=wood_grazing_k(d, 89.0, 200), theta_deg=89.0, N=N, j=8,
-                    h=0.47, A=40.0, a_coef=a, b_coef=b, L=0.5)
+                    h=0.85, A=40.0, a_coef=a, b_coef=b, L=0.5)
 
 
 def random_density(N: int, seed: int = 1) -> np.ndarray:
