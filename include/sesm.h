@@ -179,6 +179,13 @@ SESM_API const char* sesm_last_error(const sesm_ctx* ctx);
  * Synchronises the stream.  Returns SESM_EINVAL if out_len is too small. */
 SESM_API int sesm_diag_accel(sesm_ctx* ctx, const sesm_c64* mu, int32_t which, sesm_c64* out, int64_t out_len);
 
+/* Diagnostic (accelerated mode): y = the direct near-field part of the forward
+ * map alone - the intersecting interactions of eq. (final_correction_0), the
+ * singular part eq. (local_mat) and 1/2 I, for the sources of the cells in
+ * the near columns - as one kernel launch on the context's stream (no
+ * synchronisation).  mu, y: device arrays of N sesm_c64, not overlapping. */
+SESM_API int sesm_diag_near(sesm_ctx* ctx, const sesm_c64* mu, sesm_c64* y);
+
 /* Diagnostic: evaluate the library's FP64 Hankel functions H0^(1)(x),
  * H1^(1)(x) (used by every Green-function kernel, eq. free_space) at n
  * points.  x: device array of n doubles (x > 0); h0, h1: device arrays of n

@@ -80,6 +80,7 @@ def load_library(path=LIB_PATH):
         "sesm_last_error": (ctypes.c_char_p, [_P]),
         "sesm_diag_hankel": (ctypes.c_int, [_P, _P, _I, _P, _P]),
         "sesm_diag_accel": (ctypes.c_int, [_P, _P, _I, _P, ctypes.c_int64]),
+        "sesm_diag_near": (ctypes.c_int, [_P, _P, _P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -196,6 +197,11 @@ class Solver:
     def diag_accel(self, mu, which, length):
         out = self._torch.empty(length, dtype=self._torch.complex128, device=self.device)
         self._check(self.lib.sesm_diag_accel(self.h, _ptr(mu), which, _ptr(out), length))
+        return out
+
+    def diag_near(self, mu, out=None):
+        out = self.empty() if out is None else out
+        self._check(self.lib.sesm_diag_near(self.h, _ptr(mu), _ptr(out)))
         return out
 
     def diag_hankel(self, x):

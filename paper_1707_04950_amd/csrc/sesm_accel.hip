@@ -51,6 +51,8 @@ struct AccelOp {
   // device data
   int *occ_cell = nullptr, *occ_off = nullptr, *perm = nullptr, *col_lo = nullptr, *col_w = nullptr;
   int64_t* near_off = nullptr;
+  int64_t* row_off = nullptr;  // per row (cell order): offset of its near-block row
+  int *row_lo = nullptr, *row_w = nullptr;
   unsigned char* occ_flag = nullptr;
   cplx *p2e = nullptr, *nearblk = nullptr, *dens = nullptr;
   cplx *gH = nullptr, *gV = nullptr, *fH = nullptr, *fV = nullptr, *phH = nullptr, *phV = nullptr;
@@ -168,6 +170,26 @@ struct CellGeo {
   }
 };
 
+// Back-substitution R x = y on one wavefront (n <= 64): lane u holds y_u on
+// entry and x_u on exit; R row-major upper triangular (n x n).  Column-oriented:
+// x_r is broadcast and subtracted from the rows above it.
+__device__ inline cplx sesm_wave_backsub(const cplx* __restrict__ R, int n, cplx yu) {
+  const int lane = threadIdx.x & 63;
+  for (int r = n - 1; r >= 0; --r) {
+    cplx xr = cplx{0.0, 0.0};
+    if (lane == r) {
+      const cplx d = R[(int64_t)r * n + r];
+      const double dd = 1.0 / abs2(d);
+      xr = cplx{(yu.re * d.re + yu.im * d.im) * dd, (yu.im * d.re - yu.re * d.im) * dd};
+      yu = xr;
+    }
+    xr.re = __shfl(xr.re, r);
+    xr.im = __shfl(xr.im, r);
+    if (lane < r) yu -= R[(int64_t)lane * n + r] * xr;
+  }
+  return yu;
+}
+
 // sum over shifts of one free-space kernel between x and y, punctured term by
 // term (terms with R_m <= 1e-9 h are dropped: the reading of eq. phi_def).
 // kind 0: monopole Phi_j; 1: d/dy2 Phi_j (H dipole); 2: d/dy1 Phi_j (V dipole).
@@ -215,15 +237,14 @@ __global__ __launch_bounds__(256) void k_p2e_setup(KParams K, CellGeo G, double 
                                                    const int* __restrict__ perm, const double* __restrict__ x,
                                                    const double* __restrict__ f, const double* __restrict__ fp,
                                                    const cplx* __restrict__ qr, cplx* __restrict__ P) {
-  extern __shared__ cplx sh[];  // per wave: B (nrow) + y (ncol)
+  extern __shared__ cplx sh[];  // per wave: B (nrow)
   const int q = blockIdx.x;
   const int cell = occ_cell[q];
   const double ox = x0 + (cell % n_x) * G.L, oy = y0 + (cell / n_x) * G.L;
   const int off = occ_off[q], nq = occ_off[q + 1] - off;
   const int nrow = 4 * G.n_coll, ncol = 2 * G.n_eq;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  cplx* B = sh + wv * (nrow + ncol);
-  cplx* yv = B + nrow;
+  cplx* B = sh + wv * nrow;
   cplx* Pq = P + (int64_t)2 * ncol * off;
   const int64_t per_set = (int64_t)ncol * nrow + (int64_t)ncol * ncol;
   for (int t0 = 0; t0 < nq; t0 += 4) {  // uniform trip count: barriers below are block-wide
@@ -239,33 +260,20 @@ __global__ __launch_bounds__(256) void k_p2e_setup(KParams K, CellGeo G, double 
       }
     }
     __syncthreads();
-    for (int lam = 0; lam < 2; ++lam) {
+    for (int lam = 0; lam < 2; ++lam) {  // ncol <= 64: one output row per lane
       const cplx* Qh = qr + lam * per_set;
       const cplx* Rm = Qh + (int64_t)ncol * nrow;
       if (t < nq) {
-        for (int o = lane; o < ncol; o += 64) {
-          const cplx* qrow = Qh + (int64_t)o * nrow;
-          cplx s = cplx{0.0, 0.0};
-          for (int c = 0; c < nrow; ++c) s += qrow[c] * B[c];
-          yv[o] = s;
+        cplx yu = cplx{0.0, 0.0};
+        if (lane < ncol) {
+          const cplx* qrow = Qh + (int64_t)lane * nrow;
+          for (int c = 0; c < nrow; ++c) yu += qrow[c] * B[c];
         }
+        yu = sesm_wave_backsub(Rm, ncol, yu);
+        if (lane < ncol) Pq[(int64_t)(lam * ncol + lane) * nq + t] = yu;
       }
-      __syncthreads();
-      if (t < nq && lane == 0) {  // back-substitution R x = y, in place
-        for (int r = ncol - 1; r >= 0; --r) {
-          cplx s = yv[r];
-          const cplx* rr = Rm + (int64_t)r * ncol;
-          for (int u = r + 1; u < ncol; ++u) s -= rr[u] * yv[u];
-          const cplx d = rr[r];
-          const double dd = 1.0 / abs2(d);
-          yv[r] = cplx{(s.re * d.re + s.im * d.im) * dd, (s.im * d.re - s.re * d.im) * dd};
-        }
-      }
-      __syncthreads();
-      if (t < nq)
-        for (int o = lane; o < ncol; o += 64) Pq[(int64_t)(lam * ncol + o) * nq + t] = yv[o];
-      __syncthreads();
     }
+    __syncthreads();
   }
 }
 
@@ -362,50 +370,48 @@ __global__ __launch_bounds__(256) void k_near_setup(KParams K, int n_x, const in
 }
 
 // ------------------------------------------------------------------ forward-map kernels
-__global__ __launch_bounds__(256) void k_near_apply(int N, int n_x, const int* __restrict__ occ_cell,
-                                                    const int* __restrict__ occ_off, const int* __restrict__ perm,
-                                                    const int* __restrict__ col_lo, const int* __restrict__ col_w,
-                                                    const int64_t* __restrict__ near_off,
+// Near field: one wavefront per target node (rows in cell order), lanes stream
+// the node's row of the near block (coalesced) against the cyclic band of mu.
+__global__ __launch_bounds__(256) void k_near_apply(int N, const int* __restrict__ perm,
+                                                    const int64_t* __restrict__ row_off,
+                                                    const int* __restrict__ row_lo, const int* __restrict__ row_w,
                                                     const cplx* __restrict__ blk, const cplx* __restrict__ mu,
                                                     cplx* __restrict__ y) {
-  const int q = blockIdx.x;
-  const int col = occ_cell[q] % n_x;
-  const int off = occ_off[q], nq = occ_off[q + 1] - off;
-  const int lo = col_lo[col], w = col_w[col];
-  const cplx* B = blk + near_off[q];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int t = wv; t < nq; t += 4) {
-    const cplx* row = B + (int64_t)t * w;
-    cplx acc = cplx{0.0, 0.0};
-    for (int u = lane; u < w; u += 64) {
-      int l = lo + u;
-      l += (l < 0) ? N : ((l >= N) ? -N : 0);
-      acc += row[u] * mu[l];
-    }
-    acc = wave_sum(acc);
-    if (lane == 0) y[perm[off + t]] = acc;
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (t >= N) return;  // wave-uniform
+  const cplx* row = blk + row_off[t];
+  const int lo = row_lo[t], w = row_w[t];
+  cplx acc = cplx{0.0, 0.0};
+#pragma unroll 4
+  for (int u = lane; u < w; u += 64) {
+    int l = lo + u;
+    l += (l < 0) ? N : ((l >= N) ? -N : 0);
+    acc += row[u] * mu[l];
   }
+  acc = wave_sum(acc);
+  if (lane == 0) y[perm[t]] = acc;
 }
 
+// EqSources: one wavefront per (cell, output), lanes over the cell's nodes.
 __global__ __launch_bounds__(256) void k_p2e_apply(int n_eq, int n_cells, const int* __restrict__ occ_cell,
                                                    const int* __restrict__ occ_off, const int* __restrict__ perm,
                                                    const cplx* __restrict__ P, const cplx* __restrict__ mu,
                                                    cplx* __restrict__ dens) {
   const int q = blockIdx.x;
+  const int nout = 4 * n_eq;
+  const int o = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (o >= nout) return;  // wave-uniform
   const int cell = occ_cell[q];
   const int off = occ_off[q], nq = occ_off[q + 1] - off;
-  const int nout = 4 * n_eq;
-  const cplx* Pq = P + (int64_t)nout * off;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int o = wv; o < nout; o += 4) {
-    const cplx* pr = Pq + (int64_t)o * nq;
-    cplx acc = cplx{0.0, 0.0};
-    for (int t = lane; t < nq; t += 64) acc += pr[t] * mu[perm[off + t]];
-    acc = wave_sum(acc);
-    if (lane == 0) {
-      const int lam = o / (2 * n_eq), oo = o % (2 * n_eq);
-      dens[((int64_t)lam * n_cells + cell) * 2 * n_eq + oo] = acc;
-    }
+  const cplx* pr = P + (int64_t)nout * off + (int64_t)o * nq;
+  cplx acc = cplx{0.0, 0.0};
+  for (int t = lane; t < nq; t += 64) acc += pr[t] * mu[perm[off + t]];
+  acc = wave_sum(acc);
+  if (lane == 0) {
+    const int lam = o / (2 * n_eq), oo = o % (2 * n_eq);
+    dens[((int64_t)lam * n_cells + cell) * 2 * n_eq + oo] = acc;
   }
 }
 
@@ -571,24 +577,15 @@ __global__ __launch_bounds__(256) void k_cells_far(FarArgs A, const int* __restr
     bv[b] = val - (part[0][b] + part[1][b] + part[2][b] + part[3][b]);
   }
   __syncthreads();
-  // plane-wave weights: least squares R w = Q^H b (eq. plwave_QR)
-  if (threadIdx.x < A.n_plw) {
-    const cplx* qrow = pplw + (int64_t)threadIdx.x * A.n_bdry;
-    cplx s = cplx{0.0, 0.0};
-    for (int b = 0; b < A.n_bdry; ++b) s += qrow[b] * bv[b];
-    wv_sh[threadIdx.x] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const cplx* Rm = pplw + (int64_t)A.n_plw * A.n_bdry;
-    for (int r = A.n_plw - 1; r >= 0; --r) {
-      cplx s = wv_sh[r];
-      const cplx* rr = Rm + (int64_t)r * A.n_plw;
-      for (int u = r + 1; u < A.n_plw; ++u) s -= rr[u] * wv_sh[u];
-      const cplx d = rr[r];
-      const double dd = 1.0 / abs2(d);
-      wv_sh[r] = cplx{(s.re * d.re + s.im * d.im) * dd, (s.im * d.re - s.re * d.im) * dd};
+  // plane-wave weights: least squares R w = Q^H b (eq. plwave_QR), on wavefront 0
+  if (wv == 0) {
+    cplx yu = cplx{0.0, 0.0};
+    if (lane < A.n_plw) {
+      const cplx* qrow = pplw + (int64_t)lane * A.n_bdry;
+      for (int b = 0; b < A.n_bdry; ++b) yu += qrow[b] * bv[b];
     }
+    yu = sesm_wave_backsub(pplw + (int64_t)A.n_plw * A.n_bdry, A.n_plw, yu);
+    if (lane < A.n_plw) wv_sh[lane] = yu;
   }
   __syncthreads();
   // surface values (eq. planewave), plane-wave origin at the cell centre
@@ -673,8 +670,11 @@ CellGeo cell_geo(const AccelOp& A) {
 int fft_rows(sesm_ctx* ctx, const FftPlan& p, int rows, const cplx* in, cplx* out, int sign, const cplx* pre,
              const cplx* post, double scale) {
   if (rows <= 0) return SESM_OK;
-  hipLaunchKernelGGL(k_fft_rows, dim3(rows), dim3(256), 0, ctx->stream, sesm_fft_args(p), in, (int64_t)p.n, out,
-                     (int64_t)p.n, p.tw, sign, pre, post, scale);
+  // several short rows per workgroup (LDS holds SESM_FFT_MAXN points per buffer); wide workgroups for long rows
+  const int rpb = std::max(1, std::min(rows, SESM_FFT_MAXN / p.n));
+  const int threads = p.n * rpb >= 1000 ? 1024 : 256;
+  hipLaunchKernelGGL(k_fft_rows, dim3((rows + rpb - 1) / rpb), dim3(threads), 0, ctx->stream, sesm_fft_args(p), rows,
+                     rpb, in, (int64_t)p.n, out, (int64_t)p.n, p.tw, sign, pre, post, scale);
   SESM_LAUNCH_CHECK();
   return SESM_OK;
 }
@@ -793,11 +793,22 @@ int sesm_accel_setup(sesm_ctx* ctx) {
   for (int q = 0; q < A->n_occ; ++q)
     near_off[q + 1] = near_off[q] + (int64_t)(occ_off[q + 1] - occ_off[q]) * col_w[occ_cell[q] % A->n_x];
   A->near_entries = near_off[A->n_occ];
+  std::vector<int64_t> row_off(N);
+  std::vector<int> row_lo(N), row_w(N);
+  for (int q = 0; q < A->n_occ; ++q) {
+    const int col = occ_cell[q] % A->n_x;
+    for (int t = occ_off[q]; t < occ_off[q + 1]; ++t) {
+      row_off[t] = near_off[q] + (int64_t)(t - occ_off[q]) * col_w[col];
+      row_lo[t] = col_lo[col];
+      row_w[t] = col_w[col];
+    }
+  }
   int rc;
   if ((rc = upload(ctx, &A->occ_cell, occ_cell)) || (rc = upload(ctx, &A->occ_off, occ_off)) ||
       (rc = upload(ctx, &A->perm, perm)) || (rc = upload(ctx, &A->col_lo, col_lo)) ||
       (rc = upload(ctx, &A->col_w, col_w)) || (rc = upload(ctx, &A->near_off, near_off)) ||
-      (rc = upload(ctx, &A->occ_flag, occ_flag)))
+      (rc = upload(ctx, &A->occ_flag, occ_flag)) || (rc = upload(ctx, &A->row_off, row_off)) ||
+      (rc = upload(ctx, &A->row_lo, row_lo)) || (rc = upload(ctx, &A->row_w, row_w)))
     return rc;
   const KParams K = ctx->kparams();
   const CellGeo G = cell_geo(*A);
@@ -822,7 +833,8 @@ int sesm_accel_setup(sesm_ctx* ctx) {
   }
   // --- P_q for every occupied cell
   if ((rc = sesm_alloc(ctx, (void**)&A->p2e, sizeof(cplx) * (size_t)4 * A->n_eq * N))) return rc;
-  hipLaunchKernelGGL(k_p2e_setup, dim3(A->n_occ), dim3(256), sizeof(cplx) * 4 * (nrow + ncol), ctx->stream, K, G,
+  if (ncol > 64) return ctx->fail(SESM_EINVAL, "accelerator: at most 64 equivalent-source unknowns per set");
+  hipLaunchKernelGGL(k_p2e_setup, dim3(A->n_occ), dim3(256), sizeof(cplx) * 4 * nrow, ctx->stream, K, G,
                      A->x0, A->y0, A->n_x, A->occ_cell, A->occ_off, A->perm, ctx->x, ctx->f, ctx->fp, A->pinv, A->p2e);
   SESM_LAUNCH_CHECK();
   // --- global kernel tables and their spectra
@@ -925,10 +937,10 @@ static int accel_matvec_impl(sesm_ctx* ctx, const cplx* mu, cplx* y, bool keep_f
   const Problem& P = ctx->P;
   const KParams K = ctx->kparams();
   hipStream_t st = ctx->stream;
-  hipLaunchKernelGGL(k_near_apply, dim3(A->n_occ), dim3(256), 0, st, P.N, A->n_x, A->occ_cell, A->occ_off, A->perm,
-                     A->col_lo, A->col_w, A->near_off, A->nearblk, mu, y);
-  hipLaunchKernelGGL(k_p2e_apply, dim3(A->n_occ), dim3(256), 0, st, A->n_eq, A->n_cells, A->occ_cell, A->occ_off,
-                     A->perm, A->p2e, mu, A->dens);
+  hipLaunchKernelGGL(k_near_apply, dim3((P.N + 3) / 4), dim3(256), 0, st, P.N, A->perm, A->row_off, A->row_lo,
+                     A->row_w, A->nearblk, mu, y);
+  hipLaunchKernelGGL(k_p2e_apply, dim3(A->n_occ, (4 * A->n_eq + 3) / 4), dim3(256), 0, st, A->n_eq, A->n_cells,
+                     A->occ_cell, A->occ_off, A->perm, A->p2e, mu, A->dens);
   MergeArgs M{A->n_x, A->n_y, A->n_s, A->n_e, A->n_side, A->n_eq, A->n_cells,
               A->nXH, A->nYH, A->nXV, A->nYV, P.alpha * P.d};
   const int ng = A->nXH * A->nYH + A->nXV * A->nYV;
@@ -994,4 +1006,17 @@ extern "C" int sesm_diag_accel(sesm_ctx* ctx, const sesm_c64* mu, int32_t which,
   (void)hipStreamSynchronize(ctx->stream);
   (void)hipFree(ytmp);
   return rc;
+}
+
+extern "C" int sesm_diag_near(sesm_ctx* ctx, const sesm_c64* mu, sesm_c64* y) {
+  if (!ctx) return SESM_EINVAL;
+  if (!ctx->ready) return ctx->fail(SESM_ENOSURF, "no surface");
+  if (ctx->P.mode != SESM_MODE_ACCEL || !ctx->acc) return ctx->fail(SESM_EINVAL, "not in accelerated mode");
+  if (!mu || !y || (const void*)mu == (const void*)y) return ctx->fail(SESM_EINVAL, "invalid vectors");
+  SESM_HIP(hipSetDevice(ctx->device));
+  AccelOp* A = ctx->acc;
+  hipLaunchKernelGGL(k_near_apply, dim3((ctx->P.N + 3) / 4), dim3(256), 0, ctx->stream, ctx->P.N, A->perm, A->row_off,
+                     A->row_lo, A->row_w, A->nearblk, (const cplx*)mu, (cplx*)y);
+  SESM_LAUNCH_CHECK();
+  return SESM_OK;
 }

@@ -133,7 +133,7 @@ void sesm_release_surface(sesm_ctx* ctx) {
   ctx->Mdense = nullptr;
   ctx->V = nullptr;
   ctx->V_cols = 0;
-  ctx->hcol = ctx->hpart = ctx->ybuf = ctx->wtmp = nullptr;
+  ctx->hcol = ctx->hpart = ctx->ybuf = ctx->wtmp = ctx->upart = nullptr;
   if (ctx->hhost) (void)hipHostFree(ctx->hhost);
   ctx->hhost = nullptr;
   ctx->ready = false;

@@ -38,48 +38,82 @@ struct FftArgs {
   int rad[SESM_FFT_MAXRAD];
 };
 
-// rows of `in` (row r at in + r*ld_in) -> rows of `out`; in-place allowed.
-//   out = sign < 0 ? FFT(pre . in) : IFFT-like sum with e^{+}, then . post * scale
-// pre/post: optional per-column factors (length n), may be null.
-__global__ __launch_bounds__(256) void k_fft_rows(FftArgs A, const cplx* in, int64_t ld_in, cplx* out,
-                                                  int64_t ld_out, const cplx* __restrict__ tw, int sign,
-                                                  const cplx* __restrict__ pre, const cplx* __restrict__ post,
-                                                  double scale) {
+// Radix-R butterflies y_u = sum_q x_q w^{uq}, w = exp(sign 2 pi i / R).
+__device__ inline void sesm_dft_small(int R, int sign, cplx* x) {
+  const double sg = sign < 0 ? -1.0 : 1.0;
+  if (R == 2) {
+    const cplx a = x[0], b = x[1];
+    x[0] = a + b;
+    x[1] = a - b;
+  } else if (R == 4) {
+    const cplx a = x[0] + x[2], b = x[0] - x[2], c = x[1] + x[3], d = x[1] - x[3];
+    const cplx id = sg * mul_i(d);  // sign * i * d
+    x[0] = a + c;
+    x[2] = a - c;
+    x[1] = b + id;
+    x[3] = b - id;
+  } else if (R == 3) {
+    const double c1 = -0.5, s1 = sg * 0.86602540378443864676;
+    const cplx t = x[1] + x[2], u = x[1] - x[2];
+    const cplx m = x[0] + c1 * t;
+    const cplx iu = s1 * mul_i(u);
+    x[0] = x[0] + t;
+    x[1] = m + iu;
+    x[2] = m - iu;
+  } else {  // R == 5
+    const double c1 = 0.30901699437494742410, c2 = -0.80901699437494742410;
+    const double s1 = sg * 0.95105651629515357212, s2 = sg * 0.58778525229247312917;
+    const cplx t1 = x[1] + x[4], t2 = x[2] + x[3], u1 = x[1] - x[4], u2 = x[2] - x[3];
+    const cplx a1 = x[0] + c1 * t1 + c2 * t2, a2 = x[0] + c2 * t1 + c1 * t2;
+    const cplx b1 = mul_i(s1 * u1 + s2 * u2), b2 = mul_i(s2 * u1 - s1 * u2);
+    x[0] = x[0] + t1 + t2;
+    x[1] = a1 + b1;
+    x[4] = a1 - b1;
+    x[2] = a2 + b2;
+    x[3] = a2 - b2;
+  }
+}
+
+// `rpb` rows of length n per workgroup: row r read from in + r*ld_in and
+// written to out + r*ld_out (in-place allowed).  out = scale * (DFT with
+// exp(sign 2 pi i jk/n) of (pre . in)) . post; pre/post optional (length n).
+__global__ __launch_bounds__(1024) void k_fft_rows(FftArgs A, int nrows, int rpb, const cplx* in, int64_t ld_in,
+                                                   cplx* out, int64_t ld_out, const cplx* __restrict__ tw, int sign,
+                                                   const cplx* __restrict__ pre, const cplx* __restrict__ post,
+                                                   double scale) {
   __shared__ cplx buf[2][SESM_FFT_MAXN];
   const int n = A.n;
-  const cplx* src = in + (int64_t)blockIdx.x * ld_in;
+  const int r0 = blockIdx.x * rpb;
+  const int nr = min(rpb, nrows - r0);
   cplx* a = buf[0];
   cplx* b = buf[1];
-  for (int i = threadIdx.x; i < n; i += 256) {
-    cplx v = src[i];
+  for (int e = threadIdx.x; e < nr * n; e += blockDim.x) {
+    const int r = e / n, i = e % n;
+    cplx v = in[(int64_t)(r0 + r) * ld_in + i];
     if (pre) v = v * pre[i];
-    a[i] = v;
+    a[e] = v;
   }
   __syncthreads();
   int p = 1;
   for (int s = 0; s < A.nrad; ++s) {
     const int R = A.rad[s];
     const int T = n / R;
-    const int step = n / (p * R);  // twiddle stride for exp(-2 pi i q k / (p R))
-    const int rstep = n / R;       // twiddle stride for the radix-R DFT
-    for (int i = threadIdx.x; i < T; i += 256) {
+    const int step = n / (p * R);  // twiddle stride: exp(-2 pi i q k / (p R)) = tw[q k step], q k step < n
+    for (int e = threadIdx.x; e < nr * T; e += blockDim.x) {
+      const int r = e / T, i = e % T;
       const int k = i % p;
+      const cplx* ar = a + r * n;
       cplx x[5];
-      for (int q = 0; q < R; ++q) {
-        cplx w = tw[(q * k * step) % n];
+      x[0] = ar[i];
+      for (int q = 1; q < R; ++q) {
+        cplx w = tw[q * k * step];
         if (sign > 0) w = conj(w);
-        x[q] = a[i + q * T] * w;
+        x[q] = ar[i + q * T] * w;
       }
+      sesm_dft_small(R, sign, x);
+      cplx* br = b + r * n;
       const int j = (i / p) * p * R + k;
-      for (int u = 0; u < R; ++u) {
-        cplx y = x[0];
-        for (int q = 1; q < R; ++q) {
-          cplx w = tw[((u * q) % R) * rstep];
-          if (sign > 0) w = conj(w);
-          y += x[q] * w;
-        }
-        b[j + u * p] = y;
-      }
+      for (int u = 0; u < R; ++u) br[j + u * p] = x[u];
     }
     __syncthreads();
     cplx* t = a;
@@ -87,11 +121,11 @@ __global__ __launch_bounds__(256) void k_fft_rows(FftArgs A, const cplx* in, int
     b = t;
     p *= R;
   }
-  cplx* dst = out + (int64_t)blockIdx.x * ld_out;
-  for (int i = threadIdx.x; i < n; i += 256) {
-    cplx v = scale * a[i];
+  for (int e = threadIdx.x; e < nr * n; e += blockDim.x) {
+    const int r = e / n, i = e % n;
+    cplx v = scale * a[e];
     if (post) v = v * post[i];
-    dst[i] = v;
+    out[(int64_t)(r0 + r) * ld_out + i] = v;
   }
 }
 

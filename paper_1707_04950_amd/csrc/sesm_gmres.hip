@@ -55,16 +55,31 @@ __global__ void k_dots_final(int nv, const cplx* __restrict__ part, cplx* __rest
   if (lane == 0) h[v] = accumulate ? h[v] + s : s;
 }
 
-// w[i] -= sum_{v < nv} V_v[i] h[v]
-__global__ __launch_bounds__(256) void k_update(int N, int nv, const cplx* __restrict__ V, int64_t ldv,
-                                                const cplx* __restrict__ h, cplx* __restrict__ w) {
-  extern __shared__ cplx hs[];
-  for (int v = threadIdx.x; v < nv; v += 256) hs[v] = h[v];
+// part[c][i] = sum_{v in chunk c} V_v[i] h[v]  (chunks of UCH vectors: more
+// workgroups than one pass over all vectors, and independent loads in flight)
+constexpr int UCH = 32;
+__global__ __launch_bounds__(256) void k_update_part(int N, int nv, const cplx* __restrict__ V, int64_t ldv,
+                                                     const cplx* __restrict__ h, cplx* __restrict__ part) {
+  __shared__ cplx hs[UCH];
+  const int c = blockIdx.y;
+  const int v0 = c * UCH, v1 = min(nv, v0 + UCH);
+  if (threadIdx.x < v1 - v0) hs[threadIdx.x] = h[v0 + threadIdx.x];
   __syncthreads();
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= N) return;
+  cplx s = cplx{0.0, 0.0};
+#pragma unroll 8
+  for (int v = v0; v < v1; ++v) s += V[(int64_t)v * ldv + i] * hs[v - v0];
+  part[(int64_t)c * N + i] = s;
+}
+
+// w[i] -= sum_c part[c][i]
+__global__ __launch_bounds__(256) void k_update_final(int N, int nch, const cplx* __restrict__ part,
+                                                      cplx* __restrict__ w) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
   cplx s = w[i];
-  for (int v = 0; v < nv; ++v) s -= V[(int64_t)v * ldv + i] * hs[v];
+  for (int c = 0; c < nch; ++c) s -= part[(int64_t)c * N + i];
   w[i] = s;
 }
 
@@ -141,6 +156,7 @@ int ensure_workspace(sesm_ctx* ctx, int m) {
     if ((rc = sesm_alloc(ctx, (void**)&ctx->hpart, sizeof(cplx) * (size_t)4200 * NCHUNK))) return rc;
     if ((rc = sesm_alloc(ctx, (void**)&ctx->ybuf, sizeof(cplx) * 4200))) return rc;
     if ((rc = sesm_alloc(ctx, (void**)&ctx->wtmp, sizeof(cplx) * (size_t)N))) return rc;
+    if ((rc = sesm_alloc(ctx, (void**)&ctx->upart, sizeof(cplx) * (size_t)N * ((4200 + UCH - 1) / UCH)))) return rc;
     if (hipHostMalloc((void**)&ctx->hhost, sizeof(cplx) * 4200, 0) != hipSuccess)
       return ctx->fail(SESM_ENOMEM, "hipHostMalloc failed");
   }
@@ -223,7 +239,9 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
         hipLaunchKernelGGL(k_dots, gd, dim3(256), 0, st, N, nv, V, ldv, w, ctx->hpart);
         hipLaunchKernelGGL(k_dots_final, dim3((nv + 3) / 4), dim3(256), 0, st, nv, ctx->hpart, ctx->hcol, pass);
         hipLaunchKernelGGL(k_dots_final, dim3((nv + 3) / 4), dim3(256), 0, st, nv, ctx->hpart, ctx->ybuf, 0);
-        hipLaunchKernelGGL(k_update, dim3(nb), dim3(256), sizeof(cplx) * nv, st, N, nv, V, ldv, ctx->ybuf, w);
+        const int nch = (nv + UCH - 1) / UCH;
+        hipLaunchKernelGGL(k_update_part, dim3(nb, nch), dim3(256), 0, st, N, nv, V, ldv, ctx->ybuf, ctx->upart);
+        hipLaunchKernelGGL(k_update_final, dim3(nb), dim3(256), 0, st, N, nch, ctx->upart, w);
       }
       hipLaunchKernelGGL(k_norm2_part, dim3(NCHUNK), dim3(256), 0, st, N, w, npart);
       hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(64), 0, st, npart, ctx->hcol + nv);

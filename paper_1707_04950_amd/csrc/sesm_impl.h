@@ -54,6 +54,7 @@ struct sesm_ctx {
   cplx* hhost = nullptr;     // pinned host copy of the column
   cplx* ybuf = nullptr;      // device copy of the small LS solution
   cplx* wtmp = nullptr;      // scratch vector of length N
+  cplx* upart = nullptr;     // partial sums of the Gram-Schmidt update
   std::vector<void*> owned;  // every device allocation made for the surface
   int64_t bytes = 0;
 
