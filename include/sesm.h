@@ -192,6 +192,40 @@ SESM_API int sesm_diag_near(sesm_ctx* ctx, const sesm_c64* mu, sesm_c64* y);
  * sesm_c64.  Enqueued on the context's stream. */
 SESM_API int sesm_diag_hankel(sesm_ctx* ctx, const double* x, int32_t n, sesm_c64* h0, sesm_c64* h1);
 
+/* Per-kernel timing.  Bit i of a mask selects kernel class i. */
+enum {
+  SESM_KT_NEAR = 0,   /* banded near-field GEMV (intersecting + singular + 1/2 I)   */
+  SESM_KT_P2E = 1,    /* cell equivalent-source densities from mu (EqSources) and the
+                         partial sums of the completion modes                        */
+  SESM_KT_MERGE = 2,  /* merge of the cell densities onto the periodic grids         */
+  SESM_KT_FFT = 3,    /* batched FFT along x of both grids (2 per forward map)      */
+  SESM_KT_YCONV = 4,  /* convolution along y per x-frequency, both grids (1 per map) */
+  SESM_KT_CELLS = 5,  /* local correction, plane-wave fit, surface values, modes     */
+  SESM_KT_DOTS = 6,   /* GMRES: dot products of w with the Krylov basis (per pass)   */
+  SESM_KT_UPDATE = 7, /* GMRES: partial sums of the basis update (per pass)          */
+  SESM_KT_GEMV = 8,   /* dense mode: GEMV with the stored operator                   */
+  SESM_KT_COUNT = 9
+};
+
+typedef struct {
+  char name[40];     /* kernel name                                                  */
+  int64_t launches;  /* launches timed since sesm_timing_enable                       */
+  double total_ms;   /* sum of their durations (a HIP event pair around each launch,
+                        recorded on the stream the kernel runs on)                    */
+  double bytes;      /* sum of their algorithmic HBM bytes: every input array read
+                        once and every output array written once                      */
+} sesm_kernel_stat;
+
+/* Start timing the kernel classes selected by mask, clearing all counters
+ * (mask 0 stops timing).  Timed launches are bracketed by HIP events; other
+ * launches are not touched.  Enqueues nothing itself. */
+SESM_API int sesm_timing_enable(sesm_ctx* ctx, uint32_t mask);
+
+/* Synchronise every stream the timed launches ran on and store SESM_KT_COUNT
+ * records (host array, capacity n_stats >= SESM_KT_COUNT), one per class in
+ * class order.  Counters keep accumulating until the next sesm_timing_enable. */
+SESM_API int sesm_timing_read(sesm_ctx* ctx, sesm_kernel_stat* stats, int32_t n_stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -41,6 +41,16 @@ class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("rel_residual", ctypes.c_double), ("converged", ctypes.c_int32)]
 
 
+# kernel classes of sesm_timing_enable (bit i of the mask selects class i)
+KT_NEAR, KT_P2E, KT_MERGE, KT_FFT, KT_YCONV, KT_CELLS, KT_DOTS, KT_UPDATE, KT_GEMV = range(9)
+KT_COUNT = 9
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 40), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
+
+
 class SurfaceInfo(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int32), ("n_a", ctypes.c_int32), ("dx", ctypes.c_double),
                 ("a", ctypes.c_double), ("gamma", ctypes.c_double), ("h", ctypes.c_double),
@@ -81,6 +91,8 @@ def load_library(path=LIB_PATH):
         "sesm_diag_hankel": (ctypes.c_int, [_P, _P, _I, _P, _P]),
         "sesm_diag_accel": (ctypes.c_int, [_P, _P, _I, _P, ctypes.c_int64]),
         "sesm_diag_near": (ctypes.c_int, [_P, _P, _P]),
+        "sesm_timing_enable": (ctypes.c_int, [_P, ctypes.c_uint32]),
+        "sesm_timing_read": (ctypes.c_int, [_P, _P, _I]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -203,6 +215,17 @@ class Solver:
         out = self.empty() if out is None else out
         self._check(self.lib.sesm_diag_near(self.h, _ptr(mu), _ptr(out)))
         return out
+
+    def timing_enable(self, mask):
+        """Time the kernel classes in `mask` (bit i = class KT_*) from now on; clears counters."""
+        self._check(self.lib.sesm_timing_enable(self.h, int(mask)))
+
+    def timing_read(self):
+        """Per-class records {name: dict(launches, total_ms, bytes)} since timing_enable."""
+        arr = (KernelStat * KT_COUNT)()
+        self._check(self.lib.sesm_timing_read(self.h, ctypes.cast(arr, ctypes.c_void_p), KT_COUNT))
+        return {r.name.decode(): {"launches": int(r.launches), "total_ms": float(r.total_ms), "bytes": float(r.bytes)}
+                for r in arr}
 
     def diag_hankel(self, x):
         torch = self._torch

@@ -17,19 +17,21 @@
 // (eq. S_jq_hat).  On a graph surface the near set of a column is one cyclic
 // band of nodes, stored as dense FP64 blocks (the HBM-bound part).
 //
-// Forward map, one stream, in order:
-//   k_near_apply    y  = near band (intersecting part eq. final_correction_0,
-//                        singular part eq. local_mat, 1/2 I)
+// Forward map (main stream unless noted):
 //   k_p2e_apply     (xi, zeta)^{q,lambda} = P_q^lambda mu_q   (EqSources, eq. eq_source_point)
+//                   + partial sums of the completion modes    (EvalModes, eq. M_eta)
+//   k_near_apply    y  = near band (intersecting part eq. final_correction_0,
+//                        singular part eq. local_mat, 1/2 I); side stream, forked
+//                        after k_p2e_apply so that the two HBM streams do not compete
 //   k_merge         twisted merged grids                     (GlobalEqSMerge, eq. sum_eqsources)
 //   k_fft_rows      FFT along x of both grids                (GlobalFFT, eq. large_convolution_per_grid)
 //   k_yconv         kernel-spectrum x sources, direct in y
 //   k_fft_rows      inverse FFT, untwist -> phi^all
+//   (join the side stream)
 //   k_cells_far     boundary values - local correction        (LocalEqSMerge, LocalFFT, LocalSubtract,
 //                   -> plane-wave weights -> surface values      Combine-lambda, PlaneWaveWeights,
-//                                                                NonIntersecting; eqs. psi_na_sum,
+//                   + completion modes D_M                       NonIntersecting; eqs. psi_na_sum,
 //                                                                combine_psi_pna, planewave, plwave_QR)
-//   k_modes_*       completion modes D_M                     (EvalModes, eq. M_eta)
 #include <algorithm>
 #include <cmath>
 #include <complex>
@@ -45,6 +47,7 @@ struct AccelOp {
   // geometry
   int n_x = 0, n_y = 0, n_s = 0, n_e = 0, n_coll = 0, n_plw = 0, ring = 1;
   int n_side = 0, n_eq = 0, n_bH = 0, n_bdry = 0, n_cells = 0, n_occ = 0, n_off = 0;
+  int max_q = 0;  // most nodes in one occupied cell
   double L = 0, delta = 0, x0 = 0, y0 = 0;
   int nXH = 0, nYH = 0, nXV = 0, nYV = 0;
   int64_t near_entries = 0;
@@ -57,13 +60,16 @@ struct AccelOp {
   cplx *p2e = nullptr, *nearblk = nullptr, *dens = nullptr;
   cplx *gH = nullptr, *gV = nullptr, *fH = nullptr, *fV = nullptr, *phH = nullptr, *phV = nullptr;
   cplx *specH = nullptr, *specV = nullptr, *W = nullptr;
-  cplx *pplw = nullptr;  // plane-wave least squares: Q^H (n_plw x n_bdry) then R (n_plw x n_plw)
+  cplx *pplw = nullptr;  // plane-wave least squares: (Q^H)^T (n_bdry x n_plw), R (n_plw x n_plw), 1 / diag(R)
   cplx *pinv = nullptr;  // equivalent-source least squares, per set: Q^H (2n_eq x 4n_coll) then R
   cplx *twxH = nullptr, *twxV = nullptr, *utwH = nullptr, *utwV = nullptr;  // e^{-i alpha x}, e^{+i alpha x}
   double* dirs = nullptr;
   cplx* mode_part = nullptr;
   cplx* yfar = nullptr;  // diagnostic copy of the far-field contribution
   FftPlan planH, planV;
+  // side streams (default priority) and fork/join events of the forward map
+  hipStream_t s_near = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_near = nullptr;
 };
 
 namespace {
@@ -190,6 +196,27 @@ __device__ inline cplx sesm_wave_backsub(const cplx* __restrict__ R, int n, cplx
   return yu;
 }
 
+// value of v in lane l (l wave-uniform), through the scalar unit
+__device__ inline double sesm_readlane(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// As sesm_wave_backsub, with the reciprocals of the diagonal given (dinv) so
+// that each step is a multiplication, and the solved entry broadcast by
+// readlane; R and dinv may live in LDS.
+__device__ inline cplx sesm_wave_backsub_dinv(const cplx* R, const cplx* dinv, int n, cplx yu) {
+  const int lane = threadIdx.x & 63;
+  for (int r = n - 1; r >= 0; --r) {
+    if (lane == r) yu = yu * dinv[r];
+    const cplx xr = cplx{sesm_readlane(yu.re, r), sesm_readlane(yu.im, r)};
+    if (lane < r) yu -= R[lane * n + r] * xr;
+  }
+  return yu;
+}
+
 // sum over shifts of one free-space kernel between x and y, punctured term by
 // term (terms with R_m <= 1e-9 h are dropped: the reading of eq. phi_def).
 // kind 0: monopole Phi_j; 1: d/dy2 Phi_j (H dipole); 2: d/dy1 Phi_j (V dipole).
@@ -270,7 +297,7 @@ __global__ __launch_bounds__(256) void k_p2e_setup(KParams K, CellGeo G, double 
           for (int c = 0; c < nrow; ++c) yu += qrow[c] * B[c];
         }
         yu = sesm_wave_backsub(Rm, ncol, yu);
-        if (lane < ncol) Pq[(int64_t)(lam * ncol + lane) * nq + t] = yu;
+        if (lane < ncol) Pq[(int64_t)t * 2 * ncol + lam * ncol + lane] = yu;
       }
     }
     __syncthreads();
@@ -308,9 +335,9 @@ __global__ __launch_bounds__(256) void k_lattice(KParams K, int lam, int nX, int
   }
 }
 
-// Local-correction matrices W[o][b][s]: free-space punctured kernel from the
-// equivalent sources of the cell at offset o = (ox, oy) to the boundary points
-// of the cell at the origin (eq. small_convolution).
+// Local-correction matrices W[o][s][b] (boundary point fastest): free-space
+// punctured kernel from the equivalent sources of the cell at offset
+// o = (ox, oy) to the boundary points of the cell at the origin (eq. small_convolution).
 __global__ void k_wmat(KParams K, CellGeo G, int n_y, int ring, cplx* __restrict__ W) {
   const int nb = 2 * (G.n_s + 1) + 2 * (G.n_s - 1), ns2 = 2 * G.n_eq;
   const int noff = (2 * ring + 1) * (2 * n_y - 1);
@@ -327,8 +354,8 @@ __global__ void k_wmat(KParams K, CellGeo G, int n_y, int ring, cplx* __restrict
   const double X = bx - (oxi * G.L + sx), Y = by - (oyi * G.L + sy);
   cplx mono, dip;
   sesm_green_pair(K, K.j, X, Y, &mono, &dip, lam == 0 ? 1 : 2);
-  W[((int64_t)o * nb + b) * ns2 + s] = mono;
-  W[((int64_t)o * nb + b) * ns2 + G.n_eq + s] = dip;
+  W[((int64_t)o * ns2 + s) * nb + b] = mono;
+  W[((int64_t)o * ns2 + G.n_eq + s) * nb + b] = dip;
 }
 
 // Near-field blocks: rows = nodes of the cell, columns = the band of the cell's
@@ -394,24 +421,57 @@ __global__ __launch_bounds__(256) void k_near_apply(int N, const int* __restrict
 }
 
 // EqSources: one wavefront per (cell, output), lanes over the cell's nodes.
-__global__ __launch_bounds__(256) void k_p2e_apply(int n_eq, int n_cells, const int* __restrict__ occ_cell,
-                                                   const int* __restrict__ occ_off, const int* __restrict__ perm,
-                                                   const cplx* __restrict__ P, const cplx* __restrict__ mu,
-                                                   cplx* __restrict__ dens) {
+// Workgroups [0, n_occ): dens[lam][cell][oo] = sum_t P[(off + t) * nout + o] mu[perm[off + t]],
+// o = lam 2 n_eq + oo.  Lanes run over the outputs o (rows of P are contiguous
+// in o); G = 256 / OW thread groups split the cell's nodes and are summed
+// through LDS.  Workgroups [n_occ, n_occ + NCH_MODES) (when U^eta is not
+// empty): partial sums of the completion modes over chunks of nodes,
+// part[n][c] = sum_l e^{-i alpha_n x_l - i beta_n f_l} J_l dx mu_l (eq. M_eta).
+__global__ __launch_bounds__(256) void k_p2e_apply(KParams K, int n_occ, int n_eq, int n_cells,
+                                                   const int* __restrict__ occ_cell, const int* __restrict__ occ_off,
+                                                   const int* __restrict__ perm, const cplx* __restrict__ P,
+                                                   const cplx* __restrict__ mu, cplx* __restrict__ dens,
+                                                   const double* __restrict__ x, const double* __restrict__ f,
+                                                   const double* __restrict__ J, cplx* __restrict__ mode_part) {
+  __shared__ cplx red[256];
   const int q = blockIdx.x;
+  if (q >= n_occ) {
+    const int c = q - n_occ;
+    const int per = (K.N + NCH_MODES - 1) / NCH_MODES;
+    const int lo = c * per, hi = min(K.N, lo + per);
+    for (int t = 0; t < K.nU; ++t) {
+      cplx acc = cplx{0.0, 0.0};
+      for (int l = lo + threadIdx.x; l < hi; l += 256) {
+        const double mag = exp(K.Ubi[t] * f[l]) * J[l] * K.dx;
+        acc += (mag * cexp_i(-(K.Ua[t] * x[l] + K.Ubr[t] * f[l]))) * mu[l];
+      }
+      const cplx sm = block_sum<256>(acc, red);
+      if (threadIdx.x == 0) mode_part[(int64_t)t * NCH_MODES + c] = sm;
+      __syncthreads();
+    }
+    return;
+  }
   const int nout = 4 * n_eq;
-  const int o = blockIdx.y * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (o >= nout) return;  // wave-uniform
+  const int OW = nout <= 64 ? 64 : (nout <= 128 ? 128 : 256);
+  const int G = 256 / OW, g = threadIdx.x / OW, oo0 = threadIdx.x % OW;
   const int cell = occ_cell[q];
   const int off = occ_off[q], nq = occ_off[q + 1] - off;
-  const cplx* pr = P + (int64_t)nout * off + (int64_t)o * nq;
-  cplx acc = cplx{0.0, 0.0};
-  for (int t = lane; t < nq; t += 64) acc += pr[t] * mu[perm[off + t]];
-  acc = wave_sum(acc);
-  if (lane == 0) {
-    const int lam = o / (2 * n_eq), oo = o % (2 * n_eq);
-    dens[((int64_t)lam * n_cells + cell) * 2 * n_eq + oo] = acc;
+  for (int ob = 0; ob < nout; ob += OW) {
+    const int o = ob + oo0;
+    cplx acc = cplx{0.0, 0.0};
+    if (o < nout) {
+      const cplx* pr = P + (int64_t)off * nout + o;
+#pragma unroll 4
+      for (int t = g; t < nq; t += G) acc += pr[(int64_t)t * nout] * mu[perm[off + t]];
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    if (g == 0 && o < nout) {
+      for (int gg = 1; gg < G; ++gg) acc += red[gg * OW + oo0];
+      const int lam = o / (2 * n_eq), oo = o % (2 * n_eq);
+      dens[((int64_t)lam * n_cells + cell) * 2 * n_eq + oo] = acc;
+    }
+    __syncthreads();
   }
 }
 
@@ -490,74 +550,204 @@ __global__ void k_merge(MergeArgs M, const cplx* __restrict__ dens, const cplx* 
   }
 }
 
-// phi_hat[t][kx] = sum_t' spec0[t-t'+nY-1][kx] g0[t'][kx] + spec1[...] g1[t'][kx]
-__global__ void k_yconv(int nX, int nY, const cplx* __restrict__ spec, const cplx* __restrict__ g,
-                        cplx* __restrict__ out) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nX * nY) return;
-  const int t = e / nX, kx = e % nX;
-  const int nrow = 2 * nY - 1;
-  const cplx* s0 = spec;
-  const cplx* s1 = spec + (int64_t)nrow * nX;
-  const cplx* g0 = g;
-  const cplx* g1 = g + (int64_t)nY * nX;
-  cplx acc = cplx{0.0, 0.0};
-  for (int tp = 0; tp < nY; ++tp) {
-    const int r = t - tp + nY - 1;
-    acc += s0[(int64_t)r * nX + kx] * g0[(int64_t)tp * nX + kx];
-    acc += s1[(int64_t)r * nX + kx] * g1[(int64_t)tp * nX + kx];
+// One grid of the y-direction convolution.
+struct YConvJob {
+  int nX, nY;
+  const cplx* spec;  // kernel spectra [2][2nY-1][nX]
+  const cplx* g;     // source spectra [2][nY][nX]
+  cplx* out;         // [nY][nX]
+};
+
+// phi_hat[t][kx] = sum_t' spec0[t-t'+nY-1][kx] g0[t'][kx] + spec1[...] g1[t'][kx].
+// Workgroups [0, hblocks) serve grid h, the rest grid v.  Short grids
+// (nY <= 32) take 8 x-frequencies per workgroup (32 threads each); taller
+// grids take one, with the sum over t' split in YC_SPLIT parts reduced in LDS.
+// The columns (sources and kernel spectra) are gathered row-wise (coalesced
+// over kx) into LDS first.
+constexpr int YC_KPB = 8, YC_SPLIT = 4;
+inline int yconv_kpb(int nY) { return nY <= 32 ? YC_KPB : 1; }
+inline size_t yconv_lds(int nY) {
+  const int per = 6 * nY - 2;
+  return sizeof(cplx) * (nY <= 32 ? (size_t)YC_KPB * per : (size_t)per + YC_SPLIT * nY);
+}
+__global__ __launch_bounds__(256) void k_yconv(YConvJob h, YConvJob v, int hblocks) {
+  extern __shared__ cplx col[];
+  const bool first = (int)blockIdx.x < hblocks;
+  const YConvJob& J = first ? h : v;
+  const int b = first ? blockIdx.x : blockIdx.x - hblocks;
+  const int nX = J.nX, nY = J.nY;
+  const int nrow = 2 * nY - 1, per = 6 * nY - 2;
+  const int kpb = nY <= 32 ? YC_KPB : 1;
+  const int kx0 = b * kpb, nk = min(kpb, nX - kx0);
+#pragma unroll 4
+  for (int e = threadIdx.x; e < per * kpb; e += 256) {
+    const int kl = e % kpb, r = e / kpb;
+    if (kl < nk) {
+      const int kx = kx0 + kl;
+      col[kl * per + r] = r < 2 * nY ? J.g[(int64_t)r * nX + kx] : J.spec[(int64_t)(r - 2 * nY) * nX + kx];
+    }
   }
-  out[e] = acc;
+  __syncthreads();
+  if (kpb > 1) {
+    const int kl = threadIdx.x >> 5, t = threadIdx.x & 31;
+    if (kl < nk && t < nY) {
+      const cplx* g0 = col + kl * per;
+      const cplx* g1 = g0 + nY;
+      const cplx* s0 = g0 + 2 * nY;
+      const cplx* s1 = s0 + nrow;
+      cplx a0 = cplx{0.0, 0.0}, a1 = cplx{0.0, 0.0};
+      for (int tp = 0; tp < nY; ++tp) {
+        const int r = t - tp + nY - 1;
+        a0 += s0[r] * g0[tp];
+        a1 += s1[r] * g1[tp];
+      }
+      J.out[(int64_t)t * nX + kx0 + kl] = a0 + a1;
+    }
+    return;
+  }
+  const cplx* g0 = col;
+  const cplx* g1 = g0 + nY;
+  const cplx* s0 = g0 + 2 * nY;
+  const cplx* s1 = s0 + nrow;
+  cplx* red = col + per;  // [YC_SPLIT][nY]
+  const int TPT = 256 / YC_SPLIT, g = threadIdx.x / TPT, tt = threadIdx.x % TPT;
+  const int chunk = (nY + YC_SPLIT - 1) / YC_SPLIT;
+  const int lo = g * chunk, hi = min(nY, lo + chunk);
+  for (int t = tt; t < nY; t += TPT) {
+    cplx a0 = cplx{0.0, 0.0}, a1 = cplx{0.0, 0.0};
+#pragma unroll 4
+    for (int tp = lo; tp < hi; ++tp) {
+      const int r = t - tp + nY - 1;
+      a0 += s0[r] * g0[tp];
+      a1 += s1[r] * g1[tp];
+    }
+    red[g * nY + t] = a0 + a1;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nY; t += 256) {
+    cplx sm = red[t];
+    for (int gg = 1; gg < YC_SPLIT; ++gg) sm += red[gg * nY + t];
+    J.out[(int64_t)t * nX + kx0] = sm;
+  }
 }
 
 struct FarArgs {
-  int N, n_x, n_y, n_s, n_e, n_side, n_eq, n_cells, n_bdry, n_bH, n_plw, nXH, nXV, ring;
+  int N, n_x, n_y, n_s, n_e, n_side, n_eq, n_cells, n_bdry, n_bH, n_plw, nXH, nXV, ring, max_q;
   double L, x0, y0, k, alpha_d;
 };
 
 // One block per occupied cell: boundary values of phi^all (H on horizontal
 // sides incl. corners, V on vertical sides), minus the equivalent sources of
-// the three columns (local correction), plane-wave weights, surface values.
-__global__ __launch_bounds__(256) void k_cells_far(FarArgs A, const int* __restrict__ occ_cell,
+// the near columns (local correction), plane-wave weights, surface values,
+// plus the completion modes D_M (partial sums from k_p2e_apply).  Dynamic LDS:
+// the plane-wave factors ((Q^H)^T, R, 1/diag R), the cell's nodes and their
+// values, and the list of occupied candidate cells.  Each phase keeps its
+// global loads independent so that they are in flight together.
+constexpr int CELLS_TB = 13;  // correction-matrix loads batched per lane
+__global__ __launch_bounds__(256) void k_cells_far(FarArgs A, KParams K, const int* __restrict__ occ_cell,
                                                    const int* __restrict__ occ_off, const int* __restrict__ perm,
                                                    const unsigned char* __restrict__ occ_flag,
                                                    const cplx* __restrict__ phH, const cplx* __restrict__ phV,
                                                    const cplx* __restrict__ dens, const cplx* __restrict__ W,
                                                    const cplx* __restrict__ pplw, const double* __restrict__ dirs,
                                                    const double* __restrict__ x, const double* __restrict__ f,
-                                                   cplx* __restrict__ y, cplx* __restrict__ yfar) {
+                                                   const cplx* __restrict__ mode_part, cplx* __restrict__ y,
+                                                   cplx* __restrict__ yfar) {
+  extern __shared__ cplx dyn[];
   __shared__ cplx part[4][64];
   __shared__ cplx bv[64];
   __shared__ cplx wv_sh[64];
+  __shared__ cplx msum[SESM_MAX_UETA];
+  __shared__ int n_occ_cand;
   const int q = blockIdx.x;
   const int cell = occ_cell[q];
   const int cx = cell % A.n_x, cy = cell / A.n_x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int ns2 = 2 * A.n_eq;
   const int nrowoff = 2 * A.n_y - 1;
-  // local correction: waves split the near cells, lanes the boundary points
+  const int ncand = (2 * A.ring + 1) * A.n_y;
+  const int off = occ_off[q], nq = occ_off[q + 1] - off;
+  const double ccx = A.x0 + (cx + 0.5) * A.L, ccy = A.y0 + (cy + 0.5) * A.L;
+  const int npf = (A.n_bdry + A.n_plw + 1) * A.n_plw;  // plane-wave factors
+  cplx* pf = dyn;
+  cplx* ys = pf + npf;                                             // [max_q] surface values
+  double* xs = reinterpret_cast<double*>(ys + A.max_q);            // [max_q] x, then [max_q] f
+  int* node = reinterpret_cast<int*>(xs + 2 * A.max_q);            // [max_q] node index
+  int* cand = node + A.max_q;                                      // [ncand][3] (o, rc, wrap)
+  // phase 0: stage the plane-wave factors and the cell's nodes; candidate
+  // occupancy (wave 0, ordered compaction by ballot: fixed summation order);
+  // completion-mode sums (wave 1)
+  for (int e = threadIdx.x; e < npf; e += 256) pf[e] = pplw[e];
+  for (int t = threadIdx.x; t < nq; t += 256) {
+    const int i = perm[off + t];
+    node[t] = i;
+    xs[t] = x[i];
+    xs[A.max_q + t] = f[i];
+  }
+  if (wv == 0) {
+    int base = 0;
+    for (int r0 = 0; r0 < ncand; r0 += 64) {
+      const int r = r0 + lane;
+      bool occ = false;
+      int o = 0, rc = 0, Wr = 0;
+      if (r < ncand) {
+        const int dc = r / A.n_y - A.ring, ry = r % A.n_y;
+        int col = cx + dc;
+        if (col < 0) { col += A.n_x; Wr = -1; }
+        else if (col >= A.n_x) { col -= A.n_x; Wr = 1; }
+        rc = ry * A.n_x + col;
+        o = (dc + A.ring) * nrowoff + (ry - cy + A.n_y - 1);
+        occ = occ_flag[rc] != 0;
+      }
+      const unsigned long long m = __ballot(occ);
+      const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
+      if (occ) {
+        cand[3 * pos] = o;
+        cand[3 * pos + 1] = rc;
+        cand[3 * pos + 2] = Wr;
+      }
+      base += __popcll(m);
+    }
+    if (lane == 0) n_occ_cand = base;
+  } else if (wv == 1) {
+    for (int t = 0; t < K.nU; ++t) {
+      cplx a = cplx{0.0, 0.0};
+      for (int c = lane; c < NCH_MODES; c += 64) a += mode_part[(int64_t)t * NCH_MODES + c];
+      a = wave_sum(a);
+      if (lane == 0) msum[t] = a;
+    }
+  }
+  __syncthreads();
+  // phase 1: local correction: waves split the occupied candidates, lanes the
+  // boundary points; W rows are contiguous over boundary points
   cplx acc = cplx{0.0, 0.0};
+  const int nc = n_occ_cand;
   if (lane < A.n_bdry) {
     const int lam = lane < A.n_bH ? 0 : 1;
-    const int ncand = (2 * A.ring + 1) * A.n_y;
-    for (int r = wv; r < ncand; r += 4) {
-      const int dc = r / A.n_y - A.ring, ry = r % A.n_y;
-      int col = cx + dc, Wr = 0;
-      if (col < 0) { col += A.n_x; Wr = -1; }
-      else if (col >= A.n_x) { col -= A.n_x; Wr = 1; }
-      const int rc = ry * A.n_x + col;
-      if (!occ_flag[rc]) continue;
-      const int o = (dc + A.ring) * nrowoff + (ry - cy + A.n_y - 1);
-      const cplx* Wr_b = W + ((int64_t)o * A.n_bdry + lane) * ns2;
+    for (int c = wv; c < nc; c += 4) {
+      const int o = cand[3 * c], rc = cand[3 * c + 1], Wr = cand[3 * c + 2];
+      const cplx* Wo = W + (int64_t)o * ns2 * A.n_bdry + lane;
       const cplx* v = dens + ((int64_t)lam * A.n_cells + rc) * ns2;
-      cplx s = cplx{0.0, 0.0};
-      for (int t = 0; t < ns2; ++t) s += Wr_b[t] * v[t];
-      if (Wr != 0) s = cexp_i(A.alpha_d * Wr) * s;
-      acc += s;
+      cplx sm = cplx{0.0, 0.0};
+      for (int t0 = 0; t0 < ns2; t0 += CELLS_TB) {
+        cplx wt[CELLS_TB], dt[CELLS_TB];
+#pragma unroll
+        for (int u = 0; u < CELLS_TB; ++u) {
+          const int t = min(t0 + u, ns2 - 1);
+          wt[u] = Wo[(int64_t)t * A.n_bdry];
+          dt[u] = v[t];
+        }
+#pragma unroll
+        for (int u = 0; u < CELLS_TB; ++u)
+          if (t0 + u < ns2) sm += wt[u] * dt[u];
+      }
+      if (Wr != 0) sm = cexp_i(A.alpha_d * Wr) * sm;
+      acc += sm;
     }
   }
   part[wv][lane] = acc;
   __syncthreads();
+  // phase 2: boundary values of phi^all minus the local correction
   if (threadIdx.x < A.n_bdry) {
     const int b = threadIdx.x;
     cplx val;
@@ -577,71 +767,65 @@ __global__ __launch_bounds__(256) void k_cells_far(FarArgs A, const int* __restr
     bv[b] = val - (part[0][b] + part[1][b] + part[2][b] + part[3][b]);
   }
   __syncthreads();
-  // plane-wave weights: least squares R w = Q^H b (eq. plwave_QR), on wavefront 0
+  // phase 3: plane-wave weights, least squares R w = Q^H b (eq. plwave_QR), on wavefront 0
   if (wv == 0) {
     cplx yu = cplx{0.0, 0.0};
-    if (lane < A.n_plw) {
-      const cplx* qrow = pplw + (int64_t)lane * A.n_bdry;
-      for (int b = 0; b < A.n_bdry; ++b) yu += qrow[b] * bv[b];
-    }
-    yu = sesm_wave_backsub(pplw + (int64_t)A.n_plw * A.n_bdry, A.n_plw, yu);
+    if (lane < A.n_plw)
+      for (int b = 0; b < A.n_bdry; ++b) yu += pf[b * A.n_plw + lane] * bv[b];
+    const cplx* Rs = pf + A.n_bdry * A.n_plw;
+    yu = sesm_wave_backsub_dinv(Rs, Rs + A.n_plw * A.n_plw, A.n_plw, yu);
     if (lane < A.n_plw) wv_sh[lane] = yu;
   }
   __syncthreads();
-  // surface values (eq. planewave), plane-wave origin at the cell centre
-  const int off = occ_off[q], nq = occ_off[q + 1] - off;
-  const double ccx = A.x0 + (cx + 0.5) * A.L, ccy = A.y0 + (cy + 0.5) * A.L;
-  for (int t = threadIdx.x; t < nq; t += 256) {
-    const int i = perm[off + t];
-    const double px = x[i] - ccx, py = f[i] - ccy;
-    cplx s = cplx{0.0, 0.0};
-    for (int u = 0; u < A.n_plw; ++u) s += wv_sh[u] * cexp_i(A.k * (dirs[2 * u] * px + dirs[2 * u + 1] * py));
-    y[i] += s;
-    if (yfar) yfar[i] = s;
+  // phase 4: surface values (eq. planewave), origin at the cell centre.  With
+  // n_plw even, directions u and u + n_plw/2 are opposite, so one exponential
+  // serves both (its conjugate).  Groups of UPL lanes take one node each.
+  const bool pairs = (A.n_plw & 1) == 0;
+  const int nd = pairs ? A.n_plw / 2 : A.n_plw;
+  const int UPL = nd <= 16 ? 16 : (nd <= 32 ? 32 : 64);
+  const int u = threadIdx.x & (UPL - 1), slot = threadIdx.x / UPL, nslot = 256 / UPL;
+  double dxu = 0.0, dyu = 0.0;
+  cplx wa = cplx{0.0, 0.0}, wb = cplx{0.0, 0.0};
+  if (u < nd) {
+    dxu = A.k * dirs[2 * u];
+    dyu = A.k * dirs[2 * u + 1];
+    wa = wv_sh[u];
+    if (pairs) wb = wv_sh[u + nd];
   }
-}
-
-// completion modes: partial sums s_n = sum_l e^{-i alpha_n x_l - i beta_n f_l} J_l dx mu_l
-__global__ __launch_bounds__(256) void k_modes_part(KParams K, const double* __restrict__ x,
-                                                    const double* __restrict__ f, const double* __restrict__ J,
-                                                    const cplx* __restrict__ mu, cplx* __restrict__ part) {
-  __shared__ cplx sh[4];
-  const int per = (K.N + NCH_MODES - 1) / NCH_MODES;
-  const int lo = blockIdx.x * per, hi = min(K.N, lo + per);
-  for (int t = 0; t < K.nU; ++t) {
-    cplx acc = cplx{0.0, 0.0};
-    for (int l = lo + threadIdx.x; l < hi; l += 256) {
-      const double mag = exp(K.Ubi[t] * f[l]) * J[l] * K.dx;
-      acc += (mag * cexp_i(-(K.Ua[t] * x[l] + K.Ubr[t] * f[l]))) * mu[l];
+  for (int t0 = 0; t0 < nq; t0 += nslot) {  // uniform trip count (shuffles below)
+    const int t = t0 + slot;
+    cplx sv = cplx{0.0, 0.0};
+    if (t < nq && u < nd) {
+      const cplx e = cexp_i(dxu * (xs[t] - ccx) + dyu * (xs[A.max_q + t] - ccy));
+      sv = wa * e + wb * conj(e);
     }
-    const cplx s = block_sum<256>(acc, sh);
-    if (threadIdx.x == 0) part[(int64_t)t * NCH_MODES + blockIdx.x] = s;
-    __syncthreads();
-  }
-}
-
-// y_i += sum_n e^{i alpha_n x_i + i beta_n f_i} s_n  (each block re-reduces the partials)
-__global__ __launch_bounds__(256) void k_modes_add(KParams K, const double* __restrict__ x,
-                                                   const double* __restrict__ f, const cplx* __restrict__ part,
-                                                   cplx* __restrict__ y) {
-  __shared__ cplx s_sh[SESM_MAX_UETA];
-  if (threadIdx.x < 64) {
-    for (int t = 0; t < K.nU; ++t) {
-      cplx a = cplx{0.0, 0.0};
-      for (int c = threadIdx.x; c < NCH_MODES; c += 64) a += part[(int64_t)t * NCH_MODES + c];
-      a = wave_sum(a);
-      if (threadIdx.x == 0) s_sh[t] = a;
+    for (int m = UPL >> 1; m > 0; m >>= 1) {
+      sv.re += __shfl_xor(sv.re, m);
+      sv.im += __shfl_xor(sv.im, m);
     }
+    if (t < nq && u == 0) ys[t] = sv;
   }
   __syncthreads();
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= K.N) return;
-  cplx acc = cplx{0.0, 0.0};
-  for (int t = 0; t < K.nU; ++t) {
-    const double mag = exp(-K.Ubi[t] * f[i]);
-    acc += (mag * cexp_i(K.Ua[t] * x[i] + K.Ubr[t] * f[i])) * s_sh[t];
+  // phase 5: y_i += far value + completion modes sum_n e^{i alpha_n x_i + i beta_n f_i} s_n
+  for (int t = threadIdx.x; t < nq; t += 256) {
+    const int i = node[t];
+    const cplx v = ys[t];
+    cplx md = cplx{0.0, 0.0};
+    for (int n = 0; n < K.nU; ++n) {
+      const double mag = exp(-K.Ubi[n] * xs[A.max_q + t]);
+      md += (mag * cexp_i(K.Ua[n] * xs[t] + K.Ubr[n] * xs[A.max_q + t])) * msum[n];
+    }
+    y[i] += v + md;
+    if (yfar) yfar[i] = v;
   }
-  y[i] += acc;
+}
+
+// dynamic LDS bytes of k_cells_far
+inline size_t cells_far_lds(const AccelOp* A) {
+  const size_t npf = (size_t)(A->n_bdry + A->n_plw + 1) * A->n_plw;
+  const size_t ncand = (size_t)(2 * A->ring + 1) * A->n_y;
+  const size_t mq = (size_t)A->max_q;
+  return sizeof(cplx) * (npf + mq) + sizeof(double) * 2 * mq + sizeof(int) * (mq + 3 * ncand);
 }
 
 template <typename T>
@@ -667,14 +851,12 @@ CellGeo cell_geo(const AccelOp& A) {
   return G;
 }
 
-int fft_rows(sesm_ctx* ctx, const FftPlan& p, int rows, const cplx* in, cplx* out, int sign, const cplx* pre,
-             const cplx* post, double scale) {
-  if (rows <= 0) return SESM_OK;
-  // several short rows per workgroup (LDS holds SESM_FFT_MAXN points per buffer); wide workgroups for long rows
-  const int rpb = std::max(1, std::min(rows, SESM_FFT_MAXN / p.n));
-  const int threads = p.n * rpb >= 1000 ? 1024 : 256;
-  hipLaunchKernelGGL(k_fft_rows, dim3((rows + rpb - 1) / rpb), dim3(threads), 0, ctx->stream, sesm_fft_args(p), rows,
-                     rpb, in, (int64_t)p.n, out, (int64_t)p.n, p.tw, sign, pre, post, scale);
+// One launch of k_fft_rows for up to two jobs (j1 may be empty).
+int fft_launch(sesm_ctx* ctx, hipStream_t st, const FftJob& j0, const FftJob& j1, int sign) {
+  const int nb = j0.nblocks + j1.nblocks;
+  if (nb == 0) return SESM_OK;
+  const bool wide = (j0.nblocks && j0.A.n * j0.rpb >= 1000) || (j1.nblocks && j1.A.n * j1.rpb >= 1000);
+  hipLaunchKernelGGL(k_fft_rows, dim3(nb), dim3(wide ? 1024 : 256), 0, st, j0, j1, sign);
   SESM_LAUNCH_CHECK();
   return SESM_OK;
 }
@@ -682,7 +864,16 @@ int fft_rows(sesm_ctx* ctx, const FftPlan& p, int rows, const cplx* in, cplx* ou
 }  // namespace
 
 void sesm_accel_free(sesm_ctx* ctx) {
-  delete ctx->acc;  // device buffers are in ctx->owned
+  AccelOp* A = ctx->acc;
+  if (A) {
+    if (A->s_near) {
+      (void)hipStreamSynchronize(A->s_near);
+      (void)hipStreamDestroy(A->s_near);
+    }
+    for (hipEvent_t ev : {A->ev_fork, A->ev_near})
+      if (ev) (void)hipEventDestroy(ev);
+  }
+  delete A;  // device buffers are in ctx->owned
   ctx->acc = nullptr;
 }
 
@@ -751,6 +942,7 @@ int sesm_accel_setup(sesm_ctx* ctx) {
   A->nYV = A->n_y * A->n_s + 1 + 2 * A->n_e;
   if (!sesm_fft_factor(A->nXH, &A->planH) || !sesm_fft_factor(A->nXV, &A->planV) || A->nXH > SESM_FFT_MAXN)
     return ctx->fail(SESM_EINVAL, "accelerator: periodic grid length must be 5-smooth and <= 2000");
+  if (A->nYV > 400) return ctx->fail(SESM_EINVAL, "accelerator: surface too tall for the cell size (n_y n_s > 400)");
   // cells of the nodes, (a, b] convention
   std::vector<int> cellof(N), colof(N);
   for (int l = 0; l < N; ++l) {
@@ -776,6 +968,7 @@ int sesm_accel_setup(sesm_ctx* ctx) {
   }
   occ_off.push_back(N);
   A->n_occ = (int)occ_cell.size();
+  for (int q = 0; q < A->n_occ; ++q) A->max_q = std::max(A->max_q, occ_off[q + 1] - occ_off[q]);
   // column bands: nodes of columns c-ring..c+ring (cyclic), as a range [lo, lo + w)
   std::vector<int> first(A->n_x + 1, N);
   for (int l = N - 1; l >= 0; --l) first[colof[l]] = l;
@@ -871,11 +1064,17 @@ int sesm_accel_setup(sesm_ctx* ctx) {
     hipLaunchKernelGGL(k_lattice, dim3((unsigned)((ent + 3) / 4)), dim3(256), 0, ctx->stream, K, lam, nX, nY, hxs,
                        hys, pmax, spec);
     SESM_LAUNCH_CHECK();
-    if ((rc = fft_rows(ctx, lam == 0 ? A->planH : A->planV, 2 * nrows, spec, spec, -1, nullptr, nullptr, 1.0)))
-      return rc;
+    const FftJob J = sesm_fft_job(lam == 0 ? A->planH : A->planV, 2 * nrows, spec, spec, nullptr, nullptr, 1.0);
+    if ((rc = fft_launch(ctx, ctx->stream, J, FftJob{}, -1))) return rc;
   }
   // --- local correction matrices
   A->n_off = (2 * A->ring + 1) * (2 * A->n_y - 1);
+  {
+    const size_t lds = cells_far_lds(A);
+    if (lds > 140 * 1024) return ctx->fail(SESM_EINVAL, "accelerator: plane-wave factors exceed the LDS of a workgroup");
+    if (lds > 64 * 1024)
+      SESM_HIP(hipFuncSetAttribute((const void*)k_cells_far, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  }
   {
     const int64_t nW = (int64_t)A->n_off * A->n_bdry * ncol;
     if ((rc = sesm_alloc(ctx, (void**)&A->W, sizeof(cplx) * (size_t)nW))) return rc;
@@ -905,8 +1104,16 @@ int sesm_accel_setup(sesm_ctx* ctx) {
     std::vector<C> Qh, Rm;
     if (!ls_qr(A->n_bdry, A->n_plw, E, Qh, Rm)) return ctx->fail(SESM_EINVAL, "plane-wave matrix is rank deficient");
     std::vector<cplx> pv;
-    for (const C& v : Qh) pv.push_back(cplx{v.real(), v.imag()});
+    for (int b = 0; b < A->n_bdry; ++b)
+      for (int u = 0; u < A->n_plw; ++u) {
+        const C v = Qh[(size_t)u * A->n_bdry + b];
+        pv.push_back(cplx{v.real(), v.imag()});
+      }
     for (const C& v : Rm) pv.push_back(cplx{v.real(), v.imag()});
+    for (int u = 0; u < A->n_plw; ++u) {
+      const C v = 1.0 / Rm[(size_t)u * A->n_plw + u];
+      pv.push_back(cplx{v.real(), v.imag()});
+    }
     if ((rc = upload(ctx, &A->pplw, pv)) || (rc = upload(ctx, &A->dirs, dirs))) return rc;
   }
   // --- near-field blocks
@@ -929,7 +1136,49 @@ int sesm_accel_setup(sesm_ctx* ctx) {
       (rc = sesm_alloc(ctx, (void**)&A->yfar, sizeof(cplx) * (size_t)N)))
     return rc;
   SESM_HIP(hipMemsetAsync(A->dens, 0, sizeof(cplx) * (size_t)2 * A->n_cells * ncol, ctx->stream));
+  // side stream of the near field (default priority); fork/join events need
+  // only device-scope release (both streams run on this device)
+  SESM_HIP(hipStreamCreateWithFlags(&A->s_near, hipStreamNonBlocking));
+  for (hipEvent_t* ev : {&A->ev_fork, &A->ev_near})
+    SESM_HIP(hipEventCreateWithFlags(ev, hipEventDisableTiming | hipEventReleaseToDevice));
   return SESM_OK;
+}
+
+// Algorithmic HBM bytes of one launch of each forward-map kernel (every
+// input array read once, every output written once).
+struct MatvecBytes {
+  double near, p2e, merge, fftH0, fftH1, fftV0, fftV1, yconvH, yconvV, cells;
+};
+
+static MatvecBytes matvec_bytes(const sesm_ctx* ctx) {
+  const AccelOp* A = ctx->acc;
+  const double N = ctx->P.N, c = sizeof(cplx);
+  const double nout = 4.0 * A->n_eq, ns2 = 2.0 * A->n_eq;
+  const double nH = (double)A->nXH * A->nYH, nV = (double)A->nXV * A->nYV;
+  const double dens = c * 2.0 * A->n_cells * ns2;
+  MatvecBytes B;
+  // stored blocks + mu + y + per-row offset (8 B), band start, width and node index (4 B each)
+  B.near = c * (double)A->near_entries + N * (2.0 * c + 20.0);
+  // operators + mu + node index + densities of the occupied cells + cell tables
+  // (+ x, f, J and the mode partial sums when U^eta is not empty)
+  B.p2e = c * nout * N + N * (c + 4.0) + A->n_occ * (c * nout + 12.0) +
+          (ctx->P.nU > 0 ? N * 24.0 + c * ctx->P.nU * NCH_MODES : 0.0);
+  // densities + grids (xi, zeta) + twist factors
+  B.merge = dens + c * 2.0 * (nH + nV) + c * (A->nXH + A->nXV);
+  // rows in + rows out (+ twiddle table; untwist factors on the inverse transforms)
+  B.fftH0 = c * (2.0 * 2.0 * A->nYH * A->nXH + A->nXH);
+  B.fftH1 = c * (2.0 * A->nYH * A->nXH + 2.0 * A->nXH);
+  B.fftV0 = c * (2.0 * 2.0 * A->nYV * A->nXV + A->nXV);
+  B.fftV1 = c * (2.0 * A->nYV * A->nXV + 2.0 * A->nXV);
+  // spectra of both grids in, both kernel spectra, one output grid
+  B.yconvH = c * (2.0 * nH + 2.0 * (2.0 * A->nYH - 1) * A->nXH + nH);
+  B.yconvV = c * (2.0 * nV + 2.0 * (2.0 * A->nYV - 1) * A->nXV + nV);
+  // correction matrices, densities, phi grids, plane-wave QR, directions, flags,
+  // cell tables, node coordinates and index, y read and written, mode sums
+  B.cells = c * (double)A->n_off * ns2 * A->n_bdry + dens + c * (nH + nV) +
+            c * ((double)A->n_bdry * A->n_plw + (double)A->n_plw * A->n_plw + A->n_plw) + 16.0 * A->n_plw +
+            A->n_cells + 12.0 * A->n_occ + N * (16.0 + 4.0 + 2.0 * c) + c * ctx->P.nU * NCH_MODES;
+  return B;
 }
 
 static int accel_matvec_impl(sesm_ctx* ctx, const cplx* mu, cplx* y, bool keep_far) {
@@ -937,40 +1186,62 @@ static int accel_matvec_impl(sesm_ctx* ctx, const cplx* mu, cplx* y, bool keep_f
   const Problem& P = ctx->P;
   const KParams K = ctx->kparams();
   hipStream_t st = ctx->stream;
-  hipLaunchKernelGGL(k_near_apply, dim3((P.N + 3) / 4), dim3(256), 0, st, P.N, A->perm, A->row_off, A->row_lo,
+  const MatvecBytes B = ctx->kt_mask ? matvec_bytes(ctx) : MatvecBytes{};
+  int rc;
+  // cell densities (+ mode partial sums) first, alone on the HBM
+  SESM_KT_BEGIN(SESM_KT_P2E, st);
+  hipLaunchKernelGGL(k_p2e_apply, dim3(A->n_occ + (P.nU > 0 ? NCH_MODES : 0)), dim3(256), 0, st, K, A->n_occ,
+                     A->n_eq, A->n_cells, A->occ_cell, A->occ_off, A->perm, A->p2e, mu, A->dens, ctx->x, ctx->f,
+                     ctx->J, A->mode_part);
+  SESM_LAUNCH_CHECK();
+  SESM_KT_END(SESM_KT_P2E, st, B.p2e);
+  // fork: the near field (HBM-bound) runs beside the rest of the far-field pipeline
+  SESM_HIP(hipEventRecord(A->ev_fork, st));
+  SESM_HIP(hipStreamWaitEvent(A->s_near, A->ev_fork, 0));
+  SESM_KT_BEGIN(SESM_KT_NEAR, A->s_near);
+  hipLaunchKernelGGL(k_near_apply, dim3((P.N + 3) / 4), dim3(256), 0, A->s_near, P.N, A->perm, A->row_off, A->row_lo,
                      A->row_w, A->nearblk, mu, y);
-  hipLaunchKernelGGL(k_p2e_apply, dim3(A->n_occ, (4 * A->n_eq + 3) / 4), dim3(256), 0, st, A->n_eq, A->n_cells,
-                     A->occ_cell, A->occ_off, A->perm, A->p2e, mu, A->dens);
+  SESM_LAUNCH_CHECK();
+  SESM_KT_END(SESM_KT_NEAR, A->s_near, B.near);
+  SESM_HIP(hipEventRecord(A->ev_near, A->s_near));
   MergeArgs M{A->n_x, A->n_y, A->n_s, A->n_e, A->n_side, A->n_eq, A->n_cells,
               A->nXH, A->nYH, A->nXV, A->nYV, P.alpha * P.d};
   const int ng = A->nXH * A->nYH + A->nXV * A->nYV;
+  SESM_KT_BEGIN(SESM_KT_MERGE, st);
   hipLaunchKernelGGL(k_merge, dim3((ng + 255) / 256), dim3(256), 0, st, M, A->dens, A->twxH, A->twxV, A->gH, A->gV);
   SESM_LAUNCH_CHECK();
-  int rc;
-  if ((rc = fft_rows(ctx, A->planH, 2 * A->nYH, A->gH, A->fH, -1, nullptr, nullptr, 1.0)) ||
-      (rc = fft_rows(ctx, A->planV, 2 * A->nYV, A->gV, A->fV, -1, nullptr, nullptr, 1.0)))
+  SESM_KT_END(SESM_KT_MERGE, st, B.merge);
+  // both grids in each launch: forward FFT along x, y convolution, inverse FFT + untwist
+  SESM_KT_BEGIN(SESM_KT_FFT, st);
+  if ((rc = fft_launch(ctx, st, sesm_fft_job(A->planH, 2 * A->nYH, A->gH, A->fH, nullptr, nullptr, 1.0),
+                       sesm_fft_job(A->planV, 2 * A->nYV, A->gV, A->fV, nullptr, nullptr, 1.0), -1)))
     return rc;
-  // y-convolution into the second half of the f buffers, then inverse FFT with untwist
-  cplx* hatH = A->gH;  // reuse: merged grids are no longer needed
-  cplx* hatV = A->gV;
-  hipLaunchKernelGGL(k_yconv, dim3((A->nXH * A->nYH + 255) / 256), dim3(256), 0, st, A->nXH, A->nYH, A->specH, A->fH,
-                     hatH);
-  hipLaunchKernelGGL(k_yconv, dim3((A->nXV * A->nYV + 255) / 256), dim3(256), 0, st, A->nXV, A->nYV, A->specV, A->fV,
-                     hatV);
-  SESM_LAUNCH_CHECK();
-  if ((rc = fft_rows(ctx, A->planH, A->nYH, hatH, A->phH, +1, nullptr, A->utwH, 1.0 / A->nXH)) ||
-      (rc = fft_rows(ctx, A->planV, A->nYV, hatV, A->phV, +1, nullptr, A->utwV, 1.0 / A->nXV)))
-    return rc;
-  FarArgs F{P.N, A->n_x, A->n_y, A->n_s, A->n_e, A->n_side, A->n_eq, A->n_cells, A->n_bdry, A->n_bH, A->n_plw,
-            A->nXH, A->nXV, A->ring, A->L, A->x0, A->y0, P.k, P.alpha * P.d};
-  hipLaunchKernelGGL(k_cells_far, dim3(A->n_occ), dim3(256), 0, st, F, A->occ_cell, A->occ_off, A->perm, A->occ_flag,
-                     A->phH, A->phV, A->dens, A->W, A->pplw, A->dirs, ctx->x, ctx->f, y, keep_far ? A->yfar : nullptr);
-  SESM_LAUNCH_CHECK();
-  if (P.nU > 0) {
-    hipLaunchKernelGGL(k_modes_part, dim3(NCH_MODES), dim3(256), 0, st, K, ctx->x, ctx->f, ctx->J, mu, A->mode_part);
-    hipLaunchKernelGGL(k_modes_add, dim3((P.N + 255) / 256), dim3(256), 0, st, K, ctx->x, ctx->f, A->mode_part, y);
+  SESM_KT_END(SESM_KT_FFT, st, B.fftH0 + B.fftV0);
+  SESM_KT_BEGIN(SESM_KT_YCONV, st);
+  {
+    const YConvJob yh{A->nXH, A->nYH, A->specH, A->fH, A->gH}, yv{A->nXV, A->nYV, A->specV, A->fV, A->gV};
+    const int hb = (A->nXH + yconv_kpb(A->nYH) - 1) / yconv_kpb(A->nYH);
+    const int vb = (A->nXV + yconv_kpb(A->nYV) - 1) / yconv_kpb(A->nYV);
+    const size_t lds = std::max(yconv_lds(A->nYH), yconv_lds(A->nYV));
+    hipLaunchKernelGGL(k_yconv, dim3(hb + vb), dim3(256), lds, st, yh, yv, hb);
     SESM_LAUNCH_CHECK();
   }
+  SESM_KT_END(SESM_KT_YCONV, st, B.yconvH + B.yconvV);
+  SESM_KT_BEGIN(SESM_KT_FFT, st);
+  if ((rc = fft_launch(ctx, st, sesm_fft_job(A->planH, A->nYH, A->gH, A->phH, nullptr, A->utwH, 1.0 / A->nXH),
+                       sesm_fft_job(A->planV, A->nYV, A->gV, A->phV, nullptr, A->utwV, 1.0 / A->nXV), +1)))
+    return rc;
+  SESM_KT_END(SESM_KT_FFT, st, B.fftH1 + B.fftV1);
+  // join the near-field stream before the cells add the far field into y
+  SESM_HIP(hipStreamWaitEvent(st, A->ev_near, 0));
+  FarArgs F{P.N, A->n_x, A->n_y, A->n_s, A->n_e, A->n_side, A->n_eq, A->n_cells, A->n_bdry, A->n_bH, A->n_plw,
+            A->nXH, A->nXV, A->ring, A->max_q, A->L, A->x0, A->y0, P.k, P.alpha * P.d};
+  SESM_KT_BEGIN(SESM_KT_CELLS, st);
+  hipLaunchKernelGGL(k_cells_far, dim3(A->n_occ), dim3(256), cells_far_lds(A), st, F, K, A->occ_cell, A->occ_off,
+                     A->perm, A->occ_flag, A->phH, A->phV, A->dens, A->W, A->pplw, A->dirs, ctx->x, ctx->f,
+                     A->mode_part, y, keep_far ? A->yfar : nullptr);
+  SESM_LAUNCH_CHECK();
+  SESM_KT_END(SESM_KT_CELLS, st, B.cells);
   return SESM_OK;
 }
 

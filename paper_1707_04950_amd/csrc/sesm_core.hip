@@ -136,6 +136,10 @@ void sesm_release_surface(sesm_ctx* ctx) {
   ctx->hcol = ctx->hpart = ctx->ybuf = ctx->wtmp = ctx->upart = nullptr;
   if (ctx->hhost) (void)hipHostFree(ctx->hhost);
   ctx->hhost = nullptr;
+  for (hipEvent_t& ev : ctx->hev) {
+    if (ev) (void)hipEventDestroy(ev);
+    ev = nullptr;
+  }
   ctx->ready = false;
 }
 
@@ -193,6 +197,7 @@ int sesm_destroy(sesm_ctx* ctx) {
   if (!ctx) return SESM_OK;
   (void)hipSetDevice(ctx->device);
   sesm_release_surface(ctx);
+  sesm_kt_free(ctx);
   delete ctx;
   return SESM_OK;
 }
@@ -460,3 +465,87 @@ int sesm_diag_hankel(sesm_ctx* ctx, const double* x, int32_t n, sesm_c64* h0, se
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// per-kernel timing
+
+static const char* const kKtNames[SESM_KT_COUNT] = {
+    "k_near_apply", "k_p2e_apply",   "k_merge",    "k_fft_rows", "k_yconv",
+    "k_cells_far",  "k_dots",        "k_update_part", "k_gemv_rows"};
+
+static int kt_fold(sesm_ctx* ctx, KTimer& T) {
+  if (T.used == 0) return SESM_OK;
+  SESM_HIP(hipEventSynchronize(T.ev[2 * T.used - 1]));
+  for (int u = 0; u < T.used; ++u) {
+    SESM_HIP(hipEventSynchronize(T.ev[2 * u + 1]));
+    float ms = 0.f;
+    SESM_HIP(hipEventElapsedTime(&ms, T.ev[2 * u], T.ev[2 * u + 1]));
+    T.ms += ms;
+  }
+  T.used = 0;
+  return SESM_OK;
+}
+
+int sesm_kt_begin(sesm_ctx* ctx, int id, hipStream_t st) {
+  KTimer& T = ctx->kt[id];
+  if (T.ev.empty()) {
+    T.ev.assign(2 * SESM_KT_POOL, nullptr);
+    for (hipEvent_t& e : T.ev) SESM_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+  }
+  if (T.used == SESM_KT_POOL) {
+    const int rc = kt_fold(ctx, T);
+    if (rc) return rc;
+  }
+  SESM_HIP(hipEventRecord(T.ev[2 * T.used], st));
+  return SESM_OK;
+}
+
+int sesm_kt_end(sesm_ctx* ctx, int id, hipStream_t st, double nbytes) {
+  KTimer& T = ctx->kt[id];
+  SESM_HIP(hipEventRecord(T.ev[2 * T.used + 1], st));
+  ++T.used;
+  ++T.launches;
+  T.bytes += nbytes;
+  return SESM_OK;
+}
+
+void sesm_kt_free(sesm_ctx* ctx) {
+  for (KTimer& T : ctx->kt) {
+    for (hipEvent_t e : T.ev)
+      if (e) (void)hipEventDestroy(e);
+    T = KTimer{};
+  }
+  ctx->kt_mask = 0;
+}
+
+int sesm_timing_enable(sesm_ctx* ctx, uint32_t mask) {
+  if (!ctx) return SESM_EINVAL;
+  if (mask >> SESM_KT_COUNT) return ctx->fail(SESM_EINVAL, "timing mask selects unknown kernel classes");
+  SESM_HIP(hipSetDevice(ctx->device));
+  for (KTimer& T : ctx->kt) {
+    const int rc = kt_fold(ctx, T);  // let recorded events finish before they are reused
+    if (rc) return rc;
+    T.launches = 0;
+    T.ms = T.bytes = 0.0;
+  }
+  ctx->kt_mask = mask;
+  return SESM_OK;
+}
+
+int sesm_timing_read(sesm_ctx* ctx, sesm_kernel_stat* stats, int32_t n_stats) {
+  if (!ctx) return SESM_EINVAL;
+  if (!stats || n_stats < SESM_KT_COUNT) return ctx->fail(SESM_EINVAL, "need SESM_KT_COUNT records");
+  SESM_HIP(hipSetDevice(ctx->device));
+  for (int i = 0; i < SESM_KT_COUNT; ++i) {
+    KTimer& T = ctx->kt[i];
+    const int rc = kt_fold(ctx, T);
+    if (rc) return rc;
+    sesm_kernel_stat& o = stats[i];
+    std::memset(&o, 0, sizeof(o));
+    std::strncpy(o.name, kKtNames[i], sizeof(o.name) - 1);
+    o.launches = T.launches;
+    o.total_ms = T.ms;
+    o.bytes = T.bytes;
+  }
+  return SESM_OK;
+}

@@ -74,7 +74,10 @@ int sesm_dense_setup(sesm_ctx* ctx) {
 }
 
 int sesm_dense_matvec(sesm_ctx* ctx, const cplx* mu, cplx* y) {
+  const double N = ctx->P.N;
+  SESM_KT_BEGIN(SESM_KT_GEMV, ctx->stream);
   hipLaunchKernelGGL(k_gemv_rows, dim3(ctx->P.N), dim3(256), 0, ctx->stream, ctx->P.N, ctx->Mdense, mu, y);
   SESM_LAUNCH_CHECK();
+  SESM_KT_END(SESM_KT_GEMV, ctx->stream, sizeof(cplx) * (N * N + 2.0 * N));  // operator, mu, y
   return SESM_OK;
 }

@@ -1,6 +1,7 @@
 // Own FP64 complex FFT for the periodic (x) direction of the equivalent-source
 // grids: self-sorting mixed-radix (2, 3, 4, 5) Stockham transform, one row per
-// 256-thread workgroup, both ping-pong buffers in LDS, twiddles from a table
+// workgroup (several short rows share one; two grids may share a launch), both
+// ping-pong buffers in LDS, twiddles from a table
 // w[t] = exp(-2 pi i t / n) built on the host.  Rows are read and written with
 // unit stride (coalesced).  Optional fused pre/post multiplication by
 // exp(-/+ i alpha x) (the quasi-periodic twist) and 1/n scaling.
@@ -74,46 +75,77 @@ __device__ inline void sesm_dft_small(int R, int sign, cplx* x) {
   }
 }
 
-// `rpb` rows of length n per workgroup: row r read from in + r*ld_in and
-// written to out + r*ld_out (in-place allowed).  out = scale * (DFT with
-// exp(sign 2 pi i jk/n) of (pre . in)) . post; pre/post optional (length n).
-__global__ __launch_bounds__(1024) void k_fft_rows(FftArgs A, int nrows, int rpb, const cplx* in, int64_t ld_in,
-                                                   cplx* out, int64_t ld_out, const cplx* __restrict__ tw, int sign,
-                                                   const cplx* __restrict__ pre, const cplx* __restrict__ post,
-                                                   double scale) {
+// One Stockham pass of radix R (a compile-time constant, so the butterfly
+// operands stay in registers): p = product of the radices already applied,
+// step = n / (p R) is the twiddle stride, exp(-2 pi i q k / (p R)) = tw[q k step].
+template <int R>
+__device__ inline void sesm_fft_pass(const cplx* a, cplx* b, int n, int nr, int p, int step,
+                                     const cplx* __restrict__ tw, int sign) {
+  const int T = n / R;
+  for (int e = threadIdx.x; e < nr * T; e += blockDim.x) {
+    const int r = e / T, i = e - r * T;
+    const int k = i % p;
+    const cplx* ar = a + r * n;
+    cplx x[R];
+    x[0] = ar[i];
+#pragma unroll
+    for (int q = 1; q < R; ++q) {
+      cplx w = tw[q * k * step];
+      if (sign > 0) w = conj(w);
+      x[q] = ar[i + q * T] * w;
+    }
+    sesm_dft_small(R, sign, x);
+    cplx* br = b + r * n;
+    const int j = (i - k) * R + k;  // (i / p) p R + k
+#pragma unroll
+    for (int u = 0; u < R; ++u) br[j + u * p] = x[u];
+  }
+}
+
+// One batch of rows of one length: rpb rows of length n per workgroup, row r
+// read from in + r n and written to out + r n (in-place allowed).
+// out = scale * (DFT with exp(sign 2 pi i jk/n) of (pre . in)) . post;
+// pre/post optional (length n).
+struct FftJob {
+  FftArgs A;
+  int nrows, rpb, nblocks;
+  const cplx* in;
+  cplx* out;
+  const cplx* tw;
+  const cplx* pre;
+  const cplx* post;
+  double scale;
+};
+
+// Workgroups [0, j0.nblocks) run job j0, the next j1.nblocks run job j1 (two
+// grids of different lengths in one launch).
+__global__ __launch_bounds__(1024) void k_fft_rows(FftJob j0, FftJob j1, int sign) {
   __shared__ cplx buf[2][SESM_FFT_MAXN];
-  const int n = A.n;
-  const int r0 = blockIdx.x * rpb;
-  const int nr = min(rpb, nrows - r0);
+  const bool first = (int)blockIdx.x < j0.nblocks;
+  const FftJob& J = first ? j0 : j1;
+  const int blk = first ? blockIdx.x : blockIdx.x - j0.nblocks;
+  const int n = J.A.n;
+  const int r0 = blk * J.rpb;
+  const int nr = min(J.rpb, J.nrows - r0);
+  const cplx* __restrict__ tw = J.tw;
   cplx* a = buf[0];
   cplx* b = buf[1];
   for (int e = threadIdx.x; e < nr * n; e += blockDim.x) {
-    const int r = e / n, i = e % n;
-    cplx v = in[(int64_t)(r0 + r) * ld_in + i];
-    if (pre) v = v * pre[i];
+    const int i = e % n;
+    cplx v = J.in[(int64_t)r0 * n + e];
+    if (J.pre) v = v * J.pre[i];
     a[e] = v;
   }
   __syncthreads();
   int p = 1;
-  for (int s = 0; s < A.nrad; ++s) {
-    const int R = A.rad[s];
-    const int T = n / R;
-    const int step = n / (p * R);  // twiddle stride: exp(-2 pi i q k / (p R)) = tw[q k step], q k step < n
-    for (int e = threadIdx.x; e < nr * T; e += blockDim.x) {
-      const int r = e / T, i = e % T;
-      const int k = i % p;
-      const cplx* ar = a + r * n;
-      cplx x[5];
-      x[0] = ar[i];
-      for (int q = 1; q < R; ++q) {
-        cplx w = tw[q * k * step];
-        if (sign > 0) w = conj(w);
-        x[q] = ar[i + q * T] * w;
-      }
-      sesm_dft_small(R, sign, x);
-      cplx* br = b + r * n;
-      const int j = (i / p) * p * R + k;
-      for (int u = 0; u < R; ++u) br[j + u * p] = x[u];
+  for (int s = 0; s < J.A.nrad; ++s) {
+    const int R = J.A.rad[s];
+    const int step = n / (p * R);
+    switch (R) {
+      case 4: sesm_fft_pass<4>(a, b, n, nr, p, step, tw, sign); break;
+      case 2: sesm_fft_pass<2>(a, b, n, nr, p, step, tw, sign); break;
+      case 3: sesm_fft_pass<3>(a, b, n, nr, p, step, tw, sign); break;
+      default: sesm_fft_pass<5>(a, b, n, nr, p, step, tw, sign); break;
     }
     __syncthreads();
     cplx* t = a;
@@ -122,10 +154,10 @@ __global__ __launch_bounds__(1024) void k_fft_rows(FftArgs A, int nrows, int rpb
     p *= R;
   }
   for (int e = threadIdx.x; e < nr * n; e += blockDim.x) {
-    const int r = e / n, i = e % n;
-    cplx v = scale * a[e];
-    if (post) v = v * post[i];
-    out[(int64_t)(r0 + r) * ld_out + i] = v;
+    const int i = e % n;
+    cplx v = J.scale * a[e];
+    if (J.post) v = v * J.post[i];
+    J.out[(int64_t)r0 * n + e] = v;
   }
 }
 
@@ -135,4 +167,22 @@ inline FftArgs sesm_fft_args(const FftPlan& p) {
   A.nrad = p.nrad;
   for (int t = 0; t < SESM_FFT_MAXRAD; ++t) A.rad[t] = t < p.nrad ? p.rad[t] : 1;
   return A;
+}
+
+// A job for `rows` rows of plan p (empty job when rows == 0).
+inline FftJob sesm_fft_job(const FftPlan& p, int rows, const cplx* in, cplx* out, const cplx* pre, const cplx* post,
+                           double scale) {
+  FftJob J{};
+  J.A = sesm_fft_args(p);
+  J.nrows = rows;
+  J.rpb = rows > 0 ? (p.n < SESM_FFT_MAXN ? SESM_FFT_MAXN / p.n : 1) : 1;
+  if (J.rpb > rows && rows > 0) J.rpb = rows;
+  J.nblocks = rows > 0 ? (rows + J.rpb - 1) / J.rpb : 0;
+  J.in = in;
+  J.out = out;
+  J.tw = p.tw;
+  J.pre = pre;
+  J.post = post;
+  J.scale = scale;
+  return J;
 }

@@ -3,7 +3,10 @@
 // Device-resident Krylov basis V[(m+1) x N]; classical Gram-Schmidt applied
 // twice (CGS2) with tall-skinny dot-product kernels (each kernel reads every
 // basis vector once, coalesced); Givens rotations of the small Hessenberg
-// matrix on the host, which reads one column per iteration.
+// matrix on the host, which reads one column per iteration.  The host runs one
+// Arnoldi step behind the device: step it+1 is enqueued before the column of
+// step it is read back, so the device never waits for the host's rotations
+// (the extra step after convergence is discarded).
 #include <cmath>
 #include <complex>
 #include <vector>
@@ -13,74 +16,121 @@
 namespace {
 
 constexpr int VT = 8;         // basis vectors per dot-product block
-constexpr int NCHUNK = 240;   // N-chunks per dot product (about one per CU)
+constexpr int NCHUNK = 240;   // N-chunks of the single-vector norm reduction
+constexpr int DCHUNK = 32;    // N-chunks of the multi-vector dot products (about 1 KB of w per block)
 
-// part[v * NCHUNK + c] = sum_{i in chunk c} conj(V_v[i]) w[i], v in [0, nv)
+// part[v * DCHUNK + c] = sum_{i in chunk c} conj(V_v[i]) w[i], v in [0, nv).
+// Loads are unconditional (vector index clamped, surplus terms masked) so that
+// all VT basis loads of an iteration are in flight together.
 __global__ __launch_bounds__(256) void k_dots(int N, int nv, const cplx* __restrict__ V, int64_t ldv,
                                               const cplx* __restrict__ w, cplx* __restrict__ part) {
   __shared__ cplx sh[VT][4];
   const int c = blockIdx.x, v0 = blockIdx.y * VT;
-  const int per = (N + NCHUNK - 1) / NCHUNK;
+  const int per = (N + DCHUNK - 1) / DCHUNK;
   const int lo = c * per, hi = min(N, lo + per);
+  const cplx* row[VT];
+  double msk[VT];
+#pragma unroll
+  for (int t = 0; t < VT; ++t) {
+    row[t] = V + (int64_t)min(v0 + t, nv - 1) * ldv;
+    msk[t] = v0 + t < nv ? 1.0 : 0.0;
+  }
   cplx acc[VT];
 #pragma unroll
   for (int t = 0; t < VT; ++t) acc[t] = cplx{0.0, 0.0};
-  for (int i = lo + threadIdx.x; i < hi; i += 256) {
-    const cplx wi = w[i];
+  // two elements per thread and step: all 2 VT basis loads are issued before any use
+  for (int i = lo + threadIdx.x; i < hi; i += 512) {
+    const bool two = i + 256 < hi;
+    const int i2 = two ? i + 256 : i;
+    cplx a[VT], b[VT];
 #pragma unroll
-    for (int t = 0; t < VT; ++t)
-      if (v0 + t < nv) acc[t] += cmul_conj(V[(int64_t)(v0 + t) * ldv + i], wi);
+    for (int t = 0; t < VT; ++t) a[t] = row[t][i];
+#pragma unroll
+    for (int t = 0; t < VT; ++t) b[t] = row[t][i2];
+    const cplx wa = w[i];
+    const cplx wb = two ? w[i2] : cplx{0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < VT; ++t) acc[t] += cmul_conj(a[t], wa) + cmul_conj(b[t], wb);
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int t = 0; t < VT; ++t) {
     const cplx s = wave_sum(acc[t]);
-    if (lane == 0) sh[t][wv] = s;
+    if (lane == 0) sh[t][wv] = msk[t] * s;
   }
   __syncthreads();
   if (threadIdx.x < VT && v0 + (int)threadIdx.x < nv) {
     const int t = threadIdx.x;
-    part[(int64_t)(v0 + t) * NCHUNK + c] = sh[t][0] + sh[t][1] + sh[t][2] + sh[t][3];
+    part[(int64_t)(v0 + t) * DCHUNK + c] = sh[t][0] + sh[t][1] + sh[t][2] + sh[t][3];
   }
 }
 
-// h[v] (=|+=) sum_c part[v * NCHUNK + c]; one wave per v
-__global__ void k_dots_final(int nv, const cplx* __restrict__ part, cplx* __restrict__ h, int accumulate) {
-  const int v = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (v >= nv) return;
-  cplx s = cplx{0.0, 0.0};
-  for (int c = lane; c < NCHUNK; c += 64) s += part[(int64_t)v * NCHUNK + c];
-  s = wave_sum(s);
-  if (lane == 0) h[v] = accumulate ? h[v] + s : s;
-}
-
-// part[c][i] = sum_{v in chunk c} V_v[i] h[v]  (chunks of UCH vectors: more
-// workgroups than one pass over all vectors, and independent loads in flight)
+// upart[c][i] = sum_{v in chunk c} V_v[i] coef[v], chunks of UCH vectors (more
+// workgroups than one pass over all vectors, and independent loads in flight).
+// Each workgroup first reduces the dot-product partials of its chunk,
+// coef[v] = sum_c' dpart[v * DCHUNK + c'] (one wave per v); the workgroups with
+// blockIdx.x == 0 also store h[v] = coef[v] (first pass) or h[v] + coef[v].
 constexpr int UCH = 32;
 __global__ __launch_bounds__(256) void k_update_part(int N, int nv, const cplx* __restrict__ V, int64_t ldv,
-                                                     const cplx* __restrict__ h, cplx* __restrict__ part) {
+                                                     const cplx* __restrict__ dpart, cplx* __restrict__ h,
+                                                     int accumulate, cplx* __restrict__ upart) {
   __shared__ cplx hs[UCH];
   const int c = blockIdx.y;
   const int v0 = c * UCH, v1 = min(nv, v0 + UCH);
-  if (threadIdx.x < v1 - v0) hs[threadIdx.x] = h[v0 + threadIdx.x];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int v = v0 + wv; v < v1; v += 4) {
+    cplx sm = lane < DCHUNK ? dpart[(int64_t)v * DCHUNK + lane] : cplx{0.0, 0.0};
+    sm = wave_sum(sm);
+    if (lane == 0) {
+      hs[v - v0] = sm;
+      if (blockIdx.x == 0) h[v] = accumulate ? h[v] + sm : sm;
+    }
+  }
   __syncthreads();
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= N) return;
-  cplx s = cplx{0.0, 0.0};
+  cplx sm = cplx{0.0, 0.0};
 #pragma unroll 8
-  for (int v = v0; v < v1; ++v) s += V[(int64_t)v * ldv + i] * hs[v - v0];
-  part[(int64_t)c * N + i] = s;
+  for (int v = v0; v < v1; ++v) sm += V[(int64_t)v * ldv + i] * hs[v - v0];
+  upart[(int64_t)c * N + i] = sm;
 }
 
-// w[i] -= sum_c part[c][i]
+// w[i] -= sum_c part[c][i]; with npart, also npart[block] = sum over the block of |w[i]|^2
 __global__ __launch_bounds__(256) void k_update_final(int N, int nch, const cplx* __restrict__ part,
-                                                      cplx* __restrict__ w) {
+                                                      cplx* __restrict__ w, double* __restrict__ npart) {
+  __shared__ cplx sh[4];
   const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= N) return;
-  cplx s = w[i];
-  for (int c = 0; c < nch; ++c) s -= part[(int64_t)c * N + i];
-  w[i] = s;
+  double q = 0.0;
+  if (i < N) {
+    cplx s = w[i];
+    for (int c = 0; c < nch; ++c) s -= part[(int64_t)c * N + i];
+    w[i] = s;
+    q = abs2(s);
+  }
+  if (npart) {
+    const cplx r = block_sum<256>(cplx{q, 0.0}, sh);
+    if (threadIdx.x == 0) npart[blockIdx.x] = r.re;
+  }
+}
+
+// n = sqrt(sum of the nparts partial squared norms); w /= n (zero norm leaves w);
+// block 0 stores cplx(n, 0) at *hout
+__global__ __launch_bounds__(256) void k_scale_norm(int N, int nparts, const double* __restrict__ npart, cplx* w,
+                                                    cplx* __restrict__ hout) {
+  __shared__ cplx sh[4];
+  __shared__ double nrm;
+  double s = 0.0;
+  for (int c = threadIdx.x; c < nparts; c += 256) s += npart[c];
+  const cplx r = block_sum<256>(cplx{s, 0.0}, sh);
+  if (threadIdx.x == 0) {
+    nrm = sqrt(r.re);
+    if (blockIdx.x == 0) *hout = cplx{nrm, 0.0};
+  }
+  __syncthreads();
+  const double n = nrm;
+  const double inv = n > 0 ? 1.0 / n : 0.0;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < N && n > 0) w[i] = inv * w[i];
 }
 
 // x[i] += sum_{v < nv} V_v[i] y[v]
@@ -152,13 +202,16 @@ int ensure_workspace(sesm_ctx* ctx, int m) {
   if (rc) return rc;
   ctx->V_cols = m + 1;
   if (!ctx->hcol) {
-    if ((rc = sesm_alloc(ctx, (void**)&ctx->hcol, sizeof(cplx) * 4200))) return rc;
-    if ((rc = sesm_alloc(ctx, (void**)&ctx->hpart, sizeof(cplx) * (size_t)4200 * NCHUNK))) return rc;
-    if ((rc = sesm_alloc(ctx, (void**)&ctx->ybuf, sizeof(cplx) * 4200))) return rc;
+    if ((rc = sesm_alloc(ctx, (void**)&ctx->hcol, sizeof(cplx) * SESM_HRING * SESM_HSTRIDE))) return rc;
+    if ((rc = sesm_alloc(ctx, (void**)&ctx->hpart, sizeof(cplx) * (size_t)SESM_HSTRIDE * DCHUNK))) return rc;
+    if ((rc = sesm_alloc(ctx, (void**)&ctx->ybuf, sizeof(cplx) * SESM_HSTRIDE))) return rc;
     if ((rc = sesm_alloc(ctx, (void**)&ctx->wtmp, sizeof(cplx) * (size_t)N))) return rc;
-    if ((rc = sesm_alloc(ctx, (void**)&ctx->upart, sizeof(cplx) * (size_t)N * ((4200 + UCH - 1) / UCH)))) return rc;
-    if (hipHostMalloc((void**)&ctx->hhost, sizeof(cplx) * 4200, 0) != hipSuccess)
+    if ((rc = sesm_alloc(ctx, (void**)&ctx->upart, sizeof(cplx) * (size_t)N * ((SESM_HSTRIDE + UCH - 1) / UCH))))
+      return rc;
+    if (hipHostMalloc((void**)&ctx->hhost, sizeof(cplx) * (SESM_HRING + 1) * SESM_HSTRIDE, 0) != hipSuccess)
       return ctx->fail(SESM_ENOMEM, "hipHostMalloc failed");
+    for (hipEvent_t& ev : ctx->hev)
+      if (!ev) SESM_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
   }
   return SESM_OK;
 }
@@ -199,6 +252,36 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
     *out = ctx->hhost[0].re;
     return SESM_OK;
   };
+  // Arnoldi step `it`: w = A v_it, CGS2 against v_0..v_it, normalise; the
+  // column (h_0..h_it, |w|) goes to ring slot it % SESM_HRING, then to the host.
+  auto arnoldi = [&](int it) -> int {
+    cplx* w = V + (int64_t)(it + 1) * ldv;
+    int r = sesm_apply(ctx, V + (int64_t)it * ldv, w);
+    if (r) return r;
+    const int nv = it + 1, slot = it % SESM_HRING;
+    cplx* hc = ctx->hcol + (size_t)slot * SESM_HSTRIDE;
+    const dim3 gd(DCHUNK, (nv + VT - 1) / VT);
+    const int nch = (nv + UCH - 1) / UCH;
+    const double c16 = sizeof(cplx);
+    for (int pass = 0; pass < 2; ++pass) {
+      SESM_KT_BEGIN(SESM_KT_DOTS, st);
+      hipLaunchKernelGGL(k_dots, gd, dim3(256), 0, st, N, nv, V, ldv, w, ctx->hpart);
+      SESM_KT_END(SESM_KT_DOTS, st, c16 * ((double)nv * N + N + (double)nv * DCHUNK));  // basis, w, partials
+      SESM_KT_BEGIN(SESM_KT_UPDATE, st);
+      hipLaunchKernelGGL(k_update_part, dim3(nb, nch), dim3(256), 0, st, N, nv, V, ldv, ctx->hpart, hc, pass,
+                         ctx->upart);
+      // basis, update partials, dot partials
+      SESM_KT_END(SESM_KT_UPDATE, st, c16 * ((double)nv * N + (double)nch * N + (double)nv * DCHUNK));
+      hipLaunchKernelGGL(k_update_final, dim3(nb), dim3(256), 0, st, N, nch, ctx->upart, w,
+                         pass == 1 ? npart : nullptr);
+    }
+    hipLaunchKernelGGL(k_scale_norm, dim3(nb), dim3(256), 0, st, N, nb, npart, w, hc + nv);
+    SESM_LAUNCH_CHECK();
+    SESM_HIP(hipMemcpyAsync(ctx->hhost + (size_t)slot * SESM_HSTRIDE, hc, sizeof(cplx) * (nv + 1),
+                            hipMemcpyDeviceToHost, st));
+    SESM_HIP(hipEventRecord(ctx->hev[slot], st));
+    return SESM_OK;
+  };
   double bnorm = 0.0;
   if ((rc = norm_to_host(b, &bnorm))) return rc;
   SESM_HIP(hipMemsetAsync(x, 0, sizeof(cplx) * (size_t)N, st));
@@ -229,28 +312,16 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
     hipLaunchKernelGGL(k_scale, dim3(nb), dim3(256), 0, st, N, V, ctx->hcol, V);
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta0;
+    const int steps = std::min(m, max_iter - total);  // Arnoldi steps available in this cycle
+    if ((rc = arnoldi(0))) return rc;
     int it = 0;
-    for (; it < m && total < max_iter; ++it, ++total) {
-      cplx* w = V + (int64_t)(it + 1) * ldv;
-      if ((rc = sesm_apply(ctx, V + (int64_t)it * ldv, w))) return rc;
-      const int nv = it + 1;
-      const dim3 gd(NCHUNK, (nv + VT - 1) / VT);
-      for (int pass = 0; pass < 2; ++pass) {
-        hipLaunchKernelGGL(k_dots, gd, dim3(256), 0, st, N, nv, V, ldv, w, ctx->hpart);
-        hipLaunchKernelGGL(k_dots_final, dim3((nv + 3) / 4), dim3(256), 0, st, nv, ctx->hpart, ctx->hcol, pass);
-        hipLaunchKernelGGL(k_dots_final, dim3((nv + 3) / 4), dim3(256), 0, st, nv, ctx->hpart, ctx->ybuf, 0);
-        const int nch = (nv + UCH - 1) / UCH;
-        hipLaunchKernelGGL(k_update_part, dim3(nb, nch), dim3(256), 0, st, N, nv, V, ldv, ctx->ybuf, ctx->upart);
-        hipLaunchKernelGGL(k_update_final, dim3(nb), dim3(256), 0, st, N, nch, ctx->upart, w);
-      }
-      hipLaunchKernelGGL(k_norm2_part, dim3(NCHUNK), dim3(256), 0, st, N, w, npart);
-      hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(64), 0, st, npart, ctx->hcol + nv);
-      hipLaunchKernelGGL(k_scale, dim3(nb), dim3(256), 0, st, N, w, ctx->hcol + nv, w);
-      SESM_LAUNCH_CHECK();
-      SESM_HIP(hipMemcpyAsync(ctx->hhost, ctx->hcol, sizeof(cplx) * (nv + 1), hipMemcpyDeviceToHost, st));
-      SESM_HIP(hipStreamSynchronize(st));
+    for (; it < steps; ++it, ++total) {
+      if (it + 1 < steps && (rc = arnoldi(it + 1))) return rc;  // keep the device one step ahead
+      const int nv = it + 1, slot = it % SESM_HRING;
+      SESM_HIP(hipEventSynchronize(ctx->hev[slot]));
+      const cplx* hh = ctx->hhost + (size_t)slot * SESM_HSTRIDE;
       std::complex<double>* col = &H[(size_t)it * (m + 1)];
-      for (int t = 0; t <= nv; ++t) col[t] = std::complex<double>(ctx->hhost[t].re, ctx->hhost[t].im);
+      for (int t = 0; t <= nv; ++t) col[t] = std::complex<double>(hh[t].re, hh[t].im);
       for (int t = 0; t < it; ++t) {  // previous rotations [[conj c, conj s], [-s, c]]
         const std::complex<double> u = col[t], v = col[t + 1];
         col[t] = std::conj(cs[t]) * u + std::conj(sn[t]) * v;
@@ -271,7 +342,8 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
         break;
       }
     }
-    // y = R^{-1} g, x += V y
+    // y = R^{-1} g, x += V y  (a step enqueued ahead of a converged one only wrote
+    // v_{it+1} and a ring slot; both are ignored)
     const int nv = it;
     std::vector<std::complex<double>> y(nv);
     for (int t = nv - 1; t >= 0; --t) {
@@ -279,8 +351,9 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
       for (int u = t + 1; u < nv; ++u) s -= H[(size_t)u * (m + 1) + t] * y[u];
       y[t] = s / H[(size_t)t * (m + 1) + t];
     }
-    for (int t = 0; t < nv; ++t) ctx->hhost[t] = cplx{y[t].real(), y[t].imag()};
-    SESM_HIP(hipMemcpyAsync(ctx->ybuf, ctx->hhost, sizeof(cplx) * nv, hipMemcpyHostToDevice, st));
+    cplx* yh = ctx->hhost + (size_t)SESM_HRING * SESM_HSTRIDE;  // idle: each cycle ends synchronised
+    for (int t = 0; t < nv; ++t) yh[t] = cplx{y[t].real(), y[t].imag()};
+    SESM_HIP(hipMemcpyAsync(ctx->ybuf, yh, sizeof(cplx) * nv, hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), sizeof(cplx) * nv, st, N, nv, V, ldv, ctx->ybuf, x, 1);
     SESM_LAUNCH_CHECK();
     SESM_HIP(hipStreamSynchronize(st));

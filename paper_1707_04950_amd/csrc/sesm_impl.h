@@ -11,6 +11,8 @@
 
 #define SESM_MAX_J 16
 #define SESM_MAX_UETA 64
+#define SESM_HRING 4       // Hessenberg column slots in flight
+#define SESM_HSTRIDE 4208  // entries per slot (Krylov dimension <= 4000)
 
 // Scalars of one discretised problem (Algorithm 2 inputs and derived sizes).
 struct Problem {
@@ -34,6 +36,16 @@ struct KParams {
 
 struct AccelOp;  // shifted-equivalent-source accelerator (sesm_accel.hip)
 
+// Event pairs of one timed kernel class (folded into ms when the pool is full
+// and when read).
+struct KTimer {
+  std::vector<hipEvent_t> ev;  // 2 per launch slot
+  int used = 0;                // recorded pairs not yet folded
+  int64_t launches = 0;
+  double ms = 0.0, bytes = 0.0;
+};
+#define SESM_KT_POOL 2048  // launch slots per class between folds
+
 struct sesm_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -49,14 +61,18 @@ struct sesm_ctx {
   // GMRES workspace
   cplx* V = nullptr;
   int64_t V_cols = 0;
-  cplx* hcol = nullptr;      // device Hessenberg column (+ norm)
+  cplx* hcol = nullptr;      // device Hessenberg columns (+ norm), a ring of SESM_HRING slots
   cplx* hpart = nullptr;     // partial dot products
-  cplx* hhost = nullptr;     // pinned host copy of the column
+  cplx* hhost = nullptr;     // pinned host copies of the ring slots (+ one slot for uploads)
+  hipEvent_t hev[4] = {};    // per ring slot: its column has reached hhost
   cplx* ybuf = nullptr;      // device copy of the small LS solution
   cplx* wtmp = nullptr;      // scratch vector of length N
   cplx* upart = nullptr;     // partial sums of the Gram-Schmidt update
   std::vector<void*> owned;  // every device allocation made for the surface
   int64_t bytes = 0;
+  // per-kernel timing (sesm_timing_enable)
+  uint32_t kt_mask = 0;
+  KTimer kt[SESM_KT_COUNT];
 
   int fail(int code, const std::string& msg) {
     err = msg;
@@ -75,6 +91,25 @@ struct sesm_ctx {
   do {                                                                                          \
     hipError_t e_ = hipGetLastError();                                                          \
     if (e_ != hipSuccess) return ctx->fail(SESM_EHIP, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+// timing brackets (no-ops unless the class is selected)
+int sesm_kt_begin(sesm_ctx* ctx, int id, hipStream_t st);
+int sesm_kt_end(sesm_ctx* ctx, int id, hipStream_t st, double bytes);
+void sesm_kt_free(sesm_ctx* ctx);
+#define SESM_KT_BEGIN(id, st)                                   \
+  do {                                                          \
+    if ((ctx->kt_mask >> (id)) & 1u) {                          \
+      const int r_ = sesm_kt_begin(ctx, (id), (st));            \
+      if (r_) return r_;                                        \
+    }                                                           \
+  } while (0)
+#define SESM_KT_END(id, st, nbytes)                             \
+  do {                                                          \
+    if ((ctx->kt_mask >> (id)) & 1u) {                          \
+      const int r_ = sesm_kt_end(ctx, (id), (st), (nbytes));    \
+      if (r_) return r_;                                        \
+    }                                                           \
   } while (0)
 
 // allocation owned by the surface (freed by release_surface)

@@ -113,6 +113,33 @@ def test_accel_matvec_vs_oracle_accel_and_dense(torch, solver, case):
         assert e_den <= 1e-8
 
 
+def test_kernel_timing_counts_and_bytes(torch, solver, case):
+    """Per-kernel event timing: launch counts per forward map and GMRES step, the
+    near-field byte count from the stored entries, and no counting once disabled."""
+    import paper_1707_04950_amd as lib
+    from gpu_util import to_dev
+    wl, disc, M, op = case
+    _gpu_accel(solver, wl, disc)
+    inf = solver.info()
+    mu = to_dev(torch, W.random_density(disc.N, 3))
+    solver.timing_enable((1 << lib.KT_COUNT) - 1)
+    solver.matvec(mu)
+    st = solver.timing_read()
+    assert [st[k]["launches"] for k in ("k_near_apply", "k_p2e_apply", "k_merge", "k_fft_rows", "k_yconv",
+                                        "k_cells_far")] == [1, 1, 1, 2, 1, 1]
+    assert st["k_near_apply"]["bytes"] == 16.0 * inf["near_entries"] + disc.N * 52.0
+    assert all(r["total_ms"] > 0 for r in st.values() if r["launches"])
+    solver.timing_enable(1 << lib.KT_DOTS)
+    _, info = solver.solve(tol=1e-6, max_iter=40, allow_noconv=True)
+    st = solver.timing_read()
+    # two Gram-Schmidt passes per Arnoldi step; at most one step runs ahead of the last one used
+    assert 2 * info["iters"] <= st["k_dots"]["launches"] <= 2 * (info["iters"] + 1)
+    assert st["k_near_apply"]["launches"] == 0
+    solver.timing_enable(0)
+    solver.matvec(mu)
+    assert solver.timing_read()["k_dots"]["launches"] == 0
+
+
 def test_accel_solve_efficiencies_vs_dense_oracle(torch, solver, case):
     from gpu_util import to_host
     wl, disc, M, op = case
