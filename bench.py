@@ -112,8 +112,8 @@ def main():
         dom = max(ranking, key=lambda n: ranking[n]["total_ms"])
         dom_id = list(ranking).index(dom)
     else:  # no warmup: the operator's main HBM stream
-        dom_id = lib.KT_GEMV if mode == lib.MODE_DENSE else lib.KT_NEAR
-        dom = "k_gemv_rows" if mode == lib.MODE_DENSE else "k_near_apply"
+        dom_id = lib.KT_GEMV if mode == lib.MODE_DENSE else lib.KT_LOCAL
+        dom = "k_gemv_rows" if mode == lib.MODE_DENSE else "k_local_apply"
 
     # Timed region: only the dominant kernel class is bracketed by events.
     s.timing_enable(1 << dom_id)

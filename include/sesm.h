@@ -182,8 +182,8 @@ SESM_API int sesm_diag_accel(sesm_ctx* ctx, const sesm_c64* mu, int32_t which, s
 /* Diagnostic (accelerated mode): y = the direct near-field part of the forward
  * map alone - the intersecting interactions of eq. (final_correction_0), the
  * singular part eq. (local_mat) and 1/2 I, for the sources of the cells in
- * the near columns - as one kernel launch on the context's stream (no
- * synchronisation).  mu, y: device arrays of N sesm_c64, not overlapping. */
+ * the near columns - as one kernel launch (the near-field work items of the
+ * forward map's first kernel) on the context's stream (no synchronisation).  mu, y: device arrays of N sesm_c64, not overlapping. */
 SESM_API int sesm_diag_near(sesm_ctx* ctx, const sesm_c64* mu, sesm_c64* y);
 
 /* Diagnostic: evaluate the library's FP64 Hankel functions H0^(1)(x),
@@ -194,17 +194,17 @@ SESM_API int sesm_diag_hankel(sesm_ctx* ctx, const double* x, int32_t n, sesm_c6
 
 /* Per-kernel timing.  Bit i of a mask selects kernel class i. */
 enum {
-  SESM_KT_NEAR = 0,   /* banded near-field GEMV (intersecting + singular + 1/2 I)   */
-  SESM_KT_P2E = 1,    /* cell equivalent-source densities from mu (EqSources) and the
-                         partial sums of the completion modes                        */
-  SESM_KT_MERGE = 2,  /* merge of the cell densities onto the periodic grids         */
-  SESM_KT_FFT = 3,    /* batched FFT along x of both grids (2 per forward map)      */
-  SESM_KT_YCONV = 4,  /* convolution along y per x-frequency, both grids (1 per map) */
-  SESM_KT_CELLS = 5,  /* local correction, plane-wave fit, surface values, modes     */
-  SESM_KT_DOTS = 6,   /* GMRES: dot products of w with the Krylov basis (per pass)   */
-  SESM_KT_UPDATE = 7, /* GMRES: partial sums of the basis update (per pass)          */
-  SESM_KT_GEMV = 8,   /* dense mode: GEMV with the stored operator                   */
-  SESM_KT_COUNT = 9
+  SESM_KT_LOCAL = 0,  /* near-field GEMV (intersecting + singular + 1/2 I), cell
+                         equivalent-source densities (EqSources) and the partial
+                         sums of the completion modes: one launch                   */
+  SESM_KT_MERGE = 1,  /* merge onto the periodic grids + local corrections          */
+  SESM_KT_FFT = 2,    /* batched FFT along x of both grids (2 per forward map)      */
+  SESM_KT_YCONV = 3,  /* convolution along y per x-frequency, both grids (1 per map) */
+  SESM_KT_CELLS = 4,  /* boundary values, plane-wave fit, surface values, modes     */
+  SESM_KT_DOTS = 5,   /* GMRES: dot products of the Krylov basis with u and A u      */
+  SESM_KT_UPDATE = 6, /* GMRES: partial sums of the two basis updates (+ H s)        */
+  SESM_KT_GEMV = 7,   /* dense mode: GEMV with the stored operator                   */
+  SESM_KT_COUNT = 8
 };
 
 typedef struct {

@@ -42,8 +42,8 @@ class SolveInfo(ctypes.Structure):
 
 
 # kernel classes of sesm_timing_enable (bit i of the mask selects class i)
-KT_NEAR, KT_P2E, KT_MERGE, KT_FFT, KT_YCONV, KT_CELLS, KT_DOTS, KT_UPDATE, KT_GEMV = range(9)
-KT_COUNT = 9
+KT_LOCAL, KT_MERGE, KT_FFT, KT_YCONV, KT_CELLS, KT_DOTS, KT_UPDATE, KT_GEMV = range(8)
+KT_COUNT = 8
 
 
 class KernelStat(ctypes.Structure):

@@ -17,21 +17,23 @@
 // (eq. S_jq_hat).  On a graph surface the near set of a column is one cyclic
 // band of nodes, stored as dense FP64 blocks (the HBM-bound part).
 //
-// Forward map (main stream unless noted):
-//   k_p2e_apply     (xi, zeta)^{q,lambda} = P_q^lambda mu_q   (EqSources, eq. eq_source_point)
-//                   + partial sums of the completion modes    (EvalModes, eq. M_eta)
-//   k_near_apply    y  = near band (intersecting part eq. final_correction_0,
-//                        singular part eq. local_mat, 1/2 I); side stream, forked
-//                        after k_p2e_apply so that the two HBM streams do not compete
+// Forward map, one stream, in order:
+//   k_local_apply   y  = near band (intersecting part eq. final_correction_0,
+//                        singular part eq. local_mat, 1/2 I);
+//                   (xi, zeta)^{q,lambda} = P_q^lambda mu_q   (EqSources, eq. eq_source_point);
+//                   partial sums of the completion modes      (EvalModes, eq. M_eta)
 //   k_merge         twisted merged grids                     (GlobalEqSMerge, eq. sum_eqsources)
+//                   + local corrections per cell pair         (LocalEqSMerge, LocalFFT, eq. small_convolution)
 //   k_fft_rows      FFT along x of both grids                (GlobalFFT, eq. large_convolution_per_grid)
 //   k_yconv         kernel-spectrum x sources, direct in y
 //   k_fft_rows      inverse FFT, untwist -> phi^all
-//   (join the side stream)
-//   k_cells_far     boundary values - local correction        (LocalEqSMerge, LocalFFT, LocalSubtract,
-//                   -> plane-wave weights -> surface values      Combine-lambda, PlaneWaveWeights,
-//                   + completion modes D_M                       NonIntersecting; eqs. psi_na_sum,
-//                                                                combine_psi_pna, planewave, plwave_QR)
+//   k_cells_far     boundary values - local corrections       (LocalSubtract, Combine-lambda,
+//                   -> plane-wave weights -> surface values      PlaneWaveWeights, NonIntersecting;
+//                   + completion modes D_M, added into y         eqs. psi_na_sum, combine_psi_pna,
+//                                                                planewave, plwave_QR)
+// The near field and the equivalent-source densities share one launch: both
+// stream stored operators from HBM and depend on mu only, while the grid
+// stages after them are latency-bound and would slow down beside a stream.
 #include <algorithm>
 #include <cmath>
 #include <complex>
@@ -54,9 +56,8 @@ struct AccelOp {
   // device data
   int *occ_cell = nullptr, *occ_off = nullptr, *perm = nullptr, *col_lo = nullptr, *col_w = nullptr;
   int64_t* near_off = nullptr;
-  int64_t* row_off = nullptr;  // per row (cell order): offset of its near-block row
-  int *row_lo = nullptr, *row_w = nullptr;
-  unsigned char* occ_flag = nullptr;
+  int n_chunks = 0, max_w = 0;  // near-field row chunks (cell, first row); widest band
+  int *chunk_q = nullptr, *chunk_t0 = nullptr;
   cplx *p2e = nullptr, *nearblk = nullptr, *dens = nullptr;
   cplx *gH = nullptr, *gV = nullptr, *fH = nullptr, *fV = nullptr, *phH = nullptr, *phV = nullptr;
   cplx *specH = nullptr, *specV = nullptr, *W = nullptr;
@@ -65,11 +66,14 @@ struct AccelOp {
   cplx *twxH = nullptr, *twxV = nullptr, *utwH = nullptr, *utwV = nullptr;  // e^{-i alpha x}, e^{+i alpha x}
   double* dirs = nullptr;
   cplx* mode_part = nullptr;
+  // local-correction pairs (occupied cell q, occupied cell of its near columns):
+  // pair_off[q]..pair_off[q+1]-1, correction-matrix offset, source cell, wrap phase
+  int n_pairs = 0;
+  int *pair_off = nullptr, *pair_o = nullptr, *pair_rc = nullptr;
+  cplx* pair_ph = nullptr;
+  cplx* corr = nullptr;  // [n_pairs][n_bdry]
   cplx* yfar = nullptr;  // diagnostic copy of the far-field contribution
   FftPlan planH, planV;
-  // side streams (default priority) and fork/join events of the forward map
-  hipStream_t s_near = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_near = nullptr;
 };
 
 namespace {
@@ -396,82 +400,119 @@ __global__ __launch_bounds__(256) void k_near_setup(KParams K, int n_x, const in
   }
 }
 
-// ------------------------------------------------------------------ forward-map kernels
-// Near field: one wavefront per target node (rows in cell order), lanes stream
-// the node's row of the near block (coalesced) against the cyclic band of mu.
-__global__ __launch_bounds__(256) void k_near_apply(int N, const int* __restrict__ perm,
-                                                    const int64_t* __restrict__ row_off,
-                                                    const int* __restrict__ row_lo, const int* __restrict__ row_w,
-                                                    const cplx* __restrict__ blk, const cplx* __restrict__ mu,
-                                                    cplx* __restrict__ y) {
-  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (t >= N) return;  // wave-uniform
-  const cplx* row = blk + row_off[t];
-  const int lo = row_lo[t], w = row_w[t];
-  cplx acc = cplx{0.0, 0.0};
-#pragma unroll 4
-  for (int u = lane; u < w; u += 64) {
-    int l = lo + u;
-    l += (l < 0) ? N : ((l >= N) ? -N : 0);
-    acc += row[u] * mu[l];
-  }
-  acc = wave_sum(acc);
-  if (lane == 0) y[perm[t]] = acc;
-}
+// One launch for the three HBM streams of the forward map that need only mu
+// (workgroups in this order):
+//  * [0, n_occ): EqSources, dens[lam][cell][oo] = sum_t P[(off + t) nout + o] mu[perm[off + t]],
+//    o = lam 2 n_eq + oo (eq. eq_source_point).  Lanes run over the outputs o
+//    (rows of P are contiguous in o); G = LOC_NT / OW thread groups split the
+//    cell's nodes and are summed through LDS.
+//  * next n_mode_blocks: partial sums of the completion modes over chunks of
+//    nodes, part[n][c] = sum_l e^{-i alpha_n x_l - i beta_n f_l} J_l dx mu_l (eq. M_eta).
+//  * next n_chunks: the near field, y[perm[off + t]] = sum_u blk_q[t][u] mu[band_q(u)]
+//    (intersecting part eq. final_correction_0, singular part eq. local_mat,
+//    1/2 I) for up to NEAR_ROWS consecutive rows t of one cell q.
+constexpr int LOC_NT = 256, NEAR_ROWS = 8;
+struct LocalArgs {
+  int N, n_occ, n_mode_blocks, n_chunks, n_eq, n_cells, n_x;
+  const int* occ_cell;
+  const int* occ_off;
+  const int* perm;
+  const cplx* P;
+  cplx* dens;
+  const double* x;
+  const double* f;
+  const double* J;
+  cplx* mode_part;
+  const int* chunk_q;
+  const int* chunk_t0;
+  const int* col_lo;
+  const int* col_w;
+  const int64_t* near_off;
+  const cplx* nearblk;
+};
 
-// EqSources: one wavefront per (cell, output), lanes over the cell's nodes.
-// Workgroups [0, n_occ): dens[lam][cell][oo] = sum_t P[(off + t) * nout + o] mu[perm[off + t]],
-// o = lam 2 n_eq + oo.  Lanes run over the outputs o (rows of P are contiguous
-// in o); G = 256 / OW thread groups split the cell's nodes and are summed
-// through LDS.  Workgroups [n_occ, n_occ + NCH_MODES) (when U^eta is not
-// empty): partial sums of the completion modes over chunks of nodes,
-// part[n][c] = sum_l e^{-i alpha_n x_l - i beta_n f_l} J_l dx mu_l (eq. M_eta).
-__global__ __launch_bounds__(256) void k_p2e_apply(KParams K, int n_occ, int n_eq, int n_cells,
-                                                   const int* __restrict__ occ_cell, const int* __restrict__ occ_off,
-                                                   const int* __restrict__ perm, const cplx* __restrict__ P,
-                                                   const cplx* __restrict__ mu, cplx* __restrict__ dens,
-                                                   const double* __restrict__ x, const double* __restrict__ f,
-                                                   const double* __restrict__ J, cplx* __restrict__ mode_part) {
-  __shared__ cplx red[256];
-  const int q = blockIdx.x;
-  if (q >= n_occ) {
-    const int c = q - n_occ;
-    const int per = (K.N + NCH_MODES - 1) / NCH_MODES;
-    const int lo = c * per, hi = min(K.N, lo + per);
-    for (int t = 0; t < K.nU; ++t) {
+__global__ __launch_bounds__(LOC_NT) void k_local_apply(KParams K, LocalArgs L, const cplx* __restrict__ mu,
+                                                        cplx* __restrict__ y) {
+  __shared__ cplx red[LOC_NT];
+  __shared__ cplx rs[NEAR_ROWS][LOC_NT / 64];  // near-field row sums per wavefront
+  int b = blockIdx.x;
+  if (b < L.n_occ) {
+    const int q = b;
+    const int nout = 4 * L.n_eq;
+    const int OW = nout <= 64 ? 64 : (nout <= 128 ? 128 : 256);
+    const int G = LOC_NT / OW, g = threadIdx.x / OW, oo0 = threadIdx.x % OW;
+    const int cell = L.occ_cell[q];
+    const int off = L.occ_off[q], nq = L.occ_off[q + 1] - off;
+    for (int ob = 0; ob < nout; ob += OW) {
+      const int o = ob + oo0;
       cplx acc = cplx{0.0, 0.0};
-      for (int l = lo + threadIdx.x; l < hi; l += 256) {
-        const double mag = exp(K.Ubi[t] * f[l]) * J[l] * K.dx;
-        acc += (mag * cexp_i(-(K.Ua[t] * x[l] + K.Ubr[t] * f[l]))) * mu[l];
+      if (o < nout) {
+        const cplx* pr = L.P + (int64_t)off * nout + o;
+#pragma unroll 4
+        for (int t = g; t < nq; t += G) acc += pr[(int64_t)t * nout] * mu[L.perm[off + t]];
       }
-      const cplx sm = block_sum<256>(acc, red);
-      if (threadIdx.x == 0) mode_part[(int64_t)t * NCH_MODES + c] = sm;
+      red[threadIdx.x] = acc;
+      __syncthreads();
+      if (g == 0 && o < nout) {
+        for (int gg = 1; gg < G; ++gg) acc += red[gg * OW + oo0];
+        const int lam = o / (2 * L.n_eq), oo = o % (2 * L.n_eq);
+        L.dens[((int64_t)lam * L.n_cells + cell) * 2 * L.n_eq + oo] = acc;
+      }
       __syncthreads();
     }
     return;
   }
-  const int nout = 4 * n_eq;
-  const int OW = nout <= 64 ? 64 : (nout <= 128 ? 128 : 256);
-  const int G = 256 / OW, g = threadIdx.x / OW, oo0 = threadIdx.x % OW;
-  const int cell = occ_cell[q];
-  const int off = occ_off[q], nq = occ_off[q + 1] - off;
-  for (int ob = 0; ob < nout; ob += OW) {
-    const int o = ob + oo0;
-    cplx acc = cplx{0.0, 0.0};
-    if (o < nout) {
-      const cplx* pr = P + (int64_t)off * nout + o;
-#pragma unroll 4
-      for (int t = g; t < nq; t += G) acc += pr[(int64_t)t * nout] * mu[perm[off + t]];
+  b -= L.n_occ;
+  if (b < L.n_mode_blocks) {
+    const int per = (K.N + NCH_MODES - 1) / NCH_MODES;
+    const int lo = b * per, hi = min(K.N, lo + per);
+    for (int t = 0; t < K.nU; ++t) {
+      cplx acc = cplx{0.0, 0.0};
+      for (int l = lo + threadIdx.x; l < hi; l += LOC_NT) {
+        const double mag = exp(K.Ubi[t] * L.f[l]) * L.J[l] * K.dx;
+        acc += (mag * cexp_i(-(K.Ua[t] * L.x[l] + K.Ubr[t] * L.f[l]))) * mu[l];
+      }
+      const cplx sm = block_sum<LOC_NT>(acc, red);
+      if (threadIdx.x == 0) L.mode_part[(int64_t)t * NCH_MODES + b] = sm;
+      __syncthreads();
     }
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    if (g == 0 && o < nout) {
-      for (int gg = 1; gg < G; ++gg) acc += red[gg * OW + oo0];
-      const int lam = o / (2 * n_eq), oo = o % (2 * n_eq);
-      dens[((int64_t)lam * n_cells + cell) * 2 * n_eq + oo] = acc;
-    }
-    __syncthreads();
+    return;
+  }
+  b -= L.n_mode_blocks;
+  const int q = L.chunk_q[b], t0 = L.chunk_t0[b];
+  const int off = L.occ_off[q], nq = L.occ_off[q + 1] - off;
+  const int t1 = min(nq, t0 + NEAR_ROWS);
+  const int col = L.occ_cell[q] % L.n_x;
+  const int lo = L.col_lo[col], w = L.col_w[col];
+  // the workgroup streams its rows as one contiguous region: threads run over
+  // the band columns, all NEAR_ROWS row loads of a column are in flight together
+  const int N = L.N;
+  const int nr = t1 - t0;
+  const cplx* blk = L.nearblk + L.near_off[q] + (int64_t)t0 * w;
+  cplx acc[NEAR_ROWS];
+#pragma unroll
+  for (int r = 0; r < NEAR_ROWS; ++r) acc[r] = cplx{0.0, 0.0};
+  for (int u = threadIdx.x; u < w; u += LOC_NT) {
+    int l = lo + u;
+    l += (l < 0) ? N : ((l >= N) ? -N : 0);
+    const cplx m = mu[l];
+    cplx v[NEAR_ROWS];
+#pragma unroll
+    for (int r = 0; r < NEAR_ROWS; ++r) v[r] = blk[(int64_t)min(r, nr - 1) * w + u];
+#pragma unroll
+    for (int r = 0; r < NEAR_ROWS; ++r) acc[r] += v[r] * m;
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int r = 0; r < NEAR_ROWS; ++r) {
+    const cplx sm = wave_sum(acc[r]);
+    if (lane == 0) rs[r][wv] = sm;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nr) {
+    cplx sm = cplx{0.0, 0.0};
+    for (int k = 0; k < LOC_NT / 64; ++k) sm += rs[threadIdx.x][k];
+    y[L.perm[off + t0 + threadIdx.x]] = sm;
   }
 }
 
@@ -484,8 +525,56 @@ struct MergeArgs {
 // Owner-computes gather of the merged grids (eq. sum_eqsources), with the
 // quasi-periodic wrap phase and the twist exp(-i alpha x) fused.
 // g[kind][gy][gx], kind 0 = monopole density xi, 1 = dipole density zeta.
-__global__ void k_merge(MergeArgs M, const cplx* __restrict__ dens, const cplx* __restrict__ twH,
-                        const cplx* __restrict__ twV, cplx* __restrict__ gH, cplx* __restrict__ gV) {
+//
+// Workgroups from merge_blocks on compute the local corrections instead
+// (eq. small_convolution with the punctured kernel): one wavefront per pair
+// (cell q, occupied cell of its near columns), lanes over the boundary points
+// of q, corr[p][b] = e^{i alpha d W} sum_t W_o[t][b] dens_lambda(b)[rc][t].
+struct CorrArgs {
+  int n_pairs, n_bdry, n_bH, n_eq, n_cells, merge_blocks;
+  const int* pair_o;
+  const int* pair_rc;
+  const cplx* pair_ph;
+  const cplx* W;
+  cplx* corr;
+};
+constexpr int CORR_TB = 26;  // correction-matrix loads batched per lane
+
+__device__ inline void local_corr_pairs(const CorrArgs& C, const cplx* __restrict__ dens) {
+  __shared__ cplx sd[4][128];  // per wave: dens of the source cell, both sets
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int p = (blockIdx.x - C.merge_blocks) * 4 + wv;
+  const bool valid = p < C.n_pairs;
+  const int ns2 = 2 * C.n_eq;
+  const int rc = valid ? C.pair_rc[p] : 0;
+  for (int e = lane; e < 2 * ns2; e += 64) {
+    const int lam = e / ns2, t = e % ns2;
+    sd[wv][e] = valid ? dens[((int64_t)lam * C.n_cells + rc) * ns2 + t] : cplx{0.0, 0.0};
+  }
+  __syncthreads();
+  if (!valid || lane >= C.n_bdry) return;
+  const int lam = lane < C.n_bH ? 0 : 1;
+  const cplx* Wo = C.W + (int64_t)C.pair_o[p] * ns2 * C.n_bdry + lane;
+  const cplx* d = sd[wv] + lam * ns2;
+  cplx acc = cplx{0.0, 0.0};
+  for (int t0 = 0; t0 < ns2; t0 += CORR_TB) {
+    cplx wt[CORR_TB];
+#pragma unroll
+    for (int u = 0; u < CORR_TB; ++u) wt[u] = Wo[(int64_t)min(t0 + u, ns2 - 1) * C.n_bdry];
+#pragma unroll
+    for (int u = 0; u < CORR_TB; ++u)
+      if (t0 + u < ns2) acc += wt[u] * d[t0 + u];
+  }
+  C.corr[(int64_t)p * C.n_bdry + lane] = C.pair_ph[p] * acc;
+}
+
+__global__ __launch_bounds__(256) void k_merge(MergeArgs M, CorrArgs C, const cplx* __restrict__ dens,
+                                               const cplx* __restrict__ twH, const cplx* __restrict__ twV,
+                                               cplx* __restrict__ gH, cplx* __restrict__ gV) {
+  if ((int)blockIdx.x >= C.merge_blocks) {
+    local_corr_pairs(C, dens);
+    return;
+  }
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   const int nH = M.nXH * M.nYH, nV = M.nXV * M.nYV;
   if (e >= nH + nV) return;
@@ -638,34 +727,27 @@ struct FarArgs {
 
 // One block per occupied cell: boundary values of phi^all (H on horizontal
 // sides incl. corners, V on vertical sides), minus the equivalent sources of
-// the near columns (local correction), plane-wave weights, surface values,
-// plus the completion modes D_M (partial sums from k_p2e_apply).  Dynamic LDS:
-// the plane-wave factors ((Q^H)^T, R, 1/diag R), the cell's nodes and their
-// values, and the list of occupied candidate cells.  Each phase keeps its
-// global loads independent so that they are in flight together.
-constexpr int CELLS_TB = 13;  // correction-matrix loads batched per lane
+// the near columns (local corrections, from k_merge), plane-wave weights,
+// surface values, plus the completion modes D_M (partial sums from
+// k_local_apply).  Dynamic LDS: the plane-wave factors ((Q^H)^T, R, 1/diag R),
+// the cell's nodes and their values.  Each phase keeps its global loads
+// independent so that they are in flight together.
 __global__ __launch_bounds__(256) void k_cells_far(FarArgs A, KParams K, const int* __restrict__ occ_cell,
                                                    const int* __restrict__ occ_off, const int* __restrict__ perm,
-                                                   const unsigned char* __restrict__ occ_flag,
+                                                   const int* __restrict__ pair_off, const cplx* __restrict__ corr,
                                                    const cplx* __restrict__ phH, const cplx* __restrict__ phV,
-                                                   const cplx* __restrict__ dens, const cplx* __restrict__ W,
                                                    const cplx* __restrict__ pplw, const double* __restrict__ dirs,
                                                    const double* __restrict__ x, const double* __restrict__ f,
                                                    const cplx* __restrict__ mode_part, cplx* __restrict__ y,
                                                    cplx* __restrict__ yfar) {
   extern __shared__ cplx dyn[];
-  __shared__ cplx part[4][64];
   __shared__ cplx bv[64];
   __shared__ cplx wv_sh[64];
   __shared__ cplx msum[SESM_MAX_UETA];
-  __shared__ int n_occ_cand;
   const int q = blockIdx.x;
   const int cell = occ_cell[q];
   const int cx = cell % A.n_x, cy = cell / A.n_x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int ns2 = 2 * A.n_eq;
-  const int nrowoff = 2 * A.n_y - 1;
-  const int ncand = (2 * A.ring + 1) * A.n_y;
   const int off = occ_off[q], nq = occ_off[q + 1] - off;
   const double ccx = A.x0 + (cx + 0.5) * A.L, ccy = A.y0 + (cy + 0.5) * A.L;
   const int npf = (A.n_bdry + A.n_plw + 1) * A.n_plw;  // plane-wave factors
@@ -673,10 +755,9 @@ __global__ __launch_bounds__(256) void k_cells_far(FarArgs A, KParams K, const i
   cplx* ys = pf + npf;                                             // [max_q] surface values
   double* xs = reinterpret_cast<double*>(ys + A.max_q);            // [max_q] x, then [max_q] f
   int* node = reinterpret_cast<int*>(xs + 2 * A.max_q);            // [max_q] node index
-  int* cand = node + A.max_q;                                      // [ncand][3] (o, rc, wrap)
-  // phase 0: stage the plane-wave factors and the cell's nodes; candidate
-  // occupancy (wave 0, ordered compaction by ballot: fixed summation order);
-  // completion-mode sums (wave 1)
+  // phase 0: stage the plane-wave factors and the cell's nodes; completion-mode
+  // sums (wave 1); boundary values of phi^all minus the local corrections of
+  // the cell's pairs (threads b < n_bdry)
   for (int e = threadIdx.x; e < npf; e += 256) pf[e] = pplw[e];
   for (int t = threadIdx.x; t < nq; t += 256) {
     const int i = perm[off + t];
@@ -684,32 +765,7 @@ __global__ __launch_bounds__(256) void k_cells_far(FarArgs A, KParams K, const i
     xs[t] = x[i];
     xs[A.max_q + t] = f[i];
   }
-  if (wv == 0) {
-    int base = 0;
-    for (int r0 = 0; r0 < ncand; r0 += 64) {
-      const int r = r0 + lane;
-      bool occ = false;
-      int o = 0, rc = 0, Wr = 0;
-      if (r < ncand) {
-        const int dc = r / A.n_y - A.ring, ry = r % A.n_y;
-        int col = cx + dc;
-        if (col < 0) { col += A.n_x; Wr = -1; }
-        else if (col >= A.n_x) { col -= A.n_x; Wr = 1; }
-        rc = ry * A.n_x + col;
-        o = (dc + A.ring) * nrowoff + (ry - cy + A.n_y - 1);
-        occ = occ_flag[rc] != 0;
-      }
-      const unsigned long long m = __ballot(occ);
-      const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
-      if (occ) {
-        cand[3 * pos] = o;
-        cand[3 * pos + 1] = rc;
-        cand[3 * pos + 2] = Wr;
-      }
-      base += __popcll(m);
-    }
-    if (lane == 0) n_occ_cand = base;
-  } else if (wv == 1) {
+  if (wv == 1) {
     for (int t = 0; t < K.nU; ++t) {
       cplx a = cplx{0.0, 0.0};
       for (int c = lane; c < NCH_MODES; c += 64) a += mode_part[(int64_t)t * NCH_MODES + c];
@@ -717,37 +773,6 @@ __global__ __launch_bounds__(256) void k_cells_far(FarArgs A, KParams K, const i
       if (lane == 0) msum[t] = a;
     }
   }
-  __syncthreads();
-  // phase 1: local correction: waves split the occupied candidates, lanes the
-  // boundary points; W rows are contiguous over boundary points
-  cplx acc = cplx{0.0, 0.0};
-  const int nc = n_occ_cand;
-  if (lane < A.n_bdry) {
-    const int lam = lane < A.n_bH ? 0 : 1;
-    for (int c = wv; c < nc; c += 4) {
-      const int o = cand[3 * c], rc = cand[3 * c + 1], Wr = cand[3 * c + 2];
-      const cplx* Wo = W + (int64_t)o * ns2 * A.n_bdry + lane;
-      const cplx* v = dens + ((int64_t)lam * A.n_cells + rc) * ns2;
-      cplx sm = cplx{0.0, 0.0};
-      for (int t0 = 0; t0 < ns2; t0 += CELLS_TB) {
-        cplx wt[CELLS_TB], dt[CELLS_TB];
-#pragma unroll
-        for (int u = 0; u < CELLS_TB; ++u) {
-          const int t = min(t0 + u, ns2 - 1);
-          wt[u] = Wo[(int64_t)t * A.n_bdry];
-          dt[u] = v[t];
-        }
-#pragma unroll
-        for (int u = 0; u < CELLS_TB; ++u)
-          if (t0 + u < ns2) sm += wt[u] * dt[u];
-      }
-      if (Wr != 0) sm = cexp_i(A.alpha_d * Wr) * sm;
-      acc += sm;
-    }
-  }
-  part[wv][lane] = acc;
-  __syncthreads();
-  // phase 2: boundary values of phi^all minus the local correction
   if (threadIdx.x < A.n_bdry) {
     const int b = threadIdx.x;
     cplx val;
@@ -764,7 +789,11 @@ __global__ __launch_bounds__(256) void k_cells_far(FarArgs A, KParams K, const i
       val = phV[(int64_t)(cy * A.n_s + i + A.n_e) * A.nXV + gx];
       if (Wr) val = cexp_i(A.alpha_d) * val;
     }
-    bv[b] = val - (part[0][b] + part[1][b] + part[2][b] + part[3][b]);
+    cplx cs = cplx{0.0, 0.0};
+    const int p0 = pair_off[q], p1 = pair_off[q + 1];
+#pragma unroll 8
+    for (int p = p0; p < p1; ++p) cs += corr[(int64_t)p * A.n_bdry + b];
+    bv[b] = val - cs;
   }
   __syncthreads();
   // phase 3: plane-wave weights, least squares R w = Q^H b (eq. plwave_QR), on wavefront 0
@@ -823,9 +852,8 @@ __global__ __launch_bounds__(256) void k_cells_far(FarArgs A, KParams K, const i
 // dynamic LDS bytes of k_cells_far
 inline size_t cells_far_lds(const AccelOp* A) {
   const size_t npf = (size_t)(A->n_bdry + A->n_plw + 1) * A->n_plw;
-  const size_t ncand = (size_t)(2 * A->ring + 1) * A->n_y;
   const size_t mq = (size_t)A->max_q;
-  return sizeof(cplx) * (npf + mq) + sizeof(double) * 2 * mq + sizeof(int) * (mq + 3 * ncand);
+  return sizeof(cplx) * (npf + mq) + sizeof(double) * 2 * mq + sizeof(int) * mq;
 }
 
 template <typename T>
@@ -865,14 +893,6 @@ int fft_launch(sesm_ctx* ctx, hipStream_t st, const FftJob& j0, const FftJob& j1
 
 void sesm_accel_free(sesm_ctx* ctx) {
   AccelOp* A = ctx->acc;
-  if (A) {
-    if (A->s_near) {
-      (void)hipStreamSynchronize(A->s_near);
-      (void)hipStreamDestroy(A->s_near);
-    }
-    for (hipEvent_t ev : {A->ev_fork, A->ev_near})
-      if (ev) (void)hipEventDestroy(ev);
-  }
   delete A;  // device buffers are in ctx->owned
   ctx->acc = nullptr;
 }
@@ -986,23 +1006,50 @@ int sesm_accel_setup(sesm_ctx* ctx) {
   for (int q = 0; q < A->n_occ; ++q)
     near_off[q + 1] = near_off[q] + (int64_t)(occ_off[q + 1] - occ_off[q]) * col_w[occ_cell[q] % A->n_x];
   A->near_entries = near_off[A->n_occ];
-  std::vector<int64_t> row_off(N);
-  std::vector<int> row_lo(N), row_w(N);
-  for (int q = 0; q < A->n_occ; ++q) {
-    const int col = occ_cell[q] % A->n_x;
-    for (int t = occ_off[q]; t < occ_off[q + 1]; ++t) {
-      row_off[t] = near_off[q] + (int64_t)(t - occ_off[q]) * col_w[col];
-      row_lo[t] = col_lo[col];
-      row_w[t] = col_w[col];
+  // near-field work items: up to NEAR_ROWS rows of one cell
+  std::vector<int> chunk_q, chunk_t0;
+  for (int q = 0; q < A->n_occ; ++q)
+    for (int t0 = 0; t0 < occ_off[q + 1] - occ_off[q]; t0 += NEAR_ROWS) {
+      chunk_q.push_back(q);
+      chunk_t0.push_back(t0);
     }
-  }
+  A->n_chunks = (int)chunk_q.size();
+  for (int c = 0; c < A->n_x; ++c) A->max_w = std::max(A->max_w, col_w[c]);
   int rc;
   if ((rc = upload(ctx, &A->occ_cell, occ_cell)) || (rc = upload(ctx, &A->occ_off, occ_off)) ||
       (rc = upload(ctx, &A->perm, perm)) || (rc = upload(ctx, &A->col_lo, col_lo)) ||
       (rc = upload(ctx, &A->col_w, col_w)) || (rc = upload(ctx, &A->near_off, near_off)) ||
-      (rc = upload(ctx, &A->occ_flag, occ_flag)) || (rc = upload(ctx, &A->row_off, row_off)) ||
-      (rc = upload(ctx, &A->row_lo, row_lo)) || (rc = upload(ctx, &A->row_w, row_w)))
+      (rc = upload(ctx, &A->chunk_q, chunk_q)) || (rc = upload(ctx, &A->chunk_t0, chunk_t0)))
     return rc;
+  // local-correction pairs: for every occupied cell, the occupied cells of its
+  // 2 ring + 1 columns (all rows), with the correction-matrix offset and the
+  // quasi-periodic phase of a wrapped column
+  {
+    const int nrowoff = 2 * A->n_y - 1;
+    std::vector<int> pair_off(1, 0), pair_o, pair_rc;
+    std::vector<cplx> pair_ph;
+    for (int q = 0; q < A->n_occ; ++q) {
+      const int cx = occ_cell[q] % A->n_x, cy = occ_cell[q] / A->n_x;
+      for (int dc = -R; dc <= R; ++dc)
+        for (int ry = 0; ry < A->n_y; ++ry) {
+          int col = cx + dc, Wr = 0;
+          if (col < 0) { col += A->n_x; Wr = -1; }
+          else if (col >= A->n_x) { col -= A->n_x; Wr = 1; }
+          const int rcell = ry * A->n_x + col;
+          if (!occ_flag[rcell]) continue;
+          pair_o.push_back((dc + R) * nrowoff + (ry - cy + A->n_y - 1));
+          pair_rc.push_back(rcell);
+          const C ph = std::exp(C(0.0, P.alpha * P.d * Wr));
+          pair_ph.push_back(cplx{ph.real(), ph.imag()});
+        }
+      pair_off.push_back((int)pair_o.size());
+    }
+    A->n_pairs = (int)pair_o.size();
+    if ((rc = upload(ctx, &A->pair_off, pair_off)) || (rc = upload(ctx, &A->pair_o, pair_o)) ||
+        (rc = upload(ctx, &A->pair_rc, pair_rc)) || (rc = upload(ctx, &A->pair_ph, pair_ph)) ||
+        (rc = sesm_alloc(ctx, (void**)&A->corr, sizeof(cplx) * (size_t)std::max(1, A->n_pairs) * A->n_bdry)))
+      return rc;
+  }
   const KParams K = ctx->kparams();
   const CellGeo G = cell_geo(*A);
   // --- equivalent-source least squares: A_eq on the device, QR on the host
@@ -1136,18 +1183,13 @@ int sesm_accel_setup(sesm_ctx* ctx) {
       (rc = sesm_alloc(ctx, (void**)&A->yfar, sizeof(cplx) * (size_t)N)))
     return rc;
   SESM_HIP(hipMemsetAsync(A->dens, 0, sizeof(cplx) * (size_t)2 * A->n_cells * ncol, ctx->stream));
-  // side stream of the near field (default priority); fork/join events need
-  // only device-scope release (both streams run on this device)
-  SESM_HIP(hipStreamCreateWithFlags(&A->s_near, hipStreamNonBlocking));
-  for (hipEvent_t* ev : {&A->ev_fork, &A->ev_near})
-    SESM_HIP(hipEventCreateWithFlags(ev, hipEventDisableTiming | hipEventReleaseToDevice));
   return SESM_OK;
 }
 
 // Algorithmic HBM bytes of one launch of each forward-map kernel (every
 // input array read once, every output written once).
 struct MatvecBytes {
-  double near, p2e, merge, fftH0, fftH1, fftV0, fftV1, yconvH, yconvV, cells;
+  double local, merge, fftH0, fftH1, fftV0, fftV1, yconvH, yconvV, cells;
 };
 
 static MatvecBytes matvec_bytes(const sesm_ctx* ctx) {
@@ -1157,14 +1199,17 @@ static MatvecBytes matvec_bytes(const sesm_ctx* ctx) {
   const double nH = (double)A->nXH * A->nYH, nV = (double)A->nXV * A->nYV;
   const double dens = c * 2.0 * A->n_cells * ns2;
   MatvecBytes B;
-  // stored blocks + mu + y + per-row offset (8 B), band start, width and node index (4 B each)
-  B.near = c * (double)A->near_entries + N * (2.0 * c + 20.0);
-  // operators + mu + node index + densities of the occupied cells + cell tables
-  // (+ x, f, J and the mode partial sums when U^eta is not empty)
-  B.p2e = c * nout * N + N * (c + 4.0) + A->n_occ * (c * nout + 12.0) +
-          (ctx->P.nU > 0 ? N * 24.0 + c * ctx->P.nU * NCH_MODES : 0.0);
-  // densities + grids (xi, zeta) + twist factors
-  B.merge = dens + c * 2.0 * (nH + nV) + c * (A->nXH + A->nXV);
+  // near field: stored blocks, mu, y, node index, chunk tables (8 B), per-cell
+  // band start, width and block offset (16 B);
+  // EqSources: operators, densities of the occupied cells, cell tables (12 B);
+  // modes (when U^eta is not empty): x, f, J and the partial sums
+  B.local = c * (double)A->near_entries + N * (2.0 * c + 4.0) + 8.0 * A->n_chunks + 16.0 * A->n_occ +
+            c * nout * N + A->n_occ * (c * nout + 12.0) +
+            (ctx->P.nU > 0 ? N * 24.0 + c * ctx->P.nU * NCH_MODES : 0.0);
+  // densities + grids (xi, zeta) + twist factors; local corrections: correction
+  // matrices, pair tables, corrections written
+  B.merge = dens + c * 2.0 * (nH + nV) + c * (A->nXH + A->nXV) + c * (double)A->n_off * ns2 * A->n_bdry +
+            A->n_pairs * (8.0 + c) + c * (double)A->n_pairs * A->n_bdry;
   // rows in + rows out (+ twiddle table; untwist factors on the inverse transforms)
   B.fftH0 = c * (2.0 * 2.0 * A->nYH * A->nXH + A->nXH);
   B.fftH1 = c * (2.0 * A->nYH * A->nXH + 2.0 * A->nXH);
@@ -1173,12 +1218,41 @@ static MatvecBytes matvec_bytes(const sesm_ctx* ctx) {
   // spectra of both grids in, both kernel spectra, one output grid
   B.yconvH = c * (2.0 * nH + 2.0 * (2.0 * A->nYH - 1) * A->nXH + nH);
   B.yconvV = c * (2.0 * nV + 2.0 * (2.0 * A->nYV - 1) * A->nXV + nV);
-  // correction matrices, densities, phi grids, plane-wave QR, directions, flags,
-  // cell tables, node coordinates and index, y read and written, mode sums
-  B.cells = c * (double)A->n_off * ns2 * A->n_bdry + dens + c * (nH + nV) +
+  // local corrections, phi grids, plane-wave QR, directions, cell and pair
+  // tables, node coordinates and index, y read and written, mode sums
+  B.cells = c * (double)A->n_pairs * A->n_bdry + c * (nH + nV) +
             c * ((double)A->n_bdry * A->n_plw + (double)A->n_plw * A->n_plw + A->n_plw) + 16.0 * A->n_plw +
-            A->n_cells + 12.0 * A->n_occ + N * (16.0 + 4.0 + 2.0 * c) + c * ctx->P.nU * NCH_MODES;
+            16.0 * A->n_occ + N * (16.0 + 4.0 + 2.0 * c) + c * ctx->P.nU * NCH_MODES;
   return B;
+}
+
+// Arguments of k_local_apply; without_far leaves only the near-field work items.
+static LocalArgs local_args(const sesm_ctx* ctx, bool near_only) {
+  const AccelOp* A = ctx->acc;
+  LocalArgs L{};
+  L.N = ctx->P.N;
+  L.n_occ = near_only ? 0 : A->n_occ;
+  L.n_mode_blocks = (near_only || ctx->P.nU == 0) ? 0 : NCH_MODES;
+  L.n_chunks = A->n_chunks;
+  L.n_eq = A->n_eq;
+  L.n_cells = A->n_cells;
+  L.n_x = A->n_x;
+  L.occ_cell = A->occ_cell;
+  L.occ_off = A->occ_off;
+  L.perm = A->perm;
+  L.P = A->p2e;
+  L.dens = A->dens;
+  L.x = ctx->x;
+  L.f = ctx->f;
+  L.J = ctx->J;
+  L.mode_part = A->mode_part;
+  L.chunk_q = A->chunk_q;
+  L.chunk_t0 = A->chunk_t0;
+  L.col_lo = A->col_lo;
+  L.col_w = A->col_w;
+  L.near_off = A->near_off;
+  L.nearblk = A->nearblk;
+  return L;
 }
 
 static int accel_matvec_impl(sesm_ctx* ctx, const cplx* mu, cplx* y, bool keep_far) {
@@ -1188,27 +1262,20 @@ static int accel_matvec_impl(sesm_ctx* ctx, const cplx* mu, cplx* y, bool keep_f
   hipStream_t st = ctx->stream;
   const MatvecBytes B = ctx->kt_mask ? matvec_bytes(ctx) : MatvecBytes{};
   int rc;
-  // cell densities (+ mode partial sums) first, alone on the HBM
-  SESM_KT_BEGIN(SESM_KT_P2E, st);
-  hipLaunchKernelGGL(k_p2e_apply, dim3(A->n_occ + (P.nU > 0 ? NCH_MODES : 0)), dim3(256), 0, st, K, A->n_occ,
-                     A->n_eq, A->n_cells, A->occ_cell, A->occ_off, A->perm, A->p2e, mu, A->dens, ctx->x, ctx->f,
-                     ctx->J, A->mode_part);
+  const LocalArgs L = local_args(ctx, false);
+  SESM_KT_BEGIN(SESM_KT_LOCAL, st);
+  hipLaunchKernelGGL(k_local_apply, dim3(L.n_occ + L.n_mode_blocks + L.n_chunks), dim3(LOC_NT), 0, st, K, L, mu,
+                     y);
   SESM_LAUNCH_CHECK();
-  SESM_KT_END(SESM_KT_P2E, st, B.p2e);
-  // fork: the near field (HBM-bound) runs beside the rest of the far-field pipeline
-  SESM_HIP(hipEventRecord(A->ev_fork, st));
-  SESM_HIP(hipStreamWaitEvent(A->s_near, A->ev_fork, 0));
-  SESM_KT_BEGIN(SESM_KT_NEAR, A->s_near);
-  hipLaunchKernelGGL(k_near_apply, dim3((P.N + 3) / 4), dim3(256), 0, A->s_near, P.N, A->perm, A->row_off, A->row_lo,
-                     A->row_w, A->nearblk, mu, y);
-  SESM_LAUNCH_CHECK();
-  SESM_KT_END(SESM_KT_NEAR, A->s_near, B.near);
-  SESM_HIP(hipEventRecord(A->ev_near, A->s_near));
+  SESM_KT_END(SESM_KT_LOCAL, st, B.local);
   MergeArgs M{A->n_x, A->n_y, A->n_s, A->n_e, A->n_side, A->n_eq, A->n_cells,
               A->nXH, A->nYH, A->nXV, A->nYV, P.alpha * P.d};
   const int ng = A->nXH * A->nYH + A->nXV * A->nYV;
+  const int mb = (ng + 255) / 256;
+  CorrArgs CA{A->n_pairs, A->n_bdry, A->n_bH, A->n_eq, A->n_cells, mb, A->pair_o, A->pair_rc, A->pair_ph, A->W, A->corr};
   SESM_KT_BEGIN(SESM_KT_MERGE, st);
-  hipLaunchKernelGGL(k_merge, dim3((ng + 255) / 256), dim3(256), 0, st, M, A->dens, A->twxH, A->twxV, A->gH, A->gV);
+  hipLaunchKernelGGL(k_merge, dim3(mb + (A->n_pairs + 3) / 4), dim3(256), 0, st, M, CA, A->dens, A->twxH, A->twxV,
+                     A->gH, A->gV);
   SESM_LAUNCH_CHECK();
   SESM_KT_END(SESM_KT_MERGE, st, B.merge);
   // both grids in each launch: forward FFT along x, y convolution, inverse FFT + untwist
@@ -1232,14 +1299,12 @@ static int accel_matvec_impl(sesm_ctx* ctx, const cplx* mu, cplx* y, bool keep_f
                        sesm_fft_job(A->planV, A->nYV, A->gV, A->phV, nullptr, A->utwV, 1.0 / A->nXV), +1)))
     return rc;
   SESM_KT_END(SESM_KT_FFT, st, B.fftH1 + B.fftV1);
-  // join the near-field stream before the cells add the far field into y
-  SESM_HIP(hipStreamWaitEvent(st, A->ev_near, 0));
   FarArgs F{P.N, A->n_x, A->n_y, A->n_s, A->n_e, A->n_side, A->n_eq, A->n_cells, A->n_bdry, A->n_bH, A->n_plw,
             A->nXH, A->nXV, A->ring, A->max_q, A->L, A->x0, A->y0, P.k, P.alpha * P.d};
   SESM_KT_BEGIN(SESM_KT_CELLS, st);
   hipLaunchKernelGGL(k_cells_far, dim3(A->n_occ), dim3(256), cells_far_lds(A), st, F, K, A->occ_cell, A->occ_off,
-                     A->perm, A->occ_flag, A->phH, A->phV, A->dens, A->W, A->pplw, A->dirs, ctx->x, ctx->f,
-                     A->mode_part, y, keep_far ? A->yfar : nullptr);
+                     A->perm, A->pair_off, A->corr, A->phH, A->phV, A->pplw, A->dirs, ctx->x, ctx->f, A->mode_part,
+                     y, keep_far ? A->yfar : nullptr);
   SESM_LAUNCH_CHECK();
   SESM_KT_END(SESM_KT_CELLS, st, B.cells);
   return SESM_OK;
@@ -1286,8 +1351,9 @@ extern "C" int sesm_diag_near(sesm_ctx* ctx, const sesm_c64* mu, sesm_c64* y) {
   if (!mu || !y || (const void*)mu == (const void*)y) return ctx->fail(SESM_EINVAL, "invalid vectors");
   SESM_HIP(hipSetDevice(ctx->device));
   AccelOp* A = ctx->acc;
-  hipLaunchKernelGGL(k_near_apply, dim3((ctx->P.N + 3) / 4), dim3(256), 0, ctx->stream, ctx->P.N, A->perm, A->row_off,
-                     A->row_lo, A->row_w, A->nearblk, (const cplx*)mu, (cplx*)y);
+  const LocalArgs L = local_args(ctx, true);
+  hipLaunchKernelGGL(k_local_apply, dim3(L.n_chunks), dim3(LOC_NT), 0, ctx->stream, ctx->kparams(), L,
+                     (const cplx*)mu, (cplx*)y);
   SESM_LAUNCH_CHECK();
   return SESM_OK;
 }

@@ -133,7 +133,10 @@ void sesm_release_surface(sesm_ctx* ctx) {
   ctx->Mdense = nullptr;
   ctx->V = nullptr;
   ctx->V_cols = 0;
-  ctx->hcol = ctx->hpart = ctx->ybuf = ctx->wtmp = ctx->upart = nullptr;
+  ctx->hcol = ctx->hpart = ctx->ybuf = ctx->wtmp = ctx->upart = ctx->gw = ctx->Hrow = ctx->hp = ctx->gcoef = nullptr;
+  ctx->gsc = nullptr;
+  ctx->Hrow_len = 0;
+  ctx->Hrow_m = -1;
   if (ctx->hhost) (void)hipHostFree(ctx->hhost);
   ctx->hhost = nullptr;
   for (hipEvent_t& ev : ctx->hev) {
@@ -470,8 +473,8 @@ int sesm_diag_hankel(sesm_ctx* ctx, const double* x, int32_t n, sesm_c64* h0, se
 // per-kernel timing
 
 static const char* const kKtNames[SESM_KT_COUNT] = {
-    "k_near_apply", "k_p2e_apply",   "k_merge",    "k_fft_rows", "k_yconv",
-    "k_cells_far",  "k_dots",        "k_update_part", "k_gemv_rows"};
+    "k_local_apply", "k_merge", "k_fft_rows",    "k_yconv",    "k_cells_far",
+    "k_gm_dots",     "k_gm_update",   "k_gemv_rows"};
 
 static int kt_fold(sesm_ctx* ctx, KTimer& T) {
   if (T.used == 0) return SESM_OK;

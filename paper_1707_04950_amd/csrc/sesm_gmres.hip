@@ -1,12 +1,21 @@
 // GMRES (Algorithm 1: "Run GMRES iterations, using the forward map").
 //
-// Device-resident Krylov basis V[(m+1) x N]; classical Gram-Schmidt applied
-// twice (CGS2) with tall-skinny dot-product kernels (each kernel reads every
-// basis vector once, coalesced); Givens rotations of the small Hessenberg
-// matrix on the host, which reads one column per iteration.  The host runs one
-// Arnoldi step behind the device: step it+1 is enqueued before the column of
-// step it is read back, so the device never waits for the host's rotations
-// (the extra step after convergence is discarded).
+// Arnoldi with classical Gram-Schmidt and delayed reorthogonalisation: the
+// second Gram-Schmidt pass of a basis vector is carried out in the next
+// Arnoldi step, together with the first pass of the next vector, so every
+// step reads the Krylov basis twice (one dot-product sweep, one update sweep)
+// instead of four times.  With Q = [q_0 .. q_{k-1}] orthonormal and u the
+// new vector after one projection (A q_{k-1} = Q h + u), step k computes
+//   w = A u;  s = Q^H u, rho = u^H u, z = Q^H w, zeta = u^H w   (one sweep)
+//   beta = sqrt(rho - |s|^2);  column k-1 of H: (h + s, beta)
+//   q_k = (u - Q s) / beta
+//   c_k = (zeta - s^H z) / beta,  a = c_k / beta
+//   u'  = (w - Q (z - a s) - a u) / beta = A q_k - [Q q_k] h'    (one sweep)
+//   h'  = ([z; c_k] - H s) / beta   (first-pass coefficients of column k)
+// which follows from A q_k = (w - A Q s) / beta and A Q = [Q q_k] H.  The
+// initial residual enters as u in step 0 (Q empty), whose beta is its norm.
+// The Hessenberg columns are rotated (Givens) on the host, which runs one
+// Arnoldi step behind the device.
 #include <cmath>
 #include <complex>
 #include <vector>
@@ -15,19 +24,33 @@
 
 namespace {
 
-constexpr int VT = 8;         // basis vectors per dot-product block
-constexpr int NCHUNK = 240;   // N-chunks of the single-vector norm reduction
-constexpr int DCHUNK = 32;    // N-chunks of the multi-vector dot products (about 1 KB of w per block)
+constexpr int VT = 8;          // basis vectors per dot-product block
+constexpr int NCHUNK = 240;    // N-chunks of the single-vector norm reduction
+constexpr int DCHUNK = 32;     // N-chunks of the multi-vector dot products
+constexpr int UCH = 64;        // basis vectors per update block
+constexpr int STEP_NT = 1024;  // threads of the one-block Arnoldi step
+constexpr int STEP_VPT = 4;    // basis vectors per thread in that step
 
-// part[v * DCHUNK + c] = sum_{i in chunk c} conj(V_v[i]) w[i], v in [0, nv).
-// Loads are unconditional (vector index clamped, surplus terms masked) so that
-// all VT basis loads of an iteration are in flight together.
-__global__ __launch_bounds__(256) void k_dots(int N, int nv, const cplx* __restrict__ V, int64_t ldv,
-                                              const cplx* __restrict__ w, cplx* __restrict__ part) {
-  __shared__ cplx sh[VT][4];
+// Offset of row r of the packed upper-Hessenberg matrix (rows 0..m, row r
+// holds columns max(0, r-1)..m-1 contiguously).
+__host__ __device__ inline int64_t hrow_off(int r, int m) {
+  if (r == 0) return 0;
+  const int64_t t = r - 1;
+  return m + t * (m + 1) - t * (t + 1) / 2;
+}
+
+// part[(v DCHUNK + c) 2 + 0] = sum_{i in chunk c} conj(V_v[i]) u[i],
+// part[(v DCHUNK + c) 2 + 1] = sum_{i in chunk c} conj(V_v[i]) w[i] (w optional),
+// v in [0, nv).  Loads are unconditional (vector index clamped, surplus terms
+// masked) so that all basis loads of an iteration are in flight together.
+__global__ __launch_bounds__(256) void k_gm_dots(int N, int nv, const cplx* __restrict__ V, int64_t ldv,
+                                                 const cplx* __restrict__ u, const cplx* __restrict__ w,
+                                                 cplx* __restrict__ part) {
+  __shared__ cplx sh[2][VT][4];
   const int c = blockIdx.x, v0 = blockIdx.y * VT;
   const int per = (N + DCHUNK - 1) / DCHUNK;
   const int lo = c * per, hi = min(N, lo + per);
+  const bool has_w = w != nullptr;
   const cplx* row[VT];
   double msk[VT];
 #pragma unroll
@@ -35,113 +58,189 @@ __global__ __launch_bounds__(256) void k_dots(int N, int nv, const cplx* __restr
     row[t] = V + (int64_t)min(v0 + t, nv - 1) * ldv;
     msk[t] = v0 + t < nv ? 1.0 : 0.0;
   }
-  cplx acc[VT];
+  cplx au[VT], aw[VT];
 #pragma unroll
-  for (int t = 0; t < VT; ++t) acc[t] = cplx{0.0, 0.0};
-  // two elements per thread and step: all 2 VT basis loads are issued before any use
-  for (int i = lo + threadIdx.x; i < hi; i += 512) {
-    const bool two = i + 256 < hi;
-    const int i2 = two ? i + 256 : i;
-    cplx a[VT], b[VT];
+  for (int t = 0; t < VT; ++t) au[t] = aw[t] = cplx{0.0, 0.0};
+  for (int i = lo + threadIdx.x; i < hi; i += 256) {
+    cplx a[VT];
 #pragma unroll
     for (int t = 0; t < VT; ++t) a[t] = row[t][i];
+    const cplx ui = u[i];
+    const cplx wi = has_w ? w[i] : cplx{0.0, 0.0};
 #pragma unroll
-    for (int t = 0; t < VT; ++t) b[t] = row[t][i2];
-    const cplx wa = w[i];
-    const cplx wb = two ? w[i2] : cplx{0.0, 0.0};
-#pragma unroll
-    for (int t = 0; t < VT; ++t) acc[t] += cmul_conj(a[t], wa) + cmul_conj(b[t], wb);
+    for (int t = 0; t < VT; ++t) {
+      au[t] += cmul_conj(a[t], ui);
+      aw[t] += cmul_conj(a[t], wi);
+    }
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int t = 0; t < VT; ++t) {
-    const cplx s = wave_sum(acc[t]);
-    if (lane == 0) sh[t][wv] = msk[t] * s;
-  }
-  __syncthreads();
-  if (threadIdx.x < VT && v0 + (int)threadIdx.x < nv) {
-    const int t = threadIdx.x;
-    part[(int64_t)(v0 + t) * DCHUNK + c] = sh[t][0] + sh[t][1] + sh[t][2] + sh[t][3];
-  }
-}
-
-// upart[c][i] = sum_{v in chunk c} V_v[i] coef[v], chunks of UCH vectors (more
-// workgroups than one pass over all vectors, and independent loads in flight).
-// Each workgroup first reduces the dot-product partials of its chunk,
-// coef[v] = sum_c' dpart[v * DCHUNK + c'] (one wave per v); the workgroups with
-// blockIdx.x == 0 also store h[v] = coef[v] (first pass) or h[v] + coef[v].
-constexpr int UCH = 32;
-__global__ __launch_bounds__(256) void k_update_part(int N, int nv, const cplx* __restrict__ V, int64_t ldv,
-                                                     const cplx* __restrict__ dpart, cplx* __restrict__ h,
-                                                     int accumulate, cplx* __restrict__ upart) {
-  __shared__ cplx hs[UCH];
-  const int c = blockIdx.y;
-  const int v0 = c * UCH, v1 = min(nv, v0 + UCH);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int v = v0 + wv; v < v1; v += 4) {
-    cplx sm = lane < DCHUNK ? dpart[(int64_t)v * DCHUNK + lane] : cplx{0.0, 0.0};
-    sm = wave_sum(sm);
+    const cplx s0 = wave_sum(au[t]);
+    const cplx s1 = wave_sum(aw[t]);
     if (lane == 0) {
-      hs[v - v0] = sm;
-      if (blockIdx.x == 0) h[v] = accumulate ? h[v] + sm : sm;
+      sh[0][t][wv] = msk[t] * s0;
+      sh[1][t][wv] = msk[t] * s1;
     }
   }
   __syncthreads();
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= N) return;
-  cplx sm = cplx{0.0, 0.0};
-#pragma unroll 8
-  for (int v = v0; v < v1; ++v) sm += V[(int64_t)v * ldv + i] * hs[v - v0];
-  upart[(int64_t)c * N + i] = sm;
-}
-
-// w[i] -= sum_c part[c][i]; with npart, also npart[block] = sum over the block of |w[i]|^2
-__global__ __launch_bounds__(256) void k_update_final(int N, int nch, const cplx* __restrict__ part,
-                                                      cplx* __restrict__ w, double* __restrict__ npart) {
-  __shared__ cplx sh[4];
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  double q = 0.0;
-  if (i < N) {
-    cplx s = w[i];
-    for (int c = 0; c < nch; ++c) s -= part[(int64_t)c * N + i];
-    w[i] = s;
-    q = abs2(s);
-  }
-  if (npart) {
-    const cplx r = block_sum<256>(cplx{q, 0.0}, sh);
-    if (threadIdx.x == 0) npart[blockIdx.x] = r.re;
+  if (threadIdx.x < 2 * VT) {
+    const int t = threadIdx.x >> 1, j = threadIdx.x & 1;
+    if (v0 + t < nv)
+      part[((int64_t)(v0 + t) * DCHUNK + c) * 2 + j] = sh[j][t][0] + sh[j][t][1] + sh[j][t][2] + sh[j][t][3];
   }
 }
 
-// n = sqrt(sum of the nparts partial squared norms); w /= n (zero norm leaves w);
-// block 0 stores cplx(n, 0) at *hout
-__global__ __launch_bounds__(256) void k_scale_norm(int N, int nparts, const double* __restrict__ npart, cplx* w,
-                                                    cplx* __restrict__ hout) {
-  __shared__ cplx sh[4];
-  __shared__ double nrm;
-  double s = 0.0;
-  for (int c = threadIdx.x; c < nparts; c += 256) s += npart[c];
-  const cplx r = block_sum<256>(cplx{s, 0.0}, sh);
+// Arnoldi step k (one workgroup): reduce the dot products of k_gm_dots over
+// V_0..V_k (V_k = u), then beta, the final column k-1 (hp + s, beta) into the
+// packed Hessenberg matrix and into hout (the host's copy; for k = 0, hout[0]
+// = beta, the residual norm), and the update coefficients cS = s, cZ = z,
+// cC = z - a s; sc = (1/beta, Re a, Im a, beta, Re c_k, Im c_k).  beta = 0
+// (an invariant Krylov space) gives zero coefficients and 1/beta = 0.
+__global__ __launch_bounds__(STEP_NT) void k_gm_step(int k, int m, const cplx* __restrict__ part,
+                                                     const cplx* __restrict__ hp, cplx* __restrict__ Hrow,
+                                                     cplx* __restrict__ hout, cplx* __restrict__ cS,
+                                                     cplx* __restrict__ cZ, cplx* __restrict__ cC,
+                                                     double* __restrict__ sc) {
+  __shared__ cplx sh[STEP_NT / 64];
+  __shared__ cplx s_last[2];  // (rho, zeta)
+  __shared__ double s_beta;
+  __shared__ cplx s_a;
+  cplx av[STEP_VPT], bv[STEP_VPT];
+  double ns = 0.0;
+  cplx sz = cplx{0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < STEP_VPT; ++j) {
+    const int v = threadIdx.x + j * STEP_NT;
+    av[j] = bv[j] = cplx{0.0, 0.0};
+    if (v <= k) {
+      for (int c = 0; c < DCHUNK; ++c) {
+        av[j] += part[((int64_t)v * DCHUNK + c) * 2];
+        bv[j] += part[((int64_t)v * DCHUNK + c) * 2 + 1];
+      }
+      if (v < k) {
+        ns += abs2(av[j]);
+        sz += cmul_conj(av[j], bv[j]);
+      } else {
+        s_last[0] = av[j];
+        s_last[1] = bv[j];
+      }
+    }
+  }
+  const cplx t_ns = block_sum<STEP_NT>(cplx{ns, 0.0}, sh);
+  const cplx t_sz = block_sum<STEP_NT>(sz, sh);
   if (threadIdx.x == 0) {
-    nrm = sqrt(r.re);
-    if (blockIdx.x == 0) *hout = cplx{nrm, 0.0};
+    const double b2 = s_last[0].re - t_ns.re;
+    const double beta = b2 > 0.0 ? sqrt(b2) : 0.0;
+    const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
+    const cplx ck = inv * (s_last[1] - t_sz);
+    const cplx a = inv * ck;
+    s_beta = beta;
+    s_a = a;
+    sc[0] = inv;
+    sc[1] = a.re;
+    sc[2] = a.im;
+    sc[3] = beta;
+    sc[4] = ck.re;
+    sc[5] = ck.im;
+    if (k == 0) hout[0] = cplx{beta, 0.0};
   }
   __syncthreads();
-  const double n = nrm;
-  const double inv = n > 0 ? 1.0 / n : 0.0;
+  const cplx a = s_a;
+#pragma unroll
+  for (int j = 0; j < STEP_VPT; ++j) {
+    const int v = threadIdx.x + j * STEP_NT;
+    if (v < k) {
+      cS[v] = av[j];
+      cZ[v] = bv[j];
+      cC[v] = bv[j] - a * av[j];
+      const cplx hv = hp[v] + av[j];
+      hout[v] = hv;
+      Hrow[hrow_off(v, m) + (k - 1 - (v > 0 ? v - 1 : 0))] = hv;
+    }
+  }
+  if (threadIdx.x == 0 && k > 0) {
+    hout[k] = cplx{s_beta, 0.0};
+    Hrow[hrow_off(k, m)] = cplx{s_beta, 0.0};
+  }
+}
+
+// Workgroups [0, nb nch): partial sums of the two basis combinations,
+// up[2 ch][i] = sum_{v in chunk ch} V_v[i] cS[v], up[2 ch + 1][i] = ... cC[v],
+// over chunks of UCH vectors.  The following ceil((k+1)/4) workgroups compute
+// the first-pass coefficients of column k, one wavefront per row r:
+// hp[r] = (c_r - sum_{j >= max(0, r-1)} H[r][j] cS[j]) / beta, c = (cZ, c_k).
+__global__ __launch_bounds__(256) void k_gm_update(int N, int k, int m, int nb, int nch,
+                                                   const cplx* __restrict__ V, int64_t ldv,
+                                                   const cplx* __restrict__ cS, const cplx* __restrict__ cZ,
+                                                   const cplx* __restrict__ cC, const double* __restrict__ sc,
+                                                   const cplx* __restrict__ Hrow, cplx* __restrict__ hp,
+                                                   cplx* __restrict__ up) {
+  const int bid = blockIdx.x;
+  if (bid >= nb * nch) {
+    const int lane = threadIdx.x & 63;
+    const int r = (bid - nb * nch) * 4 + (threadIdx.x >> 6);
+    if (r > k) return;  // wave-uniform
+    const int j0 = r > 0 ? r - 1 : 0;
+    const cplx* hr = Hrow + hrow_off(r, m) - j0;
+    cplx acc = cplx{0.0, 0.0};
+    for (int j = j0 + lane; j < k; j += 64) acc += hr[j] * cS[j];
+    acc = wave_sum(acc);
+    if (lane == 0) {
+      const cplx cr = r < k ? cZ[r] : cplx{sc[4], sc[5]};
+      hp[r] = sc[0] * (cr - acc);
+    }
+    return;
+  }
+  __shared__ cplx hs[2][UCH];
+  const int ch = bid / nb, ib = bid % nb;
+  const int v0 = ch * UCH, v1 = min(k, v0 + UCH);
+  if ((int)threadIdx.x < v1 - v0) {
+    hs[0][threadIdx.x] = cS[v0 + threadIdx.x];
+    hs[1][threadIdx.x] = cC[v0 + threadIdx.x];
+  }
+  __syncthreads();
+  const int i = ib * 256 + threadIdx.x;
+  if (i >= N) return;
+  cplx s1 = cplx{0.0, 0.0}, s2 = cplx{0.0, 0.0};
+#pragma unroll 8
+  for (int v = v0; v < v1; ++v) {
+    const cplx x = V[(int64_t)v * ldv + i];
+    s1 += x * hs[0][v - v0];
+    s2 += x * hs[1][v - v0];
+  }
+  up[(int64_t)(2 * ch) * N + i] = s1;
+  up[(int64_t)(2 * ch + 1) * N + i] = s2;
+}
+
+// q_k = (u - sum_ch up[2 ch]) / beta into V_k (in place of u),
+// u' = (w - sum_ch up[2 ch + 1] - a u) / beta into V_{k+1}
+__global__ __launch_bounds__(256) void k_gm_final(int N, int k, int nch, const cplx* __restrict__ up, cplx* V,
+                                                  int64_t ldv, const cplx* __restrict__ w,
+                                                  const double* __restrict__ sc) {
   const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i < N && n > 0) w[i] = inv * w[i];
+  if (i >= N) return;
+  const double inv = sc[0];
+  const cplx a = cplx{sc[1], sc[2]};
+  const cplx u = V[(int64_t)k * ldv + i];
+  cplx p1 = cplx{0.0, 0.0}, p2 = cplx{0.0, 0.0};
+  for (int ch = 0; ch < nch; ++ch) {
+    p1 += up[(int64_t)(2 * ch) * N + i];
+    p2 += up[(int64_t)(2 * ch + 1) * N + i];
+  }
+  V[(int64_t)k * ldv + i] = inv * (u - p1);
+  V[(int64_t)(k + 1) * ldv + i] = inv * (w[i] - p2 - a * u);
 }
 
 // x[i] += sum_{v < nv} V_v[i] y[v]
 __global__ __launch_bounds__(256) void k_combine(int N, int nv, const cplx* __restrict__ V, int64_t ldv,
-                                                 const cplx* __restrict__ y, cplx* __restrict__ x, int add) {
+                                                 const cplx* __restrict__ y, cplx* __restrict__ x) {
   extern __shared__ cplx ys[];
   for (int v = threadIdx.x; v < nv; v += 256) ys[v] = y[v];
   __syncthreads();
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= N) return;
-  cplx s = add ? x[i] : cplx{0.0, 0.0};
+  cplx s = x[i];
   for (int v = 0; v < nv; ++v) s += V[(int64_t)v * ldv + i] * ys[v];
   x[i] = s;
 }
@@ -165,15 +264,6 @@ __global__ void k_norm_final(const double* __restrict__ part, cplx* __restrict__
   if (lane == 0) *out = cplx{sqrt(s), 0.0};
 }
 
-// dst = src / norm (norm read from device; zero norm leaves zeros)
-__global__ void k_scale(int N, const cplx* src, const cplx* __restrict__ nrm, cplx* dst) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const double n = nrm->re;
-  const double s = n > 0 ? 1.0 / n : 0.0;
-  dst[i] = s * src[i];
-}
-
 // r = b - r
 __global__ void k_sub_from(int N, const cplx* __restrict__ b, cplx* __restrict__ r) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -183,7 +273,7 @@ __global__ void k_sub_from(int N, const cplx* __restrict__ b, cplx* __restrict__
 
 int ensure_workspace(sesm_ctx* ctx, int m) {
   const int N = ctx->P.N;
-  if (ctx->V && ctx->V_cols >= m + 1) return SESM_OK;
+  if (ctx->V && ctx->V_cols >= m + 1 && ctx->Hrow_m == m) return SESM_OK;
   auto drop = [&](void* p) {
     if (!p) return;
     for (size_t t = 0; t < ctx->owned.size(); ++t)
@@ -195,19 +285,29 @@ int ensure_workspace(sesm_ctx* ctx, int m) {
   };
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->V) ctx->bytes -= (int64_t)ctx->V_cols * N * (int64_t)sizeof(cplx);
+  if (ctx->Hrow) ctx->bytes -= ctx->Hrow_len * (int64_t)sizeof(cplx);
   drop(ctx->V);
-  ctx->V = nullptr;
-  ctx->V_cols = 0;
+  drop(ctx->Hrow);
+  ctx->V = ctx->Hrow = nullptr;
+  ctx->V_cols = ctx->Hrow_len = 0;
+  ctx->Hrow_m = -1;
   int rc = sesm_alloc(ctx, (void**)&ctx->V, sizeof(cplx) * (size_t)(m + 1) * N);
   if (rc) return rc;
   ctx->V_cols = m + 1;
+  ctx->Hrow_len = hrow_off(m, m) + 1;
+  if ((rc = sesm_alloc(ctx, (void**)&ctx->Hrow, sizeof(cplx) * (size_t)ctx->Hrow_len))) return rc;
+  ctx->Hrow_m = m;
   if (!ctx->hcol) {
+    const int nchmax = (SESM_HSTRIDE + UCH - 1) / UCH;
     if ((rc = sesm_alloc(ctx, (void**)&ctx->hcol, sizeof(cplx) * SESM_HRING * SESM_HSTRIDE))) return rc;
-    if ((rc = sesm_alloc(ctx, (void**)&ctx->hpart, sizeof(cplx) * (size_t)SESM_HSTRIDE * DCHUNK))) return rc;
+    if ((rc = sesm_alloc(ctx, (void**)&ctx->hpart, sizeof(cplx) * (size_t)2 * SESM_HSTRIDE * DCHUNK))) return rc;
     if ((rc = sesm_alloc(ctx, (void**)&ctx->ybuf, sizeof(cplx) * SESM_HSTRIDE))) return rc;
+    if ((rc = sesm_alloc(ctx, (void**)&ctx->hp, sizeof(cplx) * SESM_HSTRIDE))) return rc;
+    if ((rc = sesm_alloc(ctx, (void**)&ctx->gcoef, sizeof(cplx) * 3 * SESM_HSTRIDE))) return rc;
+    if ((rc = sesm_alloc(ctx, (void**)&ctx->gsc, sizeof(double) * 8))) return rc;
     if ((rc = sesm_alloc(ctx, (void**)&ctx->wtmp, sizeof(cplx) * (size_t)N))) return rc;
-    if ((rc = sesm_alloc(ctx, (void**)&ctx->upart, sizeof(cplx) * (size_t)N * ((SESM_HSTRIDE + UCH - 1) / UCH))))
-      return rc;
+    if ((rc = sesm_alloc(ctx, (void**)&ctx->gw, sizeof(cplx) * (size_t)N))) return rc;
+    if ((rc = sesm_alloc(ctx, (void**)&ctx->upart, sizeof(cplx) * (size_t)2 * N * nchmax))) return rc;
     if (hipHostMalloc((void**)&ctx->hhost, sizeof(cplx) * (SESM_HRING + 1) * SESM_HSTRIDE, 0) != hipSuccess)
       return ctx->fail(SESM_ENOMEM, "hipHostMalloc failed");
     for (hipEvent_t& ev : ctx->hev)
@@ -226,7 +326,7 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
     return ctx->fail(SESM_EINVAL, "bad solve arguments");
   SESM_HIP(hipSetDevice(ctx->device));
   const int N = ctx->P.N;
-  int m = (restart == 0 || restart > max_iter) ? max_iter : restart;
+  const int m = (restart == 0 || restart > max_iter) ? max_iter : restart;
   if (m > 4000) return ctx->fail(SESM_EINVAL, "Krylov dimension above 4000; use restart");
   int rc = ensure_workspace(ctx, m);
   if (rc) return rc;
@@ -235,7 +335,10 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
   cplx* x = (cplx*)mu_out;
   cplx* V = ctx->V;
   const int64_t ldv = N;
-  double* npart = (double*)ctx->hpart;  // reuse for norm partials
+  double* npart = (double*)ctx->hpart;  // norm partials (before any Arnoldi step)
+  cplx* cS = ctx->gcoef;
+  cplx* cZ = cS + SESM_HSTRIDE;
+  cplx* cC = cZ + SESM_HSTRIDE;
 
   // right-hand side (incident field written into the workspace vector when NULL)
   const cplx* b = (const cplx*)b_in;
@@ -243,47 +346,13 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
     if ((rc = sesm_rhs(ctx, (sesm_c64*)ctx->wtmp))) return rc;
     b = ctx->wtmp;
   }
-  auto norm_to_host = [&](const cplx* v, double* out) -> int {
-    hipLaunchKernelGGL(k_norm2_part, dim3(NCHUNK), dim3(256), 0, st, N, v, npart);
-    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(64), 0, st, npart, ctx->hcol);
-    SESM_LAUNCH_CHECK();
-    SESM_HIP(hipMemcpyAsync(ctx->hhost, ctx->hcol, sizeof(cplx), hipMemcpyDeviceToHost, st));
-    SESM_HIP(hipStreamSynchronize(st));
-    *out = ctx->hhost[0].re;
-    return SESM_OK;
-  };
-  // Arnoldi step `it`: w = A v_it, CGS2 against v_0..v_it, normalise; the
-  // column (h_0..h_it, |w|) goes to ring slot it % SESM_HRING, then to the host.
-  auto arnoldi = [&](int it) -> int {
-    cplx* w = V + (int64_t)(it + 1) * ldv;
-    int r = sesm_apply(ctx, V + (int64_t)it * ldv, w);
-    if (r) return r;
-    const int nv = it + 1, slot = it % SESM_HRING;
-    cplx* hc = ctx->hcol + (size_t)slot * SESM_HSTRIDE;
-    const dim3 gd(DCHUNK, (nv + VT - 1) / VT);
-    const int nch = (nv + UCH - 1) / UCH;
-    const double c16 = sizeof(cplx);
-    for (int pass = 0; pass < 2; ++pass) {
-      SESM_KT_BEGIN(SESM_KT_DOTS, st);
-      hipLaunchKernelGGL(k_dots, gd, dim3(256), 0, st, N, nv, V, ldv, w, ctx->hpart);
-      SESM_KT_END(SESM_KT_DOTS, st, c16 * ((double)nv * N + N + (double)nv * DCHUNK));  // basis, w, partials
-      SESM_KT_BEGIN(SESM_KT_UPDATE, st);
-      hipLaunchKernelGGL(k_update_part, dim3(nb, nch), dim3(256), 0, st, N, nv, V, ldv, ctx->hpart, hc, pass,
-                         ctx->upart);
-      // basis, update partials, dot partials
-      SESM_KT_END(SESM_KT_UPDATE, st, c16 * ((double)nv * N + (double)nch * N + (double)nv * DCHUNK));
-      hipLaunchKernelGGL(k_update_final, dim3(nb), dim3(256), 0, st, N, nch, ctx->upart, w,
-                         pass == 1 ? npart : nullptr);
-    }
-    hipLaunchKernelGGL(k_scale_norm, dim3(nb), dim3(256), 0, st, N, nb, npart, w, hc + nv);
-    SESM_LAUNCH_CHECK();
-    SESM_HIP(hipMemcpyAsync(ctx->hhost + (size_t)slot * SESM_HSTRIDE, hc, sizeof(cplx) * (nv + 1),
-                            hipMemcpyDeviceToHost, st));
-    SESM_HIP(hipEventRecord(ctx->hev[slot], st));
-    return SESM_OK;
-  };
   double bnorm = 0.0;
-  if ((rc = norm_to_host(b, &bnorm))) return rc;
+  hipLaunchKernelGGL(k_norm2_part, dim3(NCHUNK), dim3(256), 0, st, N, b, npart);
+  hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(64), 0, st, npart, ctx->hcol);
+  SESM_LAUNCH_CHECK();
+  SESM_HIP(hipMemcpyAsync(ctx->hhost, ctx->hcol, sizeof(cplx), hipMemcpyDeviceToHost, st));
+  SESM_HIP(hipStreamSynchronize(st));
+  bnorm = ctx->hhost[0].re;
   SESM_HIP(hipMemsetAsync(x, 0, sizeof(cplx) * (size_t)N, st));
   sesm_solve_info inf{0, 0.0, 0};
   if (bnorm == 0.0) {
@@ -291,13 +360,53 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
     if (info) *info = inf;
     return SESM_OK;
   }
+
+  // Arnoldi step k of a cycle with `steps` columns: steps k < steps apply the
+  // operator and update the basis; step `steps` only finalises the last
+  // column.  The step's column (for k = 0: the residual norm) goes to ring
+  // slot k % SESM_HRING and then to the host.
+  auto arnoldi = [&](int k, int steps) -> int {
+    const bool full = k < steps;
+    cplx* u = V + (int64_t)k * ldv;
+    if (full) {
+      const int r = sesm_apply(ctx, u, ctx->gw);
+      if (r) return r;
+    }
+    const int nv = k + 1, slot = k % SESM_HRING;
+    cplx* hc = ctx->hcol + (size_t)slot * SESM_HSTRIDE;
+    const double c16 = sizeof(cplx);
+    SESM_KT_BEGIN(SESM_KT_DOTS, st);
+    hipLaunchKernelGGL(k_gm_dots, dim3(DCHUNK, (nv + VT - 1) / VT), dim3(256), 0, st, N, nv, V, ldv, u,
+                       full ? ctx->gw : nullptr, ctx->hpart);
+    SESM_LAUNCH_CHECK();
+    // basis (u among it), w, partials
+    SESM_KT_END(SESM_KT_DOTS, st, c16 * ((double)nv * N + (full ? N : 0) + 2.0 * nv * DCHUNK));
+    hipLaunchKernelGGL(k_gm_step, dim3(1), dim3(STEP_NT), 0, st, k, m, ctx->hpart, ctx->hp, ctx->Hrow, hc, cS, cZ,
+                       cC, ctx->gsc);
+    SESM_LAUNCH_CHECK();
+    if (full) {
+      const int nch = (k + UCH - 1) / UCH;
+      SESM_KT_BEGIN(SESM_KT_UPDATE, st);
+      hipLaunchKernelGGL(k_gm_update, dim3(nb * nch + (k + 1 + 3) / 4), dim3(256), 0, st, N, k, m, nb, nch, V, ldv,
+                         cS, cZ, cC, ctx->gsc, ctx->Hrow, ctx->hp, ctx->upart);
+      SESM_LAUNCH_CHECK();
+      // basis, two partial vectors per chunk
+      SESM_KT_END(SESM_KT_UPDATE, st, c16 * ((double)k * N + 2.0 * nch * N));
+      hipLaunchKernelGGL(k_gm_final, dim3(nb), dim3(256), 0, st, N, k, nch, ctx->upart, V, ldv, ctx->gw, ctx->gsc);
+      SESM_LAUNCH_CHECK();
+    }
+    SESM_HIP(hipMemcpyAsync(ctx->hhost + (size_t)slot * SESM_HSTRIDE, hc, sizeof(cplx) * (k + 1),
+                            hipMemcpyDeviceToHost, st));
+    SESM_HIP(hipEventRecord(ctx->hev[slot], st));
+    return SESM_OK;
+  };
+
   std::vector<std::complex<double>> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1);
   int total = 0;
   double res = 1.0;
   bool first = true;
   while (total < max_iter) {
-    // r = b - A x  (x = 0 on the first cycle)
-    double beta0;
+    // u_0 = r = b - A x  (x = 0 on the first cycle)
     if (first) {
       SESM_HIP(hipMemcpyAsync(V, b, sizeof(cplx) * (size_t)N, hipMemcpyDeviceToDevice, st));
       first = false;
@@ -306,45 +415,49 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
       hipLaunchKernelGGL(k_sub_from, dim3(nb), dim3(256), 0, st, N, b, V);
       SESM_LAUNCH_CHECK();
     }
-    if ((rc = norm_to_host(V, &beta0))) return rc;
-    res = beta0 / bnorm;
-    if (res <= tol) break;
-    hipLaunchKernelGGL(k_scale, dim3(nb), dim3(256), 0, st, N, V, ctx->hcol, V);
     std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta0;
-    const int steps = std::min(m, max_iter - total);  // Arnoldi steps available in this cycle
-    if ((rc = arnoldi(0))) return rc;
-    int it = 0;
-    for (; it < steps; ++it, ++total) {
-      if (it + 1 < steps && (rc = arnoldi(it + 1))) return rc;  // keep the device one step ahead
-      const int nv = it + 1, slot = it % SESM_HRING;
+    const int steps = std::min(m, max_iter - total);  // columns available in this cycle
+    if ((rc = arnoldi(0, steps))) return rc;
+    int nv = 0;
+    bool done = false;
+    for (int k = 0;; ++k) {
+      if (k + 1 <= steps && (rc = arnoldi(k + 1, steps))) return rc;  // keep the device one step ahead
+      const int slot = k % SESM_HRING;
       SESM_HIP(hipEventSynchronize(ctx->hev[slot]));
       const cplx* hh = ctx->hhost + (size_t)slot * SESM_HSTRIDE;
-      std::complex<double>* col = &H[(size_t)it * (m + 1)];
-      for (int t = 0; t <= nv; ++t) col[t] = std::complex<double>(hh[t].re, hh[t].im);
-      for (int t = 0; t < it; ++t) {  // previous rotations [[conj c, conj s], [-s, c]]
-        const std::complex<double> u = col[t], v = col[t + 1];
-        col[t] = std::conj(cs[t]) * u + std::conj(sn[t]) * v;
-        col[t + 1] = -sn[t] * u + cs[t] * v;
+      if (k == 0) {  // residual norm of this cycle
+        g[0] = hh[0].re;
+        res = hh[0].re / bnorm;
+        if (res <= tol) {
+          done = true;
+          break;
+        }
+        continue;
       }
-      const std::complex<double> a = col[it], bb = col[it + 1];
+      const int j = k - 1;  // column j is final
+      std::complex<double>* col = &H[(size_t)j * (m + 1)];
+      for (int t = 0; t <= k; ++t) col[t] = std::complex<double>(hh[t].re, hh[t].im);
+      for (int t = 0; t < j; ++t) {  // previous rotations [[conj c, conj s], [-s, c]]
+        const std::complex<double> p = col[t], q = col[t + 1];
+        col[t] = std::conj(cs[t]) * p + std::conj(sn[t]) * q;
+        col[t + 1] = -sn[t] * p + cs[t] * q;
+      }
+      const std::complex<double> a = col[j], bb = col[j + 1];
       const double r = std::sqrt(std::norm(a) + std::norm(bb));
-      cs[it] = r != 0 ? a / r : 1.0;
-      sn[it] = r != 0 ? bb / r : 0.0;
-      col[it] = r;
-      col[it + 1] = 0.0;
-      g[it + 1] = -sn[it] * g[it];
-      g[it] = std::conj(cs[it]) * g[it];
-      res = std::abs(g[it + 1]) / bnorm;
-      if (res <= tol || r == 0.0) {
-        ++it;
-        ++total;
-        break;
-      }
+      cs[j] = r != 0 ? a / r : 1.0;
+      sn[j] = r != 0 ? bb / r : 0.0;
+      col[j] = r;
+      col[j + 1] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = std::conj(cs[j]) * g[j];
+      res = std::abs(g[j + 1]) / bnorm;
+      ++total;
+      nv = k;
+      if (res <= tol || r == 0.0 || k == steps) break;
     }
-    // y = R^{-1} g, x += V y  (a step enqueued ahead of a converged one only wrote
-    // v_{it+1} and a ring slot; both are ignored)
-    const int nv = it;
+    if (done) break;
+    // y = R^{-1} g, x += Q y  (a step enqueued ahead of the last one used only
+    // wrote basis vectors beyond q_{nv-1}, the step buffers and a ring slot)
     std::vector<std::complex<double>> y(nv);
     for (int t = nv - 1; t >= 0; --t) {
       std::complex<double> s = g[t];
@@ -353,9 +466,11 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
     }
     cplx* yh = ctx->hhost + (size_t)SESM_HRING * SESM_HSTRIDE;  // idle: each cycle ends synchronised
     for (int t = 0; t < nv; ++t) yh[t] = cplx{y[t].real(), y[t].imag()};
-    SESM_HIP(hipMemcpyAsync(ctx->ybuf, yh, sizeof(cplx) * nv, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), sizeof(cplx) * nv, st, N, nv, V, ldv, ctx->ybuf, x, 1);
-    SESM_LAUNCH_CHECK();
+    if (nv > 0) {
+      SESM_HIP(hipMemcpyAsync(ctx->ybuf, yh, sizeof(cplx) * nv, hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), sizeof(cplx) * nv, st, N, nv, V, ldv, ctx->ybuf, x);
+      SESM_LAUNCH_CHECK();
+    }
     SESM_HIP(hipStreamSynchronize(st));
     if (res <= tol) break;
   }

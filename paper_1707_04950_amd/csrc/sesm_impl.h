@@ -66,8 +66,15 @@ struct sesm_ctx {
   cplx* hhost = nullptr;     // pinned host copies of the ring slots (+ one slot for uploads)
   hipEvent_t hev[4] = {};    // per ring slot: its column has reached hhost
   cplx* ybuf = nullptr;      // device copy of the small LS solution
-  cplx* wtmp = nullptr;      // scratch vector of length N
+  cplx* wtmp = nullptr;      // scratch vector of length N (the right-hand side when none is given)
+  cplx* gw = nullptr;        // A u of the current Arnoldi step
   cplx* upart = nullptr;     // partial sums of the Gram-Schmidt update
+  cplx* Hrow = nullptr;      // packed upper-Hessenberg matrix, row-major
+  int64_t Hrow_len = 0;
+  int Hrow_m = -1;
+  cplx* hp = nullptr;        // first-pass coefficients of the newest column
+  cplx* gcoef = nullptr;     // update coefficients (s, z, z - a s)
+  double* gsc = nullptr;     // step scalars
   std::vector<void*> owned;  // every device allocation made for the surface
   int64_t bytes = 0;
   // per-kernel timing (sesm_timing_enable)
