@@ -209,7 +209,7 @@ enum {
 
 typedef struct {
   char name[40];     /* kernel name                                                  */
-  int64_t launches;  /* launches timed since sesm_timing_enable                       */
+  int64_t launches;  /* launches timed (bracketed) since sesm_timing_enable           */
   double total_ms;   /* sum of their durations (a HIP event pair around each launch,
                         recorded on the stream the kernel runs on)                    */
   double bytes;      /* sum of their algorithmic HBM bytes: every input array read
@@ -217,9 +217,11 @@ typedef struct {
 } sesm_kernel_stat;
 
 /* Start timing the kernel classes selected by mask, clearing all counters
- * (mask 0 stops timing).  Timed launches are bracketed by HIP events; other
- * launches are not touched.  Enqueues nothing itself. */
-SESM_API int sesm_timing_enable(sesm_ctx* ctx, uint32_t mask);
+ * (mask 0 stops timing).  Every every-th launch of a selected class (1: each
+ * launch) is bracketed by HIP events; other launches are not touched, so a
+ * sparse sample keeps the brackets' own cost out of a timed region.
+ * Enqueues nothing itself.  every < 1 is rejected (SESM_EINVAL). */
+SESM_API int sesm_timing_enable(sesm_ctx* ctx, uint32_t mask, int32_t every);
 
 /* Synchronise every stream the timed launches ran on and store SESM_KT_COUNT
  * records (host array, capacity n_stats >= SESM_KT_COUNT), one per class in

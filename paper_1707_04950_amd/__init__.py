@@ -91,7 +91,7 @@ def load_library(path=LIB_PATH):
         "sesm_diag_hankel": (ctypes.c_int, [_P, _P, _I, _P, _P]),
         "sesm_diag_accel": (ctypes.c_int, [_P, _P, _I, _P, ctypes.c_int64]),
         "sesm_diag_near": (ctypes.c_int, [_P, _P, _P]),
-        "sesm_timing_enable": (ctypes.c_int, [_P, ctypes.c_uint32]),
+        "sesm_timing_enable": (ctypes.c_int, [_P, ctypes.c_uint32, _I]),
         "sesm_timing_read": (ctypes.c_int, [_P, _P, _I]),
     }
     for name, (res, args) in sig.items():
@@ -216,9 +216,9 @@ class Solver:
         self._check(self.lib.sesm_diag_near(self.h, _ptr(mu), _ptr(out)))
         return out
 
-    def timing_enable(self, mask):
-        """Time the kernel classes in `mask` (bit i = class KT_*) from now on; clears counters."""
-        self._check(self.lib.sesm_timing_enable(self.h, int(mask)))
+    def timing_enable(self, mask, every=1):
+        """Time every `every`-th launch of the kernel classes in `mask` (bit i = class KT_*); clears counters."""
+        self._check(self.lib.sesm_timing_enable(self.h, int(mask), int(every)))
 
     def timing_read(self):
         """Per-class records {name: dict(launches, total_ms, bytes)} since timing_enable."""

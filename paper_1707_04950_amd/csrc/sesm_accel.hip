@@ -68,9 +68,11 @@ struct AccelOp {
   cplx* mode_part = nullptr;
   // local-correction pairs (occupied cell q, occupied cell of its near columns):
   // pair_off[q]..pair_off[q+1]-1, correction-matrix offset, source cell, wrap phase
-  int n_pairs = 0;
-  int *pair_off = nullptr, *pair_o = nullptr, *pair_rc = nullptr;
-  cplx* pair_ph = nullptr;
+  int n_pairs = 0, n_groups = 0;
+  int* pair_off = nullptr;
+  int *grp_o = nullptr, *grp_start = nullptr, *grp_n = nullptr, *plist = nullptr;  // pairs grouped by offset
+  int* grp_rc = nullptr;   // source cell per pair, in plist order
+  cplx* grp_ph = nullptr;  // wrap phase per pair, in plist order
   cplx* corr = nullptr;  // [n_pairs][n_bdry]
   cplx* yfar = nullptr;  // diagnostic copy of the far-field contribution
   FftPlan planH, planV;
@@ -193,20 +195,13 @@ __device__ inline cplx sesm_wave_backsub(const cplx* __restrict__ R, int n, cplx
       xr = cplx{(yu.re * d.re + yu.im * d.im) * dd, (yu.im * d.re - yu.re * d.im) * dd};
       yu = xr;
     }
-    xr.re = __shfl(xr.re, r);
-    xr.im = __shfl(xr.im, r);
+    xr.re = sesm_readlane(xr.re, r);
+    xr.im = sesm_readlane(xr.im, r);
     if (lane < r) yu -= R[(int64_t)lane * n + r] * xr;
   }
   return yu;
 }
 
-// value of v in lane l (l wave-uniform), through the scalar unit
-__device__ inline double sesm_readlane(double v, int l) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), l);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
 
 // As sesm_wave_backsub, with the reciprocals of the diagonal given (dinv) so
 // that each step is a multiplication, and the solved entry broadcast by
@@ -527,115 +522,156 @@ struct MergeArgs {
 // g[kind][gy][gx], kind 0 = monopole density xi, 1 = dipole density zeta.
 //
 // Workgroups from merge_blocks on compute the local corrections instead
-// (eq. small_convolution with the punctured kernel): one wavefront per pair
-// (cell q, occupied cell of its near columns), lanes over the boundary points
-// of q, corr[p][b] = e^{i alpha d W} sum_t W_o[t][b] dens_lambda(b)[rc][t].
+// (eq. small_convolution with the punctured kernel) for pairs p = (cell q,
+// occupied cell rc of its near columns) at offset o:
+// corr[p][b] = e^{i alpha d W} sum_t W_o[t][b] dens_lambda(b)[rc][t].
 struct CorrArgs {
-  int n_pairs, n_bdry, n_bH, n_eq, n_cells, merge_blocks;
-  const int* pair_o;
-  const int* pair_rc;
-  const cplx* pair_ph;
+  int n_groups, n_bdry, n_bH, n_eq, n_cells, merge_blocks;
+  const int* grp_o;      // correction-matrix offset of each group
+  const int* grp_start;  // its pairs: plist[grp_start .. grp_start + grp_n)
+  const int* grp_n;
+  const int* plist;      // pair indices, grouped by offset
+  const int* grp_rc;     // source cell of each pair, in plist order
+  const cplx* grp_ph;    // quasi-periodic phase of each pair, in plist order
   const cplx* W;
   cplx* corr;
 };
-constexpr int CORR_TB = 26;  // correction-matrix loads batched per lane
+constexpr int CORR_PPW = 3;              // pairs per wavefront
+constexpr int CORR_PPB = 4 * CORR_PPW;   // pairs per correction workgroup (all share one matrix W_o)
+constexpr int CORR_SB = 9;               // staged elements per thread and round (W_o up to 9 x 256 entries)
 
-__device__ inline void local_corr_pairs(const CorrArgs& C, const cplx* __restrict__ dens) {
-  __shared__ cplx sd[4][128];  // per wave: dens of the source cell, both sets
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int p = (blockIdx.x - C.merge_blocks) * 4 + wv;
-  const bool valid = p < C.n_pairs;
-  const int ns2 = 2 * C.n_eq;
-  const int rc = valid ? C.pair_rc[p] : 0;
-  for (int e = lane; e < 2 * ns2; e += 64) {
-    const int lam = e / ns2, t = e % ns2;
-    sd[wv][e] = valid ? dens[((int64_t)lam * C.n_cells + rc) * ns2 + t] : cplx{0.0, 0.0};
+// dynamic LDS bytes of the correction workgroups: W_o and the pairs' densities
+// (about 53 KB at n_s = 10: three workgroups per CU)
+inline size_t corr_lds(int n_eq, int n_bdry) {
+  return sizeof(cplx) * ((size_t)2 * n_eq * n_bdry + (size_t)CORR_PPB * 4 * n_eq);
+}
+
+// One workgroup per group of pairs with the same offset o: W_o and the pairs'
+// source-cell densities are staged in LDS, and each W_o element serves several
+// pairs at once (lambda of the boundary point: H rows use the horizontal set,
+// V rows the vertical one).
+__device__ inline void local_corr_group(const CorrArgs& C, const cplx* __restrict__ dens) {
+  extern __shared__ cplx lds[];
+  const int gi = blockIdx.x - C.merge_blocks;
+  if (gi >= C.n_groups) return;  // block-uniform
+  const int ns2 = 2 * C.n_eq, nb = C.n_bdry;
+  const int o = C.grp_o[gi], p0 = C.grp_start[gi], np = C.grp_n[gi];
+  cplx* Ws = lds;             // [ns2][nb]
+  cplx* Ds = lds + ns2 * nb;  // [CORR_PPB][2 ns2]
+  const cplx* Wo = C.W + (int64_t)o * ns2 * nb;
+  const int tid = threadIdx.x, nW = ns2 * nb, nD = np * 2 * ns2;
+  // staging in two memory latencies: the W_o loads and the source-cell indices
+  // of this thread's density elements first, then the densities
+  for (int e0 = tid; e0 < nW || e0 < nD; e0 += CORR_SB * 256) {
+    cplx wv[CORR_SB], dv[CORR_SB];
+    int rc[CORR_SB];
+#pragma unroll
+    for (int u = 0; u < CORR_SB; ++u) {
+      wv[u] = Wo[min(e0 + u * 256, nW - 1)];
+      rc[u] = C.grp_rc[p0 + min(e0 + u * 256, nD - 1) / (2 * ns2)];
+    }
+#pragma unroll
+    for (int u = 0; u < CORR_SB; ++u) {
+      const int t = min(e0 + u * 256, nD - 1) % (2 * ns2);
+      dv[u] = dens[((int64_t)(t / ns2) * C.n_cells + rc[u]) * ns2 + t % ns2];
+    }
+#pragma unroll
+    for (int u = 0; u < CORR_SB; ++u) {
+      if (e0 + u * 256 < nW) Ws[e0 + u * 256] = wv[u];
+      if (e0 + u * 256 < nD) Ds[e0 + u * 256] = dv[u];
+    }
   }
   __syncthreads();
-  if (!valid || lane >= C.n_bdry) return;
-  const int lam = lane < C.n_bH ? 0 : 1;
-  const cplx* Wo = C.W + (int64_t)C.pair_o[p] * ns2 * C.n_bdry + lane;
-  const cplx* d = sd[wv] + lam * ns2;
-  cplx acc = cplx{0.0, 0.0};
-  for (int t0 = 0; t0 < ns2; t0 += CORR_TB) {
-    cplx wt[CORR_TB];
+  // wavefront jg takes pairs CORR_PPW jg .. CORR_PPW jg + CORR_PPW - 1, lane b a
+  // boundary point: independent sums share each W_o element
+  const int b = tid & 63, jg = tid >> 6;
+  if (b >= nb || CORR_PPW * jg >= np) return;
+  const cplx* d = Ds + (size_t)(CORR_PPW * jg) * 2 * ns2 + (b < C.n_bH ? 0 : ns2);
+  cplx acc[CORR_PPW];
 #pragma unroll
-    for (int u = 0; u < CORR_TB; ++u) wt[u] = Wo[(int64_t)min(t0 + u, ns2 - 1) * C.n_bdry];
+  for (int j = 0; j < CORR_PPW; ++j) acc[j] = cplx{0.0, 0.0};
+#pragma unroll 2
+  for (int t = 0; t < ns2; ++t) {
+    const cplx w = Ws[t * nb + b];
 #pragma unroll
-    for (int u = 0; u < CORR_TB; ++u)
-      if (t0 + u < ns2) acc += wt[u] * d[t0 + u];
+    for (int j = 0; j < CORR_PPW; ++j) acc[j] += w * d[j * 2 * ns2 + t];
   }
-  C.corr[(int64_t)p * C.n_bdry + lane] = C.pair_ph[p] * acc;
+#pragma unroll
+  for (int j = 0; j < CORR_PPW; ++j) {
+    const int jj = CORR_PPW * jg + j;
+    if (jj < np) C.corr[(int64_t)C.plist[p0 + jj] * nb + b] = C.grp_ph[p0 + jj] * acc[j];
+  }
 }
 
 __global__ __launch_bounds__(256) void k_merge(MergeArgs M, CorrArgs C, const cplx* __restrict__ dens,
                                                const cplx* __restrict__ twH, const cplx* __restrict__ twV,
                                                cplx* __restrict__ gH, cplx* __restrict__ gV) {
   if ((int)blockIdx.x >= C.merge_blocks) {
-    local_corr_pairs(C, dens);
+    local_corr_group(C, dens);
     return;
   }
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   const int nH = M.nXH * M.nYH, nV = M.nXV * M.nYV;
   if (e >= nH + nV) return;
-  cplx xi = cplx{0.0, 0.0}, ze = cplx{0.0, 0.0};
-  if (e < nH) {
-    const int gy = e / M.nXH, gx = e % M.nXH;
-    const cplx* D = dens;  // lambda = H
-    for (int side = 0; side < 2; ++side) {      // bottom side of row gy, top side of row gy-1
-      const int row = gy - side;
-      if (row < 0 || row >= M.n_y) continue;
-      const int c0 = gx / M.n_s;
-      for (int dc = -1; dc <= 1; ++dc) {
-        const int cu = c0 + dc;
-        const int ix = gx - cu * M.n_s;
-        if (ix < -M.n_e || ix > M.n_s + M.n_e) continue;
-        int c = cu, Wr = 0;
-        if (c < 0) { c += M.n_x; Wr = -1; }
-        else if (c >= M.n_x) { c -= M.n_x; Wr = 1; }
-        const int s = side * M.n_side + ix + M.n_e;
-        const cplx* v = D + (int64_t)(row * M.n_x + c) * 2 * M.n_eq;
-        cplx a = v[s], b = v[M.n_eq + s];
-        if (Wr != 0) {
-          const cplx ph = cexp_i(M.alpha_d * Wr);
-          a = ph * a;
-          b = ph * b;
-        }
-        xi += a;
-        ze += b;
+  // up to six contributing cell sides per grid point (2 sides x 3 neighbours);
+  // addresses and masks first, then all loads in flight together
+  const bool onH = e < nH;
+  const int ee = onH ? e : e - nH;
+  const int nXg = onH ? M.nXH : M.nXV;
+  const int gy = ee / nXg, gx = ee % nXg;
+  const cplx* D = onH ? dens : dens + (int64_t)M.n_cells * 2 * M.n_eq;
+  const cplx* src[6];
+  int wr[6];
+  bool ok[6];
+#pragma unroll
+  for (int side = 0; side < 2; ++side)
+#pragma unroll
+    for (int d = -1; d <= 1; ++d) {
+      const int id = side * 3 + d + 1;
+      int row, c, pos, Wr = 0;
+      if (onH) {  // bottom side of row gy, top side of row gy-1
+        row = gy - side;
+        c = gx / M.n_s + d;
+        pos = gx - c * M.n_s;
+      } else {    // left side of column gx, right side of column gx-1
+        c = gx - side;
+        row = (gy - M.n_e) / M.n_s + d;
+        pos = gy - M.n_e - row * M.n_s;
       }
-    }
-    const cplx t = twH[gx];
-    gH[e] = xi * t;
-    gH[(int64_t)nH + e] = ze * t;
-  } else {
-    const int ev = e - nH;
-    const int gy = ev / M.nXV, gx = ev % M.nXV;
-    const cplx* D = dens + (int64_t)M.n_cells * 2 * M.n_eq;  // lambda = V
-    for (int side = 0; side < 2; ++side) {      // left side of column gx, right side of column gx-1
-      int c = gx - side, Wr = 0;
+      ok[id] = row >= 0 && row < M.n_y && pos >= -M.n_e && pos <= M.n_s + M.n_e;
       if (c < 0) { c += M.n_x; Wr = -1; }
-      const int r0 = (gy - M.n_e) / M.n_s;
-      for (int dr = -1; dr <= 1; ++dr) {
-        const int row = r0 + dr;
-        if (row < 0 || row >= M.n_y) continue;
-        const int iy = gy - M.n_e - row * M.n_s;
-        if (iy < -M.n_e || iy > M.n_s + M.n_e) continue;
-        const int s = side * M.n_side + iy + M.n_e;
-        const cplx* v = D + (int64_t)(row * M.n_x + c) * 2 * M.n_eq;
-        cplx a = v[s], b = v[M.n_eq + s];
-        if (Wr != 0) {
-          const cplx ph = cexp_i(M.alpha_d * Wr);
-          a = ph * a;
-          b = ph * b;
-        }
-        xi += a;
-        ze += b;
-      }
+      else if (c >= M.n_x) { c -= M.n_x; Wr = 1; }
+      wr[id] = Wr;
+      src[id] = ok[id] ? D + (int64_t)(row * M.n_x + c) * 2 * M.n_eq + side * M.n_side + pos + M.n_e : D;
     }
+  cplx va[6], vb[6];
+#pragma unroll
+  for (int id = 0; id < 6; ++id) {
+    va[id] = src[id][0];
+    vb[id] = src[id][M.n_eq];
+  }
+  const cplx php = cexp_i(M.alpha_d), phm = conj(php);
+  cplx xi = cplx{0.0, 0.0}, ze = cplx{0.0, 0.0};
+#pragma unroll
+  for (int id = 0; id < 6; ++id) {
+    if (!ok[id]) continue;
+    cplx a = va[id], b = vb[id];
+    if (wr[id] != 0) {
+      const cplx ph = wr[id] > 0 ? php : phm;
+      a = ph * a;
+      b = ph * b;
+    }
+    xi += a;
+    ze += b;
+  }
+  if (onH) {
+    const cplx t = twH[gx];
+    gH[ee] = xi * t;
+    gH[(int64_t)nH + ee] = ze * t;
+  } else {
     const cplx t = twV[gx];
-    gV[ev] = xi * t;
-    gV[(int64_t)nV + ev] = ze * t;
+    gV[ee] = xi * t;
+    gV[(int64_t)nV + ee] = ze * t;
   }
 }
 
@@ -758,7 +794,7 @@ __global__ __launch_bounds__(256) void k_cells_far(FarArgs A, KParams K, const i
   // phase 0: stage the plane-wave factors and the cell's nodes; completion-mode
   // sums (wave 1); boundary values of phi^all minus the local corrections of
   // the cell's pairs (threads b < n_bdry)
-  for (int e = threadIdx.x; e < npf; e += 256) pf[e] = pplw[e];
+  stage_copy<10>(pf, pplw, npf, threadIdx.x, 256);
   for (int t = threadIdx.x; t < nq; t += 256) {
     const int i = perm[off + t];
     node[t] = i;
@@ -828,11 +864,17 @@ __global__ __launch_bounds__(256) void k_cells_far(FarArgs A, KParams K, const i
       const cplx e = cexp_i(dxu * (xs[t] - ccx) + dyu * (xs[A.max_q + t] - ccy));
       sv = wa * e + wb * conj(e);
     }
-    for (int m = UPL >> 1; m > 0; m >>= 1) {
-      sv.re += __shfl_xor(sv.re, m);
-      sv.im += __shfl_xor(sv.im, m);
+    if (UPL == 16) {
+      sv.re = group_sum_d<16>(sv.re);
+      sv.im = group_sum_d<16>(sv.im);
+    } else if (UPL == 32) {
+      sv.re = group_sum_d<32>(sv.re);
+      sv.im = group_sum_d<32>(sv.im);
+    } else {
+      sv.re = group_sum_d<64>(sv.re);
+      sv.im = group_sum_d<64>(sv.im);
     }
-    if (t < nq && u == 0) ys[t] = sv;
+    if (t < nq && u == UPL - 1) ys[t] = sv;
   }
   __syncthreads();
   // phase 5: y_i += far value + completion modes sum_n e^{i alpha_n x_i + i beta_n f_i} s_n
@@ -1045,10 +1087,35 @@ int sesm_accel_setup(sesm_ctx* ctx) {
       pair_off.push_back((int)pair_o.size());
     }
     A->n_pairs = (int)pair_o.size();
-    if ((rc = upload(ctx, &A->pair_off, pair_off)) || (rc = upload(ctx, &A->pair_o, pair_o)) ||
-        (rc = upload(ctx, &A->pair_rc, pair_rc)) || (rc = upload(ctx, &A->pair_ph, pair_ph)) ||
+    // groups of at most CORR_PPB pairs sharing one offset (one correction matrix)
+    std::vector<std::vector<int>> by_o((size_t)(2 * R + 1) * nrowoff);
+    for (int p = 0; p < A->n_pairs; ++p) by_o[pair_o[p]].push_back(p);
+    std::vector<int> grp_o, grp_start, grp_n, plist;
+    for (int o = 0; o < (int)by_o.size(); ++o)
+      for (size_t j0 = 0; j0 < by_o[o].size(); j0 += CORR_PPB) {
+        grp_o.push_back(o);
+        grp_start.push_back((int)plist.size());
+        const int n = (int)std::min<size_t>(CORR_PPB, by_o[o].size() - j0);
+        grp_n.push_back(n);
+        for (int j = 0; j < n; ++j) plist.push_back(by_o[o][j0 + j]);
+      }
+    A->n_groups = (int)grp_o.size();
+    std::vector<int> grp_rc(plist.size());
+    std::vector<cplx> grp_ph(plist.size());
+    for (size_t i = 0; i < plist.size(); ++i) {
+      grp_rc[i] = pair_rc[plist[i]];
+      grp_ph[i] = pair_ph[plist[i]];
+    }
+    if ((rc = upload(ctx, &A->pair_off, pair_off)) || (rc = upload(ctx, &A->grp_rc, grp_rc)) ||
+        (rc = upload(ctx, &A->grp_ph, grp_ph)) || (rc = upload(ctx, &A->grp_o, grp_o)) ||
+        (rc = upload(ctx, &A->grp_start, grp_start)) || (rc = upload(ctx, &A->grp_n, grp_n)) ||
+        (rc = upload(ctx, &A->plist, plist)) ||
         (rc = sesm_alloc(ctx, (void**)&A->corr, sizeof(cplx) * (size_t)std::max(1, A->n_pairs) * A->n_bdry)))
       return rc;
+    const size_t lds = corr_lds(A->n_eq, A->n_bdry);
+    if (lds > 140 * 1024) return ctx->fail(SESM_EINVAL, "accelerator: correction matrices exceed the LDS of a workgroup");
+    if (lds > 64 * 1024)
+      SESM_HIP(hipFuncSetAttribute((const void*)k_merge, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   }
   const KParams K = ctx->kparams();
   const CellGeo G = cell_geo(*A);
@@ -1209,7 +1276,7 @@ static MatvecBytes matvec_bytes(const sesm_ctx* ctx) {
   // densities + grids (xi, zeta) + twist factors; local corrections: correction
   // matrices, pair tables, corrections written
   B.merge = dens + c * 2.0 * (nH + nV) + c * (A->nXH + A->nXV) + c * (double)A->n_off * ns2 * A->n_bdry +
-            A->n_pairs * (8.0 + c) + c * (double)A->n_pairs * A->n_bdry;
+            A->n_pairs * (12.0 + c) + 12.0 * A->n_groups + c * (double)A->n_pairs * A->n_bdry;
   // rows in + rows out (+ twiddle table; untwist factors on the inverse transforms)
   B.fftH0 = c * (2.0 * 2.0 * A->nYH * A->nXH + A->nXH);
   B.fftH1 = c * (2.0 * A->nYH * A->nXH + 2.0 * A->nXH);
@@ -1272,10 +1339,11 @@ static int accel_matvec_impl(sesm_ctx* ctx, const cplx* mu, cplx* y, bool keep_f
               A->nXH, A->nYH, A->nXV, A->nYV, P.alpha * P.d};
   const int ng = A->nXH * A->nYH + A->nXV * A->nYV;
   const int mb = (ng + 255) / 256;
-  CorrArgs CA{A->n_pairs, A->n_bdry, A->n_bH, A->n_eq, A->n_cells, mb, A->pair_o, A->pair_rc, A->pair_ph, A->W, A->corr};
+  CorrArgs CA{A->n_groups, A->n_bdry, A->n_bH,   A->n_eq,   A->n_cells, mb,   A->grp_o,
+              A->grp_start, A->grp_n, A->plist, A->grp_rc, A->grp_ph, A->W,   A->corr};
   SESM_KT_BEGIN(SESM_KT_MERGE, st);
-  hipLaunchKernelGGL(k_merge, dim3(mb + (A->n_pairs + 3) / 4), dim3(256), 0, st, M, CA, A->dens, A->twxH, A->twxV,
-                     A->gH, A->gV);
+  hipLaunchKernelGGL(k_merge, dim3(mb + A->n_groups), dim3(256), corr_lds(A->n_eq, A->n_bdry), st, M, CA, A->dens,
+                     A->twxH, A->twxV, A->gH, A->gV);
   SESM_LAUNCH_CHECK();
   SESM_KT_END(SESM_KT_MERGE, st, B.merge);
   // both grids in each launch: forward FFT along x, y convolution, inverse FFT + untwist

@@ -138,11 +138,9 @@ void sesm_release_surface(sesm_ctx* ctx) {
   ctx->Hrow_len = 0;
   ctx->Hrow_m = -1;
   if (ctx->hhost) (void)hipHostFree(ctx->hhost);
-  ctx->hhost = nullptr;
-  for (hipEvent_t& ev : ctx->hev) {
-    if (ev) (void)hipEventDestroy(ev);
-    ev = nullptr;
-  }
+  if (ctx->hflag) (void)hipHostFree(ctx->hflag);
+  ctx->hhost = ctx->hhost_dev = nullptr;
+  ctx->hflag = ctx->hflag_dev = nullptr;
   ctx->ready = false;
 }
 
@@ -491,6 +489,8 @@ static int kt_fold(sesm_ctx* ctx, KTimer& T) {
 
 int sesm_kt_begin(sesm_ctx* ctx, int id, hipStream_t st) {
   KTimer& T = ctx->kt[id];
+  T.open = (T.calls++ % ctx->kt_every) == 0;
+  if (!T.open) return SESM_OK;
   if (T.ev.empty()) {
     T.ev.assign(2 * SESM_KT_POOL, nullptr);
     for (hipEvent_t& e : T.ev) SESM_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
@@ -505,6 +505,8 @@ int sesm_kt_begin(sesm_ctx* ctx, int id, hipStream_t st) {
 
 int sesm_kt_end(sesm_ctx* ctx, int id, hipStream_t st, double nbytes) {
   KTimer& T = ctx->kt[id];
+  if (!T.open) return SESM_OK;
+  T.open = false;
   SESM_HIP(hipEventRecord(T.ev[2 * T.used + 1], st));
   ++T.used;
   ++T.launches;
@@ -521,17 +523,20 @@ void sesm_kt_free(sesm_ctx* ctx) {
   ctx->kt_mask = 0;
 }
 
-int sesm_timing_enable(sesm_ctx* ctx, uint32_t mask) {
+int sesm_timing_enable(sesm_ctx* ctx, uint32_t mask, int32_t every) {
   if (!ctx) return SESM_EINVAL;
   if (mask >> SESM_KT_COUNT) return ctx->fail(SESM_EINVAL, "timing mask selects unknown kernel classes");
+  if (every < 1) return ctx->fail(SESM_EINVAL, "timing sample interval must be >= 1");
   SESM_HIP(hipSetDevice(ctx->device));
   for (KTimer& T : ctx->kt) {
     const int rc = kt_fold(ctx, T);  // let recorded events finish before they are reused
     if (rc) return rc;
-    T.launches = 0;
+    T.launches = T.calls = 0;
+    T.open = false;
     T.ms = T.bytes = 0.0;
   }
   ctx->kt_mask = mask;
+  ctx->kt_every = every;
   return SESM_OK;
 }
 

@@ -130,11 +130,15 @@ __global__ __launch_bounds__(1024) void k_fft_rows(FftJob j0, FftJob j1, int sig
   const cplx* __restrict__ tw = J.tw;
   cplx* a = buf[0];
   cplx* b = buf[1];
-  for (int e = threadIdx.x; e < nr * n; e += blockDim.x) {
-    const int i = e % n;
-    cplx v = J.in[(int64_t)r0 * n + e];
-    if (J.pre) v = v * J.pre[i];
-    a[e] = v;
+  for (int e0 = threadIdx.x; e0 < nr * n; e0 += 2 * blockDim.x) {  // two loads in flight per thread
+    cplx v[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) v[u] = J.in[(int64_t)r0 * n + min(e0 + u * (int)blockDim.x, nr * n - 1)];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int e = e0 + u * blockDim.x;
+      if (e < nr * n) a[e] = J.pre ? v[u] * J.pre[e % n] : v[u];
+    }
   }
   __syncthreads();
   int p = 1;

@@ -15,7 +15,10 @@
 // which follows from A q_k = (w - A Q s) / beta and A Q = [Q q_k] H.  The
 // initial residual enters as u in step 0 (Q empty), whose beta is its norm.
 // The Hessenberg columns are rotated (Givens) on the host, which runs one
-// Arnoldi step behind the device.
+// Arnoldi step behind the device and receives each column through coherent
+// pinned memory written by the step kernel.
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <complex>
 #include <vector>
@@ -24,12 +27,11 @@
 
 namespace {
 
-constexpr int VT = 8;          // basis vectors per dot-product block
+constexpr int VT = 4;          // basis vectors per dot-product block
 constexpr int NCHUNK = 240;    // N-chunks of the single-vector norm reduction
-constexpr int DCHUNK = 32;     // N-chunks of the multi-vector dot products
+constexpr int DCHUNK = 16;     // N-chunks of the multi-vector dot products
 constexpr int UCH = 64;        // basis vectors per update block
 constexpr int STEP_NT = 1024;  // threads of the one-block Arnoldi step
-constexpr int STEP_VPT = 4;    // basis vectors per thread in that step
 
 // Offset of row r of the packed upper-Hessenberg matrix (rows 0..m, row r
 // holds columns max(0, r-1)..m-1 contiguously).
@@ -61,17 +63,32 @@ __global__ __launch_bounds__(256) void k_gm_dots(int N, int nv, const cplx* __re
   cplx au[VT], aw[VT];
 #pragma unroll
   for (int t = 0; t < VT; ++t) au[t] = aw[t] = cplx{0.0, 0.0};
-  for (int i = lo + threadIdx.x; i < hi; i += 256) {
-    cplx a[VT];
+  // software pipelined: the loads of element i + 256 are issued before the
+  // products of element i
+  int i = lo + threadIdx.x;
+  cplx a[VT], ui = cplx{0.0, 0.0}, wi = cplx{0.0, 0.0};
+  if (i < hi) {
 #pragma unroll
     for (int t = 0; t < VT; ++t) a[t] = row[t][i];
-    const cplx ui = u[i];
-    const cplx wi = has_w ? w[i] : cplx{0.0, 0.0};
+    ui = u[i];
+    wi = has_w ? w[i] : cplx{0.0, 0.0};
+  }
+  for (; i < hi; i += 256) {
+    const int in = i + 256 < hi ? i + 256 : i;
+    cplx b[VT];
+#pragma unroll
+    for (int t = 0; t < VT; ++t) b[t] = row[t][in];
+    const cplx un = u[in];
+    const cplx wn = has_w ? w[in] : cplx{0.0, 0.0};
 #pragma unroll
     for (int t = 0; t < VT; ++t) {
       au[t] += cmul_conj(a[t], ui);
       aw[t] += cmul_conj(a[t], wi);
     }
+#pragma unroll
+    for (int t = 0; t < VT; ++t) a[t] = b[t];
+    ui = un;
+    wi = wn;
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -93,39 +110,60 @@ __global__ __launch_bounds__(256) void k_gm_dots(int N, int nv, const cplx* __re
 
 // Arnoldi step k (one workgroup): reduce the dot products of k_gm_dots over
 // V_0..V_k (V_k = u), then beta, the final column k-1 (hp + s, beta) into the
-// packed Hessenberg matrix and into hout (the host's copy; for k = 0, hout[0]
-// = beta, the residual norm), and the update coefficients cS = s, cZ = z,
-// cC = z - a s; sc = (1/beta, Re a, Im a, beta, Re c_k, Im c_k).  beta = 0
-// (an invariant Krylov space) gives zero coefficients and 1/beta = 0.
+// packed Hessenberg matrix and into hout (coherent pinned host memory; for
+// k = 0, hout[0] = beta, the residual norm), and the update coefficients
+// cS = s, cZ = z, cC = z - a s; sc = (1/beta, Re a, Im a, beta, Re c_k, Im c_k).
+// beta = 0 (an invariant Krylov space) gives zero coefficients and 1/beta = 0.
+// Once the column is written (a system-scope release by every writer, then a
+// workgroup barrier), thread 0 stores seq into *flag, which the host polls.
 __global__ __launch_bounds__(STEP_NT) void k_gm_step(int k, int m, const cplx* __restrict__ part,
                                                      const cplx* __restrict__ hp, cplx* __restrict__ Hrow,
                                                      cplx* __restrict__ hout, cplx* __restrict__ cS,
                                                      cplx* __restrict__ cZ, cplx* __restrict__ cC,
-                                                     double* __restrict__ sc) {
+                                                     double* __restrict__ sc, int64_t* flag, int64_t seq) {
   __shared__ cplx sh[STEP_NT / 64];
   __shared__ cplx s_last[2];  // (rho, zeta)
   __shared__ double s_beta;
   __shared__ cplx s_a;
-  cplx av[STEP_VPT], bv[STEP_VPT];
-  double ns = 0.0;
-  cplx sz = cplx{0.0, 0.0};
+  // reduce the partials: lane = 16 g + c takes chunk c of basis vector
+  // vb + 4 u + g (u < 4), so each wavefront has 16 vectors' loads in flight;
+  // sums over the 16 chunks (DPP group sums, valid in lane c = 15) against u go
+  // to cS, against w to cZ (v = k: rho and zeta)
+  static_assert(DCHUNK == 16, "lane layout assumes 16 chunks");
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int g = lane >> 4, c = lane & 15;
+  constexpr int U = 4;
+  for (int vb = wv * 4 * U; vb <= k; vb += (STEP_NT / 64) * 4 * U) {
+    cplx p0[U], p1[U];
 #pragma unroll
-  for (int j = 0; j < STEP_VPT; ++j) {
-    const int v = threadIdx.x + j * STEP_NT;
-    av[j] = bv[j] = cplx{0.0, 0.0};
-    if (v <= k) {
-      for (int c = 0; c < DCHUNK; ++c) {
-        av[j] += part[((int64_t)v * DCHUNK + c) * 2];
-        bv[j] += part[((int64_t)v * DCHUNK + c) * 2 + 1];
-      }
-      if (v < k) {
-        ns += abs2(av[j]);
-        sz += cmul_conj(av[j], bv[j]);
-      } else {
-        s_last[0] = av[j];
-        s_last[1] = bv[j];
+    for (int u = 0; u < U; ++u) {
+      const int v = min(vb + 4 * u + g, k);
+      p0[u] = part[((int64_t)v * DCHUNK + c) * 2];
+      p1[u] = part[((int64_t)v * DCHUNK + c) * 2 + 1];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int v = vb + 4 * u + g;
+      const cplx s0 = cplx{group_sum_d<16>(p0[u].re), group_sum_d<16>(p0[u].im)};
+      const cplx s1 = cplx{group_sum_d<16>(p1[u].re), group_sum_d<16>(p1[u].im)};
+      if (c == 15 && v <= k) {
+        if (v < k) {
+          cS[v] = s0;
+          cZ[v] = s1;
+        } else {
+          s_last[0] = s0;
+          s_last[1] = s1;
+        }
       }
     }
+  }
+  __syncthreads();
+  double ns = 0.0;
+  cplx sz = cplx{0.0, 0.0};
+  for (int v = threadIdx.x; v < k; v += STEP_NT) {
+    const cplx av = cS[v], bv = cZ[v];
+    ns += abs2(av);
+    sz += cmul_conj(av, bv);
   }
   const cplx t_ns = block_sum<STEP_NT>(cplx{ns, 0.0}, sh);
   const cplx t_sz = block_sum<STEP_NT>(sz, sh);
@@ -147,21 +185,24 @@ __global__ __launch_bounds__(STEP_NT) void k_gm_step(int k, int m, const cplx* _
   }
   __syncthreads();
   const cplx a = s_a;
-#pragma unroll
-  for (int j = 0; j < STEP_VPT; ++j) {
-    const int v = threadIdx.x + j * STEP_NT;
-    if (v < k) {
-      cS[v] = av[j];
-      cZ[v] = bv[j];
-      cC[v] = bv[j] - a * av[j];
-      const cplx hv = hp[v] + av[j];
-      hout[v] = hv;
-      Hrow[hrow_off(v, m) + (k - 1 - (v > 0 ? v - 1 : 0))] = hv;
-    }
+  for (int v = threadIdx.x; v < k; v += STEP_NT) {
+    const cplx av = cS[v], bv = cZ[v];
+    cC[v] = bv - a * av;
+    const cplx hv = hp[v] + av;
+    hout[v] = hv;
+    Hrow[hrow_off(v, m) + (k - 1 - (v > 0 ? v - 1 : 0))] = hv;
   }
   if (threadIdx.x == 0 && k > 0) {
     hout[k] = cplx{s_beta, 0.0};
     Hrow[hrow_off(k, m)] = cplx{s_beta, 0.0};
+  }
+  // every writer releases its column entries at system scope, then the barrier
+  // orders them before the flag store
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence_system();
+    flag[threadIdx.x] = seq;  // (vector store from one lane)
   }
 }
 
@@ -184,6 +225,7 @@ __global__ __launch_bounds__(256) void k_gm_update(int N, int k, int m, int nb, 
     const int j0 = r > 0 ? r - 1 : 0;
     const cplx* hr = Hrow + hrow_off(r, m) - j0;
     cplx acc = cplx{0.0, 0.0};
+#pragma unroll 4
     for (int j = j0 + lane; j < k; j += 64) acc += hr[j] * cS[j];
     acc = wave_sum(acc);
     if (lane == 0) {
@@ -224,6 +266,7 @@ __global__ __launch_bounds__(256) void k_gm_final(int N, int k, int nch, const c
   const cplx a = cplx{sc[1], sc[2]};
   const cplx u = V[(int64_t)k * ldv + i];
   cplx p1 = cplx{0.0, 0.0}, p2 = cplx{0.0, 0.0};
+#pragma unroll 4
   for (int ch = 0; ch < nch; ++ch) {
     p1 += up[(int64_t)(2 * ch) * N + i];
     p2 += up[(int64_t)(2 * ch + 1) * N + i];
@@ -308,10 +351,14 @@ int ensure_workspace(sesm_ctx* ctx, int m) {
     if ((rc = sesm_alloc(ctx, (void**)&ctx->wtmp, sizeof(cplx) * (size_t)N))) return rc;
     if ((rc = sesm_alloc(ctx, (void**)&ctx->gw, sizeof(cplx) * (size_t)N))) return rc;
     if ((rc = sesm_alloc(ctx, (void**)&ctx->upart, sizeof(cplx) * (size_t)2 * N * nchmax))) return rc;
-    if (hipHostMalloc((void**)&ctx->hhost, sizeof(cplx) * (SESM_HRING + 1) * SESM_HSTRIDE, 0) != hipSuccess)
+    // columns and their flags in coherent pinned memory, written by the step kernel
+    if (hipHostMalloc((void**)&ctx->hhost, sizeof(cplx) * (SESM_HRING + 1) * SESM_HSTRIDE, hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipHostMalloc((void**)&ctx->hflag, sizeof(int64_t) * SESM_HRING, hipHostMallocCoherent) != hipSuccess)
       return ctx->fail(SESM_ENOMEM, "hipHostMalloc failed");
-    for (hipEvent_t& ev : ctx->hev)
-      if (!ev) SESM_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    for (int t = 0; t < SESM_HRING; ++t) ctx->hflag[t] = 0;
+    SESM_HIP(hipHostGetDevicePointer((void**)&ctx->hhost_dev, ctx->hhost, 0));
+    SESM_HIP(hipHostGetDevicePointer((void**)&ctx->hflag_dev, ctx->hflag, 0));
   }
   return SESM_OK;
 }
@@ -361,6 +408,7 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
     return SESM_OK;
   }
 
+  int64_t slot_seq[SESM_HRING] = {};
   // Arnoldi step k of a cycle with `steps` columns: steps k < steps apply the
   // operator and update the basis; step `steps` only finalises the last
   // column.  The step's column (for k = 0: the residual norm) goes to ring
@@ -373,7 +421,6 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
       if (r) return r;
     }
     const int nv = k + 1, slot = k % SESM_HRING;
-    cplx* hc = ctx->hcol + (size_t)slot * SESM_HSTRIDE;
     const double c16 = sizeof(cplx);
     SESM_KT_BEGIN(SESM_KT_DOTS, st);
     hipLaunchKernelGGL(k_gm_dots, dim3(DCHUNK, (nv + VT - 1) / VT), dim3(256), 0, st, N, nv, V, ldv, u,
@@ -381,9 +428,11 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
     SESM_LAUNCH_CHECK();
     // basis (u among it), w, partials
     SESM_KT_END(SESM_KT_DOTS, st, c16 * ((double)nv * N + (full ? N : 0) + 2.0 * nv * DCHUNK));
-    hipLaunchKernelGGL(k_gm_step, dim3(1), dim3(STEP_NT), 0, st, k, m, ctx->hpart, ctx->hp, ctx->Hrow, hc, cS, cZ,
-                       cC, ctx->gsc);
+    const int64_t seq = ++ctx->gm_seq;
+    hipLaunchKernelGGL(k_gm_step, dim3(1), dim3(STEP_NT), 0, st, k, m, ctx->hpart, ctx->hp, ctx->Hrow,
+                       ctx->hhost_dev + (size_t)slot * SESM_HSTRIDE, cS, cZ, cC, ctx->gsc, ctx->hflag_dev + slot, seq);
     SESM_LAUNCH_CHECK();
+    slot_seq[slot] = seq;
     if (full) {
       const int nch = (k + UCH - 1) / UCH;
       SESM_KT_BEGIN(SESM_KT_UPDATE, st);
@@ -395,9 +444,22 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
       hipLaunchKernelGGL(k_gm_final, dim3(nb), dim3(256), 0, st, N, k, nch, ctx->upart, V, ldv, ctx->gw, ctx->gsc);
       SESM_LAUNCH_CHECK();
     }
-    SESM_HIP(hipMemcpyAsync(ctx->hhost + (size_t)slot * SESM_HSTRIDE, hc, sizeof(cplx) * (k + 1),
-                            hipMemcpyDeviceToHost, st));
-    SESM_HIP(hipEventRecord(ctx->hev[slot], st));
+    return SESM_OK;
+  };
+  // wait until the step's column has reached the host (its flag carries the
+  // step's sequence number); fall back to a stream synchronisation after 2 s
+  auto wait_slot = [&](int slot) -> int {
+    volatile int64_t* fl = ctx->hflag + slot;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int spin = 0; *fl != slot_seq[slot]; ++spin) {
+      if ((spin & 1023) == 1023 &&
+          std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
+        SESM_HIP(hipStreamSynchronize(st));
+        if (*fl != slot_seq[slot]) return ctx->fail(SESM_EHIP, "GMRES step result did not reach the host");
+        break;
+      }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
     return SESM_OK;
   };
 
@@ -423,7 +485,7 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
     for (int k = 0;; ++k) {
       if (k + 1 <= steps && (rc = arnoldi(k + 1, steps))) return rc;  // keep the device one step ahead
       const int slot = k % SESM_HRING;
-      SESM_HIP(hipEventSynchronize(ctx->hev[slot]));
+      if ((rc = wait_slot(slot))) return rc;
       const cplx* hh = ctx->hhost + (size_t)slot * SESM_HSTRIDE;
       if (k == 0) {  // residual norm of this cycle
         g[0] = hh[0].re;

@@ -41,7 +41,9 @@ struct AccelOp;  // shifted-equivalent-source accelerator (sesm_accel.hip)
 struct KTimer {
   std::vector<hipEvent_t> ev;  // 2 per launch slot
   int used = 0;                // recorded pairs not yet folded
-  int64_t launches = 0;
+  int64_t calls = 0;           // launches of the class since enabling
+  int64_t launches = 0;        // launches timed
+  bool open = false;           // the current launch is bracketed
   double ms = 0.0, bytes = 0.0;
 };
 #define SESM_KT_POOL 2048  // launch slots per class between folds
@@ -63,8 +65,11 @@ struct sesm_ctx {
   int64_t V_cols = 0;
   cplx* hcol = nullptr;      // device Hessenberg columns (+ norm), a ring of SESM_HRING slots
   cplx* hpart = nullptr;     // partial dot products
-  cplx* hhost = nullptr;     // pinned host copies of the ring slots (+ one slot for uploads)
-  hipEvent_t hev[4] = {};    // per ring slot: its column has reached hhost
+  cplx* hhost = nullptr;     // pinned host ring slots of Hessenberg columns (+ one slot for uploads)
+  cplx* hhost_dev = nullptr; // the same memory as the device sees it
+  int64_t* hflag = nullptr;  // per ring slot: sequence number of the step whose column it holds
+  int64_t* hflag_dev = nullptr;
+  int64_t gm_seq = 0;        // steps enqueued on this context
   cplx* ybuf = nullptr;      // device copy of the small LS solution
   cplx* wtmp = nullptr;      // scratch vector of length N (the right-hand side when none is given)
   cplx* gw = nullptr;        // A u of the current Arnoldi step
@@ -79,6 +84,7 @@ struct sesm_ctx {
   int64_t bytes = 0;
   // per-kernel timing (sesm_timing_enable)
   uint32_t kt_mask = 0;
+  int kt_every = 1;  // bracket every kt_every-th launch of a class
   KTimer kt[SESM_KT_COUNT];
 
   int fail(int code, const std::string& msg) {
@@ -136,14 +142,75 @@ void sesm_accel_info(const sesm_ctx* ctx, sesm_surface_info* info);
 // operator dispatch
 int sesm_apply(sesm_ctx* ctx, const cplx* mu, cplx* y);
 
-// block-level reductions
+// dst[e] = src[e], e < n, by nt threads (tid = own index): B loads per thread
+// are issued (indices clamped) before any store, so one memory latency covers
+// B elements instead of each element waiting for its own load.
+template <int B, typename T>
+__device__ inline void stage_copy(T* dst, const T* __restrict__ src, int n, int tid, int nt) {
+  for (int e0 = tid; e0 < n; e0 += B * nt) {
+    T v[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) v[u] = src[min(e0 + u * nt, n - 1)];
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+      if (e0 + u * nt < n) dst[e0 + u * nt] = v[u];
+  }
+}
+
+// Wavefront sums through DPP lane moves (no LDS traffic): quad permutes, row
+// half-mirror and mirror give every lane its row's sum; row broadcasts of
+// lanes 15 and 31 accumulate rows upward, so lane 63 holds the total, which
+// readlane hands to every lane.  Each double moves as two 32-bit halves;
+// lanes outside a broadcast's row mask receive 0.
+template <int CTRL, int ROW_MASK>
+__device__ inline double sesm_dpp_mov(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffull), CTRL, ROW_MASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROW_MASK, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+__device__ inline double wave_sum_d(double v) {
+  v += sesm_dpp_mov<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+  v += sesm_dpp_mov<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+  v += sesm_dpp_mov<0x141, 0xF>(v);  // row_half_mirror
+  v += sesm_dpp_mov<0x140, 0xF>(v);  // row_mirror
+  v += sesm_dpp_mov<0x142, 0xA>(v);  // row_bcast:15 into rows 1, 3
+  v += sesm_dpp_mov<0x143, 0xC>(v);  // row_bcast:31 into rows 2, 3
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), 63);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 63);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// sum over the wavefront, returned in every lane
+__device__ inline cplx wave_sum(cplx v) { return cplx{wave_sum_d(v.re), wave_sum_d(v.im)}; }
+
+// sums over aligned groups of G = 16, 32 or 64 lanes, valid in the last lane
+// of each group
+template <int G>
+__device__ inline double group_sum_d(double v) {
+  v += sesm_dpp_mov<0xB1, 0xF>(v);
+  v += sesm_dpp_mov<0x4E, 0xF>(v);
+  v += sesm_dpp_mov<0x141, 0xF>(v);
+  v += sesm_dpp_mov<0x140, 0xF>(v);
+  if (G >= 32) v += sesm_dpp_mov<0x142, 0xA>(v);
+  if (G == 64) v += sesm_dpp_mov<0x143, 0xC>(v);
+  return v;
+}
+
+// value of v in lane l (l wave-uniform), through the scalar unit
+__device__ inline double sesm_readlane(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// block-level sum: wavefront sums, then LDS across wavefronts (NT multiple of 64)
 template <int NT>
 __device__ inline cplx block_sum(cplx v, cplx* sh) {
-  // wave reduction then LDS across waves; NT multiple of 64
-  for (int o = 32; o > 0; o >>= 1) {
-    v.re += __shfl_xor(v.re, o);
-    v.im += __shfl_xor(v.im, o);
-  }
+  v = wave_sum(v);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   __syncthreads();
   if (lane == 0) sh[w] = v;
@@ -153,12 +220,4 @@ __device__ inline cplx block_sum(cplx v, cplx* sh) {
     for (int i = 0; i < NT / 64; ++i) r += sh[i];
   }
   return r;  // valid in thread 0
-}
-
-__device__ inline cplx wave_sum(cplx v) {
-  for (int o = 32; o > 0; o >>= 1) {
-    v.re += __shfl_xor(v.re, o);
-    v.im += __shfl_xor(v.im, o);
-  }
-  return v;
 }

@@ -137,6 +137,11 @@ def test_kernel_timing_counts_and_bytes(torch, solver, case):
     # at most one step runs ahead of the last one used
     assert info["iters"] + 1 <= st["k_gm_dots"]["launches"] <= info["iters"] + 2
     assert st["k_local_apply"]["launches"] == 0
+    solver.timing_enable(1 << lib.KT_LOCAL, 3)  # launches 0, 3, 6 of 7 are bracketed
+    for _ in range(7):
+        solver.matvec(mu)
+    st = solver.timing_read()
+    assert st["k_local_apply"]["launches"] == 3 and st["k_merge"]["launches"] == 0
     solver.timing_enable(0)
     solver.matvec(mu)
     assert solver.timing_read()["k_gm_dots"]["launches"] == 0
