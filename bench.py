@@ -8,6 +8,8 @@ synthetic (seeded surface coefficients).  Prints one JSON line.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode accel|dense]
                        [--N 32768] [--no-cpu-baseline]
+       python bench.py --copy-probe   (one 256 MiB device copy, the reference
+                                       kernel for scaling HBM traffic counters)
 """
 import argparse
 import json
@@ -34,7 +36,54 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--max-iter", type=int, default=3000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true")
     return ap.parse_args()
+
+
+def copy_probe():
+    """One plain device copy of 256 MiB (after two warm-up copies): a kernel of
+    known traffic (256 MiB read, 256 MiB written) for scaling FETCH_SIZE and
+    WRITE_SIZE counter readings."""
+    import torch
+    n = (256 << 20) // 16
+    a = torch.zeros(n, dtype=torch.complex128, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": 256 << 20, "copy_probe_bytes_written": 256 << 20, "launches": 3}))
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_local_apply_traffic_grazing_wood_N32768.md")
+
+
+def library_sources_sha256():
+    """Hash of the library sources (HIP files, internal headers, the C header)."""
+    import glob
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1707_04950_amd", "csrc")
+    files = sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h")))
+    files.append(os.path.join(ROOT, "include", "sesm.h"))
+    h = hashlib.sha256()
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when there is none for this kernel or the library changed since."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    fields = dict(l.strip().split(": ", 1) for l in text.splitlines() if l.strip().count(": ") == 1 and
+                  l.strip().split(": ", 1)[0] in ("traffic_kernel", "traffic_bytes_per_launch", "library_sources_sha256"))
+    if fields.get("traffic_kernel") != kernel or fields.get("library_sources_sha256") != library_sources_sha256():
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(wl, N, target_s=15.0):
@@ -66,6 +115,9 @@ def cpu_baseline(wl, N, target_s=15.0):
 
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
@@ -149,7 +201,7 @@ def main():
             "unit": "GB/s", "bytes_per_launch": kst["bytes"] / n_launch, "avg_launch_us": avg_s * 1e6,
             "launches": kst["launches"], "sampled_every": TIMING_EVERY}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(dom)
     kernels = None
     if ranking:
         kernels = {n: {"launches": r["launches"], "total_ms": round(r["total_ms"], 3),

@@ -91,6 +91,9 @@ typedef struct {
   int32_t iters;          /* Krylov iterations performed            */
   double rel_residual;    /* final ||b - A mu|| / ||b|| estimate     */
   int32_t converged;      /* 1 if rel_residual <= tol               */
+  int32_t column_mismatches; /* Hessenberg columns whose copy streamed to the host
+                                during a cycle differed from the device's (the
+                                update of mu always uses the device's); 0 expected */
 } sesm_solve_info;
 
 /* Read-only description of the discretisation chosen by sesm_set_surface. */
@@ -110,7 +113,11 @@ typedef struct {
 } sesm_surface_info;
 
 /* Create a context on HIP device `device`; `hip_stream` is a hipStream_t (NULL
- * selects the default stream).  *out receives the context. */
+ * selects the default stream).  *out receives the context.  Debug aid: when
+ * the environment variable SESM_POISON_ALLOC is set (and not "0") at this
+ * call, every device buffer the context allocates is first filled with 0xFF
+ * bytes (NaN doubles), so that a read before the first write shows up as NaN
+ * in the results. */
 SESM_API int sesm_create(sesm_ctx** out, int device, void* hip_stream);
 
 /* Release a context and every device buffer it owns.  NULL is accepted. */
@@ -185,6 +192,14 @@ SESM_API int sesm_diag_accel(sesm_ctx* ctx, const sesm_c64* mu, int32_t which, s
  * the near columns - as one kernel launch (the near-field work items of the
  * forward map's first kernel) on the context's stream (no synchronisation).  mu, y: device arrays of N sesm_c64, not overlapping. */
 SESM_API int sesm_diag_near(sesm_ctx* ctx, const sesm_c64* mu, sesm_c64* y);
+
+/* Diagnostic: the library's own FFT (the transform of the periodic grid
+ * direction, Sec. 5.5.1) on caller data: out[r][j] = sum_t in[r][t]
+ * exp(sign 2 pi i j t / n) for rows r < rows.  in, out: device arrays of
+ * rows x n sesm_c64, row-major (in-place allowed).  n must be 5-smooth and at
+ * most 2000; sign is +1 or -1.  Synchronises the stream. */
+SESM_API int sesm_diag_fft(sesm_ctx* ctx, int32_t n, int32_t rows, const sesm_c64* in, sesm_c64* out,
+                           int32_t sign);
 
 /* Diagnostic: evaluate the library's FP64 Hankel functions H0^(1)(x),
  * H1^(1)(x) (used by every Green-function kernel, eq. free_space) at n

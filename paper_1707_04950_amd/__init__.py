@@ -38,7 +38,8 @@ class Params(ctypes.Structure):
 
 
 class SolveInfo(ctypes.Structure):
-    _fields_ = [("iters", ctypes.c_int32), ("rel_residual", ctypes.c_double), ("converged", ctypes.c_int32)]
+    _fields_ = [("iters", ctypes.c_int32), ("rel_residual", ctypes.c_double), ("converged", ctypes.c_int32),
+                ("column_mismatches", ctypes.c_int32)]
 
 
 # kernel classes of sesm_timing_enable (bit i of the mask selects class i)
@@ -92,6 +93,7 @@ def load_library(path=LIB_PATH):
         "sesm_diag_accel": (ctypes.c_int, [_P, _P, _I, _P, ctypes.c_int64]),
         "sesm_diag_near": (ctypes.c_int, [_P, _P, _P]),
         "sesm_timing_enable": (ctypes.c_int, [_P, ctypes.c_uint32, _I]),
+        "sesm_diag_fft": (ctypes.c_int, [_P, _I, _I, _P, _P, _I]),
         "sesm_timing_read": (ctypes.c_int, [_P, _P, _I]),
     }
     for name, (res, args) in sig.items():
@@ -170,6 +172,9 @@ class Solver:
         return out
 
     def empty(self):
+        if os.environ.get("SESM_POISON_ALLOC", "0") not in ("", "0"):  # outputs start as NaN too
+            return self._torch.full((self.N,), complex("nan+nanj"), dtype=self._torch.complex128,
+                                    device=self.device)
         return self._torch.empty(self.N, dtype=self._torch.complex128, device=self.device)
 
     def matvec(self, mu, out=None):
@@ -188,7 +193,8 @@ class Solver:
         bp = _ptr(b) if b is not None else None
         rc = self.lib.sesm_solve(self.h, bp, _ptr(out), tol, max_iter, restart, ctypes.byref(inf))
         self._check(rc, allow=(SESM_ENOCONV,) if allow_noconv else ())
-        return out, {"iters": inf.iters, "rel_residual": inf.rel_residual, "converged": bool(inf.converged)}
+        return out, {"iters": inf.iters, "rel_residual": inf.rel_residual, "converged": bool(inf.converged),
+                     "column_mismatches": inf.column_mismatches}
 
     def efficiencies(self, mu):
         cap = 4096
@@ -226,6 +232,15 @@ class Solver:
         self._check(self.lib.sesm_timing_read(self.h, ctypes.cast(arr, ctypes.c_void_p), KT_COUNT))
         return {r.name.decode(): {"launches": int(r.launches), "total_ms": float(r.total_ms), "bytes": float(r.bytes)}
                 for r in arr}
+
+    def diag_fft(self, x, sign=-1):
+        """The library's own FFT along the last axis of a 2-D complex tensor (rows x n)."""
+        torch = self._torch
+        x = x.to(device=self.device, dtype=torch.complex128).contiguous()
+        rows, n = x.shape
+        out = torch.empty_like(x)
+        self._check(self.lib.sesm_diag_fft(self.h, n, rows, _ptr(x), _ptr(out), sign))
+        return out
 
     def diag_hankel(self, x):
         torch = self._torch

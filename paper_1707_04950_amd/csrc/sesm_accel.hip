@@ -1412,6 +1412,34 @@ extern "C" int sesm_diag_accel(sesm_ctx* ctx, const sesm_c64* mu, int32_t which,
   return rc;
 }
 
+extern "C" int sesm_diag_fft(sesm_ctx* ctx, int32_t n, int32_t rows, const sesm_c64* in, sesm_c64* out,
+                             int32_t sign) {
+  if (!ctx) return SESM_EINVAL;
+  if (!in || !out || rows < 1 || (sign != 1 && sign != -1)) return ctx->fail(SESM_EINVAL, "bad FFT arguments");
+  FftPlan p;
+  if (n < 1 || n > SESM_FFT_MAXN || !sesm_fft_factor(n, &p))
+    return ctx->fail(SESM_EINVAL, "FFT length must be 5-smooth and <= 2000");
+  SESM_HIP(hipSetDevice(ctx->device));
+  std::vector<cplx> tw(n);
+  for (int t = 0; t < n; ++t) {
+    const double ph = -2.0 * PI * t / n;
+    tw[t] = cplx{std::cos(ph), std::sin(ph)};
+  }
+  cplx* dtw = nullptr;
+  SESM_HIP(hipMalloc((void**)&dtw, sizeof(cplx) * n));
+  int rc = SESM_OK;
+  if (hipMemcpyAsync(dtw, tw.data(), sizeof(cplx) * n, hipMemcpyHostToDevice, ctx->stream) != hipSuccess) {
+    rc = ctx->fail(SESM_EHIP, "twiddle upload failed");
+  } else {
+    p.tw = dtw;
+    rc = fft_launch(ctx, ctx->stream, sesm_fft_job(p, rows, (const cplx*)in, (cplx*)out, nullptr, nullptr, 1.0),
+                    FftJob{}, sign);
+  }
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess && rc == SESM_OK) rc = ctx->fail(SESM_EHIP, "FFT failed");
+  (void)hipFree(dtw);
+  return rc;
+}
+
 extern "C" int sesm_diag_near(sesm_ctx* ctx, const sesm_c64* mu, sesm_c64* y) {
   if (!ctx) return SESM_EINVAL;
   if (!ctx->ready) return ctx->fail(SESM_ENOSURF, "no surface");

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdlib>
 #include <cstring>
 
 #include "sesm_impl.h"
@@ -120,6 +121,9 @@ int sesm_alloc(sesm_ctx* ctx, void** p, size_t bytes) {
   }
   ctx->owned.push_back(*p);
   ctx->bytes += (int64_t)bytes;
+  if (ctx->poison &&  // every byte 0xFF: a NaN in each double, so a read before the first write shows
+      (hipMemsetAsync(*p, 0xFF, bytes, ctx->stream) != hipSuccess || hipStreamSynchronize(ctx->stream) != hipSuccess))
+    return ctx->fail(SESM_EHIP, "poisoning an allocation failed");
   return SESM_OK;
 }
 
@@ -133,7 +137,7 @@ void sesm_release_surface(sesm_ctx* ctx) {
   ctx->Mdense = nullptr;
   ctx->V = nullptr;
   ctx->V_cols = 0;
-  ctx->hcol = ctx->hpart = ctx->ybuf = ctx->wtmp = ctx->upart = ctx->gw = ctx->Hrow = ctx->hp = ctx->gcoef = nullptr;
+  ctx->hcol = ctx->hpart = ctx->ybuf = ctx->wtmp = ctx->upart = ctx->gw = ctx->Hrow = ctx->htri = ctx->hp = ctx->gcoef = nullptr;
   ctx->gsc = nullptr;
   ctx->Hrow_len = 0;
   ctx->Hrow_m = -1;
@@ -190,6 +194,8 @@ int sesm_create(sesm_ctx** out, int device, void* hip_stream) {
   if (!ctx) return SESM_ENOMEM;
   ctx->device = device;
   ctx->stream = (hipStream_t)hip_stream;
+  const char* pv = std::getenv("SESM_POISON_ALLOC");
+  ctx->poison = pv && pv[0] && pv[0] != '0';
   *out = ctx;
   return SESM_OK;
 }

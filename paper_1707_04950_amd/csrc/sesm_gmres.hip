@@ -275,6 +275,14 @@ __global__ __launch_bounds__(256) void k_gm_final(int N, int k, int nch, const c
   V[(int64_t)(k + 1) * ldv + i] = inv * (w[i] - p2 - a * u);
 }
 
+// Columns 0..nv-1 of the packed Hessenberg matrix, column-major: column j
+// (rows 0..j+1) at tri[j (j + 3) / 2 ..], one workgroup per column.
+__global__ __launch_bounds__(256) void k_hess_gather(int m, const cplx* __restrict__ Hrow, cplx* __restrict__ tri) {
+  const int j = blockIdx.x;
+  for (int r = threadIdx.x; r <= j + 1; r += 256)
+    tri[(int64_t)j * (j + 3) / 2 + r] = Hrow[hrow_off(r, m) + (j - (r > 0 ? r - 1 : 0))];
+}
+
 // x[i] += sum_{v < nv} V_v[i] y[v]
 __global__ __launch_bounds__(256) void k_combine(int N, int nv, const cplx* __restrict__ V, int64_t ldv,
                                                  const cplx* __restrict__ y, cplx* __restrict__ x) {
@@ -314,6 +322,9 @@ __global__ void k_sub_from(int N, const cplx* __restrict__ b, cplx* __restrict__
   r[i] = b[i] - r[i];
 }
 
+// entries of the gathered columns 0..m-1 (column j holds j + 2)
+inline int64_t m_tri(int m) { return m > 0 ? (int64_t)m * (m + 3) / 2 : 0; }
+
 int ensure_workspace(sesm_ctx* ctx, int m) {
   const int N = ctx->P.N;
   if (ctx->V && ctx->V_cols >= m + 1 && ctx->Hrow_m == m) return SESM_OK;
@@ -329,9 +340,11 @@ int ensure_workspace(sesm_ctx* ctx, int m) {
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->V) ctx->bytes -= (int64_t)ctx->V_cols * N * (int64_t)sizeof(cplx);
   if (ctx->Hrow) ctx->bytes -= ctx->Hrow_len * (int64_t)sizeof(cplx);
+  if (ctx->htri) ctx->bytes -= (int64_t)m_tri(ctx->Hrow_m) * (int64_t)sizeof(cplx);
   drop(ctx->V);
   drop(ctx->Hrow);
-  ctx->V = ctx->Hrow = nullptr;
+  drop(ctx->htri);
+  ctx->V = ctx->Hrow = ctx->htri = nullptr;
   ctx->V_cols = ctx->Hrow_len = 0;
   ctx->Hrow_m = -1;
   int rc = sesm_alloc(ctx, (void**)&ctx->V, sizeof(cplx) * (size_t)(m + 1) * N);
@@ -339,6 +352,7 @@ int ensure_workspace(sesm_ctx* ctx, int m) {
   ctx->V_cols = m + 1;
   ctx->Hrow_len = hrow_off(m, m) + 1;
   if ((rc = sesm_alloc(ctx, (void**)&ctx->Hrow, sizeof(cplx) * (size_t)ctx->Hrow_len))) return rc;
+  if ((rc = sesm_alloc(ctx, (void**)&ctx->htri, sizeof(cplx) * (size_t)m_tri(m)))) return rc;
   ctx->Hrow_m = m;
   if (!ctx->hcol) {
     const int nchmax = (SESM_HSTRIDE + UCH - 1) / UCH;
@@ -463,8 +477,30 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
     return SESM_OK;
   };
 
-  std::vector<std::complex<double>> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1);
-  int total = 0;
+  using C = std::complex<double>;
+  // Givens QR of one Hessenberg column j (rows 0..j+1, in place) given the
+  // rotations of the columns before it; updates g and returns |g[j+1]|
+  auto rotate = [](C* col, int j, std::vector<C>& cs, std::vector<C>& sn, std::vector<C>& g) -> double {
+    for (int t = 0; t < j; ++t) {  // previous rotations [[conj c, conj s], [-s, c]]
+      const C p = col[t], q = col[t + 1];
+      col[t] = std::conj(cs[t]) * p + std::conj(sn[t]) * q;
+      col[t + 1] = -sn[t] * p + cs[t] * q;
+    }
+    const C a = col[j], bb = col[j + 1];
+    const double r = std::sqrt(std::norm(a) + std::norm(bb));
+    cs[j] = r != 0 ? a / r : 1.0;
+    sn[j] = r != 0 ? bb / r : 0.0;
+    col[j] = r;
+    col[j + 1] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = std::conj(cs[j]) * g[j];
+    return std::abs(g[j + 1]);
+  };
+  // streamed columns: raw (for the check against the device) and rotated
+  // (the running residual estimate that decides when a cycle stops)
+  std::vector<C> Hraw((size_t)m_tri(m)), H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1);
+  std::vector<cplx> tri;
+  int total = 0, mismatches = 0;
   double res = 1.0;
   bool first = true;
   while (total < max_iter) {
@@ -481,63 +517,75 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
     const int steps = std::min(m, max_iter - total);  // columns available in this cycle
     if ((rc = arnoldi(0, steps))) return rc;
     int nv = 0;
-    bool done = false;
+    double beta0 = 0.0;
     for (int k = 0;; ++k) {
       if (k + 1 <= steps && (rc = arnoldi(k + 1, steps))) return rc;  // keep the device one step ahead
       const int slot = k % SESM_HRING;
       if ((rc = wait_slot(slot))) return rc;
       const cplx* hh = ctx->hhost + (size_t)slot * SESM_HSTRIDE;
       if (k == 0) {  // residual norm of this cycle
-        g[0] = hh[0].re;
-        res = hh[0].re / bnorm;
-        if (res <= tol) {
-          done = true;
-          break;
-        }
+        beta0 = hh[0].re;
+        g[0] = beta0;
+        res = beta0 / bnorm;
+        if (res <= tol) break;
         continue;
       }
       const int j = k - 1;  // column j is final
-      std::complex<double>* col = &H[(size_t)j * (m + 1)];
-      for (int t = 0; t <= k; ++t) col[t] = std::complex<double>(hh[t].re, hh[t].im);
-      for (int t = 0; t < j; ++t) {  // previous rotations [[conj c, conj s], [-s, c]]
-        const std::complex<double> p = col[t], q = col[t + 1];
-        col[t] = std::conj(cs[t]) * p + std::conj(sn[t]) * q;
-        col[t + 1] = -sn[t] * p + cs[t] * q;
-      }
-      const std::complex<double> a = col[j], bb = col[j + 1];
-      const double r = std::sqrt(std::norm(a) + std::norm(bb));
-      cs[j] = r != 0 ? a / r : 1.0;
-      sn[j] = r != 0 ? bb / r : 0.0;
-      col[j] = r;
-      col[j + 1] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = std::conj(cs[j]) * g[j];
+      C* col = &H[(size_t)j * (m + 1)];
+      C* raw = &Hraw[(size_t)m_tri(j)];
+      for (int t = 0; t <= k; ++t) raw[t] = col[t] = C(hh[t].re, hh[t].im);
+      const double r = rotate(col, j, cs, sn, g);
       res = std::abs(g[j + 1]) / bnorm;
-      ++total;
       nv = k;
       if (res <= tol || r == 0.0 || k == steps) break;
     }
-    if (done) break;
-    // y = R^{-1} g, x += Q y  (a step enqueued ahead of the last one used only
-    // wrote basis vectors beyond q_{nv-1}, the step buffers and a ring slot)
-    std::vector<std::complex<double>> y(nv);
+    if (nv == 0) {  // converged on the initial residual (or nothing to add)
+      SESM_HIP(hipStreamSynchronize(st));
+      break;
+    }
+    // The least-squares problem is solved from the device's own Hessenberg
+    // matrix (gathered after the cycle), so the update of x does not depend
+    // on the streamed copies; a streamed column that differs from it is
+    // counted.  A step enqueued ahead of the last one used only wrote basis
+    // vectors beyond q_{nv-1}, the step buffers and a ring slot.
+    tri.resize((size_t)m_tri(nv));
+    hipLaunchKernelGGL(k_hess_gather, dim3(nv), dim3(256), 0, st, m, ctx->Hrow, ctx->htri);
+    SESM_LAUNCH_CHECK();
+    SESM_HIP(hipMemcpyAsync(tri.data(), ctx->htri, sizeof(cplx) * tri.size(), hipMemcpyDeviceToHost, st));
+    SESM_HIP(hipStreamSynchronize(st));
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta0;
+    for (int j = 0; j < nv; ++j) {
+      C* col = &H[(size_t)j * (m + 1)];
+      const cplx* dv = &tri[(size_t)m_tri(j)];
+      const C* raw = &Hraw[(size_t)m_tri(j)];
+      bool same = true;
+      for (int t = 0; t <= j + 1; ++t) {
+        col[t] = C(dv[t].re, dv[t].im);
+        same = same && col[t] == raw[t];
+      }
+      mismatches += same ? 0 : 1;
+      res = rotate(col, j, cs, sn, g) / bnorm;
+    }
+    // y = R^{-1} g, x += Q y
+    std::vector<C> y(nv);
     for (int t = nv - 1; t >= 0; --t) {
-      std::complex<double> s = g[t];
-      for (int u = t + 1; u < nv; ++u) s -= H[(size_t)u * (m + 1) + t] * y[u];
-      y[t] = s / H[(size_t)t * (m + 1) + t];
+      C sm = g[t];
+      for (int u = t + 1; u < nv; ++u) sm -= H[(size_t)u * (m + 1) + t] * y[u];
+      y[t] = sm / H[(size_t)t * (m + 1) + t];
     }
     cplx* yh = ctx->hhost + (size_t)SESM_HRING * SESM_HSTRIDE;  // idle: each cycle ends synchronised
     for (int t = 0; t < nv; ++t) yh[t] = cplx{y[t].real(), y[t].imag()};
-    if (nv > 0) {
-      SESM_HIP(hipMemcpyAsync(ctx->ybuf, yh, sizeof(cplx) * nv, hipMemcpyHostToDevice, st));
-      hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), sizeof(cplx) * nv, st, N, nv, V, ldv, ctx->ybuf, x);
-      SESM_LAUNCH_CHECK();
-    }
+    SESM_HIP(hipMemcpyAsync(ctx->ybuf, yh, sizeof(cplx) * nv, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), sizeof(cplx) * nv, st, N, nv, V, ldv, ctx->ybuf, x);
+    SESM_LAUNCH_CHECK();
     SESM_HIP(hipStreamSynchronize(st));
+    total += nv;
     if (res <= tol) break;
   }
   inf.iters = total;
   inf.rel_residual = res;
+  inf.column_mismatches = mismatches;
   inf.converged = res <= tol ? 1 : 0;
   if (info) *info = inf;
   if (!inf.converged) return ctx->fail(SESM_ENOCONV, "GMRES did not reach the tolerance");

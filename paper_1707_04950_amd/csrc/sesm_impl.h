@@ -75,12 +75,14 @@ struct sesm_ctx {
   cplx* gw = nullptr;        // A u of the current Arnoldi step
   cplx* upart = nullptr;     // partial sums of the Gram-Schmidt update
   cplx* Hrow = nullptr;      // packed upper-Hessenberg matrix, row-major
+  cplx* htri = nullptr;      // its columns gathered column-major (column j: rows 0..j+1)
   int64_t Hrow_len = 0;
   int Hrow_m = -1;
   cplx* hp = nullptr;        // first-pass coefficients of the newest column
   cplx* gcoef = nullptr;     // update coefficients (s, z, z - a s)
   double* gsc = nullptr;     // step scalars
   std::vector<void*> owned;  // every device allocation made for the surface
+  bool poison = false;       // fill new allocations with NaN bytes (SESM_POISON_ALLOC set at creation)
   int64_t bytes = 0;
   // per-kernel timing (sesm_timing_enable)
   uint32_t kt_mask = 0;

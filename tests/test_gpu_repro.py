@@ -1,0 +1,95 @@
+"""Reproducibility of the GPU path and absence of reads before writes.
+
+Every kernel of the forward map and of GMRES is free of atomics and of
+data-dependent scheduling, so repeated forward maps and repeated solves on
+one context must agree bit for bit, and the Hessenberg columns streamed to
+the host during a solve must equal the device's.  With SESM_POISON_ALLOC set,
+every library buffer (and every output the binding allocates) starts as NaN:
+a value read before it was written would turn the results into NaN.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+def _golden(name):
+    return json.load(open(os.path.join(os.path.dirname(__file__), "golden", name + ".json")))
+
+
+def _set(solver, G, mode):
+    wl = W.config_grazing_wood(G["N"])
+    solver.set_surface(np.asarray(wl.a_coef), np.asarray(wl.b_coef), wl.d, wl.k, wl.alpha, wl.j, wl.A, G["N"],
+                       h=G["h"], c=G["c"], n_a=G["n_a"], gamma_frac=G["gamma_frac"], eta=G["eta"], mode=mode,
+                       L=0.5)
+
+
+def _solve_and_check(solver, G, tol):
+    mu, info = solver.solve(tol=1e-12, max_iter=3000)
+    n, e, eps = solver.efficiencies(mu)
+    err = float(np.max(np.abs(e - np.asarray(G["efficiencies"]))))
+    print("iters", info["iters"], "mismatched columns", info["column_mismatches"], "max|e - e_oracle| %.2e" % err,
+          flush=True)
+    assert info["converged"] and info["column_mismatches"] == 0
+    assert list(n) == G["orders"] and err <= tol
+    return mu, info
+
+
+def test_repeated_forward_maps_and_solves_are_bitwise_equal(torch):
+    import paper_1707_04950_amd as lib
+    from gpu_util import to_dev, to_host
+    G = _golden("grazing4096")
+    s = lib.Solver(0)
+    try:
+        for mode, tol in ((lib.MODE_ACCEL, 1e-6), (lib.MODE_DENSE, 1e-9)):
+            _set(s, G, mode)
+            mu = to_dev(torch, W.random_density(G["N"], 7))
+            ys = [to_host(s.matvec(mu)) for _ in range(4)]
+            assert all(np.array_equal(ys[0], y) for y in ys[1:])
+            mu1, i1 = _solve_and_check(s, G, tol)
+            mu2, i2 = _solve_and_check(s, G, tol)
+            assert i1["iters"] == i2["iters"]
+            assert np.array_equal(to_host(mu1), to_host(mu2))
+    finally:
+        s.close()
+
+
+def test_no_reads_before_writes(torch, monkeypatch):
+    """The same workload on a context whose buffers all start as NaN: the
+    forward map equals the one of a plain context bit for bit and the solve
+    reaches the oracle's efficiencies; dense mode first, then accelerated
+    (the second surface reuses memory the first one freed)."""
+    import paper_1707_04950_amd as lib
+    from gpu_util import to_dev, to_host
+    G = _golden("grazing4096")
+    mu = to_dev(torch, W.random_density(G["N"], 8))
+    ref = {}
+    plain = lib.Solver(0)
+    try:
+        for mode in (lib.MODE_DENSE, lib.MODE_ACCEL):
+            _set(plain, G, mode)
+            ref[mode] = to_host(plain.matvec(mu))
+    finally:
+        plain.close()
+    monkeypatch.setenv("SESM_POISON_ALLOC", "1")
+    s = lib.Solver(0)
+    try:
+        for mode, tol in ((lib.MODE_DENSE, 1e-9), (lib.MODE_ACCEL, 1e-6)):
+            _set(s, G, mode)
+            y = to_host(s.matvec(mu))
+            assert np.all(np.isfinite(y)) and np.array_equal(y, ref[mode])
+            _solve_and_check(s, G, tol)
+    finally:
+        s.close()

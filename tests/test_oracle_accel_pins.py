@@ -1,0 +1,76 @@
+"""Pins of the accelerated-operator oracle (oracle/accel.py) against facts
+outside it: exact Hankel-function fields (SciPy/AMOS) and the dense direct
+operator (oracle/dense.py, the plain definition of eq. discrete_eq).
+
+* Equivalent sources (Sec. 5.2, eq. eq_source_point): the least-squares fit to
+  the field of a source inside a cell, taken on the 3L square, reproduces that
+  field outside the square.
+* Plane waves (eqs. planewave, plwave_QR): the fit to boundary values of the
+  field of a source outside a cell reproduces it inside the cell.
+* Forward map (Algorithm 3): equals the dense operator up to the accelerator's
+  approximation error, on a geometry whose window transition is long enough
+  for that error to stay far below the tolerance (the windowed lattice kernel
+  is not a Helmholtz solution inside the window's transition zone, where the
+  equivalent-source representation is therefore not exact).
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+from scipy.special import hankel1
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+import workloads as W  # noqa: E402
+from oracle import accel, dense  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def small():
+    a, b = W.gaussian_surface(3.0, 0.4, 1.0, W.SEED_BASE + 11)
+    wl = W.Workload(name="accel-pin", d=3.0, k=2 * math.pi, theta_deg=20.0, N=240, j=8, h=0.5, A=40.0,
+                    a_coef=a, b_coef=b, L=0.5)
+    disc = dense.Discretization(wl)
+    op = accel.AccelOperator(disc, L=0.5, n_s=10, n_e=1, n_coll=60, n_plw=32)
+    return disc, op
+
+
+@pytest.mark.parametrize("lam", ["H", "V"])
+def test_equivalent_source_fit_reproduces_interior_source(small, lam):
+    disc, op = small
+    g, k, L = op.g, disc.k, op.g.L
+    src = np.random.default_rng(5).uniform(0.1 * L, 0.9 * L, 2)
+    xc = g.collocation()
+    dens = op.pinv[lam].solve(hankel1(0, k * np.hypot(xc[:, 0] - src[0], xc[:, 1] - src[1])))
+    _, _, ys = g.eq_points(lam)
+    th = np.linspace(0.0, 2 * np.pi, 50, endpoint=False)
+    pts = np.stack([0.5 * L + 2.3 * L * np.cos(th), 0.5 * L + 2.3 * L * np.sin(th)], 1)  # outside the 3L square
+    X = pts[:, None, 0] - ys[None, :, 0]
+    Y = pts[:, None, 1] - ys[None, :, 1]
+    A = np.concatenate([accel._green_terms(k, 0, 0.0, X, Y, "mono"), accel._green_terms(k, 0, 0.0, X, Y, "dip" + lam)], 1)
+    exact = hankel1(0, k * np.hypot(pts[:, 0] - src[0], pts[:, 1] - src[1]))
+    err = np.max(np.abs(A @ dens - exact)) / np.max(np.abs(exact))
+    assert err < 1e-11, err
+
+
+def test_plane_wave_fit_reproduces_exterior_source(small):
+    disc, op = small
+    k, L = disc.k, op.g.L
+    s2 = np.array([0.5 * L + 1.6 * L, 0.5 * L - 0.9 * L])  # one cell side away
+    w = op.plw_ls.solve(hankel1(0, k * np.hypot(op.xb[:, 0] - s2[0], op.xb[:, 1] - s2[1])))
+    ip = np.random.default_rng(6).uniform(0.0, L, (40, 2))
+    approx = np.exp(1j * k * (ip - op.ctr) @ op.dirs.T) @ w
+    exact = hankel1(0, k * np.hypot(ip[:, 0] - s2[0], ip[:, 1] - s2[1]))
+    err = np.max(np.abs(approx - exact)) / np.max(np.abs(exact))
+    assert err < 1e-8, err
+
+
+def test_accelerated_forward_map_matches_dense_operator(small):
+    disc, op = small
+    M = dense.operator_matrix(disc)
+    mu = W.random_density(disc.N, 1)
+    y_ref = M @ mu
+    err = np.linalg.norm(op.matvec(mu) - y_ref) / np.linalg.norm(y_ref)
+    assert err < 1e-7, err
