@@ -478,13 +478,15 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
   };
 
   using C = std::complex<double>;
+  // plain complex product (no special-value handling: the operands are finite)
+  auto mul = [](C a, C b) { return C(a.real() * b.real() - a.imag() * b.imag(), a.real() * b.imag() + a.imag() * b.real()); };
   // Givens QR of one Hessenberg column j (rows 0..j+1, in place) given the
   // rotations of the columns before it; updates g and returns |g[j+1]|
-  auto rotate = [](C* col, int j, std::vector<C>& cs, std::vector<C>& sn, std::vector<C>& g) -> double {
+  auto rotate = [&mul](C* col, int j, std::vector<C>& cs, std::vector<C>& sn, std::vector<C>& g) -> double {
     for (int t = 0; t < j; ++t) {  // previous rotations [[conj c, conj s], [-s, c]]
       const C p = col[t], q = col[t + 1];
-      col[t] = std::conj(cs[t]) * p + std::conj(sn[t]) * q;
-      col[t + 1] = -sn[t] * p + cs[t] * q;
+      col[t] = mul(std::conj(cs[t]), p) + mul(std::conj(sn[t]), q);
+      col[t + 1] = mul(cs[t], q) - mul(sn[t], p);
     }
     const C a = col[j], bb = col[j + 1];
     const double r = std::sqrt(std::norm(a) + std::norm(bb));
@@ -498,8 +500,15 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
   };
   // streamed columns: raw (for the check against the device) and rotated
   // (the running residual estimate that decides when a cycle stops)
-  std::vector<C> Hraw((size_t)m_tri(m)), H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1);
-  std::vector<cplx> tri;
+  std::vector<C>& H = ctx->gm_rot;
+  std::vector<C>& Hraw = ctx->gm_raw;
+  std::vector<cplx>& tri = ctx->gm_tri;
+  std::vector<C> cs(m), sn(m), g(m + 1);
+  auto reserve_col = [&](int j) {  // room for columns 0..j (grown geometrically, filled on use)
+    const size_t need = (size_t)m_tri(j + 1);
+    if (H.size() < need) H.resize(std::max(need, 2 * H.size()));
+    if (Hraw.size() < need) Hraw.resize(std::max(need, 2 * Hraw.size()));
+  };
   int total = 0, mismatches = 0;
   double res = 1.0;
   bool first = true;
@@ -531,7 +540,8 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
         continue;
       }
       const int j = k - 1;  // column j is final
-      C* col = &H[(size_t)j * (m + 1)];
+      reserve_col(j);
+      C* col = &H[(size_t)m_tri(j)];
       C* raw = &Hraw[(size_t)m_tri(j)];
       for (int t = 0; t <= k; ++t) raw[t] = col[t] = C(hh[t].re, hh[t].im);
       const double r = rotate(col, j, cs, sn, g);
@@ -545,34 +555,41 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
     }
     // The least-squares problem is solved from the device's own Hessenberg
     // matrix (gathered after the cycle), so the update of x does not depend
-    // on the streamed copies; a streamed column that differs from it is
-    // counted.  A step enqueued ahead of the last one used only wrote basis
-    // vectors beyond q_{nv-1}, the step buffers and a ring slot.
-    tri.resize((size_t)m_tri(nv));
+    // on the streamed copies: when every streamed column equals the device's
+    // bit for bit the rotations already applied stand, otherwise the
+    // differing columns are counted and the rotations are redone from the
+    // device's columns.  A step enqueued ahead of the last one used only
+    // wrote basis vectors beyond q_{nv-1}, the step buffers and a ring slot.
+    if (tri.size() < (size_t)m_tri(nv)) tri.resize((size_t)m_tri(nv));
     hipLaunchKernelGGL(k_hess_gather, dim3(nv), dim3(256), 0, st, m, ctx->Hrow, ctx->htri);
     SESM_LAUNCH_CHECK();
-    SESM_HIP(hipMemcpyAsync(tri.data(), ctx->htri, sizeof(cplx) * tri.size(), hipMemcpyDeviceToHost, st));
+    SESM_HIP(hipMemcpyAsync(tri.data(), ctx->htri, sizeof(cplx) * (size_t)m_tri(nv), hipMemcpyDeviceToHost, st));
     SESM_HIP(hipStreamSynchronize(st));
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta0;
+    int bad = 0;
     for (int j = 0; j < nv; ++j) {
-      C* col = &H[(size_t)j * (m + 1)];
       const cplx* dv = &tri[(size_t)m_tri(j)];
       const C* raw = &Hraw[(size_t)m_tri(j)];
       bool same = true;
-      for (int t = 0; t <= j + 1; ++t) {
-        col[t] = C(dv[t].re, dv[t].im);
-        same = same && col[t] == raw[t];
+      for (int t = 0; t <= j + 1; ++t) same = same && C(dv[t].re, dv[t].im) == raw[t];
+      bad += same ? 0 : 1;
+    }
+    if (bad) {
+      mismatches += bad;
+      std::fill(g.begin(), g.end(), 0.0);
+      g[0] = beta0;
+      for (int j = 0; j < nv; ++j) {
+        C* col = &H[(size_t)m_tri(j)];
+        const cplx* dv = &tri[(size_t)m_tri(j)];
+        for (int t = 0; t <= j + 1; ++t) col[t] = C(dv[t].re, dv[t].im);
+        res = rotate(col, j, cs, sn, g) / bnorm;
       }
-      mismatches += same ? 0 : 1;
-      res = rotate(col, j, cs, sn, g) / bnorm;
     }
     // y = R^{-1} g, x += Q y
     std::vector<C> y(nv);
     for (int t = nv - 1; t >= 0; --t) {
       C sm = g[t];
-      for (int u = t + 1; u < nv; ++u) sm -= H[(size_t)u * (m + 1) + t] * y[u];
-      y[t] = sm / H[(size_t)t * (m + 1) + t];
+      for (int u = t + 1; u < nv; ++u) sm -= mul(H[(size_t)m_tri(u) + t], y[u]);
+      y[t] = sm / H[(size_t)m_tri(t) + t];
     }
     cplx* yh = ctx->hhost + (size_t)SESM_HRING * SESM_HSTRIDE;  // idle: each cycle ends synchronised
     for (int t = 0; t < nv; ++t) yh[t] = cplx{y[t].real(), y[t].imag()};

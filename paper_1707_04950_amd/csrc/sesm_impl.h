@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <complex>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -81,6 +82,10 @@ struct sesm_ctx {
   cplx* hp = nullptr;        // first-pass coefficients of the newest column
   cplx* gcoef = nullptr;     // update coefficients (s, z, z - a s)
   double* gsc = nullptr;     // step scalars
+  // host copies of the Hessenberg columns of a cycle, packed (column j: rows
+  // 0..j+1 at j (j + 3) / 2), kept across solves so that their pages stay mapped
+  std::vector<std::complex<double>> gm_rot, gm_raw;
+  std::vector<cplx> gm_tri;
   std::vector<void*> owned;  // every device allocation made for the surface
   bool poison = false;       // fill new allocations with NaN bytes (SESM_POISON_ALLOC set at creation)
   int64_t bytes = 0;
