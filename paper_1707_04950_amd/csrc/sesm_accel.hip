@@ -100,7 +100,13 @@ int smooth5_at_least(int n) {
 // explicit pseudo-inverse (which loses the small residual when A is
 // ill-conditioned).  False if A is rank deficient.
 bool ls_qr(int m, int n, std::vector<C> A, std::vector<C>& Qh_out, std::vector<C>& R_out) {
+  // plain complex products (finite operands), so that the loops stay inline
+  auto mul = [](C a, C b) { return C(a.real() * b.real() - a.imag() * b.imag(), a.real() * b.imag() + a.imag() * b.real()); };
+  auto cmul = [](C a, C b) {  // conj(a) b
+    return C(a.real() * b.real() + a.imag() * b.imag(), a.real() * b.imag() - a.imag() * b.real());
+  };
   std::vector<std::vector<C>> V(n);
+  std::vector<C> colk(m);
   for (int k = 0; k < n; ++k) {
     double nx = 0;
     for (int i = k; i < m; ++i) nx += std::norm(A[(size_t)i * n + k]);
@@ -116,25 +122,43 @@ bool ls_qr(int m, int n, std::vector<C> A, std::vector<C>& Qh_out, std::vector<C
     for (const C& t : v) vn += std::norm(t);
     vn = std::sqrt(vn);
     for (C& t : v) t /= vn;
-    for (int c = k; c < n; ++c) {
-      C s = 0;
-      for (int i = k; i < m; ++i) s += std::conj(v[i - k]) * A[(size_t)i * n + c];
-      for (int i = k; i < m; ++i) A[(size_t)i * n + c] -= 2.0 * v[i - k] * s;
+    // columns k..n-1 of the row-major A: one sweep over the rows accumulates
+    // all their projections (independent sums), a second applies the update
+    std::vector<C> sc(n - k, C(0.0));
+    for (int i = k; i < m; ++i) {
+      const C vi = v[i - k];
+      const C* ar = &A[(size_t)i * n];
+      for (int c = k; c < n; ++c) sc[c - k] += cmul(vi, ar[c]);
     }
-    V[k] = v;
+    for (C& t : sc) t *= 2.0;
+    for (int i = k; i < m; ++i) {
+      const C vi = v[i - k];
+      C* ar = &A[(size_t)i * n];
+      for (int c = k; c < n; ++c) ar[c] -= mul(vi, sc[c - k]);
+    }
+    V[k] = std::move(v);
   }
-  // rows 0..n-1 of Q^H = H_{n-1} ... H_0 applied to the identity
-  std::vector<C> Qh((size_t)m * m, 0.0);
-  for (int i = 0; i < m; ++i) Qh[(size_t)i * m + i] = 1.0;
-  for (int k = 0; k < n; ++k) {
+  // the first n columns of Q = H_0 H_1 ... H_{n-1} (reflectors applied to
+  // the identity's columns, last reflector first), stored column by column;
+  // rows 0..n-1 of Q^H are their conjugates
+  std::vector<C> Qc((size_t)n * m, 0.0);
+  for (int c = 0; c < n; ++c) Qc[(size_t)c * m + c] = 1.0;
+  for (int k = n - 1; k >= 0; --k) {
     const std::vector<C>& v = V[k];
-    for (int c = 0; c < m; ++c) {
-      C s = 0;
-      for (int i = k; i < m; ++i) s += std::conj(v[i - k]) * Qh[(size_t)i * m + c];
-      for (int i = k; i < m; ++i) Qh[(size_t)i * m + c] -= 2.0 * v[i - k] * s;
+    for (int c0 = 0; c0 < n; c0 += 4) {  // four columns at a time: independent sums
+      const int nc = std::min(4, n - c0);
+      C s[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int i = k; i < m; ++i)
+        for (int u = 0; u < nc; ++u) s[u] += cmul(v[i - k], Qc[(size_t)(c0 + u) * m + i]);
+      for (int u = 0; u < nc; ++u) {
+        C* q = &Qc[(size_t)(c0 + u) * m];
+        const C t = 2.0 * s[u];
+        for (int i = k; i < m; ++i) q[i] -= mul(v[i - k], t);
+      }
     }
   }
-  Qh_out.assign(Qh.begin(), Qh.begin() + (size_t)n * m);
+  Qh_out.resize((size_t)n * m);
+  for (size_t t = 0; t < Qh_out.size(); ++t) Qh_out[t] = std::conj(Qc[t]);
   R_out.assign((size_t)n * n, 0.0);
   for (int r = 0; r < n; ++r) {
     if (std::abs(A[(size_t)r * n + r]) == 0) return false;
@@ -1119,46 +1143,23 @@ int sesm_accel_setup(sesm_ctx* ctx) {
   }
   const KParams K = ctx->kparams();
   const CellGeo G = cell_geo(*A);
-  // --- equivalent-source least squares: A_eq on the device, QR on the host
+  // --- equivalent-source least squares: A_eq (cell independent) on the
+  // device, its QR on the host.  The surface-only tables are launched before
+  // the factorisation so that the host work overlaps them.
   const int nrow = 4 * A->n_coll, ncol = 2 * A->n_eq;
+  std::vector<C> hA((size_t)2 * nrow * ncol);
   {
-    std::vector<cplx> qr_all;
     cplx* dA = nullptr;
-    if ((rc = sesm_alloc(ctx, (void**)&dA, sizeof(cplx) * (size_t)nrow * ncol))) return rc;
+    if ((rc = sesm_alloc(ctx, (void**)&dA, sizeof(cplx) * hA.size()))) return rc;
     for (int lam = 0; lam < 2; ++lam) {
-      hipLaunchKernelGGL(k_aeq, dim3((nrow * A->n_eq + 255) / 256), dim3(256), 0, ctx->stream, K, G, lam, dA);
+      hipLaunchKernelGGL(k_aeq, dim3((nrow * A->n_eq + 255) / 256), dim3(256), 0, ctx->stream, K, G, lam,
+                         dA + (size_t)lam * nrow * ncol);
       SESM_LAUNCH_CHECK();
-      std::vector<C> hA((size_t)nrow * ncol);
-      SESM_HIP(hipMemcpyAsync(hA.data(), dA, sizeof(cplx) * hA.size(), hipMemcpyDeviceToHost, ctx->stream));
-      SESM_HIP(hipStreamSynchronize(ctx->stream));
-      std::vector<C> Qh, Rm;
-      if (!ls_qr(nrow, ncol, hA, Qh, Rm)) return ctx->fail(SESM_EINVAL, "equivalent-source matrix is rank deficient");
-      for (const C& v : Qh) qr_all.push_back(cplx{v.real(), v.imag()});
-      for (const C& v : Rm) qr_all.push_back(cplx{v.real(), v.imag()});
     }
-    if ((rc = upload(ctx, &A->pinv, qr_all))) return rc;
+    SESM_HIP(hipMemcpyAsync(hA.data(), dA, sizeof(cplx) * hA.size(), hipMemcpyDeviceToHost, ctx->stream));
+    SESM_HIP(hipStreamSynchronize(ctx->stream));
   }
-  // --- P_q for every occupied cell
-  if ((rc = sesm_alloc(ctx, (void**)&A->p2e, sizeof(cplx) * (size_t)4 * A->n_eq * N))) return rc;
-  if (ncol > 64) return ctx->fail(SESM_EINVAL, "accelerator: at most 64 equivalent-source unknowns per set");
-  hipLaunchKernelGGL(k_p2e_setup, dim3(A->n_occ), dim3(256), sizeof(cplx) * 4 * nrow, ctx->stream, K, G,
-                     A->x0, A->y0, A->n_x, A->occ_cell, A->occ_off, A->perm, ctx->x, ctx->f, ctx->fp, A->pinv, A->p2e);
-  SESM_LAUNCH_CHECK();
   // --- global kernel tables and their spectra
-  std::vector<cplx> twxH(A->nXH), twxV(A->nXV), utwH(A->nXH), utwV(A->nXV);
-  for (int t = 0; t < A->nXH; ++t) {
-    const double ph = P.alpha * t * A->delta;
-    twxH[t] = cplx{std::cos(ph), -std::sin(ph)};
-    utwH[t] = cplx{std::cos(ph), std::sin(ph)};
-  }
-  for (int t = 0; t < A->nXV; ++t) {
-    const double ph = P.alpha * t * A->L;
-    twxV[t] = cplx{std::cos(ph), -std::sin(ph)};
-    utwV[t] = cplx{std::cos(ph), std::sin(ph)};
-  }
-  if ((rc = upload(ctx, &A->twxH, twxH)) || (rc = upload(ctx, &A->twxV, twxV)) || (rc = upload(ctx, &A->utwH, utwH)) ||
-      (rc = upload(ctx, &A->utwV, utwV)))
-    return rc;
   for (FftPlan* pl : {&A->planH, &A->planV}) {
     std::vector<cplx> tw(pl->n);
     for (int t = 0; t < pl->n; ++t) {
@@ -1197,6 +1198,47 @@ int sesm_accel_setup(sesm_ctx* ctx) {
                        A->W);
     SESM_LAUNCH_CHECK();
   }
+  // --- near-field blocks
+  if ((rc = sesm_alloc(ctx, (void**)&A->nearblk, sizeof(cplx) * (size_t)std::max<int64_t>(A->near_entries, 1))))
+    return rc;
+  hipLaunchKernelGGL(k_near_setup, dim3(A->n_occ), dim3(256), 0, ctx->stream, K, A->n_x, A->occ_cell, A->occ_off,
+                     A->perm, A->col_lo, A->col_w, A->near_off, ctx->x, ctx->f, ctx->fp, ctx->fpp, ctx->logw,
+                     A->nearblk);
+  SESM_LAUNCH_CHECK();
+  // --- QR of A_eq (both sets), while the device builds the tables above
+  {
+    std::vector<cplx> qr_all;
+    for (int lam = 0; lam < 2; ++lam) {
+      std::vector<C> Al(hA.begin() + (size_t)lam * nrow * ncol, hA.begin() + (size_t)(lam + 1) * nrow * ncol);
+      std::vector<C> Qh, Rm;
+      if (!ls_qr(nrow, ncol, std::move(Al), Qh, Rm))
+        return ctx->fail(SESM_EINVAL, "equivalent-source matrix is rank deficient");
+      for (const C& v : Qh) qr_all.push_back(cplx{v.real(), v.imag()});
+      for (const C& v : Rm) qr_all.push_back(cplx{v.real(), v.imag()});
+    }
+    if ((rc = upload(ctx, &A->pinv, qr_all))) return rc;
+  }
+  // --- P_q for every occupied cell
+  if ((rc = sesm_alloc(ctx, (void**)&A->p2e, sizeof(cplx) * (size_t)4 * A->n_eq * N))) return rc;
+  if (ncol > 64) return ctx->fail(SESM_EINVAL, "accelerator: at most 64 equivalent-source unknowns per set");
+  hipLaunchKernelGGL(k_p2e_setup, dim3(A->n_occ), dim3(256), sizeof(cplx) * 4 * nrow, ctx->stream, K, G,
+                     A->x0, A->y0, A->n_x, A->occ_cell, A->occ_off, A->perm, ctx->x, ctx->f, ctx->fp, A->pinv, A->p2e);
+  SESM_LAUNCH_CHECK();
+  // --- twist factors of the global grids
+  std::vector<cplx> twxH(A->nXH), twxV(A->nXV), utwH(A->nXH), utwV(A->nXV);
+  for (int t = 0; t < A->nXH; ++t) {
+    const double ph = P.alpha * t * A->delta;
+    twxH[t] = cplx{std::cos(ph), -std::sin(ph)};
+    utwH[t] = cplx{std::cos(ph), std::sin(ph)};
+  }
+  for (int t = 0; t < A->nXV; ++t) {
+    const double ph = P.alpha * t * A->L;
+    twxV[t] = cplx{std::cos(ph), -std::sin(ph)};
+    utwV[t] = cplx{std::cos(ph), std::sin(ph)};
+  }
+  if ((rc = upload(ctx, &A->twxH, twxH)) || (rc = upload(ctx, &A->twxV, twxV)) || (rc = upload(ctx, &A->utwH, utwH)) ||
+      (rc = upload(ctx, &A->utwV, utwV)))
+    return rc;
   // --- plane waves: d_s = (sin 2 pi s / n_plw, cos 2 pi s / n_plw), s = 1..n_plw (eq. plwave_QR)
   {
     std::vector<double> dirs(2 * A->n_plw);
@@ -1230,13 +1272,6 @@ int sesm_accel_setup(sesm_ctx* ctx) {
     }
     if ((rc = upload(ctx, &A->pplw, pv)) || (rc = upload(ctx, &A->dirs, dirs))) return rc;
   }
-  // --- near-field blocks
-  if ((rc = sesm_alloc(ctx, (void**)&A->nearblk, sizeof(cplx) * (size_t)std::max<int64_t>(A->near_entries, 1))))
-    return rc;
-  hipLaunchKernelGGL(k_near_setup, dim3(A->n_occ), dim3(256), 0, ctx->stream, K, A->n_x, A->occ_cell, A->occ_off,
-                     A->perm, A->col_lo, A->col_w, A->near_off, ctx->x, ctx->f, ctx->fp, ctx->fpp, ctx->logw,
-                     A->nearblk);
-  SESM_LAUNCH_CHECK();
   // --- work buffers
   const size_t nH = (size_t)A->nXH * A->nYH, nV = (size_t)A->nXV * A->nYV;
   if ((rc = sesm_alloc(ctx, (void**)&A->dens, sizeof(cplx) * (size_t)2 * A->n_cells * ncol)) ||
