@@ -17,7 +17,7 @@ ARCH = os.environ.get("SESM_OFFLOAD_ARCH", "gfx950")
 
 def build(verbose=False):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    cmd = [hipcc, "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-shared", "-fPIC",
+    cmd = [hipcc, "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-shared", "-fPIC", "-pthread",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-fvisibility=hidden", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
            "-o", LIB + ".tmp"] + [os.path.join(CSRC, s) for s in SOURCES]

@@ -38,6 +38,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "sesm_fft.h"
@@ -283,23 +284,27 @@ __global__ void k_aeq(KParams K, CellGeo G, int lam, cplx* A) {
 // horizontal and the vertical set.  qr holds, per set, Q^H (ncol x nrow) then
 // R (ncol x ncol), row-major.
 __global__ __launch_bounds__(256) void k_p2e_setup(KParams K, CellGeo G, double x0, double y0, int n_x,
+                                                   const int* __restrict__ chunk_q, const int* __restrict__ chunk_t0,
+                                                   int rows_per_chunk,
                                                    const int* __restrict__ occ_cell, const int* __restrict__ occ_off,
                                                    const int* __restrict__ perm, const double* __restrict__ x,
                                                    const double* __restrict__ f, const double* __restrict__ fp,
                                                    const cplx* __restrict__ qr, cplx* __restrict__ P) {
   extern __shared__ cplx sh[];  // per wave: B (nrow)
-  const int q = blockIdx.x;
+  // one workgroup per chunk of up to rows_per_chunk nodes of one cell, one node per wavefront at a time
+  const int q = chunk_q[blockIdx.x], c0 = chunk_t0[blockIdx.x];
   const int cell = occ_cell[q];
   const double ox = x0 + (cell % n_x) * G.L, oy = y0 + (cell / n_x) * G.L;
   const int off = occ_off[q], nq = occ_off[q + 1] - off;
+  const int c1 = min(nq, c0 + rows_per_chunk);
   const int nrow = 4 * G.n_coll, ncol = 2 * G.n_eq;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   cplx* B = sh + wv * nrow;
   cplx* Pq = P + (int64_t)2 * ncol * off;
   const int64_t per_set = (int64_t)ncol * nrow + (int64_t)ncol * ncol;
-  for (int t0 = 0; t0 < nq; t0 += 4) {  // uniform trip count: barriers below are block-wide
+  for (int t0 = c0; t0 < c1; t0 += 4) {  // uniform trip count: barriers below are block-wide
     const int t = t0 + wv;
-    if (t < nq) {
+    if (t < c1) {
       const int l = perm[off + t];
       for (int c = lane; c < nrow; c += 64) {
         double cx, cy;
@@ -313,11 +318,19 @@ __global__ __launch_bounds__(256) void k_p2e_setup(KParams K, CellGeo G, double 
     for (int lam = 0; lam < 2; ++lam) {  // ncol <= 64: one output row per lane
       const cplx* Qh = qr + lam * per_set;
       const cplx* Rm = Qh + (int64_t)ncol * nrow;
-      if (t < nq) {
+      if (t < c1) {
         cplx yu = cplx{0.0, 0.0};
-        if (lane < ncol) {
+        if (lane < ncol) {  // Q^H B: sixteen loads of the row in flight at a time
           const cplx* qrow = Qh + (int64_t)lane * nrow;
-          for (int c = 0; c < nrow; ++c) yu += qrow[c] * B[c];
+          int c = 0;
+          for (; c + 16 <= nrow; c += 16) {
+            cplx qv[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) qv[u] = qrow[c + u];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) yu += qv[u] * B[c + u];
+          }
+          for (; c < nrow; ++c) yu += qrow[c] * B[c];
         }
         yu = sesm_wave_backsub(Rm, ncol, yu);
         if (lane < ncol) Pq[(int64_t)t * 2 * ncol + lam * ncol + lane] = yu;
@@ -383,21 +396,26 @@ __global__ void k_wmat(KParams K, CellGeo G, int n_y, int ring, cplx* __restrict
 
 // Near-field blocks: rows = nodes of the cell, columns = the band of the cell's
 // column; entry = operator entry for the source image in the band (phase included).
-__global__ __launch_bounds__(256) void k_near_setup(KParams K, int n_x, const int* __restrict__ occ_cell,
+__global__ __launch_bounds__(256) void k_near_setup(KParams K, int n_x, const int* __restrict__ chunk_q,
+                                                    const int* __restrict__ chunk_t0, int rows_per_chunk,
+                                                    const int* __restrict__ occ_cell,
                                                     const int* __restrict__ occ_off, const int* __restrict__ perm,
                                                     const int* __restrict__ col_lo, const int* __restrict__ col_w,
                                                     const int64_t* __restrict__ near_off,
                                                     const double* __restrict__ x, const double* __restrict__ f,
                                                     const double* __restrict__ fp, const double* __restrict__ fpp,
                                                     const double* __restrict__ logw, cplx* __restrict__ blk) {
-  const int q = blockIdx.x;
+  // one workgroup per chunk of up to rows_per_chunk rows of one cell (the
+  // rows of the forward map's near-field workgroups)
+  const int q = chunk_q[blockIdx.x], t0 = chunk_t0[blockIdx.x];
   const int col = occ_cell[q] % n_x;
   const int off = occ_off[q], nq = occ_off[q + 1] - off;
+  const int nr = min(rows_per_chunk, nq - t0);
   const int lo = col_lo[col], w = col_w[col];
-  cplx* B = blk + near_off[q];
-  const int64_t tot = (int64_t)nq * w;
-  for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
-    const int t = (int)(e / w), u = (int)(e % w);
+  cplx* B = blk + near_off[q] + (int64_t)t0 * w;
+  const int tot = nr * w;
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int t = t0 + e / w, u = e % w;
     const int i = perm[off + t];
     int l = lo + u, shift = 0;
     if (l < 0) {
@@ -1201,28 +1219,45 @@ int sesm_accel_setup(sesm_ctx* ctx) {
   // --- near-field blocks
   if ((rc = sesm_alloc(ctx, (void**)&A->nearblk, sizeof(cplx) * (size_t)std::max<int64_t>(A->near_entries, 1))))
     return rc;
-  hipLaunchKernelGGL(k_near_setup, dim3(A->n_occ), dim3(256), 0, ctx->stream, K, A->n_x, A->occ_cell, A->occ_off,
+  hipLaunchKernelGGL(k_near_setup, dim3(A->n_chunks), dim3(256), 0, ctx->stream, K, A->n_x, A->chunk_q,
+                     A->chunk_t0, NEAR_ROWS, A->occ_cell, A->occ_off,
                      A->perm, A->col_lo, A->col_w, A->near_off, ctx->x, ctx->f, ctx->fp, ctx->fpp, ctx->logw,
                      A->nearblk);
   SESM_LAUNCH_CHECK();
-  // --- QR of A_eq (both sets), while the device builds the tables above
+  // --- QR of A_eq (both sets, one on a second host thread), while the device
+  // builds the tables above
   {
+    std::vector<C> Qh[2], Rm[2];
+    bool ok[2] = {false, false};
+    auto factor = [&](int lam) {
+      std::vector<C> Al(hA.begin() + (size_t)lam * nrow * ncol, hA.begin() + (size_t)(lam + 1) * nrow * ncol);
+      ok[lam] = ls_qr(nrow, ncol, std::move(Al), Qh[lam], Rm[lam]);
+    };
+    std::thread other;
+    bool threaded = true;
+    try {
+      other = std::thread(factor, 1);
+    } catch (...) {  // no second thread: factor both here
+      threaded = false;
+    }
+    factor(0);
+    if (threaded)
+      other.join();
+    else
+      factor(1);
+    if (!ok[0] || !ok[1]) return ctx->fail(SESM_EINVAL, "equivalent-source matrix is rank deficient");
     std::vector<cplx> qr_all;
     for (int lam = 0; lam < 2; ++lam) {
-      std::vector<C> Al(hA.begin() + (size_t)lam * nrow * ncol, hA.begin() + (size_t)(lam + 1) * nrow * ncol);
-      std::vector<C> Qh, Rm;
-      if (!ls_qr(nrow, ncol, std::move(Al), Qh, Rm))
-        return ctx->fail(SESM_EINVAL, "equivalent-source matrix is rank deficient");
-      for (const C& v : Qh) qr_all.push_back(cplx{v.real(), v.imag()});
-      for (const C& v : Rm) qr_all.push_back(cplx{v.real(), v.imag()});
+      for (const C& v : Qh[lam]) qr_all.push_back(cplx{v.real(), v.imag()});
+      for (const C& v : Rm[lam]) qr_all.push_back(cplx{v.real(), v.imag()});
     }
     if ((rc = upload(ctx, &A->pinv, qr_all))) return rc;
   }
   // --- P_q for every occupied cell
   if ((rc = sesm_alloc(ctx, (void**)&A->p2e, sizeof(cplx) * (size_t)4 * A->n_eq * N))) return rc;
   if (ncol > 64) return ctx->fail(SESM_EINVAL, "accelerator: at most 64 equivalent-source unknowns per set");
-  hipLaunchKernelGGL(k_p2e_setup, dim3(A->n_occ), dim3(256), sizeof(cplx) * 4 * nrow, ctx->stream, K, G,
-                     A->x0, A->y0, A->n_x, A->occ_cell, A->occ_off, A->perm, ctx->x, ctx->f, ctx->fp, A->pinv, A->p2e);
+  hipLaunchKernelGGL(k_p2e_setup, dim3(A->n_chunks), dim3(256), sizeof(cplx) * 4 * nrow, ctx->stream, K, G,
+                     A->x0, A->y0, A->n_x, A->chunk_q, A->chunk_t0, NEAR_ROWS, A->occ_cell, A->occ_off, A->perm, ctx->x, ctx->f, ctx->fp, A->pinv, A->p2e);
   SESM_LAUNCH_CHECK();
   // --- twist factors of the global grids
   std::vector<cplx> twxH(A->nXH), twxV(A->nXV), utwH(A->nXH), utwV(A->nXV);

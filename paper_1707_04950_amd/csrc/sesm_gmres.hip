@@ -21,6 +21,7 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstring>
 #include <vector>
 
 #include "sesm_impl.h"
@@ -322,6 +323,21 @@ __global__ void k_sub_from(int N, const cplx* __restrict__ b, cplx* __restrict__
   r[i] = b[i] - r[i];
 }
 
+// A signalling-NaN bit pattern that no arithmetic produces (results are
+// quiet NaNs at worst): every entry of a host ring slot holds it until the
+// step kernel's value has arrived, and again after the host has taken it.
+constexpr uint64_t kColumnSentinel = 0x7FF4A5A5A5A5A5A5ull;
+inline double column_sentinel() {
+  double v;
+  std::memcpy(&v, &kColumnSentinel, sizeof v);
+  return v;
+}
+inline bool is_column_sentinel(double v) {
+  uint64_t b;
+  std::memcpy(&b, &v, sizeof b);
+  return b == kColumnSentinel;
+}
+
 // entries of the gathered columns 0..m-1 (column j holds j + 2)
 inline int64_t m_tri(int m) { return m > 0 ? (int64_t)m * (m + 3) / 2 : 0; }
 
@@ -371,6 +387,8 @@ int ensure_workspace(sesm_ctx* ctx, int m) {
         hipHostMalloc((void**)&ctx->hflag, sizeof(int64_t) * SESM_HRING, hipHostMallocCoherent) != hipSuccess)
       return ctx->fail(SESM_ENOMEM, "hipHostMalloc failed");
     for (int t = 0; t < SESM_HRING; ++t) ctx->hflag[t] = 0;
+    double* hv = reinterpret_cast<double*>(ctx->hhost);
+    for (size_t t = 0; t < (size_t)2 * SESM_HRING * SESM_HSTRIDE; ++t) hv[t] = column_sentinel();
     SESM_HIP(hipHostGetDevicePointer((void**)&ctx->hhost_dev, ctx->hhost, 0));
     SESM_HIP(hipHostGetDevicePointer((void**)&ctx->hflag_dev, ctx->hflag, 0));
   }
@@ -411,9 +429,10 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
   hipLaunchKernelGGL(k_norm2_part, dim3(NCHUNK), dim3(256), 0, st, N, b, npart);
   hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(64), 0, st, npart, ctx->hcol);
   SESM_LAUNCH_CHECK();
-  SESM_HIP(hipMemcpyAsync(ctx->hhost, ctx->hcol, sizeof(cplx), hipMemcpyDeviceToHost, st));
+  cplx* hup = ctx->hhost + (size_t)SESM_HRING * SESM_HSTRIDE;  // the host slot for small transfers
+  SESM_HIP(hipMemcpyAsync(hup, ctx->hcol, sizeof(cplx), hipMemcpyDeviceToHost, st));
   SESM_HIP(hipStreamSynchronize(st));
-  bnorm = ctx->hhost[0].re;
+  bnorm = hup[0].re;
   SESM_HIP(hipMemsetAsync(x, 0, sizeof(cplx) * (size_t)N, st));
   sesm_solve_info inf{0, 0.0, 0};
   if (bnorm == 0.0) {
@@ -476,6 +495,28 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
     std::atomic_thread_fence(std::memory_order_acquire);
     return SESM_OK;
   };
+  // After the flag, take the n entries of a slot once none holds the sentinel
+  // any more (an entry's store may reach host memory after the flag's), then
+  // put the sentinel back.  Falls back to a stream synchronisation after 2 s.
+  auto take_slot = [&](int slot, int n, std::complex<double>* dst) -> int {
+    volatile double* hv = reinterpret_cast<volatile double*>(ctx->hhost + (size_t)slot * SESM_HSTRIDE);
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int spin = 0;; ++spin) {
+      int t = 0;
+      while (t < 2 * n && !is_column_sentinel(hv[t])) ++t;
+      if (t == 2 * n) break;
+      if ((spin & 255) == 255 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
+        SESM_HIP(hipStreamSynchronize(st));
+        for (t = 0; t < 2 * n; ++t)
+          if (is_column_sentinel(hv[t])) return ctx->fail(SESM_EHIP, "GMRES column did not reach the host");
+        break;
+      }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    for (int t = 0; t < n; ++t) dst[t] = std::complex<double>(hv[2 * t], hv[2 * t + 1]);
+    for (int t = 0; t < 2 * n; ++t) hv[t] = column_sentinel();
+    return SESM_OK;
+  };
 
   using C = std::complex<double>;
   // plain complex product (no special-value handling: the operands are finite)
@@ -523,6 +564,10 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
       SESM_LAUNCH_CHECK();
     }
     std::fill(g.begin(), g.end(), 0.0);
+    {  // no step is in flight here: clear every ring slot (the last cycle's look-ahead step filled one)
+      double* hv = reinterpret_cast<double*>(ctx->hhost);
+      for (size_t t = 0; t < (size_t)2 * SESM_HRING * SESM_HSTRIDE; ++t) hv[t] = column_sentinel();
+    }
     const int steps = std::min(m, max_iter - total);  // columns available in this cycle
     if ((rc = arnoldi(0, steps))) return rc;
     int nv = 0;
@@ -531,9 +576,10 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
       if (k + 1 <= steps && (rc = arnoldi(k + 1, steps))) return rc;  // keep the device one step ahead
       const int slot = k % SESM_HRING;
       if ((rc = wait_slot(slot))) return rc;
-      const cplx* hh = ctx->hhost + (size_t)slot * SESM_HSTRIDE;
       if (k == 0) {  // residual norm of this cycle
-        beta0 = hh[0].re;
+        std::complex<double> r0;
+        if ((rc = take_slot(slot, 1, &r0))) return rc;
+        beta0 = r0.real();
         g[0] = beta0;
         res = beta0 / bnorm;
         if (res <= tol) break;
@@ -543,7 +589,8 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
       reserve_col(j);
       C* col = &H[(size_t)m_tri(j)];
       C* raw = &Hraw[(size_t)m_tri(j)];
-      for (int t = 0; t <= k; ++t) raw[t] = col[t] = C(hh[t].re, hh[t].im);
+      if ((rc = take_slot(slot, k + 1, raw))) return rc;
+      for (int t = 0; t <= k; ++t) col[t] = raw[t];
       const double r = rotate(col, j, cs, sn, g);
       res = std::abs(g[j + 1]) / bnorm;
       nv = k;
@@ -591,7 +638,7 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
       for (int u = t + 1; u < nv; ++u) sm -= mul(H[(size_t)m_tri(u) + t], y[u]);
       y[t] = sm / H[(size_t)m_tri(t) + t];
     }
-    cplx* yh = ctx->hhost + (size_t)SESM_HRING * SESM_HSTRIDE;  // idle: each cycle ends synchronised
+    cplx* yh = hup;  // idle: each cycle ends synchronised
     for (int t = 0; t < nv; ++t) yh[t] = cplx{y[t].real(), y[t].imag()};
     SESM_HIP(hipMemcpyAsync(ctx->ybuf, yh, sizeof(cplx) * nv, hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), sizeof(cplx) * nv, st, N, nv, V, ldv, ctx->ybuf, x);
