@@ -137,7 +137,7 @@ void sesm_release_surface(sesm_ctx* ctx) {
   ctx->Mdense = nullptr;
   ctx->V = nullptr;
   ctx->V_cols = 0;
-  ctx->hcol = ctx->hpart = ctx->ybuf = ctx->wtmp = ctx->upart = ctx->gw = ctx->Hrow = ctx->htri = ctx->hp = ctx->gcoef = nullptr;
+  ctx->hcol = ctx->hpart = ctx->ybuf = ctx->wtmp = ctx->gw = ctx->Hrow = ctx->htri = ctx->hp = ctx->gcoef = nullptr;
   ctx->gsc = nullptr;
   ctx->Hrow_len = 0;
   ctx->Hrow_m = -1;

@@ -31,7 +31,6 @@ namespace {
 constexpr int VT = 4;          // basis vectors per dot-product block
 constexpr int NCHUNK = 240;    // N-chunks of the single-vector norm reduction
 constexpr int DCHUNK = 16;     // N-chunks of the multi-vector dot products
-constexpr int UCH = 64;        // basis vectors per update block
 constexpr int STEP_NT = 1024;  // threads of the one-block Arnoldi step
 
 // Offset of row r of the packed upper-Hessenberg matrix (rows 0..m, row r
@@ -207,21 +206,27 @@ __global__ __launch_bounds__(STEP_NT) void k_gm_step(int k, int m, const cplx* _
   }
 }
 
-// Workgroups [0, nb nch): partial sums of the two basis combinations,
-// up[2 ch][i] = sum_{v in chunk ch} V_v[i] cS[v], up[2 ch + 1][i] = ... cC[v],
-// over chunks of UCH vectors.  The following ceil((k+1)/4) workgroups compute
-// the first-pass coefficients of column k, one wavefront per row r:
+// Second sweep of step k, with the first-pass coefficients of column k.
+// Workgroups [0, nrb): rows 64 rb .. 64 rb + 63, one row per lane; wavefront
+// g takes the basis vectors v = g, g + 4, ... < k, so the sums
+// Q s = sum_v V_v cS[v] and Q cC = sum_v V_v cC[v] need no exchange between
+// workgroups; the four wavefronts' sums are added through LDS and the
+// workgroup forms
+//   q_k = (u - Q s) / beta into V_k (in place of u),
+//   u'  = (w - Q cC - a u) / beta into V_{k+1}.
+// The following ceil((k+1)/4) workgroups compute the first-pass coefficients
+// of column k, one wavefront per row r:
 // hp[r] = (c_r - sum_{j >= max(0, r-1)} H[r][j] cS[j]) / beta, c = (cZ, c_k).
-__global__ __launch_bounds__(256) void k_gm_update(int N, int k, int m, int nb, int nch,
-                                                   const cplx* __restrict__ V, int64_t ldv,
+constexpr int UPD_ROWS = 64, UPD_B = 8;
+__global__ __launch_bounds__(256) void k_gm_update(int N, int k, int m, int nrb, cplx* V, int64_t ldv,
                                                    const cplx* __restrict__ cS, const cplx* __restrict__ cZ,
                                                    const cplx* __restrict__ cC, const double* __restrict__ sc,
                                                    const cplx* __restrict__ Hrow, cplx* __restrict__ hp,
-                                                   cplx* __restrict__ up) {
+                                                   const cplx* __restrict__ w) {
   const int bid = blockIdx.x;
-  if (bid >= nb * nch) {
-    const int lane = threadIdx.x & 63;
-    const int r = (bid - nb * nch) * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (bid >= nrb) {
+    const int r = (bid - nrb) * 4 + wv;
     if (r > k) return;  // wave-uniform
     const int j0 = r > 0 ? r - 1 : 0;
     const cplx* hr = Hrow + hrow_off(r, m) - j0;
@@ -235,45 +240,41 @@ __global__ __launch_bounds__(256) void k_gm_update(int N, int k, int m, int nb, 
     }
     return;
   }
-  __shared__ cplx hs[2][UCH];
-  const int ch = bid / nb, ib = bid % nb;
-  const int v0 = ch * UCH, v1 = min(k, v0 + UCH);
-  if ((int)threadIdx.x < v1 - v0) {
-    hs[0][threadIdx.x] = cS[v0 + threadIdx.x];
-    hs[1][threadIdx.x] = cC[v0 + threadIdx.x];
-  }
-  __syncthreads();
-  const int i = ib * 256 + threadIdx.x;
-  if (i >= N) return;
+  __shared__ cplx red[2][4][UPD_ROWS];
+  const int i = min(bid * UPD_ROWS + lane, N - 1);  // rows past N repeat row N-1 (not stored)
   cplx s1 = cplx{0.0, 0.0}, s2 = cplx{0.0, 0.0};
-#pragma unroll 8
-  for (int v = v0; v < v1; ++v) {
+  int v = wv;
+  for (; v + 4 * (UPD_B - 1) < k; v += 4 * UPD_B) {  // UPD_B vectors' loads in flight
+    cplx x[UPD_B], a1[UPD_B], a2[UPD_B];
+#pragma unroll
+    for (int t = 0; t < UPD_B; ++t) {
+      x[t] = V[(int64_t)(v + 4 * t) * ldv + i];
+      a1[t] = cS[v + 4 * t];
+      a2[t] = cC[v + 4 * t];
+    }
+#pragma unroll
+    for (int t = 0; t < UPD_B; ++t) {
+      s1 += x[t] * a1[t];
+      s2 += x[t] * a2[t];
+    }
+  }
+  for (; v < k; v += 4) {
     const cplx x = V[(int64_t)v * ldv + i];
-    s1 += x * hs[0][v - v0];
-    s2 += x * hs[1][v - v0];
+    s1 += x * cS[v];
+    s2 += x * cC[v];
   }
-  up[(int64_t)(2 * ch) * N + i] = s1;
-  up[(int64_t)(2 * ch + 1) * N + i] = s2;
-}
-
-// q_k = (u - sum_ch up[2 ch]) / beta into V_k (in place of u),
-// u' = (w - sum_ch up[2 ch + 1] - a u) / beta into V_{k+1}
-__global__ __launch_bounds__(256) void k_gm_final(int N, int k, int nch, const cplx* __restrict__ up, cplx* V,
-                                                  int64_t ldv, const cplx* __restrict__ w,
-                                                  const double* __restrict__ sc) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= N) return;
-  const double inv = sc[0];
-  const cplx a = cplx{sc[1], sc[2]};
-  const cplx u = V[(int64_t)k * ldv + i];
-  cplx p1 = cplx{0.0, 0.0}, p2 = cplx{0.0, 0.0};
-#pragma unroll 4
-  for (int ch = 0; ch < nch; ++ch) {
-    p1 += up[(int64_t)(2 * ch) * N + i];
-    p2 += up[(int64_t)(2 * ch + 1) * N + i];
+  red[0][wv][lane] = s1;
+  red[1][wv][lane] = s2;
+  __syncthreads();
+  if (wv == 0 && bid * UPD_ROWS + lane < N) {
+    const cplx p1 = red[0][0][lane] + red[0][1][lane] + red[0][2][lane] + red[0][3][lane];
+    const cplx p2 = red[1][0][lane] + red[1][1][lane] + red[1][2][lane] + red[1][3][lane];
+    const double inv = sc[0];
+    const cplx a = cplx{sc[1], sc[2]};
+    const cplx u = V[(int64_t)k * ldv + i];
+    V[(int64_t)k * ldv + i] = inv * (u - p1);
+    V[(int64_t)(k + 1) * ldv + i] = inv * (w[i] - p2 - a * u);
   }
-  V[(int64_t)k * ldv + i] = inv * (u - p1);
-  V[(int64_t)(k + 1) * ldv + i] = inv * (w[i] - p2 - a * u);
 }
 
 // Columns 0..nv-1 of the packed Hessenberg matrix, column-major: column j
@@ -371,7 +372,6 @@ int ensure_workspace(sesm_ctx* ctx, int m) {
   if ((rc = sesm_alloc(ctx, (void**)&ctx->htri, sizeof(cplx) * (size_t)m_tri(m)))) return rc;
   ctx->Hrow_m = m;
   if (!ctx->hcol) {
-    const int nchmax = (SESM_HSTRIDE + UCH - 1) / UCH;
     if ((rc = sesm_alloc(ctx, (void**)&ctx->hcol, sizeof(cplx) * SESM_HRING * SESM_HSTRIDE))) return rc;
     if ((rc = sesm_alloc(ctx, (void**)&ctx->hpart, sizeof(cplx) * (size_t)2 * SESM_HSTRIDE * DCHUNK))) return rc;
     if ((rc = sesm_alloc(ctx, (void**)&ctx->ybuf, sizeof(cplx) * SESM_HSTRIDE))) return rc;
@@ -380,7 +380,6 @@ int ensure_workspace(sesm_ctx* ctx, int m) {
     if ((rc = sesm_alloc(ctx, (void**)&ctx->gsc, sizeof(double) * 8))) return rc;
     if ((rc = sesm_alloc(ctx, (void**)&ctx->wtmp, sizeof(cplx) * (size_t)N))) return rc;
     if ((rc = sesm_alloc(ctx, (void**)&ctx->gw, sizeof(cplx) * (size_t)N))) return rc;
-    if ((rc = sesm_alloc(ctx, (void**)&ctx->upart, sizeof(cplx) * (size_t)2 * N * nchmax))) return rc;
     // columns and their flags in coherent pinned memory, written by the step kernel
     if (hipHostMalloc((void**)&ctx->hhost, sizeof(cplx) * (SESM_HRING + 1) * SESM_HSTRIDE, hipHostMallocCoherent) !=
             hipSuccess ||
@@ -467,15 +466,13 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
     SESM_LAUNCH_CHECK();
     slot_seq[slot] = seq;
     if (full) {
-      const int nch = (k + UCH - 1) / UCH;
+      const int nrb = (N + UPD_ROWS - 1) / UPD_ROWS;
       SESM_KT_BEGIN(SESM_KT_UPDATE, st);
-      hipLaunchKernelGGL(k_gm_update, dim3(nb * nch + (k + 1 + 3) / 4), dim3(256), 0, st, N, k, m, nb, nch, V, ldv,
-                         cS, cZ, cC, ctx->gsc, ctx->Hrow, ctx->hp, ctx->upart);
+      hipLaunchKernelGGL(k_gm_update, dim3(nrb + (k + 1 + 3) / 4), dim3(256), 0, st, N, k, m, nrb, V, ldv, cS, cZ,
+                         cC, ctx->gsc, ctx->Hrow, ctx->hp, ctx->gw);
       SESM_LAUNCH_CHECK();
-      // basis, two partial vectors per chunk
-      SESM_KT_END(SESM_KT_UPDATE, st, c16 * ((double)k * N + 2.0 * nch * N));
-      hipLaunchKernelGGL(k_gm_final, dim3(nb), dim3(256), 0, st, N, k, nch, ctx->upart, V, ldv, ctx->gw, ctx->gsc);
-      SESM_LAUNCH_CHECK();
+      // basis V_0..V_{k-1}, u and w read; q_k and u' written
+      SESM_KT_END(SESM_KT_UPDATE, st, c16 * ((double)k * N + 4.0 * N));
     }
     return SESM_OK;
   };

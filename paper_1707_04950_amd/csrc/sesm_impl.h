@@ -74,7 +74,6 @@ struct sesm_ctx {
   cplx* ybuf = nullptr;      // device copy of the small LS solution
   cplx* wtmp = nullptr;      // scratch vector of length N (the right-hand side when none is given)
   cplx* gw = nullptr;        // A u of the current Arnoldi step
-  cplx* upart = nullptr;     // partial sums of the Gram-Schmidt update
   cplx* Hrow = nullptr;      // packed upper-Hessenberg matrix, row-major
   cplx* htri = nullptr;      // its columns gathered column-major (column j: rows 0..j+1)
   int64_t Hrow_len = 0;
