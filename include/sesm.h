@@ -207,14 +207,22 @@ SESM_API int sesm_diag_fft(sesm_ctx* ctx, int32_t n, int32_t rows, const sesm_c6
  * sesm_c64.  Enqueued on the context's stream. */
 SESM_API int sesm_diag_hankel(sesm_ctx* ctx, const double* x, int32_t n, sesm_c64* h0, sesm_c64* h1);
 
+/* Diagnostic: evaluate the library's own phase factor e^{it} (reduction
+ * modulo pi/2 and Taylor polynomials; used for the plane-wave exponentials of
+ * eq. planewave) at n points, valid for |t| < 1e5.  t: device array of n
+ * doubles; out: device array of n sesm_c64.  Enqueued on the context's stream. */
+SESM_API int sesm_diag_cexp(sesm_ctx* ctx, const double* t, int32_t n, sesm_c64* out);
+
 /* Per-kernel timing.  Bit i of a mask selects kernel class i. */
 enum {
   SESM_KT_LOCAL = 0,  /* near-field GEMV (intersecting + singular + 1/2 I), cell
                          equivalent-source densities (EqSources) and the partial
                          sums of the completion modes: one launch                   */
-  SESM_KT_MERGE = 1,  /* merge onto the periodic grids + local corrections          */
-  SESM_KT_FFT = 2,    /* batched FFT along x of both grids (2 per forward map)      */
-  SESM_KT_YCONV = 3,  /* convolution along y per x-frequency, both grids (1 per map) */
+  SESM_KT_MERGE = 1,  /* merge onto the periodic grids fused with their forward FFT
+                         along x (1 per forward map)                              */
+  SESM_KT_FFT = 2,    /* inverse FFT along x of both grids + untwist (1 per map)    */
+  SESM_KT_YCONV = 3,  /* convolution along y per x-frequency, both grids, and the
+                         local corrections (1 per map)                            */
   SESM_KT_CELLS = 4,  /* boundary values, plane-wave fit, surface values, modes     */
   SESM_KT_DOTS = 5,   /* GMRES: dot products of the Krylov basis with u and A u      */
   SESM_KT_UPDATE = 6, /* GMRES: partial sums of the two basis updates (+ H s)        */

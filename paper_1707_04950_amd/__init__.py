@@ -90,6 +90,7 @@ def load_library(path=LIB_PATH):
         "sesm_get_info": (ctypes.c_int, [_P, ctypes.POINTER(SurfaceInfo)]),
         "sesm_last_error": (ctypes.c_char_p, [_P]),
         "sesm_diag_hankel": (ctypes.c_int, [_P, _P, _I, _P, _P]),
+        "sesm_diag_cexp": (ctypes.c_int, [_P, _P, _I, _P]),
         "sesm_diag_accel": (ctypes.c_int, [_P, _P, _I, _P, ctypes.c_int64]),
         "sesm_diag_near": (ctypes.c_int, [_P, _P, _P]),
         "sesm_timing_enable": (ctypes.c_int, [_P, ctypes.c_uint32, _I]),
@@ -240,6 +241,13 @@ class Solver:
         rows, n = x.shape
         out = torch.empty_like(x)
         self._check(self.lib.sesm_diag_fft(self.h, n, rows, _ptr(x), _ptr(out), sign))
+        return out
+
+    def diag_cexp(self, t):
+        torch = self._torch
+        t = t.to(device=self.device, dtype=torch.float64).contiguous()
+        out = torch.empty(t.numel(), dtype=torch.complex128, device=self.device)
+        self._check(self.lib.sesm_diag_cexp(self.h, ctypes.c_void_p(t.data_ptr()), t.numel(), _ptr(out)))
         return out
 
     def diag_hankel(self, x):

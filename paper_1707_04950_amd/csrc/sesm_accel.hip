@@ -22,10 +22,11 @@
 //                        singular part eq. local_mat, 1/2 I);
 //                   (xi, zeta)^{q,lambda} = P_q^lambda mu_q   (EqSources, eq. eq_source_point);
 //                   partial sums of the completion modes      (EvalModes, eq. M_eta)
-//   k_merge         twisted merged grids                     (GlobalEqSMerge, eq. sum_eqsources)
-//                   + local corrections per cell pair         (LocalEqSMerge, LocalFFT, eq. small_convolution)
-//   k_fft_rows      FFT along x of both grids                (GlobalFFT, eq. large_convolution_per_grid)
+//   k_merge_fft     twisted merged grids, gathered straight into the FFT along x
+//                   of both grids                            (GlobalEqSMerge, eq. sum_eqsources;
+//                                                             GlobalFFT, eq. large_convolution_per_grid)
 //   k_yconv         kernel-spectrum x sources, direct in y
+//                   + local corrections per cell pair         (LocalEqSMerge, LocalFFT, eq. small_convolution)
 //   k_fft_rows      inverse FFT, untwist -> phi^all
 //   k_cells_far     boundary values - local corrections       (LocalSubtract, Combine-lambda,
 //                   -> plane-wave weights -> surface values      PlaneWaveWeights, NonIntersecting;
@@ -233,10 +234,18 @@ __device__ inline cplx sesm_wave_backsub(const cplx* __restrict__ R, int n, cplx
 // readlane; R and dinv may live in LDS.
 __device__ inline cplx sesm_wave_backsub_dinv(const cplx* R, const cplx* dinv, int n, cplx yu) {
   const int lane = threadIdx.x & 63;
+  const int lr = lane < n ? lane : n - 1;
+  // the next step's R entry and reciprocal are loaded one step ahead
+  cplx rn = R[lr * n + n - 1], dn = dinv[n - 1];
   for (int r = n - 1; r >= 0; --r) {
-    if (lane == r) yu = yu * dinv[r];
+    const cplx rc = rn, dc = dn;
+    if (r > 0) {
+      rn = R[lr * n + r - 1];
+      dn = dinv[r - 1];
+    }
+    if (lane == r) yu = yu * dc;
     const cplx xr = cplx{sesm_readlane(yu.re, r), sesm_readlane(yu.im, r)};
-    if (lane < r) yu -= R[lane * n + r] * xr;
+    if (lane < r) yu -= rc * xr;
   }
   return yu;
 }
@@ -559,13 +568,9 @@ struct MergeArgs {
   double alpha_d;
 };
 
-// Owner-computes gather of the merged grids (eq. sum_eqsources), with the
-// quasi-periodic wrap phase and the twist exp(-i alpha x) fused.
-// g[kind][gy][gx], kind 0 = monopole density xi, 1 = dipole density zeta.
-//
-// Workgroups from merge_blocks on compute the local corrections instead
-// (eq. small_convolution with the punctured kernel) for pairs p = (cell q,
-// occupied cell rc of its near columns) at offset o:
+// Local corrections (eq. small_convolution with the punctured kernel), by the
+// workgroups from merge_blocks on of the y-convolution launch, for pairs
+// p = (cell q, occupied cell rc of its near columns) at offset o:
 // corr[p][b] = e^{i alpha d W} sum_t W_o[t][b] dens_lambda(b)[rc][t].
 struct CorrArgs {
   int n_groups, n_bdry, n_bH, n_eq, n_cells, merge_blocks;
@@ -645,23 +650,14 @@ __device__ inline void local_corr_group(const CorrArgs& C, const cplx* __restric
   }
 }
 
-__global__ __launch_bounds__(256) void k_merge(MergeArgs M, CorrArgs C, const cplx* __restrict__ dens,
-                                               const cplx* __restrict__ twH, const cplx* __restrict__ twV,
-                                               cplx* __restrict__ gH, cplx* __restrict__ gV) {
-  if ((int)blockIdx.x >= C.merge_blocks) {
-    local_corr_group(C, dens);
-    return;
-  }
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  const int nH = M.nXH * M.nYH, nV = M.nXV * M.nYV;
-  if (e >= nH + nV) return;
-  // up to six contributing cell sides per grid point (2 sides x 3 neighbours);
-  // addresses and masks first, then all loads in flight together
-  const bool onH = e < nH;
-  const int ee = onH ? e : e - nH;
-  const int nXg = onH ? M.nXH : M.nXV;
-  const int gy = ee / nXg, gx = ee % nXg;
-  const cplx* D = onH ? dens : dens + (int64_t)M.n_cells * 2 * M.n_eq;
+// Merged value of grid point (gy, gx) of one grid (eq. sum_eqsources): the
+// densities of kind `kind` (0 = monopole xi, 1 = dipole zeta) of the up to six
+// cell sides sharing the point (2 sides x 3 neighbours), with the
+// quasi-periodic phase of a wrapped column and the twist exp(-i alpha x)
+// (factor tw[gx]).  All candidate loads are issued before any is used.
+__device__ inline cplx merge_point(const MergeArgs M, const cplx* __restrict__ dens, const cplx* __restrict__ tw,
+                                   cplx php, bool onH, int kind, int gy, int gx) {
+  const cplx* D = (onH ? dens : dens + (int64_t)M.n_cells * 2 * M.n_eq) + kind * M.n_eq;
   const cplx* src[6];
   int wr[6];
   bool ok[6];
@@ -686,35 +682,36 @@ __global__ __launch_bounds__(256) void k_merge(MergeArgs M, CorrArgs C, const cp
       wr[id] = Wr;
       src[id] = ok[id] ? D + (int64_t)(row * M.n_x + c) * 2 * M.n_eq + side * M.n_side + pos + M.n_e : D;
     }
-  cplx va[6], vb[6];
+  cplx va[6];
 #pragma unroll
-  for (int id = 0; id < 6; ++id) {
-    va[id] = src[id][0];
-    vb[id] = src[id][M.n_eq];
-  }
-  const cplx php = cexp_i(M.alpha_d), phm = conj(php);
-  cplx xi = cplx{0.0, 0.0}, ze = cplx{0.0, 0.0};
+  for (int id = 0; id < 6; ++id) va[id] = src[id][0];
+  const cplx twx = tw[gx];
+  const cplx phm = conj(php);  // php = e^{i alpha d}
+  cplx acc = cplx{0.0, 0.0};
 #pragma unroll
   for (int id = 0; id < 6; ++id) {
     if (!ok[id]) continue;
-    cplx a = va[id], b = vb[id];
-    if (wr[id] != 0) {
-      const cplx ph = wr[id] > 0 ? php : phm;
-      a = ph * a;
-      b = ph * b;
-    }
-    xi += a;
-    ze += b;
+    cplx v = va[id];
+    if (wr[id] != 0) v = (wr[id] > 0 ? php : phm) * v;
+    acc += v;
   }
-  if (onH) {
-    const cplx t = twH[gx];
-    gH[ee] = xi * t;
-    gH[(int64_t)nH + ee] = ze * t;
-  } else {
-    const cplx t = twV[gx];
-    gV[ee] = xi * t;
-    gV[(int64_t)nV + ee] = ze * t;
-  }
+  return acc * twx;
+}
+
+// Merge and forward x-FFT in one launch: the FFT workgroups of job jh (H grid,
+// rows [kind][gy]) and then jv (V grid) gather their rows' merged values
+// directly from the cell densities instead of reading a stored grid.
+__global__ __launch_bounds__(1024) void k_merge_fft(MergeArgs M, const cplx* __restrict__ dens,
+                                                    const cplx* __restrict__ twH, const cplx* __restrict__ twV,
+                                                    FftJob jh, FftJob jv) {
+  const bool onH = (int)blockIdx.x < jh.nblocks;
+  const FftJob J = onH ? jh : jv;
+  const int blk = onH ? blockIdx.x : blockIdx.x - jh.nblocks;
+  const int nY = onH ? M.nYH : M.nYV;
+  const cplx* tw = onH ? twH : twV;
+  const cplx php = cexp_i(M.alpha_d);
+  const MergeArgs Mv = M;
+  sesm_fft_block(J, blk, -1, [=](int r, int i) { return merge_point(Mv, dens, tw, php, onH, r / nY, r % nY, i); });
 }
 
 // One grid of the y-direction convolution.
@@ -726,7 +723,8 @@ struct YConvJob {
 };
 
 // phi_hat[t][kx] = sum_t' spec0[t-t'+nY-1][kx] g0[t'][kx] + spec1[...] g1[t'][kx].
-// Workgroups [0, hblocks) serve grid h, the rest grid v.  Short grids
+// Workgroups [0, hblocks) serve grid h, those up to C.merge_blocks grid v,
+// and the rest compute the local corrections (above).  Short grids
 // (nY <= 32) take 8 x-frequencies per workgroup (32 threads each); taller
 // grids take one, with the sum over t' split in YC_SPLIT parts reduced in LDS.
 // The columns (sources and kernel spectra) are gathered row-wise (coalesced
@@ -737,8 +735,13 @@ inline size_t yconv_lds(int nY) {
   const int per = 6 * nY - 2;
   return sizeof(cplx) * (nY <= 32 ? (size_t)YC_KPB * per : (size_t)per + YC_SPLIT * nY);
 }
-__global__ __launch_bounds__(256) void k_yconv(YConvJob h, YConvJob v, int hblocks) {
+__global__ __launch_bounds__(256) void k_yconv(YConvJob h, YConvJob v, int hblocks, CorrArgs C,
+                                               const cplx* __restrict__ dens) {
   extern __shared__ cplx col[];
+  if ((int)blockIdx.x >= C.merge_blocks) {  // the local corrections share the launch
+    local_corr_group(C, dens);
+    return;
+  }
   const bool first = (int)blockIdx.x < hblocks;
   const YConvJob& J = first ? h : v;
   const int b = first ? blockIdx.x : blockIdx.x - hblocks;
@@ -805,7 +808,7 @@ struct FarArgs {
 
 // One block per occupied cell: boundary values of phi^all (H on horizontal
 // sides incl. corners, V on vertical sides), minus the equivalent sources of
-// the near columns (local corrections, from k_merge), plane-wave weights,
+// the near columns (local corrections, from k_yconv), plane-wave weights,
 // surface values, plus the completion modes D_M (partial sums from
 // k_local_apply).  Dynamic LDS: the plane-wave factors ((Q^H)^T, R, 1/diag R),
 // the cell's nodes and their values.  Each phase keeps its global loads
@@ -877,8 +880,16 @@ __global__ __launch_bounds__(256) void k_cells_far(FarArgs A, KParams K, const i
   // phase 3: plane-wave weights, least squares R w = Q^H b (eq. plwave_QR), on wavefront 0
   if (wv == 0) {
     cplx yu = cplx{0.0, 0.0};
-    if (lane < A.n_plw)
-      for (int b = 0; b < A.n_bdry; ++b) yu += pf[b * A.n_plw + lane] * bv[b];
+    if (lane < A.n_plw) {  // Q^H b, four independent partial sums
+      cplx y4[4] = {cplx{0.0, 0.0}, cplx{0.0, 0.0}, cplx{0.0, 0.0}, cplx{0.0, 0.0}};
+      int b = 0;
+      for (; b + 4 <= A.n_bdry; b += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) y4[u] += pf[(b + u) * A.n_plw + lane] * bv[b + u];
+      }
+      for (; b < A.n_bdry; ++b) y4[0] += pf[b * A.n_plw + lane] * bv[b];
+      yu = (y4[0] + y4[1]) + (y4[2] + y4[3]);
+    }
     const cplx* Rs = pf + A.n_bdry * A.n_plw;
     yu = sesm_wave_backsub_dinv(Rs, Rs + A.n_plw * A.n_plw, A.n_plw, yu);
     if (lane < A.n_plw) wv_sh[lane] = yu;
@@ -903,7 +914,7 @@ __global__ __launch_bounds__(256) void k_cells_far(FarArgs A, KParams K, const i
     const int t = t0 + slot;
     cplx sv = cplx{0.0, 0.0};
     if (t < nq && u < nd) {
-      const cplx e = cexp_i(dxu * (xs[t] - ccx) + dyu * (xs[A.max_q + t] - ccy));
+      const cplx e = cexp_i_reduced(dxu * (xs[t] - ccx) + dyu * (xs[A.max_q + t] - ccy));
       sv = wa * e + wb * conj(e);
     }
     if (UPL == 16) {
@@ -1154,10 +1165,10 @@ int sesm_accel_setup(sesm_ctx* ctx) {
         (rc = upload(ctx, &A->plist, plist)) ||
         (rc = sesm_alloc(ctx, (void**)&A->corr, sizeof(cplx) * (size_t)std::max(1, A->n_pairs) * A->n_bdry)))
       return rc;
-    const size_t lds = corr_lds(A->n_eq, A->n_bdry);
+    const size_t lds = std::max(std::max(yconv_lds(A->nYH), yconv_lds(A->nYV)), corr_lds(A->n_eq, A->n_bdry));
     if (lds > 140 * 1024) return ctx->fail(SESM_EINVAL, "accelerator: correction matrices exceed the LDS of a workgroup");
     if (lds > 64 * 1024)
-      SESM_HIP(hipFuncSetAttribute((const void*)k_merge, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      SESM_HIP(hipFuncSetAttribute((const void*)k_yconv, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   }
   const KParams K = ctx->kparams();
   const CellGeo G = cell_geo(*A);
@@ -1343,17 +1354,19 @@ static MatvecBytes matvec_bytes(const sesm_ctx* ctx) {
   B.local = c * (double)A->near_entries + N * (2.0 * c + 4.0) + 8.0 * A->n_chunks + 16.0 * A->n_occ +
             c * nout * N + A->n_occ * (c * nout + 12.0) +
             (ctx->P.nU > 0 ? N * 24.0 + c * ctx->P.nU * NCH_MODES : 0.0);
-  // densities + grids (xi, zeta) + twist factors; local corrections: correction
-  // matrices, pair tables, corrections written
-  B.merge = dens + c * 2.0 * (nH + nV) + c * (A->nXH + A->nXV) + c * (double)A->n_off * ns2 * A->n_bdry +
-            A->n_pairs * (12.0 + c) + 12.0 * A->n_groups + c * (double)A->n_pairs * A->n_bdry;
-  // rows in + rows out (+ twiddle table; untwist factors on the inverse transforms)
-  B.fftH0 = c * (2.0 * 2.0 * A->nYH * A->nXH + A->nXH);
+  // merge + forward FFT: densities, twist factors and twiddles in, both
+  // transformed grids (xi, zeta) out
+  B.merge = dens + c * 2.0 * (A->nXH + A->nXV) + c * 2.0 * (nH + nV);
+  // inverse FFT: rows in + rows out, twiddle table, untwist factors
   B.fftH1 = c * (2.0 * A->nYH * A->nXH + 2.0 * A->nXH);
-  B.fftV0 = c * (2.0 * 2.0 * A->nYV * A->nXV + A->nXV);
   B.fftV1 = c * (2.0 * A->nYV * A->nXV + 2.0 * A->nXV);
-  // spectra of both grids in, both kernel spectra, one output grid
-  B.yconvH = c * (2.0 * nH + 2.0 * (2.0 * A->nYH - 1) * A->nXH + nH);
+  B.fftH0 = B.fftV0 = 0.0;
+  // spectra of both grids in, both kernel spectra, one output grid; local
+  // corrections (correction matrices, densities, pair tables, corrections out)
+  // counted with the H grid
+  B.yconvH = c * (2.0 * nH + 2.0 * (2.0 * A->nYH - 1) * A->nXH + nH) + dens +
+             c * (double)A->n_off * ns2 * A->n_bdry + A->n_pairs * (12.0 + c) + 12.0 * A->n_groups +
+             c * (double)A->n_pairs * A->n_bdry;
   B.yconvV = c * (2.0 * nV + 2.0 * (2.0 * A->nYV - 1) * A->nXV + nV);
   // local corrections, phi grids, plane-wave QR, directions, cell and pair
   // tables, node coordinates and index, y read and written, mode sums
@@ -1407,28 +1420,26 @@ static int accel_matvec_impl(sesm_ctx* ctx, const cplx* mu, cplx* y, bool keep_f
   SESM_KT_END(SESM_KT_LOCAL, st, B.local);
   MergeArgs M{A->n_x, A->n_y, A->n_s, A->n_e, A->n_side, A->n_eq, A->n_cells,
               A->nXH, A->nYH, A->nXV, A->nYV, P.alpha * P.d};
-  const int ng = A->nXH * A->nYH + A->nXV * A->nYV;
-  const int mb = (ng + 255) / 256;
-  CorrArgs CA{A->n_groups, A->n_bdry, A->n_bH,   A->n_eq,   A->n_cells, mb,   A->grp_o,
-              A->grp_start, A->grp_n, A->plist, A->grp_rc, A->grp_ph, A->W,   A->corr};
+  // merge + forward FFT along x of both grids (rows [kind][gy])
   SESM_KT_BEGIN(SESM_KT_MERGE, st);
-  hipLaunchKernelGGL(k_merge, dim3(mb + A->n_groups), dim3(256), corr_lds(A->n_eq, A->n_bdry), st, M, CA, A->dens,
-                     A->twxH, A->twxV, A->gH, A->gV);
-  SESM_LAUNCH_CHECK();
+  {
+    const FftJob jh = sesm_fft_job(A->planH, 2 * A->nYH, nullptr, A->fH, nullptr, nullptr, 1.0);
+    const FftJob jv = sesm_fft_job(A->planV, 2 * A->nYV, nullptr, A->fV, nullptr, nullptr, 1.0);
+    hipLaunchKernelGGL(k_merge_fft, dim3(jh.nblocks + jv.nblocks), dim3(1024), 0, st, M, A->dens, A->twxH, A->twxV,
+                       jh, jv);
+    SESM_LAUNCH_CHECK();
+  }
   SESM_KT_END(SESM_KT_MERGE, st, B.merge);
-  // both grids in each launch: forward FFT along x, y convolution, inverse FFT + untwist
-  SESM_KT_BEGIN(SESM_KT_FFT, st);
-  if ((rc = fft_launch(ctx, st, sesm_fft_job(A->planH, 2 * A->nYH, A->gH, A->fH, nullptr, nullptr, 1.0),
-                       sesm_fft_job(A->planV, 2 * A->nYV, A->gV, A->fV, nullptr, nullptr, 1.0), -1)))
-    return rc;
-  SESM_KT_END(SESM_KT_FFT, st, B.fftH0 + B.fftV0);
+  // y convolution of both grids, with the local corrections in the same launch
   SESM_KT_BEGIN(SESM_KT_YCONV, st);
   {
     const YConvJob yh{A->nXH, A->nYH, A->specH, A->fH, A->gH}, yv{A->nXV, A->nYV, A->specV, A->fV, A->gV};
     const int hb = (A->nXH + yconv_kpb(A->nYH) - 1) / yconv_kpb(A->nYH);
     const int vb = (A->nXV + yconv_kpb(A->nYV) - 1) / yconv_kpb(A->nYV);
-    const size_t lds = std::max(yconv_lds(A->nYH), yconv_lds(A->nYV));
-    hipLaunchKernelGGL(k_yconv, dim3(hb + vb), dim3(256), lds, st, yh, yv, hb);
+    const CorrArgs CA{A->n_groups, A->n_bdry, A->n_bH,   A->n_eq,   A->n_cells, hb + vb,  A->grp_o,
+                      A->grp_start, A->grp_n, A->plist, A->grp_rc, A->grp_ph, A->W,      A->corr};
+    const size_t lds = std::max(std::max(yconv_lds(A->nYH), yconv_lds(A->nYV)), corr_lds(A->n_eq, A->n_bdry));
+    hipLaunchKernelGGL(k_yconv, dim3(hb + vb + A->n_groups), dim3(256), lds, st, yh, yv, hb, CA, A->dens);
     SESM_LAUNCH_CHECK();
   }
   SESM_KT_END(SESM_KT_YCONV, st, B.yconvH + B.yconvV);

@@ -84,6 +84,12 @@ __global__ void k_diag_hankel(int n, const double* __restrict__ x, cplx* h0, cpl
   h1[i] = b;
 }
 
+__global__ void k_diag_cexp(int n, const double* __restrict__ t, cplx* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[i] = cexp_i_reduced(t[i]);
+}
+
 double binom(int n, int m) {
   double r = 1.0;
   for (int t = 1; t <= m; ++t) r = r * (double)(n - m + t) / (double)t;
@@ -471,13 +477,23 @@ int sesm_diag_hankel(sesm_ctx* ctx, const double* x, int32_t n, sesm_c64* h0, se
   return SESM_OK;
 }
 
+int sesm_diag_cexp(sesm_ctx* ctx, const double* t, int32_t n, sesm_c64* out) {
+  if (!ctx) return SESM_EINVAL;
+  if (!t || !out || n < 0) return ctx->fail(SESM_EINVAL, "bad args");
+  if (n == 0) return SESM_OK;
+  SESM_HIP(hipSetDevice(ctx->device));
+  hipLaunchKernelGGL(k_diag_cexp, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, n, t, (cplx*)out);
+  SESM_LAUNCH_CHECK();
+  return SESM_OK;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
 // per-kernel timing
 
 static const char* const kKtNames[SESM_KT_COUNT] = {
-    "k_local_apply", "k_merge", "k_fft_rows",    "k_yconv",    "k_cells_far",
+    "k_local_apply", "k_merge_fft", "k_fft_rows",    "k_yconv",    "k_cells_far",
     "k_gm_dots",     "k_gm_update",   "k_gemv_rows"};
 
 static int kt_fold(sesm_ctx* ctx, KTimer& T) {

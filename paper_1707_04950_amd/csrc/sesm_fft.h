@@ -34,9 +34,11 @@ inline bool sesm_fft_factor(int n, FftPlan* p) {
   return n == 1;
 }
 
+// radices packed three bits each, pass s in bits 3s..3s+2 (kept free of
+// arrays so that a job copied into registers needs no private memory)
 struct FftArgs {
   int n, nrad;
-  int rad[SESM_FFT_MAXRAD];
+  uint64_t radcode;
 };
 
 // Radix-R butterflies y_u = sum_q x_q w^{uq}, w = exp(sign 2 pi i / R).
@@ -117,33 +119,35 @@ struct FftJob {
   double scale;
 };
 
-// Workgroups [0, j0.nblocks) run job j0, the next j1.nblocks run job j1 (two
-// grids of different lengths in one launch).
-__global__ __launch_bounds__(1024) void k_fft_rows(FftJob j0, FftJob j1, int sign) {
+// The transform of one workgroup's rows of job J: the rows' elements come
+// from load(row, col) (row of the job, column 0..n-1), two per thread in
+// flight; the passes run in LDS; out = scale * transform . post.
+template <class Loader>
+__device__ inline void sesm_fft_block(const FftJob J, int blk, int sign, Loader load) {
   __shared__ cplx buf[2][SESM_FFT_MAXN];
-  const bool first = (int)blockIdx.x < j0.nblocks;
-  const FftJob& J = first ? j0 : j1;
-  const int blk = first ? blockIdx.x : blockIdx.x - j0.nblocks;
   const int n = J.A.n;
   const int r0 = blk * J.rpb;
   const int nr = min(J.rpb, J.nrows - r0);
   const cplx* __restrict__ tw = J.tw;
   cplx* a = buf[0];
   cplx* b = buf[1];
-  for (int e0 = threadIdx.x; e0 < nr * n; e0 += 2 * blockDim.x) {  // two loads in flight per thread
+  for (int e0 = threadIdx.x; e0 < nr * n; e0 += 2 * blockDim.x) {  // two elements in flight per thread
     cplx v[2];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) v[u] = J.in[(int64_t)r0 * n + min(e0 + u * (int)blockDim.x, nr * n - 1)];
+    for (int u = 0; u < 2; ++u) {
+      const int e = min(e0 + u * (int)blockDim.x, nr * n - 1);
+      v[u] = load(r0 + e / n, e % n);
+    }
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int e = e0 + u * blockDim.x;
-      if (e < nr * n) a[e] = J.pre ? v[u] * J.pre[e % n] : v[u];
+      if (e < nr * n) a[e] = v[u];
     }
   }
   __syncthreads();
   int p = 1;
   for (int s = 0; s < J.A.nrad; ++s) {
-    const int R = J.A.rad[s];
+    const int R = (int)((J.A.radcode >> (3 * s)) & 7u);
     const int step = n / (p * R);
     switch (R) {
       case 4: sesm_fft_pass<4>(a, b, n, nr, p, step, tw, sign); break;
@@ -165,11 +169,27 @@ __global__ __launch_bounds__(1024) void k_fft_rows(FftJob j0, FftJob j1, int sig
   }
 }
 
+// Workgroups [0, j0.nblocks) run job j0, the next j1.nblocks run job j1 (two
+// grids of different lengths in one launch); rows read from in (times pre).
+__global__ __launch_bounds__(1024) void k_fft_rows(FftJob j0, FftJob j1, int sign) {
+  const bool first = (int)blockIdx.x < j0.nblocks;
+  const FftJob J = first ? j0 : j1;
+  const int blk = first ? blockIdx.x : blockIdx.x - j0.nblocks;
+  const int n = J.A.n;
+  const cplx* in = J.in;
+  const cplx* pre = J.pre;
+  sesm_fft_block(J, blk, sign, [=](int r, int i) {
+    const cplx v = in[(int64_t)r * n + i];
+    return pre ? v * pre[i] : v;
+  });
+}
+
 inline FftArgs sesm_fft_args(const FftPlan& p) {
   FftArgs A;
   A.n = p.n;
   A.nrad = p.nrad;
-  for (int t = 0; t < SESM_FFT_MAXRAD; ++t) A.rad[t] = t < p.nrad ? p.rad[t] : 1;
+  A.radcode = 0;
+  for (int t = 0; t < p.nrad; ++t) A.radcode |= (uint64_t)p.rad[t] << (3 * t);
   return A;
 }
 

@@ -125,8 +125,8 @@ def test_kernel_timing_counts_and_bytes(torch, solver, case):
     solver.timing_enable((1 << lib.KT_COUNT) - 1)
     solver.matvec(mu)
     st = solver.timing_read()
-    assert [st[k]["launches"] for k in ("k_local_apply", "k_merge", "k_fft_rows", "k_yconv",
-                                        "k_cells_far")] == [1, 1, 2, 1, 1]
+    assert [st[k]["launches"] for k in ("k_local_apply", "k_merge_fft", "k_fft_rows", "k_yconv",
+                                        "k_cells_far")] == [1, 1, 1, 1, 1]
     # the stored near-field blocks dominate the first kernel's bytes
     assert 16.0 * inf["near_entries"] < st["k_local_apply"]["bytes"] < 16.0 * inf["near_entries"] + 2e3 * disc.N
     assert all(r["total_ms"] > 0 for r in st.values() if r["launches"])
@@ -141,7 +141,7 @@ def test_kernel_timing_counts_and_bytes(torch, solver, case):
     for _ in range(7):
         solver.matvec(mu)
     st = solver.timing_read()
-    assert st["k_local_apply"]["launches"] == 3 and st["k_merge"]["launches"] == 0
+    assert st["k_local_apply"]["launches"] == 3 and st["k_merge_fft"]["launches"] == 0
     solver.timing_enable(0)
     solver.matvec(mu)
     assert solver.timing_read()["k_gm_dots"]["launches"] == 0

@@ -2,6 +2,8 @@
 
 * The library's own mixed-radix FFT (Sec. 5.5.1, periodic grid direction)
   against NumPy's FFT, for lengths exercising every radix and row batching.
+* The library's own phase factor e^{it} (plane-wave exponentials) against
+  NumPy's, to a few units in the last place.
 * Efficiencies are physical quantities: the accelerated solution must give the
   oracle's efficiencies whatever the method's free parameters (shift h, cell
   side L, equivalent-source density n_s), within the accelerator tolerance.
@@ -51,6 +53,21 @@ def test_fft_rejects_bad_lengths(torch, solver):
     x = torch.zeros((2, 7), dtype=torch.complex128)
     with pytest.raises(lib.SesmError):
         solver.diag_fft(x)  # 7 is not 5-smooth
+
+
+def test_own_phase_factor_matches_numpy(torch, solver):
+    """The library's e^{it} (reduction modulo pi/2, Taylor polynomials) against
+    numpy at dense small arguments, near multiples of pi/4, and large ones."""
+    rng = np.random.default_rng(17)
+    k = np.arange(-400, 401)
+    t = np.concatenate([np.linspace(-8.0, 8.0, 20001), k * (np.pi / 4), k * (np.pi / 4) + 1e-9,
+                        rng.uniform(-1e4, 1e4, 20000), [0.0, -0.0, 1e-300, 5e-324, 1e-8, -1e-8]])
+    got = solver.diag_cexp(torch.from_numpy(t)).cpu().numpy()
+    ref = np.exp(1j * t)
+    err = np.max(np.abs(got - ref))
+    print("max |e^{it} - numpy| %.2e" % err)
+    assert err <= 6e-16
+    assert np.all(np.abs(np.abs(got) - 1.0) <= 4e-16)
 
 
 @pytest.mark.parametrize("kw", [dict(h=0.85), dict(h=0.6), dict(L=0.4), dict(n_side=12)])
