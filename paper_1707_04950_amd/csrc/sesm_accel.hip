@@ -481,30 +481,61 @@ __global__ __launch_bounds__(LOC_NT) void k_local_apply(KParams K, LocalArgs L, 
                                                         cplx* __restrict__ y) {
   __shared__ cplx red[LOC_NT];
   __shared__ cplx rs[NEAR_ROWS][LOC_NT / 64];  // near-field row sums per wavefront
+  __shared__ cplx mus[LOC_NT];                 // EqSources: staged mu of the cell
+  __shared__ cplx gsum[LOC_NT / 32][128];      // EqSources: per-group sums
   int b = blockIdx.x;
   if (b < L.n_occ) {
+    // EqSources of cell q: dens[o] = sum_t P[t][o] mu_t.  Lane l of each
+    // 32-lane group holds outputs 4l..4l+3 (a 64-byte piece of a row of P);
+    // the 8 groups take every 8th node, four nodes' loads in flight; the
+    // cell's mu values are staged in LDS 256 at a time, and the groups'
+    // sums are added in LDS in a fixed order.
+    static_assert(LOC_NT == 256, "eight groups of 32 lanes");
+    constexpr int OPL = 4, GL = 32, NG = LOC_NT / GL;
     const int q = b;
-    const int nout = 4 * L.n_eq;
-    const int OW = nout <= 64 ? 64 : (nout <= 128 ? 128 : 256);
-    const int G = LOC_NT / OW, g = threadIdx.x / OW, oo0 = threadIdx.x % OW;
+    const int nout = 4 * L.n_eq;  // <= 128 = GL OPL
+    const int g = threadIdx.x / GL, l = threadIdx.x % GL;
     const int cell = L.occ_cell[q];
     const int off = L.occ_off[q], nq = L.occ_off[q + 1] - off;
-    for (int ob = 0; ob < nout; ob += OW) {
-      const int o = ob + oo0;
-      cplx acc = cplx{0.0, 0.0};
-      if (o < nout) {
-        const cplx* pr = L.P + (int64_t)off * nout + o;
-#pragma unroll 4
-        for (int t = g; t < nq; t += G) acc += pr[(int64_t)t * nout] * mu[L.perm[off + t]];
-      }
-      red[threadIdx.x] = acc;
+    cplx acc[OPL];
+#pragma unroll
+    for (int j = 0; j < OPL; ++j) acc[j] = cplx{0.0, 0.0};
+    const int oc = min(OPL * l, nout - OPL);  // lanes past the row repeat its last piece (not stored)
+    for (int c0 = 0; c0 < nq; c0 += LOC_NT) {
+      const int nc = min(LOC_NT, nq - c0);
       __syncthreads();
-      if (g == 0 && o < nout) {
-        for (int gg = 1; gg < G; ++gg) acc += red[gg * OW + oo0];
-        const int lam = o / (2 * L.n_eq), oo = o % (2 * L.n_eq);
-        L.dens[((int64_t)lam * L.n_cells + cell) * 2 * L.n_eq + oo] = acc;
-      }
+      if ((int)threadIdx.x < nc) mus[threadIdx.x] = mu[L.perm[off + c0 + threadIdx.x]];
       __syncthreads();
+      const cplx* pr = L.P + (int64_t)(off + c0) * nout + oc;
+      int t = g;
+      for (; t + 3 * NG < nc; t += 4 * NG) {
+        cplx v[4][OPL];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int j = 0; j < OPL; ++j) v[u][j] = pr[(int64_t)(t + u * NG) * nout + j];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const cplx m = mus[t + u * NG];
+#pragma unroll
+          for (int j = 0; j < OPL; ++j) acc[j] += v[u][j] * m;
+        }
+      }
+      for (; t < nc; t += NG) {
+        const cplx m = mus[t];
+#pragma unroll
+        for (int j = 0; j < OPL; ++j) acc[j] += pr[(int64_t)t * nout + j] * m;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < OPL; ++j) gsum[g][OPL * l + j] = acc[j];
+    __syncthreads();
+    if ((int)threadIdx.x < nout) {
+      const int o = threadIdx.x;
+      cplx sm = gsum[0][o];
+      for (int gg = 1; gg < NG; ++gg) sm += gsum[gg][o];
+      const int lam = o / (2 * L.n_eq), oo = o % (2 * L.n_eq);
+      L.dens[((int64_t)lam * L.n_cells + cell) * 2 * L.n_eq + oo] = sm;
     }
     return;
   }
