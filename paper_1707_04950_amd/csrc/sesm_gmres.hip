@@ -110,17 +110,17 @@ __global__ __launch_bounds__(256) void k_gm_dots(int N, int nv, const cplx* __re
 
 // Arnoldi step k (one workgroup): reduce the dot products of k_gm_dots over
 // V_0..V_k (V_k = u), then beta, the final column k-1 (hp + s, beta) into the
-// packed Hessenberg matrix and into hout (coherent pinned host memory; for
-// k = 0, hout[0] = beta, the residual norm), and the update coefficients
+// packed Hessenberg matrix and contiguously into hout (device; for k = 0,
+// hout[0] = beta, the residual norm), and the update coefficients
 // cS = s, cZ = z, cC = z - a s; sc = (1/beta, Re a, Im a, beta, Re c_k, Im c_k).
 // beta = 0 (an invariant Krylov space) gives zero coefficients and 1/beta = 0.
-// Once the column is written (a system-scope release by every writer, then a
-// workgroup barrier), thread 0 stores seq into *flag, which the host polls.
+// The column reaches the host from the last workgroup of the update launch
+// (or of k_gm_publish when no update follows).
 __global__ __launch_bounds__(STEP_NT) void k_gm_step(int k, int m, const cplx* __restrict__ part,
                                                      const cplx* __restrict__ hp, cplx* __restrict__ Hrow,
                                                      cplx* __restrict__ hout, cplx* __restrict__ cS,
                                                      cplx* __restrict__ cZ, cplx* __restrict__ cC,
-                                                     double* __restrict__ sc, int64_t* flag, int64_t seq) {
+                                                     double* __restrict__ sc) {
   __shared__ cplx sh[STEP_NT / 64];
   __shared__ cplx s_last[2];  // (rho, zeta)
   __shared__ double s_beta;
@@ -196,14 +196,25 @@ __global__ __launch_bounds__(STEP_NT) void k_gm_step(int k, int m, const cplx* _
     hout[k] = cplx{s_beta, 0.0};
     Hrow[hrow_off(k, m)] = cplx{s_beta, 0.0};
   }
-  // every writer releases its column entries at system scope, then the barrier
-  // orders them before the flag store
+}
+
+// Copies the step's column (device, k + 1 entries) to its host ring slot,
+// then, once every writer has released its entries at system scope and the
+// workgroup has met, stores seq into *flag, which the host polls.
+__device__ inline void gm_publish(int n, const cplx* __restrict__ col, cplx* __restrict__ hout, int64_t* flag,
+                                  int64_t seq) {
+  for (int t = threadIdx.x; t < n; t += blockDim.x) hout[t] = col[t];
   __threadfence_system();
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence_system();
-    flag[threadIdx.x] = seq;  // (vector store from one lane)
+    flag[0] = seq;  // (vector store from one lane)
   }
+}
+
+__global__ __launch_bounds__(256) void k_gm_publish(int n, const cplx* __restrict__ col, cplx* __restrict__ hout,
+                                                    int64_t* flag, int64_t seq) {
+  gm_publish(n, col, hout, flag, seq);
 }
 
 // Second sweep of step k, with the first-pass coefficients of column k.
@@ -222,9 +233,14 @@ __global__ __launch_bounds__(256) void k_gm_update(int N, int k, int m, int nrb,
                                                    const cplx* __restrict__ cS, const cplx* __restrict__ cZ,
                                                    const cplx* __restrict__ cC, const double* __restrict__ sc,
                                                    const cplx* __restrict__ Hrow, cplx* __restrict__ hp,
-                                                   const cplx* __restrict__ w) {
+                                                   const cplx* __restrict__ w, const cplx* __restrict__ col,
+                                                   cplx* __restrict__ hout, int64_t* flag, int64_t seq) {
   const int bid = blockIdx.x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (bid == (int)gridDim.x - 1) {  // the last workgroup hands the step's column to the host
+    gm_publish(k + 1, col, hout, flag, seq);
+    return;
+  }
   if (bid >= nrb) {
     const int r = (bid - nrb) * 4 + wv;
     if (r > k) return;  // wave-uniform
@@ -461,15 +477,21 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
     // basis (u among it), w, partials
     SESM_KT_END(SESM_KT_DOTS, st, c16 * ((double)nv * N + (full ? N : 0) + 2.0 * nv * DCHUNK));
     const int64_t seq = ++ctx->gm_seq;
-    hipLaunchKernelGGL(k_gm_step, dim3(1), dim3(STEP_NT), 0, st, k, m, ctx->hpart, ctx->hp, ctx->Hrow,
-                       ctx->hhost_dev + (size_t)slot * SESM_HSTRIDE, cS, cZ, cC, ctx->gsc, ctx->hflag_dev + slot, seq);
+    cplx* colv = ctx->hcol + (size_t)(k % 2) * SESM_HSTRIDE;  // the step's column on the device
+    hipLaunchKernelGGL(k_gm_step, dim3(1), dim3(STEP_NT), 0, st, k, m, ctx->hpart, ctx->hp, ctx->Hrow, colv, cS, cZ,
+                       cC, ctx->gsc);
     SESM_LAUNCH_CHECK();
     slot_seq[slot] = seq;
+    cplx* hout = ctx->hhost_dev + (size_t)slot * SESM_HSTRIDE;
+    if (!full) {  // no update follows: publish the column on its own
+      hipLaunchKernelGGL(k_gm_publish, dim3(1), dim3(256), 0, st, k + 1, colv, hout, ctx->hflag_dev + slot, seq);
+      SESM_LAUNCH_CHECK();
+    }
     if (full) {
       const int nrb = (N + UPD_ROWS - 1) / UPD_ROWS;
       SESM_KT_BEGIN(SESM_KT_UPDATE, st);
-      hipLaunchKernelGGL(k_gm_update, dim3(nrb + (k + 1 + 3) / 4), dim3(256), 0, st, N, k, m, nrb, V, ldv, cS, cZ,
-                         cC, ctx->gsc, ctx->Hrow, ctx->hp, ctx->gw);
+      hipLaunchKernelGGL(k_gm_update, dim3(nrb + (k + 1 + 3) / 4 + 1), dim3(256), 0, st, N, k, m, nrb, V, ldv, cS,
+                         cZ, cC, ctx->gsc, ctx->Hrow, ctx->hp, ctx->gw, colv, hout, ctx->hflag_dev + slot, seq);
       SESM_LAUNCH_CHECK();
       // basis V_0..V_{k-1}, u and w read; q_k and u' written
       SESM_KT_END(SESM_KT_UPDATE, st, c16 * ((double)k * N + 4.0 * N));
