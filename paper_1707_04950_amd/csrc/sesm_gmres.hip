@@ -121,10 +121,19 @@ __global__ __launch_bounds__(STEP_NT) void k_gm_step(int k, int m, const cplx* _
                                                      cplx* __restrict__ hout, cplx* __restrict__ cS,
                                                      cplx* __restrict__ cZ, cplx* __restrict__ cC,
                                                      double* __restrict__ sc) {
+  constexpr int STEP_LDS = 2048, PER = (SESM_HSTRIDE + STEP_NT - 1) / STEP_NT;
   __shared__ cplx sh[STEP_NT / 64];
   __shared__ cplx s_last[2];  // (rho, zeta)
   __shared__ double s_beta;
   __shared__ cplx s_a;
+  __shared__ cplx lS[STEP_LDS], lZ[STEP_LDS];  // s and z of the first STEP_LDS vectors
+  // this thread's first-pass coefficients, loaded while the partials are reduced
+  cplx hpv[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int v = threadIdx.x + j * STEP_NT;
+    hpv[j] = v < k ? hp[v] : cplx{0.0, 0.0};
+  }
   // reduce the partials: lane = 16 g + c takes chunk c of basis vector
   // vb + 4 u + g (u < 4), so each wavefront has 16 vectors' loads in flight;
   // sums over the 16 chunks (DPP group sums, valid in lane c = 15) against u go
@@ -150,6 +159,10 @@ __global__ __launch_bounds__(STEP_NT) void k_gm_step(int k, int m, const cplx* _
         if (v < k) {
           cS[v] = s0;
           cZ[v] = s1;
+          if (v < STEP_LDS) {
+            lS[v] = s0;
+            lZ[v] = s1;
+          }
         } else {
           s_last[0] = s0;
           s_last[1] = s1;
@@ -161,7 +174,7 @@ __global__ __launch_bounds__(STEP_NT) void k_gm_step(int k, int m, const cplx* _
   double ns = 0.0;
   cplx sz = cplx{0.0, 0.0};
   for (int v = threadIdx.x; v < k; v += STEP_NT) {
-    const cplx av = cS[v], bv = cZ[v];
+    const cplx av = v < STEP_LDS ? lS[v] : cS[v], bv = v < STEP_LDS ? lZ[v] : cZ[v];
     ns += abs2(av);
     sz += cmul_conj(av, bv);
   }
@@ -185,12 +198,16 @@ __global__ __launch_bounds__(STEP_NT) void k_gm_step(int k, int m, const cplx* _
   }
   __syncthreads();
   const cplx a = s_a;
-  for (int v = threadIdx.x; v < k; v += STEP_NT) {
-    const cplx av = cS[v], bv = cZ[v];
-    cC[v] = bv - a * av;
-    const cplx hv = hp[v] + av;
-    hout[v] = hv;
-    Hrow[hrow_off(v, m) + (k - 1 - (v > 0 ? v - 1 : 0))] = hv;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int v = threadIdx.x + j * STEP_NT;
+    if (v < k) {
+      const cplx av = v < STEP_LDS ? lS[v] : cS[v], bv = v < STEP_LDS ? lZ[v] : cZ[v];
+      cC[v] = bv - a * av;
+      const cplx hv = hpv[j] + av;
+      hout[v] = hv;
+      Hrow[hrow_off(v, m) + (k - 1 - (v > 0 ? v - 1 : 0))] = hv;
+    }
   }
   if (threadIdx.x == 0 && k > 0) {
     hout[k] = cplx{s_beta, 0.0};
