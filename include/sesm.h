@@ -109,7 +109,8 @@ typedef struct {
   int32_t n_x, n_y, n_cells_occupied, stencil_rows;
   double L, y0, delta;
   int64_t near_entries;       /* stored near-field entries (accelerated mode) */
-  int64_t device_bytes;       /* device memory held by the context          */
+  int64_t device_bytes;       /* device memory held by the context (including blocks
+                                 kept from an earlier surface for reuse)      */
 } sesm_surface_info;
 
 /* Create a context on HIP device `device`; `hip_stream` is a hipStream_t (NULL

@@ -116,16 +116,50 @@ std::complex<double> shift_quotient(std::complex<double> b, double h, int j) {
 
 }  // namespace
 
+// keeps released blocks for the next surface up to this many bytes
+static constexpr size_t kPoolLimit = (size_t)16 << 30;
+
+static void pool_drain(sesm_ctx* ctx) {
+  for (auto& b : ctx->pool) (void)hipFree(b.second);
+  ctx->pool.clear();
+  ctx->pool_bytes = 0;
+}
+
+void sesm_pool_put(sesm_ctx* ctx, void* p, size_t bytes) {
+  if (!p) return;
+  if (ctx->pool_bytes + bytes > kPoolLimit) {
+    (void)hipFree(p);
+    return;
+  }
+  ctx->pool.emplace_back(bytes, p);
+  ctx->pool_bytes += bytes;
+}
+
 int sesm_alloc(sesm_ctx* ctx, void** p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) bytes = 16;
-  hipError_t e = hipMalloc(p, bytes);
-  if (e != hipSuccess) {
-    *p = nullptr;
-    (void)hipGetLastError();
-    return ctx->fail(SESM_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+  for (size_t t = 0; t < ctx->pool.size(); ++t)  // a released block of exactly this size
+    if (ctx->pool[t].first == bytes) {
+      *p = ctx->pool[t].second;
+      ctx->pool[t] = ctx->pool.back();
+      ctx->pool.pop_back();
+      ctx->pool_bytes -= bytes;
+      break;
+    }
+  if (!*p) {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess && !ctx->pool.empty()) {  // give the pool back and try again
+      (void)hipGetLastError();
+      pool_drain(ctx);
+      e = hipMalloc(p, bytes);
+    }
+    if (e != hipSuccess) {
+      *p = nullptr;
+      (void)hipGetLastError();
+      return ctx->fail(SESM_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+    }
   }
-  ctx->owned.push_back(*p);
+  ctx->owned.emplace_back(*p, bytes);
   ctx->bytes += (int64_t)bytes;
   if (ctx->poison &&  // every byte 0xFF: a NaN in each double, so a read before the first write shows
       (hipMemsetAsync(*p, 0xFF, bytes, ctx->stream) != hipSuccess || hipStreamSynchronize(ctx->stream) != hipSuccess))
@@ -136,7 +170,7 @@ int sesm_alloc(sesm_ctx* ctx, void** p, size_t bytes) {
 void sesm_release_surface(sesm_ctx* ctx) {
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   sesm_accel_free(ctx);
-  for (void* p : ctx->owned) (void)hipFree(p);
+  for (auto& o : ctx->owned) sesm_pool_put(ctx, o.first, o.second);
   ctx->owned.clear();
   ctx->bytes = 0;
   ctx->x = ctx->f = ctx->fp = ctx->fpp = ctx->J = ctx->logw = nullptr;
@@ -147,11 +181,7 @@ void sesm_release_surface(sesm_ctx* ctx) {
   ctx->gsc = nullptr;
   ctx->Hrow_len = 0;
   ctx->Hrow_m = -1;
-  if (ctx->hhost) (void)hipHostFree(ctx->hhost);
-  if (ctx->hflag) (void)hipHostFree(ctx->hflag);
-  ctx->hhost = ctx->hhost_dev = nullptr;
-  ctx->hflag = ctx->hflag_dev = nullptr;
-  ctx->ready = false;
+  ctx->ready = false;  // (the pinned column slots stay: they do not depend on the surface)
 }
 
 KParams sesm_ctx::kparams() const {
@@ -210,6 +240,9 @@ int sesm_destroy(sesm_ctx* ctx) {
   if (!ctx) return SESM_OK;
   (void)hipSetDevice(ctx->device);
   sesm_release_surface(ctx);
+  pool_drain(ctx);
+  if (ctx->hhost) (void)hipHostFree(ctx->hhost);
+  if (ctx->hflag) (void)hipHostFree(ctx->hflag);
   sesm_kt_free(ctx);
   delete ctx;
   return SESM_OK;
@@ -371,7 +404,7 @@ int sesm_get_info(const sesm_ctx* ctx, sesm_surface_info* info) {
   for (int t = 0; t < P.nU && t < 16; ++t) info->U_eta[t] = P.U[t];
   info->n_first = P.n_first;
   info->n_count = P.n_count;
-  info->device_bytes = ctx->bytes;
+  info->device_bytes = ctx->bytes + (int64_t)ctx->pool_bytes;
   if (P.mode == SESM_MODE_ACCEL) sesm_accel_info(ctx, info);
   return SESM_OK;
 }

@@ -381,11 +381,11 @@ int ensure_workspace(sesm_ctx* ctx, int m) {
   auto drop = [&](void* p) {
     if (!p) return;
     for (size_t t = 0; t < ctx->owned.size(); ++t)
-      if (ctx->owned[t] == p) {
+      if (ctx->owned[t].first == p) {
+        sesm_pool_put(ctx, p, ctx->owned[t].second);
         ctx->owned.erase(ctx->owned.begin() + t);
         break;
       }
-    (void)hipFree(p);
   };
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->V) ctx->bytes -= (int64_t)ctx->V_cols * N * (int64_t)sizeof(cplx);
@@ -413,7 +413,14 @@ int ensure_workspace(sesm_ctx* ctx, int m) {
     if ((rc = sesm_alloc(ctx, (void**)&ctx->gsc, sizeof(double) * 8))) return rc;
     if ((rc = sesm_alloc(ctx, (void**)&ctx->wtmp, sizeof(cplx) * (size_t)N))) return rc;
     if ((rc = sesm_alloc(ctx, (void**)&ctx->gw, sizeof(cplx) * (size_t)N))) return rc;
-    // columns and their flags in coherent pinned memory, written by the step kernel
+  }
+  if (!ctx->hhost || !ctx->hflag) {
+    // columns and their flags in coherent pinned memory, written by the update
+    // launch (kept for the context's lifetime)
+    if (ctx->hhost) (void)hipHostFree(ctx->hhost);
+    if (ctx->hflag) (void)hipHostFree(ctx->hflag);
+    ctx->hhost = nullptr;
+    ctx->hflag = nullptr;
     if (hipHostMalloc((void**)&ctx->hhost, sizeof(cplx) * (SESM_HRING + 1) * SESM_HSTRIDE, hipHostMallocCoherent) !=
             hipSuccess ||
         hipHostMalloc((void**)&ctx->hflag, sizeof(int64_t) * SESM_HRING, hipHostMallocCoherent) != hipSuccess)

@@ -85,7 +85,11 @@ struct sesm_ctx {
   // 0..j+1 at j (j + 3) / 2), kept across solves so that their pages stay mapped
   std::vector<std::complex<double>> gm_rot, gm_raw;
   std::vector<cplx> gm_tri;
-  std::vector<void*> owned;  // every device allocation made for the surface
+  std::vector<std::pair<void*, size_t>> owned;  // every device allocation made for the surface
+  // device blocks released by an earlier surface, by size, reused by the next
+  // one (a surface of the same shape allocates the same sizes); bounded below
+  std::vector<std::pair<size_t, void*>> pool;
+  size_t pool_bytes = 0;
   bool poison = false;       // fill new allocations with NaN bytes (SESM_POISON_ALLOC set at creation)
   int64_t bytes = 0;
   // per-kernel timing (sesm_timing_enable)
@@ -134,6 +138,7 @@ void sesm_kt_free(sesm_ctx* ctx);
 // allocation owned by the surface (freed by release_surface)
 int sesm_alloc(sesm_ctx* ctx, void** p, size_t bytes);
 void sesm_release_surface(sesm_ctx* ctx);
+void sesm_pool_put(sesm_ctx* ctx, void* p, size_t bytes);  // hand a released device block to the pool
 
 // dense path (sesm_dense.hip)
 int sesm_dense_setup(sesm_ctx* ctx);
