@@ -63,7 +63,7 @@ struct AccelOp {
   cplx *p2e = nullptr, *nearblk = nullptr, *dens = nullptr;
   cplx *gH = nullptr, *gV = nullptr, *fH = nullptr, *fV = nullptr, *phH = nullptr, *phV = nullptr;
   cplx *specH = nullptr, *specV = nullptr, *W = nullptr;
-  cplx *pplw = nullptr;  // plane-wave least squares: (Q^H)^T (n_bdry x n_plw), R (n_plw x n_plw), 1 / diag(R)
+  cplx *pplw = nullptr;  // plane-wave least squares: (U^H)^T (n_bdry x n_plw), V (n_plw x n_plw), 1 / sig
   cplx *pinv = nullptr;  // equivalent-source least squares, per set: Q^H (2n_eq x 4n_coll) then R
   cplx *twxH = nullptr, *twxV = nullptr, *utwH = nullptr, *utwV = nullptr;  // e^{-i alpha x}, e^{+i alpha x}
   double* dirs = nullptr;
@@ -169,6 +169,73 @@ bool ls_qr(int m, int n, std::vector<C> A, std::vector<C>& Qh_out, std::vector<C
   return true;
 }
 
+// Singular value decomposition A = U diag(sig) V^H of an m x n matrix
+// (used for the plane-wave least squares of eq. plwave_QR)
+// (row-major, m >= n) by one-sided Jacobi rotations (Hestenes' method): pairs
+// of columns are rotated until all are mutually orthogonal; the column norms
+// are then the singular values, the normalised columns U, and the
+// accumulated rotations V.  Least squares then reads w = V diag(1/sig) U^H b,
+// applied factor by factor (stable like the QR route; the product of the
+// factors is never formed).  Returns U^H (n x m, row-major), sig (n) and V
+// (n x n, row-major).  False if a column vanishes (rank deficiency) or the
+// sweeps do not converge.
+bool ls_svd(int m, int n, const std::vector<C>& A, std::vector<C>& Uh_out, std::vector<double>& sig,
+            std::vector<C>& V_out) {
+  std::vector<C> a((size_t)n * m), v((size_t)n * n, C(0.0));  // column-major copies
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < n; ++j) a[(size_t)j * m + i] = A[(size_t)i * n + j];
+  for (int j = 0; j < n; ++j) v[(size_t)j * n + j] = 1.0;
+  bool converged = false;
+  for (int sweep = 0; sweep < 60 && !converged; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        C* ap = &a[(size_t)p * m];
+        C* aq = &a[(size_t)q * m];
+        double al = 0.0, be = 0.0;
+        C ga = 0.0;
+        for (int i = 0; i < m; ++i) {
+          al += std::norm(ap[i]);
+          be += std::norm(aq[i]);
+          ga += std::conj(ap[i]) * aq[i];
+        }
+        const double g = std::abs(ga);
+        if (!(g > 0.0) || g <= 1e-15 * std::sqrt(al * be)) continue;
+        off = std::max(off, g / std::sqrt(al * be));
+        const C e = std::conj(ga / g);  // aq e makes the pair's inner product real and positive
+        const double zeta = (be - al) / (2.0 * g);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), s = c * t;
+        for (int i = 0; i < m; ++i) {
+          const C x = ap[i], y = aq[i] * e;
+          ap[i] = c * x - s * y;
+          aq[i] = s * x + c * y;
+        }
+        C* vp = &v[(size_t)p * n];
+        C* vq = &v[(size_t)q * n];
+        for (int i = 0; i < n; ++i) {
+          const C x = vp[i], y = vq[i] * e;
+          vp[i] = c * x - s * y;
+          vq[i] = s * x + c * y;
+        }
+      }
+    converged = off <= 1e-15;
+  }
+  if (!converged) return false;
+  sig.assign(n, 0.0);
+  Uh_out.assign((size_t)n * m, C(0.0));
+  V_out.assign((size_t)n * n, C(0.0));
+  for (int j = 0; j < n; ++j) {
+    double nn = 0.0;
+    for (int i = 0; i < m; ++i) nn += std::norm(a[(size_t)j * m + i]);
+    sig[j] = std::sqrt(nn);
+    if (!(sig[j] > 0.0)) return false;
+    for (int i = 0; i < m; ++i) Uh_out[(size_t)j * m + i] = std::conj(a[(size_t)j * m + i]) / sig[j];
+    for (int i = 0; i < n; ++i) V_out[(size_t)i * n + j] = v[(size_t)j * n + i];
+  }
+  return true;
+}
+
 // Geometry of one cell, relative to its lower-left corner (all integer-indexed).
 struct CellGeo {
   int n_s, n_e, n_side, n_eq, n_coll;
@@ -228,27 +295,6 @@ __device__ inline cplx sesm_wave_backsub(const cplx* __restrict__ R, int n, cplx
   return yu;
 }
 
-
-// As sesm_wave_backsub, with the reciprocals of the diagonal given (dinv) so
-// that each step is a multiplication, and the solved entry broadcast by
-// readlane; R and dinv may live in LDS.
-__device__ inline cplx sesm_wave_backsub_dinv(const cplx* R, const cplx* dinv, int n, cplx yu) {
-  const int lane = threadIdx.x & 63;
-  const int lr = lane < n ? lane : n - 1;
-  // the next step's R entry and reciprocal are loaded one step ahead
-  cplx rn = R[lr * n + n - 1], dn = dinv[n - 1];
-  for (int r = n - 1; r >= 0; --r) {
-    const cplx rc = rn, dc = dn;
-    if (r > 0) {
-      rn = R[lr * n + r - 1];
-      dn = dinv[r - 1];
-    }
-    if (lane == r) yu = yu * dc;
-    const cplx xr = cplx{sesm_readlane(yu.re, r), sesm_readlane(yu.im, r)};
-    if (lane < r) yu -= rc * xr;
-  }
-  return yu;
-}
 
 // sum over shifts of one free-space kernel between x and y, punctured term by
 // term (terms with R_m <= 1e-9 h are dropped: the reading of eq. phi_def).
@@ -841,7 +887,7 @@ struct FarArgs {
 // sides incl. corners, V on vertical sides), minus the equivalent sources of
 // the near columns (local corrections, from k_yconv), plane-wave weights,
 // surface values, plus the completion modes D_M (partial sums from
-// k_local_apply).  Dynamic LDS: the plane-wave factors ((Q^H)^T, R, 1/diag R),
+// k_local_apply).  Dynamic LDS: the plane-wave factors ((U^H)^T, V, 1/sig),
 // the cell's nodes and their values.  Each phase keeps its global loads
 // independent so that they are in flight together.
 __global__ __launch_bounds__(256) void k_cells_far(FarArgs A, KParams K, const int* __restrict__ occ_cell,
@@ -908,10 +954,11 @@ __global__ __launch_bounds__(256) void k_cells_far(FarArgs A, KParams K, const i
     bv[b] = val - cs;
   }
   __syncthreads();
-  // phase 3: plane-wave weights, least squares R w = Q^H b (eq. plwave_QR), on wavefront 0
+  // phase 3: plane-wave weights, the least squares of eq. plwave_QR through the
+  // SVD of the plane-wave matrix, w = V diag(1/sig) U^H b, on wavefront 0
   if (wv == 0) {
     cplx yu = cplx{0.0, 0.0};
-    if (lane < A.n_plw) {  // Q^H b, four independent partial sums
+    if (lane < A.n_plw) {  // U^H b, four independent partial sums
       cplx y4[4] = {cplx{0.0, 0.0}, cplx{0.0, 0.0}, cplx{0.0, 0.0}, cplx{0.0, 0.0}};
       int b = 0;
       for (; b + 4 <= A.n_bdry; b += 4) {
@@ -921,8 +968,22 @@ __global__ __launch_bounds__(256) void k_cells_far(FarArgs A, KParams K, const i
       for (; b < A.n_bdry; ++b) y4[0] += pf[b * A.n_plw + lane] * bv[b];
       yu = (y4[0] + y4[1]) + (y4[2] + y4[3]);
     }
-    const cplx* Rs = pf + A.n_bdry * A.n_plw;
-    yu = sesm_wave_backsub_dinv(Rs, Rs + A.n_plw * A.n_plw, A.n_plw, yu);
+    // w = V (diag(1/sig) U^H b): the scaled coefficients are broadcast by readlane
+    const cplx* Vs = pf + A.n_bdry * A.n_plw;
+    const cplx* isg = Vs + A.n_plw * A.n_plw;
+    const int lr = lane < A.n_plw ? lane : A.n_plw - 1;
+    const cplx e = lane < A.n_plw ? isg[lane].re * yu : cplx{0.0, 0.0};
+    cplx w4[4] = {cplx{0.0, 0.0}, cplx{0.0, 0.0}, cplx{0.0, 0.0}, cplx{0.0, 0.0}};
+    int j = 0;
+    for (; j + 4 <= A.n_plw; j += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const cplx ej = cplx{sesm_readlane(e.re, j + u), sesm_readlane(e.im, j + u)};
+        w4[u] += Vs[lr * A.n_plw + j + u] * ej;
+      }
+    }
+    for (; j < A.n_plw; ++j) w4[0] += Vs[lr * A.n_plw + j] * cplx{sesm_readlane(e.re, j), sesm_readlane(e.im, j)};
+    yu = (w4[0] + w4[1]) + (w4[2] + w4[3]);
     if (lane < A.n_plw) wv_sh[lane] = yu;
   }
   __syncthreads();
@@ -1334,19 +1395,20 @@ int sesm_accel_setup(sesm_ctx* ctx) {
         E[(size_t)b * A->n_plw + s] = std::exp(C(0.0, P.k * (dirs[2 * s] * bx + dirs[2 * s + 1] * by)));
     }
     if (A->n_bdry < A->n_plw) return ctx->fail(SESM_EINVAL, "accelerator: need n_plw <= boundary points (4 n_side)");
-    std::vector<C> Qh, Rm;
-    if (!ls_qr(A->n_bdry, A->n_plw, E, Qh, Rm)) return ctx->fail(SESM_EINVAL, "plane-wave matrix is rank deficient");
+    // w = V diag(1/sig) U^H b: (U^H)^T, V and 1/sig for the cell kernel (the
+    // three factors are applied one after the other, never multiplied out)
+    std::vector<C> Uh, Vm;
+    std::vector<double> sig;
+    if (!ls_svd(A->n_bdry, A->n_plw, E, Uh, sig, Vm))
+      return ctx->fail(SESM_EINVAL, "plane-wave matrix is rank deficient");
     std::vector<cplx> pv;
     for (int b = 0; b < A->n_bdry; ++b)
       for (int u = 0; u < A->n_plw; ++u) {
-        const C v = Qh[(size_t)u * A->n_bdry + b];
+        const C v = Uh[(size_t)u * A->n_bdry + b];
         pv.push_back(cplx{v.real(), v.imag()});
       }
-    for (const C& v : Rm) pv.push_back(cplx{v.real(), v.imag()});
-    for (int u = 0; u < A->n_plw; ++u) {
-      const C v = 1.0 / Rm[(size_t)u * A->n_plw + u];
-      pv.push_back(cplx{v.real(), v.imag()});
-    }
+    for (const C& v : Vm) pv.push_back(cplx{v.real(), v.imag()});
+    for (int u = 0; u < A->n_plw; ++u) pv.push_back(cplx{1.0 / sig[u], 0.0});
     if ((rc = upload(ctx, &A->pplw, pv)) || (rc = upload(ctx, &A->dirs, dirs))) return rc;
   }
   // --- work buffers
@@ -1399,7 +1461,7 @@ static MatvecBytes matvec_bytes(const sesm_ctx* ctx) {
              c * (double)A->n_off * ns2 * A->n_bdry + A->n_pairs * (12.0 + c) + 12.0 * A->n_groups +
              c * (double)A->n_pairs * A->n_bdry;
   B.yconvV = c * (2.0 * nV + 2.0 * (2.0 * A->nYV - 1) * A->nXV + nV);
-  // local corrections, phi grids, plane-wave QR, directions, cell and pair
+  // local corrections, phi grids, plane-wave SVD factors, directions, cell and pair
   // tables, node coordinates and index, y read and written, mode sums
   B.cells = c * (double)A->n_pairs * A->n_bdry + c * (nH + nV) +
             c * ((double)A->n_bdry * A->n_plw + (double)A->n_plw * A->n_plw + A->n_plw) + 16.0 * A->n_plw +

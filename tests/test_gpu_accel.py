@@ -161,6 +161,45 @@ def test_accel_solve_efficiencies_vs_dense_oracle(torch, solver, case):
     assert np.max(np.abs(e - e_o)) <= 1e-6
 
 
+@pytest.mark.parametrize("offset,theta", [(0.3, 20.0), (0.0, 45.0)])
+def test_flat_surface_accelerated_closed_form(torch, solver, offset, theta):
+    """Degenerate geometry for the accelerator: a flat surface (one row of
+    cells).  The accelerated solve must give B_0 = -exp(-2 i beta f), e_0 = 1
+    (closed form, the same as the dense operator's)."""
+    import paper_1707_04950_amd as lib
+    from gpu_util import set_surface
+    wl = W.Workload(name="flat", d=5.0, k=2 * math.pi, theta_deg=theta, N=400, j=8, h=0.5, A=40.0,
+                    a_coef=(offset,), b_coef=(0.0,), L=0.5)
+    disc = dense.Discretization(wl)
+    set_surface(solver, wl, disc, mode=lib.MODE_ACCEL, n_side=ACC_KW["n_s"], n_ext=ACC_KW["n_e"],
+                n_coll=ACC_KW["n_coll"], n_plw=ACC_KW["n_plw"])
+    assert solver.info()["n_y"] == 1
+    mu, info = solver.solve(tol=1e-12, max_iter=200)
+    assert info["converged"]
+    B = solver.rayleigh(mu, [0])
+    n, e, eps = solver.efficiencies(mu)
+    err = abs(B[0] + np.exp(-2j * disc.beta * offset))
+    print("flat offset %.1f theta %.0f: |B_0 - closed form| %.2e, eps %.2e" % (offset, theta, err, eps))
+    assert err < 1e-8 and abs(eps) < 1e-8
+
+
+def test_accelerated_parameters_are_validated(torch, solver):
+    """Parameters outside the accelerator's supported range are rejected by
+    the host before any kernel runs."""
+    import paper_1707_04950_amd as lib
+    wl = W.config_random_double_wood(4096)
+    base = dict(h=wl.h, c=wl.c, gamma_frac=wl.gamma_frac, eta=wl.eta, mode=lib.MODE_ACCEL)
+    bad = [dict(L=0.5, n_side=20),            # too many equivalent sources per side
+           dict(L=0.5, near_ring=5),          # near-field ring beyond 3 columns
+           dict(L=0.04, n_a=8),               # periodic grid longer than the FFT supports
+           dict(L=0.5, n_plw=80)]             # more plane waves than supported
+    for kw in bad:
+        with pytest.raises(lib.SesmError) as ei:
+            solver.set_surface(np.asarray(wl.a_coef), np.asarray(wl.b_coef), wl.d, wl.k, wl.alpha, wl.j, wl.A,
+                               4096, **base, **kw)
+        assert ei.value.code == lib.SESM_EINVAL, kw
+
+
 # ---------------------------------------------------------------- full-size geometries
 def _golden(name):
     import json, os
