@@ -221,8 +221,7 @@ enum {
                          sums of the completion modes: one launch                   */
   SESM_KT_MERGE = 1,  /* merge onto the periodic grids fused with their forward FFT
                          along x (1 per forward map)                              */
-  SESM_KT_FFT = 2,    /* inverse FFT along x of both grids + untwist (only for the
-                         diagnostic stage outputs of sesm_diag_accel)             */
+  SESM_KT_FFT = 2,    /* inverse FFT along x of both grids + untwist (1 per map)    */
   SESM_KT_YCONV = 3,  /* convolution along y per x-frequency, both grids, and the
                          local corrections (1 per map)                            */
   SESM_KT_CELLS = 4,  /* boundary values, plane-wave fit, surface values, modes     */

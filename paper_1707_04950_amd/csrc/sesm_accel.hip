@@ -27,9 +27,8 @@
 //                                                             GlobalFFT, eq. large_convolution_per_grid)
 //   k_yconv         kernel-spectrum x sources, direct in y
 //                   + local corrections per cell pair         (LocalEqSMerge, LocalFFT, eq. small_convolution)
-//   k_cells_far     phi^all at the cell's boundary points by direct inverse DFT
-//                   of the spectra (GlobalFFT, the inverse transform at the points needed),
-//                   boundary values - local corrections       (LocalSubtract, Combine-lambda,
+//   k_fft_rows      inverse FFT, untwist -> phi^all
+//   k_cells_far     boundary values - local corrections       (LocalSubtract, Combine-lambda,
 //                   -> plane-wave weights -> surface values      PlaneWaveWeights, NonIntersecting;
 //                   + completion modes D_M, added into y         eqs. psi_na_sum, combine_psi_pna,
 //                                                                planewave, plwave_QR)
@@ -884,18 +883,6 @@ struct FarArgs {
   double L, x0, y0, k, alpha_d;
 };
 
-// Spectra of the y-convolved grids (rows [gy][kx]) with the tables that turn
-// them into phi^all at chosen grid points: twiddles exp(-2 pi i t / n) and the
-// untwist factors exp(i alpha x).
-struct FarSpectra {
-  const cplx* gH;
-  const cplx* gV;
-  const cplx* twH;
-  const cplx* twV;
-  const cplx* utwH;
-  const cplx* utwV;
-};
-
 // One block per occupied cell: boundary values of phi^all (H on horizontal
 // sides incl. corners, V on vertical sides), minus the equivalent sources of
 // the near columns (local corrections, from k_yconv), plane-wave weights,
@@ -906,7 +893,7 @@ struct FarSpectra {
 __global__ __launch_bounds__(256) void k_cells_far(FarArgs A, KParams K, const int* __restrict__ occ_cell,
                                                    const int* __restrict__ occ_off, const int* __restrict__ perm,
                                                    const int* __restrict__ pair_off, const cplx* __restrict__ corr,
-                                                   FarSpectra G,
+                                                   const cplx* __restrict__ phH, const cplx* __restrict__ phV,
                                                    const cplx* __restrict__ pplw, const double* __restrict__ dirs,
                                                    const double* __restrict__ x, const double* __restrict__ f,
                                                    const cplx* __restrict__ mode_part, cplx* __restrict__ y,
@@ -944,94 +931,27 @@ __global__ __launch_bounds__(256) void k_cells_far(FarArgs A, KParams K, const i
       if (lane == 0) msum[t] = a;
     }
   }
-  // phase 0b: phi^all at the cell's boundary points straight from the spectra,
-  // phi(gx) = (1/n) exp(i alpha x_gx) sum_kx ghat[kx] exp(2 pi i kx gx / n), so
-  // no inverse transform of the whole grids is needed.  H sides: one half of
-  // the workgroup per row (cy, cy + 1), threads over kx, the n_s + 1 points by
-  // phase stepping; V sides: one wavefront per grid row, lanes over kx, both
-  // columns (cx, cx + 1).  Raw sums go to sB (boundary point order).
-  {
-    constexpr int NS1 = 17;  // n_s + 1 <= 17
-    __shared__ cplx sB[64];
-    __shared__ cplx red2[2][2][NS1];
-    const int ns1 = A.n_s + 1;
-    {
-      const int n = A.nXH, half = threadIdx.x >> 7, t = threadIdx.x & 127;
-      const cplx* __restrict__ gr = G.gH + (int64_t)(cy + half) * n;
-      const int gx0 = cx * A.n_s;
-      cplx acc[NS1];
-#pragma unroll
-      for (int i = 0; i < NS1; ++i) acc[i] = cplx{0.0, 0.0};
-#pragma unroll 2
-      for (int kx = t; kx < n; kx += 128) {
-        const cplx g = gr[kx];
-        cplx ph = conj(G.twH[(kx * gx0) % n]);  // exp(+2 pi i kx gx0 / n)
-        const cplx st = conj(G.twH[kx]);         // exp(+2 pi i kx / n)
-#pragma unroll
-        for (int i = 0; i < NS1; ++i)
-          if (i < ns1) {
-            acc[i] += g * ph;
-            ph = ph * st;
-          }
-      }
-#pragma unroll
-      for (int i = 0; i < NS1; ++i) {
-        if (i < ns1) {  // uniform
-          const cplx sm = wave_sum(acc[i]);
-          if (lane == 0) red2[half][wv & 1][i] = sm;
-        }
-      }
-    }
-    {
-      const int n = A.nXV;
-      for (int i = 1 + wv; i < A.n_s; i += 4) {  // wave-uniform
-        const cplx* __restrict__ gr = G.gV + (int64_t)(cy * A.n_s + i + A.n_e) * n;
-        cplx a0 = cplx{0.0, 0.0}, a1 = cplx{0.0, 0.0};
-        for (int kx = lane; kx < n; kx += 64) {
-          const cplx g = gr[kx];
-          const cplx p0 = conj(G.twV[(kx * cx) % n]);  // exp(+2 pi i kx cx / n)
-          const cplx p1 = p0 * conj(G.twV[kx]);          // exp(+2 pi i kx (cx + 1) / n)
-          a0 += g * p0;
-          a1 += g * p1;
-        }
-        a0 = wave_sum(a0);
-        a1 = wave_sum(a1);
-        if (lane == 0) {
-          sB[A.n_bH + (i - 1)] = a0;
-          sB[A.n_bH + (A.n_s - 1) + (i - 1)] = a1;
-        }
-      }
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < 2 * ns1) {
-      const int half = threadIdx.x / ns1, i = threadIdx.x % ns1;
-      sB[threadIdx.x] = red2[half][0][i] + red2[half][1][i];
-    }
-    __syncthreads();
-    if (threadIdx.x < A.n_bdry) {
-      const int b = threadIdx.x;
-      int gx, Wr = 0;
-      double sc;
-      const cplx* utw;
-      if (b < A.n_bH) {
-        gx = cx * A.n_s + b % ns1;
-        if (gx >= A.nXH) { gx -= A.nXH; Wr = 1; }
-        sc = 1.0 / A.nXH;
-        utw = G.utwH;
-      } else {
-        gx = cx + (b - A.n_bH) / (A.n_s - 1);
-        if (gx >= A.nXV) { gx -= A.nXV; Wr = 1; }
-        sc = 1.0 / A.nXV;
-        utw = G.utwV;
-      }
-      cplx val = (sc * sB[b]) * utw[gx];
+  if (threadIdx.x < A.n_bdry) {
+    const int b = threadIdx.x;
+    cplx val;
+    if (b < A.n_bH) {
+      const int iy = b / (A.n_s + 1), i = b % (A.n_s + 1);
+      int gx = cx * A.n_s + i, Wr = 0;
+      if (gx >= A.nXH) { gx -= A.nXH; Wr = 1; }
+      val = phH[(int64_t)(cy + iy) * A.nXH + gx];
       if (Wr) val = cexp_i(A.alpha_d) * val;
-      cplx cs = cplx{0.0, 0.0};
-      const int p0 = pair_off[q], p1 = pair_off[q + 1];
-#pragma unroll 8
-      for (int p = p0; p < p1; ++p) cs += corr[(int64_t)p * A.n_bdry + b];
-      bv[b] = val - cs;
+    } else {
+      const int t = b - A.n_bH, ix = t / (A.n_s - 1), i = 1 + t % (A.n_s - 1);
+      int gx = cx + ix, Wr = 0;
+      if (gx >= A.nXV) { gx -= A.nXV; Wr = 1; }
+      val = phV[(int64_t)(cy * A.n_s + i + A.n_e) * A.nXV + gx];
+      if (Wr) val = cexp_i(A.alpha_d) * val;
     }
+    cplx cs = cplx{0.0, 0.0};
+    const int p0 = pair_off[q], p1 = pair_off[q + 1];
+#pragma unroll 8
+    for (int p = p0; p < p1; ++p) cs += corr[(int64_t)p * A.n_bdry + b];
+    bv[b] = val - cs;
   }
   __syncthreads();
   // phase 3: plane-wave weights, the least squares of eq. plwave_QR through the
@@ -1541,10 +1461,9 @@ static MatvecBytes matvec_bytes(const sesm_ctx* ctx) {
              c * (double)A->n_off * ns2 * A->n_bdry + A->n_pairs * (12.0 + c) + 12.0 * A->n_groups +
              c * (double)A->n_pairs * A->n_bdry;
   B.yconvV = c * (2.0 * nV + 2.0 * (2.0 * A->nYV - 1) * A->nXV + nV);
-  // local corrections, spectra of both grids and their twiddle and untwist
-  // tables, plane-wave SVD factors, directions, cell and pair
+  // local corrections, phi grids, plane-wave SVD factors, directions, cell and pair
   // tables, node coordinates and index, y read and written, mode sums
-  B.cells = c * (double)A->n_pairs * A->n_bdry + c * (nH + nV) + c * 2.0 * (A->nXH + A->nXV) +
+  B.cells = c * (double)A->n_pairs * A->n_bdry + c * (nH + nV) +
             c * ((double)A->n_bdry * A->n_plw + (double)A->n_plw * A->n_plw + A->n_plw) + 16.0 * A->n_plw +
             16.0 * A->n_occ + N * (16.0 + 4.0 + 2.0 * c) + c * ctx->P.nU * NCH_MODES;
   return B;
@@ -1617,20 +1536,17 @@ static int accel_matvec_impl(sesm_ctx* ctx, const cplx* mu, cplx* y, bool keep_f
     SESM_LAUNCH_CHECK();
   }
   SESM_KT_END(SESM_KT_YCONV, st, B.yconvH + B.yconvV);
-  if (keep_far) {  // diagnostics only: phi^all on the whole grids (the cells evaluate what they need)
-    SESM_KT_BEGIN(SESM_KT_FFT, st);
-    if ((rc = fft_launch(ctx, st, sesm_fft_job(A->planH, A->nYH, A->gH, A->phH, nullptr, A->utwH, 1.0 / A->nXH),
-                         sesm_fft_job(A->planV, A->nYV, A->gV, A->phV, nullptr, A->utwV, 1.0 / A->nXV), +1)))
-      return rc;
-    SESM_KT_END(SESM_KT_FFT, st, B.fftH1 + B.fftV1);
-  }
+  SESM_KT_BEGIN(SESM_KT_FFT, st);
+  if ((rc = fft_launch(ctx, st, sesm_fft_job(A->planH, A->nYH, A->gH, A->phH, nullptr, A->utwH, 1.0 / A->nXH),
+                       sesm_fft_job(A->planV, A->nYV, A->gV, A->phV, nullptr, A->utwV, 1.0 / A->nXV), +1)))
+    return rc;
+  SESM_KT_END(SESM_KT_FFT, st, B.fftH1 + B.fftV1);
   FarArgs F{P.N, A->n_x, A->n_y, A->n_s, A->n_e, A->n_side, A->n_eq, A->n_cells, A->n_bdry, A->n_bH, A->n_plw,
             A->nXH, A->nXV, A->ring, A->max_q, A->L, A->x0, A->y0, P.k, P.alpha * P.d};
   SESM_KT_BEGIN(SESM_KT_CELLS, st);
-  const FarSpectra G{A->gH, A->gV, A->planH.tw, A->planV.tw, A->utwH, A->utwV};
   hipLaunchKernelGGL(k_cells_far, dim3(A->n_occ), dim3(256), cells_far_lds(A), st, F, K, A->occ_cell, A->occ_off,
-                     A->perm, A->pair_off, A->corr, G, A->pplw, A->dirs, ctx->x, ctx->f, A->mode_part, y,
-                     keep_far ? A->yfar : nullptr);
+                     A->perm, A->pair_off, A->corr, A->phH, A->phV, A->pplw, A->dirs, ctx->x, ctx->f, A->mode_part,
+                     y, keep_far ? A->yfar : nullptr);
   SESM_LAUNCH_CHECK();
   SESM_KT_END(SESM_KT_CELLS, st, B.cells);
   return SESM_OK;
