@@ -144,3 +144,36 @@ def test_errors_are_reported(torch, solver):
         s2.matvec(s2.empty(), s2.empty())
     assert ei.value.code == lib.SESM_ENOSURF
     s2.close()
+
+
+@pytest.mark.parametrize("kw,why", [(dict(N=0), "empty discretisation"), (dict(N=4), "fewer than 8 nodes"),
+                                    (dict(j=17), "shift order beyond 16"), (dict(A=0.0), "no window"),
+                                    (dict(d=-1.0), "negative period"), (dict(mode=7), "unknown mode")])
+def test_degenerate_inputs_are_rejected(torch, solver, kw, why):
+    """Empty, too small or meaningless inputs are rejected by the host checks
+    (no kernel runs), with SESM_EINVAL and a message."""
+    import paper_1707_04950_amd as lib
+    wl = W.config_dense_sinusoid(64)
+    args = dict(d=wl.d, j=wl.j, A=wl.A, N=64)
+    extra = {}
+    for key, v in kw.items():
+        (args if key in args else extra)[key] = v
+    with pytest.raises(lib.SesmError) as ei:
+        solver.set_surface(np.asarray(wl.a_coef), np.asarray(wl.b_coef), args["d"], wl.k, wl.alpha, args["j"],
+                           args["A"], args["N"], **extra)
+    assert ei.value.code == lib.SESM_EINVAL, why
+
+
+def test_solve_arguments_are_validated(torch, solver, c1):
+    """A valid surface, then solver arguments outside their ranges: rejected,
+    and the context stays usable."""
+    import paper_1707_04950_amd as lib
+    from gpu_util import set_surface
+    wl, disc = c1[0], c1[1]
+    set_surface(solver, wl, disc)
+    for kw in (dict(tol=0.0), dict(tol=-1.0), dict(max_iter=0), dict(restart=-1)):
+        with pytest.raises(lib.SesmError) as ei:
+            solver.solve(**{**dict(tol=1e-10, max_iter=50), **kw})
+        assert ei.value.code == lib.SESM_EINVAL, kw
+    mu, info = solver.solve(tol=1e-10, max_iter=200)
+    assert info["converged"]
