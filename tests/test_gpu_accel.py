@@ -183,6 +183,37 @@ def test_flat_surface_accelerated_closed_form(torch, solver, offset, theta):
     assert err < 1e-8 and abs(eps) < 1e-8
 
 
+def test_translation_covariance_accelerated(torch, solver):
+    """The profile translated by s (not a multiple of the cell side) sits
+    differently on the accelerator's cell grid; its Rayleigh coefficients must
+    still be B_n e^{i (alpha - alpha_n) s} and its efficiencies the same."""
+    import paper_1707_04950_amd as lib
+    from gpu_util import set_surface
+    wl = _case("gauss30")
+    d = wl.d
+    a = np.array(wl.a_coef, float)
+    b = np.zeros_like(a)
+    b[: len(wl.b_coef)] = wl.b_coef
+    s = 0.37 * d
+    th = 2 * np.pi * np.arange(len(a)) * s / d
+    moved = wl.with_(a_coef=tuple(a * np.cos(th) - b * np.sin(th)), b_coef=tuple(a * np.sin(th) + b * np.cos(th)))
+    res = []
+    for w in (wl, moved):
+        disc = dense.Discretization(w)
+        _gpu_accel(solver, w, disc)
+        mu, info = solver.solve(tol=1e-12, max_iter=600)
+        assert info["converged"]
+        n, e, eps = solver.efficiencies(mu)
+        res.append((disc, n, e, solver.rayleigh(mu, list(n))))
+    (d1, n, e1, B1), (_, _, e2, B2) = res
+    an = d1.alpha + 2 * np.pi * np.asarray(n) / d
+    err_B = np.max(np.abs(B2 - B1 * np.exp(1j * (d1.alpha - an) * s)))
+    print("translation: max|dB| %.2e, max|de| %.2e" % (err_B, np.max(np.abs(e2 - e1))))
+    # two accelerated approximations of the same physics (each within ~1.1e-8
+    # of the dense operator's efficiencies on this workload)
+    assert err_B < 2e-7 and np.max(np.abs(e2 - e1)) < 5e-8
+
+
 def test_accelerated_parameters_are_validated(torch, solver):
     """Parameters outside the accelerator's supported range are rejected by
     the host before any kernel runs."""
