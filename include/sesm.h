@@ -138,6 +138,24 @@ SESM_API int sesm_set_surface(sesm_ctx* ctx, const sesm_profile* profile, double
  * mu, y: device arrays of N sesm_c64; they must not overlap. */
 SESM_API int sesm_matvec(sesm_ctx* ctx, const sesm_c64* mu, sesm_c64* y);
 
+/* Forward maps of several densities with the operator of the current
+ * surface: y_r = (1/2 I + D^dx) mu_r, r = 0..nrhs-1, eq. (discrete_eq).
+ * Density r is the device array mu + r ld_mu of N sesm_c64, output r is
+ * y + r ld_y (ld_mu, ld_y >= N, in elements); the span of the densities must
+ * not overlap that of the outputs.  Densities whose incident Bloch
+ * wavenumbers differ by multiples of 2 pi / d share this operator: it depends
+ * on alpha only through e^{i alpha d} (eq. shifted_periodic_green_function)
+ * and the set {alpha_n} (eqs. alpha_beta_def, M_eta).  In accelerated mode groups of up to four densities
+ * share one pass over the near-field blocks and the equivalent-source
+ * projections (Algorithm 3), and the results equal those of sesm_matvec
+ * bit for bit; in dense mode the densities are applied one at a time.
+ * nrhs = 0 does nothing; nrhs < 0, ld below N, overlap or NULL pointers give
+ * SESM_EINVAL.  The first accelerated call allocates the per-density
+ * buffers of four densities (owned by the surface).  Kernel timing records
+ * the later stages of each density, not the shared launch. */
+SESM_API int sesm_matvec_batch(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* mu, int64_t ld_mu, sesm_c64* y,
+                               int64_t ld_y);
+
 /* Right-hand side of eq. (discrete_eq): b_l = -u^inc(x_l, f(x_l)) with
  * u^inc = exp(i (alpha x - beta y)), beta = sqrt(k^2 - alpha^2) (Sec. 2).
  * b: device array of N sesm_c64. */

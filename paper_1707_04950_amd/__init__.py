@@ -82,6 +82,7 @@ def load_library(path=LIB_PATH):
         "sesm_set_surface": (ctypes.c_int, [_P, ctypes.POINTER(Profile), _D, _D, _D, _I, _D,
                                             ctypes.POINTER(Params)]),
         "sesm_matvec": (ctypes.c_int, [_P, _P, _P]),
+        "sesm_matvec_batch": (ctypes.c_int, [_P, _I, _P, ctypes.c_int64, _P, ctypes.c_int64]),
         "sesm_rhs": (ctypes.c_int, [_P, _P]),
         "sesm_solve": (ctypes.c_int, [_P, _P, _P, _D, _I, _I, ctypes.POINTER(SolveInfo)]),
         "sesm_efficiencies": (ctypes.c_int, [_P, _P, ctypes.POINTER(_I), ctypes.POINTER(_I),
@@ -115,6 +116,14 @@ def _ptr(t):
     import torch
     if not (t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()):
         raise ValueError("expected a contiguous complex128 CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _ptr_rows(t):
+    """Pointer of a 2-D complex128 CUDA tensor whose rows have unit stride."""
+    import torch
+    if not (t.is_cuda and t.dtype == torch.complex128 and t.dim() == 2 and (t.shape[1] <= 1 or t.stride(1) == 1)):
+        raise ValueError("expected a 2-D complex128 CUDA tensor with unit stride along rows")
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -181,6 +190,21 @@ class Solver:
     def matvec(self, mu, out=None):
         out = self.empty() if out is None else out
         self._check(self.lib.sesm_matvec(self.h, _ptr(mu), _ptr(out)))
+        return out
+
+    def matvec_batch(self, mu, out=None):
+        """Forward maps of the rows of mu (nrhs x >= N, complex128 on the device,
+        unit stride along a row) into the rows of out (allocated if None)."""
+        if mu.dim() != 2 or mu.shape[1] < self.N:
+            raise ValueError("mu must be a (nrhs, >= N) tensor")
+        if out is None:
+            out = self._torch.empty((mu.shape[0], self.N), dtype=self._torch.complex128, device=self.device)
+            if os.environ.get("SESM_POISON_ALLOC", "0") not in ("", "0"):
+                out.fill_(complex("nan+nanj"))
+        if out.dim() != 2 or out.shape[0] != mu.shape[0] or out.shape[1] < self.N:
+            raise ValueError("out must be a (nrhs, >= N) tensor")
+        self._check(self.lib.sesm_matvec_batch(self.h, int(mu.shape[0]), _ptr_rows(mu), int(mu.stride(0)),
+                                               _ptr_rows(out), int(out.stride(0))))
         return out
 
     def rhs(self, out=None):

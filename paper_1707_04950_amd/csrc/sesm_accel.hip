@@ -77,6 +77,9 @@ struct AccelOp {
   cplx* grp_ph = nullptr;  // wrap phase per pair, in plist order
   cplx* corr = nullptr;  // [n_pairs][n_bdry]
   cplx* yfar = nullptr;  // diagnostic copy of the far-field contribution
+  // batched forward maps: cell densities and mode partial sums of up to
+  // kBatchMax densities (allocated at the first batched call)
+  cplx *dens_b = nullptr, *mode_b = nullptr;
   FftPlan planH, planV;
 };
 
@@ -84,6 +87,7 @@ namespace {
 
 constexpr double PI = 3.14159265358979323846;
 constexpr int NCH_MODES = 240;
+constexpr int kBatchMax = 4;  // densities per batched local launch
 
 int smooth5_at_least(int n) {
   for (;; ++n) {
@@ -521,14 +525,22 @@ struct LocalArgs {
   const int* col_w;
   const int64_t* near_off;
   const cplx* nearblk;
+  int64_t dens_ld, mode_ld;  // batches: per-density strides of dens and mode_part
 };
 
-__global__ __launch_bounds__(LOC_NT) void k_local_apply(KParams K, LocalArgs L, const cplx* __restrict__ mu,
-                                                        cplx* __restrict__ y) {
+// The work of k_local_apply for NB densities at once: density r is
+// mu + r ldm, its output y + r ldy, its cell densities dens + r dens_ld and its
+// mode partial sums mode_part + r mode_ld.  Each P and near-field entry, and
+// each mode factor, is loaded or formed once and used for all NB densities;
+// every sum of density r is formed in the same order as for a single density,
+// so a batch reproduces single forward maps bit for bit.
+template <int NB>
+__device__ __forceinline__ void local_apply(const KParams& K, const LocalArgs& L, const cplx* __restrict__ mu,
+                                            int64_t ldm, cplx* __restrict__ y, int64_t ldy) {
   __shared__ cplx red[LOC_NT];
-  __shared__ cplx rs[NEAR_ROWS][LOC_NT / 64];  // near-field row sums per wavefront
-  __shared__ cplx mus[LOC_NT];                 // EqSources: staged mu of the cell
-  __shared__ cplx gsum[LOC_NT / 32][128];      // EqSources: per-group sums
+  __shared__ cplx rs[NB][NEAR_ROWS][LOC_NT / 64];  // near-field row sums per wavefront
+  __shared__ cplx mus[NB][LOC_NT];                 // EqSources: staged mu of the cell
+  __shared__ cplx gsum[LOC_NT / 32][128];          // EqSources: per-group sums (one density at a time)
   int b = blockIdx.x;
   if (b < L.n_occ) {
     // EqSources of cell q: dens[o] = sum_t P[t][o] mu_t.  Lane l of each
@@ -543,14 +555,20 @@ __global__ __launch_bounds__(LOC_NT) void k_local_apply(KParams K, LocalArgs L, 
     const int g = threadIdx.x / GL, l = threadIdx.x % GL;
     const int cell = L.occ_cell[q];
     const int off = L.occ_off[q], nq = L.occ_off[q + 1] - off;
-    cplx acc[OPL];
+    cplx acc[NB][OPL];
 #pragma unroll
-    for (int j = 0; j < OPL; ++j) acc[j] = cplx{0.0, 0.0};
+    for (int r = 0; r < NB; ++r)
+#pragma unroll
+      for (int j = 0; j < OPL; ++j) acc[r][j] = cplx{0.0, 0.0};
     const int oc = min(OPL * l, nout - OPL);  // lanes past the row repeat its last piece (not stored)
     for (int c0 = 0; c0 < nq; c0 += LOC_NT) {
       const int nc = min(LOC_NT, nq - c0);
       __syncthreads();
-      if ((int)threadIdx.x < nc) mus[threadIdx.x] = mu[L.perm[off + c0 + threadIdx.x]];
+      if ((int)threadIdx.x < nc) {
+        const int src = L.perm[off + c0 + threadIdx.x];
+#pragma unroll
+        for (int r = 0; r < NB; ++r) mus[r][threadIdx.x] = mu[r * ldm + src];
+      }
       __syncthreads();
       const cplx* pr = L.P + (int64_t)(off + c0) * nout + oc;
       int t = g;
@@ -561,27 +579,39 @@ __global__ __launch_bounds__(LOC_NT) void k_local_apply(KParams K, LocalArgs L, 
 #pragma unroll
           for (int j = 0; j < OPL; ++j) v[u][j] = pr[(int64_t)(t + u * NG) * nout + j];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const cplx m = mus[t + u * NG];
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
-          for (int j = 0; j < OPL; ++j) acc[j] += v[u][j] * m;
-        }
+          for (int r = 0; r < NB; ++r) {
+            const cplx m = mus[r][t + u * NG];
+#pragma unroll
+            for (int j = 0; j < OPL; ++j) acc[r][j] += v[u][j] * m;
+          }
       }
       for (; t < nc; t += NG) {
-        const cplx m = mus[t];
+        cplx v[OPL];
 #pragma unroll
-        for (int j = 0; j < OPL; ++j) acc[j] += pr[(int64_t)t * nout + j] * m;
+        for (int j = 0; j < OPL; ++j) v[j] = pr[(int64_t)t * nout + j];
+#pragma unroll
+        for (int r = 0; r < NB; ++r) {
+          const cplx m = mus[r][t];
+#pragma unroll
+          for (int j = 0; j < OPL; ++j) acc[r][j] += v[j] * m;
+        }
       }
     }
 #pragma unroll
-    for (int j = 0; j < OPL; ++j) gsum[g][OPL * l + j] = acc[j];
-    __syncthreads();
-    if ((int)threadIdx.x < nout) {
-      const int o = threadIdx.x;
-      cplx sm = gsum[0][o];
-      for (int gg = 1; gg < NG; ++gg) sm += gsum[gg][o];
-      const int lam = o / (2 * L.n_eq), oo = o % (2 * L.n_eq);
-      L.dens[((int64_t)lam * L.n_cells + cell) * 2 * L.n_eq + oo] = sm;
+    for (int r = 0; r < NB; ++r) {
+      if (r > 0) __syncthreads();
+#pragma unroll
+      for (int j = 0; j < OPL; ++j) gsum[g][OPL * l + j] = acc[r][j];
+      __syncthreads();
+      if ((int)threadIdx.x < nout) {
+        const int o = threadIdx.x;
+        cplx sm = gsum[0][o];
+        for (int gg = 1; gg < NG; ++gg) sm += gsum[gg][o];
+        const int lam = o / (2 * L.n_eq), oo = o % (2 * L.n_eq);
+        L.dens[r * L.dens_ld + ((int64_t)lam * L.n_cells + cell) * 2 * L.n_eq + oo] = sm;
+      }
     }
     return;
   }
@@ -590,14 +620,21 @@ __global__ __launch_bounds__(LOC_NT) void k_local_apply(KParams K, LocalArgs L, 
     const int per = (K.N + NCH_MODES - 1) / NCH_MODES;
     const int lo = b * per, hi = min(K.N, lo + per);
     for (int t = 0; t < K.nU; ++t) {
-      cplx acc = cplx{0.0, 0.0};
+      cplx acc[NB];
+#pragma unroll
+      for (int r = 0; r < NB; ++r) acc[r] = cplx{0.0, 0.0};
       for (int l = lo + threadIdx.x; l < hi; l += LOC_NT) {
         const double mag = exp(K.Ubi[t] * L.f[l]) * L.J[l] * K.dx;
-        acc += (mag * cexp_i(-(K.Ua[t] * L.x[l] + K.Ubr[t] * L.f[l]))) * mu[l];
+        const cplx e = mag * cexp_i(-(K.Ua[t] * L.x[l] + K.Ubr[t] * L.f[l]));
+#pragma unroll
+        for (int r = 0; r < NB; ++r) acc[r] += e * mu[r * ldm + l];
       }
-      const cplx sm = block_sum<LOC_NT>(acc, red);
-      if (threadIdx.x == 0) L.mode_part[(int64_t)t * NCH_MODES + b] = sm;
-      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < NB; ++r) {
+        const cplx sm = block_sum<LOC_NT>(acc[r], red);
+        if (threadIdx.x == 0) L.mode_part[r * L.mode_ld + (int64_t)t * NCH_MODES + b] = sm;
+        __syncthreads();
+      }
     }
     return;
   }
@@ -612,31 +649,55 @@ __global__ __launch_bounds__(LOC_NT) void k_local_apply(KParams K, LocalArgs L, 
   const int N = L.N;
   const int nr = t1 - t0;
   const cplx* blk = L.nearblk + L.near_off[q] + (int64_t)t0 * w;
-  cplx acc[NEAR_ROWS];
+  cplx acc[NB][NEAR_ROWS];
 #pragma unroll
-  for (int r = 0; r < NEAR_ROWS; ++r) acc[r] = cplx{0.0, 0.0};
+  for (int s = 0; s < NB; ++s)
+#pragma unroll
+    for (int r = 0; r < NEAR_ROWS; ++r) acc[s][r] = cplx{0.0, 0.0};
   for (int u = threadIdx.x; u < w; u += LOC_NT) {
     int l = lo + u;
     l += (l < 0) ? N : ((l >= N) ? -N : 0);
-    const cplx m = mu[l];
+    cplx m[NB];
+#pragma unroll
+    for (int s = 0; s < NB; ++s) m[s] = mu[s * ldm + l];
     cplx v[NEAR_ROWS];
 #pragma unroll
     for (int r = 0; r < NEAR_ROWS; ++r) v[r] = blk[(int64_t)min(r, nr - 1) * w + u];
 #pragma unroll
-    for (int r = 0; r < NEAR_ROWS; ++r) acc[r] += v[r] * m;
+    for (int s = 0; s < NB; ++s)
+#pragma unroll
+      for (int r = 0; r < NEAR_ROWS; ++r) acc[s][r] += v[r] * m[s];
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int r = 0; r < NEAR_ROWS; ++r) {
-    const cplx sm = wave_sum(acc[r]);
-    if (lane == 0) rs[r][wv] = sm;
-  }
+  for (int s = 0; s < NB; ++s)
+#pragma unroll
+    for (int r = 0; r < NEAR_ROWS; ++r) {
+      const cplx sm = wave_sum(acc[s][r]);
+      if (lane == 0) rs[s][r][wv] = sm;
+    }
   __syncthreads();
   if ((int)threadIdx.x < nr) {
-    cplx sm = cplx{0.0, 0.0};
-    for (int k = 0; k < LOC_NT / 64; ++k) sm += rs[threadIdx.x][k];
-    y[L.perm[off + t0 + threadIdx.x]] = sm;
+    const int dst = L.perm[off + t0 + threadIdx.x];
+#pragma unroll
+    for (int s = 0; s < NB; ++s) {
+      cplx sm = cplx{0.0, 0.0};
+      for (int k = 0; k < LOC_NT / 64; ++k) sm += rs[s][threadIdx.x][k];
+      y[s * ldy + dst] = sm;
+    }
   }
+}
+
+__global__ __launch_bounds__(LOC_NT) void k_local_apply(KParams K, LocalArgs L, const cplx* __restrict__ mu,
+                                                        cplx* __restrict__ y) {
+  local_apply<1>(K, L, mu, 0, y, 0);
+}
+
+// NB densities at once (strides ldm, ldy in elements)
+template <int NB>
+__global__ __launch_bounds__(LOC_NT) void k_local_apply_batch(KParams K, LocalArgs L, const cplx* __restrict__ mu,
+                                                              int64_t ldm, cplx* __restrict__ y, int64_t ldy) {
+  local_apply<NB>(K, L, mu, ldm, y, ldy);
 }
 
 struct MergeArgs {
@@ -1498,19 +1559,17 @@ static LocalArgs local_args(const sesm_ctx* ctx, bool near_only) {
   return L;
 }
 
-static int accel_matvec_impl(sesm_ctx* ctx, const cplx* mu, cplx* y, bool keep_far) {
+// The stages after the local launch for one density: merge + forward FFT, y
+// convolution + local corrections, inverse FFT, and the cell far field added
+// to y.  dens and mode_part hold that density's cell densities and mode
+// partial sums; y holds its near field.
+static int accel_far_stages(sesm_ctx* ctx, const cplx* dens, const cplx* mode_part, cplx* y, bool keep_far,
+                            const MatvecBytes& B) {
   AccelOp* A = ctx->acc;
   const Problem& P = ctx->P;
   const KParams K = ctx->kparams();
   hipStream_t st = ctx->stream;
-  const MatvecBytes B = ctx->kt_mask ? matvec_bytes(ctx) : MatvecBytes{};
   int rc;
-  const LocalArgs L = local_args(ctx, false);
-  SESM_KT_BEGIN(SESM_KT_LOCAL, st);
-  hipLaunchKernelGGL(k_local_apply, dim3(L.n_occ + L.n_mode_blocks + L.n_chunks), dim3(LOC_NT), 0, st, K, L, mu,
-                     y);
-  SESM_LAUNCH_CHECK();
-  SESM_KT_END(SESM_KT_LOCAL, st, B.local);
   MergeArgs M{A->n_x, A->n_y, A->n_s, A->n_e, A->n_side, A->n_eq, A->n_cells,
               A->nXH, A->nYH, A->nXV, A->nYV, P.alpha * P.d};
   // merge + forward FFT along x of both grids (rows [kind][gy])
@@ -1518,7 +1577,7 @@ static int accel_matvec_impl(sesm_ctx* ctx, const cplx* mu, cplx* y, bool keep_f
   {
     const FftJob jh = sesm_fft_job(A->planH, 2 * A->nYH, nullptr, A->fH, nullptr, nullptr, 1.0);
     const FftJob jv = sesm_fft_job(A->planV, 2 * A->nYV, nullptr, A->fV, nullptr, nullptr, 1.0);
-    hipLaunchKernelGGL(k_merge_fft, dim3(jh.nblocks + jv.nblocks), dim3(1024), 0, st, M, A->dens, A->twxH, A->twxV,
+    hipLaunchKernelGGL(k_merge_fft, dim3(jh.nblocks + jv.nblocks), dim3(1024), 0, st, M, dens, A->twxH, A->twxV,
                        jh, jv);
     SESM_LAUNCH_CHECK();
   }
@@ -1532,7 +1591,7 @@ static int accel_matvec_impl(sesm_ctx* ctx, const cplx* mu, cplx* y, bool keep_f
     const CorrArgs CA{A->n_groups, A->n_bdry, A->n_bH,   A->n_eq,   A->n_cells, hb + vb,  A->grp_o,
                       A->grp_start, A->grp_n, A->plist, A->grp_rc, A->grp_ph, A->W,      A->corr};
     const size_t lds = std::max(std::max(yconv_lds(A->nYH), yconv_lds(A->nYV)), corr_lds(A->n_eq, A->n_bdry));
-    hipLaunchKernelGGL(k_yconv, dim3(hb + vb + A->n_groups), dim3(256), lds, st, yh, yv, hb, CA, A->dens);
+    hipLaunchKernelGGL(k_yconv, dim3(hb + vb + A->n_groups), dim3(256), lds, st, yh, yv, hb, CA, dens);
     SESM_LAUNCH_CHECK();
   }
   SESM_KT_END(SESM_KT_YCONV, st, B.yconvH + B.yconvV);
@@ -1545,10 +1604,71 @@ static int accel_matvec_impl(sesm_ctx* ctx, const cplx* mu, cplx* y, bool keep_f
             A->nXH, A->nXV, A->ring, A->max_q, A->L, A->x0, A->y0, P.k, P.alpha * P.d};
   SESM_KT_BEGIN(SESM_KT_CELLS, st);
   hipLaunchKernelGGL(k_cells_far, dim3(A->n_occ), dim3(256), cells_far_lds(A), st, F, K, A->occ_cell, A->occ_off,
-                     A->perm, A->pair_off, A->corr, A->phH, A->phV, A->pplw, A->dirs, ctx->x, ctx->f, A->mode_part,
+                     A->perm, A->pair_off, A->corr, A->phH, A->phV, A->pplw, A->dirs, ctx->x, ctx->f, mode_part,
                      y, keep_far ? A->yfar : nullptr);
   SESM_LAUNCH_CHECK();
   SESM_KT_END(SESM_KT_CELLS, st, B.cells);
+  return SESM_OK;
+}
+
+static int accel_matvec_impl(sesm_ctx* ctx, const cplx* mu, cplx* y, bool keep_far) {
+  AccelOp* A = ctx->acc;
+  const KParams K = ctx->kparams();
+  hipStream_t st = ctx->stream;
+  const MatvecBytes B = ctx->kt_mask ? matvec_bytes(ctx) : MatvecBytes{};
+  const LocalArgs L = local_args(ctx, false);
+  SESM_KT_BEGIN(SESM_KT_LOCAL, st);
+  hipLaunchKernelGGL(k_local_apply, dim3(L.n_occ + L.n_mode_blocks + L.n_chunks), dim3(LOC_NT), 0, st, K, L, mu,
+                     y);
+  SESM_LAUNCH_CHECK();
+  SESM_KT_END(SESM_KT_LOCAL, st, B.local);
+  return accel_far_stages(ctx, A->dens, A->mode_part, y, keep_far, B);
+}
+
+template <int NB>
+static void launch_local_batch(hipStream_t st, const KParams& K, const LocalArgs& L, const cplx* mu, int64_t ldm,
+                               cplx* y, int64_t ldy) {
+  hipLaunchKernelGGL(k_local_apply_batch<NB>, dim3(L.n_occ + L.n_mode_blocks + L.n_chunks), dim3(LOC_NT), 0, st, K,
+                     L, mu, ldm, y, ldy);
+}
+
+// Forward maps of nrhs densities (column r at mu + r ldm, output at y + r ldy):
+// groups of up to kBatchMax densities share one local launch, which reads the
+// near-field blocks and P once for the group; the later stages run per density.
+int sesm_accel_matvec_batch(sesm_ctx* ctx, int nrhs, const cplx* mu, int64_t ldm, cplx* y, int64_t ldy) {
+  AccelOp* A = ctx->acc;
+  const KParams K = ctx->kparams();
+  hipStream_t st = ctx->stream;
+  const size_t dens_n = (size_t)2 * A->n_cells * 2 * A->n_eq, mode_n = (size_t)SESM_MAX_UETA * NCH_MODES;
+  int rc;
+  if (!A->dens_b) {
+    if ((rc = sesm_alloc(ctx, (void**)&A->dens_b, sizeof(cplx) * dens_n * kBatchMax)) ||
+        (rc = sesm_alloc(ctx, (void**)&A->mode_b, sizeof(cplx) * mode_n * kBatchMax)))
+      return rc;
+    // cells without nodes are never written: their densities stay zero
+    SESM_HIP(hipMemsetAsync(A->dens_b, 0, sizeof(cplx) * dens_n * kBatchMax, st));
+  }
+  const MatvecBytes B = ctx->kt_mask ? matvec_bytes(ctx) : MatvecBytes{};  // per density (far stages)
+  LocalArgs L = local_args(ctx, false);
+  L.dens = A->dens_b;
+  L.mode_part = A->mode_b;
+  L.dens_ld = (int64_t)dens_n;
+  L.mode_ld = (int64_t)mode_n;
+  for (int r0 = 0; r0 < nrhs; r0 += kBatchMax) {
+    const int nb = std::min(kBatchMax, nrhs - r0);
+    const cplx* m0 = mu + r0 * ldm;
+    cplx* y0 = y + r0 * ldy;
+    switch (nb) {
+      case 1: launch_local_batch<1>(st, K, L, m0, ldm, y0, ldy); break;
+      case 2: launch_local_batch<2>(st, K, L, m0, ldm, y0, ldy); break;
+      case 3: launch_local_batch<3>(st, K, L, m0, ldm, y0, ldy); break;
+      default: launch_local_batch<4>(st, K, L, m0, ldm, y0, ldy); break;
+    }
+    SESM_LAUNCH_CHECK();
+    for (int r = 0; r < nb; ++r)
+      if ((rc = accel_far_stages(ctx, A->dens_b + r * dens_n, A->mode_b + r * mode_n, y0 + r * ldy, false, B)))
+        return rc;
+  }
   return SESM_OK;
 }
 

@@ -417,6 +417,27 @@ int sesm_matvec(sesm_ctx* ctx, const sesm_c64* mu, sesm_c64* y) {
   return sesm_apply(ctx, (const cplx*)mu, (cplx*)y);
 }
 
+int sesm_matvec_batch(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* mu, int64_t ld_mu, sesm_c64* y, int64_t ld_y) {
+  if (!ctx) return SESM_EINVAL;
+  if (!ctx->ready) return ctx->fail(SESM_ENOSURF, "no surface");
+  if (nrhs < 0) return ctx->fail(SESM_EINVAL, "negative number of densities");
+  if (nrhs == 0) return SESM_OK;
+  const int64_t N = ctx->P.N;
+  if (!mu || !y) return ctx->fail(SESM_EINVAL, "null pointer");
+  if (ld_mu < N || ld_y < N) return ctx->fail(SESM_EINVAL, "leading dimension below N");
+  // the two spans [p, p + (nrhs - 1) ld + N) must be disjoint
+  const uintptr_t m0 = (uintptr_t)mu, m1 = (uintptr_t)(mu + (nrhs - 1) * ld_mu + N);
+  const uintptr_t y0 = (uintptr_t)y, y1 = (uintptr_t)(y + (nrhs - 1) * ld_y + N);
+  if (m0 < y1 && y0 < m1) return ctx->fail(SESM_EINVAL, "densities and outputs overlap");
+  SESM_HIP(hipSetDevice(ctx->device));
+  if (ctx->P.mode == SESM_MODE_ACCEL) return sesm_accel_matvec_batch(ctx, nrhs, (const cplx*)mu, ld_mu, (cplx*)y, ld_y);
+  for (int r = 0; r < nrhs; ++r) {
+    const int rc = sesm_dense_matvec(ctx, (const cplx*)(mu + r * ld_mu), (cplx*)(y + r * ld_y));
+    if (rc) return rc;
+  }
+  return SESM_OK;
+}
+
 int sesm_rhs(sesm_ctx* ctx, sesm_c64* b) {
   if (!ctx) return SESM_EINVAL;
   if (!ctx->ready) return ctx->fail(SESM_ENOSURF, "no surface");

@@ -147,6 +147,7 @@ int sesm_dense_matvec(sesm_ctx* ctx, const cplx* mu, cplx* y);
 // accelerated path (sesm_accel.hip)
 int sesm_accel_setup(sesm_ctx* ctx);
 int sesm_accel_matvec(sesm_ctx* ctx, const cplx* mu, cplx* y);
+int sesm_accel_matvec_batch(sesm_ctx* ctx, int nrhs, const cplx* mu, int64_t ldm, cplx* y, int64_t ldy);
 void sesm_accel_free(sesm_ctx* ctx);
 void sesm_accel_info(const sesm_ctx* ctx, sesm_surface_info* info);
 

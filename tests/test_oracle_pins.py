@@ -272,6 +272,25 @@ def test_translation_covariance():
     assert np.max(np.abs(e2 - e1)) < 1e-11
 
 
+def test_bloch_class_operator():
+    """Incidences whose Bloch wavenumbers differ by 2 pi / d see the same
+    operator: the quasi-periodic Green function depends on alpha only through
+    e^{i alpha d p} (eq. shifted_periodic_green_function), and the completion
+    modes of eq. (M_eta) only through the set {alpha_n}, which the shift
+    relabels n -> n + 1.  Only the right-hand side differs.  A Bloch phase
+    taken from alpha anywhere else (a lattice or image phase without the
+    period, modes indexed by n instead of alpha_n) breaks the identity."""
+    wl = W.config_dense_sinusoid(64).with_(theta_deg=11.0)  # U^eta = {-3}: mode n = -3 barely evanescent
+    s1 = math.sin(math.radians(wl.theta_deg)) - 2 * math.pi / (wl.k * wl.d)
+    wl2 = wl.with_(theta_deg=math.degrees(math.asin(s1)))
+    assert abs(wl2.alpha - (wl.alpha - 2 * math.pi / wl.d)) < 1e-12
+    d1, d2 = dense.Discretization(wl), dense.Discretization(wl2)
+    assert list(d2.U_eta) == [n + 1 for n in d1.U_eta] and len(d1.U_eta) > 0
+    M1, M2 = dense.operator_matrix(d1), dense.operator_matrix(d2)
+    assert np.max(np.abs(M2 - M1)) < 1e-11 * np.max(np.abs(M1))
+    assert np.max(np.abs(dense.rhs(d2) - dense.rhs(d1))) > 0.1
+
+
 def test_window_convergence():
     """Convergence in the window half-width A (Sec. 3, windowed lattice sums):
     away from a Wood anomaly the efficiencies converge faster than any power
