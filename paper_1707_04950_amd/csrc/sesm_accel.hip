@@ -77,9 +77,9 @@ struct AccelOp {
   cplx* grp_ph = nullptr;  // wrap phase per pair, in plist order
   cplx* corr = nullptr;  // [n_pairs][n_bdry]
   cplx* yfar = nullptr;  // diagnostic copy of the far-field contribution
-  // batched forward maps: cell densities and mode partial sums of up to
-  // kBatchMax densities (allocated at the first batched call)
-  cplx *dens_b = nullptr, *mode_b = nullptr;
+  // batched forward maps: the per-density work buffers of up to kBatchMax
+  // densities (allocated at the first batched call)
+  cplx* batch_ws = nullptr;
   FftPlan planH, planV;
 };
 
@@ -720,6 +720,7 @@ struct CorrArgs {
   const cplx* grp_ph;    // quasi-periodic phase of each pair, in plist order
   const cplx* W;
   cplx* corr;
+  int64_t bcorr, bdens;  // batched launches: corr and dens of batch member blockIdx.y are offset by these
 };
 constexpr int CORR_PPW = 3;              // pairs per wavefront
 constexpr int CORR_PPB = 4 * CORR_PPW;   // pairs per correction workgroup (all share one matrix W_o)
@@ -852,12 +853,32 @@ __global__ __launch_bounds__(1024) void k_merge_fft(MergeArgs M, const cplx* __r
   sesm_fft_block(J, blk, -1, [=](int r, int i) { return merge_point(Mv, dens, tw, php, onH, r / nY, r % nY, i); });
 }
 
+// The same for several batch members: grid dimension y runs over them, member
+// m reading dens + m fb.bin0 and writing the H grid at + m fb.bout0 and the V
+// grid at + m fb.bout1.
+__global__ __launch_bounds__(1024) void k_merge_fft_batch(MergeArgs M, const cplx* __restrict__ dens,
+                                                          const cplx* __restrict__ twH, const cplx* __restrict__ twV,
+                                                          FftJob jh, FftJob jv, FftBatch fb) {
+  const bool onH = (int)blockIdx.x < jh.nblocks;
+  FftJob J = onH ? jh : jv;
+  const int64_t m = blockIdx.y;
+  J.out += m * (onH ? fb.bout0 : fb.bout1);
+  const cplx* db = dens + m * fb.bin0;
+  const int blk = onH ? blockIdx.x : blockIdx.x - jh.nblocks;
+  const int nY = onH ? M.nYH : M.nYV;
+  const cplx* tw = onH ? twH : twV;
+  const cplx php = cexp_i(M.alpha_d);
+  const MergeArgs Mv = M;
+  sesm_fft_block(J, blk, -1, [=](int r, int i) { return merge_point(Mv, db, tw, php, onH, r / nY, r % nY, i); });
+}
+
 // One grid of the y-direction convolution.
 struct YConvJob {
   int nX, nY;
   const cplx* spec;  // kernel spectra [2][2nY-1][nX]
   const cplx* g;     // source spectra [2][nY][nX]
   cplx* out;         // [nY][nX]
+  int64_t bg, bout;  // batched launches: g and out of batch member blockIdx.y are offset by these
 };
 
 // phi_hat[t][kx] = sum_t' spec0[t-t'+nY-1][kx] g0[t'][kx] + spec1[...] g1[t'][kx].
@@ -877,11 +898,15 @@ __global__ __launch_bounds__(256) void k_yconv(YConvJob h, YConvJob v, int hbloc
                                                const cplx* __restrict__ dens) {
   extern __shared__ cplx col[];
   if ((int)blockIdx.x >= C.merge_blocks) {  // the local corrections share the launch
-    local_corr_group(C, dens);
+    CorrArgs Cb = C;
+    Cb.corr += (int64_t)blockIdx.y * C.bcorr;
+    local_corr_group(Cb, dens + (int64_t)blockIdx.y * C.bdens);
     return;
   }
   const bool first = (int)blockIdx.x < hblocks;
-  const YConvJob& J = first ? h : v;
+  YConvJob J = first ? h : v;
+  J.g += (int64_t)blockIdx.y * J.bg;
+  J.out += (int64_t)blockIdx.y * J.bout;
   const int b = first ? blockIdx.x : blockIdx.x - hblocks;
   const int nX = J.nX, nY = J.nY;
   const int nrow = 2 * nY - 1, per = 6 * nY - 2;
@@ -942,6 +967,8 @@ __global__ __launch_bounds__(256) void k_yconv(YConvJob h, YConvJob v, int hbloc
 struct FarArgs {
   int N, n_x, n_y, n_s, n_e, n_side, n_eq, n_cells, n_bdry, n_bH, n_plw, nXH, nXV, ring, max_q;
   double L, x0, y0, k, alpha_d;
+  // batched launches: per-member offsets of corr, phH, phV, mode_part and y
+  int64_t bcorr, bphH, bphV, bmode, by;
 };
 
 // One block per occupied cell: boundary values of phi^all (H on horizontal
@@ -951,7 +978,8 @@ struct FarArgs {
 // k_local_apply).  Dynamic LDS: the plane-wave factors ((U^H)^T, V, 1/sig),
 // the cell's nodes and their values.  Each phase keeps its global loads
 // independent so that they are in flight together.
-__global__ __launch_bounds__(256) void k_cells_far(FarArgs A, KParams K, const int* __restrict__ occ_cell,
+template <bool BATCHED>
+__device__ __forceinline__ void cells_far_body(FarArgs A, KParams K, const int* __restrict__ occ_cell,
                                                    const int* __restrict__ occ_off, const int* __restrict__ perm,
                                                    const int* __restrict__ pair_off, const cplx* __restrict__ corr,
                                                    const cplx* __restrict__ phH, const cplx* __restrict__ phV,
@@ -963,6 +991,14 @@ __global__ __launch_bounds__(256) void k_cells_far(FarArgs A, KParams K, const i
   __shared__ cplx bv[64];
   __shared__ cplx wv_sh[64];
   __shared__ cplx msum[SESM_MAX_UETA];
+  if (BATCHED) {  // batch member blockIdx.y
+    const int64_t m = blockIdx.y;
+    corr += m * A.bcorr;
+    phH += m * A.bphH;
+    phV += m * A.bphV;
+    mode_part += m * A.bmode;
+    y += m * A.by;
+  }
   const int q = blockIdx.x;
   const int cell = occ_cell[q];
   const int cx = cell % A.n_x, cy = cell / A.n_x;
@@ -1097,6 +1133,21 @@ __global__ __launch_bounds__(256) void k_cells_far(FarArgs A, KParams K, const i
   }
 }
 
+#define SESM_CELLS_FAR_PARAMS                                                                                       \
+  FarArgs A, KParams K, const int *__restrict__ occ_cell, const int *__restrict__ occ_off,                         \
+      const int *__restrict__ perm, const int *__restrict__ pair_off, const cplx *__restrict__ corr,              \
+      const cplx *__restrict__ phH, const cplx *__restrict__ phV, const cplx *__restrict__ pplw,                 \
+      const double *__restrict__ dirs, const double *__restrict__ x, const double *__restrict__ f,               \
+      const cplx *__restrict__ mode_part, cplx *__restrict__ y, cplx *__restrict__ yfar
+__global__ __launch_bounds__(256) void k_cells_far(SESM_CELLS_FAR_PARAMS) {
+  cells_far_body<false>(A, K, occ_cell, occ_off, perm, pair_off, corr, phH, phV, pplw, dirs, x, f, mode_part, y, yfar);
+}
+// grid dimension y: batch members (offsets in A)
+__global__ __launch_bounds__(256) void k_cells_far_batch(SESM_CELLS_FAR_PARAMS) {
+  cells_far_body<true>(A, K, occ_cell, occ_off, perm, pair_off, corr, phH, phV, pplw, dirs, x, f, mode_part, y, yfar);
+}
+#undef SESM_CELLS_FAR_PARAMS
+
 // dynamic LDS bytes of k_cells_far
 inline size_t cells_far_lds(const AccelOp* A) {
   const size_t npf = (size_t)(A->n_bdry + A->n_plw + 1) * A->n_plw;
@@ -1128,11 +1179,17 @@ CellGeo cell_geo(const AccelOp& A) {
 }
 
 // One launch of k_fft_rows for up to two jobs (j1 may be empty).
-int fft_launch(sesm_ctx* ctx, hipStream_t st, const FftJob& j0, const FftJob& j1, int sign) {
+// Both jobs in one launch; members > 1 run the same jobs on further buffers
+// (per-member offsets fb).
+int fft_launch(sesm_ctx* ctx, hipStream_t st, const FftJob& j0, const FftJob& j1, int sign, int members = 1,
+               FftBatch fb = FftBatch{}) {
   const int nb = j0.nblocks + j1.nblocks;
   if (nb == 0) return SESM_OK;
   const bool wide = (j0.nblocks && j0.A.n * j0.rpb >= 1000) || (j1.nblocks && j1.A.n * j1.rpb >= 1000);
-  hipLaunchKernelGGL(k_fft_rows, dim3(nb), dim3(wide ? 1024 : 256), 0, st, j0, j1, sign);
+  if (members > 1)
+    hipLaunchKernelGGL(k_fft_rows_batch, dim3(nb, members), dim3(wide ? 1024 : 256), 0, st, j0, j1, sign, fb);
+  else
+    hipLaunchKernelGGL(k_fft_rows, dim3(nb), dim3(wide ? 1024 : 256), 0, st, j0, j1, sign);
   SESM_LAUNCH_CHECK();
   return SESM_OK;
 }
@@ -1369,8 +1426,11 @@ int sesm_accel_setup(sesm_ctx* ctx) {
   {
     const size_t lds = cells_far_lds(A);
     if (lds > 140 * 1024) return ctx->fail(SESM_EINVAL, "accelerator: plane-wave factors exceed the LDS of a workgroup");
-    if (lds > 64 * 1024)
+    if (lds > 64 * 1024) {
       SESM_HIP(hipFuncSetAttribute((const void*)k_cells_far, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      SESM_HIP(
+          hipFuncSetAttribute((const void*)k_cells_far_batch, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    }
   }
   {
     const int64_t nW = (int64_t)A->n_off * A->n_bdry * ncol;
@@ -1559,55 +1619,75 @@ static LocalArgs local_args(const sesm_ctx* ctx, bool near_only) {
   return L;
 }
 
-// The stages after the local launch for one density: merge + forward FFT, y
-// convolution + local corrections, inverse FFT, and the cell far field added
-// to y.  dens and mode_part hold that density's cell densities and mode
-// partial sums; y holds its near field.
-static int accel_far_stages(sesm_ctx* ctx, const cplx* dens, const cplx* mode_part, cplx* y, bool keep_far,
-                            const MatvecBytes& B) {
+// Work buffers of the stages after the local launch, for nb densities at
+// once: member m's buffers are the base pointers plus m times the strides.
+struct FarBufs {
+  int nb;
+  const cplx *dens, *mode;
+  cplx *fH, *fV, *gH, *gV, *phH, *phV, *corr, *y;
+  int64_t bdens, bmode, bfH, bfV, bgH, bgV, bphH, bphV, bcorr, by;
+};
+
+// The stages after the local launch: merge + forward FFT, y convolution +
+// local corrections, inverse FFT, and the cell far field added to y, each one
+// launch for all nb densities (grid dimension y = batch member).  dens and
+// mode hold the densities' cell densities and mode partial sums; y holds
+// their near fields.
+static int accel_far_stages(sesm_ctx* ctx, const FarBufs& Fb, bool keep_far, const MatvecBytes& B) {
   AccelOp* A = ctx->acc;
   const Problem& P = ctx->P;
   const KParams K = ctx->kparams();
   hipStream_t st = ctx->stream;
+  const int nb = Fb.nb;
   int rc;
   MergeArgs M{A->n_x, A->n_y, A->n_s, A->n_e, A->n_side, A->n_eq, A->n_cells,
               A->nXH, A->nYH, A->nXV, A->nYV, P.alpha * P.d};
   // merge + forward FFT along x of both grids (rows [kind][gy])
   SESM_KT_BEGIN(SESM_KT_MERGE, st);
   {
-    const FftJob jh = sesm_fft_job(A->planH, 2 * A->nYH, nullptr, A->fH, nullptr, nullptr, 1.0);
-    const FftJob jv = sesm_fft_job(A->planV, 2 * A->nYV, nullptr, A->fV, nullptr, nullptr, 1.0);
-    hipLaunchKernelGGL(k_merge_fft, dim3(jh.nblocks + jv.nblocks), dim3(1024), 0, st, M, dens, A->twxH, A->twxV,
-                       jh, jv);
+    const FftJob jh = sesm_fft_job(A->planH, 2 * A->nYH, nullptr, Fb.fH, nullptr, nullptr, 1.0);
+    const FftJob jv = sesm_fft_job(A->planV, 2 * A->nYV, nullptr, Fb.fV, nullptr, nullptr, 1.0);
+    if (nb > 1)
+      hipLaunchKernelGGL(k_merge_fft_batch, dim3(jh.nblocks + jv.nblocks, nb), dim3(1024), 0, st, M, Fb.dens,
+                         A->twxH, A->twxV, jh, jv, FftBatch{Fb.bdens, Fb.bfH, 0, Fb.bfV});
+    else
+      hipLaunchKernelGGL(k_merge_fft, dim3(jh.nblocks + jv.nblocks), dim3(1024), 0, st, M, Fb.dens, A->twxH, A->twxV,
+                         jh, jv);
     SESM_LAUNCH_CHECK();
   }
-  SESM_KT_END(SESM_KT_MERGE, st, B.merge);
+  SESM_KT_END(SESM_KT_MERGE, st, nb * B.merge);
   // y convolution of both grids, with the local corrections in the same launch
   SESM_KT_BEGIN(SESM_KT_YCONV, st);
   {
-    const YConvJob yh{A->nXH, A->nYH, A->specH, A->fH, A->gH}, yv{A->nXV, A->nYV, A->specV, A->fV, A->gV};
+    const YConvJob yh{A->nXH, A->nYH, A->specH, Fb.fH, Fb.gH, Fb.bfH, Fb.bgH};
+    const YConvJob yv{A->nXV, A->nYV, A->specV, Fb.fV, Fb.gV, Fb.bfV, Fb.bgV};
     const int hb = (A->nXH + yconv_kpb(A->nYH) - 1) / yconv_kpb(A->nYH);
     const int vb = (A->nXV + yconv_kpb(A->nYV) - 1) / yconv_kpb(A->nYV);
     const CorrArgs CA{A->n_groups, A->n_bdry, A->n_bH,   A->n_eq,   A->n_cells, hb + vb,  A->grp_o,
-                      A->grp_start, A->grp_n, A->plist, A->grp_rc, A->grp_ph, A->W,      A->corr};
+                      A->grp_start, A->grp_n, A->plist, A->grp_rc, A->grp_ph, A->W,      Fb.corr,
+                      Fb.bcorr,     Fb.bdens};
     const size_t lds = std::max(std::max(yconv_lds(A->nYH), yconv_lds(A->nYV)), corr_lds(A->n_eq, A->n_bdry));
-    hipLaunchKernelGGL(k_yconv, dim3(hb + vb + A->n_groups), dim3(256), lds, st, yh, yv, hb, CA, dens);
+    hipLaunchKernelGGL(k_yconv, dim3(hb + vb + A->n_groups, nb), dim3(256), lds, st, yh, yv, hb, CA, Fb.dens);
     SESM_LAUNCH_CHECK();
   }
-  SESM_KT_END(SESM_KT_YCONV, st, B.yconvH + B.yconvV);
+  SESM_KT_END(SESM_KT_YCONV, st, nb * (B.yconvH + B.yconvV));
   SESM_KT_BEGIN(SESM_KT_FFT, st);
-  if ((rc = fft_launch(ctx, st, sesm_fft_job(A->planH, A->nYH, A->gH, A->phH, nullptr, A->utwH, 1.0 / A->nXH),
-                       sesm_fft_job(A->planV, A->nYV, A->gV, A->phV, nullptr, A->utwV, 1.0 / A->nXV), +1)))
-    return rc;
-  SESM_KT_END(SESM_KT_FFT, st, B.fftH1 + B.fftV1);
-  FarArgs F{P.N, A->n_x, A->n_y, A->n_s, A->n_e, A->n_side, A->n_eq, A->n_cells, A->n_bdry, A->n_bH, A->n_plw,
-            A->nXH, A->nXV, A->ring, A->max_q, A->L, A->x0, A->y0, P.k, P.alpha * P.d};
+  {
+    const FftJob jh = sesm_fft_job(A->planH, A->nYH, Fb.gH, Fb.phH, nullptr, A->utwH, 1.0 / A->nXH);
+    const FftJob jv = sesm_fft_job(A->planV, A->nYV, Fb.gV, Fb.phV, nullptr, A->utwV, 1.0 / A->nXV);
+    if ((rc = fft_launch(ctx, st, jh, jv, +1, nb, FftBatch{Fb.bgH, Fb.bphH, Fb.bgV, Fb.bphV}))) return rc;
+  }
+  SESM_KT_END(SESM_KT_FFT, st, nb * (B.fftH1 + B.fftV1));
+  FarArgs F{P.N,    A->n_x,   A->n_y,   A->n_s,    A->n_e, A->n_side, A->n_eq, A->n_cells, A->n_bdry, A->n_bH,
+            A->n_plw, A->nXH, A->nXV,   A->ring,   A->max_q, A->L,   A->x0,     A->y0,   P.k,        P.alpha * P.d,
+            Fb.bcorr, Fb.bphH, Fb.bphV, Fb.bmode, Fb.by};
   SESM_KT_BEGIN(SESM_KT_CELLS, st);
-  hipLaunchKernelGGL(k_cells_far, dim3(A->n_occ), dim3(256), cells_far_lds(A), st, F, K, A->occ_cell, A->occ_off,
-                     A->perm, A->pair_off, A->corr, A->phH, A->phV, A->pplw, A->dirs, ctx->x, ctx->f, mode_part,
-                     y, keep_far ? A->yfar : nullptr);
+  hipLaunchKernelGGL(nb > 1 ? k_cells_far_batch : k_cells_far, dim3(A->n_occ, nb), dim3(256), cells_far_lds(A), st,
+                     F, K, A->occ_cell,
+                     A->occ_off, A->perm, A->pair_off, Fb.corr, Fb.phH, Fb.phV, A->pplw, A->dirs, ctx->x, ctx->f,
+                     Fb.mode, Fb.y, keep_far ? A->yfar : nullptr);
   SESM_LAUNCH_CHECK();
-  SESM_KT_END(SESM_KT_CELLS, st, B.cells);
+  SESM_KT_END(SESM_KT_CELLS, st, nb * B.cells);
   return SESM_OK;
 }
 
@@ -1622,7 +1702,19 @@ static int accel_matvec_impl(sesm_ctx* ctx, const cplx* mu, cplx* y, bool keep_f
                      y);
   SESM_LAUNCH_CHECK();
   SESM_KT_END(SESM_KT_LOCAL, st, B.local);
-  return accel_far_stages(ctx, A->dens, A->mode_part, y, keep_far, B);
+  FarBufs Fb{};
+  Fb.nb = 1;
+  Fb.dens = A->dens;
+  Fb.mode = A->mode_part;
+  Fb.fH = A->fH;
+  Fb.fV = A->fV;
+  Fb.gH = A->gH;
+  Fb.gV = A->gV;
+  Fb.phH = A->phH;
+  Fb.phV = A->phV;
+  Fb.corr = A->corr;
+  Fb.y = y;
+  return accel_far_stages(ctx, Fb, keep_far, B);
 }
 
 template <int NB>
@@ -1632,28 +1724,61 @@ static void launch_local_batch(hipStream_t st, const KParams& K, const LocalArgs
                      L, mu, ldm, y, ldy);
 }
 
-// Forward maps of nrhs densities (column r at mu + r ldm, output at y + r ldy):
-// groups of up to kBatchMax densities share one local launch, which reads the
-// near-field blocks and P once for the group; the later stages run per density.
+// Forward maps of nrhs densities (column r at mu + r ldm, output at y + r ldy)
+// in groups of up to kBatchMax densities: one local launch per group reads the
+// near-field blocks and P once for the group, and each later stage is one
+// launch for the group.
 int sesm_accel_matvec_batch(sesm_ctx* ctx, int nrhs, const cplx* mu, int64_t ldm, cplx* y, int64_t ldy) {
   AccelOp* A = ctx->acc;
   const KParams K = ctx->kparams();
   hipStream_t st = ctx->stream;
+  const size_t nH = (size_t)A->nXH * A->nYH, nV = (size_t)A->nXV * A->nYV;
   const size_t dens_n = (size_t)2 * A->n_cells * 2 * A->n_eq, mode_n = (size_t)SESM_MAX_UETA * NCH_MODES;
+  const size_t corr_n = (size_t)std::max(1, A->n_pairs) * A->n_bdry;
+  // per member: dens, mode, fH, fV, gH, gV, phH, phV, corr
+  const size_t per[9] = {dens_n, mode_n, 2 * nH, 2 * nV, 2 * nH, 2 * nV, nH, nV, corr_n};
   int rc;
-  if (!A->dens_b) {
-    if ((rc = sesm_alloc(ctx, (void**)&A->dens_b, sizeof(cplx) * dens_n * kBatchMax)) ||
-        (rc = sesm_alloc(ctx, (void**)&A->mode_b, sizeof(cplx) * mode_n * kBatchMax)))
-      return rc;
+  if (!A->batch_ws) {
+    size_t tot = 0;
+    for (size_t v : per) tot += v;
+    if ((rc = sesm_alloc(ctx, (void**)&A->batch_ws, sizeof(cplx) * tot * kBatchMax))) return rc;
     // cells without nodes are never written: their densities stay zero
-    SESM_HIP(hipMemsetAsync(A->dens_b, 0, sizeof(cplx) * dens_n * kBatchMax, st));
+    SESM_HIP(hipMemsetAsync(A->batch_ws, 0, sizeof(cplx) * dens_n * kBatchMax, st));
   }
-  const MatvecBytes B = ctx->kt_mask ? matvec_bytes(ctx) : MatvecBytes{};  // per density (far stages)
+  cplx* base[9];
+  {
+    cplx* p = A->batch_ws;
+    for (int i = 0; i < 9; ++i) {
+      base[i] = p;
+      p += per[i] * kBatchMax;
+    }
+  }
+  const MatvecBytes B = ctx->kt_mask ? matvec_bytes(ctx) : MatvecBytes{};  // per density (later stages)
   LocalArgs L = local_args(ctx, false);
-  L.dens = A->dens_b;
-  L.mode_part = A->mode_b;
+  L.dens = base[0];
+  L.mode_part = base[1];
   L.dens_ld = (int64_t)dens_n;
   L.mode_ld = (int64_t)mode_n;
+  FarBufs Fb{};
+  Fb.dens = base[0];
+  Fb.mode = base[1];
+  Fb.fH = base[2];
+  Fb.fV = base[3];
+  Fb.gH = base[4];
+  Fb.gV = base[5];
+  Fb.phH = base[6];
+  Fb.phV = base[7];
+  Fb.corr = base[8];
+  Fb.bdens = (int64_t)per[0];
+  Fb.bmode = (int64_t)per[1];
+  Fb.bfH = (int64_t)per[2];
+  Fb.bfV = (int64_t)per[3];
+  Fb.bgH = (int64_t)per[4];
+  Fb.bgV = (int64_t)per[5];
+  Fb.bphH = (int64_t)per[6];
+  Fb.bphV = (int64_t)per[7];
+  Fb.bcorr = (int64_t)per[8];
+  Fb.by = ldy;
   for (int r0 = 0; r0 < nrhs; r0 += kBatchMax) {
     const int nb = std::min(kBatchMax, nrhs - r0);
     const cplx* m0 = mu + r0 * ldm;
@@ -1665,9 +1790,9 @@ int sesm_accel_matvec_batch(sesm_ctx* ctx, int nrhs, const cplx* mu, int64_t ldm
       default: launch_local_batch<4>(st, K, L, m0, ldm, y0, ldy); break;
     }
     SESM_LAUNCH_CHECK();
-    for (int r = 0; r < nb; ++r)
-      if ((rc = accel_far_stages(ctx, A->dens_b + r * dens_n, A->mode_b + r * mode_n, y0 + r * ldy, false, B)))
-        return rc;
+    Fb.nb = nb;
+    Fb.y = y0;
+    if ((rc = accel_far_stages(ctx, Fb, false, B))) return rc;
   }
   return SESM_OK;
 }

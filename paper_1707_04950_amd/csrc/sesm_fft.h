@@ -119,6 +119,12 @@ struct FftJob {
   double scale;
 };
 
+// Batched launches of two jobs: member blockIdx.y reads in + m bin and writes
+// out + m bout of each job.
+struct FftBatch {
+  int64_t bin0, bout0, bin1, bout1;
+};
+
 // The transform of one workgroup's rows of job J: the rows' elements come
 // from load(row, col) (row of the job, column 0..n-1), two per thread in
 // flight; the passes run in LDS; out = scale * transform . post.
@@ -177,6 +183,23 @@ __global__ __launch_bounds__(1024) void k_fft_rows(FftJob j0, FftJob j1, int sig
   const int blk = first ? blockIdx.x : blockIdx.x - j0.nblocks;
   const int n = J.A.n;
   const cplx* in = J.in;
+  const cplx* pre = J.pre;
+  sesm_fft_block(J, blk, sign, [=](int r, int i) {
+    const cplx v = in[(int64_t)r * n + i];
+    return pre ? v * pre[i] : v;
+  });
+}
+
+// The same for several batch members: grid dimension y runs over them, member
+// m reading in + m bin and writing out + m bout of its job.
+__global__ __launch_bounds__(1024) void k_fft_rows_batch(FftJob j0, FftJob j1, int sign, FftBatch fb) {
+  const bool first = (int)blockIdx.x < j0.nblocks;
+  FftJob J = first ? j0 : j1;
+  const int64_t m = blockIdx.y;
+  J.out += m * (first ? fb.bout0 : fb.bout1);
+  const int blk = first ? blockIdx.x : blockIdx.x - j0.nblocks;
+  const int n = J.A.n;
+  const cplx* in = J.in + m * (first ? fb.bin0 : fb.bin1);
   const cplx* pre = J.pre;
   sesm_fft_block(J, blk, sign, [=](int r, int i) {
     const cplx v = in[(int64_t)r * n + i];
