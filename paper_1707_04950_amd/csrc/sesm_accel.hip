@@ -550,6 +550,7 @@ __device__ __forceinline__ void local_apply(const KParams& K, const LocalArgs& L
     // sums are added in LDS in a fixed order.
     static_assert(LOC_NT == 256, "eight groups of 32 lanes");
     constexpr int OPL = 4, GL = 32, NG = LOC_NT / GL;
+    constexpr int PU = NB >= 4 ? 1 : (NB >= 3 ? 2 : 4);  // nodes' loads in flight per group (registers: NB OPL sums)
     const int q = b;
     const int nout = 4 * L.n_eq;  // <= 128 = GL OPL
     const int g = threadIdx.x / GL, l = threadIdx.x % GL;
@@ -572,14 +573,14 @@ __device__ __forceinline__ void local_apply(const KParams& K, const LocalArgs& L
       __syncthreads();
       const cplx* pr = L.P + (int64_t)(off + c0) * nout + oc;
       int t = g;
-      for (; t + 3 * NG < nc; t += 4 * NG) {
-        cplx v[4][OPL];
+      for (; t + (PU - 1) * NG < nc; t += PU * NG) {
+        cplx v[PU][OPL];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < PU; ++u)
 #pragma unroll
           for (int j = 0; j < OPL; ++j) v[u][j] = pr[(int64_t)(t + u * NG) * nout + j];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < PU; ++u)
 #pragma unroll
           for (int r = 0; r < NB; ++r) {
             const cplx m = mus[r][t + u * NG];
@@ -649,33 +650,40 @@ __device__ __forceinline__ void local_apply(const KParams& K, const LocalArgs& L
   const int N = L.N;
   const int nr = t1 - t0;
   const cplx* blk = L.nearblk + L.near_off[q] + (int64_t)t0 * w;
-  cplx acc[NB][NEAR_ROWS];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // rows in passes of RP (for several densities: fewer accumulators, more
+  // waves); the sum of each row is formed in the same order either way
+  constexpr int RP = NB >= 3 ? NEAR_ROWS / 2 : NEAR_ROWS;
 #pragma unroll
-  for (int s = 0; s < NB; ++s)
-#pragma unroll
-    for (int r = 0; r < NEAR_ROWS; ++r) acc[s][r] = cplx{0.0, 0.0};
-  for (int u = threadIdx.x; u < w; u += LOC_NT) {
-    int l = lo + u;
-    l += (l < 0) ? N : ((l >= N) ? -N : 0);
-    cplx m[NB];
-#pragma unroll
-    for (int s = 0; s < NB; ++s) m[s] = mu[s * ldm + l];
-    cplx v[NEAR_ROWS];
-#pragma unroll
-    for (int r = 0; r < NEAR_ROWS; ++r) v[r] = blk[(int64_t)min(r, nr - 1) * w + u];
+  for (int r0 = 0; r0 < NEAR_ROWS; r0 += RP) {
+    if (r0 >= nr) break;  // workgroup-uniform
+    cplx acc[NB][RP];
 #pragma unroll
     for (int s = 0; s < NB; ++s)
 #pragma unroll
-      for (int r = 0; r < NEAR_ROWS; ++r) acc[s][r] += v[r] * m[s];
-  }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+      for (int r = 0; r < RP; ++r) acc[s][r] = cplx{0.0, 0.0};
+    for (int u = threadIdx.x; u < w; u += LOC_NT) {
+      int l = lo + u;
+      l += (l < 0) ? N : ((l >= N) ? -N : 0);
+      cplx m[NB];
 #pragma unroll
-  for (int s = 0; s < NB; ++s)
+      for (int s = 0; s < NB; ++s) m[s] = mu[s * ldm + l];
+      cplx v[RP];
 #pragma unroll
-    for (int r = 0; r < NEAR_ROWS; ++r) {
-      const cplx sm = wave_sum(acc[s][r]);
-      if (lane == 0) rs[s][r][wv] = sm;
+      for (int r = 0; r < RP; ++r) v[r] = blk[(int64_t)min(r0 + r, nr - 1) * w + u];
+#pragma unroll
+      for (int s = 0; s < NB; ++s)
+#pragma unroll
+        for (int r = 0; r < RP; ++r) acc[s][r] += v[r] * m[s];
     }
+#pragma unroll
+    for (int s = 0; s < NB; ++s)
+#pragma unroll
+      for (int r = 0; r < RP; ++r) {
+        const cplx sm = wave_sum(acc[s][r]);
+        if (lane == 0) rs[s][r0 + r][wv] = sm;
+      }
+  }
   __syncthreads();
   if ((int)threadIdx.x < nr) {
     const int dst = L.perm[off + t0 + threadIdx.x];
