@@ -152,7 +152,8 @@ SESM_API int sesm_matvec(sesm_ctx* ctx, const sesm_c64* mu, sesm_c64* y);
  * nrhs = 0 does nothing; nrhs < 0, ld below N, overlap or NULL pointers give
  * SESM_EINVAL.  The first accelerated call allocates the per-density
  * buffers of four densities (owned by the surface).  Kernel timing records
- * the later stages of each density, not the shared launch. */
+ * each later stage once per group of up to four densities (bytes of all of
+ * them), not the shared first launch. */
 SESM_API int sesm_matvec_batch(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* mu, int64_t ld_mu, sesm_c64* y,
                                int64_t ld_y);
 

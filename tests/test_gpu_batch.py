@@ -161,6 +161,28 @@ def test_bloch_class_shares_operator(torch, solver, accelerated):
     assert rel <= 1e-10
 
 
+def test_batch_timing_counts(torch, solver):
+    """Kernel timing of a batch of six densities (groups of four and two): each
+    later stage is one launch per group carrying the bytes of all its
+    densities; the shared first launch is not timed."""
+    import paper_1707_04950_amd as lib
+    wl = _gauss30()
+    disc = dense.Discretization(wl)
+    _configure(solver, wl, disc, True)
+    mu = _densities(torch, disc.N, [51])
+    solver.timing_enable((1 << lib.KT_COUNT) - 1)
+    solver.matvec(mu[0])
+    one = solver.timing_read()
+    solver.timing_enable((1 << lib.KT_COUNT) - 1)
+    solver.matvec_batch(_densities(torch, disc.N, list(range(52, 58))))
+    st = solver.timing_read()
+    solver.timing_enable(0)
+    assert st["k_local_apply"]["launches"] == 0
+    for k in ("k_merge_fft", "k_fft_rows", "k_yconv", "k_cells_far"):
+        assert st[k]["launches"] == 2, k
+        assert st[k]["bytes"] == pytest.approx(6 * one[k]["bytes"], rel=1e-12), k
+
+
 def test_batch_degenerate_calls(torch, solver):
     import paper_1707_04950_amd as lib
     wl = _gauss30()

@@ -68,19 +68,23 @@ def test_repeated_forward_maps_and_solves_are_bitwise_equal(torch):
 
 def test_no_reads_before_writes(torch, monkeypatch):
     """The same workload on a context whose buffers all start as NaN: the
-    forward map equals the one of a plain context bit for bit and the solve
-    reaches the oracle's efficiencies; dense mode first, then accelerated
-    (the second surface reuses memory the first one freed)."""
+    forward map and a batched forward map of five densities (one group of
+    four, one single; the batch work buffers are allocated by that call)
+    equal those of a plain context bit for bit and the solve reaches the
+    oracle's efficiencies; dense mode first, then accelerated (the second
+    surface reuses memory the first one freed)."""
     import paper_1707_04950_amd as lib
     from gpu_util import to_dev, to_host
     G = _golden("grazing4096")
     mu = to_dev(torch, W.random_density(G["N"], 8))
-    ref = {}
+    mub = torch.from_numpy(np.stack([W.random_density(G["N"], 40 + r) for r in range(5)])).cuda()
+    ref, refb = {}, {}
     plain = lib.Solver(0)
     try:
         for mode in (lib.MODE_DENSE, lib.MODE_ACCEL):
             _set(plain, G, mode)
             ref[mode] = to_host(plain.matvec(mu))
+            refb[mode] = to_host(plain.matvec_batch(mub))
     finally:
         plain.close()
     monkeypatch.setenv("SESM_POISON_ALLOC", "1")
@@ -90,6 +94,8 @@ def test_no_reads_before_writes(torch, monkeypatch):
             _set(s, G, mode)
             y = to_host(s.matvec(mu))
             assert np.all(np.isfinite(y)) and np.array_equal(y, ref[mode])
+            yb = to_host(s.matvec_batch(mub))
+            assert np.all(np.isfinite(yb)) and np.array_equal(yb, refb[mode])
             _solve_and_check(s, G, tol)
     finally:
         s.close()
