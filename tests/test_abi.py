@@ -18,8 +18,8 @@ def declared():
 
 def test_header_declares_api():
     names = declared()
-    for n in ("sesm_create", "sesm_destroy", "sesm_set_surface", "sesm_matvec", "sesm_rhs", "sesm_solve",
-              "sesm_efficiencies", "sesm_last_error"):
+    for n in ("sesm_create", "sesm_destroy", "sesm_set_surface", "sesm_matvec", "sesm_matvec_batch", "sesm_rhs",
+              "sesm_solve", "sesm_efficiencies", "sesm_last_error"):
         assert n in names
 
 
@@ -36,6 +36,7 @@ def test_null_context_is_rejected_without_gpu_work():
     lib = m.load_library()
     assert lib.sesm_set_surface(None, None, 1.0, 1.0, 0.0, 0, 1.0, None) == m.SESM_EINVAL
     assert lib.sesm_matvec(None, None, None) == m.SESM_EINVAL
+    assert lib.sesm_matvec_batch(None, 1, None, 1, None, 1) == m.SESM_EINVAL
     assert lib.sesm_solve(None, None, None, 1e-10, 10, 0, None) == m.SESM_EINVAL
     assert lib.sesm_timing_enable(None, 0, 1) == m.SESM_EINVAL
     assert lib.sesm_timing_read(None, None, 0) == m.SESM_EINVAL
