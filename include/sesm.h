@@ -162,6 +162,13 @@ SESM_API int sesm_matvec_batch(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* mu, 
  * b: device array of N sesm_c64. */
 SESM_API int sesm_rhs(sesm_ctx* ctx, sesm_c64* b);
 
+/* Right-hand side of member p of the surface's Bloch class: the incidence
+ * with alpha_p = alpha + 2 pi p / d, beta_p = sqrt(k^2 - alpha_p^2), which sees
+ * the same operator (eqs. shifted_periodic_green_function, alpha_beta_def);
+ * b_l = -exp(i (alpha_p x_l - beta_p f(x_l))).  p = 0 gives sesm_rhs.  b:
+ * device array of N sesm_c64.  SESM_EINVAL if |alpha_p| >= k. */
+SESM_API int sesm_rhs_bloch(sesm_ctx* ctx, int32_t p, sesm_c64* b);
+
 /* Algorithm 1: GMRES solve of (1/2 I + D^dx) mu = b.  b: device array of N
  * (NULL selects the incident-field right-hand side of sesm_rhs).  mu: device
  * array of N, output only (the iteration starts from zero).  tol: relative residual;
@@ -170,6 +177,26 @@ SESM_API int sesm_rhs(sesm_ctx* ctx, sesm_c64* b);
  * was not reached (mu and info still hold the last iterate). */
 SESM_API int sesm_solve(sesm_ctx* ctx, const sesm_c64* b, sesm_c64* mu, double tol, int32_t max_iter,
                int32_t restart, sesm_solve_info* info);
+
+#define SESM_MAX_BATCH 64  /* right-hand sides per sesm_solve_batch call */
+
+/* Algorithm 1 for several right-hand sides with the operator of the current
+ * surface (for instance the incidences of one Bloch class, see
+ * sesm_matvec_batch): one unrestarted GMRES per right-hand side, run in
+ * lockstep so that every Arnoldi step applies the operator to all active
+ * systems with one batched forward map (Algorithm 3).  Right-hand side r is
+ * the device array b + r ld_b of N sesm_c64, solution r is mu + r ld_mu
+ * (output only; each iteration starts from zero); ld_b, ld_mu >= N and the two
+ * spans must not overlap.  A system leaves the batch once it reaches tol;
+ * each solution equals that of sesm_solve(b_r, restart = 0) with the same
+ * tol and max_iter bit for bit.  0 <= nrhs <= SESM_MAX_BATCH,
+ * 1 <= max_iter <= 4000.  info: host array of nrhs records, may be NULL.
+ * The call allocates its work space (nrhs (max_iter + 1) N complex values for
+ * the bases, plus small buffers) and returns it to the context's pool at the
+ * end.  Returns SESM_ENOCONV if any system missed tol (all outputs still
+ * written). */
+SESM_API int sesm_solve_batch(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b, int64_t ld_b, sesm_c64* mu,
+                              int64_t ld_mu, double tol, int32_t max_iter, sesm_solve_info* info);
 
 /* Efficiencies e_n = (beta_n / beta) |B_n|^2 of the propagating orders
  * (Sec. 2) and the energy-balance error eps = 1 - sum e_n, eq. (energy_error).

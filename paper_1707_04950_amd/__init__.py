@@ -45,6 +45,7 @@ class SolveInfo(ctypes.Structure):
 # kernel classes of sesm_timing_enable (bit i of the mask selects class i)
 KT_LOCAL, KT_MERGE, KT_FFT, KT_YCONV, KT_CELLS, KT_DOTS, KT_UPDATE, KT_GEMV = range(8)
 KT_COUNT = 8
+SESM_MAX_BATCH = 64  # right-hand sides per solve_batch call
 
 
 class KernelStat(ctypes.Structure):
@@ -84,7 +85,9 @@ def load_library(path=LIB_PATH):
         "sesm_matvec": (ctypes.c_int, [_P, _P, _P]),
         "sesm_matvec_batch": (ctypes.c_int, [_P, _I, _P, ctypes.c_int64, _P, ctypes.c_int64]),
         "sesm_rhs": (ctypes.c_int, [_P, _P]),
+        "sesm_rhs_bloch": (ctypes.c_int, [_P, _I, _P]),
         "sesm_solve": (ctypes.c_int, [_P, _P, _P, _D, _I, _I, ctypes.POINTER(SolveInfo)]),
+        "sesm_solve_batch": (ctypes.c_int, [_P, _I, _P, ctypes.c_int64, _P, ctypes.c_int64, _D, _I, _P]),
         "sesm_efficiencies": (ctypes.c_int, [_P, _P, ctypes.POINTER(_I), ctypes.POINTER(_I),
                                              ctypes.POINTER(_D), _I, ctypes.POINTER(_D)]),
         "sesm_rayleigh": (ctypes.c_int, [_P, _P, ctypes.POINTER(_I), _I, _P]),
@@ -212,6 +215,12 @@ class Solver:
         self._check(self.lib.sesm_rhs(self.h, _ptr(out)))
         return out
 
+    def rhs_bloch(self, p, out=None):
+        """Right-hand side of the incidence alpha + 2 pi p / d (same operator)."""
+        out = self.empty() if out is None else out
+        self._check(self.lib.sesm_rhs_bloch(self.h, int(p), _ptr(out)))
+        return out
+
     def solve(self, b=None, tol=1e-10, max_iter=1000, restart=0, out=None, allow_noconv=False):
         out = self.empty() if out is None else out
         inf = SolveInfo()
@@ -220,6 +229,26 @@ class Solver:
         self._check(rc, allow=(SESM_ENOCONV,) if allow_noconv else ())
         return out, {"iters": inf.iters, "rel_residual": inf.rel_residual, "converged": bool(inf.converged),
                      "column_mismatches": inf.column_mismatches}
+
+    def solve_batch(self, b, tol=1e-10, max_iter=1000, out=None, allow_noconv=False):
+        """Unrestarted GMRES for the rows of b (nrhs x >= N, complex128 on the
+        device) in lockstep; returns the solutions (rows of out) and one info
+        dict per row."""
+        if b.dim() != 2 or b.shape[1] < self.N:
+            raise ValueError("b must be a (nrhs, >= N) tensor")
+        n = int(b.shape[0])
+        if out is None:
+            out = self._torch.empty((n, self.N), dtype=self._torch.complex128, device=self.device)
+            if os.environ.get("SESM_POISON_ALLOC", "0") not in ("", "0"):
+                out.fill_(complex("nan+nanj"))
+        if out.dim() != 2 or out.shape[0] != n or out.shape[1] < self.N:
+            raise ValueError("out must be a (nrhs, >= N) tensor")
+        infs = (SolveInfo * max(n, 1))()
+        rc = self.lib.sesm_solve_batch(self.h, n, _ptr_rows(b), int(b.stride(0)), _ptr_rows(out), int(out.stride(0)),
+                                       tol, max_iter, ctypes.cast(infs, ctypes.c_void_p))
+        self._check(rc, allow=(SESM_ENOCONV,) if allow_noconv else ())
+        return out, [{"iters": i.iters, "rel_residual": i.rel_residual, "converged": bool(i.converged),
+                      "column_mismatches": i.column_mismatches} for i in infs[:n]]
 
     def efficiencies(self, mu):
         cap = 4096

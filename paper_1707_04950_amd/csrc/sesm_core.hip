@@ -438,6 +438,22 @@ int sesm_matvec_batch(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* mu, int64_t l
   return SESM_OK;
 }
 
+int sesm_rhs_bloch(sesm_ctx* ctx, int32_t p, sesm_c64* b) {
+  if (!ctx) return SESM_EINVAL;
+  if (!ctx->ready) return ctx->fail(SESM_ENOSURF, "no surface");
+  if (!b) return ctx->fail(SESM_EINVAL, "null vector");
+  const Problem& P = ctx->P;
+  const double PI_ = 3.14159265358979323846;
+  const double ap = P.alpha + 2.0 * PI_ * p / P.d;
+  if (!(std::fabs(ap) < P.k)) return ctx->fail(SESM_EINVAL, "Bloch-class incidence is not propagating (|alpha_p| >= k)");
+  const double bp = std::sqrt(P.k * P.k - ap * ap);
+  SESM_HIP(hipSetDevice(ctx->device));
+  hipLaunchKernelGGL(k_rhs, dim3((P.N + 255) / 256), dim3(256), 0, ctx->stream, P.N, ap, bp, ctx->x, ctx->f,
+                     (cplx*)b);
+  SESM_LAUNCH_CHECK();
+  return SESM_OK;
+}
+
 int sesm_rhs(sesm_ctx* ctx, sesm_c64* b) {
   if (!ctx) return SESM_EINVAL;
   if (!ctx->ready) return ctx->fail(SESM_ENOSURF, "no surface");

@@ -434,6 +434,71 @@ int ensure_workspace(sesm_ctx* ctx, int m) {
   return SESM_OK;
 }
 
+using Cd = std::complex<double>;
+
+// plain complex product (no special-value handling: the operands are finite)
+inline Cd gm_mul(Cd a, Cd b) {
+  return Cd(a.real() * b.real() - a.imag() * b.imag(), a.real() * b.imag() + a.imag() * b.real());
+}
+
+// Givens QR of one Hessenberg column j (rows 0..j+1, in place) given the
+// rotations of the columns before it; updates g and returns |g[j+1]|
+double gm_rotate(Cd* col, int j, std::vector<Cd>& cs, std::vector<Cd>& sn, std::vector<Cd>& g) {
+  for (int t = 0; t < j; ++t) {  // previous rotations [[conj c, conj s], [-s, c]]
+    const Cd p = col[t], q = col[t + 1];
+    col[t] = gm_mul(std::conj(cs[t]), p) + gm_mul(std::conj(sn[t]), q);
+    col[t + 1] = gm_mul(cs[t], q) - gm_mul(sn[t], p);
+  }
+  const Cd a = col[j], bb = col[j + 1];
+  const double r = std::sqrt(std::norm(a) + std::norm(bb));
+  cs[j] = r != 0 ? a / r : 1.0;
+  sn[j] = r != 0 ? bb / r : 0.0;
+  col[j] = r;
+  col[j + 1] = 0.0;
+  g[j + 1] = -sn[j] * g[j];
+  g[j] = std::conj(cs[j]) * g[j];
+  return std::abs(g[j + 1]);
+}
+
+// wait until a step's column has reached the host (its flag carries the
+// step's sequence number); fall back to a stream synchronisation after 2 s
+int gm_wait(sesm_ctx* ctx, volatile int64_t* fl, int64_t seq) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (int spin = 0; *fl != seq; ++spin) {
+    if ((spin & 1023) == 1023 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
+      SESM_HIP(hipStreamSynchronize(ctx->stream));
+      if (*fl != seq) return ctx->fail(SESM_EHIP, "GMRES step result did not reach the host");
+      break;
+    }
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
+  return SESM_OK;
+}
+
+// After the flag, take the n entries of a host slot once none holds the
+// sentinel any more (an entry's store may reach host memory after the
+// flag's), then put the sentinel back.  Falls back to a stream
+// synchronisation after 2 s.
+int gm_take(sesm_ctx* ctx, cplx* slot_mem, int n, Cd* dst) {
+  volatile double* hv = reinterpret_cast<volatile double*>(slot_mem);
+  const auto t0 = std::chrono::steady_clock::now();
+  for (int spin = 0;; ++spin) {
+    int t = 0;
+    while (t < 2 * n && !is_column_sentinel(hv[t])) ++t;
+    if (t == 2 * n) break;
+    if ((spin & 255) == 255 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
+      SESM_HIP(hipStreamSynchronize(ctx->stream));
+      for (t = 0; t < 2 * n; ++t)
+        if (is_column_sentinel(hv[t])) return ctx->fail(SESM_EHIP, "GMRES column did not reach the host");
+      break;
+    }
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
+  for (int t = 0; t < n; ++t) dst[t] = Cd(hv[2 * t], hv[2 * t + 1]);
+  for (int t = 0; t < 2 * n; ++t) hv[t] = column_sentinel();
+  return SESM_OK;
+}
+
 }  // namespace
 
 extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out, double tol, int32_t max_iter,
@@ -522,66 +587,13 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
     }
     return SESM_OK;
   };
-  // wait until the step's column has reached the host (its flag carries the
-  // step's sequence number); fall back to a stream synchronisation after 2 s
-  auto wait_slot = [&](int slot) -> int {
-    volatile int64_t* fl = ctx->hflag + slot;
-    const auto t0 = std::chrono::steady_clock::now();
-    for (int spin = 0; *fl != slot_seq[slot]; ++spin) {
-      if ((spin & 1023) == 1023 &&
-          std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
-        SESM_HIP(hipStreamSynchronize(st));
-        if (*fl != slot_seq[slot]) return ctx->fail(SESM_EHIP, "GMRES step result did not reach the host");
-        break;
-      }
-    }
-    std::atomic_thread_fence(std::memory_order_acquire);
-    return SESM_OK;
-  };
-  // After the flag, take the n entries of a slot once none holds the sentinel
-  // any more (an entry's store may reach host memory after the flag's), then
-  // put the sentinel back.  Falls back to a stream synchronisation after 2 s.
+  auto wait_slot = [&](int slot) -> int { return gm_wait(ctx, ctx->hflag + slot, slot_seq[slot]); };
   auto take_slot = [&](int slot, int n, std::complex<double>* dst) -> int {
-    volatile double* hv = reinterpret_cast<volatile double*>(ctx->hhost + (size_t)slot * SESM_HSTRIDE);
-    const auto t0 = std::chrono::steady_clock::now();
-    for (int spin = 0;; ++spin) {
-      int t = 0;
-      while (t < 2 * n && !is_column_sentinel(hv[t])) ++t;
-      if (t == 2 * n) break;
-      if ((spin & 255) == 255 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
-        SESM_HIP(hipStreamSynchronize(st));
-        for (t = 0; t < 2 * n; ++t)
-          if (is_column_sentinel(hv[t])) return ctx->fail(SESM_EHIP, "GMRES column did not reach the host");
-        break;
-      }
-    }
-    std::atomic_thread_fence(std::memory_order_acquire);
-    for (int t = 0; t < n; ++t) dst[t] = std::complex<double>(hv[2 * t], hv[2 * t + 1]);
-    for (int t = 0; t < 2 * n; ++t) hv[t] = column_sentinel();
-    return SESM_OK;
+    return gm_take(ctx, ctx->hhost + (size_t)slot * SESM_HSTRIDE, n, dst);
   };
-
   using C = std::complex<double>;
-  // plain complex product (no special-value handling: the operands are finite)
-  auto mul = [](C a, C b) { return C(a.real() * b.real() - a.imag() * b.imag(), a.real() * b.imag() + a.imag() * b.real()); };
-  // Givens QR of one Hessenberg column j (rows 0..j+1, in place) given the
-  // rotations of the columns before it; updates g and returns |g[j+1]|
-  auto rotate = [&mul](C* col, int j, std::vector<C>& cs, std::vector<C>& sn, std::vector<C>& g) -> double {
-    for (int t = 0; t < j; ++t) {  // previous rotations [[conj c, conj s], [-s, c]]
-      const C p = col[t], q = col[t + 1];
-      col[t] = mul(std::conj(cs[t]), p) + mul(std::conj(sn[t]), q);
-      col[t + 1] = mul(cs[t], q) - mul(sn[t], p);
-    }
-    const C a = col[j], bb = col[j + 1];
-    const double r = std::sqrt(std::norm(a) + std::norm(bb));
-    cs[j] = r != 0 ? a / r : 1.0;
-    sn[j] = r != 0 ? bb / r : 0.0;
-    col[j] = r;
-    col[j + 1] = 0.0;
-    g[j + 1] = -sn[j] * g[j];
-    g[j] = std::conj(cs[j]) * g[j];
-    return std::abs(g[j + 1]);
-  };
+  auto mul = gm_mul;
+  auto rotate = gm_rotate;
   // streamed columns: raw (for the check against the device) and rotated
   // (the running residual estimate that decides when a cycle stops)
   std::vector<C>& H = ctx->gm_rot;
@@ -696,5 +708,279 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
   inf.converged = res <= tol ? 1 : 0;
   if (info) *info = inf;
   if (!inf.converged) return ctx->fail(SESM_ENOCONV, "GMRES did not reach the tolerance");
+  return SESM_OK;
+}
+
+namespace {
+
+// give a block allocated with sesm_alloc back to the context's pool
+void gm_release(sesm_ctx* ctx, void* p) {
+  for (size_t t = 0; t < ctx->owned.size(); ++t)
+    if (ctx->owned[t].first == p) {
+      ctx->bytes -= (int64_t)ctx->owned[t].second;
+      sesm_pool_put(ctx, p, ctx->owned[t].second);
+      ctx->owned.erase(ctx->owned.begin() + t);
+      return;
+    }
+}
+
+// One system of a batched solve: its device buffers (inside the batch's
+// shared allocations) and its host-side state.
+struct GmMember {
+  cplx *V, *w, *x;  // basis (m + 1) x N, A u, solution
+  const cplx* b;
+  cplx *hcol, *hpart, *ybuf, *hp, *gcoef, *Hrow, *htri;
+  double* gsc;
+  cplx* hhost;  // pinned ring slots (+ one upload slot) and their flags
+  cplx* hhost_dev;
+  int64_t* hflag;
+  int64_t* hflag_dev;
+  int64_t slot_seq[SESM_HRING] = {};
+  std::vector<Cd> H, Hraw, cs, sn, g;
+  double bnorm = 0.0, beta0 = 0.0, res = 1.0;
+  int nv = 0, mism = 0;
+  bool active = false;
+};
+
+}  // namespace
+
+extern "C" int sesm_solve_batch(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_in, int64_t ld_b, sesm_c64* mu_out,
+                                int64_t ld_mu, double tol, int32_t max_iter, sesm_solve_info* info) {
+  if (!ctx) return SESM_EINVAL;
+  if (!ctx->ready) return ctx->fail(SESM_ENOSURF, "no surface");
+  if (nrhs < 0 || nrhs > SESM_MAX_BATCH || !(tol > 0) || max_iter < 1 || max_iter > 4000)
+    return ctx->fail(SESM_EINVAL, "bad batched solve arguments");
+  if (nrhs == 0) return SESM_OK;
+  const int N = ctx->P.N;
+  if (!b_in || !mu_out || ld_b < N || ld_mu < N) return ctx->fail(SESM_EINVAL, "bad batched solve arguments");
+  {  // the spans of the right-hand sides and of the solutions must be disjoint
+    const uintptr_t b0 = (uintptr_t)b_in, b1 = (uintptr_t)(b_in + (nrhs - 1) * ld_b + N);
+    const uintptr_t m0 = (uintptr_t)mu_out, m1 = (uintptr_t)(mu_out + (nrhs - 1) * ld_mu + N);
+    if (b0 < m1 && m0 < b1) return ctx->fail(SESM_EINVAL, "right-hand sides and solutions overlap");
+  }
+  SESM_HIP(hipSetDevice(ctx->device));
+  const int m = max_iter;
+  hipStream_t st = ctx->stream;
+  const int nb = (N + 255) / 256;
+  const int64_t ldv = N, vstride = (int64_t)(m + 1) * N;
+  // per-member small buffers, each rounded to 16 complex entries
+  auto r16 = [](int64_t n) { return (n + 15) / 16 * 16; };
+  const int64_t hrow_len = hrow_off(m, m) + 1;
+  const int64_t o_hcol = 0, o_hpart = o_hcol + r16((int64_t)SESM_HRING * SESM_HSTRIDE),
+                o_ybuf = o_hpart + r16((int64_t)2 * SESM_HSTRIDE * DCHUNK), o_hp = o_ybuf + r16(SESM_HSTRIDE),
+                o_gcoef = o_hp + r16(SESM_HSTRIDE), o_gsc = o_gcoef + r16(3 * SESM_HSTRIDE), o_Hrow = o_gsc + 16,
+                o_htri = o_Hrow + r16(hrow_len), per_small = o_htri + r16(m_tri(m));
+  cplx *Vall = nullptr, *Wall = nullptr, *small = nullptr;
+  cplx* pin = nullptr;
+  int rc = SESM_OK;
+  std::vector<GmMember> M(nrhs);
+  auto finish = [&](int code) -> int {  // free the workspace (after the stream has drained)
+    (void)hipStreamSynchronize(st);
+    if (pin) (void)hipHostFree(pin);
+    gm_release(ctx, Vall);
+    gm_release(ctx, Wall);
+    gm_release(ctx, small);
+    return code;
+  };
+  if ((rc = sesm_alloc(ctx, (void**)&Vall, sizeof(cplx) * (size_t)nrhs * vstride)) ||
+      (rc = sesm_alloc(ctx, (void**)&Wall, sizeof(cplx) * (size_t)nrhs * N)) ||
+      (rc = sesm_alloc(ctx, (void**)&small, sizeof(cplx) * (size_t)nrhs * per_small)))
+    return finish(rc);
+  const size_t pin_per = (size_t)(SESM_HRING + 1) * SESM_HSTRIDE + SESM_HRING;  // slots, then flags (as cplx)
+  if (hipHostMalloc((void**)&pin, sizeof(cplx) * pin_per * nrhs, hipHostMallocCoherent) != hipSuccess) {
+    pin = nullptr;
+    return finish(ctx->fail(SESM_ENOMEM, "hipHostMalloc failed"));
+  }
+  cplx* pin_dev = nullptr;
+  if (hipHostGetDevicePointer((void**)&pin_dev, pin, 0) != hipSuccess)
+    return finish(ctx->fail(SESM_EHIP, "hipHostGetDevicePointer failed"));
+  for (int r = 0; r < nrhs; ++r) {
+    GmMember& G = M[r];
+    G.V = Vall + r * vstride;
+    G.w = Wall + (int64_t)r * N;
+    G.x = (cplx*)mu_out + r * ld_mu;
+    G.b = (const cplx*)b_in + r * ld_b;
+    cplx* sm = small + r * per_small;
+    G.hcol = sm + o_hcol;
+    G.hpart = sm + o_hpart;
+    G.ybuf = sm + o_ybuf;
+    G.hp = sm + o_hp;
+    G.gcoef = sm + o_gcoef;
+    G.gsc = reinterpret_cast<double*>(sm + o_gsc);
+    G.Hrow = sm + o_Hrow;
+    G.htri = sm + o_htri;
+    G.hhost = pin + r * pin_per;
+    G.hhost_dev = pin_dev + r * pin_per;
+    G.hflag = reinterpret_cast<int64_t*>(G.hhost + (size_t)(SESM_HRING + 1) * SESM_HSTRIDE);
+    G.hflag_dev = reinterpret_cast<int64_t*>(G.hhost_dev + (size_t)(SESM_HRING + 1) * SESM_HSTRIDE);
+    for (int t = 0; t < SESM_HRING; ++t) G.hflag[t] = 0;
+    double* hv = reinterpret_cast<double*>(G.hhost);
+    for (size_t t = 0; t < (size_t)2 * SESM_HRING * SESM_HSTRIDE; ++t) hv[t] = column_sentinel();
+    G.cs.assign(m, 0.0);
+    G.sn.assign(m, 0.0);
+    G.g.assign(m + 1, 0.0);
+    // right-hand side norm and u_0 = b (x = 0)
+    hipLaunchKernelGGL(k_norm2_part, dim3(NCHUNK), dim3(256), 0, st, N, G.b, (double*)G.hpart);
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(64), 0, st, (const double*)G.hpart, G.hcol);
+    if (hipGetLastError() != hipSuccess) return finish(ctx->fail(SESM_EHIP, "batched solve: launch failed"));
+    cplx* hup = G.hhost + (size_t)SESM_HRING * SESM_HSTRIDE;
+    if (hipMemcpyAsync(hup, G.hcol, sizeof(cplx), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(G.V, G.b, sizeof(cplx) * (size_t)N, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemsetAsync(G.x, 0, sizeof(cplx) * (size_t)N, st) != hipSuccess)
+      return finish(ctx->fail(SESM_EHIP, "batched solve: initial copies failed"));
+  }
+  if (hipStreamSynchronize(st) != hipSuccess) return finish(ctx->fail(SESM_EHIP, "batched solve: synchronisation failed"));
+  for (int r = 0; r < nrhs; ++r) {
+    M[r].bnorm = M[r].hhost[(size_t)SESM_HRING * SESM_HSTRIDE].re;
+    M[r].active = M[r].bnorm != 0.0;
+    M[r].res = M[r].bnorm != 0.0 ? 1.0 : 0.0;
+  }
+  const int steps = m;  // unrestarted: every column of the basis is available
+  // Arnoldi step k of every active member: one batched forward map of the
+  // members' u = V_k, then each member's dot products, step and update (the
+  // same launches as the single solve, on the member's buffers).
+  auto arnoldi_all = [&](int k) -> int {
+    const bool full = k < steps;
+    int lo = nrhs, hi = -1;
+    for (int r = 0; r < nrhs; ++r)
+      if (M[r].active) lo = std::min(lo, r), hi = std::max(hi, r);
+    if (hi < 0) return SESM_OK;
+    if (full) {
+      int r2;
+      if (ctx->P.mode == SESM_MODE_ACCEL)
+        r2 = sesm_accel_matvec_batch(ctx, hi - lo + 1, Vall + lo * vstride + (int64_t)k * ldv, vstride,
+                                     Wall + (int64_t)lo * N, N);
+      else {
+        r2 = SESM_OK;
+        for (int r = lo; r <= hi && !r2; ++r) r2 = sesm_dense_matvec(ctx, M[r].V + (int64_t)k * ldv, M[r].w);
+      }
+      if (r2) return r2;
+    }
+    const int nv = k + 1, slot = k % SESM_HRING;
+    for (int r = lo; r <= hi; ++r) {
+      GmMember& G = M[r];
+      if (!G.active) continue;
+      cplx* u = G.V + (int64_t)k * ldv;
+      cplx* cS = G.gcoef;
+      cplx* cZ = cS + SESM_HSTRIDE;
+      cplx* cC = cZ + SESM_HSTRIDE;
+      hipLaunchKernelGGL(k_gm_dots, dim3(DCHUNK, (nv + VT - 1) / VT), dim3(256), 0, st, N, nv, G.V, ldv, u,
+                         full ? G.w : nullptr, G.hpart);
+      SESM_LAUNCH_CHECK();
+      const int64_t seq = ++ctx->gm_seq;
+      cplx* colv = G.hcol + (size_t)(k % 2) * SESM_HSTRIDE;
+      hipLaunchKernelGGL(k_gm_step, dim3(1), dim3(STEP_NT), 0, st, k, m, G.hpart, G.hp, G.Hrow, colv, cS, cZ, cC,
+                         G.gsc);
+      SESM_LAUNCH_CHECK();
+      G.slot_seq[slot] = seq;
+      cplx* hout = G.hhost_dev + (size_t)slot * SESM_HSTRIDE;
+      if (!full) {
+        hipLaunchKernelGGL(k_gm_publish, dim3(1), dim3(256), 0, st, k + 1, colv, hout, G.hflag_dev + slot, seq);
+        SESM_LAUNCH_CHECK();
+      } else {
+        const int nrb = (N + UPD_ROWS - 1) / UPD_ROWS;
+        hipLaunchKernelGGL(k_gm_update, dim3(nrb + (k + 1 + 3) / 4 + 1), dim3(256), 0, st, N, k, m, nrb, G.V, ldv,
+                           cS, cZ, cC, G.gsc, G.Hrow, G.hp, G.w, colv, hout, G.hflag_dev + slot, seq);
+        SESM_LAUNCH_CHECK();
+      }
+    }
+    return SESM_OK;
+  };
+  if ((rc = arnoldi_all(0))) return finish(rc);
+  int active = 0;
+  for (const GmMember& G : M) active += G.active ? 1 : 0;
+  for (int k = 0; active > 0; ++k) {
+    if (k + 1 <= steps && (rc = arnoldi_all(k + 1))) return finish(rc);  // the device stays one step ahead
+    const int slot = k % SESM_HRING;
+    for (int r = 0; r < nrhs; ++r) {
+      GmMember& G = M[r];
+      if (!G.active) continue;
+      if ((rc = gm_wait(ctx, G.hflag + slot, G.slot_seq[slot]))) return finish(rc);
+      cplx* hs = G.hhost + (size_t)slot * SESM_HSTRIDE;
+      if (k == 0) {  // residual norm
+        Cd r0;
+        if ((rc = gm_take(ctx, hs, 1, &r0))) return finish(rc);
+        G.beta0 = r0.real();
+        G.g[0] = G.beta0;
+        G.res = G.beta0 / G.bnorm;
+        if (G.res <= tol) G.active = false, --active;
+        continue;
+      }
+      const int j = k - 1;
+      const size_t need = (size_t)m_tri(j + 1);
+      if (G.H.size() < need) G.H.resize(std::max(need, 2 * G.H.size()));
+      if (G.Hraw.size() < need) G.Hraw.resize(std::max(need, 2 * G.Hraw.size()));
+      Cd* col = &G.H[(size_t)m_tri(j)];
+      Cd* raw = &G.Hraw[(size_t)m_tri(j)];
+      if ((rc = gm_take(ctx, hs, k + 1, raw))) return finish(rc);
+      for (int t = 0; t <= k; ++t) col[t] = raw[t];
+      const double rr = gm_rotate(col, j, G.cs, G.sn, G.g);
+      G.res = std::abs(G.g[j + 1]) / G.bnorm;
+      G.nv = k;
+      if (G.res <= tol || rr == 0.0 || k == steps) G.active = false, --active;
+    }
+  }
+  // per member: least squares from the device's own Hessenberg columns
+  // (streamed copies compared bitwise), x = V y
+  std::vector<cplx> tri;
+  for (int r = 0; r < nrhs; ++r) {
+    GmMember& G = M[r];
+    const int nv = G.nv;
+    if (nv == 0) continue;
+    if (tri.size() < (size_t)m_tri(nv)) tri.resize((size_t)m_tri(nv));
+    hipLaunchKernelGGL(k_hess_gather, dim3(nv), dim3(256), 0, st, m, G.Hrow, G.htri);
+    if (hipGetLastError() != hipSuccess) return finish(ctx->fail(SESM_EHIP, "batched solve: launch failed"));
+    if (hipMemcpyAsync(tri.data(), G.htri, sizeof(cplx) * (size_t)m_tri(nv), hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return finish(ctx->fail(SESM_EHIP, "batched solve: Hessenberg transfer failed"));
+    int bad = 0;
+    for (int j = 0; j < nv; ++j) {
+      const cplx* dv = &tri[(size_t)m_tri(j)];
+      const Cd* raw = &G.Hraw[(size_t)m_tri(j)];
+      bool same = true;
+      for (int t = 0; t <= j + 1; ++t) same = same && Cd(dv[t].re, dv[t].im) == raw[t];
+      bad += same ? 0 : 1;
+    }
+    if (bad) {
+      G.mism += bad;
+      std::fill(G.g.begin(), G.g.end(), 0.0);
+      G.g[0] = G.beta0;
+      for (int j = 0; j < nv; ++j) {
+        Cd* col = &G.H[(size_t)m_tri(j)];
+        const cplx* dv = &tri[(size_t)m_tri(j)];
+        for (int t = 0; t <= j + 1; ++t) col[t] = Cd(dv[t].re, dv[t].im);
+        G.res = gm_rotate(col, j, G.cs, G.sn, G.g) / G.bnorm;
+      }
+    }
+    std::vector<Cd> y(nv);
+    for (int t = nv - 1; t >= 0; --t) {
+      Cd sm = G.g[t];
+      for (int u = t + 1; u < nv; ++u) sm -= gm_mul(G.H[(size_t)m_tri(u) + t], y[u]);
+      y[t] = sm / G.H[(size_t)m_tri(t) + t];
+    }
+    cplx* yh = G.hhost + (size_t)SESM_HRING * SESM_HSTRIDE;
+    for (int t = 0; t < nv; ++t) yh[t] = cplx{y[t].real(), y[t].imag()};
+    if (hipMemcpyAsync(G.ybuf, yh, sizeof(cplx) * nv, hipMemcpyHostToDevice, st) != hipSuccess)
+      return finish(ctx->fail(SESM_EHIP, "batched solve: upload failed"));
+    hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), sizeof(cplx) * nv, st, N, nv, G.V, ldv, G.ybuf, G.x);
+    if (hipGetLastError() != hipSuccess) return finish(ctx->fail(SESM_EHIP, "batched solve: launch failed"));
+    if (hipStreamSynchronize(st) != hipSuccess) return finish(ctx->fail(SESM_EHIP, "batched solve: combine failed"));
+  }
+  bool all = true;
+  for (int r = 0; r < nrhs; ++r) {
+    const GmMember& G = M[r];
+    const bool conv = G.res <= tol;
+    all = all && conv;
+    if (info) {
+      info[r].iters = G.nv;
+      info[r].rel_residual = G.res;
+      info[r].converged = conv ? 1 : 0;
+      info[r].column_mismatches = G.mism;
+    }
+  }
+  rc = finish(SESM_OK);
+  if (rc) return rc;
+  if (!all) return ctx->fail(SESM_ENOCONV, "GMRES did not reach the tolerance for every right-hand side");
   return SESM_OK;
 }

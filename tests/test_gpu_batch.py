@@ -211,3 +211,125 @@ def test_batch_degenerate_calls(torch, solver):
         assert fresh.lib.sesm_matvec_batch(fresh.h, 1, pm, N, po, N) == lib.SESM_ENOSURF
     finally:
         fresh.close()
+
+
+# ---- batched solve (sesm_solve_batch) and Bloch-class right-hand sides
+
+def _bloch_member(wl, p):
+    """The workload of the incidence alpha + 2 pi p / d (same surface)."""
+    s1 = math.sin(math.radians(wl.theta_deg)) + 2 * math.pi * p / (wl.k * wl.d)
+    return wl.with_(theta_deg=math.degrees(math.asin(s1)))
+
+
+@pytest.mark.parametrize("accelerated", [True, False])
+def test_solve_batch_equals_single_solves(torch, solver, accelerated):
+    """Four Bloch-class incidences, a zero and a random right-hand side
+    (groups of four and two): every solution and iteration count equals
+    the single unrestarted solve's bit for bit."""
+    wl = _gauss30(37.0)
+    disc = dense.Discretization(wl)
+    _configure(solver, wl, disc, accelerated)
+    N = disc.N
+    rows = [solver.rhs_bloch(p) for p in (0, -1, -3, 1)]
+    rows.append(torch.zeros(N, dtype=torch.complex128, device="cuda"))
+    rows.append(_densities(torch, N, [61])[0])
+    B = torch.stack(rows)
+    assert torch.equal(B[0], solver.rhs())
+    mu, infos = solver.solve_batch(B, tol=1e-12, max_iter=400)
+    for r in range(B.shape[0]):
+        m1, i1 = solver.solve(B[r].contiguous(), tol=1e-12, max_iter=400)
+        print("member %d: iters %d (single %d), residual %.2e" % (r, infos[r]["iters"], i1["iters"],
+                                                                  infos[r]["rel_residual"]))
+        assert infos[r]["converged"] and infos[r]["column_mismatches"] == 0
+        assert infos[r]["iters"] == i1["iters"] and infos[r]["rel_residual"] == i1["rel_residual"]
+        assert torch.equal(mu[r], m1), "solution %d differs from the single solve" % r
+    assert infos[4]["iters"] == 0 and bool((mu[4] == 0).all())
+
+
+def test_solve_batch_bloch_efficiencies_vs_oracle(torch, solver):
+    """Members p = 0, -1, 1 of the Bloch class of the 37 degree incidence,
+    solved in one accelerated batch: the right-hand sides equal the oracle's
+    for each incidence, and the efficiencies (taken on a surface set up for
+    that incidence) and their energy balance match the dense oracle solved
+    for it to 1e-6."""
+    from gpu_util import to_host
+    from oracle import rayleigh
+    wl = _gauss30(37.0)
+    disc = dense.Discretization(wl)
+    _configure(solver, wl, disc, True)
+    ps = (0, -1, 1)
+    B = torch.stack([solver.rhs_bloch(p) for p in ps])
+    mu, infos = solver.solve_batch(B, tol=1e-12, max_iter=400)
+    M = dense.operator_matrix(disc)
+    for r, p in enumerate(ps):
+        wp = _bloch_member(wl, p)
+        dp = dense.Discretization(wp)
+        b_o = dense.rhs(dp)
+        assert np.max(np.abs(to_host(B[r]) - b_o)) < 1e-12
+        n_o, e_o, eps_o = rayleigh.efficiencies(dp, np.linalg.solve(M, b_o))
+        _configure(solver, wp, dp, True)
+        n, e, eps = solver.efficiencies(mu[r])
+        err = float(np.max(np.abs(e - e_o)))
+        print("p = %d: %d orders, max|e - e_oracle| %.2e, energy balance %.2e (oracle %.2e)"
+              % (p, len(n), err, eps, eps_o))
+        # the energy balance at N = 400 is the discretisation's (oracle alike)
+        assert list(n) == list(n_o) and err <= 1e-6 and abs(eps - eps_o) <= 1e-6
+
+
+def test_solve_batch_arguments(torch, solver):
+    import paper_1707_04950_amd as lib
+    wl = _gauss30(37.0)
+    disc = dense.Discretization(wl)
+    _configure(solver, wl, disc, True)
+    N = disc.N
+    f = solver.lib.sesm_solve_batch
+    b = _densities(torch, N, [1, 2])
+    x = torch.zeros((2, N), dtype=torch.complex128, device="cuda")
+    pb, px = ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr())
+    assert f(solver.h, 0, None, 0, None, 0, 1e-10, 10, None) == 0
+    assert f(solver.h, lib.SESM_MAX_BATCH + 1, pb, N, px, N, 1e-10, 10, None) == lib.SESM_EINVAL
+    assert f(solver.h, -1, pb, N, px, N, 1e-10, 10, None) == lib.SESM_EINVAL
+    assert f(solver.h, 2, pb, N, px, N, 1e-10, 0, None) == lib.SESM_EINVAL
+    assert f(solver.h, 2, pb, N, px, N, 1e-10, 4001, None) == lib.SESM_EINVAL
+    assert f(solver.h, 2, pb, N, px, N, 0.0, 10, None) == lib.SESM_EINVAL
+    assert f(solver.h, 2, pb, N - 1, px, N, 1e-10, 10, None) == lib.SESM_EINVAL
+    assert f(solver.h, 2, None, N, px, N, 1e-10, 10, None) == lib.SESM_EINVAL
+    assert f(solver.h, 2, pb, N, pb, N, 1e-10, 10, None) == lib.SESM_EINVAL
+    torch.cuda.synchronize()
+    assert bool((x == 0).all())
+    # a cap too small to converge: soft failure, outputs and records written
+    xs, infos = solver.solve_batch(b, tol=1e-14, max_iter=3, allow_noconv=True)
+    assert all(i["iters"] == 3 and not i["converged"] for i in infos) and bool(torch.isfinite(xs).all())
+    with pytest.raises(lib.SesmError):
+        solver.rhs_bloch(2)  # alpha + 4 pi / d > k at 37 degrees and d = 5
+    fresh = lib.Solver(0)
+    try:
+        assert fresh.lib.sesm_solve_batch(fresh.h, 1, pb, N, px, N, 1e-10, 10, None) == lib.SESM_ENOSURF
+        assert fresh.lib.sesm_rhs_bloch(fresh.h, 0, px) == lib.SESM_ENOSURF
+    finally:
+        fresh.close()
+
+
+def test_solve_batch_full_size_grazing_wood(torch, solver):
+    """N = 32768 near-grazing Wood workload, members p = 0, -1, -2 in one
+    batch: member 0 equals the single solve bit for bit; every member's
+    efficiencies (surface set up for its incidence) balance energy to 1e-6."""
+    import paper_1707_04950_amd as lib
+    wl = W.config_grazing_wood(32768)
+    disc = dense.Discretization(wl)
+
+    def setup(w):
+        solver.set_surface(np.asarray(w.a_coef), np.asarray(w.b_coef), w.d, w.k, w.alpha, w.j, w.A, disc.N,
+                           h=w.h, c=w.c, n_a=disc.n_a, gamma_frac=w.gamma_frac, eta=w.eta, mode=lib.MODE_ACCEL,
+                           L=w.L)
+    setup(wl)
+    ps = (0, -1, -2)
+    B = torch.stack([solver.rhs_bloch(p) for p in ps])
+    mu, infos = solver.solve_batch(B, tol=1e-10, max_iter=3000)
+    m0, i0 = solver.solve(tol=1e-10, max_iter=3000)
+    assert torch.equal(mu[0], m0) and infos[0]["iters"] == i0["iters"]
+    for r, p in enumerate(ps):
+        setup(_bloch_member(wl, p))
+        n, e, eps = solver.efficiencies(mu[r])
+        print("p = %d: %d iterations, %d orders, energy balance %.2e" % (p, infos[r]["iters"], len(n), eps))
+        assert infos[r]["converged"] and infos[r]["column_mismatches"] == 0 and abs(eps) <= 1e-6
