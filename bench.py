@@ -37,6 +37,7 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--max-iter", type=int, default=3000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched-solve", action="store_true")  # e.g. under counter collection (many dispatches)
     ap.add_argument("--copy-probe", action="store_true")
     return ap.parse_args()
 
@@ -216,6 +217,28 @@ def main():
                  "speedup_vs_single": mv_s * BATCH / bt_s,
                  "last_row_equals_single": bool(torch.equal(yb[BATCH - 1], y1))}
 
+    # batched solve: the incidences alpha + 2 pi p / d, p = 0, -1, ..., of the
+    # workload's Bloch class (one operator) in one lockstep GMRES, against the
+    # single solve of the timed steps (same tolerance, unrestarted)
+    bsolve = None
+    if args.mode == "accel" and not args.no_batched_solve:
+        B = torch.stack([s.rhs_bloch(-p) for p in range(BATCH)])
+        s.solve_batch(B[:2], tol=args.tol, max_iter=args.max_iter, allow_noconv=True)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xb, infos = s.solve_batch(B, tol=args.tol, max_iter=args.max_iter, allow_noconv=True)
+        torch.cuda.synchronize()
+        bs_s = time.perf_counter() - t0
+        x1, _ = s.solve(tol=args.tol, max_iter=args.max_iter, allow_noconv=True)
+        torch.cuda.synchronize()
+        single_s = float(np.mean([r["solve"] for r in recs]))
+        bsolve = {"nrhs": BATCH, "incidences": "alpha + 2 pi p / d, p = 0..-%d" % (BATCH - 1),
+                  "ms_per_batch": bs_s * 1e3, "solves_per_s": BATCH / bs_s,
+                  "speedup_vs_single_solve": single_s * BATCH / bs_s,
+                  "iters": [i["iters"] for i in infos], "all_converged": all(i["converged"] for i in infos),
+                  "column_mismatches": int(sum(i["column_mismatches"] for i in infos)),
+                  "member0_equals_single": bool(torch.equal(xb[0], x1))}
+
     n_launch = max(kst["launches"], 1)
     avg_s = kst["total_ms"] / 1e3 / n_launch
     roof = {"kernel": dom, "bound": "hbm", "achieved": kst["bytes"] / n_launch / avg_s / 1e9, "peak": HBM_PEAK_GBS,
@@ -249,6 +272,7 @@ def main():
         "matvec_munknowns_per_s": args.N / mv_s / 1e6,
         "matvec_ms": mv_s * 1e3,
         "batched_matvec": batch,
+        "batched_solve": bsolve,
         "gmres_iters": recs[-1]["iters"],
         "gmres_rel_residual": recs[-1]["res"],
         "energy_balance_error": max((r["eps"] for r in recs), key=abs),
