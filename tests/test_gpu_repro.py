@@ -68,23 +68,28 @@ def test_repeated_forward_maps_and_solves_are_bitwise_equal(torch):
 
 def test_no_reads_before_writes(torch, monkeypatch):
     """The same workload on a context whose buffers all start as NaN: the
-    forward map and a batched forward map of five densities (one group of
-    four, one single; the batch work buffers are allocated by that call)
-    equal those of a plain context bit for bit and the solve reaches the
-    oracle's efficiencies; dense mode first, then accelerated (the second
+    forward map, a batched forward map of five densities (one group of
+    four, one single; the batch work buffers are allocated by that call) and
+    a batched solve of two Bloch-class incidences equal those of a plain
+    context bit for bit and the solve reaches the oracle's efficiencies; dense mode first, then accelerated (the second
     surface reuses memory the first one freed)."""
     import paper_1707_04950_amd as lib
     from gpu_util import to_dev, to_host
     G = _golden("grazing4096")
     mu = to_dev(torch, W.random_density(G["N"], 8))
     mub = torch.from_numpy(np.stack([W.random_density(G["N"], 40 + r) for r in range(5)])).cuda()
-    ref, refb = {}, {}
+    ref, refb, refs = {}, {}, {}
+
+    def batch_solve(s):  # two members of the Bloch class (batched solve work space)
+        B = torch.stack([s.rhs_bloch(0), s.rhs_bloch(-1)])
+        return to_host(s.solve_batch(B, tol=1e-10, max_iter=3000)[0])
     plain = lib.Solver(0)
     try:
         for mode in (lib.MODE_DENSE, lib.MODE_ACCEL):
             _set(plain, G, mode)
             ref[mode] = to_host(plain.matvec(mu))
             refb[mode] = to_host(plain.matvec_batch(mub))
+            refs[mode] = batch_solve(plain)
     finally:
         plain.close()
     monkeypatch.setenv("SESM_POISON_ALLOC", "1")
@@ -96,6 +101,8 @@ def test_no_reads_before_writes(torch, monkeypatch):
             assert np.all(np.isfinite(y)) and np.array_equal(y, ref[mode])
             yb = to_host(s.matvec_batch(mub))
             assert np.all(np.isfinite(yb)) and np.array_equal(yb, refb[mode])
+            xs = batch_solve(s)
+            assert np.all(np.isfinite(xs)) and np.array_equal(xs, refs[mode])
             _solve_and_check(s, G, tol)
     finally:
         s.close()
