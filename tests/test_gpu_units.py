@@ -70,17 +70,20 @@ def test_own_phase_factor_matches_numpy(torch, solver):
     assert np.all(np.abs(np.abs(got) - 1.0) <= 4e-16)
 
 
-@pytest.mark.parametrize("kw", [dict(h=0.85), dict(h=0.6), dict(L=0.4), dict(n_side=12)])
+@pytest.mark.parametrize("kw", [dict(h=0.85), dict(h=0.6), dict(L=0.4), dict(n_side=12), dict(j=6), dict(j=10),
+                                dict(A=30.0)])
 def test_efficiencies_invariant_under_method_parameters(torch, solver, kw):
     """30 degree double-Wood workload (N = 4096): accelerated efficiencies
-    against the oracle's (tests/golden/wood30_4096.json, dense LU at h = 0.85)."""
+    against the oracle's (tests/golden/wood30_4096.json, dense LU at h = 0.85,
+    j = 8, A = 20 periods), also with another shift order j and window A."""
     import json
     import paper_1707_04950_amd as lib
     G = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "wood30_4096.json")))
     wl = W.config_random_double_wood(4096)
     L = kw.get("L", wl.L)
     n_a = max(8, int(math.floor(0.8 * min(L, wl.d) / wl.dx)))
-    solver.set_surface(np.asarray(wl.a_coef), np.asarray(wl.b_coef), wl.d, wl.k, wl.alpha, wl.j, wl.A, wl.N,
+    solver.set_surface(np.asarray(wl.a_coef), np.asarray(wl.b_coef), wl.d, wl.k, wl.alpha, kw.get("j", wl.j),
+                       kw.get("A", wl.A), wl.N,
                        h=kw.get("h", wl.h), c=wl.c, n_a=n_a, gamma_frac=wl.gamma_frac, eta=wl.eta,
                        mode=lib.MODE_ACCEL, L=L, n_side=kw.get("n_side", 0))
     mu, info = solver.solve(tol=1e-11, max_iter=2000)
