@@ -45,9 +45,9 @@ __host__ __device__ inline int64_t hrow_off(int r, int m) {
 // part[(v DCHUNK + c) 2 + 1] = sum_{i in chunk c} conj(V_v[i]) w[i] (w optional),
 // v in [0, nv).  Loads are unconditional (vector index clamped, surplus terms
 // masked) so that all basis loads of an iteration are in flight together.
-__global__ __launch_bounds__(256) void k_gm_dots(int N, int nv, const cplx* __restrict__ V, int64_t ldv,
-                                                 const cplx* __restrict__ u, const cplx* __restrict__ w,
-                                                 cplx* __restrict__ part) {
+__device__ __forceinline__ void gm_dots(int N, int nv, const cplx* __restrict__ V, int64_t ldv,
+                                        const cplx* __restrict__ u, const cplx* __restrict__ w,
+                                        cplx* __restrict__ part) {
   __shared__ cplx sh[2][VT][4];
   const int c = blockIdx.x, v0 = blockIdx.y * VT;
   const int per = (N + DCHUNK - 1) / DCHUNK;
@@ -116,11 +116,9 @@ __global__ __launch_bounds__(256) void k_gm_dots(int N, int nv, const cplx* __re
 // beta = 0 (an invariant Krylov space) gives zero coefficients and 1/beta = 0.
 // The column reaches the host from the last workgroup of the update launch
 // (or of k_gm_publish when no update follows).
-__global__ __launch_bounds__(STEP_NT) void k_gm_step(int k, int m, const cplx* __restrict__ part,
-                                                     const cplx* __restrict__ hp, cplx* __restrict__ Hrow,
-                                                     cplx* __restrict__ hout, cplx* __restrict__ cS,
-                                                     cplx* __restrict__ cZ, cplx* __restrict__ cC,
-                                                     double* __restrict__ sc) {
+__device__ __forceinline__ void gm_step(int k, int m, const cplx* __restrict__ part, const cplx* __restrict__ hp,
+                                        cplx* __restrict__ Hrow, cplx* __restrict__ hout, cplx* __restrict__ cS,
+                                        cplx* __restrict__ cZ, cplx* __restrict__ cC, double* __restrict__ sc) {
   constexpr int STEP_LDS = 2048, PER = (SESM_HSTRIDE + STEP_NT - 1) / STEP_NT;
   __shared__ cplx sh[STEP_NT / 64];
   __shared__ cplx s_last[2];  // (rho, zeta)
@@ -246,12 +244,12 @@ __global__ __launch_bounds__(256) void k_gm_publish(int n, const cplx* __restric
 // of column k, one wavefront per row r:
 // hp[r] = (c_r - sum_{j >= max(0, r-1)} H[r][j] cS[j]) / beta, c = (cZ, c_k).
 constexpr int UPD_ROWS = 64, UPD_B = 8;
-__global__ __launch_bounds__(256) void k_gm_update(int N, int k, int m, int nrb, cplx* V, int64_t ldv,
-                                                   const cplx* __restrict__ cS, const cplx* __restrict__ cZ,
-                                                   const cplx* __restrict__ cC, const double* __restrict__ sc,
-                                                   const cplx* __restrict__ Hrow, cplx* __restrict__ hp,
-                                                   const cplx* __restrict__ w, const cplx* __restrict__ col,
-                                                   cplx* __restrict__ hout, int64_t* flag, int64_t seq) {
+__device__ __forceinline__ void gm_update(int N, int k, int m, int nrb, cplx* V, int64_t ldv,
+                                          const cplx* __restrict__ cS, const cplx* __restrict__ cZ,
+                                          const cplx* __restrict__ cC, const double* __restrict__ sc,
+                                          const cplx* __restrict__ Hrow, cplx* __restrict__ hp,
+                                          const cplx* __restrict__ w, const cplx* __restrict__ col,
+                                          cplx* __restrict__ hout, int64_t* flag, int64_t seq) {
   const int bid = blockIdx.x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (bid == (int)gridDim.x - 1) {  // the last workgroup hands the step's column to the host
@@ -308,6 +306,89 @@ __global__ __launch_bounds__(256) void k_gm_update(int N, int k, int m, int nrb,
     V[(int64_t)k * ldv + i] = inv * (u - p1);
     V[(int64_t)(k + 1) * ldv + i] = inv * (w[i] - p2 - a * u);
   }
+}
+
+__global__ __launch_bounds__(256) void k_gm_dots(int N, int nv, const cplx* __restrict__ V, int64_t ldv,
+                                                 const cplx* __restrict__ u, const cplx* __restrict__ w,
+                                                 cplx* __restrict__ part) {
+  gm_dots(N, nv, V, ldv, u, w, part);
+}
+__global__ __launch_bounds__(STEP_NT) void k_gm_step(int k, int m, const cplx* __restrict__ part,
+                                                     const cplx* __restrict__ hp, cplx* __restrict__ Hrow,
+                                                     cplx* __restrict__ hout, cplx* __restrict__ cS,
+                                                     cplx* __restrict__ cZ, cplx* __restrict__ cC,
+                                                     double* __restrict__ sc) {
+  gm_step(k, m, part, hp, Hrow, hout, cS, cZ, cC, sc);
+}
+__global__ __launch_bounds__(256) void k_gm_update(int N, int k, int m, int nrb, cplx* V, int64_t ldv,
+                                                   const cplx* __restrict__ cS, const cplx* __restrict__ cZ,
+                                                   const cplx* __restrict__ cC, const double* __restrict__ sc,
+                                                   const cplx* __restrict__ Hrow, cplx* __restrict__ hp,
+                                                   const cplx* __restrict__ w, const cplx* __restrict__ col,
+                                                   cplx* __restrict__ hout, int64_t* flag, int64_t seq) {
+  gm_update(N, k, m, nrb, V, ldv, cS, cZ, cC, sc, Hrow, hp, w, col, hout, flag, seq);
+}
+
+// The systems of a batched solve: member q's buffers are the base pointers
+// plus q times the strides (bases (m + 1) x N, A u, the small per-member
+// buffers, the device view of its pinned ring slots and flags).  The active
+// members are the set bits of `active`; the i-th of them runs with sequence
+// number seq0 + i.
+struct GmBatch {
+  cplx* V;
+  int64_t vstride;
+  cplx* W;
+  cplx* small;
+  int64_t sstride, o_hcol, o_hpart, o_hp, o_gcoef, o_gsc, o_Hrow;
+  cplx* pin;
+  int64_t pstride;
+  int64_t seq0;
+  uint64_t active;
+};
+
+// index of the i-th set bit of mask (i < popcount(mask))
+__device__ inline int gm_nth_member(uint64_t mask, int i) {
+  for (int t = 0; t < i; ++t) mask &= mask - 1;
+  return __builtin_ctzll(mask);
+}
+
+// Arnoldi step k of every active member (grid dimension z for the sweeps,
+// x for the one-workgroup step): the same bodies as the single-system
+// kernels, on the member's buffers.
+__global__ __launch_bounds__(256) void k_gm_dots_batch(GmBatch B, int N, int k, int full) {
+  const int q = gm_nth_member(B.active, blockIdx.z);
+  const cplx* V = B.V + q * B.vstride;
+  cplx* sm = B.small + q * B.sstride;
+  gm_dots(N, k + 1, V, N, V + (int64_t)k * N, full ? B.W + (int64_t)q * N : nullptr, sm + B.o_hpart);
+}
+__global__ __launch_bounds__(STEP_NT) void k_gm_step_batch(GmBatch B, int k, int m) {
+  const int q = gm_nth_member(B.active, blockIdx.x);
+  cplx* sm = B.small + q * B.sstride;
+  cplx* cS = sm + B.o_gcoef;
+  gm_step(k, m, sm + B.o_hpart, sm + B.o_hp, sm + B.o_Hrow, sm + B.o_hcol + (int64_t)(k % 2) * SESM_HSTRIDE, cS,
+          cS + SESM_HSTRIDE, cS + 2 * SESM_HSTRIDE, reinterpret_cast<double*>(sm + B.o_gsc));
+}
+__global__ __launch_bounds__(256) void k_gm_update_batch(GmBatch B, int N, int k, int m, int nrb) {
+  const int i = blockIdx.z, q = gm_nth_member(B.active, i);
+  cplx* V = B.V + q * B.vstride;
+  cplx* sm = B.small + q * B.sstride;
+  const cplx* cS = sm + B.o_gcoef;
+  cplx* ring = B.pin + q * B.pstride;
+  const int slot = k % SESM_HRING;
+  int64_t* flags = reinterpret_cast<int64_t*>(ring + (int64_t)(SESM_HRING + 1) * SESM_HSTRIDE);
+  gm_update(N, k, m, nrb, V, N, cS, cS + SESM_HSTRIDE, cS + 2 * SESM_HSTRIDE, reinterpret_cast<const double*>(sm + B.o_gsc),
+            sm + B.o_Hrow, sm + B.o_hp, B.W + (int64_t)q * N, sm + B.o_hcol + (int64_t)(k % 2) * SESM_HSTRIDE,
+            ring + (int64_t)slot * SESM_HSTRIDE, flags + slot, B.seq0 + i);
+}
+// the last step of a cycle (no update follows): each member publishes its column
+__global__ __launch_bounds__(256) void k_gm_publish_batch(GmBatch B, int k) {
+  const int i = blockIdx.x, q = gm_nth_member(B.active, i);
+  cplx* sm = B.small + q * B.sstride;
+  cplx* ring = B.pin + q * B.pstride;
+  const int slot = k % SESM_HRING;
+  int64_t* flags = reinterpret_cast<int64_t*>(ring + (int64_t)(SESM_HRING + 1) * SESM_HSTRIDE);
+  gm_publish(k + 1, sm + B.o_hcol + (int64_t)(k % 2) * SESM_HSTRIDE, ring + (int64_t)slot * SESM_HSTRIDE,
+             flags + slot, B.seq0 + i);
 }
 
 // Columns 0..nv-1 of the packed Hessenberg matrix, column-major: column j
@@ -835,6 +916,20 @@ extern "C" int sesm_solve_batch(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_i
     M[r].active = M[r].bnorm != 0.0;
     M[r].res = M[r].bnorm != 0.0 ? 1.0 : 0.0;
   }
+  GmBatch GB0{};
+  GB0.V = Vall;
+  GB0.vstride = vstride;
+  GB0.W = Wall;
+  GB0.small = small;
+  GB0.sstride = per_small;
+  GB0.o_hcol = o_hcol;
+  GB0.o_hpart = o_hpart;
+  GB0.o_hp = o_hp;
+  GB0.o_gcoef = o_gcoef;
+  GB0.o_gsc = o_gsc;
+  GB0.o_Hrow = o_Hrow;
+  GB0.pin = pin_dev;
+  GB0.pstride = (int64_t)pin_per;
   const int steps = m;  // unrestarted: every column of the basis is available
   // Arnoldi step k of every active member: one batched forward map of the
   // members' u = V_k, then each member's dot products, step and update (the
@@ -856,34 +951,32 @@ extern "C" int sesm_solve_batch(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_i
       }
       if (r2) return r2;
     }
-    const int nv = k + 1, slot = k % SESM_HRING;
-    for (int r = lo; r <= hi; ++r) {
-      GmMember& G = M[r];
-      if (!G.active) continue;
-      cplx* u = G.V + (int64_t)k * ldv;
-      cplx* cS = G.gcoef;
-      cplx* cZ = cS + SESM_HSTRIDE;
-      cplx* cC = cZ + SESM_HSTRIDE;
-      hipLaunchKernelGGL(k_gm_dots, dim3(DCHUNK, (nv + VT - 1) / VT), dim3(256), 0, st, N, nv, G.V, ldv, u,
-                         full ? G.w : nullptr, G.hpart);
-      SESM_LAUNCH_CHECK();
-      const int64_t seq = ++ctx->gm_seq;
-      cplx* colv = G.hcol + (size_t)(k % 2) * SESM_HSTRIDE;
-      hipLaunchKernelGGL(k_gm_step, dim3(1), dim3(STEP_NT), 0, st, k, m, G.hpart, G.hp, G.Hrow, colv, cS, cZ, cC,
-                         G.gsc);
-      SESM_LAUNCH_CHECK();
-      G.slot_seq[slot] = seq;
-      cplx* hout = G.hhost_dev + (size_t)slot * SESM_HSTRIDE;
-      if (!full) {
-        hipLaunchKernelGGL(k_gm_publish, dim3(1), dim3(256), 0, st, k + 1, colv, hout, G.hflag_dev + slot, seq);
-        SESM_LAUNCH_CHECK();
-      } else {
-        const int nrb = (N + UPD_ROWS - 1) / UPD_ROWS;
-        hipLaunchKernelGGL(k_gm_update, dim3(nrb + (k + 1 + 3) / 4 + 1), dim3(256), 0, st, N, k, m, nrb, G.V, ldv,
-                           cS, cZ, cC, G.gsc, G.Hrow, G.hp, G.w, colv, hout, G.hflag_dev + slot, seq);
-        SESM_LAUNCH_CHECK();
+    // the members' dot products, steps and updates: one launch each for all
+    // active members (member i of the mask gets sequence number seq0 + i)
+    const int slot = k % SESM_HRING;
+    GmBatch GB = GB0;
+    GB.seq0 = ctx->gm_seq + 1;
+    GB.active = 0;
+    int na = 0;
+    for (int r = 0; r < nrhs; ++r)
+      if (M[r].active) {
+        GB.active |= 1ull << r;
+        M[r].slot_seq[slot] = GB.seq0 + na++;
       }
+    ctx->gm_seq += na;
+    hipLaunchKernelGGL(k_gm_dots_batch, dim3(DCHUNK, (k + 1 + VT - 1) / VT, na), dim3(256), 0, st, GB, N, k,
+                       full ? 1 : 0);
+    SESM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_gm_step_batch, dim3(na), dim3(STEP_NT), 0, st, GB, k, m);
+    SESM_LAUNCH_CHECK();
+    if (!full) {
+      hipLaunchKernelGGL(k_gm_publish_batch, dim3(na), dim3(256), 0, st, GB, k);
+    } else {
+      const int nrb = (N + UPD_ROWS - 1) / UPD_ROWS;
+      hipLaunchKernelGGL(k_gm_update_batch, dim3(nrb + (k + 1 + 3) / 4 + 1, 1, na), dim3(256), 0, st, GB, N, k, m,
+                         nrb);
     }
+    SESM_LAUNCH_CHECK();
     return SESM_OK;
   };
   if ((rc = arnoldi_all(0))) return finish(rc);
