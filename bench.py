@@ -223,7 +223,7 @@ def main():
     bsolve = None
     if args.mode == "accel" and not args.no_batched_solve:
         B = torch.stack([s.rhs_bloch(-p) for p in range(BATCH)])
-        s.solve_batch(B[:2], tol=args.tol, max_iter=args.max_iter, allow_noconv=True)  # warm-up
+        s.solve_batch(B, tol=args.tol, max_iter=args.max_iter, allow_noconv=True)  # warm-up (work space pooled)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         xb, infos = s.solve_batch(B, tol=args.tol, max_iter=args.max_iter, allow_noconv=True)
