@@ -63,7 +63,7 @@ struct AccelOp {
   cplx *p2e = nullptr, *nearblk = nullptr, *dens = nullptr;
   cplx *gH = nullptr, *gV = nullptr, *fH = nullptr, *fV = nullptr, *phH = nullptr, *phV = nullptr;
   cplx *specH = nullptr, *specV = nullptr, *W = nullptr;
-  cplx *pplw = nullptr;  // plane-wave least squares: (U^H)^T (n_bdry x n_plw), V (n_plw x n_plw), 1 / sig
+  cplx *pplw = nullptr;  // plane-wave least squares: (U^H)^T (n_bdry x n_plw), V^T (n_plw x n_plw), 1 / sig
   cplx *pinv = nullptr;  // equivalent-source least squares, per set: Q^H (2n_eq x 4n_coll) then R
   cplx *twxH = nullptr, *twxV = nullptr, *utwH = nullptr, *utwV = nullptr;  // e^{-i alpha x}, e^{+i alpha x}
   double* dirs = nullptr;
@@ -1073,7 +1073,8 @@ __device__ __forceinline__ void cells_far_body(FarArgs A, KParams K, const int* 
       for (; b < A.n_bdry; ++b) y4[0] += pf[b * A.n_plw + lane] * bv[b];
       yu = (y4[0] + y4[1]) + (y4[2] + y4[3]);
     }
-    // w = V (diag(1/sig) U^H b): the scaled coefficients are broadcast by readlane
+    // w = V (diag(1/sig) U^H b): the scaled coefficients are broadcast by readlane;
+    // V is stored transposed so that the lanes read a row of V^T contiguously
     const cplx* Vs = pf + A.n_bdry * A.n_plw;
     const cplx* isg = Vs + A.n_plw * A.n_plw;
     const int lr = lane < A.n_plw ? lane : A.n_plw - 1;
@@ -1084,10 +1085,10 @@ __device__ __forceinline__ void cells_far_body(FarArgs A, KParams K, const int* 
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const cplx ej = cplx{sesm_readlane(e.re, j + u), sesm_readlane(e.im, j + u)};
-        w4[u] += Vs[lr * A.n_plw + j + u] * ej;
+        w4[u] += Vs[(j + u) * A.n_plw + lr] * ej;
       }
     }
-    for (; j < A.n_plw; ++j) w4[0] += Vs[lr * A.n_plw + j] * cplx{sesm_readlane(e.re, j), sesm_readlane(e.im, j)};
+    for (; j < A.n_plw; ++j) w4[0] += Vs[j * A.n_plw + lr] * cplx{sesm_readlane(e.re, j), sesm_readlane(e.im, j)};
     yu = (w4[0] + w4[1]) + (w4[2] + w4[3]);
     if (lane < A.n_plw) wv_sh[lane] = yu;
   }
@@ -1536,7 +1537,11 @@ int sesm_accel_setup(sesm_ctx* ctx) {
         const C v = Uh[(size_t)u * A->n_bdry + b];
         pv.push_back(cplx{v.real(), v.imag()});
       }
-    for (const C& v : Vm) pv.push_back(cplx{v.real(), v.imag()});
+    for (int j = 0; j < A->n_plw; ++j)  // V transposed: lane l of the cell kernel reads V[l][j] contiguously in l
+      for (int l = 0; l < A->n_plw; ++l) {
+        const C v = Vm[(size_t)l * A->n_plw + j];
+        pv.push_back(cplx{v.real(), v.imag()});
+      }
     for (int u = 0; u < A->n_plw; ++u) pv.push_back(cplx{1.0 / sig[u], 0.0});
     if ((rc = upload(ctx, &A->pplw, pv)) || (rc = upload(ctx, &A->dirs, dirs))) return rc;
   }
