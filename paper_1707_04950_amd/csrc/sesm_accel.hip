@@ -983,7 +983,7 @@ struct FarArgs {
 // sides incl. corners, V on vertical sides), minus the equivalent sources of
 // the near columns (local corrections, from k_yconv), plane-wave weights,
 // surface values, plus the completion modes D_M (partial sums from
-// k_local_apply).  Dynamic LDS: the plane-wave factors ((U^H)^T, V, 1/sig),
+// k_local_apply).  Dynamic LDS: the plane-wave factors ((U^H)^T, V^T, 1/sig),
 // the cell's nodes and their values.  Each phase keeps its global loads
 // independent so that they are in flight together.
 template <bool BATCHED>
@@ -1060,37 +1060,42 @@ __device__ __forceinline__ void cells_far_body(FarArgs A, KParams K, const int* 
   }
   __syncthreads();
   // phase 3: plane-wave weights, the least squares of eq. plwave_QR through the
-  // SVD of the plane-wave matrix, w = V diag(1/sig) U^H b, on wavefront 0
-  if (wv == 0) {
-    cplx yu = cplx{0.0, 0.0};
-    if (lane < A.n_plw) {  // U^H b, four independent partial sums
-      cplx y4[4] = {cplx{0.0, 0.0}, cplx{0.0, 0.0}, cplx{0.0, 0.0}, cplx{0.0, 0.0}};
-      int b = 0;
-      for (; b + 4 <= A.n_bdry; b += 4) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) y4[u] += pf[(b + u) * A.n_plw + lane] * bv[b + u];
-      }
-      for (; b < A.n_bdry; ++b) y4[0] += pf[b * A.n_plw + lane] * bv[b];
-      yu = (y4[0] + y4[1]) + (y4[2] + y4[3]);
-    }
-    // w = V (diag(1/sig) U^H b): the scaled coefficients are broadcast by readlane;
-    // V is stored transposed so that the lanes read a row of V^T contiguously
+  // SVD of the plane-wave matrix, w = V diag(1/sig) U^H b: each product is
+  // split over the four wavefronts (a quarter of the summation index each;
+  // lane l holds output l) and the quarters are added in LDS in a fixed order;
+  // V is stored transposed so that the lanes read V^T contiguously
+  {
+    __shared__ cplx p3[4][64];
+    __shared__ cplx e_sh[64];
     const cplx* Vs = pf + A.n_bdry * A.n_plw;
     const cplx* isg = Vs + A.n_plw * A.n_plw;
-    const int lr = lane < A.n_plw ? lane : A.n_plw - 1;
-    const cplx e = lane < A.n_plw ? isg[lane].re * yu : cplx{0.0, 0.0};
-    cplx w4[4] = {cplx{0.0, 0.0}, cplx{0.0, 0.0}, cplx{0.0, 0.0}, cplx{0.0, 0.0}};
-    int j = 0;
-    for (; j + 4 <= A.n_plw; j += 4) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const cplx ej = cplx{sesm_readlane(e.re, j + u), sesm_readlane(e.im, j + u)};
-        w4[u] += Vs[(j + u) * A.n_plw + lr] * ej;
-      }
+    // U^H b: wavefront g sums its quarter of the boundary points
+    {
+      const int nb4 = (A.n_bdry + 3) / 4, b0 = wv * nb4, b1 = min(A.n_bdry, b0 + nb4);
+      cplx acc = cplx{0.0, 0.0};
+      if (lane < A.n_plw)
+        for (int b = b0; b < b1; ++b) acc += pf[b * A.n_plw + lane] * bv[b];
+      p3[wv][lane] = acc;
     }
-    for (; j < A.n_plw; ++j) w4[0] += Vs[j * A.n_plw + lr] * cplx{sesm_readlane(e.re, j), sesm_readlane(e.im, j)};
-    yu = (w4[0] + w4[1]) + (w4[2] + w4[3]);
-    if (lane < A.n_plw) wv_sh[lane] = yu;
+    __syncthreads();
+    if (threadIdx.x < A.n_plw) {
+      const int l = threadIdx.x;
+      e_sh[l] = isg[l].re * ((p3[0][l] + p3[1][l]) + (p3[2][l] + p3[3][l]));
+    }
+    __syncthreads();
+    // w = V e: wavefront g sums its quarter of the directions
+    {
+      const int nj4 = (A.n_plw + 3) / 4, j0 = wv * nj4, j1 = min(A.n_plw, j0 + nj4);
+      cplx acc = cplx{0.0, 0.0};
+      if (lane < A.n_plw)
+        for (int j = j0; j < j1; ++j) acc += Vs[j * A.n_plw + lane] * e_sh[j];
+      p3[wv][lane] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x < A.n_plw) {
+      const int l = threadIdx.x;
+      wv_sh[l] = (p3[0][l] + p3[1][l]) + (p3[2][l] + p3[3][l]);
+    }
   }
   __syncthreads();
   // phase 4: surface values (eq. planewave), origin at the cell centre.  With
@@ -1525,7 +1530,7 @@ int sesm_accel_setup(sesm_ctx* ctx) {
         E[(size_t)b * A->n_plw + s] = std::exp(C(0.0, P.k * (dirs[2 * s] * bx + dirs[2 * s + 1] * by)));
     }
     if (A->n_bdry < A->n_plw) return ctx->fail(SESM_EINVAL, "accelerator: need n_plw <= boundary points (4 n_side)");
-    // w = V diag(1/sig) U^H b: (U^H)^T, V and 1/sig for the cell kernel (the
+    // w = V diag(1/sig) U^H b: (U^H)^T, V^T and 1/sig for the cell kernel (the
     // three factors are applied one after the other, never multiplied out)
     std::vector<C> Uh, Vm;
     std::vector<double> sig;
