@@ -60,6 +60,8 @@ struct AccelOp {
   int64_t* near_off = nullptr;
   int n_chunks = 0, max_w = 0;  // near-field row chunks (cell, first row); widest band
   int *chunk_q = nullptr, *chunk_t0 = nullptr;
+  int n_cfc = 0;  // far-field work items: up to CF_NODES nodes of one cell (cell, first node)
+  int *cfc_q = nullptr, *cfc_t0 = nullptr;
   cplx *p2e = nullptr, *nearblk = nullptr, *dens = nullptr;
   cplx *gH = nullptr, *gV = nullptr, *fH = nullptr, *fV = nullptr, *phH = nullptr, *phV = nullptr;
   cplx *specH = nullptr, *specV = nullptr, *W = nullptr;
@@ -88,6 +90,7 @@ namespace {
 constexpr double PI = 3.14159265358979323846;
 constexpr int NCH_MODES = 240;
 constexpr int kBatchMax = 4;  // densities per batched local launch
+constexpr int CF_NODES = 64;  // nodes per workgroup of the cell far-field kernel
 
 int smooth5_at_least(int n) {
   for (;; ++n) {
@@ -977,6 +980,8 @@ struct FarArgs {
   double L, x0, y0, k, alpha_d;
   // batched launches: per-member offsets of corr, phH, phV, mode_part and y
   int64_t bcorr, bphH, bphV, bmode, by;
+  const int* cfc_q;   // work item -> occupied cell
+  const int* cfc_t0;  // work item -> its first node within the cell (max_q: nodes per item)
 };
 
 // One block per occupied cell: boundary values of phi^all (H on horizontal
@@ -1007,11 +1012,13 @@ __device__ __forceinline__ void cells_far_body(FarArgs A, KParams K, const int* 
     mode_part += m * A.bmode;
     y += m * A.by;
   }
-  const int q = blockIdx.x;
+  // work item: up to max_q consecutive nodes of occupied cell q (the cell's
+  // boundary values and plane-wave weights are formed by each of its items)
+  const int q = A.cfc_q[blockIdx.x], t0c = A.cfc_t0[blockIdx.x];
   const int cell = occ_cell[q];
   const int cx = cell % A.n_x, cy = cell / A.n_x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int off = occ_off[q], nq = occ_off[q + 1] - off;
+  const int off = occ_off[q] + t0c, nq = min(A.max_q, occ_off[q + 1] - off);
   const double ccx = A.x0 + (cx + 0.5) * A.L, ccy = A.y0 + (cy + 0.5) * A.L;
   const int npf = (A.n_bdry + A.n_plw + 1) * A.n_plw;  // plane-wave factors
   cplx* pf = dyn;
@@ -1165,7 +1172,7 @@ __global__ __launch_bounds__(256) void k_cells_far_batch(SESM_CELLS_FAR_PARAMS) 
 // dynamic LDS bytes of k_cells_far
 inline size_t cells_far_lds(const AccelOp* A) {
   const size_t npf = (size_t)(A->n_bdry + A->n_plw + 1) * A->n_plw;
-  const size_t mq = (size_t)A->max_q;
+  const size_t mq = (size_t)std::min(A->max_q, CF_NODES);
   return sizeof(cplx) * (npf + mq) + sizeof(double) * 2 * mq + sizeof(int) * mq;
 }
 
@@ -1333,12 +1340,21 @@ int sesm_accel_setup(sesm_ctx* ctx) {
       chunk_t0.push_back(t0);
     }
   A->n_chunks = (int)chunk_q.size();
+  // far-field work items: up to CF_NODES nodes of one cell
+  std::vector<int> cfc_q, cfc_t0;
+  for (int q = 0; q < A->n_occ; ++q)
+    for (int t0 = 0; t0 < occ_off[q + 1] - occ_off[q]; t0 += CF_NODES) {
+      cfc_q.push_back(q);
+      cfc_t0.push_back(t0);
+    }
+  A->n_cfc = (int)cfc_q.size();
   for (int c = 0; c < A->n_x; ++c) A->max_w = std::max(A->max_w, col_w[c]);
   int rc;
   if ((rc = upload(ctx, &A->occ_cell, occ_cell)) || (rc = upload(ctx, &A->occ_off, occ_off)) ||
       (rc = upload(ctx, &A->perm, perm)) || (rc = upload(ctx, &A->col_lo, col_lo)) ||
       (rc = upload(ctx, &A->col_w, col_w)) || (rc = upload(ctx, &A->near_off, near_off)) ||
-      (rc = upload(ctx, &A->chunk_q, chunk_q)) || (rc = upload(ctx, &A->chunk_t0, chunk_t0)))
+      (rc = upload(ctx, &A->chunk_q, chunk_q)) || (rc = upload(ctx, &A->chunk_t0, chunk_t0)) ||
+      (rc = upload(ctx, &A->cfc_q, cfc_q)) || (rc = upload(ctx, &A->cfc_t0, cfc_t0)))
     return rc;
   // local-correction pairs: for every occupied cell, the occupied cells of its
   // 2 ring + 1 columns (all rows), with the correction-matrix offset and the
@@ -1697,10 +1713,10 @@ static int accel_far_stages(sesm_ctx* ctx, const FarBufs& Fb, bool keep_far, con
   }
   SESM_KT_END(SESM_KT_FFT, st, nb * (B.fftH1 + B.fftV1));
   FarArgs F{P.N,    A->n_x,   A->n_y,   A->n_s,    A->n_e, A->n_side, A->n_eq, A->n_cells, A->n_bdry, A->n_bH,
-            A->n_plw, A->nXH, A->nXV,   A->ring,   A->max_q, A->L,   A->x0,     A->y0,   P.k,        P.alpha * P.d,
-            Fb.bcorr, Fb.bphH, Fb.bphV, Fb.bmode, Fb.by};
+            A->n_plw, A->nXH, A->nXV,   A->ring,   std::min(A->max_q, CF_NODES), A->L,   A->x0,     A->y0,   P.k,
+            P.alpha * P.d, Fb.bcorr, Fb.bphH, Fb.bphV, Fb.bmode, Fb.by, A->cfc_q, A->cfc_t0};
   SESM_KT_BEGIN(SESM_KT_CELLS, st);
-  hipLaunchKernelGGL(nb > 1 ? k_cells_far_batch : k_cells_far, dim3(A->n_occ, nb), dim3(256), cells_far_lds(A), st,
+  hipLaunchKernelGGL(nb > 1 ? k_cells_far_batch : k_cells_far, dim3(A->n_cfc, nb), dim3(256), cells_far_lds(A), st,
                      F, K, A->occ_cell,
                      A->occ_off, A->perm, A->pair_off, Fb.corr, Fb.phH, Fb.phV, A->pplw, A->dirs, ctx->x, ctx->f,
                      Fb.mode, Fb.y, keep_far ? A->yfar : nullptr);
