@@ -980,7 +980,7 @@ struct FarArgs {
   double L, x0, y0, k, alpha_d;
   // batched launches: per-member offsets of corr, phH, phV, mode_part and y
   int64_t bcorr, bphH, bphV, bmode, by;
-  const int* cfc_q;   // work item -> occupied cell
+  const int* cfc_q;   // work item -> occupied cell (null: one item per cell)
   const int* cfc_t0;  // work item -> its first node within the cell (max_q: nodes per item)
 };
 
@@ -1014,7 +1014,7 @@ __device__ __forceinline__ void cells_far_body(FarArgs A, KParams K, const int* 
   }
   // work item: up to max_q consecutive nodes of occupied cell q (the cell's
   // boundary values and plane-wave weights are formed by each of its items)
-  const int q = A.cfc_q[blockIdx.x], t0c = A.cfc_t0[blockIdx.x];
+  const int q = A.cfc_q ? A.cfc_q[blockIdx.x] : (int)blockIdx.x, t0c = A.cfc_q ? A.cfc_t0[blockIdx.x] : 0;
   const int cell = occ_cell[q];
   const int cx = cell % A.n_x, cy = cell / A.n_x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1169,10 +1169,10 @@ __global__ __launch_bounds__(256) void k_cells_far_batch(SESM_CELLS_FAR_PARAMS) 
 }
 #undef SESM_CELLS_FAR_PARAMS
 
-// dynamic LDS bytes of k_cells_far
-inline size_t cells_far_lds(const AccelOp* A) {
+// dynamic LDS bytes of k_cells_far for work items of up to mq nodes
+inline size_t cells_far_lds(const AccelOp* A, int mq_) {
   const size_t npf = (size_t)(A->n_bdry + A->n_plw + 1) * A->n_plw;
-  const size_t mq = (size_t)std::min(A->max_q, CF_NODES);
+  const size_t mq = (size_t)mq_;
   return sizeof(cplx) * (npf + mq) + sizeof(double) * 2 * mq + sizeof(int) * mq;
 }
 
@@ -1454,7 +1454,7 @@ int sesm_accel_setup(sesm_ctx* ctx) {
   // --- local correction matrices
   A->n_off = (2 * A->ring + 1) * (2 * A->n_y - 1);
   {
-    const size_t lds = cells_far_lds(A);
+    const size_t lds = cells_far_lds(A, A->max_q);  // whole cells (batched launches); items need less
     if (lds > 140 * 1024) return ctx->fail(SESM_EINVAL, "accelerator: plane-wave factors exceed the LDS of a workgroup");
     if (lds > 64 * 1024) {
       SESM_HIP(hipFuncSetAttribute((const void*)k_cells_far, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -1712,12 +1712,17 @@ static int accel_far_stages(sesm_ctx* ctx, const FarBufs& Fb, bool keep_far, con
     if ((rc = fft_launch(ctx, st, jh, jv, +1, nb, FftBatch{Fb.bgH, Fb.bphH, Fb.bgV, Fb.bphV}))) return rc;
   }
   SESM_KT_END(SESM_KT_FFT, st, nb * (B.fftH1 + B.fftV1));
+  // one density: work items of up to CF_NODES nodes (the fullest cells no
+  // longer set the length of the launch); several: one workgroup per cell and
+  // member (the members already fill the chip)
+  const bool items = nb == 1;
+  const int mq = items ? std::min(A->max_q, CF_NODES) : A->max_q;
   FarArgs F{P.N,    A->n_x,   A->n_y,   A->n_s,    A->n_e, A->n_side, A->n_eq, A->n_cells, A->n_bdry, A->n_bH,
-            A->n_plw, A->nXH, A->nXV,   A->ring,   std::min(A->max_q, CF_NODES), A->L,   A->x0,     A->y0,   P.k,
-            P.alpha * P.d, Fb.bcorr, Fb.bphH, Fb.bphV, Fb.bmode, Fb.by, A->cfc_q, A->cfc_t0};
+            A->n_plw, A->nXH, A->nXV,   A->ring,   mq,     A->L,   A->x0,     A->y0,   P.k,        P.alpha * P.d,
+            Fb.bcorr, Fb.bphH, Fb.bphV, Fb.bmode, Fb.by, items ? A->cfc_q : nullptr, items ? A->cfc_t0 : nullptr};
   SESM_KT_BEGIN(SESM_KT_CELLS, st);
-  hipLaunchKernelGGL(nb > 1 ? k_cells_far_batch : k_cells_far, dim3(A->n_cfc, nb), dim3(256), cells_far_lds(A), st,
-                     F, K, A->occ_cell,
+  hipLaunchKernelGGL(nb > 1 ? k_cells_far_batch : k_cells_far, dim3(items ? A->n_cfc : A->n_occ, nb), dim3(256),
+                     cells_far_lds(A, mq), st, F, K, A->occ_cell,
                      A->occ_off, A->perm, A->pair_off, Fb.corr, Fb.phH, Fb.phV, A->pplw, A->dirs, ctx->x, ctx->f,
                      Fb.mode, Fb.y, keep_far ? A->yfar : nullptr);
   SESM_LAUNCH_CHECK();
