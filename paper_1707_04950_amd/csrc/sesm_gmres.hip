@@ -810,12 +810,9 @@ void gm_release(sesm_ctx* ctx, void* p) {
 struct GmMember {
   cplx *V, *w, *x;  // basis (m + 1) x N, A u, solution
   const cplx* b;
-  cplx *hcol, *hpart, *ybuf, *hp, *gcoef, *Hrow, *htri;
-  double* gsc;
+  cplx *hcol, *hpart, *ybuf, *Hrow, *htri;  // (the step kernels derive the rest from GmBatch)
   cplx* hhost;  // pinned ring slots (+ one upload slot) and their flags
-  cplx* hhost_dev;
   int64_t* hflag;
-  int64_t* hflag_dev;
   int64_t slot_seq[SESM_HRING] = {};
   std::vector<Cd> H, Hraw, cs, sn, g;
   double bnorm = 0.0, beta0 = 0.0, res = 1.0;
@@ -885,15 +882,10 @@ extern "C" int sesm_solve_batch(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_i
     G.hcol = sm + o_hcol;
     G.hpart = sm + o_hpart;
     G.ybuf = sm + o_ybuf;
-    G.hp = sm + o_hp;
-    G.gcoef = sm + o_gcoef;
-    G.gsc = reinterpret_cast<double*>(sm + o_gsc);
     G.Hrow = sm + o_Hrow;
     G.htri = sm + o_htri;
     G.hhost = pin + r * pin_per;
-    G.hhost_dev = pin_dev + r * pin_per;
     G.hflag = reinterpret_cast<int64_t*>(G.hhost + (size_t)(SESM_HRING + 1) * SESM_HSTRIDE);
-    G.hflag_dev = reinterpret_cast<int64_t*>(G.hhost_dev + (size_t)(SESM_HRING + 1) * SESM_HSTRIDE);
     for (int t = 0; t < SESM_HRING; ++t) G.hflag[t] = 0;
     double* hv = reinterpret_cast<double*>(G.hhost);
     for (size_t t = 0; t < (size_t)2 * SESM_HRING * SESM_HSTRIDE; ++t) hv[t] = column_sentinel();
