@@ -246,6 +246,17 @@ def test_solve_batch_equals_single_solves(torch, solver, accelerated):
     assert infos[4]["iters"] == 0 and bool((mu[4] == 0).all())
 
 
+def test_solve_batch_single_member(torch, solver):
+    """A batch of one (one-member launches throughout) equals the single solve."""
+    wl = _gauss30(37.0)
+    disc = dense.Discretization(wl)
+    _configure(solver, wl, disc, True)
+    B = solver.rhs_bloch(-1)[None, :]
+    mu, infos = solver.solve_batch(B, tol=1e-12, max_iter=400)
+    m1, i1 = solver.solve(B[0].contiguous(), tol=1e-12, max_iter=400)
+    assert infos[0]["converged"] and infos[0]["iters"] == i1["iters"] and torch.equal(mu[0], m1)
+
+
 def test_solve_batch_bloch_efficiencies_vs_oracle(torch, solver):
     """Members p = 0, -1, 1 of the Bloch class of the 37 degree incidence,
     solved in one accelerated batch: the right-hand sides equal the oracle's
