@@ -984,12 +984,13 @@ struct FarArgs {
   const int* cfc_t0;  // work item -> its first node within the cell (max_q: nodes per item)
 };
 
-// One block per occupied cell: boundary values of phi^all (H on horizontal
-// sides incl. corners, V on vertical sides), minus the equivalent sources of
-// the near columns (local corrections, from k_yconv), plane-wave weights,
-// surface values, plus the completion modes D_M (partial sums from
-// k_local_apply).  Dynamic LDS: the plane-wave factors ((U^H)^T, V^T, 1/sig),
-// the cell's nodes and their values.  Each phase keeps its global loads
+// One block per work item (up to max_q nodes of one occupied cell): the
+// cell's boundary values of phi^all (H on horizontal sides incl. corners, V on
+// vertical sides), minus the equivalent sources of the near columns (local
+// corrections, from k_yconv), plane-wave weights, then the item's surface
+// values plus the completion modes D_M (partial sums from k_local_apply).
+// Dynamic LDS: the plane-wave factors ((U^H)^T, V^T, 1/sig), the item's nodes
+// and their values.  Each phase keeps its global loads
 // independent so that they are in flight together.
 template <bool BATCHED>
 __device__ __forceinline__ void cells_far_body(FarArgs A, KParams K, const int* __restrict__ occ_cell,
