@@ -89,12 +89,21 @@ typedef struct {
 
 typedef struct {
   int32_t iters;          /* Krylov iterations performed            */
-  double rel_residual;    /* final ||b - A mu|| / ||b|| estimate     */
-  int32_t converged;      /* 1 if rel_residual <= tol               */
+  double rel_residual;    /* final true relative residual ||b - A mu|| / ||b||, with
+                             A mu formed by one more forward map after the last cycle */
+  int32_t converged;      /* 1 if rel_residual (the true one) <= tol */
   int32_t column_mismatches; /* Hessenberg columns whose copy streamed to the host
                                 during a cycle differed from the device's (the
                                 update of mu always uses the device's); 0 expected */
+  double est_residual;    /* the Givens (least-squares) estimate of the relative
+                             residual at the end of the last Krylov cycle      */
+  int32_t residual_restarts; /* extra Krylov cycles started because the true
+                                residual was above tol while the estimate was not */
+  int32_t reserved_i;
 } sesm_solve_info;
+
+/* flags of sesm_solve / sesm_solve_batch */
+#define SESM_SOLVE_X0 1  /* mu holds the initial guess x0 on entry (warm start) */
 
 /* Read-only description of the discretisation chosen by sesm_set_surface. */
 typedef struct {
@@ -171,12 +180,18 @@ SESM_API int sesm_rhs_bloch(sesm_ctx* ctx, int32_t p, sesm_c64* b);
 
 /* Algorithm 1: GMRES solve of (1/2 I + D^dx) mu = b.  b: device array of N
  * (NULL selects the incident-field right-hand side of sesm_rhs).  mu: device
- * array of N, output only (the iteration starts from zero).  tol: relative residual;
- * max_iter: iteration cap; restart: Krylov dimension (0 = max_iter, i.e.
- * unrestarted).  info: host struct, may be NULL.  Returns SESM_ENOCONV if tol
- * was not reached (mu and info still hold the last iterate). */
+ * array of N; with SESM_SOLVE_X0 in flags it holds the initial guess x0 on
+ * entry (in: x0, out: solution), otherwise the iteration starts from zero and
+ * mu is output only.  tol: relative residual; max_iter: iteration cap (over
+ * all cycles); restart: Krylov dimension of a cycle (0 = max_iter, i.e.
+ * unrestarted; at most 4000).  When a cycle's least-squares estimate reaches
+ * tol, the true residual b - A mu is formed with one more forward map; if it
+ * is still above tol and iterations remain, a new cycle starts from it (the
+ * restart step).  converged and rel_residual report the true residual.
+ * info: host struct, may be NULL.  Returns SESM_ENOCONV if tol was not
+ * reached (mu and info still hold the last iterate). */
 SESM_API int sesm_solve(sesm_ctx* ctx, const sesm_c64* b, sesm_c64* mu, double tol, int32_t max_iter,
-               int32_t restart, sesm_solve_info* info);
+               int32_t restart, int32_t flags, sesm_solve_info* info);
 
 #define SESM_MAX_BATCH 64  /* right-hand sides per sesm_solve_batch call */
 
@@ -186,17 +201,22 @@ SESM_API int sesm_solve(sesm_ctx* ctx, const sesm_c64* b, sesm_c64* mu, double t
  * lockstep so that every Arnoldi step applies the operator to all active
  * systems with one batched forward map (Algorithm 3).  Right-hand side r is
  * the device array b + r ld_b of N sesm_c64, solution r is mu + r ld_mu
- * (output only; each iteration starts from zero); ld_b, ld_mu >= N and the two
- * spans must not overlap.  A system leaves the batch once it reaches tol;
- * each solution equals that of sesm_solve(b_r, restart = 0) with the same
- * tol and max_iter bit for bit.  0 <= nrhs <= SESM_MAX_BATCH,
+ * (with SESM_SOLVE_X0 in flags it holds that system's initial guess on entry,
+ * otherwise it is output only and the iteration starts from zero); ld_b,
+ * ld_mu >= N and the two spans must not overlap.  A system leaves the batch
+ * once its least-squares estimate reaches tol; the true residuals are then
+ * formed with one batched forward map, and a system whose true residual is
+ * still above tol continues alone with restarted cycles (sesm_solve with a
+ * warm start) while iterations remain.  Each solution equals that of
+ * sesm_solve(b_r, restart = 0, same flags) with the same tol and max_iter bit
+ * for bit.  0 <= nrhs <= SESM_MAX_BATCH,
  * 1 <= max_iter <= 4000.  info: host array of nrhs records, may be NULL.
  * The call allocates its work space (nrhs (max_iter + 1) N complex values for
  * the bases, plus small buffers) and returns it to the context's pool at the
  * end.  Returns SESM_ENOCONV if any system missed tol (all outputs still
  * written). */
 SESM_API int sesm_solve_batch(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b, int64_t ld_b, sesm_c64* mu,
-                              int64_t ld_mu, double tol, int32_t max_iter, sesm_solve_info* info);
+                              int64_t ld_mu, double tol, int32_t max_iter, int32_t flags, sesm_solve_info* info);
 
 /* Efficiencies e_n = (beta_n / beta) |B_n|^2 of the propagating orders
  * (Sec. 2) and the energy-balance error eps = 1 - sum e_n, eq. (energy_error).

@@ -39,7 +39,17 @@ class Params(ctypes.Structure):
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("rel_residual", ctypes.c_double), ("converged", ctypes.c_int32),
-                ("column_mismatches", ctypes.c_int32)]
+                ("column_mismatches", ctypes.c_int32), ("est_residual", ctypes.c_double),
+                ("residual_restarts", ctypes.c_int32), ("reserved_i", ctypes.c_int32)]
+
+
+SOLVE_X0 = 1  # sesm_solve flag: mu holds the initial guess on entry
+
+
+def _info_dict(i):
+    return {"iters": i.iters, "rel_residual": i.rel_residual, "converged": bool(i.converged),
+            "column_mismatches": i.column_mismatches, "est_residual": i.est_residual,
+            "residual_restarts": i.residual_restarts}
 
 
 # kernel classes of sesm_timing_enable (bit i of the mask selects class i)
@@ -86,8 +96,8 @@ def load_library(path=LIB_PATH):
         "sesm_matvec_batch": (ctypes.c_int, [_P, _I, _P, ctypes.c_int64, _P, ctypes.c_int64]),
         "sesm_rhs": (ctypes.c_int, [_P, _P]),
         "sesm_rhs_bloch": (ctypes.c_int, [_P, _I, _P]),
-        "sesm_solve": (ctypes.c_int, [_P, _P, _P, _D, _I, _I, ctypes.POINTER(SolveInfo)]),
-        "sesm_solve_batch": (ctypes.c_int, [_P, _I, _P, ctypes.c_int64, _P, ctypes.c_int64, _D, _I, _P]),
+        "sesm_solve": (ctypes.c_int, [_P, _P, _P, _D, _I, _I, _I, ctypes.POINTER(SolveInfo)]),
+        "sesm_solve_batch": (ctypes.c_int, [_P, _I, _P, ctypes.c_int64, _P, ctypes.c_int64, _D, _I, _I, _P]),
         "sesm_efficiencies": (ctypes.c_int, [_P, _P, ctypes.POINTER(_I), ctypes.POINTER(_I),
                                              ctypes.POINTER(_D), _I, ctypes.POINTER(_D)]),
         "sesm_rayleigh": (ctypes.c_int, [_P, _P, ctypes.POINTER(_I), _I, _P]),
@@ -115,18 +125,43 @@ class SesmError(RuntimeError):
         self.code = code
 
 
-def _ptr(t):
+def _ptr(t, n=None):
+    """Pointer of a contiguous complex128 CUDA tensor holding at least n
+    elements (the library reads or writes n elements through it)."""
     import torch
-    if not (t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()):
-        raise ValueError("expected a contiguous complex128 CUDA tensor")
+    if t.dtype != torch.complex128:
+        raise ValueError("expected a complex128 tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if n is not None and t.numel() < n:
+        raise ValueError("tensor holds %d elements, the library needs %d" % (t.numel(), n))
+    if not t.is_cuda:
+        raise ValueError("expected a CUDA tensor")
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _ptr_rows(t):
-    """Pointer of a 2-D complex128 CUDA tensor whose rows have unit stride."""
+def _ptr_rows(t, n, rows=None):
+    """Pointer of a 2-D complex128 CUDA tensor whose rows have unit stride:
+    row r (r < rows) is read or written as n elements at data_ptr + r stride(0),
+    so the rows must be at least n long and stride(0) >= n (no overlap)."""
     import torch
-    if not (t.is_cuda and t.dtype == torch.complex128 and t.dim() == 2 and (t.shape[1] <= 1 or t.stride(1) == 1)):
-        raise ValueError("expected a 2-D complex128 CUDA tensor with unit stride along rows")
+    if t.dtype != torch.complex128 or t.dim() != 2:
+        raise ValueError("expected a 2-D complex128 tensor")
+    rows = t.shape[0] if rows is None else rows
+    if t.shape[1] < n:
+        raise ValueError("rows hold %d elements, the library needs %d" % (t.shape[1], n))
+    if t.shape[0] < rows:
+        raise ValueError("tensor has %d rows, the call needs %d" % (t.shape[0], rows))
+    if t.shape[1] > 1 and t.stride(1) != 1:
+        raise ValueError("expected unit stride along rows")
+    if rows > 1 and t.stride(0) < n:
+        raise ValueError("row stride %d is below the row length %d" % (t.stride(0), n))
+    # the rows' span must lie inside the tensor's storage
+    end = t.storage_offset() + (rows - 1) * t.stride(0) + n if rows > 0 else 0
+    if end > t.untyped_storage().nbytes() // t.element_size():
+        raise ValueError("rows extend past the tensor's storage")
+    if not t.is_cuda:
+        raise ValueError("expected a CUDA tensor")
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -192,7 +227,7 @@ class Solver:
 
     def matvec(self, mu, out=None):
         out = self.empty() if out is None else out
-        self._check(self.lib.sesm_matvec(self.h, _ptr(mu), _ptr(out)))
+        self._check(self.lib.sesm_matvec(self.h, _ptr(mu, self.N), _ptr(out, self.N)))
         return out
 
     def matvec_batch(self, mu, out=None):
@@ -206,37 +241,51 @@ class Solver:
                 out.fill_(complex("nan+nanj"))
         if out.dim() != 2 or out.shape[0] != mu.shape[0] or out.shape[1] < self.N:
             raise ValueError("out must be a (nrhs, >= N) tensor")
-        self._check(self.lib.sesm_matvec_batch(self.h, int(mu.shape[0]), _ptr_rows(mu), int(mu.stride(0)),
-                                               _ptr_rows(out), int(out.stride(0))))
+        n = int(mu.shape[0])
+        self._check(self.lib.sesm_matvec_batch(self.h, n, _ptr_rows(mu, self.N), int(mu.stride(0)),
+                                               _ptr_rows(out, self.N, n), int(out.stride(0))))
         return out
 
     def rhs(self, out=None):
         out = self.empty() if out is None else out
-        self._check(self.lib.sesm_rhs(self.h, _ptr(out)))
+        self._check(self.lib.sesm_rhs(self.h, _ptr(out, self.N)))
         return out
 
     def rhs_bloch(self, p, out=None):
         """Right-hand side of the incidence alpha + 2 pi p / d (same operator)."""
         out = self.empty() if out is None else out
-        self._check(self.lib.sesm_rhs_bloch(self.h, int(p), _ptr(out)))
+        self._check(self.lib.sesm_rhs_bloch(self.h, int(p), _ptr(out, self.N)))
         return out
 
-    def solve(self, b=None, tol=1e-10, max_iter=1000, restart=0, out=None, allow_noconv=False):
+    def solve(self, b=None, tol=1e-10, max_iter=1000, restart=0, out=None, allow_noconv=False, x0=None):
+        """GMRES solve; x0 (a device tensor of N) is the initial guess and is
+        overwritten with the solution (warm start); otherwise the iteration
+        starts from zero and the solution goes to out (allocated if None)."""
+        flags = 0
+        if x0 is not None:
+            if out is not None and out is not x0:
+                raise ValueError("with x0 the solution overwrites x0; do not pass out")
+            out, flags = x0, SOLVE_X0
         out = self.empty() if out is None else out
         inf = SolveInfo()
-        bp = _ptr(b) if b is not None else None
-        rc = self.lib.sesm_solve(self.h, bp, _ptr(out), tol, max_iter, restart, ctypes.byref(inf))
+        bp = _ptr(b, self.N) if b is not None else None
+        rc = self.lib.sesm_solve(self.h, bp, _ptr(out, self.N), tol, max_iter, restart, flags, ctypes.byref(inf))
         self._check(rc, allow=(SESM_ENOCONV,) if allow_noconv else ())
-        return out, {"iters": inf.iters, "rel_residual": inf.rel_residual, "converged": bool(inf.converged),
-                     "column_mismatches": inf.column_mismatches}
+        return out, _info_dict(inf)
 
-    def solve_batch(self, b, tol=1e-10, max_iter=1000, out=None, allow_noconv=False):
+    def solve_batch(self, b, tol=1e-10, max_iter=1000, out=None, allow_noconv=False, x0=None):
         """Unrestarted GMRES for the rows of b (nrhs x >= N, complex128 on the
         device) in lockstep; returns the solutions (rows of out) and one info
-        dict per row."""
+        dict per row.  x0 (nrhs x >= N): initial guesses, overwritten with the
+        solutions (warm start)."""
         if b.dim() != 2 or b.shape[1] < self.N:
             raise ValueError("b must be a (nrhs, >= N) tensor")
         n = int(b.shape[0])
+        flags = 0
+        if x0 is not None:
+            if out is not None and out is not x0:
+                raise ValueError("with x0 the solutions overwrite x0; do not pass out")
+            out, flags = x0, SOLVE_X0
         if out is None:
             out = self._torch.empty((n, self.N), dtype=self._torch.complex128, device=self.device)
             if os.environ.get("SESM_POISON_ALLOC", "0") not in ("", "0"):
@@ -244,36 +293,35 @@ class Solver:
         if out.dim() != 2 or out.shape[0] != n or out.shape[1] < self.N:
             raise ValueError("out must be a (nrhs, >= N) tensor")
         infs = (SolveInfo * max(n, 1))()
-        rc = self.lib.sesm_solve_batch(self.h, n, _ptr_rows(b), int(b.stride(0)), _ptr_rows(out), int(out.stride(0)),
-                                       tol, max_iter, ctypes.cast(infs, ctypes.c_void_p))
+        rc = self.lib.sesm_solve_batch(self.h, n, _ptr_rows(b, self.N), int(b.stride(0)), _ptr_rows(out, self.N, n),
+                                       int(out.stride(0)), tol, max_iter, flags, ctypes.cast(infs, ctypes.c_void_p))
         self._check(rc, allow=(SESM_ENOCONV,) if allow_noconv else ())
-        return out, [{"iters": i.iters, "rel_residual": i.rel_residual, "converged": bool(i.converged),
-                      "column_mismatches": i.column_mismatches} for i in infs[:n]]
+        return out, [_info_dict(i) for i in infs[:n]]
 
     def efficiencies(self, mu):
         cap = 4096
         e = np.zeros(cap)
         n0, nc = _I(), _I()
         eps = _D()
-        self._check(self.lib.sesm_efficiencies(self.h, _ptr(mu), ctypes.byref(n0), ctypes.byref(nc),
+        self._check(self.lib.sesm_efficiencies(self.h, _ptr(mu, self.N), ctypes.byref(n0), ctypes.byref(nc),
                                                e.ctypes.data_as(ctypes.POINTER(_D)), cap, ctypes.byref(eps)))
         return np.arange(n0.value, n0.value + nc.value), e[: nc.value].copy(), eps.value
 
     def rayleigh(self, mu, orders):
         o = np.ascontiguousarray(orders, dtype=np.int32)
         B = np.zeros(len(o), dtype=np.complex128)
-        self._check(self.lib.sesm_rayleigh(self.h, _ptr(mu), o.ctypes.data_as(ctypes.POINTER(_I)), len(o),
+        self._check(self.lib.sesm_rayleigh(self.h, _ptr(mu, self.N), o.ctypes.data_as(ctypes.POINTER(_I)), len(o),
                                            ctypes.c_void_p(B.ctypes.data)))
         return B
 
     def diag_accel(self, mu, which, length):
         out = self._torch.empty(length, dtype=self._torch.complex128, device=self.device)
-        self._check(self.lib.sesm_diag_accel(self.h, _ptr(mu), which, _ptr(out), length))
+        self._check(self.lib.sesm_diag_accel(self.h, _ptr(mu, self.N), which, _ptr(out, length), length))
         return out
 
     def diag_near(self, mu, out=None):
         out = self.empty() if out is None else out
-        self._check(self.lib.sesm_diag_near(self.h, _ptr(mu), _ptr(out)))
+        self._check(self.lib.sesm_diag_near(self.h, _ptr(mu, self.N), _ptr(out, self.N)))
         return out
 
     def timing_enable(self, mask, every=1):

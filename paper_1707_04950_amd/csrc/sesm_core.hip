@@ -179,6 +179,9 @@ void sesm_release_surface(sesm_ctx* ctx) {
   ctx->V_cols = 0;
   ctx->hcol = ctx->hpart = ctx->ybuf = ctx->wtmp = ctx->gw = ctx->Hrow = ctx->htri = ctx->hp = ctx->gcoef = nullptr;
   ctx->gsc = nullptr;
+  ctx->ray_oc = nullptr;
+  ctx->ray_B = nullptr;
+  ctx->ray_cap = 0;
   ctx->Hrow_len = 0;
   ctx->Hrow_m = -1;
   ctx->ready = false;  // (the pinned column slots stay: they do not depend on the surface)
@@ -208,6 +211,19 @@ KParams sesm_ctx::kparams() const {
     K.Ubi[t] = P.Ubi[t];
   }
   return K;
+}
+
+// device room for the constants and results of n Rayleigh orders
+static int rayleigh_buffers(sesm_ctx* ctx, int n) {
+  int rc;
+  void* oc = nullptr;
+  cplx* B = nullptr;
+  if ((rc = sesm_alloc(ctx, &oc, sizeof(OrderCoef) * (size_t)n)) || (rc = sesm_alloc(ctx, (void**)&B, sizeof(cplx) * (size_t)n)))
+    return rc;
+  ctx->ray_oc = oc;  // (an earlier, smaller pair stays owned by the surface)
+  ctx->ray_B = B;
+  ctx->ray_cap = n;
+  return SESM_OK;
 }
 
 int sesm_apply(sesm_ctx* ctx, const cplx* mu, cplx* y) {
@@ -307,7 +323,11 @@ int sesm_set_surface(sesm_ctx* ctx, const sesm_profile* prof, double d, double k
   for (int m = 0; m <= SESM_MAX_J; ++m) P.wshift[m] = (m <= j) ? ((m & 1) ? -1.0 : 1.0) * binom(j, m) : 0.0;
   P.pmax = (int)std::ceil(A_periods) + 1;
   P.pmin = -P.pmax;
-  // U^eta = {n : |1 - e^{i beta_n h}|^j < eta}  (eq. M_eta, see oracle.rayleigh for the reading)
+  // U^eta = {n : |1 - e^{i beta_n h}|^j < eta} (eq. M_eta).  The printed set, with the
+  // factor 1/beta_n, is infinite (the quotient tends to zero for evanescent
+  // orders); on a flat surface 1/2 I + D~ has the eigenvalue (1/2)(1 - e^{i beta_n h})^j
+  // on e^{i alpha_n x}, so the orders where that factor is small are the ones
+  // the completion modes must restore.
   P.nU = 0;
   if (j > 0) {
     const double t = std::pow(prm.eta, 1.0 / j);
@@ -363,7 +383,12 @@ int sesm_set_surface(sesm_ctx* ctx, const sesm_profile* prof, double d, double k
   hipLaunchKernelGGL(k_surface, dim3((P.N + 255) / 256), dim3(256), 0, ctx->stream, P.N, d, nm, dab, dab + nm + 1,
                      ctx->x, ctx->f, ctx->fp, ctx->fpp, ctx->J);
   SESM_LAUNCH_CHECK();
-  // log-quadrature weights R_m, m = 0..n_a-1 (eq. local_mat; derivation in oracle.greens.log_weights)
+  // log-quadrature weights R_m, m = 0..n_a-1 (eq. local_mat):
+  //   R_m = -2 dx sum_{s=1}^{n_a/2} w_s cos(2 pi s m / n_a) / s,  w_s = 1/2 if 2 s = n_a, else 1,
+  // the trapezoidal weights that integrate ln(4 sin^2(pi t / a)) times a
+  // trigonometric polynomial of degree n_a on the window period a exactly,
+  // from int_{-a}^{a} ln(4 sin^2(pi t / a)) e^{i pi q t / a} dt = -4 a / |q| for
+  // even q != 0 and 0 for odd q.
   {
     std::vector<double> R(P.n_a);
     for (int m = 0; m < P.n_a; ++m) {
@@ -377,6 +402,7 @@ int sesm_set_surface(sesm_ctx* ctx, const sesm_profile* prof, double d, double k
     if ((rc = sesm_alloc(ctx, (void**)&ctx->logw, sizeof(double) * P.n_a))) return rc;
     SESM_HIP(hipMemcpyAsync(ctx->logw, R.data(), sizeof(double) * P.n_a, hipMemcpyHostToDevice, ctx->stream));
   }
+  if ((rc = rayleigh_buffers(ctx, std::max(64, P.n_count)))) return rc;
   if (P.mode == SESM_MODE_DENSE) {
     if ((rc = sesm_dense_setup(ctx))) return rc;
   } else {
@@ -490,22 +516,20 @@ int sesm_rayleigh(sesm_ctx* ctx, const sesm_c64* mu, const int32_t* orders, int3
     if (!std::isfinite(q.real()) || !std::isfinite(q.imag()))
       return ctx->fail(SESM_EINVAL, "Rayleigh coefficient undefined (Wood order with j = 0)");
   }
-  OrderCoef* doc = nullptr;
-  cplx* dB = nullptr;
-  SESM_HIP(hipStreamSynchronize(ctx->stream));
-  SESM_HIP(hipMalloc((void**)&doc, sizeof(OrderCoef) * n_orders));
-  if (hipMalloc((void**)&dB, sizeof(cplx) * n_orders) != hipSuccess) {
-    (void)hipFree(doc);
-    return ctx->fail(SESM_ENOMEM, "hipMalloc failed");
-  }
+  // the surface's buffers hold the propagating orders; more orders than that
+  // grow them once (owned by the surface like every other table)
+  int rc = SESM_OK;
+  if (n_orders > ctx->ray_cap && (rc = rayleigh_buffers(ctx, n_orders))) return rc;
+  OrderCoef* doc = (OrderCoef*)ctx->ray_oc;
+  cplx* dB = ctx->ray_B;
+  // the previous call's host copy has completed (each call synchronises), so
+  // the constants can be overwritten in stream order
   SESM_HIP(hipMemcpyAsync(doc, oc.data(), sizeof(OrderCoef) * n_orders, hipMemcpyHostToDevice, ctx->stream));
   hipLaunchKernelGGL(k_rayleigh, dim3(n_orders), dim3(256), 0, ctx->stream, P.N, P.d, P.dx, doc, ctx->x, ctx->f,
                      ctx->fp, ctx->J, (const cplx*)mu, dB);
   SESM_LAUNCH_CHECK();
   hipError_t e1 = hipMemcpyAsync(B_host, dB, sizeof(cplx) * n_orders, hipMemcpyDeviceToHost, ctx->stream);
   hipError_t e2 = hipStreamSynchronize(ctx->stream);
-  (void)hipFree(doc);
-  (void)hipFree(dB);
   if (e1 != hipSuccess || e2 != hipSuccess)
     return ctx->fail(SESM_EHIP, std::string("rayleigh: ") + hipGetErrorString(e1 != hipSuccess ? e1 : e2));
   return SESM_OK;

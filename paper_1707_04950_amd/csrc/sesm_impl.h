@@ -85,6 +85,11 @@ struct sesm_ctx {
   // 0..j+1 at j (j + 3) / 2), kept across solves so that their pages stay mapped
   std::vector<std::complex<double>> gm_rot, gm_raw;
   std::vector<cplx> gm_tri;
+  // Rayleigh coefficients: per-order constants and results (device), room for
+  // ray_cap orders; allocated with the surface
+  void* ray_oc = nullptr;
+  cplx* ray_B = nullptr;
+  int ray_cap = 0;
   std::vector<std::pair<void*, size_t>> owned;  // every device allocation made for the surface
   // device blocks released by an earlier surface, by size, reused by the next
   // one (a surface of the same shape allocates the same sizes); bounded below

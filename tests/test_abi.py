@@ -37,7 +37,7 @@ def test_null_context_is_rejected_without_gpu_work():
     assert lib.sesm_set_surface(None, None, 1.0, 1.0, 0.0, 0, 1.0, None) == m.SESM_EINVAL
     assert lib.sesm_matvec(None, None, None) == m.SESM_EINVAL
     assert lib.sesm_matvec_batch(None, 1, None, 1, None, 1) == m.SESM_EINVAL
-    assert lib.sesm_solve(None, None, None, 1e-10, 10, 0, None) == m.SESM_EINVAL
+    assert lib.sesm_solve(None, None, None, 1e-10, 10, 0, 0, None) == m.SESM_EINVAL
     assert lib.sesm_timing_enable(None, 0, 1) == m.SESM_EINVAL
     assert lib.sesm_timing_read(None, None, 0) == m.SESM_EINVAL
     assert lib.sesm_last_error(None) == b"null context"

@@ -297,15 +297,15 @@ def test_solve_batch_arguments(torch, solver):
     b = _densities(torch, N, [1, 2])
     x = torch.zeros((2, N), dtype=torch.complex128, device="cuda")
     pb, px = ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr())
-    assert f(solver.h, 0, None, 0, None, 0, 1e-10, 10, None) == 0
-    assert f(solver.h, lib.SESM_MAX_BATCH + 1, pb, N, px, N, 1e-10, 10, None) == lib.SESM_EINVAL
-    assert f(solver.h, -1, pb, N, px, N, 1e-10, 10, None) == lib.SESM_EINVAL
-    assert f(solver.h, 2, pb, N, px, N, 1e-10, 0, None) == lib.SESM_EINVAL
-    assert f(solver.h, 2, pb, N, px, N, 1e-10, 4001, None) == lib.SESM_EINVAL
-    assert f(solver.h, 2, pb, N, px, N, 0.0, 10, None) == lib.SESM_EINVAL
-    assert f(solver.h, 2, pb, N - 1, px, N, 1e-10, 10, None) == lib.SESM_EINVAL
-    assert f(solver.h, 2, None, N, px, N, 1e-10, 10, None) == lib.SESM_EINVAL
-    assert f(solver.h, 2, pb, N, pb, N, 1e-10, 10, None) == lib.SESM_EINVAL
+    assert f(solver.h, 0, None, 0, None, 0, 1e-10, 10, 0, None) == 0
+    assert f(solver.h, lib.SESM_MAX_BATCH + 1, pb, N, px, N, 1e-10, 10, 0, None) == lib.SESM_EINVAL
+    assert f(solver.h, -1, pb, N, px, N, 1e-10, 10, 0, None) == lib.SESM_EINVAL
+    assert f(solver.h, 2, pb, N, px, N, 1e-10, 0, 0, None) == lib.SESM_EINVAL
+    assert f(solver.h, 2, pb, N, px, N, 1e-10, 4001, 0, None) == lib.SESM_EINVAL
+    assert f(solver.h, 2, pb, N, px, N, 0.0, 10, 0, None) == lib.SESM_EINVAL
+    assert f(solver.h, 2, pb, N - 1, px, N, 1e-10, 10, 0, None) == lib.SESM_EINVAL
+    assert f(solver.h, 2, None, N, px, N, 1e-10, 10, 0, None) == lib.SESM_EINVAL
+    assert f(solver.h, 2, pb, N, pb, N, 1e-10, 10, 0, None) == lib.SESM_EINVAL
     torch.cuda.synchronize()
     assert bool((x == 0).all())
     # a cap too small to converge: soft failure, outputs and records written
@@ -315,7 +315,7 @@ def test_solve_batch_arguments(torch, solver):
         solver.rhs_bloch(2)  # alpha + 4 pi / d > k at 37 degrees and d = 5
     fresh = lib.Solver(0)
     try:
-        assert fresh.lib.sesm_solve_batch(fresh.h, 1, pb, N, px, N, 1e-10, 10, None) == lib.SESM_ENOSURF
+        assert fresh.lib.sesm_solve_batch(fresh.h, 1, pb, N, px, N, 1e-10, 10, 0, None) == lib.SESM_ENOSURF
         assert fresh.lib.sesm_rhs_bloch(fresh.h, 0, px) == lib.SESM_ENOSURF
     finally:
         fresh.close()
