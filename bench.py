@@ -34,7 +34,13 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", choices=["accel", "dense"], default=os.environ.get("SESM_BENCH_MODE", "accel"))
     ap.add_argument("--N", type=int, default=32768)
-    ap.add_argument("--tol", type=float, default=1e-10)
+    # relative residual; the accelerated map is linear only up to its rounding
+    # (~1e-12 relative), which puts the attainable true residual of this
+    # workload near 4e-9, so the tolerance sits above that
+    ap.add_argument("--tol", type=float, default=1e-8)
+    # the other members of the Bloch class have |mu| / |b| ~ 600 (against ~120
+    # for the benched incidence) and a true-residual floor near 2e-8
+    ap.add_argument("--batch-tol", type=float, default=5e-8)
     ap.add_argument("--max-iter", type=int, default=3000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched-solve", action="store_true")  # e.g. under counter collection (many dispatches)
@@ -115,6 +121,28 @@ def cpu_baseline(wl, N, target_s=15.0):
     }
 
 
+GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
+
+
+def efficiency_vs_oracle(n, e):
+    """max |e_n - e_n^oracle| against the finest stored oracle solution of the
+    benched workload (dense operator, LU), with the oracle's own energy error
+    and its distance to the next coarser N; None if no such file exists."""
+    import numpy as np
+    for name in ("grazing16384", "grazing8192"):
+        path = os.path.join(GOLDEN_DIR, name + ".json")
+        if not os.path.exists(path):
+            continue
+        with open(path) as fh:
+            G = json.load(fh)
+        if list(map(int, n)) != G["orders"]:
+            return {"oracle": name, "error": "order sets differ"}
+        return {"value": float(np.max(np.abs(np.asarray(e) - np.asarray(G["efficiencies"])))), "oracle": name,
+                "oracle_N": G["N"], "oracle_energy_error": G["energy_error"],
+                "oracle_self_convergence": (G.get("self_convergence") or {}).get("max_abs_efficiency_diff")}
+    return None
+
+
 def main():
     args = parse()
     if args.copy_probe:
@@ -150,7 +178,8 @@ def main():
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         return dict(setup=t1 - t0, solve=t2 - t1, eff=t3 - t2, iters=info["iters"], res=info["rel_residual"],
-                    eps=eps, n_orders=len(n), e=e, mism=info["column_mismatches"])
+                    est=info["est_residual"], conv=info["converged"], eps=eps, n_orders=len(n), n=n, e=e,
+                    mism=info["column_mismatches"])
 
     # Warmup.  The last warmup step times every kernel class (HIP events on each
     # kernel's own stream) to find the class with the largest total time.
@@ -223,21 +252,35 @@ def main():
     bsolve = None
     if args.mode == "accel" and not args.no_batched_solve:
         B = torch.stack([s.rhs_bloch(-p) for p in range(BATCH)])
-        s.solve_batch(B, tol=args.tol, max_iter=args.max_iter, allow_noconv=True)  # warm-up (work space pooled)
+        s.solve_batch(B, tol=args.batch_tol, max_iter=args.max_iter, allow_noconv=True)  # warm-up (work space pooled)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        xb, infos = s.solve_batch(B, tol=args.tol, max_iter=args.max_iter, allow_noconv=True)
+        xb, infos = s.solve_batch(B, tol=args.batch_tol, max_iter=args.max_iter, allow_noconv=True)
         torch.cuda.synchronize()
         bs_s = time.perf_counter() - t0
-        x1, _ = s.solve(tol=args.tol, max_iter=args.max_iter, allow_noconv=True)
-        torch.cuda.synchronize()
-        single_s = float(np.mean([r["solve"] for r in recs]))
-        bsolve = {"nrhs": BATCH, "incidences": "alpha + 2 pi p / d, p = 0..-%d" % (BATCH - 1),
+        # the single solves of the same eight systems at the same tolerance
+        single_s = 0.0
+        for p in range(BATCH):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            xp, _ = s.solve(B[p].contiguous(), tol=args.batch_tol, max_iter=args.max_iter, allow_noconv=True)
+            torch.cuda.synchronize()
+            single_s += time.perf_counter() - t0
+            if p == 0:
+                x1 = xp
+        single_s /= BATCH
+        bsolve = {"nrhs": BATCH, "incidences": "alpha + 2 pi p / d, p = 0..-%d" % (BATCH - 1), "tol": args.batch_tol,
+                  "single_solve_ms_mean": single_s * 1e3,
                   "ms_per_batch": bs_s * 1e3, "solves_per_s": BATCH / bs_s,
                   "speedup_vs_single_solve": single_s * BATCH / bs_s,
                   "iters": [i["iters"] for i in infos], "all_converged": all(i["converged"] for i in infos),
                   "column_mismatches": int(sum(i["column_mismatches"] for i in infos)),
                   "member0_equals_single": bool(torch.equal(xb[0], x1))}
+
+    # efficiencies against the oracle's (dense LU of the same workload at the
+    # largest N it was run at; stored by tests/golden/gen_golden.py), outside
+    # the timed region
+    oracle_cmp = efficiency_vs_oracle(recs[-1]["n"], recs[-1]["e"])
 
     n_launch = max(kst["launches"], 1)
     avg_s = kst["total_ms"] / 1e3 / n_launch
@@ -275,6 +318,9 @@ def main():
         "batched_solve": bsolve,
         "gmres_iters": recs[-1]["iters"],
         "gmres_rel_residual": recs[-1]["res"],
+        "gmres_rel_residual_estimate": recs[-1]["est"],
+        "all_steps_converged": all(r["conv"] for r in recs),
+        "efficiency_err_vs_oracle": oracle_cmp,
         "energy_balance_error": max((r["eps"] for r in recs), key=abs),
         # every step solves the same problem: its efficiencies must agree bit for bit
         "steps_identical": all(np.array_equal(r["e"], recs[0]["e"]) for r in recs),
@@ -287,6 +333,10 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.N)
     print(json.dumps(out))
+    if not out["all_steps_converged"]:
+        print("bench.py: a timed solve missed the tolerance (true residual %.3e > %.1e)" % (recs[-1]["res"], args.tol),
+              file=sys.stderr)
+        sys.exit(3)
 
 
 if __name__ == "__main__":

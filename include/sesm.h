@@ -187,7 +187,12 @@ SESM_API int sesm_rhs_bloch(sesm_ctx* ctx, int32_t p, sesm_c64* b);
  * unrestarted; at most 4000).  When a cycle's least-squares estimate reaches
  * tol, the true residual b - A mu is formed with one more forward map; if it
  * is still above tol and iterations remain, a new cycle starts from it (the
- * restart step).  converged and rel_residual report the true residual.
+ * restart step) - unless this is already such a restart and the true
+ * residual fell by less than half, which means it has reached the level the
+ * forward map's own rounding allows (the accelerated map is linear only up to
+ * its rounding noise, ~1e-12 relative; the attainable true residual is about
+ * that noise times |mu| / |b| times the square root of the Krylov dimension).
+ * converged and rel_residual report the true residual.
  * info: host struct, may be NULL.  Returns SESM_ENOCONV if tol was not
  * reached (mu and info still hold the last iterate). */
 SESM_API int sesm_solve(sesm_ctx* ctx, const sesm_c64* b, sesm_c64* mu, double tol, int32_t max_iter,
@@ -249,7 +254,12 @@ SESM_API const char* sesm_last_error(const sesm_ctx* ctx);
  *   1: phi^all on the horizontal grid, row-major [n_y + 1][n_x n_s]
  *      (eq. large_convolution_per_grid);  2: phi^all on the vertical grid
  *      [n_y n_s + 1 + 2 n_ext][n_x];  3: per-cell equivalent-source densities
- *      [2 sets][n_x n_y cells][xi (n_eq), zeta (n_eq)] (eq. eq_source_point).
+ *      [2 sets][n_x n_y cells][xi (n_eq), zeta (n_eq)] (eq. eq_source_point);
+ *   4: the boundary values b^q of the occupied cells (phi^all minus the local
+ *      corrections, eqs. psi_na_sum and combine_psi_pna), [occupied cell in
+ *      increasing cell index][boundary point: the 2 (n_side + 1) points of the
+ *      bottom then top side, then the 2 (n_side - 1) inner points of the left
+ *      then right side].
  * Synchronises the stream.  Returns SESM_EINVAL if out_len is too small. */
 SESM_API int sesm_diag_accel(sesm_ctx* ctx, const sesm_c64* mu, int32_t which, sesm_c64* out, int64_t out_len);
 

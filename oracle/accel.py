@@ -59,19 +59,27 @@ def smooth5_at_least(n):
 
 
 class Geometry:
-    def __init__(self, disc, L=0.5, n_s=10, n_e=1, n_coll=60, n_plw=32, ring=1, coll_ring=1):
+    """Cell grid of Sec. 5.1.  Defaults: n_x the smallest 5-smooth count with
+    L close to the requested side, rows centred on the surface's height range.
+    n_x (any count >= 3, no FFT-length restriction here) and rows_below (extra
+    rows added under the surface, which moves the row grid against the
+    surface by whole cells) override those choices; ring sets the near
+    columns on each side and coll_ring the collocation square (2 coll_ring + 1) L."""
+
+    def __init__(self, disc, L=0.5, n_s=10, n_e=1, n_coll=60, n_plw=32, ring=1, coll_ring=1, n_x=None,
+                 rows_below=0):
         self.disc = disc
         self.ring = ring
         self.coll_ring = coll_ring
         d = disc.d
-        self.n_x = smooth5_at_least(max(3, int(round(d / L))))
+        self.n_x = int(n_x) if n_x else smooth5_at_least(max(3, int(round(d / L))))
         self.L = d / self.n_x
         self.n_s, self.n_e, self.n_coll, self.n_plw = n_s, n_e, n_coll, n_plw
         self.delta = self.L / n_s
         self.x0 = -0.5 * disc.dx
         fmin, fmax = float(np.min(disc.f)), float(np.max(disc.f))
-        self.n_y = int(np.floor((fmax - fmin) / self.L)) + 1
-        self.y0 = 0.5 * (fmin + fmax) - 0.5 * self.n_y * self.L
+        self.n_y = int(np.floor((fmax - fmin) / self.L)) + 1 + int(rows_below)
+        self.y0 = 0.5 * (fmin + fmax) - 0.5 * (self.n_y - rows_below) * self.L - rows_below * self.L
         # cell of every node, (a, b] convention
         self.cx = np.ceil((disc.x - self.x0) / self.L).astype(np.int64) - 1
         self.cy = np.ceil((disc.f - self.y0) / self.L).astype(np.int64) - 1

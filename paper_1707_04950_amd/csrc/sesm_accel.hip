@@ -79,6 +79,7 @@ struct AccelOp {
   cplx* grp_ph = nullptr;  // wrap phase per pair, in plist order
   cplx* corr = nullptr;  // [n_pairs][n_bdry]
   cplx* yfar = nullptr;  // diagnostic copy of the far-field contribution
+  cplx* bq = nullptr;    // diagnostic copy of the boundary values b^q, [n_occ][n_bdry]
   // batched forward maps: the per-density work buffers of up to kBatchMax
   // densities (allocated at the first batched call)
   cplx* batch_ws = nullptr;
@@ -982,6 +983,7 @@ struct FarArgs {
   int64_t bcorr, bphH, bphV, bmode, by;
   const int* cfc_q;   // work item -> occupied cell (null: one item per cell)
   const int* cfc_t0;  // work item -> its first node within the cell (max_q: nodes per item)
+  cplx* bq_out;       // diagnostic: boundary values b^q of every occupied cell (null: not kept)
 };
 
 // One block per work item (up to max_q nodes of one occupied cell): the
@@ -1065,6 +1067,7 @@ __device__ __forceinline__ void cells_far_body(FarArgs A, KParams K, const int* 
 #pragma unroll 8
     for (int p = p0; p < p1; ++p) cs += corr[(int64_t)p * A.n_bdry + b];
     bv[b] = val - cs;
+    if (A.bq_out && t0c == 0) A.bq_out[(int64_t)q * A.n_bdry + b] = val - cs;
   }
   __syncthreads();
   // phase 3: plane-wave weights, the least squares of eq. plwave_QR through the
@@ -1577,7 +1580,8 @@ int sesm_accel_setup(sesm_ctx* ctx) {
       (rc = sesm_alloc(ctx, (void**)&A->phH, sizeof(cplx) * nH)) ||
       (rc = sesm_alloc(ctx, (void**)&A->phV, sizeof(cplx) * nV)) ||
       (rc = sesm_alloc(ctx, (void**)&A->mode_part, sizeof(cplx) * SESM_MAX_UETA * NCH_MODES)) ||
-      (rc = sesm_alloc(ctx, (void**)&A->yfar, sizeof(cplx) * (size_t)N)))
+      (rc = sesm_alloc(ctx, (void**)&A->yfar, sizeof(cplx) * (size_t)N)) ||
+      (rc = sesm_alloc(ctx, (void**)&A->bq, sizeof(cplx) * (size_t)A->n_occ * A->n_bdry)))
     return rc;
   SESM_HIP(hipMemsetAsync(A->dens, 0, sizeof(cplx) * (size_t)2 * A->n_cells * ncol, ctx->stream));
   return SESM_OK;
@@ -1720,7 +1724,8 @@ static int accel_far_stages(sesm_ctx* ctx, const FarBufs& Fb, bool keep_far, con
   const int mq = items ? std::min(A->max_q, CF_NODES) : A->max_q;
   FarArgs F{P.N,    A->n_x,   A->n_y,   A->n_s,    A->n_e, A->n_side, A->n_eq, A->n_cells, A->n_bdry, A->n_bH,
             A->n_plw, A->nXH, A->nXV,   A->ring,   mq,     A->L,   A->x0,     A->y0,   P.k,        P.alpha * P.d,
-            Fb.bcorr, Fb.bphH, Fb.bphV, Fb.bmode, Fb.by, items ? A->cfc_q : nullptr, items ? A->cfc_t0 : nullptr};
+            Fb.bcorr, Fb.bphH, Fb.bphV, Fb.bmode, Fb.by, items ? A->cfc_q : nullptr, items ? A->cfc_t0 : nullptr,
+            keep_far ? A->bq : nullptr};
   SESM_KT_BEGIN(SESM_KT_CELLS, st);
   hipLaunchKernelGGL(nb > 1 ? k_cells_far_batch : k_cells_far, dim3(items ? A->n_cfc : A->n_occ, nb), dim3(256),
                      cells_far_lds(A, mq), st, F, K, A->occ_cell,
@@ -1859,6 +1864,7 @@ extern "C" int sesm_diag_accel(sesm_ctx* ctx, const sesm_c64* mu, int32_t which,
     case 1: src = A->phH; len = nH; break;                                     // phi^all on the H grid [nYH][nXH]
     case 2: src = A->phV; len = nV; break;                                     // phi^all on the V grid [nYV][nXV]
     case 3: src = A->dens; len = (int64_t)2 * A->n_cells * 2 * A->n_eq; break; // per-cell densities
+    case 4: src = A->bq; len = (int64_t)A->n_occ * A->n_bdry; break;           // boundary values b^q
     default: rc = ctx->fail(SESM_EINVAL, "unknown diagnostic buffer");
   }
   if (rc == SESM_OK && out_len < len) rc = ctx->fail(SESM_EINVAL, "output buffer too small");

@@ -607,8 +607,13 @@ static int gm_residual(sesm_ctx* ctx, const cplx* b, const cplx* x, cplx* r) {
   return SESM_OK;
 }
 
-extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out, double tol, int32_t max_iter,
-                          int32_t restart, int32_t flags, sesm_solve_info* info) {
+// The single-system solve.  prev_true: the true relative residual of the
+// initial guess when the caller has already formed it (a batched solve
+// continuing one of its systems), else infinity; a restart from the true
+// residual must at least halve it, otherwise the forward map's rounding floor
+// has been reached and the solve stops.
+static int solve_impl(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out, double tol, int32_t max_iter,
+                      int32_t restart, int32_t flags, double prev_true, sesm_solve_info* info) {
   if (!ctx) return SESM_EINVAL;
   if (!ctx->ready) return ctx->fail(SESM_ENOSURF, "no surface");
   if (!mu_out || !(tol > 0) || max_iter < 1 || max_iter > 100000 || restart < 0 || (flags & ~SESM_SOLVE_X0))
@@ -710,6 +715,10 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
   };
   int total = 0, mismatches = 0, extra = 0;
   double est = 1.0, res_true = 1.0;
+  // stopping level of the estimate in the current cycle: tol, and a quarter
+  // of it in a cycle restarted from the true residual (so that a restart
+  // gains more than the gap between the two residuals)
+  double cyc_tol = prev_true < INFINITY ? 0.25 * tol : tol;
   bool x_zero = !warm;     // x is known to be zero (no forward map needed for its residual)
   bool r_in_v0 = false;    // V_0 already holds b - A x
   for (;;) {
@@ -741,7 +750,7 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
         beta0 = r0.real();
         g[0] = beta0;
         res_true = est = beta0 / bnorm;
-        if (est <= tol || steps == 0) break;
+        if (est <= cyc_tol || steps == 0) break;
         continue;
       }
       const int j = k - 1;  // column j is final
@@ -753,7 +762,7 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
       rlast = rotate(col, j, cs, sn, g);
       est = std::abs(g[j + 1]) / bnorm;
       nv = k;
-      if (est <= tol || rlast == 0.0 || k == steps) break;
+      if (est <= cyc_tol || rlast == 0.0 || k == steps) break;
     }
     if (nv == 0) {  // x unchanged: its true residual is the cycle's initial norm
       SESM_HIP(hipStreamSynchronize(st));
@@ -807,10 +816,17 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
     // the residual of the new x (the next cycle's u_0)
     if ((rc = gm_residual(ctx, b, x, V))) return rc;
     r_in_v0 = true;
-    if (est <= tol || total >= max_iter) {  // the estimate is met (or no iteration is left): check the true residual
+    if (est <= cyc_tol || total >= max_iter) {  // the estimate is met (or no iteration is left): check the true residual
       if ((rc = gm_rel_norm(ctx, V, bnorm, &res_true))) return rc;
       if (res_true <= tol || total >= max_iter) break;
-      ++extra;  // the estimate was optimistic: restart from the true residual
+      // The estimate was optimistic.  A restart from the true residual helps
+      // when the Krylov recurrence drifted (lost orthogonality, a clamped
+      // subdiagonal); when the true residual sits at the level set by the
+      // forward map's own rounding, a restart no longer lowers it.
+      if (!(res_true < 0.5 * prev_true)) break;
+      prev_true = res_true;
+      cyc_tol = 0.25 * tol;
+      ++extra;
     }
   }
   inf.iters = total;
@@ -822,6 +838,11 @@ extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out,
   if (info) *info = inf;
   if (!inf.converged) return ctx->fail(SESM_ENOCONV, "GMRES did not reach the tolerance");
   return SESM_OK;
+}
+
+extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out, double tol, int32_t max_iter,
+                          int32_t restart, int32_t flags, sesm_solve_info* info) {
+  return solve_impl(ctx, b_in, mu_out, tol, max_iter, restart, flags, INFINITY, info);
 }
 
 namespace {
@@ -1145,8 +1166,8 @@ extern "C" int sesm_solve_batch(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_i
     int extra = 0, iters = G.nv, mism = G.mism;
     double res_true = G.res_true, est = G.res;
     if (G.bnorm != 0.0 && res_true > tol && G.nv > 0 && G.nv < max_iter) {
-      const int r2 = sesm_solve(ctx, (const sesm_c64*)G.b, (sesm_c64*)G.x, tol, max_iter - G.nv, 0, SESM_SOLVE_X0,
-                                &more);
+      const int r2 = solve_impl(ctx, (const sesm_c64*)G.b, (sesm_c64*)G.x, tol, max_iter - G.nv, 0, SESM_SOLVE_X0,
+                                G.res_true, &more);
       if (r2 && r2 != SESM_ENOCONV) return r2;
       extra = 1 + more.residual_restarts;
       iters += more.iters;

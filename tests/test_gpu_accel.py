@@ -70,8 +70,19 @@ def test_geometry_matches_oracle(solver, case):
 
 
 def test_accel_stages_match_oracle(torch, solver, case):
-    """phi^all on both grids and the far-field contribution at the nodes
-    agree with the oracle's accelerated map (same algorithm)."""
+    """Stage parity of Algorithm 3 with the oracle's accelerated map (same
+    parameters): the boundary values b^q of every occupied cell (phi^all
+    minus the local corrections, eqs. psi_na_sum, combine_psi_pna) and the
+    far-field contribution at the nodes.
+
+    phi^all itself is printed, not asserted: it carries the equivalent-source
+    densities, solutions of least-squares problems of condition ~1e13-1e15,
+    and two QR implementations (host Householder here, LAPACK in the oracle)
+    put different amounts of the near-null directions into them (differences
+    ~ cond * eps relative to the densities).  Those directions radiate almost
+    nothing outside the 3L square they were fitted on, so they cancel in
+    phi^all - (local corrections) = b^q: b^q and everything after it is tight,
+    while phi^all at points next to the sources is not unique."""
     from gpu_util import to_dev, to_host
     wl, disc, M, op = case
     _gpu_accel(solver, wl, disc)
@@ -80,21 +91,58 @@ def test_accel_stages_match_oracle(torch, solver, case):
     g = op.g
     nH = (g.n_y + 1) * g.n_x * g.n_s
     nV = (g.n_y * g.n_s + 1 + 2 * g.n_e) * g.n_x
+    nb = len(op.btags)
     m = to_dev(torch, mu)
     phH = to_host(solver.diag_accel(m, 1, nH)).reshape(g.n_y + 1, g.n_x * g.n_s)
     phV = to_host(solver.diag_accel(m, 2, nV)).reshape(-1, g.n_x)
     far = to_host(solver.diag_accel(m, 0, disc.N))
-    errs = {name: float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
-            for name, got, ref in (("phiH", phH, parts["phi_all"]["H"]), ("phiV", phV, parts["phi_all"]["V"]),
-                                   ("far", far, parts["far"]))}
-    print("stage errors", errs)
-    # phi^all carries the equivalent-source densities, solutions of least-squares
-    # problems of condition up to ~1e15 (two QR implementations differ by
-    # ~cond * eps in near-null directions); those directions radiate nothing
-    # outside the 3L square and cancel in phi^all - (local correction), so the
-    # far field at the nodes is tight while phi^all is compared loosely.
-    assert errs["phiH"] <= 5e-2 and errs["phiV"] <= 5e-2
-    assert errs["far"] <= 1e-8
+    bq = to_host(solver.diag_accel(m, 4, len(g.cells) * nb)).reshape(len(g.cells), nb)
+    bq_ref = np.stack([op.boundary_values(c, parts["phi_all"], parts["dens"]) for c in g.cells])
+    rel = lambda got, ref: float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))  # noqa: E731
+    errs = {"phiH": rel(phH, parts["phi_all"]["H"]), "phiV": rel(phV, parts["phi_all"]["V"]),
+            "bq": rel(bq, bq_ref), "far": rel(far, parts["far"])}
+    print("stage errors (phi^all: diagnostic only)", errs)
+    assert errs["bq"] <= 1e-9
+    assert errs["far"] <= 1e-9
+
+
+def test_equivalent_sources_reproduce_true_field(torch, solver, case):
+    """EqSources (a2) pinned to the physics rather than to the oracle's
+    densities: for every occupied cell, the field the GPU's equivalent
+    sources radiate (free space, eq. eq_source_point) at points outside the
+    cell's 3L square equals the field of the cell's true surface sources
+    (eq. true_field, the density times dx times the double-layer kernel) to
+    1e-9 relative, for the horizontal and the vertical set.  The test points
+    lie on the square of side 5L around the cell."""
+    from gpu_util import to_dev, to_host
+    wl, disc, M, op = case
+    _gpu_accel(solver, wl, disc)
+    g = op.g
+    k = disc.k
+    mu = W.random_density(disc.N, 4)
+    ns2 = 2 * g.n_eq
+    dens = to_host(solver.diag_accel(to_dev(torch, mu), 3, 2 * g.n_x * g.n_y * ns2)).reshape(2, g.n_x * g.n_y, ns2)
+    t = (np.arange(24) + 0.5) / 24 * 5 * g.L - 2 * g.L
+    test = np.concatenate([np.stack([t, np.full(24, -2 * g.L)], 1), np.stack([t, np.full(24, 3 * g.L)], 1),
+                           np.stack([np.full(24, -2 * g.L), t], 1), np.stack([np.full(24, 3 * g.L), t], 1)])
+    worst = 0.0
+    for c in g.cells:
+        ox, oy = g.cell_origin(c)
+        idx = g.members[c]
+        pts = test + np.array([ox, oy])
+        X = pts[:, None, 0] - disc.x[None, idx]
+        Y = pts[:, None, 1] - disc.f[None, idx]
+        true = (disc.dx * accel._dl0(k, X, Y, disc.fp[None, idx])) @ mu[idx]
+        for li, lam in enumerate(("H", "V")):
+            _, _, ys = g.eq_points(lam)
+            Xe = pts[:, None, 0] - (ox + ys[None, :, 0])
+            Ye = pts[:, None, 1] - (oy + ys[None, :, 1])
+            v = dens[li, c]
+            eq = (accel._green_terms(k, 0, 0.0, Xe, Ye, "mono") @ v[: g.n_eq]
+                  + accel._green_terms(k, 0, 0.0, Xe, Ye, "dip" + lam) @ v[g.n_eq:])
+            worst = max(worst, float(np.max(np.abs(eq - true)) / np.max(np.abs(true))))
+    print("equivalent-source field vs true-source field outside the 3L squares: max rel err %.2e" % worst)
+    assert worst <= 1e-9
 
 
 def test_accel_matvec_vs_oracle_accel_and_dense(torch, solver, case):
@@ -151,7 +199,8 @@ def test_accel_solve_efficiencies_vs_dense_oracle(torch, solver, case):
     from gpu_util import to_host
     wl, disc, M, op = case
     _gpu_accel(solver, wl, disc)
-    mu, info = solver.solve(tol=1e-11, max_iter=600)
+    # tolerances above the accelerated map's rounding floor (true residual)
+    mu, info = solver.solve(tol=5e-8 if wl.name == "grazing_wood" else 1e-9, max_iter=600)
     assert info["converged"]
     n, e, eps = solver.efficiencies(mu)
     mu_ref = np.linalg.solve(M, dense.rhs(disc))
@@ -174,7 +223,7 @@ def test_flat_surface_accelerated_closed_form(torch, solver, offset, theta):
     set_surface(solver, wl, disc, mode=lib.MODE_ACCEL, n_side=ACC_KW["n_s"], n_ext=ACC_KW["n_e"],
                 n_coll=ACC_KW["n_coll"], n_plw=ACC_KW["n_plw"])
     assert solver.info()["n_y"] == 1
-    mu, info = solver.solve(tol=1e-12, max_iter=200)
+    mu, info = solver.solve(tol=1e-10, max_iter=200)
     assert info["converged"]
     B = solver.rayleigh(mu, [0])
     n, e, eps = solver.efficiencies(mu)
@@ -201,7 +250,7 @@ def test_translation_covariance_accelerated(torch, solver):
     for w in (wl, moved):
         disc = dense.Discretization(w)
         _gpu_accel(solver, w, disc)
-        mu, info = solver.solve(tol=1e-12, max_iter=600)
+        mu, info = solver.solve(tol=1e-9, max_iter=600)
         assert info["converged"]
         n, e, eps = solver.efficiencies(mu)
         res.append((disc, n, e, solver.rayleigh(mu, list(n))))
@@ -255,7 +304,11 @@ def test_golden_efficiencies_reduced_N(torch, solver, name, factory):
                            h=G["h"], c=G["c"], n_a=G["n_a"], gamma_frac=G["gamma_frac"], eta=G["eta"], mode=mode,
                            L=0.5)
         assert sorted(solver.info()["U_eta"]) == sorted(G["U_eta"])
-        mu, info = solver.solve(tol=1e-12, max_iter=3000)
+        # dense: tight; accelerated: above its rounding floor (true residual)
+        grazing = name.startswith("grazing")  # |mu| / |b| ~ 120: a higher floor in both modes
+        stol = (1e-11 if grazing else 1e-12) if mode == lib.MODE_DENSE else (1e-8 if grazing else 1e-9)
+        mu, info = solver.solve(tol=stol, max_iter=3000)
+        assert info["converged"]
         n, e, eps = solver.efficiencies(mu)
         assert list(n) == G["orders"]
         err = float(np.max(np.abs(e - np.asarray(G["efficiencies"]))))
@@ -287,7 +340,8 @@ def test_full_size_grazing_wood(torch, solver):
         rel = np.max(np.abs(y[rows] - ref_rows)) / np.max(np.abs(ref_rows))
         print("mode", mode, "64 sampled rows: max rel err vs oracle %.2e" % rel)
         assert rel <= (1e-11 if mode == lib.MODE_DENSE else 1e-8)
-        m, info = solver.solve(tol=1e-11, max_iter=3000)
+        m, info = solver.solve(tol=1e-10 if mode == lib.MODE_DENSE else 1e-8, max_iter=3000)
+        assert info["converged"]
         out[mode] = solver.efficiencies(m)
     (n0, e0, eps0), (n1, e1, eps1) = out[lib.MODE_DENSE], out[lib.MODE_ACCEL]
     print("efficiency diff accel vs dense %.2e; eps dense %.2e accel %.2e" % (np.max(np.abs(e1 - e0)), eps0, eps1))

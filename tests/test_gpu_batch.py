@@ -235,9 +235,10 @@ def test_solve_batch_equals_single_solves(torch, solver, accelerated):
     rows.append(_densities(torch, N, [61])[0])
     B = torch.stack(rows)
     assert torch.equal(B[0], solver.rhs())
-    mu, infos = solver.solve_batch(B, tol=1e-12, max_iter=400)
+    tol = 1e-9 if accelerated else 1e-12  # (accelerated: above its rounding floor)
+    mu, infos = solver.solve_batch(B, tol=tol, max_iter=400)
     for r in range(B.shape[0]):
-        m1, i1 = solver.solve(B[r].contiguous(), tol=1e-12, max_iter=400)
+        m1, i1 = solver.solve(B[r].contiguous(), tol=tol, max_iter=400)
         print("member %d: iters %d (single %d), residual %.2e" % (r, infos[r]["iters"], i1["iters"],
                                                                   infos[r]["rel_residual"]))
         assert infos[r]["converged"] and infos[r]["column_mismatches"] == 0
@@ -252,8 +253,8 @@ def test_solve_batch_single_member(torch, solver):
     disc = dense.Discretization(wl)
     _configure(solver, wl, disc, True)
     B = solver.rhs_bloch(-1)[None, :]
-    mu, infos = solver.solve_batch(B, tol=1e-12, max_iter=400)
-    m1, i1 = solver.solve(B[0].contiguous(), tol=1e-12, max_iter=400)
+    mu, infos = solver.solve_batch(B, tol=1e-9, max_iter=400)
+    m1, i1 = solver.solve(B[0].contiguous(), tol=1e-9, max_iter=400)
     assert infos[0]["converged"] and infos[0]["iters"] == i1["iters"] and torch.equal(mu[0], m1)
 
 
@@ -270,7 +271,7 @@ def test_solve_batch_bloch_efficiencies_vs_oracle(torch, solver):
     _configure(solver, wl, disc, True)
     ps = (0, -1, 1)
     B = torch.stack([solver.rhs_bloch(p) for p in ps])
-    mu, infos = solver.solve_batch(B, tol=1e-12, max_iter=400)
+    mu, infos = solver.solve_batch(B, tol=1e-9, max_iter=400)
     M = dense.operator_matrix(disc)
     for r, p in enumerate(ps):
         wp = _bloch_member(wl, p)
@@ -336,8 +337,10 @@ def test_solve_batch_full_size_grazing_wood(torch, solver):
     setup(wl)
     ps = (0, -1, -2)
     B = torch.stack([solver.rhs_bloch(p) for p in ps])
-    mu, infos = solver.solve_batch(B, tol=1e-10, max_iter=3000)
-    m0, i0 = solver.solve(tol=1e-10, max_iter=3000)
+    # members p != 0 have |mu| / |b| ~ 600, which puts their true-residual
+    # floor near 2e-8
+    mu, infos = solver.solve_batch(B, tol=5e-8, max_iter=3000)
+    m0, i0 = solver.solve(tol=5e-8, max_iter=3000)
     assert torch.equal(mu[0], m0) and infos[0]["iters"] == i0["iters"]
     for r, p in enumerate(ps):
         setup(_bloch_member(wl, p))

@@ -86,7 +86,9 @@ def test_efficiencies_invariant_under_method_parameters(torch, solver, kw):
                        kw.get("A", wl.A), wl.N,
                        h=kw.get("h", wl.h), c=wl.c, n_a=n_a, gamma_frac=wl.gamma_frac, eta=wl.eta,
                        mode=lib.MODE_ACCEL, L=L, n_side=kw.get("n_side", 0))
-    mu, info = solver.solve(tol=1e-11, max_iter=2000)
+    # above the accelerated map's rounding floor, which rises with the number
+    # of equivalent sources per side (a worse-conditioned fit)
+    mu, info = solver.solve(tol=2e-7 if kw.get("n_side", 10) > 10 else 1e-8, max_iter=2000)
     n, e, eps = solver.efficiencies(mu)
     assert list(n) == G["orders"]
     err = float(np.max(np.abs(e - np.asarray(G["efficiencies"]))))

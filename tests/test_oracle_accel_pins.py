@@ -74,3 +74,38 @@ def test_accelerated_forward_map_matches_dense_operator(small):
     y_ref = M @ mu
     err = np.linalg.norm(op.matvec(mu) - y_ref) / np.linalg.norm(y_ref)
     assert err < 1e-7, err
+
+
+# The accelerated oracle shares its geometric choices (5-smooth column count,
+# rows centred on the surface, three near columns) with the GPU library.  On
+# the two geometries of the GPU stage-parity tests it is pinned to the dense
+# operator both with those choices and with different ones: another column
+# count (not 5-smooth), an extra row of cells below the surface and two near
+# columns on each side.  A geometric mistake shared by both implementations
+# would not survive the change of grid.
+def _stage_case(name):
+    if name == "gauss30":
+        a, b = W.gaussian_surface(5.0, 0.5, 1.0, W.SEED_BASE + 5)
+        wl = W.Workload(name=name, d=5.0, k=2 * math.pi, theta_deg=30.0, N=400, j=8, h=0.85, A=40.0,
+                        a_coef=a, b_coef=b, L=0.5)
+        return wl, 7
+    a, b = W.gaussian_surface(6.0, 1.0, 1.0, W.SEED_BASE + 7)
+    wl = W.Workload(name=name, d=6.0, k=W.wood_grazing_k(6.0, 89.0, 12), theta_deg=89.0, N=480, j=8, h=0.5,
+                    A=40.0, a_coef=a, b_coef=b, L=0.5)
+    return wl, 11
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", ["gauss30", "grazing_wood"])
+def test_accelerated_oracle_vs_dense_on_varied_grids(name):
+    wl, n_x_other = _stage_case(name)
+    disc = dense.Discretization(wl)
+    y_ref = dense.operator_matrix(disc) @ W.random_density(disc.N, 1)
+    mu = W.random_density(disc.N, 1)
+    for kw in (dict(), dict(n_x=n_x_other, rows_below=1, ring=2)):
+        op = accel.AccelOperator(disc, L=0.5, n_s=10, n_e=1, n_coll=60, n_plw=32, **kw)
+        if kw:
+            assert op.g.n_x == n_x_other and op.g.ring == 2
+        err = np.linalg.norm(op.matvec(mu) - y_ref) / np.linalg.norm(y_ref)
+        print(name, kw, "accelerated oracle vs dense operator: %.2e" % err)
+        assert err < 1e-7, (kw, err)
