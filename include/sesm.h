@@ -241,6 +241,22 @@ SESM_API int sesm_efficiencies(sesm_ctx* ctx, const sesm_c64* mu, int32_t* n_fir
 SESM_API int sesm_rayleigh(sesm_ctx* ctx, const sesm_c64* mu, const int32_t* orders_host, int32_t n_orders,
                   sesm_c64* B_host);
 
+/* sesm_rayleigh for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same Rayleigh coefficients (same kernel, same values bit for bit), with
+ * the per-order constants and the results kept in a fixed device array of the
+ * library instead of the context's buffers.  The call allocates and frees no
+ * device memory.  The array holds SESM_RAYLEIGH_NOALLOC_MAX orders (256 KB on
+ * every GPU the library runs on, held until the process ends); more orders
+ * give SESM_EINVAL.  All contexts on one GPU share that array and each call
+ * leaves its results there: calls that overlap in time on one GPU (other
+ * threads or streams) race and must be serialised by the caller.  mu: device
+ * array of N; orders_host, B_host: host arrays of n_orders.  Synchronises the
+ * stream. */
+#define SESM_RAYLEIGH_NOALLOC_MAX 4096
+SESM_API int sesm_rayleigh_noalloc(sesm_ctx* ctx, const sesm_c64* mu, const int32_t* orders_host, int32_t n_orders,
+                                   sesm_c64* B_host);
+
 /* Describe the current discretisation (host struct).  Returns SESM_ENOSURF
  * before a successful sesm_set_surface. */
 SESM_API int sesm_get_info(const sesm_ctx* ctx, sesm_surface_info* info);

@@ -5,6 +5,7 @@
 #include <complex>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 
 #include "sesm_impl.h"
 
@@ -213,6 +214,58 @@ KParams sesm_ctx::kparams() const {
   return K;
 }
 
+// Per-order constants of k_rayleigh: alpha_n, beta_n, (1 - e^{i beta_n h})^j / beta_n
+// and membership in U^eta.
+static int order_constants(sesm_ctx* ctx, const int32_t* orders, int n_orders, OrderCoef* oc) {
+  const Problem& P = ctx->P;
+  for (int t = 0; t < n_orders; ++t) {
+    const int n = orders[t];
+    const double an = P.alpha + 2.0 * PI * n / P.d;
+    const std::complex<double> b = beta_of(P.k, an);
+    const std::complex<double> q = shift_quotient(b, P.h, P.j);
+    oc[t].an = an;
+    oc[t].br = b.real();
+    oc[t].bi = b.imag();
+    oc[t].qr = q.real();
+    oc[t].qi = q.imag();
+    oc[t].inU = 0;
+    oc[t].pad = 0;
+    for (int u = 0; u < P.nU; ++u)
+      if (P.U[u] == n) oc[t].inU = 1;
+    if (!std::isfinite(q.real()) || !std::isfinite(q.imag()))
+      return ctx->fail(SESM_EINVAL, "Rayleigh coefficient undefined (Wood order with j = 0)");
+  }
+  return SESM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Fixed device array for sesm_rayleigh_noalloc: the constants of up to
+// SESM_RAYLEIGH_NOALLOC_MAX orders, then their results.  Host code never uses
+// the array's name as an address: each device's copy is looked up once
+// (hipGetSymbolAddress, at the first sesm_create on that device) and only
+// that pointer is handed to kernels and copies.
+#define SESM_NOALLOC_DEVICES 64
+static __device__ __align__(256) unsigned char scratch[(size_t)SESM_RAYLEIGH_NOALLOC_MAX * (sizeof(OrderCoef) + sizeof(cplx))];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[SESM_NOALLOC_DEVICES] = {};
+
+// the device address of `scratch` on the current device `device`
+static hipError_t scratch_lookup(int device, void** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device < 0 || device >= SESM_NOALLOC_DEVICES) {
+    *out = nullptr;
+    return hipSuccess;  // (the entry point then reports that it is unavailable)
+  }
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
+
 // device room for the constants and results of n Rayleigh orders
 static int rayleigh_buffers(sesm_ctx* ctx, int n) {
   int rc;
@@ -246,6 +299,11 @@ int sesm_create(sesm_ctx** out, int device, void* hip_stream) {
   if (!ctx) return SESM_ENOMEM;
   ctx->device = device;
   ctx->stream = (hipStream_t)hip_stream;
+  if (scratch_lookup(device, &ctx->noalloc_scratch) != hipSuccess) {
+    (void)hipGetLastError();
+    delete ctx;
+    return SESM_EHIP;
+  }
   const char* pv = std::getenv("SESM_POISON_ALLOC");
   ctx->poison = pv && pv[0] && pv[0] != '0';
   *out = ctx;
@@ -500,25 +558,10 @@ int sesm_rayleigh(sesm_ctx* ctx, const sesm_c64* mu, const int32_t* orders, int3
   SESM_HIP(hipSetDevice(ctx->device));
   const Problem& P = ctx->P;
   std::vector<OrderCoef> oc(n_orders);
-  for (int t = 0; t < n_orders; ++t) {
-    const int n = orders[t];
-    const double an = P.alpha + 2.0 * PI * n / P.d;
-    const std::complex<double> b = beta_of(P.k, an);
-    const std::complex<double> q = shift_quotient(b, P.h, P.j);
-    oc[t].an = an;
-    oc[t].br = b.real();
-    oc[t].bi = b.imag();
-    oc[t].qr = q.real();
-    oc[t].qi = q.imag();
-    oc[t].inU = 0;
-    for (int u = 0; u < P.nU; ++u)
-      if (P.U[u] == n) oc[t].inU = 1;
-    if (!std::isfinite(q.real()) || !std::isfinite(q.imag()))
-      return ctx->fail(SESM_EINVAL, "Rayleigh coefficient undefined (Wood order with j = 0)");
-  }
+  int rc = order_constants(ctx, orders, n_orders, oc.data());
+  if (rc) return rc;
   // the surface's buffers hold the propagating orders; more orders than that
   // grow them once (owned by the surface like every other table)
-  int rc = SESM_OK;
   if (n_orders > ctx->ray_cap && (rc = rayleigh_buffers(ctx, n_orders))) return rc;
   OrderCoef* doc = (OrderCoef*)ctx->ray_oc;
   cplx* dB = ctx->ray_B;
@@ -532,6 +575,34 @@ int sesm_rayleigh(sesm_ctx* ctx, const sesm_c64* mu, const int32_t* orders, int3
   hipError_t e2 = hipStreamSynchronize(ctx->stream);
   if (e1 != hipSuccess || e2 != hipSuccess)
     return ctx->fail(SESM_EHIP, std::string("rayleigh: ") + hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+  return SESM_OK;
+}
+
+int sesm_rayleigh_noalloc(sesm_ctx* ctx, const sesm_c64* mu, const int32_t* orders, int32_t n_orders,
+                          sesm_c64* B_host) {
+  if (!ctx) return SESM_EINVAL;
+  if (!ctx->ready) return ctx->fail(SESM_ENOSURF, "no surface");
+  if (!mu || !orders || !B_host || n_orders < 0) return ctx->fail(SESM_EINVAL, "bad args");
+  if (n_orders > SESM_RAYLEIGH_NOALLOC_MAX)
+    return ctx->fail(SESM_EINVAL, "sesm_rayleigh_noalloc: at most SESM_RAYLEIGH_NOALLOC_MAX (" +
+                                      std::to_string(SESM_RAYLEIGH_NOALLOC_MAX) + ") orders per call");
+  if (!ctx->noalloc_scratch) return ctx->fail(SESM_EINVAL, "sesm_rayleigh_noalloc: device index out of range");
+  if (n_orders == 0) return SESM_OK;
+  SESM_HIP(hipSetDevice(ctx->device));
+  const Problem& P = ctx->P;
+  std::vector<OrderCoef> oc(n_orders);
+  int rc = order_constants(ctx, orders, n_orders, oc.data());
+  if (rc) return rc;
+  OrderCoef* doc = (OrderCoef*)ctx->noalloc_scratch;
+  cplx* dB = (cplx*)((unsigned char*)ctx->noalloc_scratch + (size_t)SESM_RAYLEIGH_NOALLOC_MAX * sizeof(OrderCoef));
+  SESM_HIP(hipMemcpyAsync(doc, oc.data(), sizeof(OrderCoef) * n_orders, hipMemcpyHostToDevice, ctx->stream));
+  hipLaunchKernelGGL(k_rayleigh, dim3(n_orders), dim3(256), 0, ctx->stream, P.N, P.d, P.dx, doc, ctx->x, ctx->f,
+                     ctx->fp, ctx->J, (const cplx*)mu, dB);
+  SESM_LAUNCH_CHECK();
+  hipError_t e1 = hipMemcpyAsync(B_host, dB, sizeof(cplx) * n_orders, hipMemcpyDeviceToHost, ctx->stream);
+  hipError_t e2 = hipStreamSynchronize(ctx->stream);
+  if (e1 != hipSuccess || e2 != hipSuccess)
+    return ctx->fail(SESM_EHIP, std::string("rayleigh_noalloc: ") + hipGetErrorString(e1 != hipSuccess ? e1 : e2));
   return SESM_OK;
 }
 

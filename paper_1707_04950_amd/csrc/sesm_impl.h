@@ -90,6 +90,7 @@ struct sesm_ctx {
   void* ray_oc = nullptr;
   cplx* ray_B = nullptr;
   int ray_cap = 0;
+  void* noalloc_scratch = nullptr;  // this device's copy of the library's fixed array (sesm_rayleigh_noalloc)
   std::vector<std::pair<void*, size_t>> owned;  // every device allocation made for the surface
   // device blocks released by an earlier surface, by size, reused by the next
   // one (a surface of the same shape allocates the same sizes); bounded below
