@@ -181,6 +181,7 @@ def main():
                     est=info["est_residual"], conv=info["converged"], eps=eps, n_orders=len(n), n=n, e=e,
                     mism=info["column_mismatches"])
 
+    split_info = {"near_items": None, "near_tuned_us": None}
     # Warmup.  The last warmup step times every kernel class (HIP events on each
     # kernel's own stream) to find the class with the largest total time.
     all_mask = (1 << lib.KT_COUNT) - 1
@@ -192,6 +193,9 @@ def main():
         if w == args.warmup - 1:
             ranking = s.timing_read()
             s.timing_enable(0)
+            if mode == lib.MODE_ACCEL:
+                inf = s.info()
+                split_info = {"near_items": inf["near_items"], "near_tuned_us": inf["near_tuned_us"]}
     if ranking:  # records come in class order
         dom = max(ranking, key=lambda n: ranking[n]["total_ms"])
         dom_id = list(ranking).index(dom)
@@ -282,6 +286,16 @@ def main():
     # the timed region
     oracle_cmp = efficiency_vs_oracle(recs[-1]["n"], recs[-1]["e"])
 
+    # the whole forward map against the HBM roof: algorithmic bytes of its five
+    # launches (per launch, from the fully timed warm-up step) over the
+    # steady-state forward-map time
+    fmap = None
+    if ranking and args.mode == "accel":
+        fb = sum(ranking[k]["bytes"] / ranking[k]["launches"] for k in
+                 ("k_local_apply", "k_merge_fft", "k_fft_rows", "k_yconv", "k_cells_far") if ranking[k]["launches"])
+        fmap = {"bytes": fb, "ms": mv_s * 1e3, "GBps": fb / mv_s / 1e9, "frac_of_hbm_peak": fb / mv_s / 1e9 / HBM_PEAK_GBS,
+                "near_items_per_launch": split_info["near_items"], "near_split_tuned_us": split_info["near_tuned_us"]}
+
     n_launch = max(kst["launches"], 1)
     avg_s = kst["total_ms"] / 1e3 / n_launch
     roof = {"kernel": dom, "bound": "hbm", "achieved": kst["bytes"] / n_launch / avg_s / 1e9, "peak": HBM_PEAK_GBS,
@@ -314,6 +328,7 @@ def main():
                    "gmres_tol": args.tol},
         "matvec_munknowns_per_s": args.N / mv_s / 1e6,
         "matvec_ms": mv_s * 1e3,
+        "forward_map": fmap,
         "batched_matvec": batch,
         "batched_solve": bsolve,
         "gmres_iters": recs[-1]["iters"],

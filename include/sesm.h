@@ -84,7 +84,15 @@ typedef struct {
   int32_t n_plw;      /* accelerator: plane waves per cell, eq. (planewave)               */
   int32_t near_ring;  /* accelerator: columns on each side of a cell treated directly
                          (near field); default 1, at most 3                              */
-  int32_t reserved[7];
+  int32_t near_split; /* accelerator: where the near-field work items of a single-density
+                         forward map run.  0 (default): a split chosen by timing candidate
+                         splits once per grid shape (cached in the context); 1: the split
+                         given by split_permille; -1: all of them in the first launch.
+                         Every split gives the same results bit for bit.              */
+  int32_t split_permille[3]; /* near_split = 1: thousandths of the items in the first
+                         launch, with merge + forward FFT, with the y convolution (the
+                         inverse FFT takes the rest); each in [0, 1000], sum <= 1000     */
+  int32_t reserved[3];
 } sesm_params;
 
 typedef struct {
@@ -120,6 +128,11 @@ typedef struct {
   int64_t near_entries;       /* stored near-field entries (accelerated mode) */
   int64_t device_bytes;       /* device memory held by the context (including blocks
                                  kept from an earlier surface for reuse)      */
+  int32_t near_items[4];      /* near-field work items per launch of a single-density
+                                 forward map: first launch, merge + FFT, y convolution,
+                                 inverse FFT                                   */
+  double near_tuned_us;       /* forward-map time of the chosen split when the tuner
+                                 measured it (0 otherwise)                     */
 } sesm_surface_info;
 
 /* Create a context on HIP device `device`; `hip_stream` is a hipStream_t (NULL

@@ -34,7 +34,8 @@ class Params(ctypes.Structure):
                 ("n_a", ctypes.c_int32), ("gamma_frac", ctypes.c_double), ("eta", ctypes.c_double),
                 ("mode", ctypes.c_int32), ("L_cell", ctypes.c_double), ("n_side", ctypes.c_int32),
                 ("n_ext", ctypes.c_int32), ("n_coll", ctypes.c_int32), ("n_plw", ctypes.c_int32),
-                ("near_ring", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("near_ring", ctypes.c_int32), ("near_split", ctypes.c_int32),
+                ("split_permille", ctypes.c_int32 * 3), ("reserved", ctypes.c_int32 * 3)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -70,7 +71,8 @@ class SurfaceInfo(ctypes.Structure):
                 ("U_eta", ctypes.c_int32 * 16), ("n_first", ctypes.c_int32), ("n_count", ctypes.c_int32),
                 ("n_x", ctypes.c_int32), ("n_y", ctypes.c_int32), ("n_cells_occupied", ctypes.c_int32),
                 ("stencil_rows", ctypes.c_int32), ("L", ctypes.c_double), ("y0", ctypes.c_double),
-                ("delta", ctypes.c_double), ("near_entries", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
+                ("delta", ctypes.c_double), ("near_entries", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("near_items", ctypes.c_int32 * 4), ("near_tuned_us", ctypes.c_double)]
 
 
 _lib = None
@@ -199,7 +201,8 @@ class Solver:
         return rc
 
     def set_surface(self, a_coef, b_coef, d, k, alpha, j, A, N, h=0.0, c=0.0, n_a=0, gamma_frac=0.0,
-                    eta=0.0, mode=MODE_DENSE, L=0.0, n_side=0, n_ext=0, n_coll=0, n_plw=0, near_ring=0):
+                    eta=0.0, mode=MODE_DENSE, L=0.0, n_side=0, n_ext=0, n_coll=0, n_plw=0, near_ring=0,
+                    near_split=0, split_permille=(0, 0, 0)):
         a = np.ascontiguousarray(a_coef, dtype=np.float64)
         b = np.zeros_like(a)
         bb = np.asarray(b_coef, dtype=np.float64)
@@ -208,7 +211,8 @@ class Solver:
         prof = Profile(len(a) - 1, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                        b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         prm = Params(N=N, h=h, c_window=c, n_a=n_a, gamma_frac=gamma_frac, eta=eta, mode=mode, L_cell=L,
-                     n_side=n_side, n_ext=n_ext, n_coll=n_coll, n_plw=n_plw, near_ring=near_ring)
+                     n_side=n_side, n_ext=n_ext, n_coll=n_coll, n_plw=n_plw, near_ring=near_ring,
+                     near_split=near_split, split_permille=(ctypes.c_int32 * 3)(*split_permille))
         self._check(self.lib.sesm_set_surface(self.h, ctypes.byref(prof), d, k, alpha, j, A, ctypes.byref(prm)))
         self.N = N
 
@@ -217,6 +221,7 @@ class Solver:
         self._check(self.lib.sesm_get_info(self.h, ctypes.byref(inf)))
         out = {f: getattr(inf, f) for f, _ in SurfaceInfo._fields_}
         out["U_eta"] = list(inf.U_eta)[: inf.n_eta]
+        out["near_items"] = list(inf.near_items)
         return out
 
     def empty(self):

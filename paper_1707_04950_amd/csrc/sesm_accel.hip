@@ -84,6 +84,13 @@ struct AccelOp {
   // densities (allocated at the first batched call)
   cplx* batch_ws = nullptr;
   FftPlan planH, planV;
+  // near-field items of a single-density forward map: [0, c1) in the first
+  // launch, [c1, c2) with merge + FFT, [c2, c3) with the y convolution,
+  // [c3, n_chunks) with the inverse FFT (chosen by the tuner or the caller)
+  int near_c1 = 0, near_c2 = 0, near_c3 = 0;
+  double tuned_us = 0.0;                  // forward-map time of the chosen split (0: not measured)
+  std::vector<int64_t> item_entries;      // prefix sums over the items: stored entries
+  std::vector<int64_t> item_rows;         //                              rows
 };
 
 namespace {
@@ -532,6 +539,135 @@ struct LocalArgs {
   int64_t dens_ld, mode_ld;  // batches: per-density strides of dens and mode_part
 };
 
+// The near-field work items: up to NEAR_ROWS consecutive rows of one
+// occupied cell against the cyclic band of its near columns,
+// y[perm[off + t]] = sum_u blk_q[t][u] mu[band_q(u)] (intersecting part
+// eq. final_correction_0, singular part eq. local_mat, 1/2 I).  The items
+// are independent HBM streams of stored blocks; besides the first launch of
+// the forward map they fill the workgroups left idle by the latency-bound
+// grid stages (merge + FFT, y convolution, inverse FFT), which carry ranges of
+// them as extra workgroups after their own.
+struct NearArgs {
+  int N, n_x;
+  const int* occ_cell;
+  const int* occ_off;
+  const int* perm;
+  const int* chunk_q;
+  const int* chunk_t0;
+  const int* col_lo;
+  const int* col_w;
+  const int64_t* near_off;
+  const cplx* nearblk;
+};
+
+// Item `it`, 256 threads (tid = 0..255 within their group): each thread runs
+// over band columns tid, tid + 256, ... with all NEAR_ROWS row loads of a
+// column in flight; per density s and row r the wavefront sums go to
+// rs[(s NEAR_ROWS + r) 4 + wave].  For several densities (NB >= 3) the rows are
+// taken in two passes of half as many accumulators; each row's sum is formed
+// in the same order either way, so every launch shape gives the same bits.
+template <int NB>
+__device__ __forceinline__ void near_accum(const NearArgs& A, int it, int tid, cplx* rs,
+                                           const cplx* __restrict__ mu, int64_t ldm) {
+  const int q = A.chunk_q[it], t0 = A.chunk_t0[it];
+  const int off = A.occ_off[q], nq = A.occ_off[q + 1] - off;
+  const int nr = min(NEAR_ROWS, nq - t0);
+  const int col = A.occ_cell[q] % A.n_x;
+  const int lo = A.col_lo[col], w = A.col_w[col];
+  const int N = A.N;
+  const cplx* blk = A.nearblk + A.near_off[q] + (int64_t)t0 * w;
+  const int lane = tid & 63, wv = tid >> 6;
+  constexpr int RP = NB >= 3 ? NEAR_ROWS / 2 : NEAR_ROWS;
+#pragma unroll
+  for (int r0 = 0; r0 < NEAR_ROWS; r0 += RP) {
+    if (r0 >= nr) break;  // uniform over the item's threads
+    cplx acc[NB][RP];
+#pragma unroll
+    for (int s = 0; s < NB; ++s)
+#pragma unroll
+      for (int r = 0; r < RP; ++r) acc[s][r] = cplx{0.0, 0.0};
+    for (int u = tid; u < w; u += 256) {
+      int l = lo + u;
+      l += (l < 0) ? N : ((l >= N) ? -N : 0);
+      cplx m[NB];
+#pragma unroll
+      for (int s = 0; s < NB; ++s) m[s] = mu[s * ldm + l];
+      cplx v[RP];
+#pragma unroll
+      for (int r = 0; r < RP; ++r) v[r] = blk[(int64_t)min(r0 + r, nr - 1) * w + u];
+#pragma unroll
+      for (int s = 0; s < NB; ++s)
+#pragma unroll
+        for (int r = 0; r < RP; ++r) acc[s][r] += v[r] * m[s];
+    }
+#pragma unroll
+    for (int s = 0; s < NB; ++s)
+#pragma unroll
+      for (int r = 0; r < RP; ++r) {
+        const cplx sm = wave_sum(acc[s][r]);
+        if (lane == 0) rs[(s * NEAR_ROWS + r0 + r) * 4 + wv] = sm;
+      }
+  }
+}
+
+// After a workgroup barrier: thread tid < rows of item `it` adds the four
+// wavefront sums of its row (fixed order) and stores it.
+template <int NB>
+__device__ __forceinline__ void near_store(const NearArgs& A, int it, int tid, const cplx* rs,
+                                           cplx* __restrict__ y, int64_t ldy) {
+  const int q = A.chunk_q[it], t0 = A.chunk_t0[it];
+  const int off = A.occ_off[q], nq = A.occ_off[q + 1] - off;
+  const int nr = min(NEAR_ROWS, nq - t0);
+  if (tid < nr) {
+    const int dst = A.perm[off + t0 + tid];
+#pragma unroll
+    for (int s = 0; s < NB; ++s) {
+      cplx sm = cplx{0.0, 0.0};
+      for (int k = 0; k < 4; ++k) sm += rs[(s * NEAR_ROWS + tid) * 4 + k];
+      y[s * ldy + dst] = sm;
+    }
+  }
+}
+
+// Near-field items [it0, it0 + GROUPS) (those below c1) for one density, by a
+// workgroup of GROUPS x 256 threads: group g takes item it0 + g.
+template <int GROUPS>
+__device__ __forceinline__ void near_fill(const NearArgs& A, int it0, int c1, const cplx* __restrict__ mu,
+                                          cplx* __restrict__ y) {
+  __shared__ cplx rs_fill[GROUPS * NEAR_ROWS * 4];
+  const int g = threadIdx.x >> 8, tid = threadIdx.x & 255;
+  const int it = it0 + g;
+  cplx* rs = rs_fill + g * NEAR_ROWS * 4;
+  if (it < c1) near_accum<1>(A, it, tid, rs, mu, 0);
+  __syncthreads();
+  if (it < c1) near_store<1>(A, it, tid, rs, y, 0);
+}
+
+// A range of near-field items carried by a launch: items [c0, c1) for the
+// density mu, results into y.
+struct NearFill {
+  int c0, c1;
+  const cplx* mu;
+  cplx* y;
+};
+
+
+__device__ __forceinline__ NearArgs near_args(const LocalArgs& L) {
+  NearArgs A;
+  A.N = L.N;
+  A.n_x = L.n_x;
+  A.occ_cell = L.occ_cell;
+  A.occ_off = L.occ_off;
+  A.perm = L.perm;
+  A.chunk_q = L.chunk_q;
+  A.chunk_t0 = L.chunk_t0;
+  A.col_lo = L.col_lo;
+  A.col_w = L.col_w;
+  A.near_off = L.near_off;
+  A.nearblk = L.nearblk;
+  return A;
+}
+
 // The work of k_local_apply for NB densities at once: density r is
 // mu + r ldm, its output y + r ldy, its cell densities dens + r dens_ld and its
 // mode partial sums mode_part + r mode_ld.  Each P and near-field entry, and
@@ -542,7 +678,6 @@ template <int NB>
 __device__ __forceinline__ void local_apply(const KParams& K, const LocalArgs& L, const cplx* __restrict__ mu,
                                             int64_t ldm, cplx* __restrict__ y, int64_t ldy) {
   __shared__ cplx red[LOC_NT];
-  __shared__ cplx rs[NB][NEAR_ROWS][LOC_NT / 64];  // near-field row sums per wavefront
   __shared__ cplx mus[NB][LOC_NT];                 // EqSources: staged mu of the cell
   __shared__ cplx gsum[LOC_NT / 32][128];          // EqSources: per-group sums (one density at a time)
   int b = blockIdx.x;
@@ -644,60 +779,12 @@ __device__ __forceinline__ void local_apply(const KParams& K, const LocalArgs& L
     return;
   }
   b -= L.n_mode_blocks;
-  const int q = L.chunk_q[b], t0 = L.chunk_t0[b];
-  const int off = L.occ_off[q], nq = L.occ_off[q + 1] - off;
-  const int t1 = min(nq, t0 + NEAR_ROWS);
-  const int col = L.occ_cell[q] % L.n_x;
-  const int lo = L.col_lo[col], w = L.col_w[col];
-  // the workgroup streams its rows as one contiguous region: threads run over
-  // the band columns, all NEAR_ROWS row loads of a column are in flight together
-  const int N = L.N;
-  const int nr = t1 - t0;
-  const cplx* blk = L.nearblk + L.near_off[q] + (int64_t)t0 * w;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  // rows in passes of RP (for several densities: fewer accumulators, more
-  // waves); the sum of each row is formed in the same order either way
-  constexpr int RP = NB >= 3 ? NEAR_ROWS / 2 : NEAR_ROWS;
-#pragma unroll
-  for (int r0 = 0; r0 < NEAR_ROWS; r0 += RP) {
-    if (r0 >= nr) break;  // workgroup-uniform
-    cplx acc[NB][RP];
-#pragma unroll
-    for (int s = 0; s < NB; ++s)
-#pragma unroll
-      for (int r = 0; r < RP; ++r) acc[s][r] = cplx{0.0, 0.0};
-    for (int u = threadIdx.x; u < w; u += LOC_NT) {
-      int l = lo + u;
-      l += (l < 0) ? N : ((l >= N) ? -N : 0);
-      cplx m[NB];
-#pragma unroll
-      for (int s = 0; s < NB; ++s) m[s] = mu[s * ldm + l];
-      cplx v[RP];
-#pragma unroll
-      for (int r = 0; r < RP; ++r) v[r] = blk[(int64_t)min(r0 + r, nr - 1) * w + u];
-#pragma unroll
-      for (int s = 0; s < NB; ++s)
-#pragma unroll
-        for (int r = 0; r < RP; ++r) acc[s][r] += v[r] * m[s];
-    }
-#pragma unroll
-    for (int s = 0; s < NB; ++s)
-#pragma unroll
-      for (int r = 0; r < RP; ++r) {
-        const cplx sm = wave_sum(acc[s][r]);
-        if (lane == 0) rs[s][r0 + r][wv] = sm;
-      }
-  }
+  // near-field work item b (the launch carries items [0, n_chunks))
+  __shared__ cplx rs[NB * NEAR_ROWS * 4];  // near-field row sums per wavefront
+  const NearArgs NA = near_args(L);
+  near_accum<NB>(NA, b, threadIdx.x, rs, mu, ldm);
   __syncthreads();
-  if ((int)threadIdx.x < nr) {
-    const int dst = L.perm[off + t0 + threadIdx.x];
-#pragma unroll
-    for (int s = 0; s < NB; ++s) {
-      cplx sm = cplx{0.0, 0.0};
-      for (int k = 0; k < LOC_NT / 64; ++k) sm += rs[s][threadIdx.x][k];
-      y[s * ldy + dst] = sm;
-    }
-  }
+  near_store<NB>(NA, b, threadIdx.x, rs, y, ldy);
 }
 
 __global__ __launch_bounds__(LOC_NT) void k_local_apply(KParams K, LocalArgs L, const cplx* __restrict__ mu,
@@ -854,7 +941,12 @@ __device__ inline cplx merge_point(const MergeArgs M, const cplx* __restrict__ d
 // directly from the cell densities instead of reading a stored grid.
 __global__ __launch_bounds__(1024) void k_merge_fft(MergeArgs M, const cplx* __restrict__ dens,
                                                     const cplx* __restrict__ twH, const cplx* __restrict__ twV,
-                                                    FftJob jh, FftJob jv) {
+                                                    FftJob jh, FftJob jv, NearArgs NA, NearFill F) {
+  const int nfft = jh.nblocks + jv.nblocks;
+  if ((int)blockIdx.x >= nfft) {  // near-field items, four per workgroup
+    near_fill<4>(NA, F.c0 + 4 * ((int)blockIdx.x - nfft), F.c1, F.mu, F.y);
+    return;
+  }
   const bool onH = (int)blockIdx.x < jh.nblocks;
   const FftJob J = onH ? jh : jv;
   const int blk = onH ? blockIdx.x : blockIdx.x - jh.nblocks;
@@ -907,8 +999,12 @@ inline size_t yconv_lds(int nY) {
   return sizeof(cplx) * (nY <= 32 ? (size_t)YC_KPB * per : (size_t)per + YC_SPLIT * nY);
 }
 __global__ __launch_bounds__(256) void k_yconv(YConvJob h, YConvJob v, int hblocks, CorrArgs C,
-                                               const cplx* __restrict__ dens) {
+                                               const cplx* __restrict__ dens, NearArgs NA, NearFill F) {
   extern __shared__ cplx col[];
+  if ((int)blockIdx.x >= C.merge_blocks + C.n_groups) {  // near-field items, one per workgroup
+    near_fill<1>(NA, F.c0 + (int)blockIdx.x - C.merge_blocks - C.n_groups, F.c1, F.mu, F.y);
+    return;
+  }
   if ((int)blockIdx.x >= C.merge_blocks) {  // the local corrections share the launch
     CorrArgs Cb = C;
     Cb.corr += (int64_t)blockIdx.y * C.bcorr;
@@ -974,6 +1070,30 @@ __global__ __launch_bounds__(256) void k_yconv(YConvJob h, YConvJob v, int hbloc
     for (int gg = 1; gg < YC_SPLIT; ++gg) sm += red[gg * nY + t];
     J.out[(int64_t)t * nX + kx0] = sm;
   }
+}
+
+// Inverse x-FFT of both grids (k_fft_rows) with near-field items as extra
+// workgroups after the transform's (four per 1024-thread workgroup, one per
+// 256-thread workgroup).
+__global__ __launch_bounds__(1024) void k_fft_rows_near(FftJob j0, FftJob j1, int sign, NearArgs NA, NearFill F) {
+  const int nfft = j0.nblocks + j1.nblocks;
+  if ((int)blockIdx.x >= nfft) {
+    if (blockDim.x == 1024)
+      near_fill<4>(NA, F.c0 + 4 * ((int)blockIdx.x - nfft), F.c1, F.mu, F.y);
+    else
+      near_fill<1>(NA, F.c0 + (int)blockIdx.x - nfft, F.c1, F.mu, F.y);
+    return;
+  }
+  const bool first = (int)blockIdx.x < j0.nblocks;
+  const FftJob J = first ? j0 : j1;
+  const int blk = first ? blockIdx.x : blockIdx.x - j0.nblocks;
+  const int n = J.A.n;
+  const cplx* in = J.in;
+  const cplx* pre = J.pre;
+  sesm_fft_block(J, blk, sign, [=](int r, int i) {
+    const cplx v = in[(int64_t)r * n + i];
+    return pre ? v * pre[i] : v;
+  });
 }
 
 struct FarArgs {
@@ -1238,7 +1358,14 @@ void sesm_accel_info(const sesm_ctx* ctx, sesm_surface_info* info) {
   info->y0 = A->y0;
   info->delta = A->delta;
   info->near_entries = A->near_entries;
+  info->near_items[0] = A->near_c1;
+  info->near_items[1] = A->near_c2 - A->near_c1;
+  info->near_items[2] = A->near_c3 - A->near_c2;
+  info->near_items[3] = A->n_chunks - A->near_c3;
+  info->near_tuned_us = A->tuned_us;
 }
+
+static int choose_near_split(sesm_ctx* ctx);
 
 int sesm_accel_setup(sesm_ctx* ctx) {
   const Problem& P = ctx->P;
@@ -1344,6 +1471,14 @@ int sesm_accel_setup(sesm_ctx* ctx) {
       chunk_t0.push_back(t0);
     }
   A->n_chunks = (int)chunk_q.size();
+  A->item_entries.assign(A->n_chunks + 1, 0);
+  A->item_rows.assign(A->n_chunks + 1, 0);
+  for (int it = 0; it < A->n_chunks; ++it) {
+    const int q = chunk_q[it];
+    const int rows = std::min(NEAR_ROWS, occ_off[q + 1] - occ_off[q] - chunk_t0[it]);
+    A->item_rows[it + 1] = A->item_rows[it] + rows;
+    A->item_entries[it + 1] = A->item_entries[it] + (int64_t)rows * col_w[occ_cell[q] % A->n_x];
+  }
   // far-field work items: up to CF_NODES nodes of one cell
   std::vector<int> cfc_q, cfc_t0;
   for (int q = 0; q < A->n_occ; ++q)
@@ -1584,7 +1719,7 @@ int sesm_accel_setup(sesm_ctx* ctx) {
       (rc = sesm_alloc(ctx, (void**)&A->bq, sizeof(cplx) * (size_t)A->n_occ * A->n_bdry)))
     return rc;
   SESM_HIP(hipMemsetAsync(A->dens, 0, sizeof(cplx) * (size_t)2 * A->n_cells * ncol, ctx->stream));
-  return SESM_OK;
+  return choose_near_split(ctx);
 }
 
 // Algorithmic HBM bytes of one launch of each forward-map kernel (every
@@ -1593,33 +1728,45 @@ struct MatvecBytes {
   double local, merge, fftH0, fftH1, fftV0, fftV1, yconvH, yconvV, cells;
 };
 
-static MatvecBytes matvec_bytes(const sesm_ctx* ctx) {
+// near-field items [c0, c1): stored entries, and per row mu, y and the node
+// index (16 + 16 + 4 bytes); per item the chunk tables (8 bytes)
+static double near_bytes(const AccelOp* A, int c0, int c1) {
+  if (c1 <= c0) return 0.0;
+  const double ent = (double)(A->item_entries[c1] - A->item_entries[c0]);
+  const double rows = (double)(A->item_rows[c1] - A->item_rows[c0]);
+  return 16.0 * ent + rows * (2.0 * 16.0 + 4.0) + 8.0 * (c1 - c0);
+}
+
+// fill = true: the near-field items split over the launches as in a
+// single-density forward map; false: all of them in the first launch
+static MatvecBytes matvec_bytes(const sesm_ctx* ctx, bool fill) {
   const AccelOp* A = ctx->acc;
   const double N = ctx->P.N, c = sizeof(cplx);
   const double nout = 4.0 * A->n_eq, ns2 = 2.0 * A->n_eq;
   const double nH = (double)A->nXH * A->nYH, nV = (double)A->nXV * A->nYV;
   const double dens = c * 2.0 * A->n_cells * ns2;
+  const int c1 = fill ? A->near_c1 : A->n_chunks, c2 = fill ? A->near_c2 : A->n_chunks,
+            c3 = fill ? A->near_c3 : A->n_chunks;
   MatvecBytes B;
-  // near field: stored blocks, mu, y, node index, chunk tables (8 B), per-cell
-  // band start, width and block offset (16 B);
-  // EqSources: operators, densities of the occupied cells, cell tables (12 B);
-  // modes (when U^eta is not empty): x, f, J and the partial sums
-  B.local = c * (double)A->near_entries + N * (2.0 * c + 4.0) + 8.0 * A->n_chunks + 16.0 * A->n_occ +
-            c * nout * N + A->n_occ * (c * nout + 12.0) +
+  // near field (its items in this launch), per-cell band start, width and
+  // block offset (16 B); EqSources: operators, densities of the occupied
+  // cells, cell tables (12 B); modes (when U^eta is not empty): x, f, J and
+  // the partial sums
+  B.local = near_bytes(A, 0, c1) + 16.0 * A->n_occ + c * nout * N + A->n_occ * (c * nout + 12.0) +
             (ctx->P.nU > 0 ? N * 24.0 + c * ctx->P.nU * NCH_MODES : 0.0);
   // merge + forward FFT: densities, twist factors and twiddles in, both
-  // transformed grids (xi, zeta) out
-  B.merge = dens + c * 2.0 * (A->nXH + A->nXV) + c * 2.0 * (nH + nV);
+  // transformed grids (xi, zeta) out; near-field items carried along
+  B.merge = dens + c * 2.0 * (A->nXH + A->nXV) + c * 2.0 * (nH + nV) + near_bytes(A, c1, c2);
   // inverse FFT: rows in + rows out, twiddle table, untwist factors
-  B.fftH1 = c * (2.0 * A->nYH * A->nXH + 2.0 * A->nXH);
+  B.fftH1 = c * (2.0 * A->nYH * A->nXH + 2.0 * A->nXH) + near_bytes(A, c3, A->n_chunks);
   B.fftV1 = c * (2.0 * A->nYV * A->nXV + 2.0 * A->nXV);
   B.fftH0 = B.fftV0 = 0.0;
   // spectra of both grids in, both kernel spectra, one output grid; local
   // corrections (correction matrices, densities, pair tables, corrections out)
-  // counted with the H grid
+  // counted with the H grid; near-field items carried along
   B.yconvH = c * (2.0 * nH + 2.0 * (2.0 * A->nYH - 1) * A->nXH + nH) + dens +
              c * (double)A->n_off * ns2 * A->n_bdry + A->n_pairs * (12.0 + c) + 12.0 * A->n_groups +
-             c * (double)A->n_pairs * A->n_bdry;
+             c * (double)A->n_pairs * A->n_bdry + near_bytes(A, c2, c3);
   B.yconvV = c * (2.0 * nV + 2.0 * (2.0 * A->nYV - 1) * A->nXV + nV);
   // local corrections, phi grids, plane-wave SVD factors, directions, cell and pair
   // tables, node coordinates and index, y read and written, mode sums
@@ -1627,6 +1774,23 @@ static MatvecBytes matvec_bytes(const sesm_ctx* ctx) {
             c * ((double)A->n_bdry * A->n_plw + (double)A->n_plw * A->n_plw + A->n_plw) + 16.0 * A->n_plw +
             16.0 * A->n_occ + N * (16.0 + 4.0 + 2.0 * c) + c * ctx->P.nU * NCH_MODES;
   return B;
+}
+
+static NearArgs near_args_host(const sesm_ctx* ctx) {
+  const AccelOp* A = ctx->acc;
+  NearArgs NA;
+  NA.N = ctx->P.N;
+  NA.n_x = A->n_x;
+  NA.occ_cell = A->occ_cell;
+  NA.occ_off = A->occ_off;
+  NA.perm = A->perm;
+  NA.chunk_q = A->chunk_q;
+  NA.chunk_t0 = A->chunk_t0;
+  NA.col_lo = A->col_lo;
+  NA.col_w = A->col_w;
+  NA.near_off = A->near_off;
+  NA.nearblk = A->nearblk;
+  return NA;
 }
 
 // Arguments of k_local_apply; without_far leaves only the near-field work items.
@@ -1672,13 +1836,24 @@ struct FarBufs {
 // launch for all nb densities (grid dimension y = batch member).  dens and
 // mode hold the densities' cell densities and mode partial sums; y holds
 // their near fields.
-static int accel_far_stages(sesm_ctx* ctx, const FarBufs& Fb, bool keep_far, const MatvecBytes& B) {
+// fill_mu (one density only): the near-field items of the split beyond the
+// first launch are carried by the merge, y-convolution and inverse-FFT
+// launches, for the density fill_mu, into Fb.y.
+static int accel_far_stages(sesm_ctx* ctx, const FarBufs& Fb, bool keep_far, const MatvecBytes& B,
+                            const cplx* fill_mu = nullptr) {
   AccelOp* A = ctx->acc;
   const Problem& P = ctx->P;
   const KParams K = ctx->kparams();
   hipStream_t st = ctx->stream;
   const int nb = Fb.nb;
   int rc;
+  const NearArgs NA = near_args_host(ctx);
+  NearFill fm{0, 0, nullptr, nullptr}, fy = fm, ff = fm;
+  if (fill_mu && nb == 1) {
+    fm = NearFill{A->near_c1, A->near_c2, fill_mu, Fb.y};
+    fy = NearFill{A->near_c2, A->near_c3, fill_mu, Fb.y};
+    ff = NearFill{A->near_c3, A->n_chunks, fill_mu, Fb.y};
+  }
   MergeArgs M{A->n_x, A->n_y, A->n_s, A->n_e, A->n_side, A->n_eq, A->n_cells,
               A->nXH, A->nYH, A->nXV, A->nYV, P.alpha * P.d};
   // merge + forward FFT along x of both grids (rows [kind][gy])
@@ -1690,8 +1865,8 @@ static int accel_far_stages(sesm_ctx* ctx, const FarBufs& Fb, bool keep_far, con
       hipLaunchKernelGGL(k_merge_fft_batch, dim3(jh.nblocks + jv.nblocks, nb), dim3(1024), 0, st, M, Fb.dens,
                          A->twxH, A->twxV, jh, jv, FftBatch{Fb.bdens, Fb.bfH, 0, Fb.bfV});
     else
-      hipLaunchKernelGGL(k_merge_fft, dim3(jh.nblocks + jv.nblocks), dim3(1024), 0, st, M, Fb.dens, A->twxH, A->twxV,
-                         jh, jv);
+      hipLaunchKernelGGL(k_merge_fft, dim3(jh.nblocks + jv.nblocks + (fm.c1 - fm.c0 + 3) / 4), dim3(1024), 0, st, M,
+                         Fb.dens, A->twxH, A->twxV, jh, jv, NA, fm);
     SESM_LAUNCH_CHECK();
   }
   SESM_KT_END(SESM_KT_MERGE, st, nb * B.merge);
@@ -1706,7 +1881,8 @@ static int accel_far_stages(sesm_ctx* ctx, const FarBufs& Fb, bool keep_far, con
                       A->grp_start, A->grp_n, A->plist, A->grp_rc, A->grp_ph, A->W,      Fb.corr,
                       Fb.bcorr,     Fb.bdens};
     const size_t lds = std::max(std::max(yconv_lds(A->nYH), yconv_lds(A->nYV)), corr_lds(A->n_eq, A->n_bdry));
-    hipLaunchKernelGGL(k_yconv, dim3(hb + vb + A->n_groups, nb), dim3(256), lds, st, yh, yv, hb, CA, Fb.dens);
+    hipLaunchKernelGGL(k_yconv, dim3(hb + vb + A->n_groups + (fy.c1 - fy.c0), nb), dim3(256), lds, st, yh, yv, hb,
+                       CA, Fb.dens, NA, fy);
     SESM_LAUNCH_CHECK();
   }
   SESM_KT_END(SESM_KT_YCONV, st, nb * (B.yconvH + B.yconvV));
@@ -1714,7 +1890,15 @@ static int accel_far_stages(sesm_ctx* ctx, const FarBufs& Fb, bool keep_far, con
   {
     const FftJob jh = sesm_fft_job(A->planH, A->nYH, Fb.gH, Fb.phH, nullptr, A->utwH, 1.0 / A->nXH);
     const FftJob jv = sesm_fft_job(A->planV, A->nYV, Fb.gV, Fb.phV, nullptr, A->utwV, 1.0 / A->nXV);
-    if ((rc = fft_launch(ctx, st, jh, jv, +1, nb, FftBatch{Fb.bgH, Fb.bphH, Fb.bgV, Fb.bphV}))) return rc;
+    if (ff.c1 > ff.c0) {  // one density with near-field items: the carrying variant
+      const bool wide = (jh.nblocks && jh.A.n * jh.rpb >= 1000) || (jv.nblocks && jv.A.n * jv.rpb >= 1000);
+      const int per = wide ? 4 : 1, nfill = (ff.c1 - ff.c0 + per - 1) / per;
+      hipLaunchKernelGGL(k_fft_rows_near, dim3(jh.nblocks + jv.nblocks + nfill), dim3(wide ? 1024 : 256), 0, st, jh,
+                         jv, +1, NA, ff);
+      SESM_LAUNCH_CHECK();
+    } else if ((rc = fft_launch(ctx, st, jh, jv, +1, nb, FftBatch{Fb.bgH, Fb.bphH, Fb.bgV, Fb.bphV}))) {
+      return rc;
+    }
   }
   SESM_KT_END(SESM_KT_FFT, st, nb * (B.fftH1 + B.fftV1));
   // one density: work items of up to CF_NODES nodes (the fullest cells no
@@ -1740,8 +1924,9 @@ static int accel_matvec_impl(sesm_ctx* ctx, const cplx* mu, cplx* y, bool keep_f
   AccelOp* A = ctx->acc;
   const KParams K = ctx->kparams();
   hipStream_t st = ctx->stream;
-  const MatvecBytes B = ctx->kt_mask ? matvec_bytes(ctx) : MatvecBytes{};
-  const LocalArgs L = local_args(ctx, false);
+  const MatvecBytes B = ctx->kt_mask ? matvec_bytes(ctx, true) : MatvecBytes{};
+  LocalArgs L = local_args(ctx, false);
+  L.n_chunks = A->near_c1;  // the other near-field items ride on the grid stages
   SESM_KT_BEGIN(SESM_KT_LOCAL, st);
   hipLaunchKernelGGL(k_local_apply, dim3(L.n_occ + L.n_mode_blocks + L.n_chunks), dim3(LOC_NT), 0, st, K, L, mu,
                      y);
@@ -1759,7 +1944,7 @@ static int accel_matvec_impl(sesm_ctx* ctx, const cplx* mu, cplx* y, bool keep_f
   Fb.phV = A->phV;
   Fb.corr = A->corr;
   Fb.y = y;
-  return accel_far_stages(ctx, Fb, keep_far, B);
+  return accel_far_stages(ctx, Fb, keep_far, B, mu);
 }
 
 template <int NB>
@@ -1798,7 +1983,7 @@ int sesm_accel_matvec_batch(sesm_ctx* ctx, int nrhs, const cplx* mu, int64_t ldm
       p += per[i] * kBatchMax;
     }
   }
-  const MatvecBytes B = ctx->kt_mask ? matvec_bytes(ctx) : MatvecBytes{};  // per density (later stages)
+  const MatvecBytes B = ctx->kt_mask ? matvec_bytes(ctx, false) : MatvecBytes{};  // per density (later stages)
   LocalArgs L = local_args(ctx, false);
   L.dens = base[0];
   L.mode_part = base[1];
@@ -1843,6 +2028,121 @@ int sesm_accel_matvec_batch(sesm_ctx* ctx, int nrhs, const cplx* mu, int64_t ldm
 }
 
 int sesm_accel_matvec(sesm_ctx* ctx, const cplx* mu, cplx* y) { return accel_matvec_impl(ctx, mu, y, false); }
+
+// Where the near-field items of a single-density forward map run (see
+// AccelOp::near_c1).  The tuner times candidate splits on the device and keeps
+// the fastest; the candidates give the merge + FFT, y-convolution and
+// inverse-FFT launches shares of the items in the ratio of those stages'
+// durations on the benched shapes (0.34 : 0.37 : 0.22 of the near-field
+// stream's time), scaled by a = 0 .. 1, the first launch keeping the rest
+// (a = 0: every item in the first launch); then each launch's share is moved
+// by +-6% and +-3% of the items while that helps (coordinate descent).
+// Results are cached per grid shape in the context, so a surface of a known
+// shape is not timed again.
+static void set_split(AccelOp* A, double f_local, double f_merge, double f_yconv) {
+  const int n = A->n_chunks;
+  auto at = [&](double f) { return std::min(n, std::max(0, (int)std::lround(f * n))); };
+  A->near_c1 = at(f_local);
+  A->near_c2 = std::max(A->near_c1, at(f_local + f_merge));
+  A->near_c3 = std::max(A->near_c2, at(f_local + f_merge + f_yconv));
+}
+
+static int choose_near_split(sesm_ctx* ctx) {
+  AccelOp* A = ctx->acc;
+  const sesm_params& prm = ctx->prm;
+  A->tuned_us = 0.0;
+  if (prm.near_split < 0) {
+    set_split(A, 1.0, 0.0, 0.0);
+    return SESM_OK;
+  }
+  if (prm.near_split == 1) {
+    const int* f = prm.split_permille;
+    if (f[0] < 0 || f[1] < 0 || f[2] < 0 || f[0] > 1000 || f[1] > 1000 || f[2] > 1000 || f[0] + f[1] + f[2] > 1000)
+      return ctx->fail(SESM_EINVAL, "split_permille: each in [0, 1000], sum at most 1000");
+    set_split(A, f[0] / 1000.0, f[1] / 1000.0, f[2] / 1000.0);
+    return SESM_OK;
+  }
+  if (prm.near_split != 0) return ctx->fail(SESM_EINVAL, "near_split must be -1, 0 or 1");
+  const int64_t key[8] = {ctx->P.N, A->n_chunks, A->n_occ, A->nXH, A->nYH, A->nXV, A->nYV, A->n_groups};
+  for (const NearSplit& c : ctx->near_splits)
+    if (std::equal(key, key + 8, c.key)) {
+      A->near_c1 = c.c1;
+      A->near_c2 = c.c2;
+      A->near_c3 = c.c3;
+      A->tuned_us = c.us;
+      return SESM_OK;
+    }
+  const int N = ctx->P.N;
+  int rc;
+  cplx *mu = nullptr, *y = nullptr;
+  if ((rc = sesm_alloc(ctx, (void**)&mu, sizeof(cplx) * N)) || (rc = sesm_alloc(ctx, (void**)&y, sizeof(cplx) * N)))
+    return rc;
+  SESM_HIP(hipMemsetAsync(mu, 0x3F, sizeof(cplx) * N, ctx->stream));  // any finite density: times do not depend on it
+  hipEvent_t e0, e1;
+  SESM_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return ctx->fail(SESM_EHIP, "hipEventCreate failed");
+  }
+  const uint32_t kt = ctx->kt_mask;
+  ctx->kt_mask = 0;  // the tuner's maps are not counted by the timing classes
+  auto trial = [&](double* us) -> int {
+    for (int w = 0; w < 2; ++w)
+      if (int r = accel_matvec_impl(ctx, mu, y, false)) return r;
+    double best = 1e30;
+    for (int rep = 0; rep < 3; ++rep) {
+      SESM_HIP(hipEventRecord(e0, ctx->stream));
+      for (int t = 0; t < 4; ++t)
+        if (int r = accel_matvec_impl(ctx, mu, y, false)) return r;
+      SESM_HIP(hipEventRecord(e1, ctx->stream));
+      SESM_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      SESM_HIP(hipEventElapsedTime(&ms, e0, e1));
+      best = std::min(best, 1e3 * ms / 4);
+    }
+    *us = best;
+    return SESM_OK;
+  };
+  // shares of the items with merge + FFT, y convolution, inverse FFT
+  const double wm = 0.34, wy = 0.37, wf = 0.22;
+  double best_us = 1e30, best[3] = {0.0, 0.0, 0.0};
+  auto try_split = [&](const double* f, double* us) -> int {
+    set_split(A, 1.0 - (f[0] + f[1] + f[2]), f[0], f[1]);
+    return trial(us);
+  };
+  // scan the overall share, then refine each launch's share (coordinate descent)
+  for (double a : {0.0, 0.3, 0.5, 0.7, 0.85, 1.0}) {  // a = 0: every item in the first launch
+    const double f[3] = {a * wm, a * wy, a * wf};
+    double us = 0.0;
+    if ((rc = try_split(f, &us))) break;
+    if (us < best_us) best_us = us, std::copy(f, f + 3, best);
+  }
+  for (double step : {0.06, 0.03}) {
+    for (int i = 0; i < 3 && !rc; ++i)
+      for (double sg : {1.0, -1.0}) {
+        double f[3] = {best[0], best[1], best[2]};
+        f[i] += sg * step;
+        if (f[i] < 0.0 || f[0] + f[1] + f[2] > 1.0) continue;
+        double us = 0.0;
+        if ((rc = try_split(f, &us))) break;
+        if (us < best_us) best_us = us, std::copy(f, f + 3, best);
+      }
+  }
+  ctx->kt_mask = kt;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  set_split(A, 1.0 - (best[0] + best[1] + best[2]), best[0], best[1]);
+  A->tuned_us = best_us;
+  NearSplit c;
+  std::copy(key, key + 8, c.key);
+  c.c1 = A->near_c1;
+  c.c2 = A->near_c2;
+  c.c3 = A->near_c3;
+  c.us = best_us;
+  ctx->near_splits.push_back(c);
+  return SESM_OK;
+}
 
 extern "C" int sesm_diag_accel(sesm_ctx* ctx, const sesm_c64* mu, int32_t which, sesm_c64* out, int64_t out_len) {
   if (!ctx) return SESM_EINVAL;

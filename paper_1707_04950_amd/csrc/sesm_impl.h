@@ -37,6 +37,13 @@ struct KParams {
 
 struct AccelOp;  // shifted-equivalent-source accelerator (sesm_accel.hip)
 
+// A near-field split chosen by the tuner for one accelerator grid shape.
+struct NearSplit {
+  int64_t key[8];
+  int c1, c2, c3;
+  double us;
+};
+
 // Event pairs of one timed kernel class (folded into ms when the pool is full
 // and when read).
 struct KTimer {
@@ -91,6 +98,7 @@ struct sesm_ctx {
   cplx* ray_B = nullptr;
   int ray_cap = 0;
   void* noalloc_scratch = nullptr;  // this device's copy of the library's fixed array (sesm_rayleigh_noalloc)
+  std::vector<NearSplit> near_splits;  // tuned near-field splits by grid shape (kept across surfaces)
   std::vector<std::pair<void*, size_t>> owned;  // every device allocation made for the surface
   // device blocks released by an earlier surface, by size, reused by the next
   // one (a surface of the same shape allocates the same sizes); bounded below

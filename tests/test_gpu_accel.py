@@ -175,8 +175,10 @@ def test_kernel_timing_counts_and_bytes(torch, solver, case):
     st = solver.timing_read()
     assert [st[k]["launches"] for k in ("k_local_apply", "k_merge_fft", "k_fft_rows", "k_yconv",
                                         "k_cells_far")] == [1, 1, 1, 1, 1]
-    # the stored near-field blocks dominate the first kernel's bytes
-    assert 16.0 * inf["near_entries"] < st["k_local_apply"]["bytes"] < 16.0 * inf["near_entries"] + 2e3 * disc.N
+    # the stored near-field blocks dominate the bytes of the four launches that
+    # carry near-field items (the first launch and the grid stages)
+    carry = sum(st[k]["bytes"] for k in ("k_local_apply", "k_merge_fft", "k_fft_rows", "k_yconv"))
+    assert 16.0 * inf["near_entries"] < carry < 16.0 * inf["near_entries"] + 2e3 * disc.N + 2e7
     assert all(r["total_ms"] > 0 for r in st.values() if r["launches"])
     solver.timing_enable(1 << lib.KT_DOTS)
     _, info = solver.solve(tol=1e-6, max_iter=40, allow_noconv=True)
@@ -347,3 +349,35 @@ def test_full_size_grazing_wood(torch, solver):
     print("efficiency diff accel vs dense %.2e; eps dense %.2e accel %.2e" % (np.max(np.abs(e1 - e0)), eps0, eps1))
     assert np.max(np.abs(e1 - e0)) <= 1e-6
     assert abs(eps0) <= 1e-7 and abs(eps1) <= 1e-6
+
+
+@pytest.mark.parametrize("N", [4096, 32768])
+def test_near_field_split_is_bitwise_neutral(torch, solver, N):
+    """The near-field work items of a forward map may run in the first launch
+    or ride on the grid-stage launches (merge + FFT, y convolution, inverse
+    FFT); every split, including the tuner's, gives the same forward map bit
+    for bit, and the item counts reported add up to all items."""
+    import paper_1707_04950_amd as lib
+    from gpu_util import to_dev, to_host
+    wl = W.config_grazing_wood(N)
+    disc = dense.Discretization(wl)
+    mu = to_dev(torch, W.random_density(N, 9))
+    ys, items = [], []
+    for kw in (dict(near_split=-1), dict(near_split=1, split_permille=(1000, 0, 0)),
+               dict(near_split=1, split_permille=(100, 300, 350)), dict(near_split=1, split_permille=(0, 0, 0)),
+               dict(near_split=1, split_permille=(0, 500, 0)), dict()):
+        solver.set_surface(np.asarray(wl.a_coef), np.asarray(wl.b_coef), wl.d, wl.k, wl.alpha, wl.j, wl.A, N,
+                           h=wl.h, c=wl.c, n_a=disc.n_a, gamma_frac=wl.gamma_frac, eta=wl.eta, mode=lib.MODE_ACCEL,
+                           L=wl.L, **kw)
+        inf = solver.info()
+        ys.append(to_host(solver.matvec(mu)))
+        items.append(inf["near_items"])
+        print(kw, "items per launch", inf["near_items"], "tuned %.1f us" % inf["near_tuned_us"])
+    total = sum(items[0])
+    assert items[0] == [total, 0, 0, 0] and items[3][0] == 0 and items[4][1] == int(round(0.5 * total))
+    assert all(sum(it) == total for it in items)
+    assert all(np.array_equal(ys[0], y) for y in ys[1:])
+    with pytest.raises(lib.SesmError):
+        solver.set_surface(np.asarray(wl.a_coef), np.asarray(wl.b_coef), wl.d, wl.k, wl.alpha, wl.j, wl.A, N,
+                           h=wl.h, c=wl.c, n_a=disc.n_a, gamma_frac=wl.gamma_frac, eta=wl.eta, mode=lib.MODE_ACCEL,
+                           L=wl.L, near_split=1, split_permille=(600, 500, 0))
