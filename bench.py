@@ -45,6 +45,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched-solve", action="store_true")  # e.g. under counter collection (many dispatches)
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--workload", choices=["grazing", "c4"], default="grazing")
+    ap.add_argument("--c4-angles", type=int, default=64)
+    ap.add_argument("--c4-N", type=int, default=16384)
+    ap.add_argument("--c4-max-iter", type=int, default=1000)
     return ap.parse_args()
 
 
@@ -143,10 +147,97 @@ def efficiency_vs_oracle(n, e):
     return None
 
 
+def bench_c4(args):
+    """Many incidences (C4): a Gaussian random surface of period 50, N = 16384,
+    64 incidence angles uniform in [0, 85] degrees at each of 4 wavenumbers
+    (d/lambda = 50, 50.5, 51, 51.5).  Each wavenumber is one surface with one
+    incidence set: the alpha-independent operator parts are built once, every
+    member gets its own lattice-sum spectra, and the 64 systems are solved in
+    lockstep (batched forward maps, one launch per stage and group).  The
+    baseline solves the same 256 problems one at a time (set_surface at the
+    angle, solve, efficiencies).  Prints one JSON line."""
+    import numpy as np
+    import torch
+
+    import paper_1707_04950_amd as lib
+    import workloads as W
+    s = lib.Solver(0)
+    angles = W.c4_angles(args.c4_angles)
+    nk = len(W.C4_D_OVER_LAMBDA)
+
+    def setup(wl, theta=0.0):
+        n_a = max(8, int(math.floor(0.8 * min(wl.L, wl.d) / wl.dx)))
+        w = wl.with_(theta_deg=theta)
+        s.set_surface(np.asarray(w.a_coef), np.asarray(w.b_coef), w.d, w.k, w.alpha, w.j, w.A, w.N, h=w.h, c=w.c,
+                      n_a=n_a, gamma_frac=w.gamma_frac, eta=w.eta, mode=lib.MODE_ACCEL, L=w.L)
+
+    def batched(ik):
+        wl = W.config_c4(ik, args.c4_N)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        setup(wl)
+        s.set_incidences([wl.k * math.sin(math.radians(t)) for t in angles])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        X, infos = s.solve_incidences(tol=args.tol, max_iter=args.c4_max_iter, allow_noconv=True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        effs = [s.efficiencies_incidence(r, X[r].contiguous()) for r in range(len(angles))]
+        t3 = time.perf_counter()
+        return dict(setup=t1 - t0, solve=t2 - t1, eff=t3 - t2, iters=[i["iters"] for i in infos],
+                    conv=[i["converged"] for i in infos], e=[e for _, e, _ in effs], eps=[p for _, _, p in effs])
+
+    def single(ik):
+        wl = W.config_c4(ik, args.c4_N)
+        out = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for th in angles:
+            setup(wl, th)
+            mu, info = s.solve(tol=args.tol, max_iter=args.c4_max_iter, allow_noconv=True)
+            out.append((s.efficiencies(mu)[1], info["iters"], info["converged"]))
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, out
+
+    batched(0)  # warm-up: tuner, pools, code objects
+    single(0)
+    recs = [batched(ik) for ik in range(nk)]
+    t_batch = sum(r["setup"] + r["solve"] + r["eff"] for r in recs)
+    sing = [single(ik) for ik in range(nk)]
+    t_single = sum(t for t, _ in sing)
+    n_solves = nk * len(angles)
+    diff = max(float(np.max(np.abs(np.asarray(eb) - np.asarray(es)))) for r, (_, o) in zip(recs, sing)
+               for eb, (es, _, _) in zip(r["e"], o))
+    out = {
+        "metric": "incidence sweep solves/s (C4: 64 angles x 4 wavenumbers, N=%d)" % args.c4_N,
+        "value": n_solves / t_batch, "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "gauss-d50-rms0.5 incidence sweep", "N": args.c4_N, "angles": len(angles),
+                   "d_over_lambda": list(W.C4_D_OVER_LAMBDA), "gmres_tol": args.tol},
+        "single_solves_per_s": n_solves / t_single, "speedup_vs_single": t_single / t_batch,
+        "phase_s": {"setup": sum(r["setup"] for r in recs), "solve": sum(r["solve"] for r in recs),
+                    "eff": sum(r["eff"] for r in recs)},
+        "iters_min_median_max": [int(min(min(r["iters"]) for r in recs)),
+                                 int(np.median([i for r in recs for i in r["iters"]])),
+                                 int(max(max(r["iters"]) for r in recs))],
+        "all_converged": all(all(r["conv"]) for r in recs) and all(c for _, o in sing for _, _, c in o),
+        "max_energy_balance_error": max(abs(p) for r in recs for p in r["eps"]),
+        "max_efficiency_diff_batched_vs_single": diff,
+    }
+    s.close()
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.workload == "c4":
+        if args.gpus != 1:
+            print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus, file=sys.stderr)
+            sys.exit(2)
+        bench_c4(args)
         return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus, file=sys.stderr)

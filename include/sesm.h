@@ -236,6 +236,55 @@ SESM_API int sesm_solve(sesm_ctx* ctx, const sesm_c64* b, sesm_c64* mu, double t
 SESM_API int sesm_solve_batch(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b, int64_t ld_b, sesm_c64* mu,
                               int64_t ld_mu, double tol, int32_t max_iter, int32_t flags, sesm_solve_info* info);
 
+/* ---- Incidence sets: several incidences on one surface and wavenumber ----
+ *
+ * The accelerated operator depends on the incidence only through the Bloch
+ * wavenumber alpha: the phase e^{-i alpha d p} of the lattice sums (eq.
+ * shifted_periodic_green_function, eq. Gq_limit), the phase e^{i alpha d} of
+ * source images across the period boundary, and the completion set U^eta
+ * with its modes (eq. M_eta).  The near-field blocks, the EqSources
+ * operators (eq. eq_source_point), the local-correction matrices
+ * (eq. small_convolution) and the plane-wave factors (eq. plwave_QR) do not
+ * depend on alpha.  An incidence set keeps one copy of those and, per
+ * member, only the alpha-dependent tables (kernel spectra, twist factors,
+ * completion modes; about 3 MB per member at N = 32768).  Accelerated mode
+ * only.  A new sesm_set_surface clears the set. */
+#define SESM_MAX_INCIDENCES 4096
+
+/* Set the incidence set: n Bloch wavenumbers alpha_host[0..n-1] (host,
+ * |alpha| < k each; n = 0 clears the set).  Builds the members' tables
+ * (their windowed lattice sums: about 1 ms each at N = 32768).  The surface's
+ * own incidence (sesm_set_surface's alpha) is unaffected. */
+SESM_API int sesm_set_incidences(sesm_ctx* ctx, int32_t n, const double* alpha_host);
+
+/* Right-hand side of member r: b_l = -exp(i (alpha_r x_l - beta_r f(x_l))).
+ * b: device array of N sesm_c64. */
+SESM_API int sesm_rhs_incidence(sesm_ctx* ctx, int32_t r, sesm_c64* b);
+
+/* Forward maps (Algorithm 3) of members r0 .. r0 + nrhs - 1: density i
+ * (device array mu + i ld_mu of N) with the operator of member r0 + i, into
+ * y + i ld_y.  Groups of up to four densities share one pass over the
+ * near-field blocks and EqSources operators; each later stage is one launch
+ * per group with the members' own tables.  Same argument rules as
+ * sesm_matvec_batch; member indices beyond the set give SESM_EINVAL. */
+SESM_API int sesm_matvec_incidences(sesm_ctx* ctx, int32_t r0, int32_t nrhs, const sesm_c64* mu, int64_t ld_mu,
+                                    sesm_c64* y, int64_t ld_y);
+
+/* Algorithm 1 for members r0 .. r0 + nrhs - 1 in lockstep (as
+ * sesm_solve_batch): system i has the operator of member r0 + i and the
+ * right-hand side b + i ld_b, or, with b = NULL, that member's incident
+ * field (sesm_rhs_incidence).  mu, flags, tol, max_iter and info as in
+ * sesm_solve_batch (nrhs <= SESM_MAX_BATCH). */
+SESM_API int sesm_solve_incidences(sesm_ctx* ctx, int32_t r0, int32_t nrhs, const sesm_c64* b, int64_t ld_b,
+                                   sesm_c64* mu, int64_t ld_mu, double tol, int32_t max_iter, int32_t flags,
+                                   sesm_solve_info* info);
+
+/* Efficiencies and energy balance (as sesm_efficiencies) of a density mu
+ * solved for member r: the Rayleigh coefficients with alpha_r, its orders
+ * and completion set. */
+SESM_API int sesm_efficiencies_incidence(sesm_ctx* ctx, int32_t r, const sesm_c64* mu, int32_t* n_first,
+                                         int32_t* n_count, double* e_host, int32_t e_capacity, double* energy_error);
+
 /* Efficiencies e_n = (beta_n / beta) |B_n|^2 of the propagating orders
  * (Sec. 2) and the energy-balance error eps = 1 - sum e_n, eq. (energy_error).
  * B_n are the Rayleigh coefficients of the representation

@@ -112,6 +112,12 @@ def load_library(path=LIB_PATH):
         "sesm_timing_enable": (ctypes.c_int, [_P, ctypes.c_uint32, _I]),
         "sesm_diag_fft": (ctypes.c_int, [_P, _I, _I, _P, _P, _I]),
         "sesm_timing_read": (ctypes.c_int, [_P, _P, _I]),
+        "sesm_set_incidences": (ctypes.c_int, [_P, _I, ctypes.POINTER(_D)]),
+        "sesm_rhs_incidence": (ctypes.c_int, [_P, _I, _P]),
+        "sesm_matvec_incidences": (ctypes.c_int, [_P, _I, _I, _P, ctypes.c_int64, _P, ctypes.c_int64]),
+        "sesm_solve_incidences": (ctypes.c_int, [_P, _I, _I, _P, ctypes.c_int64, _P, ctypes.c_int64, _D, _I, _I, _P]),
+        "sesm_efficiencies_incidence": (ctypes.c_int, [_P, _I, _P, ctypes.POINTER(_I), ctypes.POINTER(_I),
+                                                       ctypes.POINTER(_D), _I, ctypes.POINTER(_D)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -310,6 +316,60 @@ class Solver:
         eps = _D()
         self._check(self.lib.sesm_efficiencies(self.h, _ptr(mu, self.N), ctypes.byref(n0), ctypes.byref(nc),
                                                e.ctypes.data_as(ctypes.POINTER(_D)), cap, ctypes.byref(eps)))
+        return np.arange(n0.value, n0.value + nc.value), e[: nc.value].copy(), eps.value
+
+    # ---- incidence sets (several alpha on one surface and wavenumber)
+    def set_incidences(self, alphas):
+        a = np.ascontiguousarray(alphas, dtype=np.float64)
+        self._check(self.lib.sesm_set_incidences(self.h, len(a), a.ctypes.data_as(ctypes.POINTER(_D))))
+        self.n_inc = len(a)
+
+    def rhs_incidence(self, r, out=None):
+        out = self.empty() if out is None else out
+        self._check(self.lib.sesm_rhs_incidence(self.h, int(r), _ptr(out, self.N)))
+        return out
+
+    def matvec_incidences(self, mu, r0=0, out=None):
+        """Forward maps of the rows of mu, row i with the operator of member r0 + i."""
+        if mu.dim() != 2 or mu.shape[1] < self.N:
+            raise ValueError("mu must be a (nrhs, >= N) tensor")
+        n = int(mu.shape[0])
+        if out is None:
+            out = self._torch.empty((n, self.N), dtype=self._torch.complex128, device=self.device)
+        self._check(self.lib.sesm_matvec_incidences(self.h, int(r0), n, _ptr_rows(mu, self.N), int(mu.stride(0)),
+                                                    _ptr_rows(out, self.N, n), int(out.stride(0))))
+        return out
+
+    def solve_incidences(self, r0=0, n=None, b=None, tol=1e-10, max_iter=1000, out=None, allow_noconv=False,
+                         x0=None):
+        """Lockstep GMRES for members r0 .. r0 + n - 1 (their incident fields when b is None)."""
+        n = (self.n_inc - r0) if n is None else int(n)
+        flags = 0
+        if x0 is not None:
+            out, flags = x0, SOLVE_X0
+        if out is None:
+            out = self._torch.empty((n, self.N), dtype=self._torch.complex128, device=self.device)
+        if out.dim() != 2 or out.shape[0] != n or out.shape[1] < self.N:
+            raise ValueError("out must be a (n, >= N) tensor")
+        bp, ldb = None, self.N
+        if b is not None:
+            if b.dim() != 2 or b.shape[0] != n:
+                raise ValueError("b must be a (n, >= N) tensor")
+            bp, ldb = _ptr_rows(b, self.N), int(b.stride(0))
+        infs = (SolveInfo * max(n, 1))()
+        rc = self.lib.sesm_solve_incidences(self.h, int(r0), n, bp, ldb, _ptr_rows(out, self.N, n), int(out.stride(0)),
+                                            tol, max_iter, flags, ctypes.cast(infs, ctypes.c_void_p))
+        self._check(rc, allow=(SESM_ENOCONV,) if allow_noconv else ())
+        return out, [_info_dict(i) for i in infs[:n]]
+
+    def efficiencies_incidence(self, r, mu):
+        cap = 4096
+        e = np.zeros(cap)
+        n0, nc = _I(), _I()
+        eps = _D()
+        self._check(self.lib.sesm_efficiencies_incidence(self.h, int(r), _ptr(mu, self.N), ctypes.byref(n0),
+                                                         ctypes.byref(nc), e.ctypes.data_as(ctypes.POINTER(_D)), cap,
+                                                         ctypes.byref(eps)))
         return np.arange(n0.value, n0.value + nc.value), e[: nc.value].copy(), eps.value
 
     def rayleigh(self, mu, orders):

@@ -64,10 +64,10 @@ struct AccelOp {
   int *cfc_q = nullptr, *cfc_t0 = nullptr;
   cplx *p2e = nullptr, *nearblk = nullptr, *dens = nullptr;
   cplx *gH = nullptr, *gV = nullptr, *fH = nullptr, *fV = nullptr, *phH = nullptr, *phV = nullptr;
-  cplx *specH = nullptr, *specV = nullptr, *W = nullptr;
+  cplx *specH = nullptr, *specV = nullptr, *W = nullptr;  // (inside self_spec)
   cplx *pplw = nullptr;  // plane-wave least squares: (U^H)^T (n_bdry x n_plw), V^T (n_plw x n_plw), 1 / sig
   cplx *pinv = nullptr;  // equivalent-source least squares, per set: Q^H (2n_eq x 4n_coll) then R
-  cplx *twxH = nullptr, *twxV = nullptr, *utwH = nullptr, *utwV = nullptr;  // e^{-i alpha x}, e^{+i alpha x}
+  cplx *twxH = nullptr, *twxV = nullptr, *utwH = nullptr, *utwV = nullptr;  // e^{-i alpha x}, e^{+i alpha x} (inside self_tw)
   double* dirs = nullptr;
   cplx* mode_part = nullptr;
   // local-correction pairs (occupied cell q, occupied cell of its near columns):
@@ -76,7 +76,7 @@ struct AccelOp {
   int* pair_off = nullptr;
   int *grp_o = nullptr, *grp_start = nullptr, *grp_n = nullptr, *plist = nullptr;  // pairs grouped by offset
   int* grp_rc = nullptr;   // source cell per pair, in plist order
-  cplx* grp_ph = nullptr;  // wrap phase per pair, in plist order
+
   cplx* corr = nullptr;  // [n_pairs][n_bdry]
   cplx* yfar = nullptr;  // diagnostic copy of the far-field contribution
   cplx* bq = nullptr;    // diagnostic copy of the boundary values b^q, [n_occ][n_bdry]
@@ -91,6 +91,18 @@ struct AccelOp {
   double tuned_us = 0.0;                  // forward-map time of the chosen split (0: not measured)
   std::vector<int64_t> item_entries;      // prefix sums over the items: stored entries
   std::vector<int64_t> item_rows;         //                              rows
+  // incidence-dependent tables, laid out alike for the surface's own
+  // incidence and for each member of an incidence set: kernel spectra
+  // [specH | specV] (spec_len entries) and twist factors
+  // [e^{-i alpha x} on H | on V | e^{+i alpha x} on H | on V] (tw_len entries)
+  int64_t spec_len = 0, tw_len = 0;
+  cplx *self_spec = nullptr, *self_tw = nullptr;
+  IncParams* inc_self = nullptr;          // device record of the surface's incidence
+  int n_inc = 0;                          // incidence set (sesm_set_incidences)
+  IncParams* inc_set = nullptr;           // device records [n_inc]
+  cplx *inc_spec = nullptr, *inc_tw = nullptr;
+  std::vector<Problem> inc_prob;          // each member's incidence-dependent scalars (host)
+  int* grp_wr = nullptr;                  // column wrap of each correction pair's source cell
 };
 
 namespace {
@@ -465,7 +477,10 @@ __global__ void k_wmat(KParams K, CellGeo G, int n_y, int ring, cplx* __restrict
 }
 
 // Near-field blocks: rows = nodes of the cell, columns = the band of the cell's
-// column; entry = operator entry for the source image in the band (phase included).
+// column; entry = operator entry for the source image in the band.  The
+// Bloch phase e^{i alpha d shift} of a wrapped column is left out (applied to
+// the density when the block is applied), so the blocks serve every
+// incidence on the surface.
 __global__ __launch_bounds__(256) void k_near_setup(KParams K, int n_x, const int* __restrict__ chunk_q,
                                                     const int* __restrict__ chunk_t0, int rows_per_chunk,
                                                     const int* __restrict__ occ_cell,
@@ -501,7 +516,6 @@ __global__ __launch_bounds__(256) void k_near_setup(KParams K, int n_x, const in
     } else {
       const double X = x[i] - (x[l] + shift * K.d), Y = f[i] - f[l];
       v = sesm_entry_offdiag(K, logw, X, Y, fp[l], 1.0);
-      if (shift != 0) v = cexp_i(K.alpha * K.d * shift) * v;
     }
     B[e] = v;
   }
@@ -562,13 +576,15 @@ struct NearArgs {
 
 // Item `it`, 256 threads (tid = 0..255 within their group): each thread runs
 // over band columns tid, tid + 256, ... with all NEAR_ROWS row loads of a
-// column in flight; per density s and row r the wavefront sums go to
+// column in flight; a wrapped column's density carries the Bloch phase
+// ph[s] = e^{i alpha_s d} of density s (or its conjugate); per density s and
+// row r the wavefront sums go to
 // rs[(s NEAR_ROWS + r) 4 + wave].  For several densities (NB >= 3) the rows are
 // taken in two passes of half as many accumulators; each row's sum is formed
 // in the same order either way, so every launch shape gives the same bits.
 template <int NB>
 __device__ __forceinline__ void near_accum(const NearArgs& A, int it, int tid, cplx* rs,
-                                           const cplx* __restrict__ mu, int64_t ldm) {
+                                           const cplx* __restrict__ mu, int64_t ldm, const cplx* ph) {
   const int q = A.chunk_q[it], t0 = A.chunk_t0[it];
   const int off = A.occ_off[q], nq = A.occ_off[q + 1] - off;
   const int nr = min(NEAR_ROWS, nq - t0);
@@ -588,10 +604,14 @@ __device__ __forceinline__ void near_accum(const NearArgs& A, int it, int tid, c
       for (int r = 0; r < RP; ++r) acc[s][r] = cplx{0.0, 0.0};
     for (int u = tid; u < w; u += 256) {
       int l = lo + u;
-      l += (l < 0) ? N : ((l >= N) ? -N : 0);
+      const int wr = (l < 0) ? -1 : ((l >= N) ? 1 : 0);  // source image x_l + wr d
+      l -= wr * N;
       cplx m[NB];
 #pragma unroll
-      for (int s = 0; s < NB; ++s) m[s] = mu[s * ldm + l];
+      for (int s = 0; s < NB; ++s) {
+        m[s] = mu[s * ldm + l];
+        if (wr != 0) m[s] = cmul_fixed(wr > 0 ? ph[s] : conj(ph[s]), m[s]);  // its density mu_l e^{i alpha d wr}
+      }
       cplx v[RP];
 #pragma unroll
       for (int r = 0; r < RP; ++r) v[r] = blk[(int64_t)min(r0 + r, nr - 1) * w + u];
@@ -633,12 +653,13 @@ __device__ __forceinline__ void near_store(const NearArgs& A, int it, int tid, c
 // workgroup of GROUPS x 256 threads: group g takes item it0 + g.
 template <int GROUPS>
 __device__ __forceinline__ void near_fill(const NearArgs& A, int it0, int c1, const cplx* __restrict__ mu,
-                                          cplx* __restrict__ y) {
+                                          cplx* __restrict__ y, double alpha_d) {
   __shared__ cplx rs_fill[GROUPS * NEAR_ROWS * 4];
   const int g = threadIdx.x >> 8, tid = threadIdx.x & 255;
   const int it = it0 + g;
   cplx* rs = rs_fill + g * NEAR_ROWS * 4;
-  if (it < c1) near_accum<1>(A, it, tid, rs, mu, 0);
+  const cplx ph = cexp_i(alpha_d);  // (formed as in the first launch: the same bits)
+  if (it < c1) near_accum<1>(A, it, tid, rs, mu, 0, &ph);
   __syncthreads();
   if (it < c1) near_store<1>(A, it, tid, rs, y, 0);
 }
@@ -649,6 +670,7 @@ struct NearFill {
   int c0, c1;
   const cplx* mu;
   cplx* y;
+  double alpha_d;  // alpha d of the density's incidence
 };
 
 
@@ -676,7 +698,8 @@ __device__ __forceinline__ NearArgs near_args(const LocalArgs& L) {
 // so a batch reproduces single forward maps bit for bit.
 template <int NB>
 __device__ __forceinline__ void local_apply(const KParams& K, const LocalArgs& L, const cplx* __restrict__ mu,
-                                            int64_t ldm, cplx* __restrict__ y, int64_t ldy) {
+                                            int64_t ldm, cplx* __restrict__ y, int64_t ldy,
+                                            const IncParams* __restrict__ inc, int inc_step) {
   __shared__ cplx red[LOC_NT];
   __shared__ cplx mus[NB][LOC_NT];                 // EqSources: staged mu of the cell
   __shared__ cplx gsum[LOC_NT / 32][128];          // EqSources: per-group sums (one density at a time)
@@ -757,21 +780,21 @@ __device__ __forceinline__ void local_apply(const KParams& K, const LocalArgs& L
   }
   b -= L.n_occ;
   if (b < L.n_mode_blocks) {
+    // density r with the completion modes of its incidence inc[r inc_step]
     const int per = (K.N + NCH_MODES - 1) / NCH_MODES;
     const int lo = b * per, hi = min(K.N, lo + per);
-    for (int t = 0; t < K.nU; ++t) {
-      cplx acc[NB];
 #pragma unroll
-      for (int r = 0; r < NB; ++r) acc[r] = cplx{0.0, 0.0};
-      for (int l = lo + threadIdx.x; l < hi; l += LOC_NT) {
-        const double mag = exp(K.Ubi[t] * L.f[l]) * L.J[l] * K.dx;
-        const cplx e = mag * cexp_i(-(K.Ua[t] * L.x[l] + K.Ubr[t] * L.f[l]));
-#pragma unroll
-        for (int r = 0; r < NB; ++r) acc[r] += e * mu[r * ldm + l];
-      }
-#pragma unroll
-      for (int r = 0; r < NB; ++r) {
-        const cplx sm = block_sum<LOC_NT>(acc[r], red);
+    for (int r = 0; r < NB; ++r) {
+      const IncParams& I = inc[r * inc_step];
+      for (int t = 0; t < I.nU; ++t) {
+        const double ua = I.Ua[t], ubr = I.Ubr[t], ubi = I.Ubi[t];
+        cplx acc = cplx{0.0, 0.0};
+        for (int l = lo + threadIdx.x; l < hi; l += LOC_NT) {
+          const double mag = exp(ubi * L.f[l]) * L.J[l] * K.dx;
+          const cplx e = mag * cexp_i(-(ua * L.x[l] + ubr * L.f[l]));
+          acc += e * mu[r * ldm + l];
+        }
+        const cplx sm = block_sum<LOC_NT>(acc, red);
         if (threadIdx.x == 0) L.mode_part[r * L.mode_ld + (int64_t)t * NCH_MODES + b] = sm;
         __syncthreads();
       }
@@ -782,21 +805,25 @@ __device__ __forceinline__ void local_apply(const KParams& K, const LocalArgs& L
   // near-field work item b (the launch carries items [0, n_chunks))
   __shared__ cplx rs[NB * NEAR_ROWS * 4];  // near-field row sums per wavefront
   const NearArgs NA = near_args(L);
-  near_accum<NB>(NA, b, threadIdx.x, rs, mu, ldm);
+  cplx ph[NB];
+#pragma unroll
+  for (int r = 0; r < NB; ++r) ph[r] = cexp_i(inc[r * inc_step].alpha_d);
+  near_accum<NB>(NA, b, threadIdx.x, rs, mu, ldm, ph);
   __syncthreads();
   near_store<NB>(NA, b, threadIdx.x, rs, y, ldy);
 }
 
 __global__ __launch_bounds__(LOC_NT) void k_local_apply(KParams K, LocalArgs L, const cplx* __restrict__ mu,
-                                                        cplx* __restrict__ y) {
-  local_apply<1>(K, L, mu, 0, y, 0);
+                                                        cplx* __restrict__ y, const IncParams* __restrict__ inc) {
+  local_apply<1>(K, L, mu, 0, y, 0, inc, 0);
 }
 
 // NB densities at once (strides ldm, ldy in elements)
 template <int NB>
 __global__ __launch_bounds__(LOC_NT) void k_local_apply_batch(KParams K, LocalArgs L, const cplx* __restrict__ mu,
-                                                              int64_t ldm, cplx* __restrict__ y, int64_t ldy) {
-  local_apply<NB>(K, L, mu, ldm, y, ldy);
+                                                              int64_t ldm, cplx* __restrict__ y, int64_t ldy,
+                                                              const IncParams* __restrict__ inc, int inc_step) {
+  local_apply<NB>(K, L, mu, ldm, y, ldy, inc, inc_step);
 }
 
 struct MergeArgs {
@@ -808,7 +835,7 @@ struct MergeArgs {
 // Local corrections (eq. small_convolution with the punctured kernel), by the
 // workgroups from merge_blocks on of the y-convolution launch, for pairs
 // p = (cell q, occupied cell rc of its near columns) at offset o:
-// corr[p][b] = e^{i alpha d W} sum_t W_o[t][b] dens_lambda(b)[rc][t].
+// corr[p][b] = e^{i alpha d wr} sum_t W_o[t][b] dens_lambda(b)[rc][t].
 struct CorrArgs {
   int n_groups, n_bdry, n_bH, n_eq, n_cells, merge_blocks;
   const int* grp_o;      // correction-matrix offset of each group
@@ -816,10 +843,12 @@ struct CorrArgs {
   const int* grp_n;
   const int* plist;      // pair indices, grouped by offset
   const int* grp_rc;     // source cell of each pair, in plist order
-  const cplx* grp_ph;    // quasi-periodic phase of each pair, in plist order
+  const int* grp_wr;     // column wrap (-1, 0, 1) of each pair's source cell, in plist order
   const cplx* W;
   cplx* corr;
   int64_t bcorr, bdens;  // batched launches: corr and dens of batch member blockIdx.y are offset by these
+  const IncParams* inc;  // incidence of member m: inc[m inc_step] (quasi-periodic phase of wrapped pairs)
+  int inc_step;
 };
 constexpr int CORR_PPW = 3;              // pairs per wavefront
 constexpr int CORR_PPB = 4 * CORR_PPW;   // pairs per correction workgroup (all share one matrix W_o)
@@ -881,10 +910,15 @@ __device__ inline void local_corr_group(const CorrArgs& C, const cplx* __restric
 #pragma unroll
     for (int j = 0; j < CORR_PPW; ++j) acc[j] += w * d[j * 2 * ns2 + t];
   }
+  const cplx php = cexp_i(C.inc[blockIdx.y * C.inc_step].alpha_d);
 #pragma unroll
   for (int j = 0; j < CORR_PPW; ++j) {
     const int jj = CORR_PPW * jg + j;
-    if (jj < np) C.corr[(int64_t)C.plist[p0 + jj] * nb + b] = C.grp_ph[p0 + jj] * acc[j];
+    if (jj < np) {
+      const int wr = C.grp_wr[p0 + jj];
+      const cplx v = wr == 0 ? acc[j] : cmul_fixed(wr > 0 ? php : conj(php), acc[j]);
+      C.corr[(int64_t)C.plist[p0 + jj] * nb + b] = v;
+    }
   }
 }
 
@@ -930,7 +964,7 @@ __device__ inline cplx merge_point(const MergeArgs M, const cplx* __restrict__ d
   for (int id = 0; id < 6; ++id) {
     if (!ok[id]) continue;
     cplx v = va[id];
-    if (wr[id] != 0) v = (wr[id] > 0 ? php : phm) * v;
+    if (wr[id] != 0) v = cmul_fixed(wr[id] > 0 ? php : phm, v);
     acc += v;
   }
   return acc * twx;
@@ -944,7 +978,7 @@ __global__ __launch_bounds__(1024) void k_merge_fft(MergeArgs M, const cplx* __r
                                                     FftJob jh, FftJob jv, NearArgs NA, NearFill F) {
   const int nfft = jh.nblocks + jv.nblocks;
   if ((int)blockIdx.x >= nfft) {  // near-field items, four per workgroup
-    near_fill<4>(NA, F.c0 + 4 * ((int)blockIdx.x - nfft), F.c1, F.mu, F.y);
+    near_fill<4>(NA, F.c0 + 4 * ((int)blockIdx.x - nfft), F.c1, F.mu, F.y, F.alpha_d);
     return;
   }
   const bool onH = (int)blockIdx.x < jh.nblocks;
@@ -962,7 +996,9 @@ __global__ __launch_bounds__(1024) void k_merge_fft(MergeArgs M, const cplx* __r
 // grid at + m fb.bout1.
 __global__ __launch_bounds__(1024) void k_merge_fft_batch(MergeArgs M, const cplx* __restrict__ dens,
                                                           const cplx* __restrict__ twH, const cplx* __restrict__ twV,
-                                                          FftJob jh, FftJob jv, FftBatch fb) {
+                                                          FftJob jh, FftJob jv, FftBatch fb,
+                                                          const IncParams* __restrict__ inc, int inc_step,
+                                                          int64_t btw) {
   const bool onH = (int)blockIdx.x < jh.nblocks;
   FftJob J = onH ? jh : jv;
   const int64_t m = blockIdx.y;
@@ -970,8 +1006,8 @@ __global__ __launch_bounds__(1024) void k_merge_fft_batch(MergeArgs M, const cpl
   const cplx* db = dens + m * fb.bin0;
   const int blk = onH ? blockIdx.x : blockIdx.x - jh.nblocks;
   const int nY = onH ? M.nYH : M.nYV;
-  const cplx* tw = onH ? twH : twV;
-  const cplx php = cexp_i(M.alpha_d);
+  const cplx* tw = (onH ? twH : twV) + m * btw;  // the member's twist e^{-i alpha_m x}
+  const cplx php = cexp_i(inc[m * inc_step].alpha_d);
   const MergeArgs Mv = M;
   sesm_fft_block(J, blk, -1, [=](int r, int i) { return merge_point(Mv, db, tw, php, onH, r / nY, r % nY, i); });
 }
@@ -983,6 +1019,7 @@ struct YConvJob {
   const cplx* g;     // source spectra [2][nY][nX]
   cplx* out;         // [nY][nX]
   int64_t bg, bout;  // batched launches: g and out of batch member blockIdx.y are offset by these
+  int64_t bspec;     // and its kernel spectra (incidence sets; 0 when the members share them)
 };
 
 // phi_hat[t][kx] = sum_t' spec0[t-t'+nY-1][kx] g0[t'][kx] + spec1[...] g1[t'][kx].
@@ -1002,7 +1039,7 @@ __global__ __launch_bounds__(256) void k_yconv(YConvJob h, YConvJob v, int hbloc
                                                const cplx* __restrict__ dens, NearArgs NA, NearFill F) {
   extern __shared__ cplx col[];
   if ((int)blockIdx.x >= C.merge_blocks + C.n_groups) {  // near-field items, one per workgroup
-    near_fill<1>(NA, F.c0 + (int)blockIdx.x - C.merge_blocks - C.n_groups, F.c1, F.mu, F.y);
+    near_fill<1>(NA, F.c0 + (int)blockIdx.x - C.merge_blocks - C.n_groups, F.c1, F.mu, F.y, F.alpha_d);
     return;
   }
   if ((int)blockIdx.x >= C.merge_blocks) {  // the local corrections share the launch
@@ -1015,6 +1052,7 @@ __global__ __launch_bounds__(256) void k_yconv(YConvJob h, YConvJob v, int hbloc
   YConvJob J = first ? h : v;
   J.g += (int64_t)blockIdx.y * J.bg;
   J.out += (int64_t)blockIdx.y * J.bout;
+  J.spec += (int64_t)blockIdx.y * J.bspec;
   const int b = first ? blockIdx.x : blockIdx.x - hblocks;
   const int nX = J.nX, nY = J.nY;
   const int nrow = 2 * nY - 1, per = 6 * nY - 2;
@@ -1079,9 +1117,9 @@ __global__ __launch_bounds__(1024) void k_fft_rows_near(FftJob j0, FftJob j1, in
   const int nfft = j0.nblocks + j1.nblocks;
   if ((int)blockIdx.x >= nfft) {
     if (blockDim.x == 1024)
-      near_fill<4>(NA, F.c0 + 4 * ((int)blockIdx.x - nfft), F.c1, F.mu, F.y);
+      near_fill<4>(NA, F.c0 + 4 * ((int)blockIdx.x - nfft), F.c1, F.mu, F.y, F.alpha_d);
     else
-      near_fill<1>(NA, F.c0 + (int)blockIdx.x - nfft, F.c1, F.mu, F.y);
+      near_fill<1>(NA, F.c0 + (int)blockIdx.x - nfft, F.c1, F.mu, F.y, F.alpha_d);
     return;
   }
   const bool first = (int)blockIdx.x < j0.nblocks;
@@ -1122,11 +1160,14 @@ __device__ __forceinline__ void cells_far_body(FarArgs A, KParams K, const int* 
                                                    const cplx* __restrict__ pplw, const double* __restrict__ dirs,
                                                    const double* __restrict__ x, const double* __restrict__ f,
                                                    const cplx* __restrict__ mode_part, cplx* __restrict__ y,
-                                                   cplx* __restrict__ yfar) {
+                                                   cplx* __restrict__ yfar, const IncParams* __restrict__ inc,
+                                                   int inc_step) {
   extern __shared__ cplx dyn[];
   __shared__ cplx bv[64];
   __shared__ cplx wv_sh[64];
   __shared__ cplx msum[SESM_MAX_UETA];
+  // the incidence of this member: Bloch phase of wrapped grid columns and completion modes
+  const IncParams& I = inc[(BATCHED ? (int)blockIdx.y : 0) * inc_step];
   if (BATCHED) {  // batch member blockIdx.y
     const int64_t m = blockIdx.y;
     corr += m * A.bcorr;
@@ -1159,7 +1200,7 @@ __device__ __forceinline__ void cells_far_body(FarArgs A, KParams K, const int* 
     xs[A.max_q + t] = f[i];
   }
   if (wv == 1) {
-    for (int t = 0; t < K.nU; ++t) {
+    for (int t = 0; t < I.nU; ++t) {
       cplx a = cplx{0.0, 0.0};
       for (int c = lane; c < NCH_MODES; c += 64) a += mode_part[(int64_t)t * NCH_MODES + c];
       a = wave_sum(a);
@@ -1174,13 +1215,13 @@ __device__ __forceinline__ void cells_far_body(FarArgs A, KParams K, const int* 
       int gx = cx * A.n_s + i, Wr = 0;
       if (gx >= A.nXH) { gx -= A.nXH; Wr = 1; }
       val = phH[(int64_t)(cy + iy) * A.nXH + gx];
-      if (Wr) val = cexp_i(A.alpha_d) * val;
+      if (Wr) val = cmul_fixed(cexp_i(I.alpha_d), val);
     } else {
       const int t = b - A.n_bH, ix = t / (A.n_s - 1), i = 1 + t % (A.n_s - 1);
       int gx = cx + ix, Wr = 0;
       if (gx >= A.nXV) { gx -= A.nXV; Wr = 1; }
       val = phV[(int64_t)(cy * A.n_s + i + A.n_e) * A.nXV + gx];
-      if (Wr) val = cexp_i(A.alpha_d) * val;
+      if (Wr) val = cmul_fixed(cexp_i(I.alpha_d), val);
     }
     cplx cs = cplx{0.0, 0.0};
     const int p0 = pair_off[q], p1 = pair_off[q + 1];
@@ -1269,9 +1310,9 @@ __device__ __forceinline__ void cells_far_body(FarArgs A, KParams K, const int* 
     const int i = node[t];
     const cplx v = ys[t];
     cplx md = cplx{0.0, 0.0};
-    for (int n = 0; n < K.nU; ++n) {
-      const double mag = exp(-K.Ubi[n] * xs[A.max_q + t]);
-      md += (mag * cexp_i(K.Ua[n] * xs[t] + K.Ubr[n] * xs[A.max_q + t])) * msum[n];
+    for (int n = 0; n < I.nU; ++n) {
+      const double mag = exp(-I.Ubi[n] * xs[A.max_q + t]);
+      md += (mag * cexp_i(I.Ua[n] * xs[t] + I.Ubr[n] * xs[A.max_q + t])) * msum[n];
     }
     y[i] += v + md;
     if (yfar) yfar[i] = v;
@@ -1283,13 +1324,16 @@ __device__ __forceinline__ void cells_far_body(FarArgs A, KParams K, const int* 
       const int *__restrict__ perm, const int *__restrict__ pair_off, const cplx *__restrict__ corr,              \
       const cplx *__restrict__ phH, const cplx *__restrict__ phV, const cplx *__restrict__ pplw,                 \
       const double *__restrict__ dirs, const double *__restrict__ x, const double *__restrict__ f,               \
-      const cplx *__restrict__ mode_part, cplx *__restrict__ y, cplx *__restrict__ yfar
+      const cplx *__restrict__ mode_part, cplx *__restrict__ y, cplx *__restrict__ yfar,                           \
+      const IncParams *__restrict__ inc, int inc_step
 __global__ __launch_bounds__(256) void k_cells_far(SESM_CELLS_FAR_PARAMS) {
-  cells_far_body<false>(A, K, occ_cell, occ_off, perm, pair_off, corr, phH, phV, pplw, dirs, x, f, mode_part, y, yfar);
+  cells_far_body<false>(A, K, occ_cell, occ_off, perm, pair_off, corr, phH, phV, pplw, dirs, x, f, mode_part, y, yfar,
+                        inc, inc_step);
 }
 // grid dimension y: batch members (offsets in A)
 __global__ __launch_bounds__(256) void k_cells_far_batch(SESM_CELLS_FAR_PARAMS) {
-  cells_far_body<true>(A, K, occ_cell, occ_off, perm, pair_off, corr, phH, phV, pplw, dirs, x, f, mode_part, y, yfar);
+  cells_far_body<true>(A, K, occ_cell, occ_off, perm, pair_off, corr, phH, phV, pplw, dirs, x, f, mode_part, y, yfar,
+                       inc, inc_step);
 }
 #undef SESM_CELLS_FAR_PARAMS
 
@@ -1337,6 +1381,55 @@ int fft_launch(sesm_ctx* ctx, hipStream_t st, const FftJob& j0, const FftJob& j1
     hipLaunchKernelGGL(k_fft_rows, dim3(nb), dim3(wide ? 1024 : 256), 0, st, j0, j1, sign);
   SESM_LAUNCH_CHECK();
   return SESM_OK;
+}
+
+// The windowed lattice-sum tables (eq. Gq_limit with the Bloch phase of K.alpha)
+// of both grids, twisted and transformed along x, into spec = [specH | specV].
+int build_spectra(sesm_ctx* ctx, const KParams& K, cplx* spec) {
+  AccelOp* A = ctx->acc;
+  const int pmax = (int)std::ceil(K.A_len / K.d) + 2;
+  int rc;
+  for (int lam = 0; lam < 2; ++lam) {
+    const int nX = lam == 0 ? A->nXH : A->nXV, nY = lam == 0 ? A->nYH : A->nYV;
+    const double hxs = lam == 0 ? A->delta : A->L, hys = lam == 0 ? A->L : A->delta;
+    const int nrows = 2 * nY - 1;
+    cplx* sp = spec + (lam == 0 ? 0 : (int64_t)2 * (2 * A->nYH - 1) * A->nXH);
+    const int64_t ent = (int64_t)nrows * nX;
+    hipLaunchKernelGGL(k_lattice, dim3((unsigned)((ent + 3) / 4)), dim3(256), 0, ctx->stream, K, lam, nX, nY, hxs,
+                       hys, pmax, sp);
+    SESM_LAUNCH_CHECK();
+    const FftJob J = sesm_fft_job(lam == 0 ? A->planH : A->planV, 2 * nrows, sp, sp, nullptr, nullptr, 1.0);
+    if ((rc = fft_launch(ctx, ctx->stream, J, FftJob{}, -1))) return rc;
+  }
+  return SESM_OK;
+}
+
+// [e^{-i alpha x} on the H grid | on the V grid | e^{+i alpha x} on H | on V]
+void twist_tables(const AccelOp* A, double alpha, std::vector<cplx>& tw) {
+  tw.assign((size_t)A->tw_len, cplx{0.0, 0.0});
+  for (int t = 0; t < A->nXH; ++t) {
+    const double ph = alpha * t * A->delta;
+    tw[t] = cplx{std::cos(ph), -std::sin(ph)};
+    tw[A->nXH + A->nXV + t] = cplx{std::cos(ph), std::sin(ph)};
+  }
+  for (int t = 0; t < A->nXV; ++t) {
+    const double ph = alpha * t * A->L;
+    tw[A->nXH + t] = cplx{std::cos(ph), -std::sin(ph)};
+    tw[2 * A->nXH + A->nXV + t] = cplx{std::cos(ph), std::sin(ph)};
+  }
+}
+
+IncParams inc_record(const Problem& P) {
+  IncParams I{};
+  I.alpha = P.alpha;
+  I.alpha_d = P.alpha * P.d;
+  I.nU = P.nU;
+  for (int t = 0; t < P.nU; ++t) {
+    I.Ua[t] = P.Ua[t];
+    I.Ubr[t] = P.Ubr[t];
+    I.Ubi[t] = P.Ubi[t];
+  }
+  return I;
 }
 
 }  // namespace
@@ -1500,8 +1593,7 @@ int sesm_accel_setup(sesm_ctx* ctx) {
   // quasi-periodic phase of a wrapped column
   {
     const int nrowoff = 2 * A->n_y - 1;
-    std::vector<int> pair_off(1, 0), pair_o, pair_rc;
-    std::vector<cplx> pair_ph;
+    std::vector<int> pair_off(1, 0), pair_o, pair_rc, pair_wr;
     for (int q = 0; q < A->n_occ; ++q) {
       const int cx = occ_cell[q] % A->n_x, cy = occ_cell[q] / A->n_x;
       for (int dc = -R; dc <= R; ++dc)
@@ -1513,8 +1605,7 @@ int sesm_accel_setup(sesm_ctx* ctx) {
           if (!occ_flag[rcell]) continue;
           pair_o.push_back((dc + R) * nrowoff + (ry - cy + A->n_y - 1));
           pair_rc.push_back(rcell);
-          const C ph = std::exp(C(0.0, P.alpha * P.d * Wr));
-          pair_ph.push_back(cplx{ph.real(), ph.imag()});
+          pair_wr.push_back(Wr);
         }
       pair_off.push_back((int)pair_o.size());
     }
@@ -1532,14 +1623,13 @@ int sesm_accel_setup(sesm_ctx* ctx) {
         for (int j = 0; j < n; ++j) plist.push_back(by_o[o][j0 + j]);
       }
     A->n_groups = (int)grp_o.size();
-    std::vector<int> grp_rc(plist.size());
-    std::vector<cplx> grp_ph(plist.size());
+    std::vector<int> grp_rc(plist.size()), grp_wr(plist.size());
     for (size_t i = 0; i < plist.size(); ++i) {
       grp_rc[i] = pair_rc[plist[i]];
-      grp_ph[i] = pair_ph[plist[i]];
+      grp_wr[i] = pair_wr[plist[i]];
     }
     if ((rc = upload(ctx, &A->pair_off, pair_off)) || (rc = upload(ctx, &A->grp_rc, grp_rc)) ||
-        (rc = upload(ctx, &A->grp_ph, grp_ph)) || (rc = upload(ctx, &A->grp_o, grp_o)) ||
+        (rc = upload(ctx, &A->grp_wr, grp_wr)) || (rc = upload(ctx, &A->grp_o, grp_o)) ||
         (rc = upload(ctx, &A->grp_start, grp_start)) || (rc = upload(ctx, &A->grp_n, grp_n)) ||
         (rc = upload(ctx, &A->plist, plist)) ||
         (rc = sesm_alloc(ctx, (void**)&A->corr, sizeof(cplx) * (size_t)std::max(1, A->n_pairs) * A->n_bdry)))
@@ -1576,20 +1666,12 @@ int sesm_accel_setup(sesm_ctx* ctx) {
     }
     if ((rc = upload(ctx, &pl->tw, tw))) return rc;
   }
-  const int pmax = (int)std::ceil(P.A_len / P.d) + 2;
-  for (int lam = 0; lam < 2; ++lam) {
-    const int nX = lam == 0 ? A->nXH : A->nXV, nY = lam == 0 ? A->nYH : A->nYV;
-    const double hxs = lam == 0 ? A->delta : A->L, hys = lam == 0 ? A->L : A->delta;
-    const int nrows = 2 * nY - 1;
-    cplx*& spec = lam == 0 ? A->specH : A->specV;
-    if ((rc = sesm_alloc(ctx, (void**)&spec, sizeof(cplx) * (size_t)2 * nrows * nX))) return rc;
-    const int64_t ent = (int64_t)nrows * nX;
-    hipLaunchKernelGGL(k_lattice, dim3((unsigned)((ent + 3) / 4)), dim3(256), 0, ctx->stream, K, lam, nX, nY, hxs,
-                       hys, pmax, spec);
-    SESM_LAUNCH_CHECK();
-    const FftJob J = sesm_fft_job(lam == 0 ? A->planH : A->planV, 2 * nrows, spec, spec, nullptr, nullptr, 1.0);
-    if ((rc = fft_launch(ctx, ctx->stream, J, FftJob{}, -1))) return rc;
-  }
+  A->spec_len = (int64_t)2 * (2 * A->nYH - 1) * A->nXH + (int64_t)2 * (2 * A->nYV - 1) * A->nXV;
+  A->tw_len = (int64_t)2 * (A->nXH + A->nXV);
+  if ((rc = sesm_alloc(ctx, (void**)&A->self_spec, sizeof(cplx) * (size_t)A->spec_len))) return rc;
+  A->specH = A->self_spec;
+  A->specV = A->self_spec + (int64_t)2 * (2 * A->nYH - 1) * A->nXH;
+  if ((rc = build_spectra(ctx, K, A->self_spec))) return rc;
   // --- local correction matrices
   A->n_off = (2 * A->ring + 1) * (2 * A->n_y - 1);
   {
@@ -1652,21 +1734,18 @@ int sesm_accel_setup(sesm_ctx* ctx) {
   hipLaunchKernelGGL(k_p2e_setup, dim3(A->n_chunks), dim3(256), sizeof(cplx) * 4 * nrow, ctx->stream, K, G,
                      A->x0, A->y0, A->n_x, A->chunk_q, A->chunk_t0, NEAR_ROWS, A->occ_cell, A->occ_off, A->perm, ctx->x, ctx->f, ctx->fp, A->pinv, A->p2e);
   SESM_LAUNCH_CHECK();
-  // --- twist factors of the global grids
-  std::vector<cplx> twxH(A->nXH), twxV(A->nXV), utwH(A->nXH), utwV(A->nXV);
-  for (int t = 0; t < A->nXH; ++t) {
-    const double ph = P.alpha * t * A->delta;
-    twxH[t] = cplx{std::cos(ph), -std::sin(ph)};
-    utwH[t] = cplx{std::cos(ph), std::sin(ph)};
+  // --- twist factors of the global grids, and the incidence record
+  {
+    std::vector<cplx> tw;
+    twist_tables(A, P.alpha, tw);
+    if ((rc = upload(ctx, &A->self_tw, tw))) return rc;
+    A->twxH = A->self_tw;
+    A->twxV = A->self_tw + A->nXH;
+    A->utwH = A->self_tw + A->nXH + A->nXV;
+    A->utwV = A->self_tw + 2 * A->nXH + A->nXV;
+    std::vector<IncParams> ip(1, inc_record(P));
+    if ((rc = upload(ctx, &A->inc_self, ip))) return rc;
   }
-  for (int t = 0; t < A->nXV; ++t) {
-    const double ph = P.alpha * t * A->L;
-    twxV[t] = cplx{std::cos(ph), -std::sin(ph)};
-    utwV[t] = cplx{std::cos(ph), std::sin(ph)};
-  }
-  if ((rc = upload(ctx, &A->twxH, twxH)) || (rc = upload(ctx, &A->twxV, twxV)) || (rc = upload(ctx, &A->utwH, utwH)) ||
-      (rc = upload(ctx, &A->utwV, utwV)))
-    return rc;
   // --- plane waves: d_s = (sin 2 pi s / n_plw, cos 2 pi s / n_plw), s = 1..n_plw (eq. plwave_QR)
   {
     std::vector<double> dirs(2 * A->n_plw);
@@ -1829,7 +1908,28 @@ struct FarBufs {
   const cplx *dens, *mode;
   cplx *fH, *fV, *gH, *gV, *phH, *phV, *corr, *y;
   int64_t bdens, bmode, bfH, bfV, bgH, bgV, bphH, bphV, bcorr, by;
+  // incidence of member m: inc[m inc_step], spectra spec + m bspec, twist
+  // factors tw + m btw (the tables' layout of AccelOp); alpha_d0 = alpha d of member 0
+  const IncParams* inc;
+  int inc_step;
+  const cplx* spec;
+  int64_t bspec;
+  const cplx* tw;
+  int64_t btw;
+  double alpha_d0;
 };
+
+// the tables of the surface's own incidence, shared by every member
+static void own_incidence(const sesm_ctx* ctx, FarBufs& Fb) {
+  const AccelOp* A = ctx->acc;
+  Fb.inc = A->inc_self;
+  Fb.inc_step = 0;
+  Fb.spec = A->self_spec;
+  Fb.bspec = 0;
+  Fb.tw = A->self_tw;
+  Fb.btw = 0;
+  Fb.alpha_d0 = ctx->P.alpha * ctx->P.d;
+}
 
 // The stages after the local launch: merge + forward FFT, y convolution +
 // local corrections, inverse FFT, and the cell far field added to y, each one
@@ -1848,38 +1948,44 @@ static int accel_far_stages(sesm_ctx* ctx, const FarBufs& Fb, bool keep_far, con
   const int nb = Fb.nb;
   int rc;
   const NearArgs NA = near_args_host(ctx);
-  NearFill fm{0, 0, nullptr, nullptr}, fy = fm, ff = fm;
+  NearFill fm{0, 0, nullptr, nullptr, 0.0}, fy = fm, ff = fm;
   if (fill_mu && nb == 1) {
-    fm = NearFill{A->near_c1, A->near_c2, fill_mu, Fb.y};
-    fy = NearFill{A->near_c2, A->near_c3, fill_mu, Fb.y};
-    ff = NearFill{A->near_c3, A->n_chunks, fill_mu, Fb.y};
+    fm = NearFill{A->near_c1, A->near_c2, fill_mu, Fb.y, Fb.alpha_d0};
+    fy = NearFill{A->near_c2, A->near_c3, fill_mu, Fb.y, Fb.alpha_d0};
+    ff = NearFill{A->near_c3, A->n_chunks, fill_mu, Fb.y, Fb.alpha_d0};
   }
   MergeArgs M{A->n_x, A->n_y, A->n_s, A->n_e, A->n_side, A->n_eq, A->n_cells,
-              A->nXH, A->nYH, A->nXV, A->nYV, P.alpha * P.d};
+              A->nXH, A->nYH, A->nXV, A->nYV, Fb.alpha_d0};
+  const cplx* twH = Fb.tw;                              // e^{-i alpha x}, H grid (member 0)
+  const cplx* twV = Fb.tw + A->nXH;                     //                V grid
+  const cplx* utH = Fb.tw + A->nXH + A->nXV;            // e^{+i alpha x}, H grid
+  const cplx* utV = Fb.tw + 2 * A->nXH + A->nXV;        //                V grid
+  const cplx* spH = Fb.spec;
+  const cplx* spV = Fb.spec + (int64_t)2 * (2 * A->nYH - 1) * A->nXH;
   // merge + forward FFT along x of both grids (rows [kind][gy])
   SESM_KT_BEGIN(SESM_KT_MERGE, st);
   {
     const FftJob jh = sesm_fft_job(A->planH, 2 * A->nYH, nullptr, Fb.fH, nullptr, nullptr, 1.0);
     const FftJob jv = sesm_fft_job(A->planV, 2 * A->nYV, nullptr, Fb.fV, nullptr, nullptr, 1.0);
     if (nb > 1)
-      hipLaunchKernelGGL(k_merge_fft_batch, dim3(jh.nblocks + jv.nblocks, nb), dim3(1024), 0, st, M, Fb.dens,
-                         A->twxH, A->twxV, jh, jv, FftBatch{Fb.bdens, Fb.bfH, 0, Fb.bfV});
+      hipLaunchKernelGGL(k_merge_fft_batch, dim3(jh.nblocks + jv.nblocks, nb), dim3(1024), 0, st, M, Fb.dens, twH,
+                         twV, jh, jv, FftBatch{Fb.bdens, Fb.bfH, 0, Fb.bfV, 0, 0}, Fb.inc, Fb.inc_step, Fb.btw);
     else
       hipLaunchKernelGGL(k_merge_fft, dim3(jh.nblocks + jv.nblocks + (fm.c1 - fm.c0 + 3) / 4), dim3(1024), 0, st, M,
-                         Fb.dens, A->twxH, A->twxV, jh, jv, NA, fm);
+                         Fb.dens, twH, twV, jh, jv, NA, fm);
     SESM_LAUNCH_CHECK();
   }
   SESM_KT_END(SESM_KT_MERGE, st, nb * B.merge);
   // y convolution of both grids, with the local corrections in the same launch
   SESM_KT_BEGIN(SESM_KT_YCONV, st);
   {
-    const YConvJob yh{A->nXH, A->nYH, A->specH, Fb.fH, Fb.gH, Fb.bfH, Fb.bgH};
-    const YConvJob yv{A->nXV, A->nYV, A->specV, Fb.fV, Fb.gV, Fb.bfV, Fb.bgV};
+    const YConvJob yh{A->nXH, A->nYH, spH, Fb.fH, Fb.gH, Fb.bfH, Fb.bgH, Fb.bspec};
+    const YConvJob yv{A->nXV, A->nYV, spV, Fb.fV, Fb.gV, Fb.bfV, Fb.bgV, Fb.bspec};
     const int hb = (A->nXH + yconv_kpb(A->nYH) - 1) / yconv_kpb(A->nYH);
     const int vb = (A->nXV + yconv_kpb(A->nYV) - 1) / yconv_kpb(A->nYV);
     const CorrArgs CA{A->n_groups, A->n_bdry, A->n_bH,   A->n_eq,   A->n_cells, hb + vb,  A->grp_o,
-                      A->grp_start, A->grp_n, A->plist, A->grp_rc, A->grp_ph, A->W,      Fb.corr,
-                      Fb.bcorr,     Fb.bdens};
+                      A->grp_start, A->grp_n, A->plist, A->grp_rc, A->grp_wr, A->W,      Fb.corr,
+                      Fb.bcorr,     Fb.bdens,  Fb.inc,   Fb.inc_step};
     const size_t lds = std::max(std::max(yconv_lds(A->nYH), yconv_lds(A->nYV)), corr_lds(A->n_eq, A->n_bdry));
     hipLaunchKernelGGL(k_yconv, dim3(hb + vb + A->n_groups + (fy.c1 - fy.c0), nb), dim3(256), lds, st, yh, yv, hb,
                        CA, Fb.dens, NA, fy);
@@ -1888,15 +1994,15 @@ static int accel_far_stages(sesm_ctx* ctx, const FarBufs& Fb, bool keep_far, con
   SESM_KT_END(SESM_KT_YCONV, st, nb * (B.yconvH + B.yconvV));
   SESM_KT_BEGIN(SESM_KT_FFT, st);
   {
-    const FftJob jh = sesm_fft_job(A->planH, A->nYH, Fb.gH, Fb.phH, nullptr, A->utwH, 1.0 / A->nXH);
-    const FftJob jv = sesm_fft_job(A->planV, A->nYV, Fb.gV, Fb.phV, nullptr, A->utwV, 1.0 / A->nXV);
+    const FftJob jh = sesm_fft_job(A->planH, A->nYH, Fb.gH, Fb.phH, nullptr, utH, 1.0 / A->nXH);
+    const FftJob jv = sesm_fft_job(A->planV, A->nYV, Fb.gV, Fb.phV, nullptr, utV, 1.0 / A->nXV);
     if (ff.c1 > ff.c0) {  // one density with near-field items: the carrying variant
       const bool wide = (jh.nblocks && jh.A.n * jh.rpb >= 1000) || (jv.nblocks && jv.A.n * jv.rpb >= 1000);
       const int per = wide ? 4 : 1, nfill = (ff.c1 - ff.c0 + per - 1) / per;
       hipLaunchKernelGGL(k_fft_rows_near, dim3(jh.nblocks + jv.nblocks + nfill), dim3(wide ? 1024 : 256), 0, st, jh,
                          jv, +1, NA, ff);
       SESM_LAUNCH_CHECK();
-    } else if ((rc = fft_launch(ctx, st, jh, jv, +1, nb, FftBatch{Fb.bgH, Fb.bphH, Fb.bgV, Fb.bphV}))) {
+    } else if ((rc = fft_launch(ctx, st, jh, jv, +1, nb, FftBatch{Fb.bgH, Fb.bphH, Fb.bgV, Fb.bphV, Fb.btw, Fb.btw}))) {
       return rc;
     }
   }
@@ -1907,14 +2013,14 @@ static int accel_far_stages(sesm_ctx* ctx, const FarBufs& Fb, bool keep_far, con
   const bool items = nb == 1;
   const int mq = items ? std::min(A->max_q, CF_NODES) : A->max_q;
   FarArgs F{P.N,    A->n_x,   A->n_y,   A->n_s,    A->n_e, A->n_side, A->n_eq, A->n_cells, A->n_bdry, A->n_bH,
-            A->n_plw, A->nXH, A->nXV,   A->ring,   mq,     A->L,   A->x0,     A->y0,   P.k,        P.alpha * P.d,
+            A->n_plw, A->nXH, A->nXV,   A->ring,   mq,     A->L,   A->x0,     A->y0,   P.k,        Fb.alpha_d0,
             Fb.bcorr, Fb.bphH, Fb.bphV, Fb.bmode, Fb.by, items ? A->cfc_q : nullptr, items ? A->cfc_t0 : nullptr,
             keep_far ? A->bq : nullptr};
   SESM_KT_BEGIN(SESM_KT_CELLS, st);
   hipLaunchKernelGGL(nb > 1 ? k_cells_far_batch : k_cells_far, dim3(items ? A->n_cfc : A->n_occ, nb), dim3(256),
                      cells_far_lds(A, mq), st, F, K, A->occ_cell,
                      A->occ_off, A->perm, A->pair_off, Fb.corr, Fb.phH, Fb.phV, A->pplw, A->dirs, ctx->x, ctx->f,
-                     Fb.mode, Fb.y, keep_far ? A->yfar : nullptr);
+                     Fb.mode, Fb.y, keep_far ? A->yfar : nullptr, Fb.inc, nb > 1 ? Fb.inc_step : 0);
   SESM_LAUNCH_CHECK();
   SESM_KT_END(SESM_KT_CELLS, st, nb * B.cells);
   return SESM_OK;
@@ -1929,7 +2035,7 @@ static int accel_matvec_impl(sesm_ctx* ctx, const cplx* mu, cplx* y, bool keep_f
   L.n_chunks = A->near_c1;  // the other near-field items ride on the grid stages
   SESM_KT_BEGIN(SESM_KT_LOCAL, st);
   hipLaunchKernelGGL(k_local_apply, dim3(L.n_occ + L.n_mode_blocks + L.n_chunks), dim3(LOC_NT), 0, st, K, L, mu,
-                     y);
+                     y, A->inc_self);
   SESM_LAUNCH_CHECK();
   SESM_KT_END(SESM_KT_LOCAL, st, B.local);
   FarBufs Fb{};
@@ -1944,22 +2050,25 @@ static int accel_matvec_impl(sesm_ctx* ctx, const cplx* mu, cplx* y, bool keep_f
   Fb.phV = A->phV;
   Fb.corr = A->corr;
   Fb.y = y;
+  own_incidence(ctx, Fb);
   return accel_far_stages(ctx, Fb, keep_far, B, mu);
 }
 
 template <int NB>
 static void launch_local_batch(hipStream_t st, const KParams& K, const LocalArgs& L, const cplx* mu, int64_t ldm,
-                               cplx* y, int64_t ldy) {
+                               cplx* y, int64_t ldy, const IncParams* inc, int inc_step) {
   hipLaunchKernelGGL(k_local_apply_batch<NB>, dim3(L.n_occ + L.n_mode_blocks + L.n_chunks), dim3(LOC_NT), 0, st, K,
-                     L, mu, ldm, y, ldy);
+                     L, mu, ldm, y, ldy, inc, inc_step);
 }
 
 // Forward maps of nrhs densities (column r at mu + r ldm, output at y + r ldy)
 // in groups of up to kBatchMax densities: one local launch per group reads the
 // near-field blocks and P once for the group, and each later stage is one
 // launch for the group.
-int sesm_accel_matvec_batch(sesm_ctx* ctx, int nrhs, const cplx* mu, int64_t ldm, cplx* y, int64_t ldy) {
+int sesm_accel_matvec_batch(sesm_ctx* ctx, int nrhs, const cplx* mu, int64_t ldm, cplx* y, int64_t ldy, int inc0) {
   AccelOp* A = ctx->acc;
+  if (inc0 >= 0 && (inc0 + nrhs > A->n_inc || !A->inc_set))
+    return ctx->fail(SESM_EINVAL, "incidence index beyond the incidence set");
   const KParams K = ctx->kparams();
   hipStream_t st = ctx->stream;
   const size_t nH = (size_t)A->nXH * A->nYH, nV = (size_t)A->nXV * A->nYV;
@@ -2013,11 +2122,26 @@ int sesm_accel_matvec_batch(sesm_ctx* ctx, int nrhs, const cplx* mu, int64_t ldm
     const int nb = std::min(kBatchMax, nrhs - r0);
     const cplx* m0 = mu + r0 * ldm;
     cplx* y0 = y + r0 * ldy;
+    if (inc0 < 0) {  // one operator for all: the surface's own incidence
+      own_incidence(ctx, Fb);
+    } else {         // densities r0.. with members inc0 + r0.. of the incidence set
+      const int i0 = inc0 + r0;
+      Fb.inc = A->inc_set + i0;
+      Fb.inc_step = 1;
+      Fb.spec = A->inc_spec + (int64_t)i0 * A->spec_len;
+      Fb.bspec = A->spec_len;
+      Fb.tw = A->inc_tw + (int64_t)i0 * A->tw_len;
+      Fb.btw = A->tw_len;
+      Fb.alpha_d0 = A->inc_prob[i0].alpha * ctx->P.d;
+      bool modes = false;
+      for (int r = 0; r < nb; ++r) modes = modes || A->inc_prob[i0 + r].nU > 0;
+      L.n_mode_blocks = modes ? NCH_MODES : 0;
+    }
     switch (nb) {
-      case 1: launch_local_batch<1>(st, K, L, m0, ldm, y0, ldy); break;
-      case 2: launch_local_batch<2>(st, K, L, m0, ldm, y0, ldy); break;
-      case 3: launch_local_batch<3>(st, K, L, m0, ldm, y0, ldy); break;
-      default: launch_local_batch<4>(st, K, L, m0, ldm, y0, ldy); break;
+      case 1: launch_local_batch<1>(st, K, L, m0, ldm, y0, ldy, Fb.inc, Fb.inc_step); break;
+      case 2: launch_local_batch<2>(st, K, L, m0, ldm, y0, ldy, Fb.inc, Fb.inc_step); break;
+      case 3: launch_local_batch<3>(st, K, L, m0, ldm, y0, ldy, Fb.inc, Fb.inc_step); break;
+      default: launch_local_batch<4>(st, K, L, m0, ldm, y0, ldy, Fb.inc, Fb.inc_step); break;
     }
     SESM_LAUNCH_CHECK();
     Fb.nb = nb;
@@ -2028,6 +2152,72 @@ int sesm_accel_matvec_batch(sesm_ctx* ctx, int nrhs, const cplx* mu, int64_t ldm
 }
 
 int sesm_accel_matvec(sesm_ctx* ctx, const cplx* mu, cplx* y) { return accel_matvec_impl(ctx, mu, y, false); }
+
+// give a block allocated with sesm_alloc back to the context's pool
+static void accel_release(sesm_ctx* ctx, void* p) {
+  if (!p) return;
+  for (size_t t = 0; t < ctx->owned.size(); ++t)
+    if (ctx->owned[t].first == p) {
+      ctx->bytes -= (int64_t)ctx->owned[t].second;
+      sesm_pool_put(ctx, p, ctx->owned[t].second);
+      ctx->owned.erase(ctx->owned.begin() + t);
+      return;
+    }
+}
+
+// The incidence set: for every alpha_r, the problem's incidence-dependent
+// scalars (completion set U^eta of eq. M_eta, propagating orders), the
+// kernel spectra of the windowed lattice sums with the Bloch phase
+// e^{-i alpha_r d p} (eq. Gq_limit), the twist factors and the device record.
+// Everything else of the operator (near-field blocks, EqSources operators,
+// local-correction matrices, plane-wave factors) does not depend on alpha
+// and is shared.
+int sesm_accel_set_incidences(sesm_ctx* ctx, int n, const double* alpha) {
+  AccelOp* A = ctx->acc;
+  const Problem& P = ctx->P;
+  for (int r = 0; r < n; ++r)
+    if (!std::isfinite(alpha[r]) || !(std::fabs(alpha[r]) < P.k))
+      return ctx->fail(SESM_EINVAL, "incidence set: need |alpha| < k for every member");
+  std::vector<Problem> probs(n, P);
+  std::vector<IncParams> recs(n);
+  for (int r = 0; r < n; ++r) {
+    if (!sesm_problem_alpha(probs[r], alpha[r], P.eta))
+      return ctx->fail(SESM_EINVAL, "incidence set: more than 64 completion modes; lower eta");
+    recs[r] = inc_record(probs[r]);
+  }
+  SESM_HIP(hipStreamSynchronize(ctx->stream));
+  accel_release(ctx, A->inc_set);
+  accel_release(ctx, A->inc_spec);
+  accel_release(ctx, A->inc_tw);
+  A->inc_set = nullptr;
+  A->inc_spec = A->inc_tw = nullptr;
+  A->n_inc = 0;
+  A->inc_prob.clear();
+  if (n == 0) return SESM_OK;
+  int rc;
+  if ((rc = upload(ctx, &A->inc_set, recs))) return rc;
+  if ((rc = sesm_alloc(ctx, (void**)&A->inc_spec, sizeof(cplx) * (size_t)n * A->spec_len))) return rc;
+  std::vector<cplx> tw_all((size_t)n * A->tw_len), tw;
+  for (int r = 0; r < n; ++r) {
+    KParams K = ctx->kparams();
+    K.alpha = alpha[r];
+    if ((rc = build_spectra(ctx, K, A->inc_spec + (int64_t)r * A->spec_len))) return rc;
+    twist_tables(A, alpha[r], tw);
+    std::copy(tw.begin(), tw.end(), tw_all.begin() + (int64_t)r * A->tw_len);
+  }
+  if ((rc = upload(ctx, &A->inc_tw, tw_all))) return rc;
+  SESM_HIP(hipStreamSynchronize(ctx->stream));
+  A->inc_prob = std::move(probs);
+  A->n_inc = n;
+  return SESM_OK;
+}
+
+int sesm_accel_n_incidences(const sesm_ctx* ctx) { return ctx->acc ? ctx->acc->n_inc : 0; }
+
+const Problem* sesm_accel_incidence(const sesm_ctx* ctx, int r) {
+  const AccelOp* A = ctx->acc;
+  return (A && r >= 0 && r < A->n_inc) ? &A->inc_prob[r] : nullptr;
+}
 
 // Where the near-field items of a single-density forward map run (see
 // AccelOp::near_c1).  The tuner times candidate splits on the device and keeps
@@ -2214,7 +2404,7 @@ extern "C" int sesm_diag_near(sesm_ctx* ctx, const sesm_c64* mu, sesm_c64* y) {
   AccelOp* A = ctx->acc;
   const LocalArgs L = local_args(ctx, true);
   hipLaunchKernelGGL(k_local_apply, dim3(L.n_chunks), dim3(LOC_NT), 0, ctx->stream, ctx->kparams(), L,
-                     (const cplx*)mu, (cplx*)y);
+                     (const cplx*)mu, (cplx*)y, A->inc_self);
   SESM_LAUNCH_CHECK();
   return SESM_OK;
 }

@@ -117,6 +117,55 @@ std::complex<double> shift_quotient(std::complex<double> b, double h, int j) {
 
 }  // namespace
 
+// The incidence-dependent scalars of a problem whose d, k, j and h are set:
+// alpha, beta, the completion set U^eta with its alpha_n, beta_n, and the
+// propagating orders.  False if U^eta has more than SESM_MAX_UETA members.
+bool sesm_problem_alpha(Problem& P, double alpha, double eta) {
+  const double d = P.d, k = P.k, h = P.h;
+  const int j = P.j;
+  P.alpha = alpha;
+  P.beta = std::sqrt(std::max(0.0, k * k - alpha * alpha));
+  // U^eta = {n : |1 - e^{i beta_n h}|^j < eta} (eq. M_eta).  The printed set, with the
+  // factor 1/beta_n, is infinite (the quotient tends to zero for evanescent
+  // orders); on a flat surface 1/2 I + D~ has the eigenvalue (1/2)(1 - e^{i beta_n h})^j
+  // on e^{i alpha_n x}, so the orders where that factor is small are the ones
+  // the completion modes must restore.
+  P.nU = 0;
+  if (j > 0) {
+    const double t = std::pow(eta, 1.0 / j);
+    const double kmax = -std::log(1.0 - std::min(t, 0.999999)) / h + 1.0;
+    const double K = std::sqrt(k * k + kmax * kmax);
+    const int nlo = (int)std::floor((-K - alpha) * d / (2 * PI)) - 1;
+    const int nhi = (int)std::ceil((K - alpha) * d / (2 * PI)) + 1;
+    for (int n = nlo; n <= nhi; ++n) {
+      const double an = alpha + 2.0 * PI * n / d;
+      const std::complex<double> b = beta_of(k, an);
+      const double fac = std::pow(std::abs(1.0 - std::exp(std::complex<double>(0.0, 1.0) * b * h)), j);
+      if (fac < eta) {
+        if (P.nU >= SESM_MAX_UETA) return false;
+        P.U[P.nU] = n;
+        P.Ua[P.nU] = an;
+        P.Ubr[P.nU] = b.real();
+        P.Ubi[P.nU] = b.imag();
+        ++P.nU;
+      }
+    }
+  }
+  const int nlo = (int)std::floor((-k - alpha) * d / (2 * PI)) - 1;
+  const int nhi = (int)std::ceil((k - alpha) * d / (2 * PI)) + 1;
+  int first = 0, count = 0;
+  for (int n = nlo; n <= nhi; ++n) {
+    const double an = alpha + 2.0 * PI * n / d;
+    if (k * k - an * an > 0) {
+      if (count == 0) first = n;
+      ++count;
+    }
+  }
+  P.n_first = first;
+  P.n_count = count;
+  return true;
+}
+
 // keeps released blocks for the next surface up to this many bytes
 static constexpr size_t kPoolLimit = (size_t)16 << 30;
 
@@ -284,6 +333,20 @@ int sesm_apply(sesm_ctx* ctx, const cplx* mu, cplx* y) {
   return sesm_dense_matvec(ctx, mu, y);
 }
 
+int sesm_apply_inc(sesm_ctx* ctx, const cplx* mu, cplx* y, int inc) {
+  if (inc < 0) return sesm_apply(ctx, mu, y);
+  return sesm_accel_matvec_batch(ctx, 1, mu, ctx->P.N, y, ctx->P.N, inc);
+}
+
+// checks shared by the incidence-set entry points
+static int incidence_ready(sesm_ctx* ctx, int r0, int n) {
+  if (!ctx->ready) return ctx->fail(SESM_ENOSURF, "no surface");
+  if (ctx->P.mode != SESM_MODE_ACCEL) return ctx->fail(SESM_EINVAL, "incidence sets need the accelerated mode");
+  const int ni = sesm_accel_n_incidences(ctx);
+  if (r0 < 0 || n < 0 || r0 + n > ni) return ctx->fail(SESM_EINVAL, "incidence index beyond the incidence set");
+  return SESM_OK;
+}
+
 extern "C" {
 
 int sesm_create(sesm_ctx** out, int device, void* hip_stream) {
@@ -381,46 +444,7 @@ int sesm_set_surface(sesm_ctx* ctx, const sesm_profile* prof, double d, double k
   for (int m = 0; m <= SESM_MAX_J; ++m) P.wshift[m] = (m <= j) ? ((m & 1) ? -1.0 : 1.0) * binom(j, m) : 0.0;
   P.pmax = (int)std::ceil(A_periods) + 1;
   P.pmin = -P.pmax;
-  // U^eta = {n : |1 - e^{i beta_n h}|^j < eta} (eq. M_eta).  The printed set, with the
-  // factor 1/beta_n, is infinite (the quotient tends to zero for evanescent
-  // orders); on a flat surface 1/2 I + D~ has the eigenvalue (1/2)(1 - e^{i beta_n h})^j
-  // on e^{i alpha_n x}, so the orders where that factor is small are the ones
-  // the completion modes must restore.
-  P.nU = 0;
-  if (j > 0) {
-    const double t = std::pow(prm.eta, 1.0 / j);
-    const double kmax = -std::log(1.0 - std::min(t, 0.999999)) / prm.h + 1.0;
-    const double K = std::sqrt(k * k + kmax * kmax);
-    const int nlo = (int)std::floor((-K - alpha) * d / (2 * PI)) - 1;
-    const int nhi = (int)std::ceil((K - alpha) * d / (2 * PI)) + 1;
-    for (int n = nlo; n <= nhi; ++n) {
-      const double an = alpha + 2.0 * PI * n / d;
-      const std::complex<double> b = beta_of(k, an);
-      const double fac = std::pow(std::abs(1.0 - std::exp(std::complex<double>(0.0, 1.0) * b * prm.h)), j);
-      if (fac < prm.eta) {
-        if (P.nU >= SESM_MAX_UETA) return ctx->fail(SESM_EINVAL, "more than 64 completion modes; lower eta");
-        P.U[P.nU] = n;
-        P.Ua[P.nU] = an;
-        P.Ubr[P.nU] = b.real();
-        P.Ubi[P.nU] = b.imag();
-        ++P.nU;
-      }
-    }
-  }
-  {
-    const int nlo = (int)std::floor((-k - alpha) * d / (2 * PI)) - 1;
-    const int nhi = (int)std::ceil((k - alpha) * d / (2 * PI)) + 1;
-    int first = 0, count = 0;
-    for (int n = nlo; n <= nhi; ++n) {
-      const double an = alpha + 2.0 * PI * n / d;
-      if (k * k - an * an > 0) {
-        if (count == 0) first = n;
-        ++count;
-      }
-    }
-    P.n_first = first;
-    P.n_count = count;
-  }
+  if (!sesm_problem_alpha(P, alpha, prm.eta)) return ctx->fail(SESM_EINVAL, "more than 64 completion modes; lower eta");
 
   // surface samples
   int rc;
@@ -630,6 +654,57 @@ int sesm_efficiencies(sesm_ctx* ctx, const sesm_c64* mu, int32_t* n_first, int32
   *n_count = P.n_count;
   if (energy_error) *energy_error = 1.0 - s;
   return SESM_OK;
+}
+
+int sesm_set_incidences(sesm_ctx* ctx, int32_t n, const double* alpha) {
+  if (!ctx) return SESM_EINVAL;
+  if (n < 0 || n > SESM_MAX_INCIDENCES || (n > 0 && !alpha)) return ctx->fail(SESM_EINVAL, "bad incidence set");
+  int rc = incidence_ready(ctx, 0, 0);
+  if (rc) return rc;
+  SESM_HIP(hipSetDevice(ctx->device));
+  return sesm_accel_set_incidences(ctx, n, alpha);
+}
+
+int sesm_rhs_incidence(sesm_ctx* ctx, int32_t r, sesm_c64* b) {
+  if (!ctx) return SESM_EINVAL;
+  int rc = incidence_ready(ctx, r, 1);
+  if (rc) return rc;
+  if (!b) return ctx->fail(SESM_EINVAL, "null vector");
+  SESM_HIP(hipSetDevice(ctx->device));
+  const Problem* Q = sesm_accel_incidence(ctx, r);
+  hipLaunchKernelGGL(k_rhs, dim3((ctx->P.N + 255) / 256), dim3(256), 0, ctx->stream, ctx->P.N, Q->alpha, Q->beta,
+                     ctx->x, ctx->f, (cplx*)b);
+  SESM_LAUNCH_CHECK();
+  return SESM_OK;
+}
+
+int sesm_matvec_incidences(sesm_ctx* ctx, int32_t r0, int32_t nrhs, const sesm_c64* mu, int64_t ld_mu, sesm_c64* y,
+                           int64_t ld_y) {
+  if (!ctx) return SESM_EINVAL;
+  int rc = incidence_ready(ctx, r0, nrhs);
+  if (rc) return rc;
+  if (nrhs == 0) return SESM_OK;
+  const int64_t N = ctx->P.N;
+  if (!mu || !y) return ctx->fail(SESM_EINVAL, "null pointer");
+  if (ld_mu < N || ld_y < N) return ctx->fail(SESM_EINVAL, "leading dimension below N");
+  const uintptr_t m0 = (uintptr_t)mu, m1 = (uintptr_t)(mu + (nrhs - 1) * ld_mu + N);
+  const uintptr_t y0 = (uintptr_t)y, y1 = (uintptr_t)(y + (nrhs - 1) * ld_y + N);
+  if (m0 < y1 && y0 < m1) return ctx->fail(SESM_EINVAL, "densities and outputs overlap");
+  SESM_HIP(hipSetDevice(ctx->device));
+  return sesm_accel_matvec_batch(ctx, nrhs, (const cplx*)mu, ld_mu, (cplx*)y, ld_y, r0);
+}
+
+int sesm_efficiencies_incidence(sesm_ctx* ctx, int32_t r, const sesm_c64* mu, int32_t* n_first, int32_t* n_count,
+                                double* e_host, int32_t e_capacity, double* energy_error) {
+  if (!ctx) return SESM_EINVAL;
+  int rc = incidence_ready(ctx, r, 1);
+  if (rc) return rc;
+  // the Rayleigh coefficients of member r: the problem's scalars with its alpha
+  const Problem saved = ctx->P;
+  ctx->P = *sesm_accel_incidence(ctx, r);
+  rc = sesm_efficiencies(ctx, mu, n_first, n_count, e_host, e_capacity, energy_error);
+  ctx->P = saved;
+  return rc;
 }
 
 int sesm_diag_hankel(sesm_ctx* ctx, const double* x, int32_t n, sesm_c64* h0, sesm_c64* h1) {

@@ -123,6 +123,7 @@ struct FftJob {
 // out + m bout of each job.
 struct FftBatch {
   int64_t bin0, bout0, bin1, bout1;
+  int64_t bpost0, bpost1;  // per-member offsets of each job's post factors (0: shared)
 };
 
 // The transform of one workgroup's rows of job J: the rows' elements come
@@ -191,12 +192,14 @@ __global__ __launch_bounds__(1024) void k_fft_rows(FftJob j0, FftJob j1, int sig
 }
 
 // The same for several batch members: grid dimension y runs over them, member
-// m reading in + m bin and writing out + m bout of its job.
+// m reading in + m bin and writing out + m bout of its job (post factors at
+// post + m bpost).
 __global__ __launch_bounds__(1024) void k_fft_rows_batch(FftJob j0, FftJob j1, int sign, FftBatch fb) {
   const bool first = (int)blockIdx.x < j0.nblocks;
   FftJob J = first ? j0 : j1;
   const int64_t m = blockIdx.y;
   J.out += m * (first ? fb.bout0 : fb.bout1);
+  if (J.post) J.post += m * (first ? fb.bpost0 : fb.bpost1);
   const int blk = first ? blockIdx.x : blockIdx.x - j0.nblocks;
   const int n = J.A.n;
   const cplx* in = J.in + m * (first ? fb.bin0 : fb.bin1);

@@ -597,9 +597,9 @@ static int gm_rel_norm(sesm_ctx* ctx, const cplx* r, double bnorm, double* out) 
   return SESM_OK;
 }
 
-// r = b - A x (one forward map)
-static int gm_residual(sesm_ctx* ctx, const cplx* b, const cplx* x, cplx* r) {
-  const int rc = sesm_apply(ctx, x, r);
+// r = b - A x (one forward map; the operator of incidence inc, or the surface's own when inc < 0)
+static int gm_residual(sesm_ctx* ctx, const cplx* b, const cplx* x, cplx* r, int inc) {
+  const int rc = sesm_apply_inc(ctx, x, r, inc);
   if (rc) return rc;
   const int N = ctx->P.N;
   hipLaunchKernelGGL(k_sub_from, dim3((N + 255) / 256), dim3(256), 0, ctx->stream, N, b, r);
@@ -612,8 +612,9 @@ static int gm_residual(sesm_ctx* ctx, const cplx* b, const cplx* x, cplx* r) {
 // continuing one of its systems), else infinity; a restart from the true
 // residual must at least halve it, otherwise the forward map's rounding floor
 // has been reached and the solve stops.
+// inc >= 0: the operator and incident field of member inc of the incidence set.
 static int solve_impl(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out, double tol, int32_t max_iter,
-                      int32_t restart, int32_t flags, double prev_true, sesm_solve_info* info) {
+                      int32_t restart, int32_t flags, double prev_true, sesm_solve_info* info, int inc = -1) {
   if (!ctx) return SESM_EINVAL;
   if (!ctx->ready) return ctx->fail(SESM_ENOSURF, "no surface");
   if (!mu_out || !(tol > 0) || max_iter < 1 || max_iter > 100000 || restart < 0 || (flags & ~SESM_SOLVE_X0))
@@ -638,7 +639,8 @@ static int solve_impl(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out, dou
   // right-hand side (incident field written into the workspace vector when NULL)
   const cplx* b = (const cplx*)b_in;
   if (!b) {
-    if ((rc = sesm_rhs(ctx, (sesm_c64*)ctx->wtmp))) return rc;
+    if ((rc = inc < 0 ? sesm_rhs(ctx, (sesm_c64*)ctx->wtmp) : sesm_rhs_incidence(ctx, inc, (sesm_c64*)ctx->wtmp)))
+      return rc;
     b = ctx->wtmp;
   }
   double bnorm = 0.0;
@@ -662,7 +664,7 @@ static int solve_impl(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out, dou
     const bool full = k < steps;
     cplx* u = V + (int64_t)k * ldv;
     if (full) {
-      const int r = sesm_apply(ctx, u, ctx->gw);
+      const int r = sesm_apply_inc(ctx, u, ctx->gw, inc);
       if (r) return r;
     }
     const int nv = k + 1, slot = k % SESM_HRING;
@@ -726,7 +728,7 @@ static int solve_impl(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out, dou
     if (!r_in_v0) {
       if (x_zero) {
         SESM_HIP(hipMemcpyAsync(V, b, sizeof(cplx) * (size_t)N, hipMemcpyDeviceToDevice, st));
-      } else if ((rc = gm_residual(ctx, b, x, V))) {
+      } else if ((rc = gm_residual(ctx, b, x, V, inc))) {
         return rc;
       }
     }
@@ -814,7 +816,7 @@ static int solve_impl(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out, dou
     total += nv;
     x_zero = false;
     // the residual of the new x (the next cycle's u_0)
-    if ((rc = gm_residual(ctx, b, x, V))) return rc;
+    if ((rc = gm_residual(ctx, b, x, V, inc))) return rc;
     r_in_v0 = true;
     if (est <= cyc_tol || total >= max_iter) {  // the estimate is met (or no iteration is left): check the true residual
       if ((rc = gm_rel_norm(ctx, V, bnorm, &res_true))) return rc;
@@ -876,8 +878,11 @@ struct GmMember {
 
 }  // namespace
 
-extern "C" int sesm_solve_batch(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_in, int64_t ld_b, sesm_c64* mu_out,
-                                int64_t ld_mu, double tol, int32_t max_iter, int32_t flags, sesm_solve_info* info) {
+// inc0 >= 0: system r uses the operator of member inc0 + r of the incidence
+// set (b may then be NULL: each member's incident field)
+static int solve_batch_impl(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_in, int64_t ld_b, sesm_c64* mu_out,
+                            int64_t ld_mu, double tol, int32_t max_iter, int32_t flags, sesm_solve_info* info,
+                            int inc0) {
   if (!ctx) return SESM_EINVAL;
   if (!ctx->ready) return ctx->fail(SESM_ENOSURF, "no surface");
   if (nrhs < 0 || nrhs > SESM_MAX_BATCH || !(tol > 0) || max_iter < 1 || max_iter > 4000 ||
@@ -886,8 +891,9 @@ extern "C" int sesm_solve_batch(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_i
   const bool warm = (flags & SESM_SOLVE_X0) != 0;
   if (nrhs == 0) return SESM_OK;
   const int N = ctx->P.N;
-  if (!b_in || !mu_out || ld_b < N || ld_mu < N) return ctx->fail(SESM_EINVAL, "bad batched solve arguments");
-  {  // the spans of the right-hand sides and of the solutions must be disjoint
+  if ((!b_in && inc0 < 0) || !mu_out || ld_b < N || ld_mu < N)
+    return ctx->fail(SESM_EINVAL, "bad batched solve arguments");
+  if (b_in) {  // the spans of the right-hand sides and of the solutions must be disjoint
     const uintptr_t b0 = (uintptr_t)b_in, b1 = (uintptr_t)(b_in + (nrhs - 1) * ld_b + N);
     const uintptr_t m0 = (uintptr_t)mu_out, m1 = (uintptr_t)(mu_out + (nrhs - 1) * ld_mu + N);
     if (b0 < m1 && m0 < b1) return ctx->fail(SESM_EINVAL, "right-hand sides and solutions overlap");
@@ -916,18 +922,33 @@ extern "C" int sesm_solve_batch(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_i
     gm_release(ctx, small);
     return code;
   };
+  // the members' incident fields when no right-hand sides are given (kept
+  // until a system continuing alone has finished)
+  cplx* Ball = nullptr;
+  auto finish_all = [&](int code) -> int {
+    const int c = finish(code);
+    gm_release(ctx, Ball);
+    return c;
+  };
+  if (!b_in) {
+    if ((rc = sesm_alloc(ctx, (void**)&Ball, sizeof(cplx) * (size_t)nrhs * N))) return rc;
+    for (int r = 0; r < nrhs; ++r)
+      if ((rc = sesm_rhs_incidence(ctx, inc0 + r, (sesm_c64*)(Ball + (int64_t)r * N)))) return finish_all(rc);
+    b_in = (const sesm_c64*)Ball;
+    ld_b = N;
+  }
   if ((rc = sesm_alloc(ctx, (void**)&Vall, sizeof(cplx) * (size_t)nrhs * vstride)) ||
       (rc = sesm_alloc(ctx, (void**)&Wall, sizeof(cplx) * (size_t)nrhs * N)) ||
       (rc = sesm_alloc(ctx, (void**)&small, sizeof(cplx) * (size_t)nrhs * per_small)))
-    return finish(rc);
+    return finish_all(rc);
   const size_t pin_per = (size_t)(SESM_HRING + 1) * SESM_HSTRIDE + SESM_HRING;  // slots, then flags (as cplx)
   if (hipHostMalloc((void**)&pin, sizeof(cplx) * pin_per * nrhs, hipHostMallocCoherent) != hipSuccess) {
     pin = nullptr;
-    return finish(ctx->fail(SESM_ENOMEM, "hipHostMalloc failed"));
+    return finish_all(ctx->fail(SESM_ENOMEM, "hipHostMalloc failed"));
   }
   cplx* pin_dev = nullptr;
   if (hipHostGetDevicePointer((void**)&pin_dev, pin, 0) != hipSuccess)
-    return finish(ctx->fail(SESM_EHIP, "hipHostGetDevicePointer failed"));
+    return finish_all(ctx->fail(SESM_EHIP, "hipHostGetDevicePointer failed"));
   for (int r = 0; r < nrhs; ++r) {
     GmMember& G = M[r];
     G.V = Vall + r * vstride;
@@ -951,12 +972,12 @@ extern "C" int sesm_solve_batch(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_i
     // right-hand side norm and u_0 = b (x = 0)
     hipLaunchKernelGGL(k_norm2_part, dim3(NCHUNK), dim3(256), 0, st, N, G.b, (double*)G.hpart);
     hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(64), 0, st, (const double*)G.hpart, G.hcol);
-    if (hipGetLastError() != hipSuccess) return finish(ctx->fail(SESM_EHIP, "batched solve: launch failed"));
+    if (hipGetLastError() != hipSuccess) return finish_all(ctx->fail(SESM_EHIP, "batched solve: launch failed"));
     cplx* hup = G.hhost + (size_t)SESM_HRING * SESM_HSTRIDE;
     if (hipMemcpyAsync(hup, G.hcol, sizeof(cplx), hipMemcpyDeviceToHost, st) != hipSuccess)
-      return finish(ctx->fail(SESM_EHIP, "batched solve: initial copies failed"));
+      return finish_all(ctx->fail(SESM_EHIP, "batched solve: initial copies failed"));
   }
-  if (hipStreamSynchronize(st) != hipSuccess) return finish(ctx->fail(SESM_EHIP, "batched solve: synchronisation failed"));
+  if (hipStreamSynchronize(st) != hipSuccess) return finish_all(ctx->fail(SESM_EHIP, "batched solve: synchronisation failed"));
   for (int r = 0; r < nrhs; ++r) {
     M[r].bnorm = M[r].hhost[(size_t)SESM_HRING * SESM_HSTRIDE].re;
     M[r].active = M[r].bnorm != 0.0;
@@ -968,10 +989,10 @@ extern "C" int sesm_solve_batch(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_i
   if (warm) {
     int r2 = SESM_OK;
     if (ctx->P.mode == SESM_MODE_ACCEL)
-      r2 = sesm_accel_matvec_batch(ctx, nrhs, (const cplx*)mu_out, ld_mu, Wall, N);
+      r2 = sesm_accel_matvec_batch(ctx, nrhs, (const cplx*)mu_out, ld_mu, Wall, N, inc0);
     else
       for (int r = 0; r < nrhs && !r2; ++r) r2 = sesm_dense_matvec(ctx, M[r].x, M[r].w);
-    if (r2) return finish(r2);
+    if (r2) return finish_all(r2);
   }
   for (int r = 0; r < nrhs; ++r) {
     GmMember& G = M[r];
@@ -979,10 +1000,10 @@ extern "C" int sesm_solve_batch(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_i
       hipLaunchKernelGGL(k_sub_from, dim3(nb), dim3(256), 0, st, N, G.b, G.w);
       if (hipGetLastError() != hipSuccess ||
           hipMemcpyAsync(G.V, G.w, sizeof(cplx) * (size_t)N, hipMemcpyDeviceToDevice, st) != hipSuccess)
-        return finish(ctx->fail(SESM_EHIP, "batched solve: initial residual failed"));
+        return finish_all(ctx->fail(SESM_EHIP, "batched solve: initial residual failed"));
     } else if (hipMemcpyAsync(G.V, G.b, sizeof(cplx) * (size_t)N, hipMemcpyDeviceToDevice, st) != hipSuccess ||
                hipMemsetAsync(G.x, 0, sizeof(cplx) * (size_t)N, st) != hipSuccess) {
-      return finish(ctx->fail(SESM_EHIP, "batched solve: initial copies failed"));
+      return finish_all(ctx->fail(SESM_EHIP, "batched solve: initial copies failed"));
     }
   }
   GmBatch GB0{};
@@ -1013,7 +1034,7 @@ extern "C" int sesm_solve_batch(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_i
       int r2;
       if (ctx->P.mode == SESM_MODE_ACCEL)
         r2 = sesm_accel_matvec_batch(ctx, hi - lo + 1, Vall + lo * vstride + (int64_t)k * ldv, vstride,
-                                     Wall + (int64_t)lo * N, N);
+                                     Wall + (int64_t)lo * N, N, inc0 < 0 ? -1 : inc0 + lo);
       else {
         r2 = SESM_OK;
         for (int r = lo; r <= hi && !r2; ++r) r2 = sesm_dense_matvec(ctx, M[r].V + (int64_t)k * ldv, M[r].w);
@@ -1048,20 +1069,20 @@ extern "C" int sesm_solve_batch(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_i
     SESM_LAUNCH_CHECK();
     return SESM_OK;
   };
-  if ((rc = arnoldi_all(0))) return finish(rc);
+  if ((rc = arnoldi_all(0))) return finish_all(rc);
   int active = 0;
   for (const GmMember& G : M) active += G.active ? 1 : 0;
   for (int k = 0; active > 0; ++k) {
-    if (k + 1 <= steps && (rc = arnoldi_all(k + 1))) return finish(rc);  // the device stays one step ahead
+    if (k + 1 <= steps && (rc = arnoldi_all(k + 1))) return finish_all(rc);  // the device stays one step ahead
     const int slot = k % SESM_HRING;
     for (int r = 0; r < nrhs; ++r) {
       GmMember& G = M[r];
       if (!G.active) continue;
-      if ((rc = gm_wait(ctx, G.hflag + slot, G.slot_seq[slot]))) return finish(rc);
+      if ((rc = gm_wait(ctx, G.hflag + slot, G.slot_seq[slot]))) return finish_all(rc);
       cplx* hs = G.hhost + (size_t)slot * SESM_HSTRIDE;
       if (k == 0) {  // residual norm
         Cd r0;
-        if ((rc = gm_take(ctx, hs, 1, &r0))) return finish(rc);
+        if ((rc = gm_take(ctx, hs, 1, &r0))) return finish_all(rc);
         G.beta0 = r0.real();
         G.g[0] = G.beta0;
         G.res = G.res_true = G.beta0 / G.bnorm;
@@ -1074,7 +1095,7 @@ extern "C" int sesm_solve_batch(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_i
       if (G.Hraw.size() < need) G.Hraw.resize(std::max(need, 2 * G.Hraw.size()));
       Cd* col = &G.H[(size_t)m_tri(j)];
       Cd* raw = &G.Hraw[(size_t)m_tri(j)];
-      if ((rc = gm_take(ctx, hs, k + 1, raw))) return finish(rc);
+      if ((rc = gm_take(ctx, hs, k + 1, raw))) return finish_all(rc);
       for (int t = 0; t <= k; ++t) col[t] = raw[t];
       const double rr = gm_rotate(col, j, G.cs, G.sn, G.g);
       G.res = std::abs(G.g[j + 1]) / G.bnorm;
@@ -1091,11 +1112,11 @@ extern "C" int sesm_solve_batch(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_i
     if (nv == 0) continue;
     if (tri.size() < (size_t)m_tri(nv)) tri.resize((size_t)m_tri(nv));
     hipLaunchKernelGGL(k_hess_gather, dim3(nv), dim3(256), 0, st, m, G.Hrow, G.htri);
-    if (hipGetLastError() != hipSuccess) return finish(ctx->fail(SESM_EHIP, "batched solve: launch failed"));
+    if (hipGetLastError() != hipSuccess) return finish_all(ctx->fail(SESM_EHIP, "batched solve: launch failed"));
     if (hipMemcpyAsync(tri.data(), G.htri, sizeof(cplx) * (size_t)m_tri(nv), hipMemcpyDeviceToHost, st) !=
             hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
-      return finish(ctx->fail(SESM_EHIP, "batched solve: Hessenberg transfer failed"));
+      return finish_all(ctx->fail(SESM_EHIP, "batched solve: Hessenberg transfer failed"));
     int bad = 0;
     for (int j = 0; j < nv; ++j) {
       const cplx* dv = &tri[(size_t)m_tri(j)];
@@ -1124,10 +1145,10 @@ extern "C" int sesm_solve_batch(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_i
     cplx* yh = G.hhost + (size_t)SESM_HRING * SESM_HSTRIDE;
     for (int t = 0; t < nv; ++t) yh[t] = cplx{y[t].real(), y[t].imag()};
     if (hipMemcpyAsync(G.ybuf, yh, sizeof(cplx) * nv, hipMemcpyHostToDevice, st) != hipSuccess)
-      return finish(ctx->fail(SESM_EHIP, "batched solve: upload failed"));
+      return finish_all(ctx->fail(SESM_EHIP, "batched solve: upload failed"));
     hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), sizeof(cplx) * nv, st, N, nv, G.V, ldv, G.ybuf, G.x);
-    if (hipGetLastError() != hipSuccess) return finish(ctx->fail(SESM_EHIP, "batched solve: launch failed"));
-    if (hipStreamSynchronize(st) != hipSuccess) return finish(ctx->fail(SESM_EHIP, "batched solve: combine failed"));
+    if (hipGetLastError() != hipSuccess) return finish_all(ctx->fail(SESM_EHIP, "batched solve: launch failed"));
+    if (hipStreamSynchronize(st) != hipSuccess) return finish_all(ctx->fail(SESM_EHIP, "batched solve: combine failed"));
   }
   // true residuals b - A x of the updated systems: one batched forward map of
   // all solutions, then each updated system's norm (the others' true residual
@@ -1135,11 +1156,11 @@ extern "C" int sesm_solve_batch(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_i
   {
     int r2 = SESM_OK;
     if (ctx->P.mode == SESM_MODE_ACCEL)
-      r2 = sesm_accel_matvec_batch(ctx, nrhs, (const cplx*)mu_out, ld_mu, Wall, N);
+      r2 = sesm_accel_matvec_batch(ctx, nrhs, (const cplx*)mu_out, ld_mu, Wall, N, inc0);
     else
       for (int r = 0; r < nrhs && !r2; ++r)
         if (M[r].nv > 0) r2 = sesm_dense_matvec(ctx, M[r].x, M[r].w);
-    if (r2) return finish(r2);
+    if (r2) return finish_all(r2);
     for (int r = 0; r < nrhs; ++r) {
       GmMember& G = M[r];
       if (G.nv == 0) continue;
@@ -1149,9 +1170,9 @@ extern "C" int sesm_solve_batch(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_i
       if (hipGetLastError() != hipSuccess ||
           hipMemcpyAsync(G.hhost + (size_t)SESM_HRING * SESM_HSTRIDE, G.hcol, sizeof(cplx), hipMemcpyDeviceToHost,
                          st) != hipSuccess)
-        return finish(ctx->fail(SESM_EHIP, "batched solve: residual check failed"));
+        return finish_all(ctx->fail(SESM_EHIP, "batched solve: residual check failed"));
     }
-    if (hipStreamSynchronize(st) != hipSuccess) return finish(ctx->fail(SESM_EHIP, "batched solve: residual check failed"));
+    if (hipStreamSynchronize(st) != hipSuccess) return finish_all(ctx->fail(SESM_EHIP, "batched solve: residual check failed"));
     for (int r = 0; r < nrhs; ++r)
       if (M[r].nv > 0) M[r].res_true = M[r].hhost[(size_t)SESM_HRING * SESM_HSTRIDE].re / M[r].bnorm;
   }
@@ -1167,8 +1188,11 @@ extern "C" int sesm_solve_batch(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_i
     double res_true = G.res_true, est = G.res;
     if (G.bnorm != 0.0 && res_true > tol && G.nv > 0 && G.nv < max_iter) {
       const int r2 = solve_impl(ctx, (const sesm_c64*)G.b, (sesm_c64*)G.x, tol, max_iter - G.nv, 0, SESM_SOLVE_X0,
-                                G.res_true, &more);
-      if (r2 && r2 != SESM_ENOCONV) return r2;
+                                G.res_true, &more, inc0 < 0 ? -1 : inc0 + r);
+      if (r2 && r2 != SESM_ENOCONV) {
+        gm_release(ctx, Ball);
+        return r2;
+      }
       extra = 1 + more.residual_restarts;
       iters += more.iters;
       mism += more.column_mismatches;
@@ -1188,6 +1212,24 @@ extern "C" int sesm_solve_batch(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_i
       info[r].column_mismatches = mism;
     }
   }
+  gm_release(ctx, Ball);
   if (!all) return ctx->fail(SESM_ENOCONV, "GMRES did not reach the tolerance for every right-hand side");
   return SESM_OK;
+}
+
+extern "C" int sesm_solve_batch(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b, int64_t ld_b, sesm_c64* mu,
+                                int64_t ld_mu, double tol, int32_t max_iter, int32_t flags, sesm_solve_info* info) {
+  return solve_batch_impl(ctx, nrhs, b, ld_b, mu, ld_mu, tol, max_iter, flags, info, -1);
+}
+
+extern "C" int sesm_solve_incidences(sesm_ctx* ctx, int32_t r0, int32_t nrhs, const sesm_c64* b, int64_t ld_b,
+                                     sesm_c64* mu, int64_t ld_mu, double tol, int32_t max_iter, int32_t flags,
+                                     sesm_solve_info* info) {
+  if (!ctx) return SESM_EINVAL;
+  if (!ctx->ready) return ctx->fail(SESM_ENOSURF, "no surface");
+  if (ctx->P.mode != SESM_MODE_ACCEL) return ctx->fail(SESM_EINVAL, "incidence sets need the accelerated mode");
+  if (r0 < 0 || nrhs < 0 || r0 + nrhs > sesm_accel_n_incidences(ctx))
+    return ctx->fail(SESM_EINVAL, "incidence index beyond the incidence set");
+  if (!b) ld_b = ctx->P.N;
+  return solve_batch_impl(ctx, nrhs, b, ld_b, mu, ld_mu, tol, max_iter, flags, info, r0);
 }

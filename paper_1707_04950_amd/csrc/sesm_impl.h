@@ -27,6 +27,16 @@ struct Problem {
   int n_first = 0, n_count = 0;   // propagating orders
 };
 
+// The incidence-dependent constants of the accelerated operator, one record
+// per incidence (device memory): the Bloch phase e^{i alpha d} of wrapped
+// columns and grid points (eq. shifted_periodic_green_function) and the
+// completion modes of eq. M_eta.
+struct IncParams {
+  double alpha, alpha_d;
+  int nU, pad;
+  double Ua[SESM_MAX_UETA], Ubr[SESM_MAX_UETA], Ubi[SESM_MAX_UETA];
+};
+
 // Parameters handed by value to the operator kernels.
 struct KParams {
   int N, j, n_a, pmin, pmax, nU;
@@ -161,12 +171,23 @@ int sesm_dense_matvec(sesm_ctx* ctx, const cplx* mu, cplx* y);
 // accelerated path (sesm_accel.hip)
 int sesm_accel_setup(sesm_ctx* ctx);
 int sesm_accel_matvec(sesm_ctx* ctx, const cplx* mu, cplx* y);
-int sesm_accel_matvec_batch(sesm_ctx* ctx, int nrhs, const cplx* mu, int64_t ldm, cplx* y, int64_t ldy);
+// inc0 < 0: every density with the surface's own incidence; inc0 >= 0: density
+// r with member inc0 + r of the incidence set
+int sesm_accel_matvec_batch(sesm_ctx* ctx, int nrhs, const cplx* mu, int64_t ldm, cplx* y, int64_t ldy,
+                            int inc0 = -1);
+int sesm_accel_set_incidences(sesm_ctx* ctx, int n, const double* alpha);
+int sesm_accel_n_incidences(const sesm_ctx* ctx);
+const Problem* sesm_accel_incidence(const sesm_ctx* ctx, int r);
 void sesm_accel_free(sesm_ctx* ctx);
 void sesm_accel_info(const sesm_ctx* ctx, sesm_surface_info* info);
 
-// operator dispatch
+// operator dispatch; sesm_apply_inc applies the operator of member inc of the
+// incidence set (inc < 0: the surface's own incidence)
 int sesm_apply(sesm_ctx* ctx, const cplx* mu, cplx* y);
+int sesm_apply_inc(sesm_ctx* ctx, const cplx* mu, cplx* y, int inc);
+
+// incidence-dependent scalars (alpha, beta, U^eta, propagating orders) of P
+bool sesm_problem_alpha(Problem& P, double alpha, double eta);
 
 // dst[e] = src[e], e < n, by nt threads (tid = own index): B loads per thread
 // are issued (indices clamped) before any store, so one memory latency covers

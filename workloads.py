@@ -153,3 +153,23 @@ def random_density(N: int, seed: int = 1) -> np.ndarray:
     """Seeded complex normal density vector (complex128)."""
     rng = np.random.default_rng(seed)
     return (rng.standard_normal(N) + 1j * rng.standard_normal(N)) / math.sqrt(2.0)
+
+
+C4_D_OVER_LAMBDA = (50.0, 50.5, 51.0, 51.5)
+
+
+def config_c4(i_k: int = 0, N: int = 16384) -> Workload:
+    """Many incidences: Gaussian random surface of period d = 50 (units of
+    the first wavelength), rms 0.5, l_c = 1, wavenumber k = 2 pi (d/lambda)/d
+    for d/lambda in C4_D_OVER_LAMBDA[i_k]; the incidence angle of the returned
+    workload is 0 (the set's angles are given by c4_angles)."""
+    d = 50.0
+    a, b = gaussian_surface(d, 0.5, 1.0, SEED_BASE + 4)
+    k = TWO_PI * C4_D_OVER_LAMBDA[i_k] / d
+    return Workload(name="gauss-d50-rms0.5-k%d-N%d" % (i_k, N), d=d, k=k, theta_deg=0.0, N=N, j=8, h=0.85,
+                    A=40.0, a_coef=a, b_coef=b, L=0.5)
+
+
+def c4_angles(n: int = 64):
+    """n incidence angles uniform in [0, 85] degrees."""
+    return [85.0 * i / (n - 1) for i in range(n)]
