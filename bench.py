@@ -165,26 +165,27 @@ def bench_c4(args):
     angles = W.c4_angles(args.c4_angles)
     nk = len(W.C4_D_OVER_LAMBDA)
 
-    def setup(wl, theta=0.0):
+    def setup(wl, theta=0.0, mixed=False):
         n_a = max(8, int(math.floor(0.8 * min(wl.L, wl.d) / wl.dx)))
         w = wl.with_(theta_deg=theta)
         s.set_surface(np.asarray(w.a_coef), np.asarray(w.b_coef), w.d, w.k, w.alpha, w.j, w.A, w.N, h=w.h, c=w.c,
-                      n_a=n_a, gamma_frac=w.gamma_frac, eta=w.eta, mode=lib.MODE_ACCEL, L=w.L)
+                      n_a=n_a, gamma_frac=w.gamma_frac, eta=w.eta, mode=lib.MODE_ACCEL, L=w.L, mixed=int(mixed))
 
-    def batched(ik):
+    def batched(ik, mixed=False):
         wl = W.config_c4(ik, args.c4_N)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        setup(wl)
+        setup(wl, mixed=mixed)
         s.set_incidences([wl.k * math.sin(math.radians(t)) for t in angles])
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        X, infos = s.solve_incidences(tol=args.tol, max_iter=args.c4_max_iter, allow_noconv=True)
+        X, infos = s.solve_incidences(tol=args.tol, max_iter=args.c4_max_iter, allow_noconv=True, mixed=mixed)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         effs = [s.efficiencies_incidence(r, X[r].contiguous()) for r in range(len(angles))]
         t3 = time.perf_counter()
         return dict(setup=t1 - t0, solve=t2 - t1, eff=t3 - t2, iters=[i["iters"] for i in infos],
+                    steps=[i["residual_restarts"] for i in infos],
                     conv=[i["converged"] for i in infos], e=[e for _, e, _ in effs], eps=[p for _, _, p in effs])
 
     def single(ik):
@@ -200,9 +201,14 @@ def bench_c4(args):
         return time.perf_counter() - t0, out
 
     batched(0)  # warm-up: tuner, pools, code objects
+    batched(0, mixed=True)
     single(0)
     recs = [batched(ik) for ik in range(nk)]
     t_batch = sum(r["setup"] + r["solve"] + r["eff"] for r in recs)
+    mrecs = [batched(ik, mixed=True) for ik in range(nk)]
+    t_mixed = sum(r["setup"] + r["solve"] + r["eff"] for r in mrecs)
+    dmix = max(float(np.max(np.abs(np.asarray(em) - np.asarray(eb)))) for r, m in zip(recs, mrecs)
+               for eb, em in zip(r["e"], m["e"]))
     sing = [single(ik) for ik in range(nk)]
     t_single = sum(t for t, _ in sing)
     n_solves = nk * len(angles)
@@ -223,6 +229,16 @@ def bench_c4(args):
         "all_converged": all(all(r["conv"]) for r in recs) and all(c for _, o in sing for _, _, c in o),
         "max_energy_balance_error": max(abs(p) for r in recs for p in r["eps"]),
         "max_efficiency_diff_batched_vs_single": diff,
+        "mixed_precision_batched": {
+            "solves_per_s": n_solves / t_mixed, "speedup_vs_fp64_batched": t_batch / t_mixed,
+            "solve_s": sum(r["solve"] for r in mrecs),
+            "iters_min_median_max": [int(min(min(r["iters"]) for r in mrecs)),
+                                     int(np.median([i for r in mrecs for i in r["iters"]])),
+                                     int(max(max(r["iters"]) for r in mrecs))],
+            "refinement_steps_max": int(max(max(r["steps"]) for r in mrecs)),
+            "all_converged": all(all(r["conv"]) for r in mrecs),
+            "max_efficiency_diff_vs_fp64": dmix,
+            "max_energy_balance_error": max(abs(p) for r in mrecs for p in r["eps"])},
     }
     s.close()
     print(json.dumps(out))
@@ -372,6 +388,28 @@ def main():
                   "column_mismatches": int(sum(i["column_mismatches"] for i in infos)),
                   "member0_equals_single": bool(torch.equal(xb[0], x1))}
 
+    # mixed precision (FP32 EqSources operators and Krylov basis under FP64
+    # refinement) on the same workload, outside the timed region: a surface
+    # set up with the FP32 operators, one warm-up and one timed solve
+    mixed = None
+    if args.mode == "accel":
+        s.set_surface(np.asarray(wl.a_coef), np.asarray(wl.b_coef), wl.d, wl.k, wl.alpha, wl.j, wl.A, args.N,
+                      h=wl.h, c=wl.c, n_a=n_a, gamma_frac=wl.gamma_frac, eta=wl.eta, mode=mode, L=wl.L, mixed=1)
+        s.solve(tol=args.tol, max_iter=args.max_iter, allow_noconv=True, mixed=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mu_m, inf_m = s.solve(tol=args.tol, max_iter=args.max_iter, allow_noconv=True, mixed=True)
+        torch.cuda.synchronize()
+        t_m = time.perf_counter() - t0
+        n_m, e_m, eps_m = s.efficiencies(mu_m)
+        cmp_m = efficiency_vs_oracle(n_m, e_m)
+        mixed = {"solve_ms": t_m * 1e3, "fp64_solve_ms": float(np.mean([r["solve"] for r in recs])) * 1e3,
+                 "speedup_vs_fp64": float(np.mean([r["solve"] for r in recs])) / t_m, "iters": inf_m["iters"],
+                 "refinement_steps": inf_m["residual_restarts"], "converged": inf_m["converged"],
+                 "rel_residual": inf_m["rel_residual"],
+                 "max_efficiency_diff_vs_fp64": float(np.max(np.abs(e_m - recs[-1]["e"]))),
+                 "efficiency_err_vs_oracle": cmp_m["value"] if cmp_m else None, "energy_balance_error": eps_m}
+
     # efficiencies against the oracle's (dense LU of the same workload at the
     # largest N it was run at; stored by tests/golden/gen_golden.py), outside
     # the timed region
@@ -427,6 +465,7 @@ def main():
         "gmres_rel_residual_estimate": recs[-1]["est"],
         "all_steps_converged": all(r["conv"] for r in recs),
         "efficiency_err_vs_oracle": oracle_cmp,
+        "mixed_precision_solve": mixed,
         "energy_balance_error": max((r["eps"] for r in recs), key=abs),
         # every step solves the same problem: its efficiencies must agree bit for bit
         "steps_identical": all(np.array_equal(r["e"], recs[0]["e"]) for r in recs),

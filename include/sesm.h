@@ -92,7 +92,10 @@ typedef struct {
   int32_t split_permille[3]; /* near_split = 1: thousandths of the items in the first
                          launch, with merge + forward FFT, with the y convolution (the
                          inverse FFT takes the rest); each in [0, 1000], sum <= 1000     */
-  int32_t reserved[3];
+  int32_t mixed;      /* accelerator: 1 also builds the FP32 copy of the EqSources
+                         operators (eq. eq_source_point) used by mixed-precision solves
+                         (SESM_SOLVE_MIXED); 0 (default) does not                      */
+  int32_t reserved[2];
 } sesm_params;
 
 typedef struct {
@@ -112,6 +115,12 @@ typedef struct {
 
 /* flags of sesm_solve / sesm_solve_batch */
 #define SESM_SOLVE_X0 1  /* mu holds the initial guess x0 on entry (warm start) */
+#define SESM_SOLVE_MIXED 2 /* mixed precision: FP64 iterative refinement (true residuals
+                              with the FP64 forward map) around inner GMRES solves with an
+                              FP32 Krylov basis and the mixed-precision map (EqSources
+                              operators in FP32, all sums and the near field in FP64);
+                              needs a surface set up with sesm_params.mixed = 1.
+                              residual_restarts then counts the refinement steps. */
 
 /* Read-only description of the discretisation chosen by sesm_set_surface. */
 typedef struct {

@@ -35,7 +35,7 @@ class Params(ctypes.Structure):
                 ("mode", ctypes.c_int32), ("L_cell", ctypes.c_double), ("n_side", ctypes.c_int32),
                 ("n_ext", ctypes.c_int32), ("n_coll", ctypes.c_int32), ("n_plw", ctypes.c_int32),
                 ("near_ring", ctypes.c_int32), ("near_split", ctypes.c_int32),
-                ("split_permille", ctypes.c_int32 * 3), ("reserved", ctypes.c_int32 * 3)]
+                ("split_permille", ctypes.c_int32 * 3), ("mixed", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -45,6 +45,7 @@ class SolveInfo(ctypes.Structure):
 
 
 SOLVE_X0 = 1  # sesm_solve flag: mu holds the initial guess on entry
+SOLVE_MIXED = 2  # mixed precision: FP64 refinement around FP32-basis inner solves
 
 
 def _info_dict(i):
@@ -208,7 +209,7 @@ class Solver:
 
     def set_surface(self, a_coef, b_coef, d, k, alpha, j, A, N, h=0.0, c=0.0, n_a=0, gamma_frac=0.0,
                     eta=0.0, mode=MODE_DENSE, L=0.0, n_side=0, n_ext=0, n_coll=0, n_plw=0, near_ring=0,
-                    near_split=0, split_permille=(0, 0, 0)):
+                    near_split=0, split_permille=(0, 0, 0), mixed=0):
         a = np.ascontiguousarray(a_coef, dtype=np.float64)
         b = np.zeros_like(a)
         bb = np.asarray(b_coef, dtype=np.float64)
@@ -218,7 +219,7 @@ class Solver:
                        b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         prm = Params(N=N, h=h, c_window=c, n_a=n_a, gamma_frac=gamma_frac, eta=eta, mode=mode, L_cell=L,
                      n_side=n_side, n_ext=n_ext, n_coll=n_coll, n_plw=n_plw, near_ring=near_ring,
-                     near_split=near_split, split_permille=(ctypes.c_int32 * 3)(*split_permille))
+                     near_split=near_split, split_permille=(ctypes.c_int32 * 3)(*split_permille), mixed=int(mixed))
         self._check(self.lib.sesm_set_surface(self.h, ctypes.byref(prof), d, k, alpha, j, A, ctypes.byref(prm)))
         self.N = N
 
@@ -268,15 +269,18 @@ class Solver:
         self._check(self.lib.sesm_rhs_bloch(self.h, int(p), _ptr(out, self.N)))
         return out
 
-    def solve(self, b=None, tol=1e-10, max_iter=1000, restart=0, out=None, allow_noconv=False, x0=None):
+    def solve(self, b=None, tol=1e-10, max_iter=1000, restart=0, out=None, allow_noconv=False, x0=None,
+              mixed=False):
         """GMRES solve; x0 (a device tensor of N) is the initial guess and is
         overwritten with the solution (warm start); otherwise the iteration
-        starts from zero and the solution goes to out (allocated if None)."""
-        flags = 0
+        starts from zero and the solution goes to out (allocated if None).
+        mixed: FP64 refinement around FP32-basis inner solves (surface set up
+        with mixed=1)."""
+        flags = SOLVE_MIXED if mixed else 0
         if x0 is not None:
             if out is not None and out is not x0:
                 raise ValueError("with x0 the solution overwrites x0; do not pass out")
-            out, flags = x0, SOLVE_X0
+            out, flags = x0, flags | SOLVE_X0
         out = self.empty() if out is None else out
         inf = SolveInfo()
         bp = _ptr(b, self.N) if b is not None else None
@@ -284,7 +288,7 @@ class Solver:
         self._check(rc, allow=(SESM_ENOCONV,) if allow_noconv else ())
         return out, _info_dict(inf)
 
-    def solve_batch(self, b, tol=1e-10, max_iter=1000, out=None, allow_noconv=False, x0=None):
+    def solve_batch(self, b, tol=1e-10, max_iter=1000, out=None, allow_noconv=False, x0=None, mixed=False):
         """Unrestarted GMRES for the rows of b (nrhs x >= N, complex128 on the
         device) in lockstep; returns the solutions (rows of out) and one info
         dict per row.  x0 (nrhs x >= N): initial guesses, overwritten with the
@@ -292,11 +296,11 @@ class Solver:
         if b.dim() != 2 or b.shape[1] < self.N:
             raise ValueError("b must be a (nrhs, >= N) tensor")
         n = int(b.shape[0])
-        flags = 0
+        flags = SOLVE_MIXED if mixed else 0
         if x0 is not None:
             if out is not None and out is not x0:
                 raise ValueError("with x0 the solutions overwrite x0; do not pass out")
-            out, flags = x0, SOLVE_X0
+            out, flags = x0, flags | SOLVE_X0
         if out is None:
             out = self._torch.empty((n, self.N), dtype=self._torch.complex128, device=self.device)
             if os.environ.get("SESM_POISON_ALLOC", "0") not in ("", "0"):
@@ -341,12 +345,12 @@ class Solver:
         return out
 
     def solve_incidences(self, r0=0, n=None, b=None, tol=1e-10, max_iter=1000, out=None, allow_noconv=False,
-                         x0=None):
+                         x0=None, mixed=False):
         """Lockstep GMRES for members r0 .. r0 + n - 1 (their incident fields when b is None)."""
         n = (self.n_inc - r0) if n is None else int(n)
-        flags = 0
+        flags = SOLVE_MIXED if mixed else 0
         if x0 is not None:
-            out, flags = x0, SOLVE_X0
+            out, flags = x0, flags | SOLVE_X0
         if out is None:
             out = self._torch.empty((n, self.N), dtype=self._torch.complex128, device=self.device)
         if out.dim() != 2 or out.shape[0] != n or out.shape[1] < self.N:

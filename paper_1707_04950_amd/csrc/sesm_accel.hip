@@ -63,6 +63,7 @@ struct AccelOp {
   int n_cfc = 0;  // far-field work items: up to CF_NODES nodes of one cell (cell, first node)
   int *cfc_q = nullptr, *cfc_t0 = nullptr;
   cplx *p2e = nullptr, *nearblk = nullptr, *dens = nullptr;
+  cplxf* p2e32 = nullptr;  // the EqSources operators in FP32 (mixed-precision map; built on request)
   cplx *gH = nullptr, *gV = nullptr, *fH = nullptr, *fV = nullptr, *phH = nullptr, *phV = nullptr;
   cplx *specH = nullptr, *specV = nullptr, *W = nullptr;  // (inside self_spec)
   cplx *pplw = nullptr;  // plane-wave least squares: (U^H)^T (n_bdry x n_plw), V^T (n_plw x n_plw), 1 / sig
@@ -422,6 +423,12 @@ __global__ __launch_bounds__(256) void k_p2e_setup(KParams K, CellGeo G, double 
   }
 }
 
+// dst = src rounded to FP32 (n complex values)
+__global__ void k_narrow(int64_t n, const cplx* __restrict__ src, cplxf* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = narrow_to<cplxf>(src[i]);
+}
+
 // Windowed lattice sums (eq. Gq_limit with the Bloch phase) of the monopole and
 // dipole kernels on the difference grid, twisted by exp(-i alpha X):
 // tab[kind][row][mx], row = my + nY - 1.  One wavefront per entry, lanes over images.
@@ -538,7 +545,7 @@ struct LocalArgs {
   const int* occ_cell;
   const int* occ_off;
   const int* perm;
-  const cplx* P;
+  const void* P;     // EqSources operators: cplx, or cplxf in the mixed-precision map
   cplx* dens;
   const double* x;
   const double* f;
@@ -696,7 +703,7 @@ __device__ __forceinline__ NearArgs near_args(const LocalArgs& L) {
 // each mode factor, is loaded or formed once and used for all NB densities;
 // every sum of density r is formed in the same order as for a single density,
 // so a batch reproduces single forward maps bit for bit.
-template <int NB>
+template <int NB, typename PT>
 __device__ __forceinline__ void local_apply(const KParams& K, const LocalArgs& L, const cplx* __restrict__ mu,
                                             int64_t ldm, cplx* __restrict__ y, int64_t ldy,
                                             const IncParams* __restrict__ inc, int inc_step) {
@@ -733,14 +740,14 @@ __device__ __forceinline__ void local_apply(const KParams& K, const LocalArgs& L
         for (int r = 0; r < NB; ++r) mus[r][threadIdx.x] = mu[r * ldm + src];
       }
       __syncthreads();
-      const cplx* pr = L.P + (int64_t)(off + c0) * nout + oc;
+      const PT* pr = static_cast<const PT*>(L.P) + (int64_t)(off + c0) * nout + oc;
       int t = g;
       for (; t + (PU - 1) * NG < nc; t += PU * NG) {
         cplx v[PU][OPL];
 #pragma unroll
         for (int u = 0; u < PU; ++u)
 #pragma unroll
-          for (int j = 0; j < OPL; ++j) v[u][j] = pr[(int64_t)(t + u * NG) * nout + j];
+          for (int j = 0; j < OPL; ++j) v[u][j] = widen(pr[(int64_t)(t + u * NG) * nout + j]);
 #pragma unroll
         for (int u = 0; u < PU; ++u)
 #pragma unroll
@@ -753,7 +760,7 @@ __device__ __forceinline__ void local_apply(const KParams& K, const LocalArgs& L
       for (; t < nc; t += NG) {
         cplx v[OPL];
 #pragma unroll
-        for (int j = 0; j < OPL; ++j) v[j] = pr[(int64_t)t * nout + j];
+        for (int j = 0; j < OPL; ++j) v[j] = widen(pr[(int64_t)t * nout + j]);
 #pragma unroll
         for (int r = 0; r < NB; ++r) {
           const cplx m = mus[r][t];
@@ -813,17 +820,19 @@ __device__ __forceinline__ void local_apply(const KParams& K, const LocalArgs& L
   near_store<NB>(NA, b, threadIdx.x, rs, y, ldy);
 }
 
+// PT: storage of the EqSources operators (cplx; cplxf in the mixed-precision map)
+template <typename PT>
 __global__ __launch_bounds__(LOC_NT) void k_local_apply(KParams K, LocalArgs L, const cplx* __restrict__ mu,
                                                         cplx* __restrict__ y, const IncParams* __restrict__ inc) {
-  local_apply<1>(K, L, mu, 0, y, 0, inc, 0);
+  local_apply<1, PT>(K, L, mu, 0, y, 0, inc, 0);
 }
 
 // NB densities at once (strides ldm, ldy in elements)
-template <int NB>
+template <int NB, typename PT>
 __global__ __launch_bounds__(LOC_NT) void k_local_apply_batch(KParams K, LocalArgs L, const cplx* __restrict__ mu,
                                                               int64_t ldm, cplx* __restrict__ y, int64_t ldy,
                                                               const IncParams* __restrict__ inc, int inc_step) {
-  local_apply<NB>(K, L, mu, ldm, y, ldy, inc, inc_step);
+  local_apply<NB, PT>(K, L, mu, ldm, y, ldy, inc, inc_step);
 }
 
 struct MergeArgs {
@@ -1734,6 +1743,12 @@ int sesm_accel_setup(sesm_ctx* ctx) {
   hipLaunchKernelGGL(k_p2e_setup, dim3(A->n_chunks), dim3(256), sizeof(cplx) * 4 * nrow, ctx->stream, K, G,
                      A->x0, A->y0, A->n_x, A->chunk_q, A->chunk_t0, NEAR_ROWS, A->occ_cell, A->occ_off, A->perm, ctx->x, ctx->f, ctx->fp, A->pinv, A->p2e);
   SESM_LAUNCH_CHECK();
+  if (prm.mixed) {  // FP32 copy of the EqSources operators for the mixed-precision map
+    const int64_t n32 = (int64_t)4 * A->n_eq * N;
+    if ((rc = sesm_alloc(ctx, (void**)&A->p2e32, sizeof(cplxf) * (size_t)n32))) return rc;
+    hipLaunchKernelGGL(k_narrow, dim3((unsigned)((n32 + 255) / 256)), dim3(256), 0, ctx->stream, n32, A->p2e, A->p2e32);
+    SESM_LAUNCH_CHECK();
+  }
   // --- twist factors of the global grids, and the incidence record
   {
     std::vector<cplx> tw;
@@ -2026,16 +2041,24 @@ static int accel_far_stages(sesm_ctx* ctx, const FarBufs& Fb, bool keep_far, con
   return SESM_OK;
 }
 
-static int accel_matvec_impl(sesm_ctx* ctx, const cplx* mu, cplx* y, bool keep_far) {
+// mixed: the mixed-precision map (EqSources operators in FP32, products in FP64)
+static int accel_matvec_impl(sesm_ctx* ctx, const cplx* mu, cplx* y, bool keep_far, bool mixed = false) {
   AccelOp* A = ctx->acc;
   const KParams K = ctx->kparams();
   hipStream_t st = ctx->stream;
   const MatvecBytes B = ctx->kt_mask ? matvec_bytes(ctx, true) : MatvecBytes{};
   LocalArgs L = local_args(ctx, false);
   L.n_chunks = A->near_c1;  // the other near-field items ride on the grid stages
+  if (mixed && !A->p2e32) return ctx->fail(SESM_EINVAL, "mixed-precision map: surface set up without sesm_params.mixed");
   SESM_KT_BEGIN(SESM_KT_LOCAL, st);
-  hipLaunchKernelGGL(k_local_apply, dim3(L.n_occ + L.n_mode_blocks + L.n_chunks), dim3(LOC_NT), 0, st, K, L, mu,
-                     y, A->inc_self);
+  if (mixed) {
+    L.P = A->p2e32;
+    hipLaunchKernelGGL(k_local_apply<cplxf>, dim3(L.n_occ + L.n_mode_blocks + L.n_chunks), dim3(LOC_NT), 0, st, K, L,
+                       mu, y, A->inc_self);
+  } else {
+    hipLaunchKernelGGL(k_local_apply<cplx>, dim3(L.n_occ + L.n_mode_blocks + L.n_chunks), dim3(LOC_NT), 0, st, K, L,
+                       mu, y, A->inc_self);
+  }
   SESM_LAUNCH_CHECK();
   SESM_KT_END(SESM_KT_LOCAL, st, B.local);
   FarBufs Fb{};
@@ -2056,17 +2079,24 @@ static int accel_matvec_impl(sesm_ctx* ctx, const cplx* mu, cplx* y, bool keep_f
 
 template <int NB>
 static void launch_local_batch(hipStream_t st, const KParams& K, const LocalArgs& L, const cplx* mu, int64_t ldm,
-                               cplx* y, int64_t ldy, const IncParams* inc, int inc_step) {
-  hipLaunchKernelGGL(k_local_apply_batch<NB>, dim3(L.n_occ + L.n_mode_blocks + L.n_chunks), dim3(LOC_NT), 0, st, K,
-                     L, mu, ldm, y, ldy, inc, inc_step);
+                               cplx* y, int64_t ldy, const IncParams* inc, int inc_step, bool mixed) {
+  const dim3 grid(L.n_occ + L.n_mode_blocks + L.n_chunks);
+  if (mixed)
+    hipLaunchKernelGGL((k_local_apply_batch<NB, cplxf>), grid, dim3(LOC_NT), 0, st, K, L, mu, ldm, y, ldy, inc,
+                       inc_step);
+  else
+    hipLaunchKernelGGL((k_local_apply_batch<NB, cplx>), grid, dim3(LOC_NT), 0, st, K, L, mu, ldm, y, ldy, inc,
+                       inc_step);
 }
 
 // Forward maps of nrhs densities (column r at mu + r ldm, output at y + r ldy)
 // in groups of up to kBatchMax densities: one local launch per group reads the
 // near-field blocks and P once for the group, and each later stage is one
 // launch for the group.
-int sesm_accel_matvec_batch(sesm_ctx* ctx, int nrhs, const cplx* mu, int64_t ldm, cplx* y, int64_t ldy, int inc0) {
+int sesm_accel_matvec_batch(sesm_ctx* ctx, int nrhs, const cplx* mu, int64_t ldm, cplx* y, int64_t ldy, int inc0,
+                            bool mixed) {
   AccelOp* A = ctx->acc;
+  if (mixed && !A->p2e32) return ctx->fail(SESM_EINVAL, "mixed-precision map: surface set up without sesm_params.mixed");
   if (inc0 >= 0 && (inc0 + nrhs > A->n_inc || !A->inc_set))
     return ctx->fail(SESM_EINVAL, "incidence index beyond the incidence set");
   const KParams K = ctx->kparams();
@@ -2094,6 +2124,7 @@ int sesm_accel_matvec_batch(sesm_ctx* ctx, int nrhs, const cplx* mu, int64_t ldm
   }
   const MatvecBytes B = ctx->kt_mask ? matvec_bytes(ctx, false) : MatvecBytes{};  // per density (later stages)
   LocalArgs L = local_args(ctx, false);
+  if (mixed) L.P = A->p2e32;
   L.dens = base[0];
   L.mode_part = base[1];
   L.dens_ld = (int64_t)dens_n;
@@ -2138,10 +2169,10 @@ int sesm_accel_matvec_batch(sesm_ctx* ctx, int nrhs, const cplx* mu, int64_t ldm
       L.n_mode_blocks = modes ? NCH_MODES : 0;
     }
     switch (nb) {
-      case 1: launch_local_batch<1>(st, K, L, m0, ldm, y0, ldy, Fb.inc, Fb.inc_step); break;
-      case 2: launch_local_batch<2>(st, K, L, m0, ldm, y0, ldy, Fb.inc, Fb.inc_step); break;
-      case 3: launch_local_batch<3>(st, K, L, m0, ldm, y0, ldy, Fb.inc, Fb.inc_step); break;
-      default: launch_local_batch<4>(st, K, L, m0, ldm, y0, ldy, Fb.inc, Fb.inc_step); break;
+      case 1: launch_local_batch<1>(st, K, L, m0, ldm, y0, ldy, Fb.inc, Fb.inc_step, mixed); break;
+      case 2: launch_local_batch<2>(st, K, L, m0, ldm, y0, ldy, Fb.inc, Fb.inc_step, mixed); break;
+      case 3: launch_local_batch<3>(st, K, L, m0, ldm, y0, ldy, Fb.inc, Fb.inc_step, mixed); break;
+      default: launch_local_batch<4>(st, K, L, m0, ldm, y0, ldy, Fb.inc, Fb.inc_step, mixed); break;
     }
     SESM_LAUNCH_CHECK();
     Fb.nb = nb;
@@ -2151,7 +2182,9 @@ int sesm_accel_matvec_batch(sesm_ctx* ctx, int nrhs, const cplx* mu, int64_t ldm
   return SESM_OK;
 }
 
-int sesm_accel_matvec(sesm_ctx* ctx, const cplx* mu, cplx* y) { return accel_matvec_impl(ctx, mu, y, false); }
+int sesm_accel_matvec(sesm_ctx* ctx, const cplx* mu, cplx* y, bool mixed) {
+  return accel_matvec_impl(ctx, mu, y, false, mixed);
+}
 
 // give a block allocated with sesm_alloc back to the context's pool
 static void accel_release(sesm_ctx* ctx, void* p) {
@@ -2403,7 +2436,7 @@ extern "C" int sesm_diag_near(sesm_ctx* ctx, const sesm_c64* mu, sesm_c64* y) {
   SESM_HIP(hipSetDevice(ctx->device));
   AccelOp* A = ctx->acc;
   const LocalArgs L = local_args(ctx, true);
-  hipLaunchKernelGGL(k_local_apply, dim3(L.n_chunks), dim3(LOC_NT), 0, ctx->stream, ctx->kparams(), L,
+  hipLaunchKernelGGL(k_local_apply<cplx>, dim3(L.n_chunks), dim3(LOC_NT), 0, ctx->stream, ctx->kparams(), L,
                      (const cplx*)mu, (cplx*)y, A->inc_self);
   SESM_LAUNCH_CHECK();
   return SESM_OK;

@@ -229,6 +229,7 @@ void sesm_release_surface(sesm_ctx* ctx) {
   ctx->V_cols = 0;
   ctx->hcol = ctx->hpart = ctx->ybuf = ctx->wtmp = ctx->gw = ctx->Hrow = ctx->htri = ctx->hp = ctx->gcoef = nullptr;
   ctx->gsc = nullptr;
+  ctx->umix = ctx->mx_r = ctx->mx_R = ctx->mx_D = nullptr;
   ctx->ray_oc = nullptr;
   ctx->ray_B = nullptr;
   ctx->ray_cap = 0;
@@ -333,9 +334,10 @@ int sesm_apply(sesm_ctx* ctx, const cplx* mu, cplx* y) {
   return sesm_dense_matvec(ctx, mu, y);
 }
 
-int sesm_apply_inc(sesm_ctx* ctx, const cplx* mu, cplx* y, int inc) {
-  if (inc < 0) return sesm_apply(ctx, mu, y);
-  return sesm_accel_matvec_batch(ctx, 1, mu, ctx->P.N, y, ctx->P.N, inc);
+int sesm_apply_inc(sesm_ctx* ctx, const cplx* mu, cplx* y, int inc, bool mixed) {
+  if (mixed && ctx->P.mode != SESM_MODE_ACCEL) return ctx->fail(SESM_EINVAL, "mixed precision needs the accelerated mode");
+  if (inc < 0) return ctx->P.mode == SESM_MODE_ACCEL ? sesm_accel_matvec(ctx, mu, y, mixed) : sesm_dense_matvec(ctx, mu, y);
+  return sesm_accel_matvec_batch(ctx, 1, mu, ctx->P.N, y, ctx->P.N, inc, mixed);
 }
 
 // checks shared by the incidence-set entry points

@@ -22,13 +22,14 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "sesm_impl.h"
 
 namespace {
 
-constexpr int VT = 4;          // basis vectors per dot-product block
+constexpr int VB = 4;          // basis vectors per dot-product block
 constexpr int NCHUNK = 240;    // N-chunks of the single-vector norm reduction
 constexpr int DCHUNK = 16;     // N-chunks of the multi-vector dot products
 constexpr int STEP_NT = 1024;  // threads of the one-block Arnoldi step
@@ -45,54 +46,57 @@ __host__ __device__ inline int64_t hrow_off(int r, int m) {
 // part[(v DCHUNK + c) 2 + 1] = sum_{i in chunk c} conj(V_v[i]) w[i] (w optional),
 // v in [0, nv).  Loads are unconditional (vector index clamped, surplus terms
 // masked) so that all basis loads of an iteration are in flight together.
-__device__ __forceinline__ void gm_dots(int N, int nv, const cplx* __restrict__ V, int64_t ldv,
-                                        const cplx* __restrict__ u, const cplx* __restrict__ w,
+// VT: storage of the basis (cplx; cplxf for the FP32 bases of mixed-precision
+// solves); the sums are formed in FP64.
+template <typename VT>
+__device__ __forceinline__ void gm_dots(int N, int nv, const VT* __restrict__ V, int64_t ldv,
+                                        const VT* __restrict__ u, const cplx* __restrict__ w,
                                         cplx* __restrict__ part) {
-  __shared__ cplx sh[2][VT][4];
-  const int c = blockIdx.x, v0 = blockIdx.y * VT;
+  __shared__ cplx sh[2][VB][4];
+  const int c = blockIdx.x, v0 = blockIdx.y * VB;
   const int per = (N + DCHUNK - 1) / DCHUNK;
   const int lo = c * per, hi = min(N, lo + per);
   const bool has_w = w != nullptr;
-  const cplx* row[VT];
-  double msk[VT];
+  const VT* row[VB];
+  double msk[VB];
 #pragma unroll
-  for (int t = 0; t < VT; ++t) {
+  for (int t = 0; t < VB; ++t) {
     row[t] = V + (int64_t)min(v0 + t, nv - 1) * ldv;
     msk[t] = v0 + t < nv ? 1.0 : 0.0;
   }
-  cplx au[VT], aw[VT];
+  cplx au[VB], aw[VB];
 #pragma unroll
-  for (int t = 0; t < VT; ++t) au[t] = aw[t] = cplx{0.0, 0.0};
+  for (int t = 0; t < VB; ++t) au[t] = aw[t] = cplx{0.0, 0.0};
   // software pipelined: the loads of element i + 256 are issued before the
   // products of element i
   int i = lo + threadIdx.x;
-  cplx a[VT], ui = cplx{0.0, 0.0}, wi = cplx{0.0, 0.0};
+  cplx a[VB], ui = cplx{0.0, 0.0}, wi = cplx{0.0, 0.0};
   if (i < hi) {
 #pragma unroll
-    for (int t = 0; t < VT; ++t) a[t] = row[t][i];
-    ui = u[i];
+    for (int t = 0; t < VB; ++t) a[t] = widen(row[t][i]);
+    ui = widen(u[i]);
     wi = has_w ? w[i] : cplx{0.0, 0.0};
   }
   for (; i < hi; i += 256) {
     const int in = i + 256 < hi ? i + 256 : i;
-    cplx b[VT];
+    cplx b[VB];
 #pragma unroll
-    for (int t = 0; t < VT; ++t) b[t] = row[t][in];
-    const cplx un = u[in];
+    for (int t = 0; t < VB; ++t) b[t] = widen(row[t][in]);
+    const cplx un = widen(u[in]);
     const cplx wn = has_w ? w[in] : cplx{0.0, 0.0};
 #pragma unroll
-    for (int t = 0; t < VT; ++t) {
+    for (int t = 0; t < VB; ++t) {
       au[t] += cmul_conj(a[t], ui);
       aw[t] += cmul_conj(a[t], wi);
     }
 #pragma unroll
-    for (int t = 0; t < VT; ++t) a[t] = b[t];
+    for (int t = 0; t < VB; ++t) a[t] = b[t];
     ui = un;
     wi = wn;
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int t = 0; t < VT; ++t) {
+  for (int t = 0; t < VB; ++t) {
     const cplx s0 = wave_sum(au[t]);
     const cplx s1 = wave_sum(aw[t]);
     if (lane == 0) {
@@ -101,7 +105,7 @@ __device__ __forceinline__ void gm_dots(int N, int nv, const cplx* __restrict__ 
     }
   }
   __syncthreads();
-  if (threadIdx.x < 2 * VT) {
+  if (threadIdx.x < 2 * VB) {
     const int t = threadIdx.x >> 1, j = threadIdx.x & 1;
     if (v0 + t < nv)
       part[((int64_t)(v0 + t) * DCHUNK + c) * 2 + j] = sh[j][t][0] + sh[j][t][1] + sh[j][t][2] + sh[j][t][3];
@@ -243,13 +247,18 @@ __global__ __launch_bounds__(256) void k_gm_publish(int n, const cplx* __restric
 // The following ceil((k+1)/4) workgroups compute the first-pass coefficients
 // of column k, one wavefront per row r:
 // hp[r] = (c_r - sum_{j >= max(0, r-1)} H[r][j] cS[j]) / beta, c = (cZ, c_k).
+// With an FP32 basis (VT = cplxf) the new vectors are stored rounded and
+// unext (when given) receives u' as stored, widened to FP64: the input of
+// the next forward map, so that the Arnoldi relation holds for the stored basis.
 constexpr int UPD_ROWS = 64, UPD_B = 8;
-__device__ __forceinline__ void gm_update(int N, int k, int m, int nrb, cplx* V, int64_t ldv,
+template <typename VT>
+__device__ __forceinline__ void gm_update(int N, int k, int m, int nrb, VT* V, int64_t ldv,
                                           const cplx* __restrict__ cS, const cplx* __restrict__ cZ,
                                           const cplx* __restrict__ cC, const double* __restrict__ sc,
                                           const cplx* __restrict__ Hrow, cplx* __restrict__ hp,
                                           const cplx* __restrict__ w, const cplx* __restrict__ col,
-                                          cplx* __restrict__ hout, int64_t* flag, int64_t seq) {
+                                          cplx* __restrict__ hout, int64_t* flag, int64_t seq,
+                                          cplx* __restrict__ unext) {
   const int bid = blockIdx.x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (bid == (int)gridDim.x - 1) {  // the last workgroup hands the step's column to the host
@@ -279,7 +288,7 @@ __device__ __forceinline__ void gm_update(int N, int k, int m, int nrb, cplx* V,
     cplx x[UPD_B], a1[UPD_B], a2[UPD_B];
 #pragma unroll
     for (int t = 0; t < UPD_B; ++t) {
-      x[t] = V[(int64_t)(v + 4 * t) * ldv + i];
+      x[t] = widen(V[(int64_t)(v + 4 * t) * ldv + i]);
       a1[t] = cS[v + 4 * t];
       a2[t] = cC[v + 4 * t];
     }
@@ -290,7 +299,7 @@ __device__ __forceinline__ void gm_update(int N, int k, int m, int nrb, cplx* V,
     }
   }
   for (; v < k; v += 4) {
-    const cplx x = V[(int64_t)v * ldv + i];
+    const cplx x = widen(V[(int64_t)v * ldv + i]);
     s1 += x * cS[v];
     s2 += x * cC[v];
   }
@@ -302,16 +311,19 @@ __device__ __forceinline__ void gm_update(int N, int k, int m, int nrb, cplx* V,
     const cplx p2 = red[1][0][lane] + red[1][1][lane] + red[1][2][lane] + red[1][3][lane];
     const double inv = sc[0];
     const cplx a = cplx{sc[1], sc[2]};
-    const cplx u = V[(int64_t)k * ldv + i];
-    V[(int64_t)k * ldv + i] = inv * (u - p1);
-    V[(int64_t)(k + 1) * ldv + i] = inv * (w[i] - p2 - a * u);
+    const cplx u = widen(V[(int64_t)k * ldv + i]);
+    V[(int64_t)k * ldv + i] = narrow_to<VT>(inv * (u - p1));
+    const VT un = narrow_to<VT>(inv * (w[i] - p2 - a * u));
+    V[(int64_t)(k + 1) * ldv + i] = un;
+    if (unext) unext[i] = widen(un);
   }
 }
 
-__global__ __launch_bounds__(256) void k_gm_dots(int N, int nv, const cplx* __restrict__ V, int64_t ldv,
-                                                 const cplx* __restrict__ u, const cplx* __restrict__ w,
+template <typename VT>
+__global__ __launch_bounds__(256) void k_gm_dots(int N, int nv, const VT* __restrict__ V, int64_t ldv,
+                                                 const VT* __restrict__ u, const cplx* __restrict__ w,
                                                  cplx* __restrict__ part) {
-  gm_dots(N, nv, V, ldv, u, w, part);
+  gm_dots<VT>(N, nv, V, ldv, u, w, part);
 }
 __global__ __launch_bounds__(STEP_NT) void k_gm_step(int k, int m, const cplx* __restrict__ part,
                                                      const cplx* __restrict__ hp, cplx* __restrict__ Hrow,
@@ -320,13 +332,15 @@ __global__ __launch_bounds__(STEP_NT) void k_gm_step(int k, int m, const cplx* _
                                                      double* __restrict__ sc) {
   gm_step(k, m, part, hp, Hrow, hout, cS, cZ, cC, sc);
 }
-__global__ __launch_bounds__(256) void k_gm_update(int N, int k, int m, int nrb, cplx* V, int64_t ldv,
+template <typename VT>
+__global__ __launch_bounds__(256) void k_gm_update(int N, int k, int m, int nrb, VT* V, int64_t ldv,
                                                    const cplx* __restrict__ cS, const cplx* __restrict__ cZ,
                                                    const cplx* __restrict__ cC, const double* __restrict__ sc,
                                                    const cplx* __restrict__ Hrow, cplx* __restrict__ hp,
                                                    const cplx* __restrict__ w, const cplx* __restrict__ col,
-                                                   cplx* __restrict__ hout, int64_t* flag, int64_t seq) {
-  gm_update(N, k, m, nrb, V, ldv, cS, cZ, cC, sc, Hrow, hp, w, col, hout, flag, seq);
+                                                   cplx* __restrict__ hout, int64_t* flag, int64_t seq,
+                                                   cplx* __restrict__ unext) {
+  gm_update<VT>(N, k, m, nrb, V, ldv, cS, cZ, cC, sc, Hrow, hp, w, col, hout, flag, seq, unext);
 }
 
 // The systems of a batched solve: member q's buffers are the base pointers
@@ -335,8 +349,9 @@ __global__ __launch_bounds__(256) void k_gm_update(int N, int k, int m, int nrb,
 // members are the set bits of `active`; the i-th of them runs with sequence
 // number seq0 + i.
 struct GmBatch {
-  cplx* V;
+  void* V;           // bases, stored as cplx or cplxf (the kernels' VT)
   int64_t vstride;
+  cplx* U;           // FP32 bases: each member's next forward-map input (N each), else null
   cplx* W;
   cplx* small;
   int64_t sstride, o_hcol, o_hpart, o_hp, o_gcoef, o_gsc, o_Hrow;
@@ -355,11 +370,12 @@ __device__ inline int gm_nth_member(uint64_t mask, int i) {
 // Arnoldi step k of every active member (grid dimension z for the sweeps,
 // x for the one-workgroup step): the same bodies as the single-system
 // kernels, on the member's buffers.
+template <typename VT>
 __global__ __launch_bounds__(256) void k_gm_dots_batch(GmBatch B, int N, int k, int full) {
   const int q = gm_nth_member(B.active, blockIdx.z);
-  const cplx* V = B.V + q * B.vstride;
+  const VT* V = static_cast<const VT*>(B.V) + q * B.vstride;
   cplx* sm = B.small + q * B.sstride;
-  gm_dots(N, k + 1, V, N, V + (int64_t)k * N, full ? B.W + (int64_t)q * N : nullptr, sm + B.o_hpart);
+  gm_dots<VT>(N, k + 1, V, N, V + (int64_t)k * N, full ? B.W + (int64_t)q * N : nullptr, sm + B.o_hpart);
 }
 __global__ __launch_bounds__(STEP_NT) void k_gm_step_batch(GmBatch B, int k, int m) {
   const int q = gm_nth_member(B.active, blockIdx.x);
@@ -368,9 +384,10 @@ __global__ __launch_bounds__(STEP_NT) void k_gm_step_batch(GmBatch B, int k, int
   gm_step(k, m, sm + B.o_hpart, sm + B.o_hp, sm + B.o_Hrow, sm + B.o_hcol + (int64_t)(k % 2) * SESM_HSTRIDE, cS,
           cS + SESM_HSTRIDE, cS + 2 * SESM_HSTRIDE, reinterpret_cast<double*>(sm + B.o_gsc));
 }
+template <typename VT>
 __global__ __launch_bounds__(256) void k_gm_update_batch(GmBatch B, int N, int k, int m, int nrb) {
   const int i = blockIdx.z, q = gm_nth_member(B.active, i);
-  cplx* V = B.V + q * B.vstride;
+  VT* V = static_cast<VT*>(B.V) + q * B.vstride;
   cplx* sm = B.small + q * B.sstride;
   const cplx* cS = sm + B.o_gcoef;
   cplx* ring = B.pin + q * B.pstride;
@@ -378,7 +395,7 @@ __global__ __launch_bounds__(256) void k_gm_update_batch(GmBatch B, int N, int k
   int64_t* flags = reinterpret_cast<int64_t*>(ring + (int64_t)(SESM_HRING + 1) * SESM_HSTRIDE);
   gm_update(N, k, m, nrb, V, N, cS, cS + SESM_HSTRIDE, cS + 2 * SESM_HSTRIDE, reinterpret_cast<const double*>(sm + B.o_gsc),
             sm + B.o_Hrow, sm + B.o_hp, B.W + (int64_t)q * N, sm + B.o_hcol + (int64_t)(k % 2) * SESM_HSTRIDE,
-            ring + (int64_t)slot * SESM_HSTRIDE, flags + slot, B.seq0 + i);
+            ring + (int64_t)slot * SESM_HSTRIDE, flags + slot, B.seq0 + i, B.U ? B.U + (int64_t)q * N : nullptr);
 }
 // the last step of a cycle (no update follows): each member publishes its column
 __global__ __launch_bounds__(256) void k_gm_publish_batch(GmBatch B, int k) {
@@ -400,7 +417,8 @@ __global__ __launch_bounds__(256) void k_hess_gather(int m, const cplx* __restri
 }
 
 // x[i] += sum_{v < nv} V_v[i] y[v]
-__global__ __launch_bounds__(256) void k_combine(int N, int nv, const cplx* __restrict__ V, int64_t ldv,
+template <typename VT>
+__global__ __launch_bounds__(256) void k_combine(int N, int nv, const VT* __restrict__ V, int64_t ldv,
                                                  const cplx* __restrict__ y, cplx* __restrict__ x) {
   extern __shared__ cplx ys[];
   for (int v = threadIdx.x; v < nv; v += 256) ys[v] = y[v];
@@ -408,8 +426,25 @@ __global__ __launch_bounds__(256) void k_combine(int N, int nv, const cplx* __re
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= N) return;
   cplx s = x[i];
-  for (int v = 0; v < nv; ++v) s += V[(int64_t)v * ldv + i] * ys[v];
+  for (int v = 0; v < nv; ++v) s += widen(V[(int64_t)v * ldv + i]) * ys[v];
   x[i] = s;
+}
+
+// The first basis vector from r: V0 = r as stored (VT) and, for an FP32
+// basis, u0 = that value widened (the first forward-map input).
+template <typename VT>
+__global__ void k_basis0(int N, const cplx* __restrict__ r, VT* __restrict__ V0, cplx* __restrict__ u0) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const VT v = narrow_to<VT>(r[i]);
+  V0[i] = v;
+  if (u0) u0[i] = widen(v);
+}
+
+// x += d; r = b - r (a forward map's output in r)
+__global__ void k_axpy1(int N, cplx* __restrict__ x, const cplx* __restrict__ d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) x[i] = x[i] + d[i];
 }
 
 __global__ __launch_bounds__(256) void k_norm2_part(int N, const cplx* __restrict__ w, double* __restrict__ part) {
@@ -456,6 +491,47 @@ inline bool is_column_sentinel(double v) {
 // entries of the gathered columns 0..m-1 (column j holds j + 2)
 inline int64_t m_tri(int m) { return m > 0 ? (int64_t)m * (m + 3) / 2 : 0; }
 
+// The small per-context buffers of a solve (Hessenberg column ring, partial
+// sums, step scalars, work vectors of N) and the pinned host slots; kept
+// until the surface is released.
+int ensure_small(sesm_ctx* ctx) {
+  const int N = ctx->P.N;
+  int rc;
+  if (!ctx->hcol) {
+    if ((rc = sesm_alloc(ctx, (void**)&ctx->hcol, sizeof(cplx) * SESM_HRING * SESM_HSTRIDE))) return rc;
+    if ((rc = sesm_alloc(ctx, (void**)&ctx->hpart, sizeof(cplx) * (size_t)2 * SESM_HSTRIDE * DCHUNK))) return rc;
+    if ((rc = sesm_alloc(ctx, (void**)&ctx->ybuf, sizeof(cplx) * SESM_HSTRIDE))) return rc;
+    if ((rc = sesm_alloc(ctx, (void**)&ctx->hp, sizeof(cplx) * SESM_HSTRIDE))) return rc;
+    if ((rc = sesm_alloc(ctx, (void**)&ctx->gcoef, sizeof(cplx) * 3 * SESM_HSTRIDE))) return rc;
+    if ((rc = sesm_alloc(ctx, (void**)&ctx->gsc, sizeof(double) * 8))) return rc;
+    if ((rc = sesm_alloc(ctx, (void**)&ctx->wtmp, sizeof(cplx) * (size_t)N))) return rc;
+    if ((rc = sesm_alloc(ctx, (void**)&ctx->gw, sizeof(cplx) * (size_t)N))) return rc;
+    if ((rc = sesm_alloc(ctx, (void**)&ctx->umix, sizeof(cplx) * (size_t)N)) ||
+        (rc = sesm_alloc(ctx, (void**)&ctx->mx_r, sizeof(cplx) * (size_t)N)) ||
+        (rc = sesm_alloc(ctx, (void**)&ctx->mx_R, sizeof(cplx) * (size_t)N)) ||
+        (rc = sesm_alloc(ctx, (void**)&ctx->mx_D, sizeof(cplx) * (size_t)N)))
+      return rc;
+  }
+  if (!ctx->hhost || !ctx->hflag) {
+    // columns and their flags in coherent pinned memory, written by the update
+    // launch (kept for the context's lifetime)
+    if (ctx->hhost) (void)hipHostFree(ctx->hhost);
+    if (ctx->hflag) (void)hipHostFree(ctx->hflag);
+    ctx->hhost = nullptr;
+    ctx->hflag = nullptr;
+    if (hipHostMalloc((void**)&ctx->hhost, sizeof(cplx) * (SESM_HRING + 1) * SESM_HSTRIDE, hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipHostMalloc((void**)&ctx->hflag, sizeof(int64_t) * SESM_HRING, hipHostMallocCoherent) != hipSuccess)
+      return ctx->fail(SESM_ENOMEM, "hipHostMalloc failed");
+    for (int t = 0; t < SESM_HRING; ++t) ctx->hflag[t] = 0;
+    double* hv = reinterpret_cast<double*>(ctx->hhost);
+    for (size_t t = 0; t < (size_t)2 * SESM_HRING * SESM_HSTRIDE; ++t) hv[t] = column_sentinel();
+    SESM_HIP(hipHostGetDevicePointer((void**)&ctx->hhost_dev, ctx->hhost, 0));
+    SESM_HIP(hipHostGetDevicePointer((void**)&ctx->hflag_dev, ctx->hflag, 0));
+  }
+  return SESM_OK;
+}
+
 int ensure_workspace(sesm_ctx* ctx, int m) {
   const int N = ctx->P.N;
   if (ctx->V && ctx->V_cols >= m + 1 && ctx->Hrow_m == m) return SESM_OK;
@@ -485,33 +561,7 @@ int ensure_workspace(sesm_ctx* ctx, int m) {
   if ((rc = sesm_alloc(ctx, (void**)&ctx->Hrow, sizeof(cplx) * (size_t)ctx->Hrow_len))) return rc;
   if ((rc = sesm_alloc(ctx, (void**)&ctx->htri, sizeof(cplx) * (size_t)m_tri(m)))) return rc;
   ctx->Hrow_m = m;
-  if (!ctx->hcol) {
-    if ((rc = sesm_alloc(ctx, (void**)&ctx->hcol, sizeof(cplx) * SESM_HRING * SESM_HSTRIDE))) return rc;
-    if ((rc = sesm_alloc(ctx, (void**)&ctx->hpart, sizeof(cplx) * (size_t)2 * SESM_HSTRIDE * DCHUNK))) return rc;
-    if ((rc = sesm_alloc(ctx, (void**)&ctx->ybuf, sizeof(cplx) * SESM_HSTRIDE))) return rc;
-    if ((rc = sesm_alloc(ctx, (void**)&ctx->hp, sizeof(cplx) * SESM_HSTRIDE))) return rc;
-    if ((rc = sesm_alloc(ctx, (void**)&ctx->gcoef, sizeof(cplx) * 3 * SESM_HSTRIDE))) return rc;
-    if ((rc = sesm_alloc(ctx, (void**)&ctx->gsc, sizeof(double) * 8))) return rc;
-    if ((rc = sesm_alloc(ctx, (void**)&ctx->wtmp, sizeof(cplx) * (size_t)N))) return rc;
-    if ((rc = sesm_alloc(ctx, (void**)&ctx->gw, sizeof(cplx) * (size_t)N))) return rc;
-  }
-  if (!ctx->hhost || !ctx->hflag) {
-    // columns and their flags in coherent pinned memory, written by the update
-    // launch (kept for the context's lifetime)
-    if (ctx->hhost) (void)hipHostFree(ctx->hhost);
-    if (ctx->hflag) (void)hipHostFree(ctx->hflag);
-    ctx->hhost = nullptr;
-    ctx->hflag = nullptr;
-    if (hipHostMalloc((void**)&ctx->hhost, sizeof(cplx) * (SESM_HRING + 1) * SESM_HSTRIDE, hipHostMallocCoherent) !=
-            hipSuccess ||
-        hipHostMalloc((void**)&ctx->hflag, sizeof(int64_t) * SESM_HRING, hipHostMallocCoherent) != hipSuccess)
-      return ctx->fail(SESM_ENOMEM, "hipHostMalloc failed");
-    for (int t = 0; t < SESM_HRING; ++t) ctx->hflag[t] = 0;
-    double* hv = reinterpret_cast<double*>(ctx->hhost);
-    for (size_t t = 0; t < (size_t)2 * SESM_HRING * SESM_HSTRIDE; ++t) hv[t] = column_sentinel();
-    SESM_HIP(hipHostGetDevicePointer((void**)&ctx->hhost_dev, ctx->hhost, 0));
-    SESM_HIP(hipHostGetDevicePointer((void**)&ctx->hflag_dev, ctx->hflag, 0));
-  }
+  if ((rc = ensure_small(ctx))) return rc;
   return SESM_OK;
 }
 
@@ -597,9 +647,10 @@ static int gm_rel_norm(sesm_ctx* ctx, const cplx* r, double bnorm, double* out) 
   return SESM_OK;
 }
 
-// r = b - A x (one forward map; the operator of incidence inc, or the surface's own when inc < 0)
-static int gm_residual(sesm_ctx* ctx, const cplx* b, const cplx* x, cplx* r, int inc) {
-  const int rc = sesm_apply_inc(ctx, x, r, inc);
+// r = b - A x (one forward map; the operator of incidence inc, or the
+// surface's own when inc < 0; mixed: the mixed-precision map)
+static int gm_residual(sesm_ctx* ctx, const cplx* b, const cplx* x, cplx* r, int inc, bool mixed = false) {
+  const int rc = sesm_apply_inc(ctx, x, r, inc, mixed);
   if (rc) return rc;
   const int N = ctx->P.N;
   hipLaunchKernelGGL(k_sub_from, dim3((N + 255) / 256), dim3(256), 0, ctx->stream, N, b, r);
@@ -613,8 +664,13 @@ static int gm_residual(sesm_ctx* ctx, const cplx* b, const cplx* x, cplx* r, int
 // residual must at least halve it, otherwise the forward map's rounding floor
 // has been reached and the solve stops.
 // inc >= 0: the operator and incident field of member inc of the incidence set.
-static int solve_impl(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out, double tol, int32_t max_iter,
-                      int32_t restart, int32_t flags, double prev_true, sesm_solve_info* info, int inc = -1) {
+// VT: storage of the Krylov basis.  With VT = cplxf (the inner solves of a
+// mixed-precision solve) the forward map is the mixed-precision one when
+// mixed is set, and its input is the FP64 mirror ctx->umix of the current
+// basis vector.
+template <typename VT>
+static int solve_impl_t(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out, double tol, int32_t max_iter,
+                        int32_t restart, int32_t flags, double prev_true, sesm_solve_info* info, int inc, bool mixed) {
   if (!ctx) return SESM_EINVAL;
   if (!ctx->ready) return ctx->fail(SESM_ENOSURF, "no surface");
   if (!mu_out || !(tol > 0) || max_iter < 1 || max_iter > 100000 || restart < 0 || (flags & ~SESM_SOLVE_X0))
@@ -629,8 +685,11 @@ static int solve_impl(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out, dou
   hipStream_t st = ctx->stream;
   const int nb = (N + 255) / 256;
   cplx* x = (cplx*)mu_out;
-  cplx* V = ctx->V;
+  VT* V = reinterpret_cast<VT*>(ctx->V);  // (the allocation holds (m + 1) N complex FP64 values)
   const int64_t ldv = N;
+  constexpr bool f32 = !std::is_same<VT, cplx>::value;
+  cplx* um = f32 ? ctx->umix : nullptr;                           // FP64 mirror of the current basis vector
+  cplx* rb = f32 ? ctx->mx_r : reinterpret_cast<cplx*>(V);       // where the residual is formed (V_0 itself for FP64)
   cplx* cS = ctx->gcoef;
   cplx* cZ = cS + SESM_HSTRIDE;
   cplx* cC = cZ + SESM_HSTRIDE;
@@ -662,15 +721,15 @@ static int solve_impl(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out, dou
   // slot k % SESM_HRING and then to the host.
   auto arnoldi = [&](int k, int steps) -> int {
     const bool full = k < steps;
-    cplx* u = V + (int64_t)k * ldv;
+    VT* u = V + (int64_t)k * ldv;
     if (full) {
-      const int r = sesm_apply_inc(ctx, u, ctx->gw, inc);
+      const int r = sesm_apply_inc(ctx, f32 ? um : reinterpret_cast<const cplx*>(u), ctx->gw, inc, mixed);
       if (r) return r;
     }
     const int nv = k + 1, slot = k % SESM_HRING;
-    const double c16 = sizeof(cplx);
+    const double c16 = sizeof(VT);
     SESM_KT_BEGIN(SESM_KT_DOTS, st);
-    hipLaunchKernelGGL(k_gm_dots, dim3(DCHUNK, (nv + VT - 1) / VT), dim3(256), 0, st, N, nv, V, ldv, u,
+    hipLaunchKernelGGL(k_gm_dots<VT>, dim3(DCHUNK, (nv + VB - 1) / VB), dim3(256), 0, st, N, nv, V, ldv, u,
                        full ? ctx->gw : nullptr, ctx->hpart);
     SESM_LAUNCH_CHECK();
     // basis (u among it), w, partials
@@ -689,8 +748,9 @@ static int solve_impl(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out, dou
     if (full) {
       const int nrb = (N + UPD_ROWS - 1) / UPD_ROWS;
       SESM_KT_BEGIN(SESM_KT_UPDATE, st);
-      hipLaunchKernelGGL(k_gm_update, dim3(nrb + (k + 1 + 3) / 4 + 1), dim3(256), 0, st, N, k, m, nrb, V, ldv, cS,
-                         cZ, cC, ctx->gsc, ctx->Hrow, ctx->hp, ctx->gw, colv, hout, ctx->hflag_dev + slot, seq);
+      hipLaunchKernelGGL(k_gm_update<VT>, dim3(nrb + (k + 1 + 3) / 4 + 1), dim3(256), 0, st, N, k, m, nrb, V, ldv,
+                         cS, cZ, cC, ctx->gsc, ctx->Hrow, ctx->hp, ctx->gw, colv, hout, ctx->hflag_dev + slot, seq,
+                         um);
       SESM_LAUNCH_CHECK();
       // basis V_0..V_{k-1}, u and w read; q_k and u' written
       SESM_KT_END(SESM_KT_UPDATE, st, c16 * ((double)k * N + 4.0 * N));
@@ -727,10 +787,14 @@ static int solve_impl(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out, dou
     // u_0 = r = b - A x
     if (!r_in_v0) {
       if (x_zero) {
-        SESM_HIP(hipMemcpyAsync(V, b, sizeof(cplx) * (size_t)N, hipMemcpyDeviceToDevice, st));
-      } else if ((rc = gm_residual(ctx, b, x, V, inc))) {
+        SESM_HIP(hipMemcpyAsync(rb, b, sizeof(cplx) * (size_t)N, hipMemcpyDeviceToDevice, st));
+      } else if ((rc = gm_residual(ctx, b, x, rb, inc, mixed))) {
         return rc;
       }
+    }
+    if (f32) {  // the stored first vector and its FP64 mirror
+      hipLaunchKernelGGL(k_basis0<VT>, dim3(nb), dim3(256), 0, st, N, rb, V, um);
+      SESM_LAUNCH_CHECK();
     }
     r_in_v0 = false;
     std::fill(g.begin(), g.end(), 0.0);
@@ -811,15 +875,15 @@ static int solve_impl(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out, dou
     cplx* yh = hup;  // idle: each cycle ends synchronised
     for (int t = 0; t < nv; ++t) yh[t] = cplx{y[t].real(), y[t].imag()};
     SESM_HIP(hipMemcpyAsync(ctx->ybuf, yh, sizeof(cplx) * nv, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), sizeof(cplx) * nv, st, N, nv, V, ldv, ctx->ybuf, x);
+    hipLaunchKernelGGL(k_combine<VT>, dim3(nb), dim3(256), sizeof(cplx) * nv, st, N, nv, V, ldv, ctx->ybuf, x);
     SESM_LAUNCH_CHECK();
     total += nv;
     x_zero = false;
     // the residual of the new x (the next cycle's u_0)
-    if ((rc = gm_residual(ctx, b, x, V, inc))) return rc;
+    if ((rc = gm_residual(ctx, b, x, rb, inc, mixed))) return rc;
     r_in_v0 = true;
     if (est <= cyc_tol || total >= max_iter) {  // the estimate is met (or no iteration is left): check the true residual
-      if ((rc = gm_rel_norm(ctx, V, bnorm, &res_true))) return rc;
+      if ((rc = gm_rel_norm(ctx, rb, bnorm, &res_true))) return rc;
       if (res_true <= tol || total >= max_iter) break;
       // The estimate was optimistic.  A restart from the true residual helps
       // when the Krylov recurrence drifted (lost orthogonality, a clamped
@@ -842,8 +906,89 @@ static int solve_impl(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out, dou
   return SESM_OK;
 }
 
+static int solve_impl(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out, double tol, int32_t max_iter,
+                      int32_t restart, int32_t flags, double prev_true, sesm_solve_info* info, int inc = -1) {
+  return solve_impl_t<cplx>(ctx, b_in, mu_out, tol, max_iter, restart, flags, prev_true, info, inc, false);
+}
+
+// Mixed precision (SESM_SOLVE_MIXED): FP64 iterative refinement around inner
+// GMRES solves with an FP32 Krylov basis and the mixed-precision forward map
+// (EqSources operators in FP32): r = b - A x with the FP64 map; the inner solve
+// reduces ||A_mixed d - r|| by the factor tau = max(tol ||b|| / (2 ||r||), 1e-4)
+// (a reduction an FP32 basis reaches reliably); x += d; repeated while the FP64
+// residual at least halves.
+constexpr double kMixedInnerFloor = 1e-4;
+static int solve_mixed(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out, double tol, int32_t max_iter,
+                       int32_t restart, int32_t flags, sesm_solve_info* info, int inc) {
+  if (!ctx->ready) return ctx->fail(SESM_ENOSURF, "no surface");
+  if (ctx->P.mode != SESM_MODE_ACCEL) return ctx->fail(SESM_EINVAL, "mixed precision needs the accelerated mode");
+  if (!mu_out || !(tol > 0) || max_iter < 1 || max_iter > 100000 || restart < 0)
+    return ctx->fail(SESM_EINVAL, "bad solve arguments");
+  SESM_HIP(hipSetDevice(ctx->device));
+  const int N = ctx->P.N;
+  const int m = (restart == 0 || restart > max_iter) ? max_iter : restart;
+  if (m > 4000) return ctx->fail(SESM_EINVAL, "Krylov dimension above 4000; use restart");
+  int rc = ensure_workspace(ctx, m);
+  if (rc) return rc;
+  hipStream_t st = ctx->stream;
+  const int nb = (N + 255) / 256;
+  cplx* x = (cplx*)mu_out;
+  const cplx* b = (const cplx*)b_in;
+  if (!b) {
+    if ((rc = inc < 0 ? sesm_rhs(ctx, (sesm_c64*)ctx->wtmp) : sesm_rhs_incidence(ctx, inc, (sesm_c64*)ctx->wtmp)))
+      return rc;
+    b = ctx->wtmp;
+  }
+  double bnorm = 0.0;
+  if ((rc = gm_rel_norm(ctx, b, 0.0, &bnorm))) return rc;
+  if (!(flags & SESM_SOLVE_X0) || bnorm == 0.0) SESM_HIP(hipMemsetAsync(x, 0, sizeof(cplx) * (size_t)N, st));
+  sesm_solve_info inf{};
+  if (bnorm == 0.0) {
+    SESM_HIP(hipStreamSynchronize(st));
+    inf.converged = 1;
+    if (info) *info = inf;
+    return SESM_OK;
+  }
+  cplx* R = ctx->mx_R;
+  cplx* D = ctx->mx_D;
+  double rel = 1.0;
+  if ((rc = gm_residual(ctx, b, x, R, inc, false)) || (rc = gm_rel_norm(ctx, R, bnorm, &rel))) return rc;
+  int total = 0, outer = 0, mism = 0;
+  double est = rel;
+  while (rel > tol && total < max_iter) {
+    const double tau = std::max(0.5 * tol / rel, kMixedInnerFloor);
+    sesm_solve_info in{};
+    rc = solve_impl_t<cplxf>(ctx, (const sesm_c64*)R, (sesm_c64*)D, tau, max_iter - total, restart, 0, INFINITY, &in,
+                             inc, true);
+    if (rc && rc != SESM_ENOCONV) return rc;
+    total += in.iters;
+    mism += in.column_mismatches;
+    ++outer;
+    est = in.est_residual * rel;
+    hipLaunchKernelGGL(k_axpy1, dim3(nb), dim3(256), 0, st, N, x, D);
+    SESM_LAUNCH_CHECK();
+    double rel_new = 1.0;
+    if ((rc = gm_residual(ctx, b, x, R, inc, false)) || (rc = gm_rel_norm(ctx, R, bnorm, &rel_new))) return rc;
+    const bool progress = rel_new < 0.5 * rel;
+    rel = rel_new;
+    if (!progress || in.iters == 0) break;
+  }
+  inf.iters = total;
+  inf.rel_residual = rel;
+  inf.est_residual = est;
+  inf.residual_restarts = outer;
+  inf.column_mismatches = mism;
+  inf.converged = rel <= tol ? 1 : 0;
+  if (info) *info = inf;
+  if (!inf.converged) return ctx->fail(SESM_ENOCONV, "mixed-precision GMRES did not reach the tolerance");
+  return SESM_OK;
+}
+
 extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out, double tol, int32_t max_iter,
                           int32_t restart, int32_t flags, sesm_solve_info* info) {
+  if (!ctx) return SESM_EINVAL;
+  if (flags & SESM_SOLVE_MIXED)
+    return solve_mixed(ctx, b_in, mu_out, tol, max_iter, restart, flags & ~SESM_SOLVE_MIXED, info, -1);
   return solve_impl(ctx, b_in, mu_out, tol, max_iter, restart, flags, INFINITY, info);
 }
 
@@ -863,7 +1008,8 @@ void gm_release(sesm_ctx* ctx, void* p) {
 // One system of a batched solve: its device buffers (inside the batch's
 // shared allocations) and its host-side state.
 struct GmMember {
-  cplx *V, *w, *x;  // basis (m + 1) x N, A u, solution
+  void* V;          // basis (m + 1) x N, stored as the solve's VT
+  cplx *w, *x;      // A u, solution
   const cplx* b;
   cplx *hcol, *hpart, *ybuf, *Hrow, *htri;  // (the step kernels derive the rest from GmBatch)
   cplx* hhost;  // pinned ring slots (+ one upload slot) and their flags
@@ -879,10 +1025,14 @@ struct GmMember {
 }  // namespace
 
 // inc0 >= 0: system r uses the operator of member inc0 + r of the incidence
-// set (b may then be NULL: each member's incident field)
+// set (b may then be NULL: each member's incident field).  VT: storage of the
+// bases (cplxf: the inner solves of mixed precision, whose forward maps are
+// the mixed-precision ones when mixed is set and read the FP64 mirrors Umir).
+template <typename VT>
 static int solve_batch_impl(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_in, int64_t ld_b, sesm_c64* mu_out,
                             int64_t ld_mu, double tol, int32_t max_iter, int32_t flags, sesm_solve_info* info,
-                            int inc0) {
+                            int inc0, bool mixed = false) {
+  constexpr bool f32 = !std::is_same<VT, cplx>::value;
   if (!ctx) return SESM_EINVAL;
   if (!ctx->ready) return ctx->fail(SESM_ENOSURF, "no surface");
   if (nrhs < 0 || nrhs > SESM_MAX_BATCH || !(tol > 0) || max_iter < 1 || max_iter > 4000 ||
@@ -910,7 +1060,8 @@ static int solve_batch_impl(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_in, i
                 o_ybuf = o_hpart + r16((int64_t)2 * SESM_HSTRIDE * DCHUNK), o_hp = o_ybuf + r16(SESM_HSTRIDE),
                 o_gcoef = o_hp + r16(SESM_HSTRIDE), o_gsc = o_gcoef + r16(3 * SESM_HSTRIDE), o_Hrow = o_gsc + 16,
                 o_htri = o_Hrow + r16(hrow_len), per_small = o_htri + r16(m_tri(m));
-  cplx *Vall = nullptr, *Wall = nullptr, *small = nullptr;
+  VT* Vall = nullptr;
+  cplx *Wall = nullptr, *small = nullptr, *Umir = nullptr;
   cplx* pin = nullptr;
   int rc = SESM_OK;
   std::vector<GmMember> M(nrhs);
@@ -920,6 +1071,7 @@ static int solve_batch_impl(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_in, i
     gm_release(ctx, Vall);
     gm_release(ctx, Wall);
     gm_release(ctx, small);
+    gm_release(ctx, Umir);
     return code;
   };
   // the members' incident fields when no right-hand sides are given (kept
@@ -937,9 +1089,10 @@ static int solve_batch_impl(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_in, i
     b_in = (const sesm_c64*)Ball;
     ld_b = N;
   }
-  if ((rc = sesm_alloc(ctx, (void**)&Vall, sizeof(cplx) * (size_t)nrhs * vstride)) ||
+  if ((rc = sesm_alloc(ctx, (void**)&Vall, sizeof(VT) * (size_t)nrhs * vstride)) ||
       (rc = sesm_alloc(ctx, (void**)&Wall, sizeof(cplx) * (size_t)nrhs * N)) ||
-      (rc = sesm_alloc(ctx, (void**)&small, sizeof(cplx) * (size_t)nrhs * per_small)))
+      (rc = sesm_alloc(ctx, (void**)&small, sizeof(cplx) * (size_t)nrhs * per_small)) ||
+      (f32 && (rc = sesm_alloc(ctx, (void**)&Umir, sizeof(cplx) * (size_t)nrhs * N))))
     return finish_all(rc);
   const size_t pin_per = (size_t)(SESM_HRING + 1) * SESM_HSTRIDE + SESM_HRING;  // slots, then flags (as cplx)
   if (hipHostMalloc((void**)&pin, sizeof(cplx) * pin_per * nrhs, hipHostMallocCoherent) != hipSuccess) {
@@ -989,25 +1142,27 @@ static int solve_batch_impl(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_in, i
   if (warm) {
     int r2 = SESM_OK;
     if (ctx->P.mode == SESM_MODE_ACCEL)
-      r2 = sesm_accel_matvec_batch(ctx, nrhs, (const cplx*)mu_out, ld_mu, Wall, N, inc0);
+      r2 = sesm_accel_matvec_batch(ctx, nrhs, (const cplx*)mu_out, ld_mu, Wall, N, inc0, mixed);
     else
       for (int r = 0; r < nrhs && !r2; ++r) r2 = sesm_dense_matvec(ctx, M[r].x, M[r].w);
     if (r2) return finish_all(r2);
   }
   for (int r = 0; r < nrhs; ++r) {
     GmMember& G = M[r];
+    cplx* um = f32 ? Umir + (int64_t)r * N : nullptr;
     if (warm && G.bnorm != 0.0) {
       hipLaunchKernelGGL(k_sub_from, dim3(nb), dim3(256), 0, st, N, G.b, G.w);
-      if (hipGetLastError() != hipSuccess ||
-          hipMemcpyAsync(G.V, G.w, sizeof(cplx) * (size_t)N, hipMemcpyDeviceToDevice, st) != hipSuccess)
-        return finish_all(ctx->fail(SESM_EHIP, "batched solve: initial residual failed"));
-    } else if (hipMemcpyAsync(G.V, G.b, sizeof(cplx) * (size_t)N, hipMemcpyDeviceToDevice, st) != hipSuccess ||
-               hipMemsetAsync(G.x, 0, sizeof(cplx) * (size_t)N, st) != hipSuccess) {
-      return finish_all(ctx->fail(SESM_EHIP, "batched solve: initial copies failed"));
+      hipLaunchKernelGGL(k_basis0<VT>, dim3(nb), dim3(256), 0, st, N, G.w, (VT*)G.V, um);
+      if (hipGetLastError() != hipSuccess) return finish_all(ctx->fail(SESM_EHIP, "batched solve: initial residual failed"));
+    } else {
+      hipLaunchKernelGGL(k_basis0<VT>, dim3(nb), dim3(256), 0, st, N, G.b, (VT*)G.V, um);
+      if (hipGetLastError() != hipSuccess || hipMemsetAsync(G.x, 0, sizeof(cplx) * (size_t)N, st) != hipSuccess)
+        return finish_all(ctx->fail(SESM_EHIP, "batched solve: initial copies failed"));
     }
   }
   GmBatch GB0{};
   GB0.V = Vall;
+  GB0.U = Umir;
   GB0.vstride = vstride;
   GB0.W = Wall;
   GB0.small = small;
@@ -1033,11 +1188,14 @@ static int solve_batch_impl(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_in, i
     if (full) {
       int r2;
       if (ctx->P.mode == SESM_MODE_ACCEL)
-        r2 = sesm_accel_matvec_batch(ctx, hi - lo + 1, Vall + lo * vstride + (int64_t)k * ldv, vstride,
-                                     Wall + (int64_t)lo * N, N, inc0 < 0 ? -1 : inc0 + lo);
+        r2 = f32 ? sesm_accel_matvec_batch(ctx, hi - lo + 1, Umir + (int64_t)lo * N, N, Wall + (int64_t)lo * N, N,
+                                           inc0 < 0 ? -1 : inc0 + lo, mixed)
+                 : sesm_accel_matvec_batch(ctx, hi - lo + 1, (const cplx*)(Vall + lo * vstride + (int64_t)k * ldv),
+                                           vstride, Wall + (int64_t)lo * N, N, inc0 < 0 ? -1 : inc0 + lo, mixed);
       else {
         r2 = SESM_OK;
-        for (int r = lo; r <= hi && !r2; ++r) r2 = sesm_dense_matvec(ctx, M[r].V + (int64_t)k * ldv, M[r].w);
+        for (int r = lo; r <= hi && !r2; ++r)
+          r2 = sesm_dense_matvec(ctx, (const cplx*)M[r].V + (int64_t)k * ldv, M[r].w);  // (FP64 bases only)
       }
       if (r2) return r2;
     }
@@ -1054,7 +1212,7 @@ static int solve_batch_impl(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_in, i
         M[r].slot_seq[slot] = GB.seq0 + na++;
       }
     ctx->gm_seq += na;
-    hipLaunchKernelGGL(k_gm_dots_batch, dim3(DCHUNK, (k + 1 + VT - 1) / VT, na), dim3(256), 0, st, GB, N, k,
+    hipLaunchKernelGGL(k_gm_dots_batch<VT>, dim3(DCHUNK, (k + 1 + VB - 1) / VB, na), dim3(256), 0, st, GB, N, k,
                        full ? 1 : 0);
     SESM_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_gm_step_batch, dim3(na), dim3(STEP_NT), 0, st, GB, k, m);
@@ -1063,7 +1221,7 @@ static int solve_batch_impl(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_in, i
       hipLaunchKernelGGL(k_gm_publish_batch, dim3(na), dim3(256), 0, st, GB, k);
     } else {
       const int nrb = (N + UPD_ROWS - 1) / UPD_ROWS;
-      hipLaunchKernelGGL(k_gm_update_batch, dim3(nrb + (k + 1 + 3) / 4 + 1, 1, na), dim3(256), 0, st, GB, N, k, m,
+      hipLaunchKernelGGL(k_gm_update_batch<VT>, dim3(nrb + (k + 1 + 3) / 4 + 1, 1, na), dim3(256), 0, st, GB, N, k, m,
                          nrb);
     }
     SESM_LAUNCH_CHECK();
@@ -1146,7 +1304,8 @@ static int solve_batch_impl(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_in, i
     for (int t = 0; t < nv; ++t) yh[t] = cplx{y[t].real(), y[t].imag()};
     if (hipMemcpyAsync(G.ybuf, yh, sizeof(cplx) * nv, hipMemcpyHostToDevice, st) != hipSuccess)
       return finish_all(ctx->fail(SESM_EHIP, "batched solve: upload failed"));
-    hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), sizeof(cplx) * nv, st, N, nv, G.V, ldv, G.ybuf, G.x);
+    hipLaunchKernelGGL(k_combine<VT>, dim3(nb), dim3(256), sizeof(cplx) * nv, st, N, nv, (const VT*)G.V, ldv, G.ybuf,
+                       G.x);
     if (hipGetLastError() != hipSuccess) return finish_all(ctx->fail(SESM_EHIP, "batched solve: launch failed"));
     if (hipStreamSynchronize(st) != hipSuccess) return finish_all(ctx->fail(SESM_EHIP, "batched solve: combine failed"));
   }
@@ -1156,7 +1315,7 @@ static int solve_batch_impl(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_in, i
   {
     int r2 = SESM_OK;
     if (ctx->P.mode == SESM_MODE_ACCEL)
-      r2 = sesm_accel_matvec_batch(ctx, nrhs, (const cplx*)mu_out, ld_mu, Wall, N, inc0);
+      r2 = sesm_accel_matvec_batch(ctx, nrhs, (const cplx*)mu_out, ld_mu, Wall, N, inc0, mixed);
     else
       for (int r = 0; r < nrhs && !r2; ++r)
         if (M[r].nv > 0) r2 = sesm_dense_matvec(ctx, M[r].x, M[r].w);
@@ -1187,8 +1346,8 @@ static int solve_batch_impl(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_in, i
     int extra = 0, iters = G.nv, mism = G.mism;
     double res_true = G.res_true, est = G.res;
     if (G.bnorm != 0.0 && res_true > tol && G.nv > 0 && G.nv < max_iter) {
-      const int r2 = solve_impl(ctx, (const sesm_c64*)G.b, (sesm_c64*)G.x, tol, max_iter - G.nv, 0, SESM_SOLVE_X0,
-                                G.res_true, &more, inc0 < 0 ? -1 : inc0 + r);
+      const int r2 = solve_impl_t<VT>(ctx, (const sesm_c64*)G.b, (sesm_c64*)G.x, tol, max_iter - G.nv, 0, SESM_SOLVE_X0,
+                                      G.res_true, &more, inc0 < 0 ? -1 : inc0 + r, mixed);
       if (r2 && r2 != SESM_ENOCONV) {
         gm_release(ctx, Ball);
         return r2;
@@ -1217,9 +1376,126 @@ static int solve_batch_impl(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_in, i
   return SESM_OK;
 }
 
+// Mixed precision for a batch: FP64 refinement around lockstep inner solves
+// with FP32 bases and the mixed-precision map (as solve_mixed, one
+// refinement step for all systems that have not yet reached tol; a system
+// stops when its FP64 residual fails to halve).
+static int solve_batch_mixed(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b_in, int64_t ld_b, sesm_c64* mu_out,
+                             int64_t ld_mu, double tol, int32_t max_iter, int32_t flags, sesm_solve_info* info,
+                             int inc0) {
+  if (!ctx->ready) return ctx->fail(SESM_ENOSURF, "no surface");
+  if (ctx->P.mode != SESM_MODE_ACCEL) return ctx->fail(SESM_EINVAL, "mixed precision needs the accelerated mode");
+  if (nrhs < 0 || nrhs > SESM_MAX_BATCH || !(tol > 0) || max_iter < 1 || max_iter > 4000)
+    return ctx->fail(SESM_EINVAL, "bad batched solve arguments");
+  if (nrhs == 0) return SESM_OK;
+  const int N = ctx->P.N;
+  if ((!b_in && inc0 < 0) || !mu_out || ld_mu < N || (b_in && ld_b < N))
+    return ctx->fail(SESM_EINVAL, "bad batched solve arguments");
+  SESM_HIP(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  const int nb = (N + 255) / 256;
+  int rc = ensure_small(ctx);  // (norms go through the small buffers)
+  if (rc) return rc;
+  cplx *B = nullptr, *R = nullptr, *D = nullptr;
+  auto done = [&](int code) -> int {
+    (void)hipStreamSynchronize(st);
+    gm_release(ctx, B);
+    gm_release(ctx, R);
+    gm_release(ctx, D);
+    return code;
+  };
+  if ((rc = sesm_alloc(ctx, (void**)&B, sizeof(cplx) * (size_t)nrhs * N)) ||
+      (rc = sesm_alloc(ctx, (void**)&R, sizeof(cplx) * (size_t)nrhs * N)) ||
+      (rc = sesm_alloc(ctx, (void**)&D, sizeof(cplx) * (size_t)nrhs * N)))
+    return done(rc);
+  // right-hand sides (given or the members' incident fields), initial x
+  for (int r = 0; r < nrhs; ++r) {
+    cplx* br = B + (int64_t)r * N;
+    if (b_in) {
+      SESM_HIP(hipMemcpyAsync(br, (const cplx*)b_in + r * ld_b, sizeof(cplx) * N, hipMemcpyDeviceToDevice, st));
+    } else if ((rc = sesm_rhs_incidence(ctx, inc0 + r, (sesm_c64*)br))) {
+      return done(rc);
+    }
+    if (!(flags & SESM_SOLVE_X0)) SESM_HIP(hipMemsetAsync((cplx*)mu_out + r * ld_mu, 0, sizeof(cplx) * N, st));
+  }
+  std::vector<double> bn(nrhs), rel(nrhs, 1.0), est(nrhs, 1.0);
+  std::vector<int> iters(nrhs, 0), steps(nrhs, 0), mism(nrhs, 0);
+  std::vector<char> active(nrhs, 1);
+  auto residuals = [&]() -> int {  // R = B - A X with the FP64 map, and the relative norms
+    int r2 = sesm_accel_matvec_batch(ctx, nrhs, (const cplx*)mu_out, ld_mu, R, N, inc0, false);
+    if (r2) return r2;
+    for (int r = 0; r < nrhs; ++r) {
+      hipLaunchKernelGGL(k_sub_from, dim3(nb), dim3(256), 0, st, N, B + (int64_t)r * N, R + (int64_t)r * N);
+      SESM_LAUNCH_CHECK();
+      double v = 0.0;
+      if ((r2 = gm_rel_norm(ctx, R + (int64_t)r * N, bn[r], &v))) return r2;
+      if (active[r]) rel[r] = v;
+    }
+    return SESM_OK;
+  };
+  for (int r = 0; r < nrhs; ++r)
+    if ((rc = gm_rel_norm(ctx, B + (int64_t)r * N, 0.0, &bn[r]))) return done(rc);
+  for (int r = 0; r < nrhs; ++r) active[r] = bn[r] > 0.0;
+  if ((rc = residuals())) return done(rc);
+  std::vector<sesm_solve_info> in(nrhs);
+  for (int used = 0;;) {
+    double worst = 0.0;
+    int n_act = 0;
+    for (int r = 0; r < nrhs; ++r) {
+      if (active[r] && rel[r] <= tol) active[r] = 0;
+      if (active[r]) worst = std::max(worst, rel[r]), ++n_act;
+    }
+    if (n_act == 0 || used >= max_iter) break;
+    // systems that are done get a zero right-hand side (their correction is 0)
+    for (int r = 0; r < nrhs; ++r)
+      if (!active[r]) SESM_HIP(hipMemsetAsync(R + (int64_t)r * N, 0, sizeof(cplx) * N, st));
+    const double tau = std::max(0.5 * tol / worst, kMixedInnerFloor);
+    rc = solve_batch_impl<cplxf>(ctx, nrhs, (const sesm_c64*)R, N, (sesm_c64*)D, N, tau, max_iter - used, 0,
+                                 in.data(), inc0, true);
+    if (rc && rc != SESM_ENOCONV) return done(rc);
+    int most = 0;
+    std::vector<double> before(rel);
+    for (int r = 0; r < nrhs; ++r) {
+      if (!active[r]) continue;
+      hipLaunchKernelGGL(k_axpy1, dim3(nb), dim3(256), 0, st, N, (cplx*)mu_out + r * ld_mu, D + (int64_t)r * N);
+      SESM_LAUNCH_CHECK();
+      iters[r] += in[r].iters;
+      mism[r] += in[r].column_mismatches;
+      ++steps[r];
+      est[r] = in[r].est_residual * rel[r];
+      most = std::max(most, in[r].iters);
+    }
+    used += most;
+    if ((rc = residuals())) return done(rc);
+    for (int r = 0; r < nrhs; ++r)
+      if (active[r] && (!(rel[r] < 0.5 * before[r]) || in[r].iters == 0)) active[r] = 0;  // no progress
+  }
+  bool all = true;
+  for (int r = 0; r < nrhs; ++r) {
+    const bool conv = bn[r] == 0.0 || rel[r] <= tol;
+    all = all && conv;
+    if (info) {
+      info[r] = sesm_solve_info{};
+      info[r].iters = iters[r];
+      info[r].rel_residual = bn[r] == 0.0 ? 0.0 : rel[r];
+      info[r].est_residual = bn[r] == 0.0 ? 0.0 : est[r];
+      info[r].residual_restarts = steps[r];
+      info[r].column_mismatches = mism[r];
+      info[r].converged = conv ? 1 : 0;
+    }
+  }
+  rc = done(SESM_OK);
+  if (rc) return rc;
+  if (!all) return ctx->fail(SESM_ENOCONV, "mixed-precision GMRES did not reach the tolerance for every system");
+  return SESM_OK;
+}
+
 extern "C" int sesm_solve_batch(sesm_ctx* ctx, int32_t nrhs, const sesm_c64* b, int64_t ld_b, sesm_c64* mu,
                                 int64_t ld_mu, double tol, int32_t max_iter, int32_t flags, sesm_solve_info* info) {
-  return solve_batch_impl(ctx, nrhs, b, ld_b, mu, ld_mu, tol, max_iter, flags, info, -1);
+  if (!ctx) return SESM_EINVAL;
+  if (flags & SESM_SOLVE_MIXED)
+    return solve_batch_mixed(ctx, nrhs, b, ld_b, mu, ld_mu, tol, max_iter, flags & ~SESM_SOLVE_MIXED, info, -1);
+  return solve_batch_impl<cplx>(ctx, nrhs, b, ld_b, mu, ld_mu, tol, max_iter, flags, info, -1);
 }
 
 extern "C" int sesm_solve_incidences(sesm_ctx* ctx, int32_t r0, int32_t nrhs, const sesm_c64* b, int64_t ld_b,
@@ -1231,5 +1507,7 @@ extern "C" int sesm_solve_incidences(sesm_ctx* ctx, int32_t r0, int32_t nrhs, co
   if (r0 < 0 || nrhs < 0 || r0 + nrhs > sesm_accel_n_incidences(ctx))
     return ctx->fail(SESM_EINVAL, "incidence index beyond the incidence set");
   if (!b) ld_b = ctx->P.N;
-  return solve_batch_impl(ctx, nrhs, b, ld_b, mu, ld_mu, tol, max_iter, flags, info, r0);
+  if (flags & SESM_SOLVE_MIXED)
+    return solve_batch_mixed(ctx, nrhs, b, ld_b, mu, ld_mu, tol, max_iter, flags & ~SESM_SOLVE_MIXED, info, r0);
+  return solve_batch_impl<cplx>(ctx, nrhs, b, ld_b, mu, ld_mu, tol, max_iter, flags, info, r0);
 }

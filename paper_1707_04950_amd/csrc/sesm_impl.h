@@ -91,6 +91,9 @@ struct sesm_ctx {
   cplx* ybuf = nullptr;      // device copy of the small LS solution
   cplx* wtmp = nullptr;      // scratch vector of length N (the right-hand side when none is given)
   cplx* gw = nullptr;        // A u of the current Arnoldi step
+  // mixed-precision solves: FP64 mirror of the current FP32 basis vector, the
+  // inner solve's residual, the outer residual and correction (N each)
+  cplx *umix = nullptr, *mx_r = nullptr, *mx_R = nullptr, *mx_D = nullptr;
   cplx* Hrow = nullptr;      // packed upper-Hessenberg matrix, row-major
   cplx* htri = nullptr;      // its columns gathered column-major (column j: rows 0..j+1)
   int64_t Hrow_len = 0;
@@ -170,11 +173,12 @@ int sesm_dense_matvec(sesm_ctx* ctx, const cplx* mu, cplx* y);
 
 // accelerated path (sesm_accel.hip)
 int sesm_accel_setup(sesm_ctx* ctx);
-int sesm_accel_matvec(sesm_ctx* ctx, const cplx* mu, cplx* y);
+int sesm_accel_matvec(sesm_ctx* ctx, const cplx* mu, cplx* y, bool mixed = false);
 // inc0 < 0: every density with the surface's own incidence; inc0 >= 0: density
 // r with member inc0 + r of the incidence set
+// mixed: the mixed-precision map (EqSources operators in FP32)
 int sesm_accel_matvec_batch(sesm_ctx* ctx, int nrhs, const cplx* mu, int64_t ldm, cplx* y, int64_t ldy,
-                            int inc0 = -1);
+                            int inc0 = -1, bool mixed = false);
 int sesm_accel_set_incidences(sesm_ctx* ctx, int n, const double* alpha);
 int sesm_accel_n_incidences(const sesm_ctx* ctx);
 const Problem* sesm_accel_incidence(const sesm_ctx* ctx, int r);
@@ -184,7 +188,7 @@ void sesm_accel_info(const sesm_ctx* ctx, sesm_surface_info* info);
 // operator dispatch; sesm_apply_inc applies the operator of member inc of the
 // incidence set (inc < 0: the surface's own incidence)
 int sesm_apply(sesm_ctx* ctx, const cplx* mu, cplx* y);
-int sesm_apply_inc(sesm_ctx* ctx, const cplx* mu, cplx* y, int inc);
+int sesm_apply_inc(sesm_ctx* ctx, const cplx* mu, cplx* y, int inc, bool mixed = false);
 
 // incidence-dependent scalars (alpha, beta, U^eta, propagating orders) of P
 bool sesm_problem_alpha(Problem& P, double alpha, double eta);

@@ -83,7 +83,8 @@ def test_incidence_solves_match_oracle_efficiencies(torch, solver):
     base = _wl(30.0)
     _set(solver, base)
     solver.set_incidences([_wl(t).alpha for t in THETAS])
-    X, infos = solver.solve_incidences(tol=1e-8, max_iter=600)  # (above the accelerated floor at h = 0.5)
+    # (h = 0.5 raises |mu| and with it the accelerated map's rounding floor: 1.5e-8 at 10 degrees)
+    X, infos = solver.solve_incidences(tol=3e-8, max_iter=600)
     for r, th in enumerate(THETAS):
         n, e, eps = solver.efficiencies_incidence(r, X[r].contiguous())
         disc = dense.Discretization(_wl(th))
