@@ -44,6 +44,14 @@ def parse():
     ap.add_argument("--max-iter", type=int, default=3000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched-solve", action="store_true")  # e.g. under counter collection (many dispatches)
+    # near-field work items per launch of the single-density forward map:
+    # "auto" lets the library's tuner time candidate splits; otherwise the
+    # thousandths of the items in the first launch, the merge + FFT launch and
+    # the y-convolution launch (the inverse FFT takes the rest).  The default is
+    # a split the tuner settles near on this workload: fixed, so the kernel
+    # shapes (and the counter-measured traffic) are the same from run to run.
+    ap.add_argument("--near-split", default="595,110,125")
+    ap.add_argument("--no-mixed", action="store_true")  # skip the mixed-precision comparison solve
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--workload", choices=["grazing", "c4"], default="grazing")
     ap.add_argument("--c4-angles", type=int, default=64)
@@ -84,16 +92,21 @@ def library_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, near_items=None):
     """HBM bytes per launch of `kernel` from the committed counter summary, or
-    None when there is none for this kernel or the library changed since."""
+    None when there is none for this kernel, the library changed since, or the
+    near-field work items were split over the launches differently."""
     try:
         text = open(TRAFFIC_PROFILE).read()
     except OSError:
         return None
     fields = dict(l.strip().split(": ", 1) for l in text.splitlines() if l.strip().count(": ") == 1 and
-                  l.strip().split(": ", 1)[0] in ("traffic_kernel", "traffic_bytes_per_launch", "library_sources_sha256"))
+                  l.strip().split(": ", 1)[0] in ("traffic_kernel", "traffic_bytes_per_launch", "library_sources_sha256",
+                                                  "near_items_per_launch"))
     if fields.get("traffic_kernel") != kernel or fields.get("library_sources_sha256") != library_sources_sha256():
+        return None
+    if "near_items_per_launch" in fields and near_items is not None and \
+            [int(v) for v in fields["near_items_per_launch"].split(",")] != list(near_items):
         return None
     return float(fields["traffic_bytes_per_launch"])
 
@@ -269,9 +282,15 @@ def main():
     s = lib.Solver(0)
     n_a = max(8, int(math.floor(0.8 * min(wl.L, wl.d) / wl.dx)))  # a = n_a dx just below the cell side
 
-    def setup():
+    if args.near_split == "auto":
+        split_kw = {"near_split": 0}
+    else:
+        split_kw = {"near_split": 1, "split_permille": tuple(int(v) for v in args.near_split.split(","))}
+
+    def setup(**kw):
         s.set_surface(np.asarray(wl.a_coef), np.asarray(wl.b_coef), wl.d, wl.k, wl.alpha, wl.j, wl.A, args.N,
-                      h=wl.h, c=wl.c, n_a=n_a, gamma_frac=wl.gamma_frac, eta=wl.eta, mode=mode, L=wl.L)
+                      h=wl.h, c=wl.c, n_a=n_a, gamma_frac=wl.gamma_frac, eta=wl.eta, mode=mode, L=wl.L,
+                      **(kw or split_kw))
 
     def step():
         t0 = time.perf_counter()
@@ -325,16 +344,29 @@ def main():
     # steady-state forward map: events on the library's stream (torch's current stream)
     mu = torch.from_numpy(W.random_density(args.N, 1)).cuda()
     y = torch.empty_like(mu)
-    for _ in range(5):
-        s.matvec(mu, y)
     reps = 30
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(reps):
-        s.matvec(mu, y)
-    ev1.record()
-    torch.cuda.synchronize()
-    mv_s = ev0.elapsed_time(ev1) / 1e3 / reps
+
+    def time_matvec():
+        for _ in range(5):
+            s.matvec(mu, y)
+        ev0.record()
+        for _ in range(reps):
+            s.matvec(mu, y)
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / 1e3 / reps
+
+    mv_s = time_matvec()
+    y_fixed = y.clone()
+    auto_split = None
+    if mode == lib.MODE_ACCEL and args.near_split != "auto":
+        # the tuner's own pick for comparison (a surface set up with near_split = 0)
+        setup(near_split=0)
+        inf = s.info()
+        auto_split = {"near_items_per_launch": inf["near_items"], "ms": time_matvec() * 1e3,
+                      "same_result": bool(torch.equal(y, y_fixed))}
+        setup()
 
     # batched forward maps (one operator, BATCH densities: groups of four share
     # the near-field and projection pass); same events, same stream
@@ -392,7 +424,7 @@ def main():
     # refinement) on the same workload, outside the timed region: a surface
     # set up with the FP32 operators, one warm-up and one timed solve
     mixed = None
-    if args.mode == "accel":
+    if args.mode == "accel" and not args.no_mixed:
         s.set_surface(np.asarray(wl.a_coef), np.asarray(wl.b_coef), wl.d, wl.k, wl.alpha, wl.j, wl.A, args.N,
                       h=wl.h, c=wl.c, n_a=n_a, gamma_frac=wl.gamma_frac, eta=wl.eta, mode=mode, L=wl.L, mixed=1)
         s.solve(tol=args.tol, max_iter=args.max_iter, allow_noconv=True, mixed=True)
@@ -423,7 +455,8 @@ def main():
         fb = sum(ranking[k]["bytes"] / ranking[k]["launches"] for k in
                  ("k_local_apply", "k_merge_fft", "k_fft_rows", "k_yconv", "k_cells_far") if ranking[k]["launches"])
         fmap = {"bytes": fb, "ms": mv_s * 1e3, "GBps": fb / mv_s / 1e9, "frac_of_hbm_peak": fb / mv_s / 1e9 / HBM_PEAK_GBS,
-                "near_items_per_launch": split_info["near_items"], "near_split_tuned_us": split_info["near_tuned_us"]}
+                "near_split": args.near_split, "near_items_per_launch": split_info["near_items"],
+                "tuned_split": auto_split}
 
     n_launch = max(kst["launches"], 1)
     avg_s = kst["total_ms"] / 1e3 / n_launch
@@ -431,7 +464,7 @@ def main():
             "unit": "GB/s", "bytes_per_launch": kst["bytes"] / n_launch, "avg_launch_us": avg_s * 1e6,
             "launches": kst["launches"], "sampled_every": TIMING_EVERY}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic(dom)
+    roof["traffic"] = measured_traffic(dom, split_info["near_items"])
     kernels = None
     if ranking:
         kernels = {n: {"launches": r["launches"], "total_ms": round(r["total_ms"], 3),

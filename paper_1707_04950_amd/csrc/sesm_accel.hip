@@ -589,14 +589,11 @@ struct NearArgs {
 // rs[(s NEAR_ROWS + r) 4 + wave].  For several densities (NB >= 3) the rows are
 // taken in two passes of half as many accumulators; each row's sum is formed
 // in the same order either way, so every launch shape gives the same bits.
-template <int NB>
-__device__ __forceinline__ void near_accum(const NearArgs& A, int it, int tid, cplx* rs,
-                                           const cplx* __restrict__ mu, int64_t ldm, const cplx* ph) {
-  const int q = A.chunk_q[it], t0 = A.chunk_t0[it];
-  const int off = A.occ_off[q], nq = A.occ_off[q + 1] - off;
-  const int nr = min(NEAR_ROWS, nq - t0);
-  const int col = A.occ_cell[q] % A.n_x;
-  const int lo = A.col_lo[col], w = A.col_w[col];
+// WRAP: the item's band reaches past the period (only cells next to x = 0 or
+// x = d); other items skip the per-column image test.
+template <int NB, bool WRAP>
+__device__ __forceinline__ void near_accum_band(const NearArgs& A, int q, int t0, int nr, int lo, int w, int tid,
+                                                cplx* rs, const cplx* __restrict__ mu, int64_t ldm, const cplx* ph) {
   const int N = A.N;
   const cplx* blk = A.nearblk + A.near_off[q] + (int64_t)t0 * w;
   const int lane = tid & 63, wv = tid >> 6;
@@ -611,13 +608,18 @@ __device__ __forceinline__ void near_accum(const NearArgs& A, int it, int tid, c
       for (int r = 0; r < RP; ++r) acc[s][r] = cplx{0.0, 0.0};
     for (int u = tid; u < w; u += 256) {
       int l = lo + u;
-      const int wr = (l < 0) ? -1 : ((l >= N) ? 1 : 0);  // source image x_l + wr d
-      l -= wr * N;
       cplx m[NB];
+      if (WRAP) {
+        const int wr = (l < 0) ? -1 : ((l >= N) ? 1 : 0);  // source image x_l + wr d
+        l -= wr * N;
 #pragma unroll
-      for (int s = 0; s < NB; ++s) {
-        m[s] = mu[s * ldm + l];
-        if (wr != 0) m[s] = cmul_fixed(wr > 0 ? ph[s] : conj(ph[s]), m[s]);  // its density mu_l e^{i alpha d wr}
+        for (int s = 0; s < NB; ++s) {
+          m[s] = mu[s * ldm + l];
+          if (wr != 0) m[s] = cmul_fixed(wr > 0 ? ph[s] : conj(ph[s]), m[s]);  // its density mu_l e^{i alpha d wr}
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < NB; ++s) m[s] = mu[s * ldm + l];
       }
       cplx v[RP];
 #pragma unroll
@@ -635,6 +637,20 @@ __device__ __forceinline__ void near_accum(const NearArgs& A, int it, int tid, c
         if (lane == 0) rs[(s * NEAR_ROWS + r0 + r) * 4 + wv] = sm;
       }
   }
+}
+
+template <int NB>
+__device__ __forceinline__ void near_accum(const NearArgs& A, int it, int tid, cplx* rs,
+                                           const cplx* __restrict__ mu, int64_t ldm, const cplx* ph) {
+  const int q = A.chunk_q[it], t0 = A.chunk_t0[it];
+  const int off = A.occ_off[q], nq = A.occ_off[q + 1] - off;
+  const int nr = min(NEAR_ROWS, nq - t0);
+  const int col = A.occ_cell[q] % A.n_x;
+  const int lo = A.col_lo[col], w = A.col_w[col];
+  if (lo < 0 || lo + w > A.N)
+    near_accum_band<NB, true>(A, q, t0, nr, lo, w, tid, rs, mu, ldm, ph);
+  else
+    near_accum_band<NB, false>(A, q, t0, nr, lo, w, tid, rs, mu, ldm, ph);
 }
 
 // After a workgroup barrier: thread tid < rows of item `it` adds the four
