@@ -183,11 +183,18 @@ def _dl0(k, X, Y, fps):
     return 0.25j * k * hankel1(1, k * R) * (Y - fps * X) / R
 
 
-def lattice_table(geom, lam, kind):
+HYBRID_WINDOW = 8.0
+
+
+def lattice_table(geom, lam, kind, table="windowed"):
     """Windowed shifted lattice sum of the kernel `kind` (eq. Gq_limit with the
     Bloch phase) on the difference grid of the global grid Pi_lam:
     X = mx * hx, mx = 0..nX-1 (one period), Y = my * hy, my = -(nY-1)..nY-1.
-    Returns T[my + nY - 1, mx]."""
+    Returns T[my + nY - 1, mx].  table="hybrid" (Sec. 3.2): the rows that
+    greens.hybrid_row_order admits take the spectral series of G~_j instead
+    (greens.qper_spectral; no window), the others keep the windowed sums, with
+    a window HYBRID_WINDOW times as wide (the spatial series "with a
+    sufficiently large value of A" of Sec. 4.2.3)."""
     disc = geom.disc
     k, j, h, d, alpha = disc.k, disc.j, disc.h, disc.d, disc.alpha
     A_len, cA = disc.A * d, disc.c * disc.A * d
@@ -200,13 +207,23 @@ def lattice_table(geom, lam, kind):
     X = mx[None, :] * hx + 0 * my[:, None]
     Y = my[:, None] * hy + 0 * mx[None, :]
     T = np.zeros(X.shape, dtype=np.complex128)
-    pmax = int(np.ceil(disc.A)) + 2
+    spatial = np.ones(len(my), dtype=bool)
+    if table == "hybrid":
+        for r, yy in enumerate(my * hy):
+            nm = greens.hybrid_row_order(k, d, j, h, yy)
+            if nm is not None:
+                T[r] = greens.qper_spectral(k, alpha, d, j, h, mx * hx, yy, nm, kind)
+                spatial[r] = False
+    Xs, Ys = X[spatial], Y[spatial]
+    if table == "hybrid":
+        A_len, cA = HYBRID_WINDOW * A_len, HYBRID_WINDOW * cA
+    pmax = int(np.ceil(A_len / d)) + 2
     for p in range(-pmax, pmax + 1):
-        Xp = X + d * p
+        Xp = Xs + d * p
         S = greens.window(Xp, cA, A_len)
         if not np.any(S > 0):
             continue
-        T += np.exp(-1j * alpha * d * p) * S * _green_terms(k, j, h, Xp, Y, kind)
+        T[spatial] += np.exp(-1j * alpha * d * p) * S * _green_terms(k, j, h, Xp, Ys, kind)
     return T
 
 
@@ -214,8 +231,9 @@ def lattice_table(geom, lam, kind):
 class AccelOperator:
     """Precomputed tables of Algorithm 2 and the forward map of Algorithm 3."""
 
-    def __init__(self, disc, **geom_kw):
+    def __init__(self, disc, table="windowed", **geom_kw):
         self.disc = disc
+        self.table = table
         g = self.g = Geometry(disc, **geom_kw)
         k = disc.k
         # Equivalent-source least squares, eq. (eq_source_point): A_eq is the same
@@ -242,8 +260,8 @@ class AccelOperator:
         self.spec = {}
         for lam in ("H", "V"):
             hx = g.delta if lam == "H" else g.L
-            Tm = lattice_table(g, lam, "mono")
-            Td = lattice_table(g, lam, "dip" + lam)
+            Tm = lattice_table(g, lam, "mono", table)
+            Td = lattice_table(g, lam, "dip" + lam, table)
             nX = Tm.shape[1]
             tw = np.exp(-1j * disc.alpha * np.arange(nX) * hx)[None, :]
             self.spec[lam] = (np.fft.fft(Tm * tw, axis=1), np.fft.fft(Td * tw, axis=1))

@@ -11,6 +11,7 @@ definitions directly:
   with the Bloch phase exp(-i alpha d p) that eq. (Gq_limit) omits and
   eq. (shifted_periodic_green_function) carries
 * the spectral (Rayleigh) series of G~_j                          eq. (shifted_quasi_per_rayleigh)
+  and its form valid at Wood anomalies                           eq. (betan_taylor), Sec. 3.2
 * the double-layer kernel, the Martensen-Kussmaul split K_s, K_r and the
   Fourier-based log-quadrature weights R                          Sec. 4.2.1, eqs. (descomp)-(local_mat)
 
@@ -179,3 +180,101 @@ def lattice_sum_spectral(k, alpha, d, j, h, X, Y, nmax, kernel="G", fps=0.0):
                 term = (fps * 1j * an - 1j * bn * np.sign(Ym)) * e
             out += w[m] * (1j / (2.0 * d * bn)) * ex * term
     return out
+
+
+# ---------------------------------------------------------------- Sec. 3.2: spectral series at Wood anomalies
+def _q_pow(beta, h, j):
+    """(1 - e^{i beta h})^j / beta for j >= 1 (beta complex, scalar): directly
+    for |beta| >= 0.5, else with (1 - e^{i beta h}) / beta summed as its Taylor
+    series -i h sum_{n>=0} (i beta h)^n / (n+1)!."""
+    z = 1j * beta * h
+    if abs(beta) >= 0.5:
+        return (1.0 - np.exp(z)) ** j / beta
+    q, term, n = 0j, 1.0 + 0j, 0
+    while True:
+        add = term / _fact(n + 1)
+        q += add
+        if abs(add) < 1e-20 * max(abs(q), 1e-300) or n > 60:
+            break
+        n += 1
+        term *= z
+    q *= -1j * h  # (1 - e^{i beta h}) / beta
+    return q ** j * beta ** (j - 1)
+
+
+def _q_odd(beta, t):
+    """(e^{i beta t} - e^{-i beta t}) / beta = 2i sin(beta t) / beta: directly
+    for |beta| >= 0.5, else as 2i sum_{n>=0} (-1)^n beta^{2n} t^{2n+1} / (2n+1)!."""
+    if abs(beta) >= 0.5:
+        return (np.exp(1j * beta * t) - np.exp(-1j * beta * t)) / beta
+    s, n = 0j, 0
+    b2 = beta * beta
+    term = t + 0j
+    while True:
+        add = term / _fact(2 * n + 1)
+        s += add
+        if abs(add) < 1e-20 * max(abs(s), 1e-300) or n > 60:
+            break
+        n += 1
+        term *= -b2 * t * t
+    return 2j * s
+
+
+def _fact(n):
+    out = 1.0
+    for i in range(2, n + 1):
+        out *= i
+    return out
+
+
+def qper_spectral(k, alpha, d, j, h, X, Y, nmax, kind="mono"):
+    """G~_j (eq. shifted_periodic_green_function) from its spectral series, eq.
+    (shifted_quasi_per_rayleigh), summed over |n| <= nmax, for points whose
+    height Y keeps away from every shifted pole row Y = -m h (then the terms
+    decay like exp(-|beta_n| min_m |Y + m h|), eq. spectral_exp_estimate).  The
+    beta_n-quotient of each term is taken in the form of eq. (betan_taylor),
+        sum_m w_m e^{i beta |Y+mh|} / beta
+          = e^{i beta Y} (1 - e^{i beta h})^j / beta
+            - sum_{m: Y+mh < 0} w_m (e^{i beta (Y+mh)} - e^{-i beta (Y+mh)}) / beta,
+    with both quotients summed as Taylor series, for |beta_n| < 0.5, so the
+    series also holds at Wood anomalies (beta_n = 0; needs j >= 1); the other
+    terms take the quotient as printed.
+    kind: "mono" G~_j; "dipH" -dG~_j/dY (derivative in the source height);
+    "dipV" -dG~_j/dX (in the source abscissa).  X: array, Y: scalar."""
+    assert j >= 1
+    w = shift_weights(j)
+    X = np.asarray(X, dtype=np.float64)
+    Y = float(Y)
+    out = np.zeros(X.shape, dtype=np.complex128)
+    for n in range(-nmax, nmax + 1):
+        an = alpha + 2.0 * np.pi * n / d
+        g = (k - an) * (k + an)
+        bn = np.sqrt(g) + 0j if g >= 0 else 1j * np.sqrt(-g)
+        ts = Y + h * np.arange(j + 1)
+        if kind == "dipH":
+            coef = np.sum(w * np.sign(ts) * np.exp(1j * bn * np.abs(ts))) / (2.0 * d)
+        else:
+            if abs(bn) >= 0.5:  # the plain quotient (the closed form would cancel for evanescent terms)
+                q = np.sum(w * np.exp(1j * bn * np.abs(ts))) / bn
+            else:
+                q = np.exp(1j * bn * Y) * _q_pow(bn, h, j)
+                for m in range(j + 1):
+                    if ts[m] < 0:
+                        q -= w[m] * _q_odd(bn, ts[m])
+            coef = (1j if kind == "mono" else an) * q / (2.0 * d)
+        out += coef * np.exp(1j * an * X)
+    return out
+
+
+def hybrid_row_order(k, d, j, h, Y):
+    """The hybrid tables' choice for a row at height Y (Sec. 3.2): the
+    truncation order of its spectral series, or None when the row keeps the
+    windowed sums.  delta = min_m |Y + m h|; the terms fall below e^{-42}
+    where |beta_n| delta > 42, i.e. beyond |alpha_n| = sqrt((42/delta)^2 + k^2),
+    and |alpha| < k; rows needing more than 40000 orders, or on a pole row,
+    keep the windowed sums."""
+    delta = min(abs(Y + m * h) for m in range(j + 1))
+    if not delta > 0:
+        return None
+    nm = int(np.ceil((np.sqrt((42.0 / delta) ** 2 + k * k) + k) * d / (2.0 * np.pi))) + 2
+    return nm if nm <= 40000 else None
