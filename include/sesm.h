@@ -95,7 +95,22 @@ typedef struct {
   int32_t mixed;      /* accelerator: 1 also builds the FP32 copy of the EqSources
                          operators (eq. eq_source_point) used by mixed-precision solves
                          (SESM_SOLVE_MIXED); 0 (default) does not                      */
-  int32_t reserved[2];
+  int32_t table;      /* accelerator kernel tables (the only use of G~_j, Sec. 5.5.1):
+                         0 (default): windowed spatial lattice sums (eq. Gq_limit) on
+                         every row of the difference grids; 1: hybrid (Sec. 3.2, Remark
+                         large_FFT_eval): rows whose height Y keeps a distance
+                         delta > 0 from every shifted pole row Y = -m h take the
+                         exponentially convergent spectral series (eq.
+                         shifted_quasi_per_rayleigh, in the form of eq. betan_taylor
+                         at and around Wood anomalies; the exact G~_j, no window),
+                         truncated where e^{-|beta_n| delta} < e^{-42} (at most
+                         40000 orders); the other rows keep the windowed sums,
+                         with a window 8 times as wide (their window error would
+                         otherwise jump between neighbouring rows, and at Wood
+                         anomalies, where it decays only like A^{-3.5}, the
+                         cells' plane-wave fits amplify such jumps).
+                         Needs j >= 1 and the accelerated mode.                   */
+  int32_t reserved;
 } sesm_params;
 
 typedef struct {
@@ -142,6 +157,9 @@ typedef struct {
                                  inverse FFT                                   */
   double near_tuned_us;       /* forward-map time of the chosen split when the tuner
                                  measured it (0 otherwise)                     */
+  int32_t spectral_rows[2];   /* hybrid tables: rows of the horizontal and vertical
+                                 difference grids taken from the spectral series
+                                 (of 2 n_rows - 1 each; 0 with windowed tables)   */
 } sesm_surface_info;
 
 /* Create a context on HIP device `device`; `hip_stream` is a hipStream_t (NULL
@@ -328,6 +346,33 @@ SESM_API int sesm_rayleigh(sesm_ctx* ctx, const sesm_c64* mu, const int32_t* ord
 SESM_API int sesm_rayleigh_noalloc(sesm_ctx* ctx, const sesm_c64* mu, const int32_t* orders_host, int32_t n_orders,
                                    sesm_c64* B_host);
 
+/* Scattered field off the surface: u(P) of eq. (eq:int_eq_dirichlet) for the
+ * density mu (device, N sesm_c64; e.g. a solution of sesm_solve) at n points
+ * P_t = (xy[2t], xy[2t + 1]) (device array of 2n doubles, any x: the field is
+ * alpha-quasi-periodic), written to u (device, n sesm_c64).  The points must
+ * lie off the curve y = f(x) (several dx away for full accuracy: the
+ * trapezoidal rule's error falls like exp(-2 pi distance / dx)); below the
+ * curve the result is the representation's value, not a physical field.
+ * Routes (per point):
+ *  - accelerated mode, points inside the accelerator's cell grid
+ *    (y0 <= y < y0 + n_y L, sesm_get_info): one forward map of mu and then,
+ *    per cell holding points, the plane-wave expansion of the cell's far field
+ *    fitted to its boundary values (eq. planewave), the direct sum over the
+ *    nodes of the near columns and the completion modes - the "slightly
+ *    modified Algorithm 3" of the remark closing Sec. 5.7;
+ *  - accelerated mode, points at least L/4 above max f: the Rayleigh
+ *    expansion sum_n B_n e^{i alpha_n x + i beta_n y} (Sec. 2; the exact
+ *    lattice sum, no window), with every order up to where the terms fall
+ *    below e^{-40};
+ *  - all other points, and all points in dense mode: the trapezoidal rule of
+ *    the windowed lattice sums over all nodes plus the completion modes
+ *    (cost O(N A/d j) per point).
+ * The grid and direct routes share the operator's window S_{cA,A}; the
+ * Rayleigh route is its A -> infinity limit (they differ by the window's
+ * truncation error).  Allocates and frees a temporary device buffer;
+ * synchronises the stream.  SESM_EINVAL for non-finite coordinates. */
+SESM_API int sesm_field(sesm_ctx* ctx, const sesm_c64* mu, int32_t n, const double* xy, sesm_c64* u);
+
 /* Describe the current discretisation (host struct).  Returns SESM_ENOSURF
  * before a successful sesm_set_surface. */
 SESM_API int sesm_get_info(const sesm_ctx* ctx, sesm_surface_info* info);
@@ -346,7 +391,13 @@ SESM_API const char* sesm_last_error(const sesm_ctx* ctx);
  *      corrections, eqs. psi_na_sum and combine_psi_pna), [occupied cell in
  *      increasing cell index][boundary point: the 2 (n_side + 1) points of the
  *      bottom then top side, then the 2 (n_side - 1) inner points of the left
- *      then right side].
+ *      then right side];
+ *   5: the kernel spectra of the surface's own incidence: the x-transforms
+ *      (sum_t tab[t] e^{-2 pi i b t / nX}) of the twisted tables
+ *      G~_j(X, Y) e^{-i alpha X} of the monopole then the dipole kernel, for
+ *      the horizontal grid [2][2 (n_y + 1) - 1][n_x n_s] followed by the
+ *      vertical grid [2][2 (n_y n_s + 1 + 2 n_ext) - 1][n_x]; row r holds
+ *      height Y = (r - n_rows + 1) hy (mu is not used).
  * Synchronises the stream.  Returns SESM_EINVAL if out_len is too small. */
 SESM_API int sesm_diag_accel(sesm_ctx* ctx, const sesm_c64* mu, int32_t which, sesm_c64* out, int64_t out_len);
 

@@ -35,7 +35,7 @@ class Params(ctypes.Structure):
                 ("mode", ctypes.c_int32), ("L_cell", ctypes.c_double), ("n_side", ctypes.c_int32),
                 ("n_ext", ctypes.c_int32), ("n_coll", ctypes.c_int32), ("n_plw", ctypes.c_int32),
                 ("near_ring", ctypes.c_int32), ("near_split", ctypes.c_int32),
-                ("split_permille", ctypes.c_int32 * 3), ("mixed", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("split_permille", ctypes.c_int32 * 3), ("mixed", ctypes.c_int32), ("table", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -73,7 +73,8 @@ class SurfaceInfo(ctypes.Structure):
                 ("n_x", ctypes.c_int32), ("n_y", ctypes.c_int32), ("n_cells_occupied", ctypes.c_int32),
                 ("stencil_rows", ctypes.c_int32), ("L", ctypes.c_double), ("y0", ctypes.c_double),
                 ("delta", ctypes.c_double), ("near_entries", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
-                ("near_items", ctypes.c_int32 * 4), ("near_tuned_us", ctypes.c_double)]
+                ("near_items", ctypes.c_int32 * 4), ("near_tuned_us", ctypes.c_double),
+                ("spectral_rows", ctypes.c_int32 * 2)]
 
 
 _lib = None
@@ -119,6 +120,7 @@ def load_library(path=LIB_PATH):
         "sesm_solve_incidences": (ctypes.c_int, [_P, _I, _I, _P, ctypes.c_int64, _P, ctypes.c_int64, _D, _I, _I, _P]),
         "sesm_efficiencies_incidence": (ctypes.c_int, [_P, _I, _P, ctypes.POINTER(_I), ctypes.POINTER(_I),
                                                        ctypes.POINTER(_D), _I, ctypes.POINTER(_D)]),
+        "sesm_field": (ctypes.c_int, [_P, _P, _I, _P, _P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -209,7 +211,7 @@ class Solver:
 
     def set_surface(self, a_coef, b_coef, d, k, alpha, j, A, N, h=0.0, c=0.0, n_a=0, gamma_frac=0.0,
                     eta=0.0, mode=MODE_DENSE, L=0.0, n_side=0, n_ext=0, n_coll=0, n_plw=0, near_ring=0,
-                    near_split=0, split_permille=(0, 0, 0), mixed=0):
+                    near_split=0, split_permille=(0, 0, 0), mixed=0, table=0):
         a = np.ascontiguousarray(a_coef, dtype=np.float64)
         b = np.zeros_like(a)
         bb = np.asarray(b_coef, dtype=np.float64)
@@ -219,7 +221,8 @@ class Solver:
                        b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         prm = Params(N=N, h=h, c_window=c, n_a=n_a, gamma_frac=gamma_frac, eta=eta, mode=mode, L_cell=L,
                      n_side=n_side, n_ext=n_ext, n_coll=n_coll, n_plw=n_plw, near_ring=near_ring,
-                     near_split=near_split, split_permille=(ctypes.c_int32 * 3)(*split_permille), mixed=int(mixed))
+                     near_split=near_split, split_permille=(ctypes.c_int32 * 3)(*split_permille), mixed=int(mixed),
+                     table=int(table))
         self._check(self.lib.sesm_set_surface(self.h, ctypes.byref(prof), d, k, alpha, j, A, ctypes.byref(prm)))
         self.N = N
 
@@ -229,6 +232,7 @@ class Solver:
         out = {f: getattr(inf, f) for f, _ in SurfaceInfo._fields_}
         out["U_eta"] = list(inf.U_eta)[: inf.n_eta]
         out["near_items"] = list(inf.near_items)
+        out["spectral_rows"] = list(inf.spectral_rows)
         return out
 
     def empty(self):
@@ -375,6 +379,18 @@ class Solver:
                                                          ctypes.byref(nc), e.ctypes.data_as(ctypes.POINTER(_D)), cap,
                                                          ctypes.byref(eps)))
         return np.arange(n0.value, n0.value + nc.value), e[: nc.value].copy(), eps.value
+
+    def field(self, mu, x, y, out=None):
+        """Scattered field at the points (x[t], y[t]) (host arrays or sequences)."""
+        xy = np.ascontiguousarray(np.stack([np.asarray(x, dtype=np.float64).ravel(),
+                                            np.asarray(y, dtype=np.float64).ravel()], 1))
+        n = xy.shape[0]
+        dxy = self._torch.from_numpy(xy.reshape(-1)).to(self.device)
+        out = self._torch.empty(n, dtype=self._torch.complex128, device=self.device) if out is None else out
+        if n:
+            self._check(self.lib.sesm_field(self.h, _ptr(mu, self.N), n, ctypes.c_void_p(dxy.data_ptr()),
+                                            _ptr(out, n)))
+        return out
 
     def rayleigh(self, mu, orders):
         o = np.ascontiguousarray(orders, dtype=np.int32)

@@ -98,6 +98,13 @@ struct AccelOp {
   // [e^{-i alpha x} on H | on V | e^{+i alpha x} on H | on V] (tw_len entries)
   int64_t spec_len = 0, tw_len = 0;
   cplx *self_spec = nullptr, *self_tw = nullptr;
+  // hybrid tables (Sec. 3.2): per grid, the rows taken by the windowed sums and
+  // the rows taken by the spectral series with their truncation orders
+  struct HybridRows {
+    std::vector<int> spatial, spectral, nmax;
+    int *d_spatial = nullptr, *d_spectral = nullptr, *d_nmax = nullptr;
+  } hyb[2];
+  bool hybrid = false;
   IncParams* inc_self = nullptr;          // device record of the surface's incidence
   int n_inc = 0;                          // incidence set (sesm_set_incidences)
   IncParams* inc_set = nullptr;           // device records [n_inc]
@@ -432,13 +439,14 @@ __global__ void k_narrow(int64_t n, const cplx* __restrict__ src, cplxf* __restr
 // Windowed lattice sums (eq. Gq_limit with the Bloch phase) of the monopole and
 // dipole kernels on the difference grid, twisted by exp(-i alpha X):
 // tab[kind][row][mx], row = my + nY - 1.  One wavefront per entry, lanes over images.
+// rowmap (nullable): the rows to fill, nmap of them (otherwise all 2 nY - 1).
 __global__ __launch_bounds__(256) void k_lattice(KParams K, int lam, int nX, int nY, double hx, double hy, int pmax,
-                                                 cplx* __restrict__ tab) {
+                                                 const int* __restrict__ rowmap, int nmap, cplx* __restrict__ tab) {
   const int lane = threadIdx.x & 63;
   const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int nrow = 2 * nY - 1;
-  if (e >= (int64_t)nrow * nX) return;
-  const int row = (int)(e / nX), mx = (int)(e % nX);
+  if (e >= (int64_t)nmap * nX) return;
+  const int row = rowmap ? rowmap[e / nX] : (int)(e / nX), mx = (int)(e % nX);
   const double X = mx * hx, Y = (row - (nY - 1)) * hy;
   cplx sm = cplx{0.0, 0.0}, sd = cplx{0.0, 0.0};
   for (int p = -pmax + lane; p <= pmax; p += 64) {
@@ -457,6 +465,95 @@ __global__ __launch_bounds__(256) void k_lattice(KParams K, int lam, int nX, int
     const cplx tw = cexp_i(-K.alpha * X);
     tab[(int64_t)row * nX + mx] = sm * tw;
     tab[(int64_t)(nrow + row) * nX + mx] = sd * tw;
+  }
+}
+
+// ---- hybrid tables: the spectral series of G~_j (Sec. 3.2)
+
+__device__ inline cplx cdiv(cplx a, cplx b) { return (1.0 / abs2(b)) * cmul_conj(b, a); }
+__device__ inline cplx cexp_iz(cplx z) {  // e^{i z}, z complex
+  double sn, cs;
+  sincos(z.re, &sn, &cs);
+  const double m = exp(-z.im);
+  return cplx{m * cs, m * sn};
+}
+__device__ inline cplx csin(cplx z) {
+  double sn, cs;
+  sincos(z.re, &sn, &cs);
+  return cplx{sn * cosh(z.im), cs * sinh(z.im)};
+}
+__device__ inline cplx csinc(cplx z) {  // sin(z) / z
+  if (abs2(z) < 1e-6) {
+    const cplx z2 = z * z;
+    return cplx{1.0, 0.0} - (1.0 / 6.0) * z2 + (1.0 / 120.0) * (z2 * z2);
+  }
+  return cdiv(csin(z), z);
+}
+
+// The y-dependence of mode n of the spectral series of G~_j (eq.
+// shifted_quasi_per_rayleigh) at height Y, with t_m = Y + m h:
+//   sb = sum_m w_m e^{i beta |t_m|} / beta,   sd = sum_m w_m sgn(t_m) e^{i beta |t_m|}.
+// For |beta| < 1/2 (at and around Wood anomalies) sb takes the form of eq.
+// betan_taylor with its beta-quotients written as limits-safe products:
+//   e^{i beta Y} (1 - e^{i beta h})^j / beta
+//     = e^{i beta (Y + j h / 2)} (-2i)^j sin^{j-1}(beta h / 2) (h / 2) sinc(beta h / 2),
+//   (e^{i beta t} - e^{-i beta t}) / beta = 2 i t sinc(beta t)   (the rows t_m < 0).
+// Needs j >= 1.
+__device__ inline void spectral_y_sums(const KParams& K, cplx beta, double Y, cplx* sb, cplx* sd) {
+  cplx b_ = cplx{0.0, 0.0}, d_ = cplx{0.0, 0.0};
+  const bool small = abs2(beta) < 0.25;  // (the closed form grows like e^{|Im beta| |Y|} for evanescent terms)
+  for (int m = 0; m <= K.j; ++m) {
+    const double t = Y + m * K.h, at = fabs(t);
+    const cplx e = cexp_iz(at * beta);
+    d_ += (t < 0.0 ? -K.wshift[m] : K.wshift[m]) * e;
+    if (!small) b_ += K.wshift[m] * e;
+    else if (t < 0.0) b_ -= (2.0 * K.wshift[m] * t) * mul_i(csinc(t * beta));
+  }
+  if (small) {
+    const cplx half = (0.5 * K.h) * beta;
+    const cplx sh = csin(half);
+    cplx pw = (0.5 * K.h) * csinc(half);
+    for (int m = 1; m < K.j; ++m) pw = pw * sh;
+    cplx c2 = cplx{1.0, 0.0};  // (-2i)^j
+    for (int m = 0; m < K.j; ++m) c2 = cplx{2.0 * c2.im, -2.0 * c2.re};
+    b_ += cexp_iz((Y + 0.5 * K.j * K.h) * beta) * (c2 * pw);
+  } else {
+    b_ = cdiv(b_, beta);
+  }
+  *sb = b_;
+  *sd = d_;
+}
+
+// Spectral rows of the hybrid tables.  With X = mx d / nX on the periodic
+// grid, G~_j e^{-i alpha X} = sum_n c_n e^{2 pi i n mx / nX}, so the x-transform
+// of a table row is spec[b] = nX sum_{n = b (mod nX), |n| <= nmax} c_n, with
+//   monopole c_n = (i / 2d) sb,  H dipole (d/dy2) c_n = (1 / 2d) sd,
+//   V dipole (d/dx2) c_n = (alpha_n / 2d) sb.
+// One workgroup per listed row (row r with truncation order nmax[r]);
+// threads over the bins b; the terms of a bin are added in increasing n.
+__global__ __launch_bounds__(256) void k_spectral_rows(KParams K, int lam, int nX, int nY, double hy,
+                                                       const int* __restrict__ rows, const int* __restrict__ nmax,
+                                                       cplx* __restrict__ spec) {
+  const int row = rows[blockIdx.x], nm = nmax[blockIdx.x];
+  const int nrow = 2 * nY - 1;
+  const double Y = (row - (nY - 1)) * hy;
+  const double inv2d = 0.5 / K.d, kk = K.k;
+  for (int b = threadIdx.x; b < nX; b += blockDim.x) {
+    const int qlo = -((nm + b) / nX);
+    const int qhi = nm >= b ? (nm - b) / nX : -((b - nm + nX - 1) / nX);
+    cplx am = cplx{0.0, 0.0}, ad = cplx{0.0, 0.0};
+    for (int q = qlo; q <= qhi; ++q) {
+      const int n = b + q * nX;
+      const double an = K.alpha + 2.0 * SESM_PI * n / K.d;
+      const double g = (kk - an) * (kk + an);
+      const cplx beta = g >= 0.0 ? cplx{sqrt(g), 0.0} : cplx{0.0, sqrt(-g)};
+      cplx sb, sd;
+      spectral_y_sums(K, beta, Y, &sb, &sd);
+      am += mul_i(inv2d * sb);
+      ad += lam == 0 ? inv2d * sd : (an * inv2d) * sb;
+    }
+    spec[(int64_t)row * nX + b] = (double)nX * am;
+    spec[(int64_t)(nrow + row) * nX + b] = (double)nX * ad;
   }
 }
 
@@ -1408,23 +1505,82 @@ int fft_launch(sesm_ctx* ctx, hipStream_t st, const FftJob& j0, const FftJob& j1
   return SESM_OK;
 }
 
+constexpr double kHybridWindow = 8.0;
 // The windowed lattice-sum tables (eq. Gq_limit with the Bloch phase of K.alpha)
 // of both grids, twisted and transformed along x, into spec = [specH | specV].
 int build_spectra(sesm_ctx* ctx, const KParams& K, cplx* spec) {
   AccelOp* A = ctx->acc;
-  const int pmax = (int)std::ceil(K.A_len / K.d) + 2;
+  // the windowed rows of hybrid tables take a window kHybridWindow times wider
+  // (their window error must stay far below that of a windowed table: next to
+  // exact rows, a row's window error is a jump between rows that the
+  // plane-wave fit of the cells amplifies)
+  KParams Kw = K;
+  if (A->hybrid) {
+    Kw.A_len *= kHybridWindow;
+    Kw.cA *= kHybridWindow;
+  }
+  const int pmax = (int)std::ceil(Kw.A_len / Kw.d) + 2;
   int rc;
   for (int lam = 0; lam < 2; ++lam) {
     const int nX = lam == 0 ? A->nXH : A->nXV, nY = lam == 0 ? A->nYH : A->nYV;
     const double hxs = lam == 0 ? A->delta : A->L, hys = lam == 0 ? A->L : A->delta;
     const int nrows = 2 * nY - 1;
     cplx* sp = spec + (lam == 0 ? 0 : (int64_t)2 * (2 * A->nYH - 1) * A->nXH);
-    const int64_t ent = (int64_t)nrows * nX;
-    hipLaunchKernelGGL(k_lattice, dim3((unsigned)((ent + 3) / 4)), dim3(256), 0, ctx->stream, K, lam, nX, nY, hxs,
-                       hys, pmax, sp);
-    SESM_LAUNCH_CHECK();
+    const AccelOp::HybridRows& H = A->hyb[lam];
+    const int nmap = A->hybrid ? (int)H.spatial.size() : nrows;
+    const int64_t ent = (int64_t)nmap * nX;
+    if (ent > 0) {
+      hipLaunchKernelGGL(k_lattice, dim3((unsigned)((ent + 3) / 4)), dim3(256), 0, ctx->stream, Kw, lam, nX, nY, hxs,
+                         hys, pmax, A->hybrid ? H.d_spatial : nullptr, nmap, sp);
+      SESM_LAUNCH_CHECK();
+    }
     const FftJob J = sesm_fft_job(lam == 0 ? A->planH : A->planV, 2 * nrows, sp, sp, nullptr, nullptr, 1.0);
     if ((rc = fft_launch(ctx, ctx->stream, J, FftJob{}, -1))) return rc;
+    if (A->hybrid && !H.spectral.empty()) {  // the spectral rows replace their (unfilled) transforms
+      hipLaunchKernelGGL(k_spectral_rows, dim3((unsigned)H.spectral.size()), dim3(256), 0, ctx->stream, K, lam, nX,
+                         nY, hys, H.d_spectral, H.d_nmax, sp);
+      SESM_LAUNCH_CHECK();
+    }
+  }
+  return SESM_OK;
+}
+
+// Which table rows the hybrid tables take from the spectral series (Sec. 3.2):
+// at height Y the terms of mode n decay like e^{-|beta_n| delta}, delta =
+// min_m |Y + m h| (eq. spectral_exp_estimate), so a row is spectral when delta > 0
+// and the order nmax at which e^{-|beta_n| delta} < e^{-42} for every incidence
+// (|alpha| < k) stays below kHybridMaxOrder; the rows close to a shifted pole
+// row Y = -m h keep the windowed sums.
+constexpr int kHybridMaxOrder = 40000;
+int hybrid_rows(sesm_ctx* ctx, AccelOp* A) {
+  const Problem& P = ctx->P;
+  int rc;
+  for (int lam = 0; lam < 2; ++lam) {
+    AccelOp::HybridRows& H = A->hyb[lam];
+    const int nY = lam == 0 ? A->nYH : A->nYV;
+    const double hy = lam == 0 ? A->L : A->delta;
+    H.spatial.clear();
+    H.spectral.clear();
+    H.nmax.clear();
+    for (int row = 0; row < 2 * nY - 1; ++row) {
+      const double Y = (row - (nY - 1)) * hy;
+      double delta = 1e300;
+      for (int m = 0; m <= P.j; ++m) delta = std::min(delta, std::fabs(Y + m * P.h));
+      bool spectral = false;
+      if (delta > 1e-9 * (P.h + hy)) {
+        const double need = std::sqrt((42.0 / delta) * (42.0 / delta) + P.k * P.k) + P.k;
+        const double nm = std::ceil(need * P.d / (2.0 * PI)) + 2.0;
+        if (nm <= kHybridMaxOrder) {
+          spectral = true;
+          H.spectral.push_back(row);
+          H.nmax.push_back((int)nm);
+        }
+      }
+      if (!spectral) H.spatial.push_back(row);
+    }
+    if ((rc = upload(ctx, &H.d_spatial, H.spatial)) || (rc = upload(ctx, &H.d_spectral, H.spectral)) ||
+        (rc = upload(ctx, &H.d_nmax, H.nmax)))
+      return rc;
   }
   return SESM_OK;
 }
@@ -1481,6 +1637,8 @@ void sesm_accel_info(const sesm_ctx* ctx, sesm_surface_info* info) {
   info->near_items[2] = A->near_c3 - A->near_c2;
   info->near_items[3] = A->n_chunks - A->near_c3;
   info->near_tuned_us = A->tuned_us;
+  info->spectral_rows[0] = A->hybrid ? (int32_t)A->hyb[0].spectral.size() : 0;
+  info->spectral_rows[1] = A->hybrid ? (int32_t)A->hyb[1].spectral.size() : 0;
 }
 
 static int choose_near_split(sesm_ctx* ctx);
@@ -1696,6 +1854,8 @@ int sesm_accel_setup(sesm_ctx* ctx) {
   if ((rc = sesm_alloc(ctx, (void**)&A->self_spec, sizeof(cplx) * (size_t)A->spec_len))) return rc;
   A->specH = A->self_spec;
   A->specV = A->self_spec + (int64_t)2 * (2 * A->nYH - 1) * A->nXH;
+  A->hybrid = prm.table == 1;
+  if (A->hybrid && (rc = hybrid_rows(ctx, A))) return rc;
   if ((rc = build_spectra(ctx, K, A->self_spec))) return rc;
   // --- local correction matrices
   A->n_off = (2 * A->ring + 1) * (2 * A->n_y - 1);
@@ -2383,6 +2543,257 @@ static int choose_near_split(sesm_ctx* ctx) {
   return SESM_OK;
 }
 
+// ------------------------------------------------------------------ off-surface field
+// The field at points inside the cell grid by the forward map's own stages,
+// as the remark closing Sec. 5.7 describes: for a point P in cell c^q,
+//   u(P) = (plane-wave expansion of psi^{ni,q}, eq. planewave, at P)
+//        + sum over the nodes of the near columns of dx K_dl(P - x_l) mu_l
+//        + the completion modes (eq. M_eta) at P,
+// where the plane-wave weights come from the boundary values b^q = phi^all
+// minus the local corrections of every occupied cell in the near columns
+// (eqs. small_convolution, combine_psi_pna) - formed here for any cell,
+// occupied or not.  One workgroup per cell holding points.
+struct FieldCellArgs {
+  int n_x, n_y, n_s, n_e, n_bH, n_bdry, n_eq, n_plw, nXH, nXV, ring, n_cells, N;
+  double L, x0, y0;
+  const int* tc_cell;      // cells holding points
+  const int* tc_off;       // their points: [tc_off[t], tc_off[t + 1]) of the lists below
+  const int* tgt;          // point index
+  const double* tx;        // point coordinates (x in [x0, x0 + d))
+  const double* ty;
+  const int* tp;           // quasi-periodic shift (periods) of each listed point
+  const int* col_occ_off;  // occupied cells of each column: col_occ[col_occ_off[c] .. col_occ_off[c + 1])
+  const int* col_occ;
+  const int* col_lo;
+  const int* col_w;
+  const cplx* W;
+  const cplx* dens;
+  const cplx* phH;
+  const cplx* phV;
+  const cplx* pplw;
+  const double* dirs;
+  const double* x;
+  const double* f;
+  const double* fp;
+  const cplx* mu;
+  const cplx* mode_part;
+  cplx* u;
+};
+
+__global__ __launch_bounds__(256) void k_field_cells(FieldCellArgs A, KParams K) {
+  extern __shared__ cplx dyn[];
+  __shared__ cplx bv[64];
+  __shared__ cplx wv_sh[64];
+  __shared__ cplx msum[SESM_MAX_UETA];
+  __shared__ cplx red[256];
+  const int cell = A.tc_cell[blockIdx.x];
+  const int cx = cell % A.n_x, cy = cell / A.n_x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const double ccx = A.x0 + (cx + 0.5) * A.L, ccy = A.y0 + (cy + 0.5) * A.L;
+  const int npf = (A.n_bdry + A.n_plw + 1) * A.n_plw;
+  cplx* pf = dyn;
+  const cplx php = cexp_i(K.alpha * K.d);
+  stage_copy<10>(pf, A.pplw, npf, threadIdx.x, 256);
+  if (wv == 1) {
+    for (int t = 0; t < K.nU; ++t) {
+      cplx a = cplx{0.0, 0.0};
+      for (int c = lane; c < NCH_MODES; c += 64) a += A.mode_part[(int64_t)t * NCH_MODES + c];
+      a = wave_sum(a);
+      if (lane == 0) msum[t] = a;
+    }
+  }
+  if (threadIdx.x < A.n_bdry) {
+    const int b = threadIdx.x;
+    cplx val;
+    if (b < A.n_bH) {
+      const int iy = b / (A.n_s + 1), i = b % (A.n_s + 1);
+      int gx = cx * A.n_s + i, Wr = 0;
+      if (gx >= A.nXH) { gx -= A.nXH; Wr = 1; }
+      val = A.phH[(int64_t)(cy + iy) * A.nXH + gx];
+      if (Wr) val = php * val;
+    } else {
+      const int t = b - A.n_bH, ix = t / (A.n_s - 1), i = 1 + t % (A.n_s - 1);
+      int gx = cx + ix, Wr = 0;
+      if (gx >= A.nXV) { gx -= A.nXV; Wr = 1; }
+      val = A.phV[(int64_t)(cy * A.n_s + i + A.n_e) * A.nXV + gx];
+      if (Wr) val = php * val;
+    }
+    // local corrections of the occupied cells of the near columns (offset o of
+    // the source cell, its densities of this boundary point's set)
+    const int ns2 = 2 * A.n_eq, lamb = b < A.n_bH ? 0 : 1;
+    cplx cs = cplx{0.0, 0.0};
+    for (int ox = -A.ring; ox <= A.ring; ++ox) {
+      int col = cx + ox;
+      const int wr = col < 0 ? -1 : (col >= A.n_x ? 1 : 0);
+      col -= wr * A.n_x;
+      for (int r = A.col_occ_off[col]; r < A.col_occ_off[col + 1]; ++r) {
+        const int rc = A.col_occ[r];
+        const int oy = rc / A.n_x - cy;
+        const int o = (ox + A.ring) * (2 * A.n_y - 1) + (oy + A.n_y - 1);
+        const cplx* Wo = A.W + (int64_t)o * ns2 * A.n_bdry + b;
+        const cplx* dv = A.dens + ((int64_t)lamb * A.n_cells + rc) * ns2;
+        cplx acc = cplx{0.0, 0.0};
+        for (int t = 0; t < ns2; ++t) acc += Wo[(int64_t)t * A.n_bdry] * dv[t];
+        cs += wr == 0 ? acc : (wr > 0 ? php : conj(php)) * acc;
+      }
+    }
+    bv[b] = val - cs;
+  }
+  __syncthreads();
+  // plane-wave weights w = V diag(1/sig) U^H b (eq. plwave_QR), one wavefront
+  if (wv == 0 && lane < A.n_plw) {
+    const cplx* Vs = pf + A.n_bdry * A.n_plw;
+    const cplx* isg = Vs + A.n_plw * A.n_plw;
+    cplx e = cplx{0.0, 0.0};
+    for (int b = 0; b < A.n_bdry; ++b) e += pf[b * A.n_plw + lane] * bv[b];
+    red[lane] = isg[lane].re * e;
+  }
+  __syncthreads();
+  if (wv == 0 && lane < A.n_plw) {
+    const cplx* Vs = pf + A.n_bdry * A.n_plw;
+    cplx w = cplx{0.0, 0.0};
+    for (int j = 0; j < A.n_plw; ++j) w += Vs[j * A.n_plw + lane] * red[j];
+    wv_sh[lane] = w;
+  }
+  __syncthreads();
+  // the points of the cell, one after another: threads over the near columns'
+  // nodes, the plane waves and the modes; a fixed-order block sum
+  const int lo = A.col_lo[cx], wdt = A.col_w[cx];
+  for (int t = A.tc_off[blockIdx.x]; t < A.tc_off[blockIdx.x + 1]; ++t) {
+    const double X = A.tx[t], Y = A.ty[t];
+    cplx acc = cplx{0.0, 0.0};
+    for (int uu = threadIdx.x; uu < wdt; uu += 256) {
+      int l = lo + uu;
+      const int wr = l < 0 ? -1 : (l >= A.N ? 1 : 0);
+      l -= wr * A.N;
+      cplx m = A.mu[l];
+      if (wr != 0) m = (wr > 0 ? php : conj(php)) * m;
+      acc += (K.dx * m) * sesm_kdl(K, X - (A.x[l] + wr * K.d), Y - A.f[l], A.fp[l]);
+    }
+    if (threadIdx.x < A.n_plw)
+      acc += wv_sh[threadIdx.x] *
+             cexp_i(K.k * (A.dirs[2 * threadIdx.x] * (X - ccx) + A.dirs[2 * threadIdx.x + 1] * (Y - ccy)));
+    if (threadIdx.x >= 128 && threadIdx.x - 128 < K.nU) {
+      const int n = threadIdx.x - 128;
+      acc += (exp(-K.Ubi[n] * Y) * cexp_i(K.Ua[n] * X + K.Ubr[n] * Y)) * msum[n];
+    }
+    const cplx s = block_sum<256>(acc, red);
+    if (threadIdx.x == 0) A.u[A.tgt[t]] = cexp_i(K.alpha * K.d * A.tp[t]) * s;
+  }
+}
+
+AccelGrid sesm_accel_grid(const sesm_ctx* ctx) {
+  const AccelOp* A = ctx->acc;
+  return AccelGrid{A->x0, A->y0, A->L, A->n_x, A->n_y};
+}
+
+int sesm_accel_field_cells(sesm_ctx* ctx, const cplx* mu, int n, const int* idx, const double* px, const double* py,
+                           const int* p, cplx* u) {
+  AccelOp* A = ctx->acc;
+  if (n == 0) return SESM_OK;
+  // points by cell
+  std::vector<int> cellof(n), order(n);
+  for (int t = 0; t < n; ++t) {
+    const int cx = std::min(A->n_x - 1, std::max(0, (int)std::floor((px[t] - A->x0) / A->L)));
+    const int cy = std::min(A->n_y - 1, std::max(0, (int)std::floor((py[t] - A->y0) / A->L)));
+    cellof[t] = cy * A->n_x + cx;
+    order[t] = t;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cellof[a] < cellof[b]; });
+  std::vector<int> tc_cell, tc_off, tgt(n), tp(n);
+  std::vector<double> tx(n), ty(n);
+  for (int r = 0; r < n; ++r) {
+    const int t = order[r];
+    if (tc_cell.empty() || tc_cell.back() != cellof[t]) {
+      tc_cell.push_back(cellof[t]);
+      tc_off.push_back(r);
+    }
+    tgt[r] = idx[t];
+    tx[r] = px[t];
+    ty[r] = py[t];
+    tp[r] = p[t];
+  }
+  tc_off.push_back(n);
+  // occupied cells of each column, in increasing cell index
+  std::vector<int> occ(A->n_occ);
+  SESM_HIP(hipMemcpyAsync(occ.data(), A->occ_cell, sizeof(int) * A->n_occ, hipMemcpyDeviceToHost, ctx->stream));
+  SESM_HIP(hipStreamSynchronize(ctx->stream));
+  std::vector<int> col_occ_off(A->n_x + 1, 0), col_occ;
+  for (int c : occ) ++col_occ_off[c % A->n_x + 1];
+  for (int c = 0; c < A->n_x; ++c) col_occ_off[c + 1] += col_occ_off[c];
+  col_occ.resize(A->n_occ);
+  {
+    std::vector<int> fill(col_occ_off.begin(), col_occ_off.end() - 1);
+    for (int c : occ) col_occ[fill[c % A->n_x]++] = c;
+  }
+  // device copies (freed before returning; the stream is synchronised)
+  const size_t nb = sizeof(int) * (tc_cell.size() + tc_off.size() + 2 * (size_t)n + col_occ_off.size() +
+                                   std::max<size_t>(col_occ.size(), 1)) +
+                    sizeof(double) * 2 * (size_t)n + sizeof(cplx) * (size_t)ctx->P.N + 256;
+  char* buf = nullptr;
+  SESM_HIP(hipMalloc((void**)&buf, nb));
+  char* cur = buf;
+  auto put = [&](const void* src, size_t bytes) -> void* {
+    void* d = cur;
+    if (bytes) (void)hipMemcpyAsync(d, src, bytes, hipMemcpyHostToDevice, ctx->stream);
+    cur += (bytes + 15) / 16 * 16;
+    return d;
+  };
+  cplx* ytmp = (cplx*)cur;
+  cur += sizeof(cplx) * (size_t)ctx->P.N;
+  FieldCellArgs F;
+  F.tc_cell = (const int*)put(tc_cell.data(), sizeof(int) * tc_cell.size());
+  F.tc_off = (const int*)put(tc_off.data(), sizeof(int) * tc_off.size());
+  F.tgt = (const int*)put(tgt.data(), sizeof(int) * n);
+  F.tp = (const int*)put(tp.data(), sizeof(int) * n);
+  F.tx = (const double*)put(tx.data(), sizeof(double) * n);
+  F.ty = (const double*)put(ty.data(), sizeof(double) * n);
+  F.col_occ_off = (const int*)put(col_occ_off.data(), sizeof(int) * col_occ_off.size());
+  F.col_occ = (const int*)put(col_occ.data(), sizeof(int) * col_occ.size());
+  int rc = accel_matvec_impl(ctx, mu, ytmp, false);  // phi^all grids, densities and mode sums of mu
+  if (rc == SESM_OK) {
+    F.n_x = A->n_x;
+    F.n_y = A->n_y;
+    F.n_s = A->n_s;
+    F.n_e = A->n_e;
+    F.n_bH = A->n_bH;
+    F.n_bdry = A->n_bdry;
+    F.n_eq = A->n_eq;
+    F.n_plw = A->n_plw;
+    F.nXH = A->nXH;
+    F.nXV = A->nXV;
+    F.ring = A->ring;
+    F.n_cells = A->n_cells;
+    F.N = ctx->P.N;
+    F.L = A->L;
+    F.x0 = A->x0;
+    F.y0 = A->y0;
+    F.col_lo = A->col_lo;
+    F.col_w = A->col_w;
+    F.W = A->W;
+    F.dens = A->dens;
+    F.phH = A->phH;
+    F.phV = A->phV;
+    F.pplw = A->pplw;
+    F.dirs = A->dirs;
+    F.x = ctx->x;
+    F.f = ctx->f;
+    F.fp = ctx->fp;
+    F.mu = mu;
+    F.mode_part = A->mode_part;
+    F.u = u;
+    const size_t lds = sizeof(cplx) * (size_t)(A->n_bdry + A->n_plw + 1) * A->n_plw;
+    hipLaunchKernelGGL(k_field_cells, dim3((unsigned)tc_cell.size()), dim3(256), lds, ctx->stream, F,
+                       ctx->kparams());
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) rc = ctx->fail(SESM_EHIP, std::string("k_field_cells: ") + hipGetErrorString(e));
+  }
+  const hipError_t es = hipStreamSynchronize(ctx->stream);
+  (void)hipFree(buf);
+  if (rc == SESM_OK && es != hipSuccess) rc = ctx->fail(SESM_EHIP, hipGetErrorString(es));
+  return rc;
+}
+
 extern "C" int sesm_diag_accel(sesm_ctx* ctx, const sesm_c64* mu, int32_t which, sesm_c64* out, int64_t out_len) {
   if (!ctx) return SESM_EINVAL;
   if (!ctx->ready) return ctx->fail(SESM_ENOSURF, "no surface");
@@ -2404,6 +2815,7 @@ extern "C" int sesm_diag_accel(sesm_ctx* ctx, const sesm_c64* mu, int32_t which,
     case 2: src = A->phV; len = nV; break;                                     // phi^all on the V grid [nYV][nXV]
     case 3: src = A->dens; len = (int64_t)2 * A->n_cells * 2 * A->n_eq; break; // per-cell densities
     case 4: src = A->bq; len = (int64_t)A->n_occ * A->n_bdry; break;           // boundary values b^q
+    case 5: src = A->self_spec; len = A->spec_len; break;                      // kernel spectra
     default: rc = ctx->fail(SESM_EINVAL, "unknown diagnostic buffer");
   }
   if (rc == SESM_OK && out_len < len) rc = ctx->fail(SESM_EINVAL, "output buffer too small");

@@ -419,6 +419,9 @@ int sesm_set_surface(sesm_ctx* ctx, const sesm_profile* prof, double d, double k
       !(prm.eta > 0) || !(prm.L_cell > 0) || prm.n_a < 2)
     return ctx->fail(SESM_EINVAL, "invalid discretisation parameter");
   if (prm.mode != SESM_MODE_DENSE && prm.mode != SESM_MODE_ACCEL) return ctx->fail(SESM_EINVAL, "unknown mode");
+  if (prm.table != 0 && prm.table != 1) return ctx->fail(SESM_EINVAL, "table must be 0 (windowed) or 1 (hybrid)");
+  if (prm.table == 1 && (prm.mode != SESM_MODE_ACCEL || j < 1))
+    return ctx->fail(SESM_EINVAL, "hybrid tables need the accelerated mode and j >= 1");
   const double a = prm.n_a * dx;
   if (!(a < d)) return ctx->fail(SESM_EINVAL, "singular window a = n_a dx must be < d (Remark selec_a)");
   if (!(prm.c_window * A_periods * d > a)) return ctx->fail(SESM_EINVAL, "window plateau c A must exceed a");

@@ -180,6 +180,17 @@ int sesm_accel_matvec(sesm_ctx* ctx, const cplx* mu, cplx* y, bool mixed = false
 int sesm_accel_matvec_batch(sesm_ctx* ctx, int nrhs, const cplx* mu, int64_t ldm, cplx* y, int64_t ldy,
                             int inc0 = -1, bool mixed = false);
 int sesm_accel_set_incidences(sesm_ctx* ctx, int n, const double* alpha);
+// Off-surface field (sesm_field): the accelerator's cell grid, and the field
+// at the points inside it (point index idx[t], coordinates px[t], py[t] with
+// px in [x0, x0 + d), quasi-periodic shift p[t] periods) into u (device, by
+// point index), from one forward map of mu
+struct AccelGrid {
+  double x0, y0, L;
+  int n_x, n_y;
+};
+AccelGrid sesm_accel_grid(const sesm_ctx* ctx);
+int sesm_accel_field_cells(sesm_ctx* ctx, const cplx* mu, int n, const int* idx, const double* px, const double* py,
+                           const int* p, cplx* u);
 int sesm_accel_n_incidences(const sesm_ctx* ctx);
 const Problem* sesm_accel_incidence(const sesm_ctx* ctx, int r);
 void sesm_accel_free(sesm_ctx* ctx);
