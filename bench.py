@@ -51,7 +51,7 @@ def parse():
     # a split the tuner settles near on this workload: fixed, so the kernel
     # shapes (and the counter-measured traffic) are the same from run to run.
     ap.add_argument("--near-split", default="595,110,125")
-    ap.add_argument("--no-mixed", action="store_true")  # skip the mixed-precision comparison solve
+    ap.add_argument("--no-mixed", action="store_true")  # skip the extra solves (mixed precision, hybrid tables, field)
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--workload", choices=["grazing", "c4"], default="grazing")
     ap.add_argument("--c4-angles", type=int, default=64)
@@ -447,6 +447,42 @@ def main():
     # the timed region
     oracle_cmp = efficiency_vs_oracle(recs[-1]["n"], recs[-1]["e"])
 
+    # hybrid spatial/spectral kernel tables (the same workload set up with
+    # table = 1), and the scattered field off the surface, outside the timed region
+    hybrid = field_rec = None
+    if args.mode == "accel" and not args.no_mixed:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        setup(table=1, **split_kw)
+        torch.cuda.synchronize()
+        t_set = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        mu_h, inf_h = s.solve(tol=args.tol, max_iter=args.max_iter, allow_noconv=True)
+        torch.cuda.synchronize()
+        t_sol = time.perf_counter() - t0
+        n_h, e_h, eps_h = s.efficiencies(mu_h)
+        cmp_h = efficiency_vs_oracle(n_h, e_h)
+        hybrid = {"setup_ms": t_set * 1e3, "windowed_setup_ms": float(np.mean([r["setup"] for r in recs])) * 1e3,
+                  "spectral_rows": s.info()["spectral_rows"], "solve_ms": t_sol * 1e3, "iters": inf_h["iters"],
+                  "converged": inf_h["converged"], "efficiency_err_vs_oracle": cmp_h["value"] if cmp_h else None,
+                  "max_efficiency_diff_vs_windowed": float(np.max(np.abs(e_h - recs[-1]["e"]))),
+                  "energy_balance_error": eps_h}
+        setup()
+        mu_f, _ = s.solve(tol=args.tol, max_iter=args.max_iter, allow_noconv=True)
+        inf = s.info()
+        ytop = inf["y0"] + inf["n_y"] * inf["L"]
+        rng = np.random.default_rng(3)
+        npts = 16384
+        field_rec = {"points": npts}
+        for name, yy in (("grid_ms", ytop - rng.uniform(0.01, 0.4, npts)), ("rayleigh_ms", ytop + 0.5 + rng.uniform(0, 2, npts))):
+            xx = rng.uniform(0, wl.d, npts)
+            s.field(mu_f, xx[:16], yy[:16])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.field(mu_f, xx, yy)
+            torch.cuda.synchronize()
+            field_rec[name] = (time.perf_counter() - t0) * 1e3
+
     # the whole forward map against the HBM roof: algorithmic bytes of its five
     # launches (per launch, from the fully timed warm-up step) over the
     # steady-state forward-map time
@@ -499,6 +535,8 @@ def main():
         "all_steps_converged": all(r["conv"] for r in recs),
         "efficiency_err_vs_oracle": oracle_cmp,
         "mixed_precision_solve": mixed,
+        "hybrid_table": hybrid,
+        "off_surface_field": field_rec,
         "energy_balance_error": max((r["eps"] for r in recs), key=abs),
         # every step solves the same problem: its efficiencies must agree bit for bit
         "steps_identical": all(np.array_equal(r["e"], recs[0]["e"]) for r in recs),
