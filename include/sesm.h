@@ -136,6 +136,9 @@ typedef struct {
                               operators in FP32, all sums and the near field in FP64);
                               needs a surface set up with sesm_params.mixed = 1.
                               residual_restarts then counts the refinement steps. */
+#define SESM_SOLVE_ADJOINT 4 /* solve the conjugate-transpose system (1/2 I + D^dx)^H mu = b
+                              (dense mode; b must be given): the adjoint densities of
+                              sesm_shape_gradient. */
 
 /* Read-only description of the discretisation chosen by sesm_set_surface. */
 typedef struct {
@@ -372,6 +375,38 @@ SESM_API int sesm_rayleigh_noalloc(sesm_ctx* ctx, const sesm_c64* mu, const int3
  * truncation error).  Allocates and frees a temporary device buffer;
  * synchronises the stream.  SESM_EINVAL for non-finite coordinates. */
 SESM_API int sesm_field(sesm_ctx* ctx, const sesm_c64* mu, int32_t n, const double* xy, sesm_c64* u);
+
+/* Adjoint map (dense mode): y = (1/2 I + D^dx)^H mu, the conjugate transpose of
+ * the operator of eq. (discrete_eq).  mu, y: device arrays of N sesm_c64, not
+ * overlapping.  Enqueued on the context's stream. */
+SESM_API int sesm_matvec_adjoint(sesm_ctx* ctx, const sesm_c64* mu, sesm_c64* y);
+
+/* Efficiency objective and its adjoint right-hand side (both modes).  For the
+ * density mu (device, N) of the current surface and weights w[t] of the
+ * propagating orders n = n_first + t (host, n_w = n_count values, the order of
+ * sesm_efficiencies): *J = sum_n w_n e_n with e_n = (beta_n / beta) |B_n|^2
+ * (Sec. 2; B_n = sum_l c_n(l) mu_l as in sesm_rayleigh), and
+ * rhs = conj(g), g_l = sum_n w_n (beta_n / beta) conj(B_n) c_n(l) (device, N):
+ * the right-hand side of the adjoint solve (SESM_SOLVE_ADJOINT) whose solution
+ * sesm_shape_gradient takes.  J may be NULL.  Synchronises the stream. */
+SESM_API int sesm_objective_adjoint_rhs(sesm_ctx* ctx, const sesm_c64* mu, const double* w, int32_t n_w,
+                                        sesm_c64* rhs, double* J);
+
+/* Shape gradient (dense mode) of the objective J of sesm_objective_adjoint_rhs
+ * with respect to the profile's Fourier coefficients (sesm_profile a[m], b[m],
+ * m = 0..n_modes): for the solution mu of the direct problem and the adjoint
+ * density nu (solution of SESM_SOLVE_ADJOINT with the right-hand side of
+ * sesm_objective_adjoint_rhs),
+ *   dJ/dtheta = 2 Re[ sum_n a_n sum_l (dc_n(l)/dtheta) mu_l
+ *                     + sum_i conj(nu_i) (db_i/dtheta - sum_l (dA_il/dtheta) mu_l) ],
+ * a_n = w_n (beta_n / beta) conj(B_n), with the entry derivatives taken
+ * analytically (the double-layer kernel and its windowed lattice sum, eq.
+ * DAdx_def; the singular split of eq. local_mat with K_s of eq. ks_def and the
+ * log weights; K_r(x, x); the completion modes of eq. M_eta).  grad_a,
+ * grad_b: host arrays of n_modes + 1 doubles (grad_b[0] = 0).  Allocates two
+ * N x N complex work matrices for the call; synchronises the stream. */
+SESM_API int sesm_shape_gradient(sesm_ctx* ctx, const sesm_c64* mu, const sesm_c64* nu, const double* w,
+                                 int32_t n_w, int32_t n_modes, double* grad_a, double* grad_b);
 
 /* Describe the current discretisation (host struct).  Returns SESM_ENOSURF
  * before a successful sesm_set_surface. */

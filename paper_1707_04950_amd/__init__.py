@@ -46,6 +46,7 @@ class SolveInfo(ctypes.Structure):
 
 SOLVE_X0 = 1  # sesm_solve flag: mu holds the initial guess on entry
 SOLVE_MIXED = 2  # mixed precision: FP64 refinement around FP32-basis inner solves
+SOLVE_ADJOINT = 4  # the conjugate-transpose system (dense mode)
 
 
 def _info_dict(i):
@@ -121,6 +122,10 @@ def load_library(path=LIB_PATH):
         "sesm_efficiencies_incidence": (ctypes.c_int, [_P, _I, _P, ctypes.POINTER(_I), ctypes.POINTER(_I),
                                                        ctypes.POINTER(_D), _I, ctypes.POINTER(_D)]),
         "sesm_field": (ctypes.c_int, [_P, _P, _I, _P, _P]),
+        "sesm_matvec_adjoint": (ctypes.c_int, [_P, _P, _P]),
+        "sesm_objective_adjoint_rhs": (ctypes.c_int, [_P, _P, ctypes.POINTER(_D), _I, _P, ctypes.POINTER(_D)]),
+        "sesm_shape_gradient": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(_D), _I, _I, ctypes.POINTER(_D),
+                                               ctypes.POINTER(_D)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -274,13 +279,14 @@ class Solver:
         return out
 
     def solve(self, b=None, tol=1e-10, max_iter=1000, restart=0, out=None, allow_noconv=False, x0=None,
-              mixed=False):
+              mixed=False, adjoint=False):
         """GMRES solve; x0 (a device tensor of N) is the initial guess and is
         overwritten with the solution (warm start); otherwise the iteration
         starts from zero and the solution goes to out (allocated if None).
         mixed: FP64 refinement around FP32-basis inner solves (surface set up
-        with mixed=1)."""
-        flags = SOLVE_MIXED if mixed else 0
+        with mixed=1).  adjoint: the conjugate-transpose system (dense mode,
+        b required)."""
+        flags = (SOLVE_MIXED if mixed else 0) | (SOLVE_ADJOINT if adjoint else 0)
         if x0 is not None:
             if out is not None and out is not x0:
                 raise ValueError("with x0 the solution overwrites x0; do not pass out")
@@ -392,6 +398,32 @@ class Solver:
                                             _ptr(out, n)))
         return out
 
+    def matvec_adjoint(self, mu, out=None):
+        out = self.empty() if out is None else out
+        self._check(self.lib.sesm_matvec_adjoint(self.h, _ptr(mu, self.N), _ptr(out, self.N)))
+        return out
+
+    def objective_adjoint_rhs(self, mu, weights):
+        """(J, rhs): J = sum_n w_n e_n over the propagating orders, rhs the
+        right-hand side of the adjoint solve."""
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        rhs = self.empty()
+        J = _D()
+        self._check(self.lib.sesm_objective_adjoint_rhs(self.h, _ptr(mu, self.N), w.ctypes.data_as(ctypes.POINTER(_D)),
+                                                        len(w), _ptr(rhs, self.N), ctypes.byref(J)))
+        return J.value, rhs
+
+    def shape_gradient(self, mu, nu, weights, n_modes):
+        """dJ/da_m, dJ/db_m (m = 0..n_modes) from the direct and adjoint densities."""
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        ga = np.zeros(n_modes + 1)
+        gb = np.zeros(n_modes + 1)
+        self._check(self.lib.sesm_shape_gradient(self.h, _ptr(mu, self.N), _ptr(nu, self.N),
+                                                 w.ctypes.data_as(ctypes.POINTER(_D)), len(w), int(n_modes),
+                                                 ga.ctypes.data_as(ctypes.POINTER(_D)),
+                                                 gb.ctypes.data_as(ctypes.POINTER(_D))))
+        return ga, gb
+
     def rayleigh(self, mu, orders):
         o = np.ascontiguousarray(orders, dtype=np.int32)
         B = np.zeros(len(o), dtype=np.complex128)
@@ -443,3 +475,36 @@ class Solver:
         h1 = torch.empty_like(h0)
         self._check(self.lib.sesm_diag_hankel(self.h, ctypes.c_void_p(x.data_ptr()), x.numel(), _ptr(h0), _ptr(h1)))
         return h0, h1
+
+
+def efficiency_objective(solver, a_coef, b_coef, weights, surface, tol=1e-10, max_iter=1000):
+    """J = sum_n w_n e_n of the surface with Fourier coefficients (a_coef,
+    b_coef) (torch tensors, float64, on the host; b_coef[0] unused) as a
+    differentiable function: a torch.autograd.Function whose forward sets up
+    the surface on `solver` (dense mode; `surface`: the other set_surface
+    keywords, d, k, alpha, j, A, N and discretisation parameters), solves and
+    forms J, and whose backward solves the adjoint system and takes the shape
+    gradient on the device."""
+    import torch
+
+    class _Objective(torch.autograd.Function):
+        @staticmethod
+        def forward(fctx, a, b):
+            kw = dict(surface)
+            kw["mode"] = MODE_DENSE
+            solver.set_surface(a.detach().cpu().numpy(), b.detach().cpu().numpy(), **kw)
+            mu, info = solver.solve(tol=tol, max_iter=max_iter)
+            J, _ = solver.objective_adjoint_rhs(mu, weights)
+            fctx.mu = mu
+            fctx.n_modes = a.shape[0] - 1
+            return torch.tensor(J, dtype=torch.float64)
+
+        @staticmethod
+        def backward(fctx, gJ):
+            J, rhs = solver.objective_adjoint_rhs(fctx.mu, weights)
+            nu, info = solver.solve(b=rhs, tol=tol, max_iter=max_iter, adjoint=True)
+            ga, gb = solver.shape_gradient(fctx.mu, nu, weights, fctx.n_modes)
+            g = float(gJ)
+            return torch.from_numpy(g * ga), torch.from_numpy(g * gb)
+
+    return _Objective.apply(a_coef, b_coef)

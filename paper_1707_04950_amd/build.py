@@ -11,7 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsesm.so")
-SOURCES = ["sesm_core.hip", "sesm_dense.hip", "sesm_gmres.hip", "sesm_accel.hip", "sesm_field.hip"]
+SOURCES = ["sesm_core.hip", "sesm_dense.hip", "sesm_gmres.hip", "sesm_accel.hip", "sesm_field.hip",
+           "sesm_adjoint.hip"]
 ARCH = os.environ.get("SESM_OFFLOAD_ARCH", "gfx950")
 
 

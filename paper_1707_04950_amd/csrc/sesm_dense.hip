@@ -74,6 +74,7 @@ int sesm_dense_setup(sesm_ctx* ctx) {
 }
 
 int sesm_dense_matvec(sesm_ctx* ctx, const cplx* mu, cplx* y) {
+  if (ctx->adjoint) return sesm_dense_matvec_adjoint(ctx, mu, y);
   const double N = ctx->P.N;
   SESM_KT_BEGIN(SESM_KT_GEMV, ctx->stream);
   hipLaunchKernelGGL(k_gemv_rows, dim3(ctx->P.N), dim3(256), 0, ctx->stream, ctx->P.N, ctx->Mdense, mu, y);

@@ -987,6 +987,16 @@ static int solve_mixed(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out, do
 extern "C" int sesm_solve(sesm_ctx* ctx, const sesm_c64* b_in, sesm_c64* mu_out, double tol, int32_t max_iter,
                           int32_t restart, int32_t flags, sesm_solve_info* info) {
   if (!ctx) return SESM_EINVAL;
+  if (flags & SESM_SOLVE_ADJOINT) {  // the conjugate-transpose system (dense mode)
+    if (!ctx->ready) return ctx->fail(SESM_ENOSURF, "no surface");
+    if (ctx->P.mode != SESM_MODE_DENSE || (flags & SESM_SOLVE_MIXED))
+      return ctx->fail(SESM_EINVAL, "adjoint solves need the dense mode (and no mixed precision)");
+    if (!b_in) return ctx->fail(SESM_EINVAL, "adjoint solves need a right-hand side");
+    ctx->adjoint = true;
+    const int rc = solve_impl(ctx, b_in, mu_out, tol, max_iter, restart, flags & ~SESM_SOLVE_ADJOINT, INFINITY, info);
+    ctx->adjoint = false;
+    return rc;
+  }
   if (flags & SESM_SOLVE_MIXED)
     return solve_mixed(ctx, b_in, mu_out, tol, max_iter, restart, flags & ~SESM_SOLVE_MIXED, info, -1);
   return solve_impl(ctx, b_in, mu_out, tol, max_iter, restart, flags, INFINITY, info);

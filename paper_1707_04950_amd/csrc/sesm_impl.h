@@ -71,6 +71,7 @@ struct sesm_ctx {
   hipStream_t stream = nullptr;
   std::string err;
   bool ready = false;
+  bool adjoint = false;  // dense-mode operator applications use the conjugate transpose (adjoint solves)
   Problem P;
   sesm_params prm{};
   // surface samples (device), length N
@@ -199,6 +200,7 @@ void sesm_accel_info(const sesm_ctx* ctx, sesm_surface_info* info);
 // operator dispatch; sesm_apply_inc applies the operator of member inc of the
 // incidence set (inc < 0: the surface's own incidence)
 int sesm_apply(sesm_ctx* ctx, const cplx* mu, cplx* y);
+int sesm_dense_matvec_adjoint(sesm_ctx* ctx, const cplx* mu, cplx* y);
 int sesm_apply_inc(sesm_ctx* ctx, const cplx* mu, cplx* y, int inc, bool mixed = false);
 
 // incidence-dependent scalars (alpha, beta, U^eta, propagating orders) of P
