@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--near-split", default="595,110,125")
     ap.add_argument("--no-mixed", action="store_true")  # skip the extra solves (mixed precision, hybrid tables, field)
     ap.add_argument("--copy-probe", action="store_true")
-    ap.add_argument("--workload", choices=["grazing", "c4"], default="grazing")
+    ap.add_argument("--workload", choices=["grazing", "c4", "c5"], default="grazing")
     ap.add_argument("--c4-angles", type=int, default=64)
     ap.add_argument("--c4-N", type=int, default=16384)
     ap.add_argument("--c4-max-iter", type=int, default=1000)
@@ -160,6 +160,88 @@ def efficiency_vs_oracle(n, e):
     return None
 
 
+def bench_c5(args):
+    """Adjoint gradient of the specular efficiency with respect to the 256
+    cosine and 256 sine coefficients of the deep-corrugation profile (dense
+    mode, N = 8192): set-up, direct solve, adjoint solve and shape gradient,
+    timed; checked against central finite differences (step 1e-6, and
+    Richardson-extrapolated steps 1e-3 / 5e-4) of the library's own solves for
+    the largest entries, outside the timed region."""
+    import numpy as np
+    import torch
+
+    import paper_1707_04950_amd as lib
+    import workloads as W
+
+    wl = W.config_c5(8192)
+    s = lib.Solver(0)
+    N = wl.N
+    n_a = max(8, int(math.floor(0.8 * min(wl.L, wl.d) / wl.dx)))
+    kw = dict(d=wl.d, k=wl.k, alpha=wl.alpha, j=wl.j, A=wl.A, N=N, h=wl.h, c=wl.c, n_a=n_a,
+              gamma_frac=wl.gamma_frac, eta=wl.eta, L=wl.L, mode=lib.MODE_DENSE)
+    a0, b0 = np.array(wl.a_coef), np.array(wl.b_coef)
+
+    def J_of(a, b, w):
+        s.set_surface(a, b, **kw)
+        mu, _ = s.solve(tol=1e-11, max_iter=3000, allow_noconv=True)
+        return s.objective_adjoint_rhs(mu, w)[0]
+
+    def gradient():
+        t0 = time.perf_counter()
+        s.set_surface(a0, b0, **kw)
+        mu, info = s.solve(tol=1e-11, max_iter=3000, allow_noconv=True)
+        n, e, eps = s.efficiencies(mu)
+        w = np.zeros(len(n))
+        w[list(n).index(0)] = 1.0
+        J, rhs = s.objective_adjoint_rhs(mu, w)
+        t1 = time.perf_counter()
+        nu, info2 = s.solve(b=rhs, tol=1e-12, max_iter=3000, adjoint=True, allow_noconv=True)
+        ga, gb = s.shape_gradient(mu, nu, w, 256)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return dict(t_forward=t1 - t0, t_adjoint=t2 - t1, J=J, eps=eps, iters=info["iters"],
+                    res=info["rel_residual"], adj_iters=info2["iters"], ga=ga, gb=gb, w=w)
+
+    gradient()  # warm-up
+    steps = max(1, args.steps)
+    t0 = time.perf_counter()
+    recs = [gradient() for _ in range(steps)]
+    total = time.perf_counter() - t0
+    r = recs[-1]
+    scale = max(np.max(np.abs(r["ga"])), np.max(np.abs(r["gb"])))
+    checks = []
+    for kind, g in (("a", r["ga"]), ("b", r["gb"])):
+        for m in list(np.argsort(-np.abs(g[1:]))[:2] + 1):
+            fd = []
+            for hh in (1e-6, 1e-3, 5e-4):
+                ap, bp, am, bm = a0.copy(), b0.copy(), a0.copy(), b0.copy()
+                (ap if kind == "a" else bp)[m] += hh
+                (am if kind == "a" else bm)[m] -= hh
+                fd.append((J_of(ap, bp, r["w"]) - J_of(am, bm, r["w"])) / (2 * hh))
+            rich = (4 * fd[2] - fd[1]) / 3
+            checks.append({"coef": "%s_%d" % (kind, m), "adjoint": float(g[m]), "fd_step_1e-6": fd[0],
+                           "fd_richardson": rich, "rel_err_fd_1e-6": abs(fd[0] - g[m]) / scale,
+                           "rel_err_richardson": abs(rich - g[m]) / scale})
+    out = {
+        "metric": "adjoint gradients/s: d(specular efficiency)/d(512 profile coefficients), deep corrugation N=8192",
+        "value": steps / total,
+        "unit": "gradients/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "N": N, "d_over_lambda": wl.d, "depth_pp": 10.0, "coefficients": 256,
+                   "theta_deg": wl.theta_deg, "j": wl.j, "h": wl.h, "A_periods": wl.A, "mode": "dense"},
+        "phase_s": {"setup_forward_solve": float(np.mean([x["t_forward"] for x in recs])),
+                    "adjoint_solve_and_gradient": float(np.mean([x["t_adjoint"] for x in recs]))},
+        "specular_efficiency": r["J"], "energy_balance_error": r["eps"], "iters": r["iters"],
+        "rel_residual": r["res"], "adjoint_iters": r["adj_iters"],
+        "gradient_max_abs": scale, "finite_difference_checks": checks,
+    }
+    s.close()
+    print(json.dumps(out))
+
+
 def bench_c4(args):
     """Many incidences (C4): a Gaussian random surface of period 50, N = 16384,
     64 incidence angles uniform in [0, 85] degrees at each of 4 wavenumbers
@@ -261,6 +343,12 @@ def main():
     args = parse()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.workload == "c5":
+        if args.gpus != 1:
+            print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus, file=sys.stderr)
+            sys.exit(2)
+        bench_c5(args)
         return
     if args.workload == "c4":
         if args.gpus != 1:

@@ -173,6 +173,38 @@ def test_shape_gradient_vs_finite_differences(torch, solver):
         assert abs(fo - g) <= 1e-8 * scale
 
 
+def test_deep_corrugation_gradient(torch, solver):
+    """The deep-corrugation workload (256 Fourier coefficients, 10 lambda peak
+    to peak, period 10 lambda) at N = 2048: the gradient of the specular
+    efficiency with respect to all 256 cosine coefficients by one adjoint
+    solve, against Richardson-extrapolated finite differences of the library's
+    own solves for the three largest entries and one of the smallest; energy
+    balance holds."""
+    wl = W.config_c5(2048)
+    disc = _set(solver, wl)
+    mu, info = solver.solve(tol=1e-11, max_iter=3000, allow_noconv=True)
+    n, e, eps = solver.efficiencies(mu)
+    w = np.zeros(len(n))
+    w[list(n).index(0)] = 1.0
+    J, rhs = solver.objective_adjoint_rhs(mu, w)
+    nu, _ = solver.solve(b=rhs, tol=1e-12, max_iter=3000, adjoint=True, allow_noconv=True)
+    ga, gb = solver.shape_gradient(mu, nu, w, 256)
+    a0, b0 = np.array(wl.a_coef, dtype=float), np.array(wl.b_coef, dtype=float)
+
+    def Jg(a, b):
+        _set(solver, wl, a, b)
+        m_, _ = solver.solve(tol=1e-11, max_iter=3000, allow_noconv=True)
+        return solver.objective_adjoint_rhs(m_, w)[0]
+
+    scale = np.max(np.abs(ga))
+    idx = list(np.argsort(-np.abs(ga[1:]))[:3] + 1) + [200]
+    errs = [abs(_richardson(Jg, a0, b0, "a", m) - ga[m]) / scale for m in idx]
+    print("deep profile N = 2048: %d iterations, eps %.1e, e_0 %.6f; d e_0 / d a_m for m = %s: %s; "
+          "vs finite differences %s" % (info["iters"], eps, J, idx, np.array2string(ga[idx], precision=6),
+                                        ["%.1e" % v for v in errs]))
+    assert abs(eps) <= 1e-4 and max(errs) <= 1e-6
+
+
 def test_autograd_function(torch, solver):
     """The torch.autograd.Function: J.backward() fills the coefficient
     gradients with the adjoint shape gradient."""
