@@ -436,14 +436,19 @@ def main():
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
     def time_matvec():
-        for _ in range(5):
+        # steady state: the median of three rounds of `reps` maps after a warm-up
+        # (the first round after the solves runs a few per cent slow)
+        for _ in range(10):
             s.matvec(mu, y)
-        ev0.record()
-        for _ in range(reps):
-            s.matvec(mu, y)
-        ev1.record()
-        torch.cuda.synchronize()
-        return ev0.elapsed_time(ev1) / 1e3 / reps
+        rounds = []
+        for _ in range(3):
+            ev0.record()
+            for _ in range(reps):
+                s.matvec(mu, y)
+            ev1.record()
+            torch.cuda.synchronize()
+            rounds.append(ev0.elapsed_time(ev1) / 1e3 / reps)
+        return sorted(rounds)[1]
 
     mv_s = time_matvec()
     y_fixed = y.clone()
