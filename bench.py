@@ -260,17 +260,18 @@ def bench_c4(args):
     angles = W.c4_angles(args.c4_angles)
     nk = len(W.C4_D_OVER_LAMBDA)
 
-    def setup(wl, theta=0.0, mixed=False):
+    def setup(wl, theta=0.0, mixed=False, mfma=False):
         n_a = max(8, int(math.floor(0.8 * min(wl.L, wl.d) / wl.dx)))
         w = wl.with_(theta_deg=theta)
         s.set_surface(np.asarray(w.a_coef), np.asarray(w.b_coef), w.d, w.k, w.alpha, w.j, w.A, w.N, h=w.h, c=w.c,
-                      n_a=n_a, gamma_frac=w.gamma_frac, eta=w.eta, mode=lib.MODE_ACCEL, L=w.L, mixed=int(mixed))
+                      n_a=n_a, gamma_frac=w.gamma_frac, eta=w.eta, mode=lib.MODE_ACCEL, L=w.L, mixed=int(mixed),
+                      batch_mfma=int(mfma))
 
-    def batched(ik, mixed=False):
+    def batched(ik, mixed=False, mfma=False):
         wl = W.config_c4(ik, args.c4_N)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        setup(wl, mixed=mixed)
+        setup(wl, mixed=mixed, mfma=mfma)
         s.set_incidences([wl.k * math.sin(math.radians(t)) for t in angles])
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -297,9 +298,14 @@ def bench_c4(args):
 
     batched(0)  # warm-up: tuner, pools, code objects
     batched(0, mixed=True)
+    batched(0, mfma=True)
     single(0)
     recs = [batched(ik) for ik in range(nk)]
     t_batch = sum(r["setup"] + r["solve"] + r["eff"] for r in recs)
+    frecs = [batched(ik, mfma=True) for ik in range(nk)]
+    t_mfma = sum(r["setup"] + r["solve"] + r["eff"] for r in frecs)
+    dmf = max(float(np.max(np.abs(np.asarray(em) - np.asarray(eb)))) for r, m in zip(recs, frecs)
+              for eb, em in zip(r["e"], m["e"]))
     mrecs = [batched(ik, mixed=True) for ik in range(nk)]
     t_mixed = sum(r["setup"] + r["solve"] + r["eff"] for r in mrecs)
     dmix = max(float(np.max(np.abs(np.asarray(em) - np.asarray(eb)))) for r, m in zip(recs, mrecs)
@@ -324,6 +330,10 @@ def bench_c4(args):
         "all_converged": all(all(r["conv"]) for r in recs) and all(c for _, o in sing for _, _, c in o),
         "max_energy_balance_error": max(abs(p) for r in recs for p in r["eps"]),
         "max_efficiency_diff_batched_vs_single": diff,
+        "matrix_cores_batched": {
+            "solves_per_s": n_solves / t_mfma, "speedup_vs_single": t_single / t_mfma,
+            "speedup_vs_vector_batched": t_batch / t_mfma, "solve_s": sum(r["solve"] for r in frecs),
+            "all_converged": all(all(r["conv"]) for r in frecs), "max_efficiency_diff_vs_vector_batched": dmf},
         "mixed_precision_batched": {
             "solves_per_s": n_solves / t_mixed, "speedup_vs_fp64_batched": t_batch / t_mixed,
             "solve_s": sum(r["solve"] for r in mrecs),
@@ -512,6 +522,29 @@ def main():
                   "iters": [i["iters"] for i in infos], "all_converged": all(i["converged"] for i in infos),
                   "column_mismatches": int(sum(i["column_mismatches"] for i in infos)),
                   "member0_equals_single": bool(torch.equal(xb[0], x1))}
+        # the same batch with the near field of the eight densities on the matrix cores
+        setup(batch_mfma=1, **split_kw)
+        s.solve_batch(B, tol=args.batch_tol, max_iter=args.max_iter, allow_noconv=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xm, infm = s.solve_batch(B, tol=args.batch_tol, max_iter=args.max_iter, allow_noconv=True)
+        torch.cuda.synchronize()
+        bm_s = time.perf_counter() - t0
+        ybm = torch.empty_like(mub)
+        s.matvec_batch(mub, ybm)
+        for _ in range(3):
+            s.matvec_batch(mub, ybm)
+        ev0.record()
+        for _ in range(reps // 3):
+            s.matvec_batch(mub, ybm)
+        ev1.record()
+        torch.cuda.synchronize()
+        bsolve["matrix_cores"] = {
+            "ms_per_batch": bm_s * 1e3, "solves_per_s": BATCH / bm_s, "speedup_vs_single_solve": single_s * BATCH / bm_s,
+            "forward_map_ms_per_8": ev0.elapsed_time(ev1) / (reps // 3),
+            "iters": [i["iters"] for i in infm], "all_converged": all(i["converged"] for i in infm),
+            "max_rel_diff_vs_vector_solutions": float((xm - xb).abs().max() / xb.abs().max())}
+        setup()
 
     # mixed precision (FP32 EqSources operators and Krylov basis under FP64
     # refinement) on the same workload, outside the timed region: a surface

@@ -110,7 +110,14 @@ typedef struct {
                          anomalies, where it decays only like A^{-3.5}, the
                          cells' plane-wave fits amplify such jumps).
                          Needs j >= 1 and the accelerated mode.                   */
-  int32_t reserved;
+  int32_t batch_mfma; /* accelerator: 1 applies the near field of batched forward maps
+                         (sesm_matvec_batch, sesm_solve_batch and the incidence-set
+                         calls) to groups of up to eight densities on the FP64 matrix
+                         cores (one pass over the stored blocks per eight densities);
+                         the sums are then formed in another order than in
+                         sesm_matvec, so batch members agree with single forward maps
+                         to rounding, not bit for bit.  0 (default): four densities
+                         per pass on the vector units, bit for bit.               */
 } sesm_params;
 
 typedef struct {

@@ -105,6 +105,10 @@ struct AccelOp {
     int *d_spatial = nullptr, *d_spectral = nullptr, *d_nmax = nullptr;
   } hyb[2];
   bool hybrid = false;
+  // batched near field on the matrix cores: 16-row tiles (cell, first row)
+  bool batch_mfma = false;
+  int n_tiles = 0;
+  int *tile_q = nullptr, *tile_t0 = nullptr;
   IncParams* inc_self = nullptr;          // device record of the surface's incidence
   int n_inc = 0;                          // incidence set (sesm_set_incidences)
   IncParams* inc_set = nullptr;           // device records [n_inc]
@@ -794,7 +798,7 @@ struct NearFill {
 };
 
 
-__device__ __forceinline__ NearArgs near_args(const LocalArgs& L) {
+__host__ __device__ inline NearArgs near_args(const LocalArgs& L) {
   NearArgs A;
   A.N = L.N;
   A.n_x = L.n_x;
@@ -946,6 +950,109 @@ __global__ __launch_bounds__(LOC_NT) void k_local_apply_batch(KParams K, LocalAr
                                                               int64_t ldm, cplx* __restrict__ y, int64_t ldy,
                                                               const IncParams* __restrict__ inc, int inc_step) {
   local_apply<NB, PT>(K, L, mu, ldm, y, ldy, inc, inc_step);
+}
+
+// The near field of up to eight densities on the matrix cores (FP64 MFMA,
+// 16 x 16 x 4): a workgroup takes 16 rows t of one occupied cell q and forms
+// Y[t][s] = sum_u blk_q[t][u] mu_s[band_q(u)] for the densities s < nm as the
+// real product [Re Y | Im Y] (16 x 16) = A (16 x 2w) B (2w x 16) with
+//   A[t][2u + c] = (c = 0: Re, 1: Im) blk_q[t][u],
+//   B[2u][s] = Re m_s(u), B[2u][8 + s] = Im m_s(u), B[2u + 1][s] = -Im m_s(u), B[2u + 1][8 + s] = Re m_s(u),
+// m_s(u) the density of band column u (with its Bloch phase for a wrapped
+// column).  Each of the four wavefronts takes a quarter of the columns
+// (steps of two columns = one MFMA of K = 4) and the quarters are added in LDS
+// in a fixed order.  Lane layouts of v_mfma_f64_16x16x4f64: A[l % 16][l / 16],
+// B[l / 16][l % 16], D[4 r + l / 16][l % 16] in register r.
+typedef double sesm_v4d __attribute__((ext_vector_type(4)));
+constexpr int MF_COLS = 16;  // band columns per staged chunk and wavefront
+__global__ __launch_bounds__(256) void k_near_mfma8(NearArgs NA, const int* __restrict__ tile_q,
+                                                    const int* __restrict__ tile_t0, int nm,
+                                                    const cplx* __restrict__ mu, int64_t ldm, cplx* __restrict__ y,
+                                                    int64_t ldy, const IncParams* __restrict__ inc, int inc_step) {
+  // per wavefront: the chunk's 16 rows x MF_COLS columns of the block (row
+  // stride padded by one double against bank conflicts) and its densities
+  constexpr int AS = 2 * MF_COLS + 1;
+  __shared__ double As[4][16 * AS];
+  __shared__ cplx Ms[4][MF_COLS * 8];
+  __shared__ double red[4][4][64];
+  const int q = tile_q[blockIdx.x], t0 = tile_t0[blockIdx.x];
+  const int off = NA.occ_off[q], nq = NA.occ_off[q + 1] - off;
+  const int nr = min(16, nq - t0);
+  const int col = NA.occ_cell[q] % NA.n_x;
+  const int lo = NA.col_lo[col], w = NA.col_w[col];
+  const int N = NA.N;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const cplx* blk = NA.nearblk + NA.near_off[q] + (int64_t)t0 * w;
+  // this wavefront's columns [u_begin, u_end); every wavefront runs the same number of chunks
+  const int quarter = ((w + 4 * MF_COLS - 1) / (4 * MF_COLS)) * MF_COLS;
+  const int u_begin = min(w, wv * quarter), u_end = min(w, u_begin + quarter);
+  // staging roles: block rows lane / 4 (clamped to the tile), columns 4 (lane % 4) .. + 3;
+  // densities: member lane % 8, columns 2 (lane / 8) .. + 1
+  const int sr = min(lane >> 2, nr - 1), sc = (lane & 3) * 4;
+  const int ms = lane & 7, mc = (lane >> 3) * 2;
+  cplx phs = cplx{1.0, 0.0};
+  if (ms < nm) phs = cexp_i(inc[ms * inc_step].alpha_d);
+  // MFMA roles
+  const int kk = lane >> 4, i = lane & 15;
+  const int s = i & 7, part = i >> 3, cb = kk & 1;
+  double* Aw = As[wv];
+  cplx* Mw = Ms[wv];
+  sesm_v4d acc = {0.0, 0.0, 0.0, 0.0};
+  // the next chunk's loads are issued before the current chunk's products
+  cplx av[4], mv[2];
+  auto load = [&](int ub) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int u = ub + sc + t;
+      av[t] = u < u_end ? blk[(int64_t)sr * w + u] : cplx{0.0, 0.0};
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int u = ub + mc + t;
+      cplx m = cplx{0.0, 0.0};
+      if (u < u_end && ms < nm) {
+        int l = lo + u;
+        const int wr = (l < 0) ? -1 : ((l >= N) ? 1 : 0);
+        l -= wr * N;
+        m = mu[(int64_t)ms * ldm + l];
+        if (wr != 0) m = cmul_fixed(wr > 0 ? phs : conj(phs), m);
+      }
+      mv[t] = m;
+    }
+  };
+  load(u_begin);
+  for (int c0 = 0; c0 < quarter; c0 += MF_COLS) {
+    __syncthreads();  // the previous chunk's reads are done
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      Aw[(lane >> 2) * AS + 2 * (sc + t)] = av[t].re;
+      Aw[(lane >> 2) * AS + 2 * (sc + t) + 1] = av[t].im;
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) Mw[(mc + t) * 8 + ms] = mv[t];
+    __syncthreads();
+    if (c0 + MF_COLS < quarter) load(u_begin + c0 + MF_COLS);
+#pragma unroll
+    for (int st = 0; st < MF_COLS / 2; ++st) {
+      const int ul = 2 * st + (kk >> 1);
+      const double a = Aw[i * AS + 2 * ul + cb];
+      const cplx m = Mw[ul * 8 + s];
+      const double b = cb == 0 ? (part == 0 ? m.re : m.im) : (part == 0 ? -m.im : m.re);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) red[wv][r][lane] = acc[r];
+  __syncthreads();
+  // thread (r, l) of the sum: element D[4 r + l / 16][l % 16]
+  const int r = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const double v = (red[0][r][l] + red[1][r][l]) + (red[2][r][l] + red[3][r][l]);
+  const int row = 4 * r + (l >> 4), j = l & 15;
+  if (row < nr && (j & 7) < nm) {
+    const int dst = NA.perm[off + t0 + row];
+    double* yd = reinterpret_cast<double*>(y + (int64_t)(j & 7) * ldy + dst);
+    yd[j >> 3] = v;
+  }
 }
 
 struct MergeArgs {
@@ -1764,12 +1871,23 @@ int sesm_accel_setup(sesm_ctx* ctx) {
     }
   A->n_cfc = (int)cfc_q.size();
   for (int c = 0; c < A->n_x; ++c) A->max_w = std::max(A->max_w, col_w[c]);
+  // tiles of the batched near field on the matrix cores: up to 16 rows of one cell
+  std::vector<int> tile_q, tile_t0;
+  A->batch_mfma = prm.batch_mfma == 1;
+  if (A->batch_mfma)
+    for (int q = 0; q < A->n_occ; ++q)
+      for (int t0 = 0; t0 < occ_off[q + 1] - occ_off[q]; t0 += 16) {
+        tile_q.push_back(q);
+        tile_t0.push_back(t0);
+      }
+  A->n_tiles = (int)tile_q.size();
   int rc;
   if ((rc = upload(ctx, &A->occ_cell, occ_cell)) || (rc = upload(ctx, &A->occ_off, occ_off)) ||
       (rc = upload(ctx, &A->perm, perm)) || (rc = upload(ctx, &A->col_lo, col_lo)) ||
       (rc = upload(ctx, &A->col_w, col_w)) || (rc = upload(ctx, &A->near_off, near_off)) ||
       (rc = upload(ctx, &A->chunk_q, chunk_q)) || (rc = upload(ctx, &A->chunk_t0, chunk_t0)) ||
-      (rc = upload(ctx, &A->cfc_q, cfc_q)) || (rc = upload(ctx, &A->cfc_t0, cfc_t0)))
+      (rc = upload(ctx, &A->cfc_q, cfc_q)) || (rc = upload(ctx, &A->cfc_t0, cfc_t0)) ||
+      (rc = upload(ctx, &A->tile_q, tile_q)) || (rc = upload(ctx, &A->tile_t0, tile_t0)))
     return rc;
   // local-correction pairs: for every occupied cell, the occupied cells of its
   // 2 ring + 1 columns (all rows), with the correction-matrix offset and the
@@ -2325,6 +2443,20 @@ int sesm_accel_matvec_batch(sesm_ctx* ctx, int nrhs, const cplx* mu, int64_t ldm
   Fb.bphV = (int64_t)per[7];
   Fb.bcorr = (int64_t)per[8];
   Fb.by = ldy;
+  const bool mfma = A->batch_mfma && A->n_tiles > 0;
+  if (mfma) {
+    // the near field of groups of up to eight densities on the matrix cores;
+    // the local launches below then carry the EqSources and mode sums only
+    L.n_chunks = 0;
+    const NearArgs NA = near_args(L);
+    for (int r0 = 0; r0 < nrhs; r0 += 8) {
+      const int nm = std::min(8, nrhs - r0);
+      const IncParams* ip = inc0 < 0 ? A->inc_self : A->inc_set + inc0 + r0;
+      hipLaunchKernelGGL(k_near_mfma8, dim3(A->n_tiles), dim3(256), 0, st, NA, A->tile_q, A->tile_t0, nm,
+                         mu + r0 * ldm, ldm, y + r0 * ldy, ldy, ip, inc0 < 0 ? 0 : 1);
+      SESM_LAUNCH_CHECK();
+    }
+  }
   for (int r0 = 0; r0 < nrhs; r0 += kBatchMax) {
     const int nb = std::min(kBatchMax, nrhs - r0);
     const cplx* m0 = mu + r0 * ldm;

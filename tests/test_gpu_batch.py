@@ -349,3 +349,44 @@ def test_solve_batch_full_size_grazing_wood(torch, solver):
         n, e, eps = solver.efficiencies(mu[r])
         print("p = %d: %d iterations, %d orders, energy balance %.2e" % (p, infos[r]["iters"], len(n), eps))
         assert infos[r]["converged"] and infos[r]["column_mismatches"] == 0 and abs(eps) <= 1e-6
+
+
+@pytest.mark.parametrize("nrhs,pad", [(1, 0), (5, 3), (8, 0), (9, 2), (17, 0)])
+def test_batch_matrix_cores_match_single(torch, solver, nrhs, pad):
+    """batch_mfma = 1: the near field of up to eight densities per pass on the
+    FP64 matrix cores.  Every row equals its single forward map to rounding
+    (the sums run in another order: not bit for bit), the padding stays
+    untouched."""
+    wl = _gauss30()
+    disc = dense.Discretization(wl)
+    _configure(solver, wl, disc, True)
+    N = disc.N
+    mu = _densities(torch, N, list(range(31, 31 + nrhs)), pad)
+    ys = torch.stack([solver.matvec(mu[r, :N].contiguous()) for r in range(nrhs)])
+    _configure(solver, wl, disc, True, batch_mfma=1)
+    out = torch.full((nrhs, N + pad), complex(-5.0, 2.0), dtype=torch.complex128, device="cuda")
+    solver.matvec_batch(mu[:, :N], out[:, :N])
+    torch.cuda.synchronize()
+    err = float((out[:, :N] - ys).abs().max() / ys.abs().max())
+    print("nrhs %d: matrix-core batch vs single maps %.2e" % (nrhs, err))
+    assert err <= 1e-14
+    if pad:
+        assert bool((out[:, N:] == complex(-5.0, 2.0)).all())
+
+
+def test_incidence_set_matrix_cores(torch, solver):
+    """Incidence sets (different alpha per member) with batch_mfma = 1: each
+    member's forward map equals the vector-unit one to rounding."""
+    wl = _gauss30()
+    disc = dense.Discretization(wl)
+    alphas = [wl.k * math.sin(math.radians(t)) for t in (5.0, 17.0, 30.0, 44.0, 61.0)]
+    mu = _densities(torch, disc.N, list(range(51, 56)))
+    _configure(solver, wl, disc, True)
+    solver.set_incidences(alphas)
+    yv = solver.matvec_incidences(mu)
+    _configure(solver, wl, disc, True, batch_mfma=1)
+    solver.set_incidences(alphas)
+    ym = solver.matvec_incidences(mu)
+    err = float((ym - yv).abs().max() / yv.abs().max())
+    print("incidence set, matrix cores vs vector units: %.2e" % err)
+    assert err <= 1e-14
