@@ -79,7 +79,8 @@ typedef struct {
   double L_cell;      /* accelerator cell side L, eq. (L_constr); default 0.5 * 2 pi / k  */
   int32_t n_side;     /* accelerator: equivalent-source grid intervals per cell side      */
   int32_t n_ext;      /* accelerator: extra equivalent-source points beyond each corner;
-                         0 selects 1, a negative value selects none                        */
+                         0 selects 1, a negative value selects none; the points per side,
+                         n_side + 1 + 2 n_ext, must not exceed 16 (SESM_EINVAL)           */
   int32_t n_coll;     /* accelerator: collocation points per side of the 3L square, eq. (eq_source_point) */
   int32_t n_plw;      /* accelerator: plane waves per cell, eq. (planewave)               */
   int32_t near_ring;  /* accelerator: columns on each side of a cell treated directly

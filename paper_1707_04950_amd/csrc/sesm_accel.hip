@@ -724,11 +724,11 @@ __device__ __forceinline__ void near_accum_band(const NearArgs& A, int q, int t0
       }
       cplx v[RP];
 #pragma unroll
-      for (int r = 0; r < RP; ++r) v[r] = blk[(int64_t)min(r0 + r, nr - 1) * w + u];
+      for (int r = 0; r < RP; ++r) v[r] = load_stream(&blk[(int64_t)min(r0 + r, nr - 1) * w + u]);
 #pragma unroll
       for (int s = 0; s < NB; ++s)
 #pragma unroll
-        for (int r = 0; r < RP; ++r) acc[s][r] += v[r] * m[s];
+        for (int r = 0; r < RP; ++r) acc[s][r] = cmac(acc[s][r], v[r], m[s]);
     }
 #pragma unroll
     for (int s = 0; s < NB; ++s)
@@ -871,7 +871,7 @@ __device__ __forceinline__ void local_apply(const KParams& K, const LocalArgs& L
           for (int r = 0; r < NB; ++r) {
             const cplx m = mus[r][t + u * NG];
 #pragma unroll
-            for (int j = 0; j < OPL; ++j) acc[r][j] += v[u][j] * m;
+            for (int j = 0; j < OPL; ++j) acc[r][j] = cmac(acc[r][j], v[u][j], m);
           }
       }
       for (; t < nc; t += NG) {
@@ -882,7 +882,7 @@ __device__ __forceinline__ void local_apply(const KParams& K, const LocalArgs& L
         for (int r = 0; r < NB; ++r) {
           const cplx m = mus[r][t];
 #pragma unroll
-          for (int j = 0; j < OPL; ++j) acc[r][j] += v[j] * m;
+          for (int j = 0; j < OPL; ++j) acc[r][j] = cmac(acc[r][j], v[j], m);
         }
       }
     }
@@ -916,7 +916,7 @@ __device__ __forceinline__ void local_apply(const KParams& K, const LocalArgs& L
         for (int l = lo + threadIdx.x; l < hi; l += LOC_NT) {
           const double mag = exp(ubi * L.f[l]) * L.J[l] * K.dx;
           const cplx e = mag * cexp_i(-(ua * L.x[l] + ubr * L.f[l]));
-          acc += e * mu[r * ldm + l];
+          acc = cmac(acc, e, mu[r * ldm + l]);
         }
         const cplx sm = block_sum<LOC_NT>(acc, red);
         if (threadIdx.x == 0) L.mode_part[r * L.mode_ld + (int64_t)t * NCH_MODES + b] = sm;
@@ -1004,7 +1004,7 @@ __global__ __launch_bounds__(256) void k_near_mfma8(NearArgs NA, const int* __re
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int u = ub + sc + t;
-      av[t] = u < u_end ? blk[(int64_t)sr * w + u] : cplx{0.0, 0.0};
+      av[t] = u < u_end ? load_stream(&blk[(int64_t)sr * w + u]) : cplx{0.0, 0.0};
     }
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
@@ -1774,6 +1774,8 @@ int sesm_accel_setup(sesm_ctx* ctx) {
   if (!(P.a < A->L)) return ctx->fail(SESM_EINVAL, "accelerator: singular window a must be < L (Remark a_cond)");
   A->n_side = A->n_s + 1 + 2 * A->n_e;
   A->n_eq = 2 * A->n_side;
+  if (A->n_side > 16)  // the EqSources lane layout holds 4 n_eq <= 128 outputs per cell
+    return ctx->fail(SESM_EINVAL, "accelerator: n_side + 1 + 2 n_ext (equivalent sources per cell side) must be <= 16");
   A->n_bH = 2 * (A->n_s + 1);
   A->n_bdry = A->n_bH + 2 * (A->n_s - 1);
   if (A->n_bdry > 64) return ctx->fail(SESM_EINVAL, "accelerator: too many boundary points");

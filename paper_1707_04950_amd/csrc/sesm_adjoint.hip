@@ -150,7 +150,7 @@ __global__ __launch_bounds__(256) void k_gemv_cols(int N, const cplx* __restrict
   cplx acc = cplx{0.0, 0.0};
   if (l < N)
     for (int i = wv; i < N; i += 4) {
-      const cplx m = M[(int64_t)i * N + l];
+      const cplx m = load_stream(&M[(int64_t)i * N + l]);
       acc += (CONJ ? conj(m) : m) * x[i];
     }
   part[wv][lane] = acc;
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(256) void k_gemv_rows_g(int N, const cplx* __restri
   __shared__ cplx sh[4];
   const cplx* row = M + (int64_t)blockIdx.x * N;
   cplx acc = cplx{0.0, 0.0};
-  for (int l = threadIdx.x; l < N; l += 256) acc += row[l] * x[l];
+  for (int l = threadIdx.x; l < N; l += 256) acc += load_stream(&row[l]) * x[l];
   const cplx s = block_sum<256>(acc, sh);
   if (threadIdx.x == 0) y[blockIdx.x] = s;
 }

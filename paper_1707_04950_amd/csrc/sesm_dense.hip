@@ -47,13 +47,14 @@ __global__ __launch_bounds__(256) void k_dense_assemble(KParams K, const double*
   }
 }
 
-// y_i = sum_l M_il mu_l: one 256-thread block per row.
+// y_i = sum_l M_il mu_l: one 256-thread block per row (the operator streamed
+// past the caches, which keep the Krylov basis).
 __global__ __launch_bounds__(256) void k_gemv_rows(int N, const cplx* __restrict__ M, const cplx* __restrict__ mu,
                                                    cplx* __restrict__ y) {
   __shared__ cplx sh[4];
   const cplx* row = M + (int64_t)blockIdx.x * N;
   cplx acc = cplx{0.0, 0.0};
-  for (int l = threadIdx.x; l < N; l += 256) acc += row[l] * mu[l];
+  for (int l = threadIdx.x; l < N; l += 256) acc += load_stream(&row[l]) * mu[l];
   const cplx s = block_sum<256>(acc, sh);
   if (threadIdx.x == 0) y[blockIdx.x] = s;
 }

@@ -272,6 +272,8 @@ def test_accelerated_parameters_are_validated(torch, solver):
     wl = W.config_random_double_wood(4096)
     base = dict(h=wl.h, c=wl.c, gamma_frac=wl.gamma_frac, eta=wl.eta, mode=lib.MODE_ACCEL)
     bad = [dict(L=0.5, n_side=20),            # too many equivalent sources per side
+           dict(L=0.5, n_side=14),            # 14 + 1 + 2 > 16 sources per side (EqSources layout)
+           dict(L=0.5, n_side=10, n_ext=3),   # 10 + 1 + 6 > 16
            dict(L=0.5, near_ring=5),          # near-field ring beyond 3 columns
            dict(L=0.04, n_a=8),               # periodic grid longer than the FFT supports
            dict(L=0.5, n_plw=80)]             # more plane waves than supported
