@@ -86,8 +86,8 @@ __device__ __forceinline__ void gm_dots(int N, int nv, const VT* __restrict__ V,
     const cplx wn = has_w ? w[in] : cplx{0.0, 0.0};
 #pragma unroll
     for (int t = 0; t < VB; ++t) {
-      au[t] += cmul_conj(a[t], ui);
-      aw[t] += cmul_conj(a[t], wi);
+      au[t] = cmac_conj(au[t], a[t], ui);
+      aw[t] = cmac_conj(aw[t], a[t], wi);
     }
 #pragma unroll
     for (int t = 0; t < VB; ++t) a[t] = b[t];
@@ -294,14 +294,16 @@ __device__ __forceinline__ void gm_update(int N, int k, int m, int nrb, VT* V, i
     }
 #pragma unroll
     for (int t = 0; t < UPD_B; ++t) {
-      s1 += x[t] * a1[t];
-      s2 += x[t] * a2[t];
+      s1 = cmac(s1, x[t], a1[t]);
+      s2 = cmac(s2, x[t], a2[t]);
     }
   }
+  // (the remaining vectors one at a time: a tail padded with zero-weight
+  // loads measured slower)
   for (; v < k; v += 4) {
     const cplx x = widen(V[(int64_t)v * ldv + i]);
-    s1 += x * cS[v];
-    s2 += x * cC[v];
+    s1 = cmac(s1, x, cS[v]);
+    s2 = cmac(s2, x, cC[v]);
   }
   red[0][wv][lane] = s1;
   red[1][wv][lane] = s2;
