@@ -315,21 +315,22 @@ struct CellGeo {
 };
 
 // Back-substitution R x = y on one wavefront (n <= 64): lane u holds y_u on
-// entry and x_u on exit; R row-major upper triangular (n x n).  Column-oriented:
-// x_r is broadcast and subtracted from the rows above it.
-__device__ inline cplx sesm_wave_backsub(const cplx* __restrict__ R, int n, cplx yu) {
+// entry and x_u on exit; R upper triangular (n x n) stored column-major,
+// R[u][r] at Rc[r n + u], so that the lanes' reads of a column are contiguous.
+// Column-oriented: x_r is broadcast and subtracted from the rows above it.
+__device__ inline cplx sesm_wave_backsub(const cplx* __restrict__ Rc, int n, cplx yu) {
   const int lane = threadIdx.x & 63;
   for (int r = n - 1; r >= 0; --r) {
     cplx xr = cplx{0.0, 0.0};
     if (lane == r) {
-      const cplx d = R[(int64_t)r * n + r];
+      const cplx d = Rc[(int64_t)r * n + r];
       const double dd = 1.0 / abs2(d);
       xr = cplx{(yu.re * d.re + yu.im * d.im) * dd, (yu.im * d.re - yu.re * d.im) * dd};
       yu = xr;
     }
     xr.re = sesm_readlane(xr.re, r);
     xr.im = sesm_readlane(xr.im, r);
-    if (lane < r) yu -= R[(int64_t)lane * n + r] * xr;
+    if (lane < r) yu -= Rc[(int64_t)r * n + lane] * xr;
   }
   return yu;
 }
@@ -414,17 +415,17 @@ __global__ __launch_bounds__(256) void k_p2e_setup(KParams K, CellGeo G, double 
       const cplx* Rm = Qh + (int64_t)ncol * nrow;
       if (t < c1) {
         cplx yu = cplx{0.0, 0.0};
-        if (lane < ncol) {  // Q^H B: sixteen loads of the row in flight at a time
-          const cplx* qrow = Qh + (int64_t)lane * nrow;
+        if (lane < ncol) {  // Q^H B: sixteen loads in flight, each a contiguous row of (Q^H)^T
+          const cplx* qcol = Qh + lane;
           int c = 0;
           for (; c + 16 <= nrow; c += 16) {
             cplx qv[16];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) qv[u] = qrow[c + u];
+            for (int u = 0; u < 16; ++u) qv[u] = qcol[(int64_t)(c + u) * ncol];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) yu += qv[u] * B[c + u];
+            for (int u = 0; u < 16; ++u) yu = cmac(yu, qv[u], B[c + u]);
           }
-          for (; c < nrow; ++c) yu += qrow[c] * B[c];
+          for (; c < nrow; ++c) yu = cmac(yu, qcol[(int64_t)c * ncol], B[c]);
         }
         yu = sesm_wave_backsub(Rm, ncol, yu);
         if (lane < ncol) Pq[(int64_t)t * 2 * ncol + lam * ncol + lane] = yu;
@@ -2026,10 +2027,20 @@ int sesm_accel_setup(sesm_ctx* ctx) {
     else
       factor(1);
     if (!ok[0] || !ok[1]) return ctx->fail(SESM_EINVAL, "equivalent-source matrix is rank deficient");
+    // per set: Q^H (ncol x nrow) and R (ncol x ncol), both stored column-major
+    // (the P2E set-up's lanes run over the rows)
     std::vector<cplx> qr_all;
     for (int lam = 0; lam < 2; ++lam) {
-      for (const C& v : Qh[lam]) qr_all.push_back(cplx{v.real(), v.imag()});
-      for (const C& v : Rm[lam]) qr_all.push_back(cplx{v.real(), v.imag()});
+      for (int c = 0; c < nrow; ++c)
+        for (int j = 0; j < ncol; ++j) {
+          const C v = Qh[lam][(size_t)j * nrow + c];
+          qr_all.push_back(cplx{v.real(), v.imag()});
+        }
+      for (int r = 0; r < ncol; ++r)
+        for (int u = 0; u < ncol; ++u) {
+          const C v = Rm[lam][(size_t)u * ncol + r];
+          qr_all.push_back(cplx{v.real(), v.imag()});
+        }
     }
     if ((rc = upload(ctx, &A->pinv, qr_all))) return rc;
   }
