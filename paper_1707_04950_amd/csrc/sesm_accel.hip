@@ -1005,7 +1005,7 @@ __global__ __launch_bounds__(256) void k_near_mfma8(NearArgs NA, const int* __re
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int u = ub + sc + t;
-      av[t] = u < u_end ? load_stream(&blk[(int64_t)sr * w + u]) : cplx{0.0, 0.0};
+      av[t] = u < u_end ? blk[(int64_t)sr * w + u] : cplx{0.0, 0.0};  // (plain loads: the non-temporal hint measured slower here)
     }
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
