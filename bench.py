@@ -356,18 +356,18 @@ def main():
         return
     if args.workload == "c5":
         if args.gpus != 1:
-            print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus, file=sys.stderr)
+            print("bench.py: the solver runs on a single GPU; --gpus %d is not supported" % args.gpus, file=sys.stderr)
             sys.exit(2)
         bench_c5(args)
         return
     if args.workload == "c4":
         if args.gpus != 1:
-            print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus, file=sys.stderr)
+            print("bench.py: the solver runs on a single GPU; --gpus %d is not supported" % args.gpus, file=sys.stderr)
             sys.exit(2)
         bench_c4(args)
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        print("bench.py: the solver runs on a single GPU; --gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
