@@ -138,24 +138,43 @@ __global__ __launch_bounds__(256) void k_dense_deriv(KParams K, const double* __
   }
 }
 
-// y = M^H x: 64 columns per workgroup (lane = column), the four wavefronts
-// take every fourth row, their partial sums added in LDS in a fixed order.
-// conj_m = false gives y = M^T x.
+// y = M^H x (CONJ; M^T x otherwise): 64 columns per workgroup (lane =
+// column; each wavefront load reads 1 KB of a row), the sixteen wavefronts
+// take every sixteenth row with eight rows' loads in flight per lane, and
+// their partial sums are added in LDS in a fixed order.  (With N / 64
+// workgroups the launch is narrow, hence the many rows in flight per
+// workgroup.)
 template <bool CONJ>
-__global__ __launch_bounds__(256) void k_gemv_cols(int N, const cplx* __restrict__ M, const cplx* __restrict__ x,
-                                                   cplx* __restrict__ y) {
-  __shared__ cplx part[4][64];
+__global__ __launch_bounds__(1024) void k_gemv_cols(int N, const cplx* __restrict__ M, const cplx* __restrict__ x,
+                                                    cplx* __restrict__ y) {
+  constexpr int NW = 16, U = 8;
+  __shared__ cplx part[NW][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int l = blockIdx.x * 64 + lane;
+  const int lc = min(l, N - 1);  // lanes past N repeat the last column (not stored)
   cplx acc = cplx{0.0, 0.0};
-  if (l < N)
-    for (int i = wv; i < N; i += 4) {
-      const cplx m = load_stream(&M[(int64_t)i * N + l]);
-      acc += (CONJ ? conj(m) : m) * x[i];
+  int i = wv;
+  for (; i + NW * (U - 1) < N; i += NW * U) {
+    cplx m[U], xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      m[u] = load_stream(&M[(int64_t)(i + NW * u) * N + lc]);
+      xv[u] = x[i + NW * u];
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc = cmac(acc, CONJ ? conj(m[u]) : m[u], xv[u]);
+  }
+  for (; i < N; i += NW) {
+    const cplx m = load_stream(&M[(int64_t)i * N + lc]);
+    acc = cmac(acc, CONJ ? conj(m) : m, x[i]);
+  }
   part[wv][lane] = acc;
   __syncthreads();
-  if (wv == 0 && l < N) y[l] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+  if (wv == 0 && l < N) {
+    cplx sm = part[0][lane];
+    for (int w = 1; w < NW; ++w) sm += part[w][lane];
+    y[l] = sm;
+  }
 }
 
 // y = M x, one workgroup per row
@@ -403,8 +422,8 @@ extern "C" int sesm_shape_gradient(sesm_ctx* ctx, const sesm_c64* mu_, const ses
     hipLaunchKernelGGL(k_dense_deriv, dim3((N + 3) / 4, N), dim3(256), 0, ctx->stream, K, ctx->x, ctx->f, ctx->fp,
                        ctx->fpp, ctx->J, ctx->logw, DY, DF);
     hipLaunchKernelGGL(k_gemv_rows_g, dim3(N), dim3(256), 0, ctx->stream, N, DY, mu, DYmu);
-    hipLaunchKernelGGL(k_gemv_cols<false>, dim3((N + 63) / 64), dim3(256), 0, ctx->stream, N, DY, cnu, DYtnu);
-    hipLaunchKernelGGL(k_gemv_cols<false>, dim3((N + 63) / 64), dim3(256), 0, ctx->stream, N, DF, cnu, DFtnu);
+    hipLaunchKernelGGL(k_gemv_cols<false>, dim3((N + 63) / 64), dim3(1024), 0, ctx->stream, N, DY, cnu, DYtnu);
+    hipLaunchKernelGGL(k_gemv_cols<false>, dim3((N + 63) / 64), dim3(1024), 0, ctx->stream, N, DF, cnu, DFtnu);
     hipLaunchKernelGGL(k_grad_nodes, dim3((N + 255) / 256), dim3(256), 0, ctx->stream, K, no, dord, da, P.beta,
                        ctx->x, ctx->f, ctx->fp, ctx->fpp, ctx->J, mu, nu, DYmu, DYtnu, DFtnu, Pk, Qk, Rk);
     hipLaunchKernelGGL(k_grad_modes, dim3(2 * (n_modes + 1)), dim3(256), 0, ctx->stream, N, P.d, ctx->x, Pk, Qk, Rk,
@@ -425,7 +444,7 @@ extern "C" int sesm_shape_gradient(sesm_ctx* ctx, const sesm_c64* mu_, const ses
 // y = (1/2 I + D^dx)^H mu (dense mode)
 int sesm_dense_matvec_adjoint(sesm_ctx* ctx, const cplx* mu, cplx* y) {
   const int N = ctx->P.N;
-  hipLaunchKernelGGL(k_gemv_cols<true>, dim3((N + 63) / 64), dim3(256), 0, ctx->stream, N, ctx->Mdense, mu, y);
+  hipLaunchKernelGGL(k_gemv_cols<true>, dim3((N + 63) / 64), dim3(1024), 0, ctx->stream, N, ctx->Mdense, mu, y);
   SESM_LAUNCH_CHECK();
   return SESM_OK;
 }
