@@ -188,7 +188,7 @@ def bench_c5(args):
 
     def gradient():
         t0 = time.perf_counter()
-        s.set_surface(a0, b0, **kw)
+        s.set_surface(a0, b0, adjoint=1, **kw)  # the derivative matrices in the same pass as the operator
         mu, info = s.solve(tol=1e-11, max_iter=3000, allow_noconv=True)
         n, e, eps = s.efficiencies(mu)
         w = np.zeros(len(n))

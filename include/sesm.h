@@ -119,6 +119,13 @@ typedef struct {
                          sesm_matvec, so batch members agree with single forward maps
                          to rounding, not bit for bit.  0 (default): four densities
                          per pass on the vector units, bit for bit.               */
+  int32_t adjoint;    /* dense mode: 1 also forms the derivative matrices dA/dY and
+                         dA/df' of the operator entries (sesm_shape_gradient) in the
+                         same pass over the lattice sums as the operator itself, and
+                         keeps them with the surface (2 N^2 more complex values), so
+                         that sesm_shape_gradient does not form them again; 0
+                         (default): sesm_shape_gradient forms them on each call.
+                         SESM_EINVAL with the accelerated mode.                   */
 } sesm_params;
 
 typedef struct {
@@ -411,8 +418,10 @@ SESM_API int sesm_objective_adjoint_rhs(sesm_ctx* ctx, const sesm_c64* mu, const
  * analytically (the double-layer kernel and its windowed lattice sum, eq.
  * DAdx_def; the singular split of eq. local_mat with K_s of eq. ks_def and the
  * log weights; K_r(x, x); the completion modes of eq. M_eta).  grad_a,
- * grad_b: host arrays of n_modes + 1 doubles (grad_b[0] = 0).  Allocates two
- * N x N complex work matrices for the call; synchronises the stream. */
+ * grad_b: host arrays of n_modes + 1 doubles (grad_b[0] = 0).  The derivative
+ * matrices dA/dY, dA/df' are those the set-up kept (sesm_params.adjoint = 1),
+ * else formed for the call in two N x N complex work matrices; synchronises
+ * the stream. */
 SESM_API int sesm_shape_gradient(sesm_ctx* ctx, const sesm_c64* mu, const sesm_c64* nu, const double* w,
                                  int32_t n_w, int32_t n_modes, double* grad_a, double* grad_b);
 

@@ -35,7 +35,8 @@ class Params(ctypes.Structure):
                 ("mode", ctypes.c_int32), ("L_cell", ctypes.c_double), ("n_side", ctypes.c_int32),
                 ("n_ext", ctypes.c_int32), ("n_coll", ctypes.c_int32), ("n_plw", ctypes.c_int32),
                 ("near_ring", ctypes.c_int32), ("near_split", ctypes.c_int32),
-                ("split_permille", ctypes.c_int32 * 3), ("mixed", ctypes.c_int32), ("table", ctypes.c_int32), ("batch_mfma", ctypes.c_int32)]
+                ("split_permille", ctypes.c_int32 * 3), ("mixed", ctypes.c_int32), ("table", ctypes.c_int32), ("batch_mfma", ctypes.c_int32),
+                ("adjoint", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -216,7 +217,7 @@ class Solver:
 
     def set_surface(self, a_coef, b_coef, d, k, alpha, j, A, N, h=0.0, c=0.0, n_a=0, gamma_frac=0.0,
                     eta=0.0, mode=MODE_DENSE, L=0.0, n_side=0, n_ext=0, n_coll=0, n_plw=0, near_ring=0,
-                    near_split=0, split_permille=(0, 0, 0), mixed=0, table=0, batch_mfma=0):
+                    near_split=0, split_permille=(0, 0, 0), mixed=0, table=0, batch_mfma=0, adjoint=0):
         a = np.ascontiguousarray(a_coef, dtype=np.float64)
         b = np.zeros_like(a)
         bb = np.asarray(b_coef, dtype=np.float64)
@@ -227,7 +228,7 @@ class Solver:
         prm = Params(N=N, h=h, c_window=c, n_a=n_a, gamma_frac=gamma_frac, eta=eta, mode=mode, L_cell=L,
                      n_side=n_side, n_ext=n_ext, n_coll=n_coll, n_plw=n_plw, near_ring=near_ring,
                      near_split=near_split, split_permille=(ctypes.c_int32 * 3)(*split_permille), mixed=int(mixed),
-                     table=int(table), batch_mfma=int(batch_mfma))
+                     table=int(table), batch_mfma=int(batch_mfma), adjoint=int(adjoint))
         self._check(self.lib.sesm_set_surface(self.h, ctypes.byref(prof), d, k, alpha, j, A, ctypes.byref(prm)))
         self.N = N
 
@@ -492,6 +493,8 @@ def efficiency_objective(solver, a_coef, b_coef, weights, surface, tol=1e-10, ma
         def forward(fctx, a, b):
             kw = dict(surface)
             kw["mode"] = MODE_DENSE
+            # a gradient to come: the derivative matrices with the operator, in one pass
+            kw.setdefault("adjoint", int(a.requires_grad or b.requires_grad))
             solver.set_surface(a.detach().cpu().numpy(), b.detach().cpu().numpy(), **kw)
             mu, info = solver.solve(tol=tol, max_iter=max_iter)
             J, _ = solver.objective_adjoint_rhs(mu, weights)

@@ -96,6 +96,109 @@ __device__ inline void entry_offdiag_deriv(const KParams& K, const double* __res
   *dF = ef;
 }
 
+// One source image: the entry of sesm_entry_offdiag and its two derivatives
+// of entry_offdiag_deriv in one evaluation, the Hankel functions of each
+// shifted image computed once (H1 for the entry, H0 and H1 for the
+// derivatives; the entry's own terms in the same order as sesm_entry_offdiag).
+__device__ inline void entry_and_derivs(const KParams& K, const double* __restrict__ logw, double X, double Y,
+                                        double fps, double SA, cplx* ent, cplx* dY, cplx* dF) {
+  cplx kd = cplx{0.0, 0.0}, ay = cplx{0.0, 0.0}, af = cplx{0.0, 0.0};
+  for (int m = 0; m <= K.j; ++m) {
+    const double Ym = Y + m * K.h;
+    const double R = sqrt(X * X + Ym * Ym);
+    cplx H0, H1;
+    sesm_hankel01(K.k * R, &H0, &H1);
+    kd += (K.wshift[m] * (Ym - fps * X) / R) * H1;
+    const double num = Ym - fps * X;
+    const cplx dR = (K.k / R) * H0 - (2.0 / (R * R)) * H1;  // d/dR (H1(kR)/R)
+    ay += K.wshift[m] * ((1.0 / R) * H1 + (num * Ym / R) * dR);
+    af += (-K.wshift[m] * X / R) * H1;
+  }
+  const cplx Kd = (0.25 * K.k) * mul_i(kd);
+  const cplx dKy = (0.25 * K.k) * mul_i(ay), dKf = (0.25 * K.k) * mul_i(af);
+  const double r = sqrt(X * X + Y * Y);
+  const double Sf = sesm_window(r, K.gamma, K.a);
+  cplx term = (K.dx * SA * (1.0 - Sf)) * Kd;
+  cplx ey = (K.dx * SA * (1.0 - Sf)) * dKy, ef = (K.dx * SA * (1.0 - Sf)) * dKf;
+  const double dSf = window_dx(r, K.gamma, K.a) * (r > 0.0 ? Y / r : 0.0);
+  if (Sf > 0.0 || dSf != 0.0) {
+    const double sn = sin(SESM_PI * X / K.a);
+    const double lg = log(4.0 * sn * sn);
+    int mi = (int)llrint(-X / K.dx);
+    mi = mi < 0 ? -mi : mi;
+    mi %= K.n_a;
+    const double Rm = logw[mi];
+    if (Sf > 0.0) {
+      const double Ks = (K.k / (4.0 * SESM_PI)) * (fps * X - Y) * sesm_besselj1(K.k * r) / r;
+      term += Sf * (cplx{Rm * Ks, 0.0} + K.dx * (Kd - cplx{Ks * lg, 0.0}));
+    }
+    cplx H0, H1;
+    sesm_hankel01(K.k * r, &H0, &H1);
+    const double J0 = H0.re, J1 = H1.re;
+    const double c = K.k / (4.0 * SESM_PI);
+    const double Ks = c * (fps * X - Y) * J1 / r;
+    const double dJr = K.k * J0 / r - 2.0 * J1 / (r * r);
+    const double dKs_y = c * (-J1 / r + (fps * X - Y) * dJr * (Y / r));
+    const double dKs_f = c * X * J1 / r;
+    ey += dSf * (cplx{Rm * Ks, 0.0} + K.dx * (Kd - cplx{Ks * lg, 0.0}) - (K.dx * SA) * Kd);
+    ey += Sf * (cplx{Rm * dKs_y, 0.0} + K.dx * (dKy - cplx{dKs_y * lg, 0.0}));
+    ef += Sf * (cplx{Rm * dKs_f, 0.0} + K.dx * (dKf - cplx{dKs_f * lg, 0.0}));
+  }
+  *ent = term;
+  *dY = ey;
+  *dF = ef;
+}
+
+// The dense operator (as k_dense_assemble) together with DY and DF (as
+// k_dense_deriv), one wave per entry, lanes over the source images.
+__global__ __launch_bounds__(256) void k_dense_assemble_deriv(KParams K, const double* __restrict__ x,
+                                                              const double* __restrict__ f,
+                                                              const double* __restrict__ fp,
+                                                              const double* __restrict__ fpp,
+                                                              const double* __restrict__ J,
+                                                              const double* __restrict__ logw, cplx* __restrict__ M,
+                                                              cplx* __restrict__ DY, cplx* __restrict__ DF) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.y;
+  const int l = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (l >= K.N) return;  // wave-uniform
+  const int64_t e = (int64_t)i * K.N + l;
+  const double X0 = x[i] - x[l], Y = f[i] - f[l], fps = fp[l];
+  cplx acc = cplx{0.0, 0.0}, ay = cplx{0.0, 0.0}, af = cplx{0.0, 0.0};
+  for (int p = K.pmin + lane; p <= K.pmax; p += 64) {
+    const double Xp = X0 - p * K.d;
+    const double SA = sesm_window(Xp, K.cA, K.A_len);
+    if (SA == 0.0) continue;
+    if (p == 0 && i == l) continue;  // diagonal: handled below
+    cplx en, dy, df;
+    entry_and_derivs(K, logw, Xp, Y, fps, SA, &en, &dy, &df);
+    const cplx ph = cexp_i(K.alpha * p * K.d);
+    acc += ph * en;
+    ay += ph * dy;
+    af += ph * df;
+  }
+  acc = wave_sum(acc);
+  ay = wave_sum(ay);
+  af = wave_sum(af);
+  if (lane == 0) {
+    if (i == l) {
+      acc += sesm_entry_diag(K, fp[i], fpp[i]);
+      const double q = 1.0 + fps * fps;
+      af.re += K.dx * (-fpp[i] * fps / (2.0 * SESM_PI * q * q));
+    }
+    for (int t = 0; t < K.nU; ++t) {
+      const double mag = exp(-K.Ubi[t] * Y);
+      acc += (mag * J[l] * K.dx) * cexp_i(K.Ua[t] * X0 + K.Ubr[t] * Y);
+      const cplx e0 = (exp(-K.Ubi[t] * Y) * K.dx) * cexp_i(K.Ua[t] * X0 + K.Ubr[t] * Y);
+      ay += (J[l] * e0) * cplx{-K.Ubi[t], K.Ubr[t]};  // i beta_n
+      af += (fps / J[l]) * e0;
+    }
+    M[e] = acc;
+    DY[e] = ay;
+    DF[e] = af;
+  }
+}
+
 // DY[i][l] = dA_il/dY, DF[i][l] = dA_il/df'_l (the diagonal: df'_i, with the
 // K_r(x, x) term), over the images p as in the assembly; one wave per entry.
 __global__ __launch_bounds__(256) void k_dense_deriv(KParams K, const double* __restrict__ x,
@@ -384,8 +487,10 @@ extern "C" int sesm_shape_gradient(sesm_ctx* ctx, const sesm_c64* mu_, const ses
   const int no = (int)ord.size(), nob = std::max(no, 1);
   const cplx* mu = (const cplx*)mu_;
   const cplx* nu = (const cplx*)nu_;
-  // work space: DY, DF (N x N each), conj(nu), three contractions, P, Q, R, orders, B, a, gradients
-  const size_t NN = (size_t)N * N;
+  // work space: DY, DF (N x N each, unless the set-up kept them), conj(nu),
+  // three contractions, P, Q, R, orders, B, a, gradients
+  const bool kept = ctx->dA_dY && ctx->dA_dF;
+  const size_t NN = kept ? 0 : (size_t)N * N;
   const size_t bytes = sizeof(cplx) * (2 * NN + 7 * (size_t)N + 2 * (size_t)nob) + sizeof(Order) * nob +
                        sizeof(double) * 2 * ((size_t)n_modes + 1) + 16 * 256;  // (each piece rounded up to 256 B)
   char* buf = nullptr;
@@ -396,8 +501,8 @@ extern "C" int sesm_shape_gradient(sesm_ctx* ctx, const sesm_c64* mu_, const ses
     cur += (b + 255) / 256 * 256;
     return (void*)p;
   };
-  cplx* DY = (cplx*)take(sizeof(cplx) * NN);
-  cplx* DF = (cplx*)take(sizeof(cplx) * NN);
+  cplx* DY = kept ? ctx->dA_dY : (cplx*)take(sizeof(cplx) * NN);
+  cplx* DF = kept ? ctx->dA_dF : (cplx*)take(sizeof(cplx) * NN);
   cplx* cnu = (cplx*)take(sizeof(cplx) * N);
   cplx* DYmu = (cplx*)take(sizeof(cplx) * N);
   cplx* DYtnu = (cplx*)take(sizeof(cplx) * N);
@@ -419,8 +524,9 @@ extern "C" int sesm_shape_gradient(sesm_ctx* ctx, const sesm_c64* mu_, const ses
     (void)hipStreamSynchronize(ctx->stream);
     for (auto& v : hnu) v.im = -v.im;
     (void)hipMemcpyAsync(cnu, hnu.data(), sizeof(cplx) * N, hipMemcpyHostToDevice, ctx->stream);
-    hipLaunchKernelGGL(k_dense_deriv, dim3((N + 3) / 4, N), dim3(256), 0, ctx->stream, K, ctx->x, ctx->f, ctx->fp,
-                       ctx->fpp, ctx->J, ctx->logw, DY, DF);
+    if (!kept)
+      hipLaunchKernelGGL(k_dense_deriv, dim3((N + 3) / 4, N), dim3(256), 0, ctx->stream, K, ctx->x, ctx->f,
+                         ctx->fp, ctx->fpp, ctx->J, ctx->logw, DY, DF);
     hipLaunchKernelGGL(k_gemv_rows_g, dim3(N), dim3(256), 0, ctx->stream, N, DY, mu, DYmu);
     hipLaunchKernelGGL(k_gemv_cols<false>, dim3((N + 63) / 64), dim3(1024), 0, ctx->stream, N, DY, cnu, DYtnu);
     hipLaunchKernelGGL(k_gemv_cols<false>, dim3((N + 63) / 64), dim3(1024), 0, ctx->stream, N, DF, cnu, DFtnu);
@@ -439,6 +545,22 @@ extern "C" int sesm_shape_gradient(sesm_ctx* ctx, const sesm_c64* mu_, const ses
   (void)hipFree(buf);
   if (rc == SESM_OK && es != hipSuccess) rc = ctx->fail(SESM_EHIP, hipGetErrorString(es));
   return rc;
+}
+
+// Dense set-up with sesm_params.adjoint = 1: the operator and its derivative
+// matrices in one pass, all three kept with the surface.
+int sesm_dense_assemble_with_derivs(sesm_ctx* ctx) {
+  const Problem& P = ctx->P;
+  const size_t NN = (size_t)P.N * P.N;
+  int rc;
+  if ((rc = sesm_alloc(ctx, (void**)&ctx->dA_dY, sizeof(cplx) * NN)) ||
+      (rc = sesm_alloc(ctx, (void**)&ctx->dA_dF, sizeof(cplx) * NN)))
+    return rc;
+  const KParams K = ctx->kparams();
+  hipLaunchKernelGGL(k_dense_assemble_deriv, dim3((P.N + 3) / 4, P.N), dim3(256), 0, ctx->stream, K, ctx->x, ctx->f,
+                     ctx->fp, ctx->fpp, ctx->J, ctx->logw, ctx->Mdense, ctx->dA_dY, ctx->dA_dF);
+  SESM_LAUNCH_CHECK();
+  return SESM_OK;
 }
 
 // y = (1/2 I + D^dx)^H mu (dense mode)

@@ -224,7 +224,7 @@ void sesm_release_surface(sesm_ctx* ctx) {
   ctx->owned.clear();
   ctx->bytes = 0;
   ctx->x = ctx->f = ctx->fp = ctx->fpp = ctx->J = ctx->logw = nullptr;
-  ctx->Mdense = nullptr;
+  ctx->Mdense = ctx->dA_dY = ctx->dA_dF = nullptr;
   ctx->V = nullptr;
   ctx->V_cols = 0;
   ctx->hcol = ctx->hpart = ctx->ybuf = ctx->wtmp = ctx->gw = ctx->Hrow = ctx->htri = ctx->hp = ctx->gcoef = nullptr;
@@ -420,6 +420,9 @@ int sesm_set_surface(sesm_ctx* ctx, const sesm_profile* prof, double d, double k
     return ctx->fail(SESM_EINVAL, "invalid discretisation parameter");
   if (prm.mode != SESM_MODE_DENSE && prm.mode != SESM_MODE_ACCEL) return ctx->fail(SESM_EINVAL, "unknown mode");
   if (prm.table != 0 && prm.table != 1) return ctx->fail(SESM_EINVAL, "table must be 0 (windowed) or 1 (hybrid)");
+  if (prm.adjoint != 0 && prm.adjoint != 1) return ctx->fail(SESM_EINVAL, "adjoint must be 0 or 1");
+  if (prm.adjoint == 1 && prm.mode != SESM_MODE_DENSE)
+    return ctx->fail(SESM_EINVAL, "adjoint = 1 (derivative matrices) needs the dense mode");
   if (prm.table == 1 && (prm.mode != SESM_MODE_ACCEL || j < 1))
     return ctx->fail(SESM_EINVAL, "hybrid tables need the accelerated mode and j >= 1");
   const double a = prm.n_a * dx;

@@ -68,6 +68,7 @@ int sesm_dense_setup(sesm_ctx* ctx) {
   if (rc) return rc;
   const KParams K = ctx->kparams();
   if (P.N > 65535) return ctx->fail(SESM_EINVAL, "dense mode supports N <= 65535");
+  if (ctx->prm.adjoint == 1) return sesm_dense_assemble_with_derivs(ctx);
   hipLaunchKernelGGL(k_dense_assemble, dim3((P.N + 3) / 4, P.N), dim3(256), 0, ctx->stream, K, ctx->x, ctx->f, ctx->fp,
                      ctx->fpp, ctx->J, ctx->logw, ctx->Mdense);
   SESM_LAUNCH_CHECK();

@@ -78,6 +78,8 @@ struct sesm_ctx {
   double *x = nullptr, *f = nullptr, *fp = nullptr, *fpp = nullptr, *J = nullptr;
   double* logw = nullptr;  // log-quadrature weights R_m, m = 0..n_a-1
   cplx* Mdense = nullptr;  // dense operator, row-major N x N
+  cplx* dA_dY = nullptr;   // with sesm_params.adjoint: dA/dY and dA/df' (row-major N x N each)
+  cplx* dA_dF = nullptr;
   AccelOp* acc = nullptr;
   // GMRES workspace
   cplx* V = nullptr;
@@ -200,6 +202,7 @@ void sesm_accel_info(const sesm_ctx* ctx, sesm_surface_info* info);
 // operator dispatch; sesm_apply_inc applies the operator of member inc of the
 // incidence set (inc < 0: the surface's own incidence)
 int sesm_apply(sesm_ctx* ctx, const cplx* mu, cplx* y);
+int sesm_dense_assemble_with_derivs(sesm_ctx* ctx);
 int sesm_dense_matvec_adjoint(sesm_ctx* ctx, const cplx* mu, cplx* y);
 int sesm_apply_inc(sesm_ctx* ctx, const cplx* mu, cplx* y, int inc, bool mixed = false);
 

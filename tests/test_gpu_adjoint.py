@@ -38,11 +38,11 @@ def _surface_kw(wl, disc):
                 gamma_frac=wl.gamma_frac, eta=wl.eta, L=wl.L)
 
 
-def _set(solver, wl, a=None, b=None):
+def _set(solver, wl, a=None, b=None, adjoint=0):
     import paper_1707_04950_amd as lib
     disc = dense.Discretization(wl)
     solver.set_surface(np.asarray(wl.a_coef if a is None else a), np.asarray(wl.b_coef if b is None else b),
-                       mode=lib.MODE_DENSE, **_surface_kw(wl, disc))
+                       mode=lib.MODE_DENSE, adjoint=adjoint, **_surface_kw(wl, disc))
     return disc
 
 
@@ -227,6 +227,36 @@ def test_autograd_function(torch, solver):
     # (the function's solves stop at 1e-12, the reference ones at 1e-13)
     assert np.allclose(a.grad.numpy(), ga, rtol=0, atol=1e-8 * np.max(np.abs(ga)))
     assert np.allclose(b.grad.numpy(), gb, rtol=0, atol=1e-8 * np.max(np.abs(ga)))
+
+
+def test_kept_derivative_matrices(torch, solver):
+    """sesm_params.adjoint = 1: the operator assembled together with its
+    derivative matrices equals the plain assembly (forward maps to rounding),
+    and the shape gradient from the kept matrices equals the one that forms
+    them on the call; the accelerated mode rejects the flag."""
+    import paper_1707_04950_amd as lib
+    from gpu_util import set_surface, to_dev, to_host
+    wl = _case()
+    disc = dense.Discretization(wl)
+    orders = rayleigh.propagating_orders(disc.k, disc.alpha, disc.d)
+    w = _weights(len(orders))
+    m = to_dev(torch, W.random_density(disc.N, 4))
+    out = {}
+    for flag in (0, 1):
+        _set(solver, wl, adjoint=flag)
+        y = to_host(solver.matvec(m))
+        mu, _ = solver.solve(tol=1e-13, max_iter=1000, allow_noconv=True)
+        J, rhs = solver.objective_adjoint_rhs(mu, w)
+        nu, _ = solver.solve(b=rhs, tol=1e-13, max_iter=1000, adjoint=True, allow_noconv=True)
+        ga, gb = solver.shape_gradient(mu, nu, w, 2)
+        out[flag] = (y, np.concatenate([ga, gb]))
+    dy = np.max(np.abs(out[1][0] - out[0][0])) / np.max(np.abs(out[0][0]))
+    dg = np.max(np.abs(out[1][1] - out[0][1])) / np.max(np.abs(out[0][1]))
+    print("kept derivatives: forward map %.2e (bitwise %s), gradient %.2e" %
+          (dy, np.array_equal(out[1][0], out[0][0]), dg))
+    assert dy <= 1e-14 and dg <= 1e-10
+    with pytest.raises(lib.SesmError):
+        set_surface(solver, wl, disc, mode=lib.MODE_ACCEL, adjoint=1)
 
 
 def test_adjoint_arguments(torch, solver):
