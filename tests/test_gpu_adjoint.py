@@ -179,9 +179,10 @@ def test_deep_corrugation_gradient(torch, solver):
     efficiency with respect to all 256 cosine coefficients by one adjoint
     solve, against Richardson-extrapolated finite differences of the library's
     own solves for the three largest entries and one of the smallest; energy
-    balance holds."""
+    balance holds.  (The set-up keeps the derivative matrices: the one-pass
+    assembly on this geometry; the finite differences use plain set-ups.)"""
     wl = W.config_c5(2048)
-    disc = _set(solver, wl)
+    disc = _set(solver, wl, adjoint=1)
     mu, info = solver.solve(tol=1e-11, max_iter=3000, allow_noconv=True)
     n, e, eps = solver.efficiencies(mu)
     w = np.zeros(len(n))
